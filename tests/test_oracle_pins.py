@@ -1,0 +1,396 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(brute force on tiny tensors, closed forms, exact identities, invariants,
+error bounds).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tt_inputs as G
+
+RNG_SEEDS = [0, 1, 2]
+
+
+def tiny_tt(seed, N=5, I=3, R=4, scale="unit"):
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    return G.random_tt(seed, dims, ranks, scale=scale)
+
+
+# ---------------------------------------------------------------- generator
+
+def _mix_int(z):
+    M = (1 << 64) - 1
+    z &= M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_matches_python_integers():
+    # the numpy uint64 version must equal arbitrary-precision integer arithmetic
+    for state in [0, 1, 12345, (1 << 64) - 1, 0x0123456789ABCDEF]:
+        idx = np.arange(1, 40, dtype=np.uint64)
+        got = O.splitmix64_stream(state, idx)
+        want = [_mix_int(state + int(k) * 0x9E3779B97F4A7C15) for k in range(1, 40)]
+        assert [int(x) for x in got] == want
+
+
+def test_gaussian_stream_box_muller_closed_form():
+    key = O.sketch_core_key(7, 3)
+    z = O.gaussian_stream(key, 9)
+    M = (1 << 64) - 1
+    for p in range(5):
+        a = _mix_int((key + (2 * p + 1) * 0x9E3779B97F4A7C15) & M)
+        b = _mix_int((key + (2 * p + 2) * 0x9E3779B97F4A7C15) & M)
+        u1 = ((a >> 11) + 1) / 2.0 ** 53
+        u2 = (b >> 11) / 2.0 ** 53
+        r = math.sqrt(-2.0 * math.log(u1))
+        assert z[2 * p] == pytest.approx(r * math.cos(2 * math.pi * u2), rel=0, abs=1e-14)
+        if 2 * p + 1 < 9:
+            assert z[2 * p + 1] == pytest.approx(r * math.sin(2 * math.pi * u2), rel=0, abs=1e-14)
+
+
+def test_sketch_distribution_definition_31():
+    # Definition 3.1: iid N(0, 1/(l_{n-1} I_n l_n)) entries, E||core||^2 = 1
+    dims = [40, 50, 30]
+    ell = [1, 40, 30, 1]
+    S = O.make_sketch(99, dims, ell)
+    for c in S:
+        x = c.ravel()
+        n = x.size
+        var = 1.0 / n
+        assert abs(x.mean()) < 6 * math.sqrt(var / n)
+        assert abs(x.var() / var - 1.0) < 6 * math.sqrt(2.0 / n)
+        kurt = np.mean(x ** 4) / np.mean(x ** 2) ** 2
+        assert abs(kurt - 3.0) < 0.2
+    # seeds and cores give distinct streams
+    S2 = O.make_sketch(100, dims, ell)
+    assert not np.allclose(S[1], S2[1])
+    assert O.sketch_core_key(1, 0) != O.sketch_core_key(1, 1)
+
+
+# ---------------------------------------------------------------- plan
+
+def test_plan_ranks_small_sum_workload():
+    # A+A assembled: N=8, I=10, formal rank 20, target 10, oversample 5
+    ell, out = O.plan_ranks([10] * 8, [1] + [20] * 7 + [1], 10, 5)
+    assert ell == [1, 10, 15, 15, 15, 15, 15, 10, 1]
+    assert out == [1] + [10] * 7 + [1]
+
+
+def test_plan_ranks_clamps():
+    ell, out = O.plan_ranks([2, 2, 2, 2], [1, 2, 4, 2, 1], 6, 2)
+    assert ell == [1, 2, 4, 2, 1]
+    assert out == [1, 2, 4, 2, 1]
+    for n in range(1, 4):
+        assert ell[n] <= ell[n - 1] * 2
+
+
+# ---------------------------------------------------------------- Algorithm 3
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_partial_contractions_brute_force(seed):
+    # closed form W_n = H(X_{n+1:N}) H(Y_{n+1:N})^T by dense partial products
+    X = tiny_tt(seed, N=5, I=3, R=4)
+    Y = G.random_tt(seed + 50, [3] * 5, [1, 2, 3, 3, 2, 1], scale="unit")
+    W = O.partial_contractions_rl(X, Y)
+    for n in range(1, 5):
+        A = O.full_with_left_rank(X[n:])
+        B = O.full_with_left_rank(Y[n:])
+        np.testing.assert_allclose(W[n], A @ B.T, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_inner_product_is_sum_of_squares(seed):
+    # appendix A: Algorithm 3 with both tensors equal yields ||Y||^2
+    Y = tiny_tt(seed, N=6, I=3, R=3)
+    T = O.full(Y)
+    assert O.inner(Y, Y) == pytest.approx(float(np.sum(T * T)), rel=1e-12)
+    assert O.tt_norm(Y) == pytest.approx(float(np.linalg.norm(T)), rel=1e-12)
+
+
+def test_sum_stacking_identity():
+    # section 3.4: W^{Y+Z}_n = [W^Y_n ; W^Z_n]
+    A = tiny_tt(3, N=5, I=3, R=3)
+    B = G.random_tt(4, [3] * 5, [1, 2, 4, 2, 2, 1], scale="unit")
+    S = G.random_tt(5, [3] * 5, [1, 3, 3, 3, 3, 1], scale="unit")
+    X = G.block_sum([A, B])
+    WX = O.partial_contractions_rl(X, S)
+    WA = O.partial_contractions_rl(A, S)
+    WB = O.partial_contractions_rl(B, S)
+    for n in range(1, 5):
+        np.testing.assert_allclose(WX[n], np.vstack([WA[n], WB[n]]), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- Algorithm 5
+
+def _sketch(seed, Y, target, over):
+    ell, out = O.plan_ranks(O.dims_of(Y), O.ranks_of(Y), target, over)
+    return O.make_sketch(seed, O.dims_of(Y), ell), ell, out
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_rto_equals_dense_range_finder(seed):
+    # Algorithm 5 is the sequential range finder on unfoldings in factored form
+    Y = tiny_tt(seed, N=5, I=4, R=5)
+    S, ell, _ = _sketch(seed + 10, Y, 3, 0)
+    X = O.rto_sweep(Y, O.partial_contractions_rl(Y, S))
+    D = O.dense_rto(O.full(Y), S)
+    for a, b in zip(X, D):
+        assert a.shape == b.shape
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * max(1.0, np.abs(b).max()))
+
+
+def test_rto_exact_on_small_sum_workload():
+    # rounding A+A (rank 10 formally 20) to 10 through a 15 sketch returns 2A
+    w = G.workload_small_sum()
+    X = O.round_rand(w["X"], w["target"], w["oversample"], seed=w["sketch_seed"])
+    twoA = [2.0 * w["A"][0]] + [c.copy() for c in w["A"][1:]]
+    assert O.rel_diff(X, twoA) <= 1e-12
+    assert O.ranks_of(X) == [1] + [10] * 7 + [1]
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_rto_output_left_orthogonal(seed):
+    Y = tiny_tt(seed, N=6, I=4, R=6, scale="nominal")
+    S, ell, _ = _sketch(seed, Y, 4, 1)
+    X = O.rto_sweep(Y, O.partial_contractions_rl(Y, S))
+    for c in X[:-1]:
+        Vn = O.V(c)
+        assert np.abs(Vn.T @ Vn - np.eye(Vn.shape[1])).max() < 1e-13
+
+
+def test_rto_exact_when_ranks_suffice():
+    # every unfolding rank <= l_n  =>  X == Y
+    Y = tiny_tt(11, N=6, I=3, R=3, scale="nominal")
+    X = O.round_rand(Y, 3, 2, seed=5)
+    assert O.rel_diff(X, Y) < 1e-13
+
+
+def test_rto_gauge_invariance():
+    # Y_n <- Y_n G, Y_{n+1} <- G^{-1} Y_{n+1} leaves the output unchanged
+    Y = tiny_tt(21, N=5, I=4, R=5, scale="nominal")
+    rng = np.random.default_rng(0)
+    Y2 = [c.copy() for c in Y]
+    for n in range(4):
+        Gm = rng.standard_normal((5, 5)) + 3 * np.eye(5)
+        Y2[n] = (O.V(Y2[n]) @ Gm).reshape(Y2[n].shape)
+        Y2[n + 1] = (np.linalg.solve(Gm, O.H(Y2[n + 1]))).reshape(Y2[n + 1].shape)
+    S, ell, _ = _sketch(3, Y, 3, 0)
+    X1 = O.rto_sweep(Y, O.partial_contractions_rl(Y, S))
+    X2 = O.rto_sweep(Y2, O.partial_contractions_rl(Y2, S))
+    for a, b in zip(X1, X2):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-10 * max(1, np.abs(a).max()))
+
+
+def test_rto_sketch_scale_invariance():
+    # Q depends only on the range of the sketch: positive core scalings cancel
+    Y = tiny_tt(22, N=5, I=4, R=5, scale="nominal")
+    S, ell, _ = _sketch(4, Y, 3, 0)
+    S2 = [c * s for c, s in zip(S, [2.0 ** 30, 3.0, 0.25, 7.0, 1e-20])]
+    X1 = O.rto_sweep(Y, O.partial_contractions_rl(Y, S))
+    X2 = O.rto_sweep(Y, O.partial_contractions_rl(Y, S2))
+    for a, b in zip(X1, X2):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * max(1, np.abs(a).max()))
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_randomized_error_lower_bounds(seed):
+    # Eckart-Young on every unfolding, and TT-SVD quasi-optimality
+    Y = tiny_tt(seed, N=5, I=4, R=6, scale="nominal")
+    X = O.round_rand(Y, 3, 1, seed=seed + 7)
+    T = O.full(Y)
+    err = np.linalg.norm(O.full(X) - T)
+    dims = O.dims_of(Y)
+    for n in range(1, 5):
+        s = np.linalg.svd(T.reshape(int(np.prod(dims[:n])), -1), compute_uv=False)
+        r = O.ranks_of(X)[n]
+        assert err >= math.sqrt(np.sum(s[r:] ** 2)) * (1 - 1e-12)
+    Xs, _, _ = O.round_svd(Y, 0.0, 3)
+    assert err >= np.linalg.norm(O.full(Xs) - T) / math.sqrt(4) * (1 - 1e-12)
+
+
+# ---------------------------------------------------------------- truncation
+
+def test_truncation_equals_dense_tt_svd_from_the_right():
+    # R->L truncation of a left-orthogonal TT == TT-SVD of the mode-reversed tensor
+    Y = tiny_tt(31, N=5, I=4, R=6, scale="nominal")
+    S, ell, out = _sketch(8, Y, 3, 3)
+    X = O.rto_sweep(Y, O.partial_contractions_rl(Y, S))
+    Xt, tails = O.truncate_rl(X, out)
+    assert O.ranks_of(Xt) == out
+    T = O.full(X)
+    Trev = np.transpose(T, axes=list(range(4, -1, -1)))
+    D = O.dense_tt_svd(Trev, out[::-1])
+    Dfull = np.transpose(O.full(D), axes=list(range(4, -1, -1)))
+    np.testing.assert_allclose(O.full(Xt), Dfull, rtol=0, atol=1e-12)
+    # discarded energy adds up (orthogonal projections)
+    err2 = np.sum((O.full(Xt) - T) ** 2)
+    assert err2 == pytest.approx(sum(tails), rel=1e-8, abs=1e-28)
+    # cores 2..N right-orthogonal
+    for c in Xt[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-12
+
+
+# ---------------------------------------------------------------- Algorithm 7
+
+@pytest.mark.parametrize("s", [2, 3, 5])
+def test_sum_rto_equals_rto_on_assembled_sum(s):
+    dims = [4] * 5
+    tts = [G.random_tt(40 + j, dims, [1, 2 + j % 2, 3, 2, 2 + j % 3, 1], scale="nominal")
+           for j in range(s)]
+    coeffs = G.sum_coefficients(7, s)
+    Xs = G.block_sum(tts, coeffs)
+    A = O.round_sum_rand(tts, coeffs, 4, 1, seed=77)
+    B = O.round_rand(Xs, 4, 1, seed=77)
+    for a, b in zip(A, B):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * max(1, np.abs(b).max()))
+
+
+def test_sum_rto_exact_small_workload():
+    w = G.workload_small_sum()
+    X = O.round_sum_rand(w["summands"], None, w["target"], w["oversample"],
+                         seed=w["sketch_seed"])
+    twoA = [2.0 * w["A"][0]] + [c.copy() for c in w["A"][1:]]
+    assert O.rel_diff(X, twoA) <= 1e-12
+
+
+# ---------------------------------------------------------------- Algorithms 1, 2
+
+def test_orthogonalize_rl_right_orthogonal_and_equivalent():
+    Y = tiny_tt(51, N=5, I=3, R=4)
+    X = O.orthogonalize_rl(Y)
+    for c in X[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-13
+    np.testing.assert_allclose(O.full(X), O.full(Y), rtol=0, atol=1e-12 * np.abs(O.full(Y)).max())
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_round_svd_equals_dense_tt_svd(seed):
+    Y = tiny_tt(seed, N=5, I=4, R=6, scale="nominal")
+    X, ranks, _ = O.round_svd(Y, 0.0, 3)
+    D = O.dense_tt_svd(O.full(Y), 3)
+    assert ranks == O.ranks_of(D)
+    np.testing.assert_allclose(O.full(X), O.full(D), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("eps0", [1e-1, 1e-3, 1e-8])
+def test_round_svd_error_bound(eps0):
+    # Algorithm 2 guarantees ||X - Y|| <= eps0 ||Y||; the tails add up
+    X0, _, _ = G.perturbed_tt(5, 6, 5, 3, 1e-4)
+    X, ranks, tails = O.round_svd(X0, eps0)
+    err = O.rel_diff(X, X0)
+    assert err <= eps0 * (1 + 1e-10)
+    nrm = O.tt_norm(X0)
+    assert (err * nrm) ** 2 == pytest.approx(sum(tails), rel=1e-6, abs=1e-30)
+
+
+# ---------------------------------------------------------------- norms
+
+def test_rel_diff_matches_dense():
+    A = tiny_tt(61, N=4, I=3, R=3)
+    B = tiny_tt(62, N=4, I=3, R=3)
+    d = O.rel_diff(A, B)
+    Fa, Fb = O.full(A), O.full(B)
+    assert d == pytest.approx(np.linalg.norm(Fa - Fb) / np.linalg.norm(Fb), rel=1e-12)
+    assert O.rel_diff(A, A) < 1e-14
+
+
+# ---------------------------------------------------------------- paper behaviour
+
+def test_perturbed_tt_behaviour():
+    # section 4.1: with l above the rank of X1, the deterministic error is about
+    # eps (relative); randomized errors are not smaller than deterministic/sqrt(N-1)
+    N, I, R, eps = 6, 12, 4, 1e-6
+    X, X1, X2 = G.perturbed_tt(123, N, I, R, eps)
+    Xd, _, _ = O.round_svd(X, 0.0, 6)
+    ed = O.rel_diff(Xd, X)
+    scale = O.tt_norm(X2) / O.tt_norm(X)
+    assert 0.05 * eps * scale < ed < 2 * eps * scale
+    Xr = O.round_rand(X, 6, 0, seed=9)
+    er = O.rel_diff(Xr, X)
+    assert er >= ed / math.sqrt(N - 1)
+    assert er < 1e3 * eps * scale
+
+
+def test_hilbert_tt_similar_accuracy():
+    # appendix C: deterministic and RtO reach very similar accuracy
+    dims = [6, 8, 10, 12, 14, 16]
+    ranks = [1, 4, 5, 6, 7, 8, 1]
+    Y = G.hilbert_tt(dims, ranks)
+    for r in [2, 3, 4]:
+        Xd, _, _ = O.round_svd(Y, 0.0, r)
+        Xr = O.round_rand(Y, r, 2, seed=3)
+        ed, er = O.rel_diff(Xd, Y), O.rel_diff(Xr, Y)
+        assert er >= ed / math.sqrt(5)
+        assert er < 50 * ed + 1e-14
+
+
+# ---------------------------------------------------------------- flop model
+
+def test_flop_count_matches_table1_leading_order():
+    # C_RtO = I (N-2) (4 R^2 l + 6 R l^2 + 4 l^3) at leading order (section 3.5)
+    I, R, l = 100, 200, 60
+    for N in [200, 2000]:
+        dims, ranks = G.uniform_tt_shape(N, I, R)
+        ell = [1] + [l] * (N - 1) + [1]
+        f = O.rto_flops(dims, ranks, ell)
+        model = I * (N - 2) * (4 * R * R * l + 6 * R * l * l + 4 * l ** 3)
+        assert abs(f / model - 1) < 10.0 / N
+
+
+# ---------------------------------------------------------------- conventions
+
+def test_rto_qr_sign_convention():
+    # reading of the QR normalisation: R = Q^T (Z_n W_n) has a non-negative diagonal
+    Y = tiny_tt(71, N=5, I=4, R=5, scale="nominal")
+    S, ell, _ = _sketch(12, Y, 3, 1)
+    W = O.partial_contractions_rl(Y, S)
+    X = O.rto_sweep(Y, W)
+    # rebuild Z_n from the output: Z_1 = V(Y_1); Z_{n+1} = (Q_n^T Z_n) H(Y_{n+1})
+    Z = O.V(Y[0])
+    for n in range(1, 5):
+        Q = O.V(X[n - 1])
+        R = Q.T @ (Z @ W[n])
+        assert np.all(np.diag(R) >= 0)
+        assert np.abs(np.tril(R, -1)).max() < 1e-12 * np.abs(R).max()
+        M = Q.T @ Z
+        Z = (M @ O.H(Y[n])).reshape(-1, Y[n].shape[2])
+
+
+def superdiagonal_tt(sigmas, N):
+    """T = sum_k sigma_k e_k (x) ... (x) e_k: every unfolding has singular
+    values exactly sigma (closed form)."""
+    K = len(sigmas)
+    cores = []
+    for n in range(N):
+        if n == 0:
+            c = np.zeros((1, K, K))
+            for k in range(K):
+                c[0, k, k] = sigmas[k]
+        elif n == N - 1:
+            c = np.zeros((K, K, 1))
+            for k in range(K):
+                c[k, k, 0] = 1.0
+        else:
+            c = np.zeros((K, K, K))
+            for k in range(K):
+                c[k, k, k] = 1.0
+        cores.append(c)
+    return cores
+
+
+def test_round_svd_eps_threshold_closed_form():
+    # Algorithm 2 line 3: eps = ||Y|| eps0 / sqrt(N-1).  With singular values
+    # (1,1,1,a) at every bond, N=5, eps0=1e-3: eps = 8.66e-4 < a = 1.2e-3, so
+    # rank 4 is kept; a threshold without the sqrt(N-1) would cut to 3.
+    a = 1.2e-3
+    Y = superdiagonal_tt([1.0, 1.0, 1.0, a], 5)
+    X, ranks, tails = O.round_svd(Y, 1e-3)
+    assert ranks == [1, 4, 4, 4, 4, 1]
+    X, ranks, tails = O.round_svd(Y, 2.0 * a * 2 / math.sqrt(3 + a * a))
+    assert ranks == [1, 3, 3, 3, 3, 1]
+    assert sum(tails) == pytest.approx(a * a, rel=1e-10)
