@@ -1,0 +1,203 @@
+/*
+ * tt_round.h -- C ABI of the MI355X (gfx950) randomized TT-rounding library.
+ *
+ * Method: Al Daas, Ballard, Cazeaux, Hallman, Miedlar, Pasha, Reid, Saibaba,
+ * "Randomized algorithms for rounding in the Tensor-Train format".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * TT layout.  A TT of order N is given by N core pointers; core n (0-based)
+ *   is a C-contiguous array of shape (ranks[n], dims[n], ranks[n+1]) with
+ *   ranks[0] = ranks[N] = 1 (the TT format of section 2.1).  With this layout
+ *   the horizontal unfolding H (r_{n-1} x I_n r_n) and the vertical unfolding
+ *   V (r_{n-1} I_n x r_n) are plain row-major views.
+ * Memory.  `dims`, `ranks`, the core-pointer arrays and every `*_host`
+ *   argument are HOST memory.  Core pointers and `workspace` point to DEVICE
+ *   memory owned by the caller; the library never allocates device memory
+ *   and never frees caller memory.  Input cores are never modified.
+ * Streams.  `stream` is a hipStream_t (NULL = legacy default stream).  Device
+ *   work is enqueued asynchronously; the call returns before it completes
+ *   unless stated otherwise.  Calls that share a workspace must be ordered
+ *   on one stream.
+ * Workspace.  Each device entry point takes a workspace whose minimum size
+ *   is returned by the matching *_workspace query (host only, no GPU).
+ * Errors.  Every function returns a tt_status.  Argument errors are detected
+ *   on the host before any launch; then nothing is enqueued and outputs are
+ *   untouched.  tt_last_error() returns a thread-local message describing the
+ *   last non-OK status of the calling thread.
+ * Precision.  `dtype` is the storage type of the cores (TT_F64 or TT_F32);
+ *   `prec` the arithmetic mode (TT_PREC_F64 needs TT_F64 storage,
+ *   TT_PREC_F32 and TT_PREC_MIXED_BF16 need TT_F32 storage).
+ */
+#ifndef TT_ROUND_H
+#define TT_ROUND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TT_API __attribute__((visibility("default")))
+#else
+#define TT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TT_OK = 0,
+  TT_EINVAL = -1,       /* invalid argument (shape, rank, size, pointer)        */
+  TT_ENOMEM = -2,       /* workspace smaller than the query returned             */
+  TT_EHIP = -3,         /* a HIP runtime call failed                             */
+  TT_ENUMERIC = -4,     /* non-finite result detected                            */
+  TT_EUNSUPPORTED = -5  /* valid request outside the implemented limits          */
+} tt_status;
+
+typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
+
+typedef enum {
+  TT_PREC_F64 = 0,        /* all arithmetic in FP64 (MFMA f64)                    */
+  TT_PREC_F32 = 1,        /* all arithmetic in FP32 except Gram/Cholesky in FP64  */
+  TT_PREC_MIXED_BF16 = 2  /* W chain in BF16 MFMA with FP32 accumulation, sweep
+                             in FP32, Gram/Cholesky and tails in FP64            */
+} tt_prec;
+
+/* Limits of this build. */
+#define TT_MAX_ORDER 512          /* N                                          */
+#define TT_MAX_SKETCH_RANK 96     /* l_n after clamping                         */
+
+/* Thread-local description of the last non-OK status (never NULL). */
+TT_API const char *tt_last_error(void);
+
+/* ABI version (major*10000 + minor*100 + patch). */
+TT_API int tt_version(void);
+
+/*
+ * Rank plan of randomized rounding (host only, no GPU).
+ * Section 3 (target ranks include oversampling) and Algorithm 5.  With
+ * l = target_rank + oversample:  u_N = 1, u_n = min(l, I_{n+1} u_{n+1});
+ * l_0 = 1, l_n = min(l, l_{n-1} I_n, u_n, R_n), l_N = 1 (the thin QR of the
+ * (l_{n-1} I_n) x l_n sketch needs l_n <= l_{n-1} I_n, the right factor has
+ * rank <= I_{n+1}..I_N, and sketch columns beyond R_n add nothing).
+ * Output ranks r_n = min(target_rank, l_n).
+ *   N            order, 1 <= N <= TT_MAX_ORDER
+ *   dims[N]      mode sizes I_n >= 1
+ *   ranks[N+1]   input ranks, ranks[0] = ranks[N] = 1
+ *   sketch_ranks[N+1], out_ranks[N+1]   written on success
+ * Returns TT_EINVAL on bad shapes, target_rank < 1 or oversample < 0.
+ */
+TT_API int tt_round_rand_plan(int32_t N, const int64_t *dims, const int64_t *ranks,
+                       int64_t target_rank, int64_t oversample,
+                       int64_t *sketch_ranks, int64_t *out_ranks);
+
+/* Workspace bytes needed by tt_round_rand / tt_round_rand_with_sketch for
+ * these shapes and precision mode (host only). */
+TT_API int tt_round_rand_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                            int64_t target_rank, int64_t oversample, int32_t prec,
+                            size_t *bytes);
+
+/*
+ * Random Gaussian TT of Definition 3.1, drawn on the device.
+ * Core n (0-based) has shape (sketch_ranks[n], dims[n], sketch_ranks[n+1])
+ * and iid N(0, 1/(l_{n-1} I_n l_n)) entries.  Generator: element k (C order)
+ * of core n takes pair p = k/2 of the SplitMix64 stream keyed
+ * key_n = mix(seed + (n+1) gamma); the pair uses stream outputs
+ * a = mix(key_n + (2p+1) gamma), b = mix(key_n + (2p+2) gamma),
+ * u1 = ((a >> 11) + 1) 2^-53, u2 = (b >> 11) 2^-53 and the Box-Muller values
+ * sqrt(-2 ln u1) cos(2 pi u2) (even k) and sqrt(-2 ln u1) sin(2 pi u2) (odd k),
+ * divided by sqrt(l_{n-1} I_n l_n).  mix is the SplitMix64 output function,
+ * gamma = 0x9E3779B97F4A7C15.
+ *   cores[N]   device pointers of the caller's output cores (dtype storage;
+ *              TT_F32 rounds the FP64 value to nearest)
+ */
+TT_API int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims,
+                   const int64_t *sketch_ranks, int32_t dtype, void *const *cores,
+                   void *stream);
+
+/*
+ * Right-to-left partial contractions, Algorithm 3 / eq. (RLContraction):
+ * W_n = H(X_{n+1:N}) H(Y_{n+1:N})^T for n = 1..N-1, computed as
+ * W_{N-1} = H(X_N) H(Y_N)^T and, for n = N-1..2, V(Z_n) = V(X_n) W_n,
+ * W_{n-1} = H(Z_n) H(Y_n)^T.
+ *   X: N cores with ranks_x[N+1];  Y: N cores with ranks_y[N+1]; same dims.
+ *   W_out[N-1]  device pointers; W_out[n-1] receives W_n as a row-major
+ *               ranks_x[n] x ranks_y[n] matrix (n = 1..N-1).
+ * FP64 storage and arithmetic (dtype must be TT_F64).  Needs N >= 2.
+ */
+TT_API int tt_partial_contractions_rl_workspace(int32_t N, const int64_t *dims,
+                                         const int64_t *ranks_x, const int64_t *ranks_y,
+                                         size_t *bytes);
+TT_API int tt_partial_contractions_rl(int32_t N, const int64_t *dims,
+                               const int64_t *ranks_x, const void *const *x_cores,
+                               const int64_t *ranks_y, const void *const *y_cores,
+                               void *const *W_out, void *workspace, size_t ws_bytes,
+                               void *stream);
+
+/*
+ * Randomized TT-rounding, Randomize-then-Orthogonalize (Algorithm 5).
+ * Draws the sketch of Definition 3.1 from `sketch_seed` (generator as in
+ * tt_make_sketch) with the ranks of tt_round_rand_plan, computes the partial
+ * contractions W_n of the input with it (Algorithm 3), then sweeps left to
+ * right: Z_n = V(X_n), Y_n = Z_n W_n, thin QR Y_n = Q R with diag(R) >= 0,
+ * V(X_n) <- Q, M_n = Q^T Z_n, H(X_{n+1}) = M_n H(Y_{n+1}).  When some
+ * out rank r_n < l_n the left-orthogonal result is truncated by a right-to-
+ * left sweep (section 3.2 remark; mirror of the truncation loop of
+ * Algorithm 2): for
+ * n = N..2 the Gram H(X_n) H(X_n)^T is diagonalised, the r_{n-1} leading
+ * eigenpairs (U, s^2) are kept, H(X_n) <- s^-1 U^T H(X_n) and
+ * X_{n-1} <- X_{n-1} x_3 (U s).  Then cores 2..N are right-orthogonal;
+ * otherwise cores 1..N-1 are left-orthogonal.
+ *   N, dims, ranks, cores   input TT (dtype storage), read only
+ *   target_rank, oversample see tt_round_rand_plan
+ *   out_cores[N]            caller's device buffers of shape
+ *                           (out_ranks[n], dims[n], out_ranks[n+1])
+ *   workspace, ws_bytes     >= tt_round_rand_workspace(...)
+ * N = 1 copies the single core.
+ */
+TT_API int tt_round_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
+                  const void *const *cores, int32_t dtype, int64_t target_rank,
+                  int64_t oversample, uint64_t sketch_seed, int32_t prec,
+                  void *const *out_cores, void *workspace, size_t ws_bytes,
+                  void *stream);
+
+/* As tt_round_rand with a caller-given sketch TT (device cores of shape
+ * (sketch_ranks[n], dims[n], sketch_ranks[n+1]) in `dtype` storage).
+ * sketch_ranks must equal the plan's sketch ranks. */
+TT_API int tt_round_rand_with_sketch(int32_t N, const int64_t *dims, const int64_t *ranks,
+                              const void *const *cores, int32_t dtype,
+                              int64_t target_rank, int64_t oversample,
+                              const int64_t *sketch_ranks,
+                              const void *const *sketch_cores, int32_t prec,
+                              void *const *out_cores, void *workspace,
+                              size_t ws_bytes, void *stream);
+
+/*
+ * Rounding of a sum of s TTs, Randomize-then-Orthogonalize (Algorithm 7).
+ * X = sum_j coeffs[j] Y^(j) (coeffs NULL = all 1; coeffs[j] scales the first
+ * core of summand j).  One sketch (ranks from tt_round_rand_plan applied to
+ * the formal ranks sum_j R^(j)_n) for all summands; W^(j)_n per summand; the
+ * sweep sketches with the stacked [W^(1)_n; ...; W^(s)_n] and forms the next
+ * core summand by summand, X_{n+1}(:, i, block j) = M^(j)_n Y^(j)_{n+1}(:, i, :),
+ * and X_N = sum_j M^(j)_{N-1} Y^(j)_N.  Then the same truncation as
+ * tt_round_rand.
+ *   s                 number of summands >= 1
+ *   ranks[s*(N+1)]    ranks of summand j at ranks[j*(N+1) .. j*(N+1)+N]
+ *   cores[s*N]        device pointers, summand j at cores[j*N .. j*N+N-1]
+ *   coeffs[s]         host, or NULL
+ *   out_cores[N]      shapes from tt_round_rand_plan on the formal ranks
+ */
+TT_API int tt_sum_round_workspace(int32_t s, int32_t N, const int64_t *dims,
+                           const int64_t *ranks, int64_t target_rank,
+                           int64_t oversample, int32_t prec, size_t *bytes);
+TT_API int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                 const void *const *cores, const double *coeffs, int32_t dtype,
+                 int64_t target_rank, int64_t oversample, uint64_t sketch_seed,
+                 int32_t prec, void *const *out_cores, void *workspace,
+                 size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_ROUND_H */

@@ -31,7 +31,7 @@ Readings taken where the paper is silent (each also listed in the design notes):
 * The sketch generator (the paper fixes only the distribution): SplitMix64
   (Steele, Lea, Flood 2014) evaluated at a counter, Box-Muller transform.
 * When r_n < l_n somewhere, the left-orthogonal RtO output is truncated by a
-  right-to-left sweep of SVDs (the mirror of Algorithm 2 lines 3-10, since the
+  right-to-left sweep of SVDs (the mirror of the truncation loop of Algorithm 2, since the
   output is left- and not right-orthogonal).
 * eps-truncation is absolute: keep the smallest k >= 1 with
   sqrt(sum_{j>k} s_j^2) <= eps0 ||Y|| / sqrt(N-1), capped by max_rank.

@@ -1,0 +1,231 @@
+"""Python binding of libttround: torch tensors in, torch tensors out.
+
+Torch only provides device memory and the stream; every arithmetic step runs
+in the library's HIP kernels.  Cores are lists of C-contiguous device tensors
+of shape (r_{n-1}, I_n, r_n).
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+_PREC = {"f64": L.TT_PREC_F64, "f32": L.TT_PREC_F32, "bf16": L.TT_PREC_MIXED_BF16}
+_DTYPE = {torch.float64: L.TT_F64, torch.float32: L.TT_F32}
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes_void(s.cuda_stream)
+
+
+def ctypes_void(v):
+    import ctypes
+    return ctypes.c_void_p(int(v))
+
+
+def _shape_of(cores):
+    dims = [int(c.shape[1]) for c in cores]
+    ranks = [1] + [int(c.shape[2]) for c in cores]
+    return dims, ranks
+
+
+def _check_cores(cores, what="cores"):
+    if len(cores) == 0:
+        raise ValueError(f"{what}: empty TT")
+    dt = cores[0].dtype
+    dev = cores[0].device
+    prev = 1
+    for n, c in enumerate(cores):
+        if c.dim() != 3:
+            raise ValueError(f"{what}[{n}] must be 3-D (r_prev, I, r_next)")
+        if not c.is_cuda:
+            raise ValueError(f"{what}[{n}] must be a device tensor")
+        if c.dtype != dt or c.device != dev:
+            raise ValueError(f"{what}: mixed dtypes/devices")
+        if not c.is_contiguous():
+            raise ValueError(f"{what}[{n}] must be contiguous")
+        if int(c.shape[0]) != prev:
+            raise ValueError(f"{what}[{n}]: left rank {c.shape[0]} != {prev}")
+        prev = int(c.shape[2])
+    if prev != 1:
+        raise ValueError(f"{what}: last rank must be 1")
+    if dt not in _DTYPE:
+        raise ValueError(f"{what}: dtype must be float64 or float32")
+
+
+def version() -> int:
+    return L.lib().tt_version()
+
+
+def plan(dims: Sequence[int], ranks: Sequence[int], target_rank: int, oversample: int = 0):
+    """Sketch ranks l_n and output ranks r_n (host only)."""
+    N = len(dims)
+    sr = L.i64_array([0] * (N + 1))
+    orr = L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_round_rand_plan(N, L.i64_array(dims), L.i64_array(ranks),
+                                       int(target_rank), int(oversample), sr, orr))
+    return [sr[i] for i in range(N + 1)], [orr[i] for i in range(N + 1)]
+
+
+def round_rand_workspace(dims, ranks, target_rank, oversample=0, prec="f64") -> int:
+    import ctypes
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_round_rand_workspace(len(dims), L.i64_array(dims), L.i64_array(ranks),
+                                            int(target_rank), int(oversample), _PREC[prec],
+                                            ctypes.byref(b)))
+    return int(b.value)
+
+
+def sum_round_workspace(dims, ranks_list, target_rank, oversample=0, prec="f64") -> int:
+    import ctypes
+    b = ctypes.c_size_t(0)
+    flat = [r for rr in ranks_list for r in rr]
+    L.check(L.lib().tt_sum_round_workspace(len(ranks_list), len(dims), L.i64_array(dims),
+                                           L.i64_array(flat), int(target_rank), int(oversample),
+                                           _PREC[prec], ctypes.byref(b)))
+    return int(b.value)
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def make_sketch(seed: int, dims, sketch_ranks, dtype=torch.float64, device="cuda", stream=None):
+    """Random Gaussian TT of Definition 3.1 drawn on the device."""
+    N = len(dims)
+    cores = [torch.empty((int(sketch_ranks[n]), int(dims[n]), int(sketch_ranks[n + 1])),
+                         dtype=dtype, device=device) for n in range(N)]
+    L.check(L.lib().tt_make_sketch(int(seed) & ((1 << 64) - 1), N, L.i64_array(dims),
+                                   L.i64_array(sketch_ranks), _DTYPE[dtype],
+                                   L.ptr_array([c.data_ptr() for c in cores]),
+                                   _stream_handle(stream)))
+    return cores
+
+
+def partial_contractions_rl(X, Y, stream=None):
+    """W_n = H(X_{n+1:N}) H(Y_{n+1:N})^T, n = 1..N-1 (Algorithm 3); returns a
+    list indexed by n with entry 0 = None."""
+    import ctypes
+    _check_cores(X, "X")
+    _check_cores(Y, "Y")
+    dims, rx = _shape_of(X)
+    dy, ry = _shape_of(Y)
+    if dims != dy:
+        raise ValueError("X and Y must share mode sizes")
+    N = len(dims)
+    dev = X[0].device
+    W = [None] + [torch.empty((rx[n], ry[n]), dtype=torch.float64, device=dev)
+                  for n in range(1, N)]
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_partial_contractions_rl_workspace(N, L.i64_array(dims), L.i64_array(rx),
+                                                         L.i64_array(ry), ctypes.byref(b)))
+    ws = _workspace(b.value, dev)
+    L.check(L.lib().tt_partial_contractions_rl(
+        N, L.i64_array(dims), L.i64_array(rx), L.ptr_array([c.data_ptr() for c in X]),
+        L.i64_array(ry), L.ptr_array([c.data_ptr() for c in Y]),
+        L.ptr_array([w.data_ptr() for w in W[1:]]), ctypes.c_void_p(ws.data_ptr()),
+        ws.numel(), _stream_handle(stream)))
+    return W
+
+
+class RoundPlan:
+    """Pre-sized outputs and workspace for repeated roundings of one shape
+    (the timed benchmark loop allocates nothing)."""
+
+    def __init__(self, dims, ranks, target_rank, oversample=0, prec="f64", device="cuda",
+                 dtype=torch.float64, summand_ranks=None):
+        self.dims = [int(d) for d in dims]
+        self.N = len(self.dims)
+        self.target = int(target_rank)
+        self.oversample = int(oversample)
+        self.prec = prec
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.summand_ranks = summand_ranks
+        if summand_ranks is not None:
+            formal = [1] + [sum(r[n] for r in summand_ranks) for n in range(1, self.N)] + [1]
+            self.ranks = formal
+            self.ws_bytes = sum_round_workspace(self.dims, summand_ranks, self.target,
+                                                self.oversample, prec)
+        else:
+            self.ranks = [int(r) for r in ranks]
+            self.ws_bytes = round_rand_workspace(self.dims, self.ranks, self.target,
+                                                 self.oversample, prec)
+        self.sketch_ranks, self.out_ranks = plan(self.dims, self.ranks, self.target,
+                                                 self.oversample)
+        self.workspace = _workspace(self.ws_bytes, self.device)
+        self.out = [torch.empty((self.out_ranks[n], self.dims[n], self.out_ranks[n + 1]),
+                                dtype=dtype, device=self.device) for n in range(self.N)]
+        self._out_ptrs = L.ptr_array([c.data_ptr() for c in self.out])
+        self._dims = L.i64_array(self.dims)
+
+    def run(self, cores, seed=0, sketch=None, stream=None):
+        import ctypes
+        _check_cores(cores)
+        dims, ranks = _shape_of(cores)
+        if dims != self.dims or ranks != self.ranks:
+            raise ValueError("cores do not match the plan's shape")
+        st = _stream_handle(stream)
+        ptrs = L.ptr_array([c.data_ptr() for c in cores])
+        ws = ctypes.c_void_p(self.workspace.data_ptr())
+        if sketch is None:
+            L.check(L.lib().tt_round_rand(self.N, self._dims, L.i64_array(ranks), ptrs,
+                                          _DTYPE[cores[0].dtype], self.target, self.oversample,
+                                          int(seed) & ((1 << 64) - 1), _PREC[self.prec],
+                                          self._out_ptrs, ws, self.workspace.numel(), st))
+        else:
+            _check_cores(sketch, "sketch")
+            _, sr = _shape_of(sketch)
+            L.check(L.lib().tt_round_rand_with_sketch(
+                self.N, self._dims, L.i64_array(ranks), ptrs, _DTYPE[cores[0].dtype],
+                self.target, self.oversample, L.i64_array(sr),
+                L.ptr_array([c.data_ptr() for c in sketch]), _PREC[self.prec], self._out_ptrs,
+                ws, self.workspace.numel(), st))
+        return self.out
+
+    def run_sum(self, summands, coeffs=None, seed=0, stream=None):
+        import ctypes
+        s = len(summands)
+        flat_ranks, ptrs = [], []
+        for t in summands:
+            _check_cores(t)
+            d, r = _shape_of(t)
+            if d != self.dims:
+                raise ValueError("summand mode sizes differ from the plan")
+            flat_ranks += r
+            ptrs += [c.data_ptr() for c in t]
+        if self.summand_ranks is None or [list(map(int, r)) for r in self.summand_ranks] != \
+                [_shape_of(t)[1] for t in summands]:
+            raise ValueError("summand ranks differ from the plan")
+        cf = None
+        if coeffs is not None:
+            cf = (ctypes.c_double * s)(*[float(c) for c in coeffs])
+        L.check(L.lib().tt_sum_round(s, self.N, self._dims, L.i64_array(flat_ranks),
+                                     L.ptr_array(ptrs), cf, _DTYPE[summands[0][0].dtype],
+                                     self.target, self.oversample, int(seed) & ((1 << 64) - 1),
+                                     _PREC[self.prec], self._out_ptrs,
+                                     ctypes.c_void_p(self.workspace.data_ptr()),
+                                     self.workspace.numel(), _stream_handle(stream)))
+        return self.out
+
+
+def round_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0, prec: str = "f64",
+               sketch: Optional[list] = None, stream=None):
+    """Randomize-then-Orthogonalize rounding (Algorithm 5) of a TT; returns
+    new output cores (clones)."""
+    _check_cores(cores)
+    dims, ranks = _shape_of(cores)
+    p = RoundPlan(dims, ranks, target_rank, oversample, prec, cores[0].device, cores[0].dtype)
+    return [c.clone() for c in p.run(cores, seed=seed, sketch=sketch, stream=stream)]
+
+
+def sum_round(summands, coeffs, target_rank: int, oversample: int = 0, seed: int = 0,
+              prec: str = "f64", stream=None):
+    """Rounding of sum_j coeffs[j] * summands[j] (Algorithm 7)."""
+    dims, _ = _shape_of(summands[0])
+    p = RoundPlan(dims, None, target_rank, oversample, prec, summands[0][0].device,
+                  summands[0][0].dtype, summand_ranks=[_shape_of(t)[1] for t in summands])
+    return [c.clone() for c in p.run_sum(summands, coeffs, seed=seed, stream=stream)]

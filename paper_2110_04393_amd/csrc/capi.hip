@@ -1,0 +1,630 @@
+// extern "C" entry points and the host-side sequencing of the rounding.
+//
+// Each device entry point is written once as an `exec` routine over an Arena;
+// run with a null base it only measures, which is how the *_workspace queries
+// compute sizes, so queries and runs cannot disagree about the layout.
+//
+// Path of tt_round_rand (Algorithm 5; Algorithm 7 for tt_sum_round):
+//   1. sketch cores (Definition 3.1) drawn on the device into the workspace
+//   2. W chain (Algorithm 3), right to left, one MFMA GEMM pair per core
+//   3. left-to-right sweep: Y_n = Z_n W_n, thin QR, M_n = Q^T Z_n,
+//      next core M_n H(Y_{n+1}) (per summand for sums)
+//   4. right-to-left truncation when an output rank is below the sketch rank
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "tt_internal.h"
+
+namespace ttr {
+
+static thread_local std::string g_err = "no error";
+
+void set_error(const std::string &msg) { g_err = msg; }
+int fail(int status, const std::string &msg) {
+  g_err = msg;
+  return status;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- validation
+
+int check_shape(int32_t N, const int64_t *dims, const int64_t *ranks, const char *what) {
+  if (N < 1 || N > TT_MAX_ORDER)
+    return fail(TT_EINVAL, std::string(what) + ": order N out of range");
+  if (!dims || !ranks) return fail(TT_EINVAL, std::string(what) + ": null dims/ranks");
+  if (ranks[0] != 1 || ranks[N] != 1)
+    return fail(TT_EINVAL, std::string(what) + ": ranks[0] and ranks[N] must be 1");
+  for (int n = 0; n < N; ++n) {
+    if (dims[n] < 1) return fail(TT_EINVAL, std::string(what) + ": dims must be >= 1");
+    if (ranks[n + 1] < 1) return fail(TT_EINVAL, std::string(what) + ": ranks must be >= 1");
+    if (dims[n] > (int64_t(1) << 31) || ranks[n + 1] > (int64_t(1) << 20))
+      return fail(TT_EINVAL, std::string(what) + ": dimension too large");
+  }
+  return TT_OK;
+}
+
+int check_ptrs(int32_t N, const void *const *p, const char *what) {
+  if (!p) return fail(TT_EINVAL, std::string(what) + ": null pointer array");
+  for (int n = 0; n < N; ++n)
+    if (!p[n]) return fail(TT_EINVAL, std::string(what) + ": null core pointer");
+  return TT_OK;
+}
+
+void plan_ranks(int N, const int64_t *dims, const int64_t *R, int64_t target, int64_t over,
+                std::vector<int64_t> &ell, std::vector<int64_t> &out) {
+  const int64_t lreq = target + over;
+  std::vector<int64_t> u(N + 1, 1);
+  for (int n = N - 1; n >= 1; --n) u[n] = std::min<int64_t>(lreq, dims[n] * u[n + 1]);
+  ell.assign(N + 1, 1);
+  for (int n = 1; n < N; ++n)
+    ell[n] = std::min({lreq, ell[n - 1] * dims[n - 1], u[n], R[n]});
+  out.assign(N + 1, 1);
+  for (int n = 1; n < N; ++n) out[n] = std::min(target, ell[n]);
+}
+
+int prec_supported(int32_t dtype, int32_t prec) {
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "unknown dtype");
+  if (prec < TT_PREC_F64 || prec > TT_PREC_MIXED_BF16) return fail(TT_EINVAL, "unknown prec");
+  if (dtype == TT_F64 && prec == TT_PREC_F64) return TT_OK;
+  return fail(TT_EUNSUPPORTED, "only TT_F64 storage with TT_PREC_F64 is implemented");
+}
+
+void read_env() {
+  const char *q = std::getenv("TT_QR");
+  if (!q) qr_set_mode(0);
+  else if (!std::strcmp(q, "householder")) qr_set_mode(1);
+  else if (!std::strcmp(q, "cholqr2")) qr_set_mode(2);
+  else qr_set_mode(0);
+}
+
+// ---------------------------------------------------------------- context
+
+struct Ctx {
+  bool dry = true;
+  Arena arena;
+  hipStream_t s = nullptr;
+  size_t partial_need = 0;  // elements
+  double *partial = nullptr;
+  size_t partial_cap = 0;
+};
+
+template <typename T>
+int gemm(Ctx &c, Gemm<T> g) {
+  const int sp = (g.batch > 1) ? 1 : gemm_pick_splits(g.M, g.N, g.K);
+  const size_t need = sp > 1 ? (size_t)sp * g.M * g.N : 0;
+  c.partial_need = std::max(c.partial_need, need);
+  if (c.dry) return TT_OK;
+  if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split-K buffer too small");
+  g.splits = sp;
+  g.partial = reinterpret_cast<T *>(c.partial);
+  return gemm_run<T>(g, c.s);
+}
+
+// Problem description shared by single-TT and sum rounding.  A single TT is
+// a sum with s = 1.
+struct Problem {
+  int N = 0, s = 1;
+  std::vector<int64_t> dims;
+  std::vector<std::vector<int64_t>> R;  // per summand, N+1 ranks
+  std::vector<int64_t> Rsum;            // formal ranks
+  std::vector<int64_t> ell, out;
+  std::vector<double> coeffs;
+  bool truncate = false;
+  int64_t max_ell = 1;
+};
+
+int make_problem(Problem &P, int s, int N, const int64_t *dims, const int64_t *ranks,
+                 int64_t target, int64_t over, const double *coeffs) {
+  if (s < 1) return fail(TT_EINVAL, "need at least one summand");
+  if (target < 1) return fail(TT_EINVAL, "target_rank must be >= 1");
+  if (over < 0) return fail(TT_EINVAL, "oversample must be >= 0");
+  P.N = N;
+  P.s = s;
+  P.dims.assign(dims, dims + N);
+  P.R.resize(s);
+  P.Rsum.assign(N + 1, 0);
+  for (int j = 0; j < s; ++j) {
+    TTR_TRY(check_shape(N, dims, ranks + (size_t)j * (N + 1), "input TT"));
+    P.R[j].assign(ranks + (size_t)j * (N + 1), ranks + (size_t)(j + 1) * (N + 1));
+    for (int n = 0; n <= N; ++n) P.Rsum[n] += P.R[j][n];
+  }
+  P.Rsum[0] = P.Rsum[N] = 1;
+  plan_ranks(N, dims, P.Rsum.data(), target, over, P.ell, P.out);
+  P.coeffs.assign(s, 1.0);
+  if (coeffs)
+    for (int j = 0; j < s; ++j) P.coeffs[j] = coeffs[j];
+  P.truncate = false;
+  P.max_ell = 1;
+  for (int n = 0; n <= N; ++n) {
+    if (P.out[n] < P.ell[n]) P.truncate = true;
+    P.max_ell = std::max(P.max_ell, P.ell[n]);
+  }
+  if (N > 1 && P.max_ell > TT_MAX_SKETCH_RANK)
+    return fail(TT_EUNSUPPORTED, "sketch rank above TT_MAX_SKETCH_RANK");
+  return TT_OK;
+}
+
+// ---------------------------------------------------------------- W chain
+// W[n] (n = 1..N-1) = H(Y_{n+1:N}) H(Sk_{n+1:N})^T, row-major R_n x L_n with
+// leading dimension ldw[n] (its column count) at the given pointer.
+template <typename T>
+int wchain(Ctx &c, int N, const int64_t *dims, const int64_t *R, const T *const *Y,
+           const int64_t *L, const T *const *Sk, T *const *W) {
+  T *zc = nullptr;
+  int64_t zmax = 0;
+  for (int n = 2; n <= N - 1; ++n) zmax = std::max(zmax, R[n - 1] * dims[n - 1] * L[n]);
+  zc = c.arena.take<T>((size_t)zmax);
+  {
+    Gemm<T> g;  // W_{N-1} = H(Y_N) H(Sk_N)^T
+    const int64_t I = dims[N - 1];
+    g.A = Y[N - 1];
+    g.lda = I;
+    g.a_kc = true;
+    g.B = Sk[N - 1];
+    g.ldb = I;
+    g.b_kc = true;
+    g.C = W[N - 1];
+    g.ldc = L[N - 1];
+    g.M = R[N - 1];
+    g.N = L[N - 1];
+    g.K = I;
+    TTR_TRY(gemm(c, g));
+  }
+  for (int n = N - 1; n >= 2; --n) {
+    const int64_t I = dims[n - 1];
+    Gemm<T> g;  // V(Z_n) = V(Y_n) W_n
+    g.A = Y[n - 1];
+    g.lda = R[n];
+    g.a_kc = true;
+    g.B = W[n];
+    g.ldb = L[n];
+    g.b_kc = false;
+    g.C = zc;
+    g.ldc = L[n];
+    g.M = R[n - 1] * I;
+    g.N = L[n];
+    g.K = R[n];
+    TTR_TRY(gemm(c, g));
+    Gemm<T> h;  // W_{n-1} = H(Z_n) H(Sk_n)^T
+    h.A = zc;
+    h.lda = I * L[n];
+    h.a_kc = true;
+    h.B = Sk[n - 1];
+    h.ldb = I * L[n];
+    h.b_kc = true;
+    h.C = W[n - 1];
+    h.ldc = L[n - 1];
+    h.M = R[n - 1];
+    h.N = L[n - 1];
+    h.K = I * L[n];
+    TTR_TRY(gemm(c, h));
+  }
+  return TT_OK;
+}
+
+// ---------------------------------------------------------------- rounding
+// Y: s summands, cores Y[j*N + n].  Sk: sketch cores.  out: output cores.
+template <typename T>
+int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
+               T *const *out) {
+  const int N = P.N, s = P.s;
+  const int64_t *dims = P.dims.data();
+  const std::vector<int64_t> &L = P.ell;
+  const std::vector<int64_t> &Rs = P.Rsum;
+
+  // ---- W chains: stacked W_n = [W^(1)_n; ...; W^(s)_n], (sum_j R^(j)_n) x l_n
+  std::vector<T *> W(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) W[n] = c.arena.take<T>((size_t)(Rs[n] * L[n]));
+  for (int j = 0; j < s; ++j) {
+    std::vector<T *> Wj(N, nullptr);
+    for (int n = 1; n <= N - 1; ++n) {
+      int64_t off = 0;
+      for (int i = 0; i < j; ++i) off += P.R[i][n];
+      Wj[n] = W[n] ? W[n] + off * L[n] : nullptr;
+    }
+    TTR_TRY(wchain<T>(c, N, dims, P.R[j].data(), Y + (size_t)j * N, L.data(), Sk, Wj.data()));
+  }
+
+  // ---- buffers of the sweep
+  int64_t ys_max = 1, x_max = 1, m_max = 1;
+  for (int n = 1; n <= N - 1; ++n) {
+    ys_max = std::max(ys_max, L[n - 1] * dims[n - 1] * L[n]);
+    m_max = std::max(m_max, L[n] * Rs[n]);
+    if (n + 1 <= N - 1) x_max = std::max(x_max, L[n] * dims[n] * Rs[n + 1]);
+  }
+  T *ys = c.arena.take<T>((size_t)ys_max);
+  T *mbuf = c.arena.take<T>((size_t)m_max);
+  T *xb[2] = {c.arena.take<T>((size_t)x_max), c.arena.take<T>((size_t)x_max)};
+  const bool plain_first = (s == 1 && P.coeffs[0] == 1.0);
+  T *x1 = plain_first ? nullptr : c.arena.take<T>((size_t)(dims[0] * Rs[1]));
+  QrScratch qs;
+  const int64_t lm = P.max_ell;
+  qs.gram = c.arena.take<double>((size_t)std::max(lm * lm, 2 * lm));
+  qs.rinv = c.arena.take<double>((size_t)std::max(lm * lm, 2 * lm));
+  qs.q1 = c.arena.take<double>((size_t)ys_max * sizeof(T) / sizeof(double) + 1);
+  qs.flag = c.arena.take<int>(4);
+  // the QR's own split-K Gram uses the shared partial buffer
+  for (int n = 1; n <= N - 1; ++n) {
+    const size_t need = qr_partial_elems(L[n - 1] * dims[n - 1], L[n]);
+    c.partial_need = std::max(c.partial_need, need);
+  }
+  // sweep output: straight into `out` unless a truncation follows
+  std::vector<T *> xs(N + 1, nullptr);
+  for (int n = 1; n <= N; ++n)
+    xs[n] = P.truncate ? c.arena.take<T>((size_t)(L[n - 1] * dims[n - 1] * L[n])) : out[n - 1];
+  // truncation scratch
+  double *gbuf = nullptr, *lam = nullptr, *U = nullptr, *tails = nullptr;
+  T *Pf = nullptr, *Sf = nullptr, *tb[2] = {nullptr, nullptr};
+  if (P.truncate) {
+    gbuf = c.arena.take<double>((size_t)(lm * lm));
+    lam = c.arena.take<double>((size_t)lm);
+    U = c.arena.take<double>((size_t)(lm * lm));
+    tails = c.arena.take<double>((size_t)(N + 1));
+    Pf = c.arena.take<T>((size_t)(lm * lm));
+    Sf = c.arena.take<T>((size_t)(lm * lm));
+    int64_t tmax = 1;
+    for (int n = 2; n <= N - 1; ++n) tmax = std::max(tmax, L[n - 1] * dims[n - 1] * P.out[n]);
+    tb[0] = c.arena.take<T>((size_t)tmax);
+    tb[1] = c.arena.take<T>((size_t)tmax);
+  }
+  // ---- first core: X_1 = [c_1 Y^(1)_1 ... c_s Y^(s)_1]
+  const T *cur = nullptr;
+  if (plain_first) {
+    cur = Y[0];
+  } else {
+    int64_t off = 0;
+    for (int j = 0; j < s; ++j) {
+      const int64_t rj = P.R[j][1];
+      if (!c.dry)
+        TTR_TRY(copy2d<T>(x1 + off, Rs[1], Y[(size_t)j * N], rj, dims[0], rj, P.coeffs[j], 0.0,
+                          c.s));
+      off += rj;
+    }
+    cur = x1;
+  }
+
+  // ---- left-to-right sweep
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t m = L[n - 1] * dims[n - 1];
+    Gemm<T> g;  // Y_n = Z_n W_n
+    g.A = cur;
+    g.lda = Rs[n];
+    g.a_kc = true;
+    g.B = W[n];
+    g.ldb = L[n];
+    g.b_kc = false;
+    g.C = ys;
+    g.ldc = L[n];
+    g.M = m;
+    g.N = L[n];
+    g.K = Rs[n];
+    TTR_TRY(gemm(c, g));
+    qs.partial = c.partial;
+    if (!c.dry) TTR_TRY(qr_thin<T>(ys, xs[n], m, L[n], qs, c.s));
+    Gemm<T> h;  // M_n = Q^T Z_n
+    h.A = xs[n];
+    h.lda = L[n];
+    h.a_kc = false;
+    h.B = cur;
+    h.ldb = Rs[n];
+    h.b_kc = false;
+    h.C = mbuf;
+    h.ldc = Rs[n];
+    h.M = L[n];
+    h.N = Rs[n];
+    h.K = m;
+    TTR_TRY(gemm(c, h));
+    // next core
+    const int64_t I1 = dims[n];
+    const bool last = (n + 1 == N);
+    T *dst = last ? xs[N] : xb[n & 1];
+    int64_t offm = 0, offn = 0;
+    for (int j = 0; j < s; ++j) {
+      const T *Yj = Y[(size_t)j * N + n];
+      const int64_t rj = P.R[j][n], rj1 = P.R[j][n + 1];
+      Gemm<T> k;
+      k.A = mbuf + offm;  // columns offm.. of M_n
+      k.lda = Rs[n];
+      k.a_kc = true;
+      k.M = L[n];
+      k.K = rj;
+      if (s == 1 || last) {
+        // H(X_{n+1}) (+)= M^(j) H(Y^(j)_{n+1})
+        k.B = Yj;
+        k.ldb = I1 * rj1;
+        k.b_kc = false;
+        k.C = dst;
+        k.ldc = I1 * rj1;
+        k.N = I1 * rj1;
+        k.beta = (last && j > 0) ? T(1) : T(0);
+      } else {
+        // slice-wise: X_{n+1}(:, i, offn + r) = (M^(j) Y^(j)_{n+1}(:, i, :))(:, r)
+        k.B = Yj;
+        k.ldb = I1 * rj1;
+        k.b_kc = false;
+        k.C = dst + offn;
+        k.ldc = I1 * Rs[n + 1];
+        k.N = rj1;
+        k.batch = I1;
+        k.sB = rj1;
+        k.sC = Rs[n + 1];
+      }
+      TTR_TRY(gemm(c, k));
+      offm += rj;
+      offn += rj1;
+    }
+    cur = dst;
+  }
+
+  if (!P.truncate) return TT_OK;
+
+  // ---- right-to-left truncation of the left-orthogonal result
+  const T *hsrc = xs[N];
+  int64_t rr = 1;  // right rank of the current core
+  for (int n = N; n >= 2; --n) {
+    const int64_t lr = L[n - 1], k = P.out[n - 1], cols = dims[n - 1] * rr;
+    Gemm<T> g;  // G = H H^T (FP64 accumulate; T = double here)
+    g.A = hsrc;
+    g.lda = cols;
+    g.a_kc = true;
+    g.B = hsrc;
+    g.ldb = cols;
+    g.b_kc = true;
+    g.C = reinterpret_cast<T *>(gbuf);
+    g.ldc = lr;
+    g.M = lr;
+    g.N = lr;
+    g.K = cols;
+    TTR_TRY(gemm(c, g));
+    if (!c.dry) {
+      TTR_TRY(sym_eig(gbuf, lam, U, lr, c.s));
+      TTR_TRY(trunc_factors<T>(lam, U, lr, k, Pf, Sf, tails + n - 1, c.s));
+    }
+    Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n)
+    h.A = Sf;
+    h.lda = lr;
+    h.a_kc = true;
+    h.B = hsrc;
+    h.ldb = cols;
+    h.b_kc = false;
+    h.C = out[n - 1];
+    h.ldc = cols;
+    h.M = k;
+    h.N = cols;
+    h.K = lr;
+    TTR_TRY(gemm(c, h));
+    Gemm<T> p;  // X_{n-1} <- X_{n-1} x_3 (U s)
+    const int64_t rows = L[n - 2] * dims[n - 2];
+    p.A = xs[n - 1];
+    p.lda = lr;
+    p.a_kc = true;
+    p.B = Pf;
+    p.ldb = k;
+    p.b_kc = false;
+    T *dst = (n - 1 == 1) ? out[0] : tb[n & 1];
+    p.C = dst;
+    p.ldc = k;
+    p.M = rows;
+    p.N = k;
+    p.K = lr;
+    TTR_TRY(gemm(c, p));
+    hsrc = dst;
+    rr = k;
+  }
+  return TT_OK;
+}
+
+template <typename T>
+int sketch_exec(Ctx &c, const Problem &P, std::vector<T *> &Sk) {
+  Sk.assign(P.N, nullptr);
+  for (int n = 0; n < P.N; ++n)
+    Sk[n] = c.arena.take<T>((size_t)(P.ell[n] * P.dims[n] * P.ell[n + 1]));
+  return TT_OK;
+}
+
+// Runs `body(ctx)` twice: dry to size the split-K buffer, then for real with
+// the partial buffer first in the workspace.
+template <typename F>
+int run_with_workspace(void *workspace, size_t ws_bytes, hipStream_t s, F body) {
+  Ctx dry;
+  dry.dry = true;
+  TTR_TRY(body(dry));
+  const size_t partial_bytes = (dry.partial_need * sizeof(double) + 255) & ~size_t(255);
+  const size_t need = partial_bytes + dry.arena.off;
+  if (!workspace && need > 0) return fail(TT_EINVAL, "null workspace");
+  if (ws_bytes < need)
+    return fail(TT_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(TT_EINVAL, "workspace must be 256-byte aligned");
+  Ctx real;
+  real.dry = false;
+  real.s = s;
+  real.arena.base = static_cast<char *>(workspace);
+  real.partial = real.arena.take<double>(dry.partial_need);
+  real.partial_cap = dry.partial_need;
+  real.arena.off = partial_bytes;
+  return body(real);
+}
+
+template <typename F>
+int measure_workspace(F body, size_t *bytes) {
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  Ctx dry;
+  dry.dry = true;
+  TTR_TRY(body(dry));
+  *bytes = ((dry.partial_need * sizeof(double) + 255) & ~size_t(255)) + dry.arena.off;
+  return TT_OK;
+}
+
+}  // namespace
+}  // namespace ttr
+
+using namespace ttr;
+
+extern "C" {
+
+const char *tt_last_error(void) { return g_err.c_str(); }
+
+int tt_version(void) { return 100; }
+
+int tt_round_rand_plan(int32_t N, const int64_t *dims, const int64_t *ranks, int64_t target_rank,
+                       int64_t oversample, int64_t *sketch_ranks, int64_t *out_ranks) {
+  TTR_TRY(check_shape(N, dims, ranks, "tt_round_rand_plan"));
+  if (target_rank < 1) return fail(TT_EINVAL, "target_rank must be >= 1");
+  if (oversample < 0) return fail(TT_EINVAL, "oversample must be >= 0");
+  if (!sketch_ranks || !out_ranks) return fail(TT_EINVAL, "null output arrays");
+  std::vector<int64_t> ell, out;
+  plan_ranks(N, dims, ranks, target_rank, oversample, ell, out);
+  for (int n = 0; n <= N; ++n) {
+    sketch_ranks[n] = ell[n];
+    out_ranks[n] = out[n];
+  }
+  return TT_OK;
+}
+
+int tt_round_rand_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                            int64_t target_rank, int64_t oversample, int32_t prec, size_t *bytes) {
+  return tt_sum_round_workspace(1, N, dims, ranks, target_rank, oversample, prec, bytes);
+}
+
+int tt_sum_round_workspace(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                           int64_t target_rank, int64_t oversample, int32_t prec,
+                           size_t *bytes) {
+  Problem P;
+  TTR_TRY(make_problem(P, s, N, dims, ranks, target_rank, oversample, nullptr));
+  if (prec != TT_PREC_F64) return fail(TT_EUNSUPPORTED, "only TT_PREC_F64 is implemented");
+  if (N == 1) {
+    *bytes = 0;
+    return TT_OK;
+  }
+  return measure_workspace(
+      [&](Ctx &c) {
+        std::vector<double *> Sk;
+        TTR_TRY(sketch_exec<double>(c, P, Sk));
+        std::vector<const double *> Y((size_t)s * N, nullptr);
+        std::vector<double *> out(N, nullptr);
+        return round_exec<double>(c, P, Y.data(), (const double *const *)Sk.data(), out.data());
+      },
+      bytes);
+}
+
+int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims, const int64_t *sketch_ranks,
+                   int32_t dtype, void *const *cores, void *stream) {
+  TTR_TRY(check_shape(N, dims, sketch_ranks, "tt_make_sketch"));
+  TTR_TRY(check_ptrs(N, cores, "tt_make_sketch"));
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "unknown dtype");
+  return sketch_generate(seed, N, dims, sketch_ranks, dtype, cores, (hipStream_t)stream);
+}
+
+static int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                        const void *const *cores, const double *coeffs, int32_t dtype,
+                        int64_t target_rank, int64_t oversample, bool gen, uint64_t seed,
+                        const int64_t *sketch_ranks, const void *const *sketch_cores,
+                        int32_t prec, void *const *out_cores, void *workspace, size_t ws_bytes,
+                        void *stream) {
+  read_env();
+  Problem P;
+  TTR_TRY(make_problem(P, s, N, dims, ranks, target_rank, oversample, coeffs));
+  TTR_TRY(prec_supported(dtype, prec));
+  TTR_TRY(check_ptrs(s * N, cores, "input cores"));
+  TTR_TRY(check_ptrs(N, out_cores, "output cores"));
+  hipStream_t st = (hipStream_t)stream;
+  if (!gen) {
+    if (!sketch_ranks) return fail(TT_EINVAL, "null sketch ranks");
+    for (int n = 0; n <= N; ++n)
+      if (sketch_ranks[n] != P.ell[n])
+        return fail(TT_EINVAL, "sketch ranks differ from the plan's sketch ranks");
+    TTR_TRY(check_ptrs(N, sketch_cores, "sketch cores"));
+  }
+  if (N == 1) {
+    // a single core: the (weighted) sum itself
+    const int64_t cnt = dims[0];
+    double *dst = (double *)out_cores[0];
+    for (int j = 0; j < s; ++j)
+      TTR_TRY(copy2d<double>(dst, cnt, (const double *)cores[j], cnt, 1, cnt, P.coeffs[j],
+                             j == 0 ? 0.0 : 1.0, st));
+    return TT_OK;
+  }
+  const double *const *Y = (const double *const *)cores;
+  double *const *out = (double *const *)out_cores;
+  return run_with_workspace(workspace, ws_bytes, st, [&](Ctx &c) -> int {
+    std::vector<double *> Skw;
+    std::vector<const double *> Sk(N, nullptr);
+    if (gen) {
+      TTR_TRY(sketch_exec<double>(c, P, Skw));
+      if (!c.dry) {
+        TTR_TRY(sketch_generate(seed, N, dims, P.ell.data(), TT_F64, (void *const *)Skw.data(),
+                                c.s));
+      }
+      for (int n = 0; n < N; ++n) Sk[n] = Skw[n];
+    } else {
+      TTR_TRY(sketch_exec<double>(c, P, Skw));  // keep the layout identical to the query
+      for (int n = 0; n < N; ++n) Sk[n] = (const double *)sketch_cores[n];
+    }
+    return round_exec<double>(c, P, Y, Sk.data(), out);
+  });
+}
+
+int tt_round_rand(int32_t N, const int64_t *dims, const int64_t *ranks, const void *const *cores,
+                  int32_t dtype, int64_t target_rank, int64_t oversample, uint64_t sketch_seed,
+                  int32_t prec, void *const *out_cores, void *workspace, size_t ws_bytes,
+                  void *stream) {
+  return round_common(1, N, dims, ranks, cores, nullptr, dtype, target_rank, oversample, true,
+                      sketch_seed, nullptr, nullptr, prec, out_cores, workspace, ws_bytes,
+                      stream);
+}
+
+int tt_round_rand_with_sketch(int32_t N, const int64_t *dims, const int64_t *ranks,
+                              const void *const *cores, int32_t dtype, int64_t target_rank,
+                              int64_t oversample, const int64_t *sketch_ranks,
+                              const void *const *sketch_cores, int32_t prec,
+                              void *const *out_cores, void *workspace, size_t ws_bytes,
+                              void *stream) {
+  return round_common(1, N, dims, ranks, cores, nullptr, dtype, target_rank, oversample, false, 0,
+                      sketch_ranks, sketch_cores, prec, out_cores, workspace, ws_bytes, stream);
+}
+
+int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                 const void *const *cores, const double *coeffs, int32_t dtype,
+                 int64_t target_rank, int64_t oversample, uint64_t sketch_seed, int32_t prec,
+                 void *const *out_cores, void *workspace, size_t ws_bytes, void *stream) {
+  return round_common(s, N, dims, ranks, cores, coeffs, dtype, target_rank, oversample, true,
+                      sketch_seed, nullptr, nullptr, prec, out_cores, workspace, ws_bytes,
+                      stream);
+}
+
+int tt_partial_contractions_rl_workspace(int32_t N, const int64_t *dims, const int64_t *ranks_x,
+                                         const int64_t *ranks_y, size_t *bytes) {
+  TTR_TRY(check_shape(N, dims, ranks_x, "X"));
+  TTR_TRY(check_shape(N, dims, ranks_y, "Y"));
+  if (N < 2) return fail(TT_EINVAL, "partial contractions need N >= 2");
+  return measure_workspace(
+      [&](Ctx &c) {
+        std::vector<const double *> X(N, nullptr), Yc(N, nullptr);
+        std::vector<double *> W(N, nullptr);
+        return wchain<double>(c, N, dims, ranks_x, X.data(), ranks_y, Yc.data(), W.data());
+      },
+      bytes);
+}
+
+int tt_partial_contractions_rl(int32_t N, const int64_t *dims, const int64_t *ranks_x,
+                               const void *const *x_cores, const int64_t *ranks_y,
+                               const void *const *y_cores, void *const *W_out, void *workspace,
+                               size_t ws_bytes, void *stream) {
+  TTR_TRY(check_shape(N, dims, ranks_x, "X"));
+  TTR_TRY(check_shape(N, dims, ranks_y, "Y"));
+  if (N < 2) return fail(TT_EINVAL, "partial contractions need N >= 2");
+  TTR_TRY(check_ptrs(N, x_cores, "X cores"));
+  TTR_TRY(check_ptrs(N, y_cores, "Y cores"));
+  TTR_TRY(check_ptrs(N - 1, W_out, "W"));
+  std::vector<double *> W(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) W[n] = (double *)W_out[n - 1];
+  return run_with_workspace(workspace, ws_bytes, (hipStream_t)stream, [&](Ctx &c) {
+    return wchain<double>(c, N, dims, ranks_x, (const double *const *)x_cores, ranks_y,
+                          (const double *const *)y_cores, W.data());
+  });
+}
+
+}  // extern "C"

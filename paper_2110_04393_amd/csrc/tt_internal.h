@@ -1,0 +1,125 @@
+// Internal declarations shared by the HIP translation units of libttround.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tt_round.h"
+
+namespace ttr {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+
+struct Status {
+  int code = TT_OK;
+  std::string msg;
+};
+
+#define TTR_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::ttr::fail(TT_EHIP, std::string(#call) + ": " +                \
+                                     hipGetErrorString(e_));                 \
+  } while (0)
+
+#define TTR_TRY(expr)            \
+  do {                           \
+    int s_ = (expr);             \
+    if (s_ != TT_OK) return s_;  \
+  } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures (used by the *_workspace queries), so the query and the run share
+// one layout function.
+struct Arena {
+  char *base = nullptr;
+  size_t off = 0;
+  size_t cap = 0;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ---------------------------------------------------------------- GEMM
+// C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n), C row-major (ldc).
+// A(m,k) = a_kc ? A[m*lda + k] : A[k*lda + m]
+// B(k,n) = b_kc ? B[n*ldb + k] : B[k*ldb + n]
+// With splits > 1 the K range is cut into `splits` chunks whose partial
+// products go to `partial` (splits*M*N elements) and are summed in chunk
+// order by a second kernel (deterministic).
+template <typename T>
+struct Gemm {
+  const T *A = nullptr;
+  int64_t lda = 0;
+  bool a_kc = true;
+  const T *B = nullptr;
+  int64_t ldb = 0;
+  bool b_kc = false;
+  T *C = nullptr;
+  int64_t ldc = 0;
+  int64_t M = 0, N = 0, K = 0;
+  T alpha = 1, beta = 0;
+  int splits = 1;
+  T *partial = nullptr;
+  // batch of independent products: operand pointers advance by sA/sB/sC per
+  // batch entry (split-K is not combined with batching)
+  int64_t batch = 1;
+  int64_t sA = 0, sB = 0, sC = 0;
+};
+
+// Number of K chunks chosen for a problem (0 = let the planner decide);
+// returns the partial-buffer element count needed.
+int gemm_pick_splits(int64_t M, int64_t N, int64_t K);
+template <typename T>
+int gemm_run(const Gemm<T> &g, hipStream_t s);
+
+// ---------------------------------------------------------------- sketch
+int sketch_generate(uint64_t seed, int N, const int64_t *dims, const int64_t *sranks,
+                    int dtype, void *const *cores, hipStream_t s);
+
+// ---------------------------------------------------------------- QR
+// Thin QR of the m x n row-major matrix Y (n <= TT_MAX_SKETCH_RANK, m >= n),
+// Q written row-major m x n to Q (may not alias Y), diag(R) >= 0.
+struct QrScratch {
+  double *gram = nullptr;      // n*n
+  double *rinv = nullptr;      // n*n
+  double *q1 = nullptr;        // m*n (T)
+  int *flag = nullptr;         // 1 int
+  void *partial = nullptr;     // split-K partials
+};
+size_t qr_partial_elems(int64_t m, int64_t n);
+template <typename T>
+int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s);
+void qr_set_mode(int mode);  // 0 auto, 1 force householder, 2 force cholqr2
+
+// ---------------------------------------------------------------- eigen
+// Symmetric eigendecomposition of an n x n matrix (n <= TT_MAX_SKETCH_RANK)
+// by cyclic Jacobi: eigenvalues descending to `lam`, eigenvectors as the
+// columns of U (row-major n x n).
+int sym_eig(const double *G, double *lam, double *U, int64_t n, hipStream_t s);
+
+// Truncation factors from (lam, U): P = U_k sqrt(lam_k) (n x k, row-major),
+// S = sqrt(lam_k)^-1 U_k^T (k x n, row-major), tail = sum_{j>=k} max(lam_j,0).
+template <typename T>
+int trunc_factors(const double *lam, const double *U, int64_t n, int64_t k, T *P, T *S,
+                  double *tail, hipStream_t s);
+
+// ---------------------------------------------------------------- misc
+// dst[r*ldd + c] = alpha * src[r*lds + c] + beta * dst[r*ldd + c]
+template <typename T>
+int copy2d(T *dst, int64_t ldd, const T *src, int64_t lds, int64_t rows, int64_t cols,
+           double alpha, double beta, hipStream_t s);
+
+}  // namespace ttr

@@ -1,0 +1,89 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/tt_round.h declares, plans ranks like the oracle and rejects bad
+arguments before touching the GPU."""
+import ctypes
+import random
+
+import pytest
+
+import oracle as O
+import paper_2110_04393_amd as tt
+from paper_2110_04393_amd import _lib as L
+
+
+def test_library_exports_every_header_function():
+    lib = tt.lib()
+    names = tt.header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert tt.version() >= 100
+
+
+def test_plan_matches_oracle():
+    rng = random.Random(0)
+    for _ in range(200):
+        N = rng.randint(1, 9)
+        dims = [rng.randint(1, 7) for _ in range(N)]
+        ranks = [1] + [rng.randint(1, 12) for _ in range(N - 1)] + [1]
+        t, p = rng.randint(1, 10), rng.randint(0, 6)
+        assert tt.plan(dims, ranks, t, p) == tuple(O.plan_ranks(dims, ranks, t, p))
+
+
+def test_workspace_queries_positive():
+    assert tt.round_rand_workspace([100] * 30, [1] + [200] * 29 + [1], 50, 10) > 0
+    assert tt.sum_round_workspace([128] * 16, [[1] + [20] * 15 + [1]] * 20, 60, 10) > 0
+
+
+@pytest.mark.parametrize("dims,ranks,t,p", [
+    ([3, 3], [1, 2, 2], 1, 0),        # last rank != 1
+    ([3, 0, 3], [1, 2, 2, 1], 1, 0),  # zero mode size
+    ([3, 3], [1, 2, 1], 0, 0),        # target < 1
+    ([3, 3], [1, 2, 1], 1, -1),       # oversample < 0
+])
+def test_plan_rejects_bad_arguments(dims, ranks, t, p):
+    with pytest.raises(tt.TTError) as e:
+        tt.plan(dims, ranks, t, p)
+    assert e.value.status == L.TT_EINVAL
+    assert len(str(e.value)) > 10
+
+
+def test_unsupported_sketch_rank():
+    with pytest.raises(tt.TTError) as e:
+        tt.round_rand_workspace([100] * 5, [1, 200, 200, 200, 200, 1], 150, 10)
+    assert e.value.status == L.TT_EUNSUPPORTED
+
+
+def _call_round(ws_bytes, dtype=L.TT_F64, prec=L.TT_PREC_F64, target=2):
+    # fake (never dereferenced) device pointers: validation fails before any launch
+    N = 3
+    dims, ranks = [4, 4, 4], [1, 3, 3, 1]
+    fake = [0x1000 * (i + 1) for i in range(N)]
+    outs = [0x9000 * (i + 1) for i in range(N)]
+    st = L.lib().tt_round_rand(N, L.i64_array(dims), L.i64_array(ranks), L.ptr_array(fake),
+                               dtype, target, 0, 7, prec, L.ptr_array(outs),
+                               ctypes.c_void_p(0x100000), ws_bytes, None)
+    return st, L.lib().tt_last_error().decode()
+
+
+def test_round_rejects_small_workspace_before_launch():
+    st, msg = _call_round(0)
+    assert st == L.TT_ENOMEM and "workspace" in msg
+
+
+def test_round_rejects_unknown_precision():
+    st, msg = _call_round(1 << 30, prec=7)
+    assert st == L.TT_EINVAL
+
+
+def test_round_rejects_null_cores():
+    N = 2
+    st = L.lib().tt_round_rand(N, L.i64_array([3, 3]), L.i64_array([1, 2, 1]), None, 0, 1, 0, 0,
+                               0, L.ptr_array([1, 2]), None, 0, None)
+    assert st == L.TT_EINVAL
+
+
+def test_sketch_rejects_bad_shape():
+    st = L.lib().tt_make_sketch(1, 2, L.i64_array([3, 3]), L.i64_array([1, 2, 2]), 0,
+                                L.ptr_array([1, 2]), None)
+    assert st == L.TT_EINVAL

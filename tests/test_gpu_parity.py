@@ -1,0 +1,202 @@
+"""GPU parity of the HIP path (called through the C ABI) with the FP64 oracle
+on the same seeded inputs."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tt_inputs as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(cores):
+    return [torch.from_numpy(np.ascontiguousarray(c)).cuda() for c in cores]
+
+
+def host(cores):
+    torch.cuda.synchronize()
+    return [c.detach().cpu().numpy() for c in cores]
+
+
+def max_core_rel(a, b):
+    return max(float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)) for x, y in zip(a, b))
+
+
+# ------------------------------------------------------------------ sketch
+
+@pytest.mark.parametrize("shape", [
+    ([10] * 8, [1, 10, 15, 15, 15, 15, 15, 10, 1]),
+    ([7, 5, 3], [1, 3, 2, 1]),
+    ([100, 100, 100], [1, 60, 60, 1]),
+])
+def test_device_sketch_matches_oracle(gpu_lib, shape):
+    dims, sr = shape
+    say(f"sketch {dims} {sr}")
+    S = host(gpu_lib.make_sketch(2001, dims, sr))
+    R = O.make_sketch(2001, dims, sr)
+    for a, b in zip(S, R):
+        assert a.shape == b.shape
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-15 * np.abs(b).max())
+
+
+def test_device_sketch_float32(gpu_lib):
+    say("sketch f32")
+    S = host(gpu_lib.make_sketch(5, [6, 7], [1, 4, 1], dtype=torch.float32))
+    R = O.make_sketch(5, [6, 7], [1, 4, 1])
+    for a, b in zip(S, R):
+        np.testing.assert_array_equal(a, b.astype(np.float32))
+
+
+# ------------------------------------------------------------------ Algorithm 3
+
+@pytest.mark.parametrize("case", [
+    (5, 3, 4, 3),      # tiny
+    (6, 17, 37, 21),   # ragged tiles
+    (4, 100, 200, 60),  # workload-sized cores
+    (2, 5, 3, 2),      # N = 2
+])
+def test_partial_contractions_match_oracle(gpu_lib, case):
+    N, I, R, l = case
+    say(f"W chain N={N} I={I} R={R} l={l}")
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    X = G.random_tt(11, dims, ranks, scale="nominal")
+    Y = G.random_tt(12, dims, [1] + [l] * (N - 1) + [1], scale="def31")
+    W = gpu_lib.partial_contractions_rl(dev(X), dev(Y))
+    torch.cuda.synchronize()
+    Wo = O.partial_contractions_rl(X, Y)
+    for n in range(1, N):
+        a = W[n].cpu().numpy()
+        err = np.linalg.norm(a - Wo[n]) / np.linalg.norm(Wo[n])
+        assert err < 1e-13, (n, err)
+
+
+# ------------------------------------------------------------------ Algorithm 5
+
+def test_small_sum_workload_exact(gpu_lib):
+    # X = A + A (formal rank 20) rounded to 10 through a sketch of 15 -> 2A
+    say("A+A -> 2A")
+    w = G.workload_small_sum()
+    out = host(gpu_lib.round_rand(dev(w["X"]), w["target"], w["oversample"],
+                                  seed=w["sketch_seed"]))
+    assert O.ranks_of(out) == [1] + [10] * 7 + [1]
+    twoA = [2.0 * w["A"][0]] + [c.copy() for c in w["A"][1:]]
+    assert O.rel_diff(out, twoA) <= 1e-12
+    ref = O.round_rand(w["X"], w["target"], w["oversample"], seed=w["sketch_seed"])
+    assert O.rel_diff(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("qr", ["auto", "householder", "cholqr2"])
+@pytest.mark.parametrize("case", [
+    (6, 9, 12, 7, 0),     # small: Householder panels
+    (5, 40, 50, 23, 0),   # ragged, CholeskyQR2 panels
+    (4, 64, 64, 32, 0),
+])
+def test_rto_cores_match_oracle(gpu_lib, case, qr, monkeypatch):
+    # without truncation the output is unique (diag R >= 0): compare core by core
+    N, I, R, t, p = case
+    say(f"RtO cores {case} qr={qr}")
+    if qr != "auto":
+        monkeypatch.setenv("TT_QR", qr)
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    Y = G.random_tt(21 + N, dims, ranks, scale="nominal")
+    out = host(gpu_lib.round_rand(dev(Y), t, p, seed=77))
+    ref = O.round_rand(Y, t, p, seed=77)
+    assert [c.shape for c in out] == [c.shape for c in ref]
+    assert max_core_rel(out, ref) < 1e-10
+    for c in out[:-1]:
+        Vn = O.V(c)
+        assert np.abs(Vn.T @ Vn - np.eye(Vn.shape[1])).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", [
+    (6, 9, 12, 5, 3),
+    (5, 40, 50, 20, 6),
+    (3, 7, 5, 2, 1),
+])
+def test_rto_truncated_matches_oracle(gpu_lib, case):
+    N, I, R, t, p = case
+    say(f"RtO truncated {case}")
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    Y = G.random_tt(31 + N, dims, ranks, scale="nominal")
+    out = host(gpu_lib.round_rand(dev(Y), t, p, seed=5))
+    ref = O.round_rand(Y, t, p, seed=5)
+    assert O.ranks_of(out) == O.ranks_of(ref)
+    assert O.rel_diff(out, ref) < 1e-10
+    for c in out[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-10
+
+
+def test_rto_with_given_sketch_and_scale_invariance(gpu_lib):
+    say("given sketch")
+    dims, ranks = G.uniform_tt_shape(5, 20, 16)
+    Y = G.random_tt(41, dims, ranks, scale="nominal")
+    ell, _ = O.plan_ranks(dims, ranks, 8, 0)
+    S = O.make_sketch(3, dims, ell)
+    S2 = [c * f for c, f in zip(S, [1e10, 2.0, 0.5, 3.0, 1e-12])]
+    a = host(gpu_lib.round_rand(dev(Y), 8, 0, sketch=dev(S)))
+    b = host(gpu_lib.round_rand(dev(Y), 8, 0, sketch=dev(S2)))
+    ref = O.rto_sweep(Y, O.partial_contractions_rl(Y, S))
+    assert max_core_rel(a, ref) < 1e-10
+    assert max_core_rel(b, ref) < 1e-10
+
+
+def test_order_one_and_two(gpu_lib):
+    say("N=1, N=2")
+    Y1 = [np.random.default_rng(0).standard_normal((1, 7, 1))]
+    out = host(gpu_lib.round_rand(dev(Y1), 3, 0, seed=1))
+    np.testing.assert_array_equal(out[0], Y1[0])
+    dims, ranks = [6, 5], [1, 4, 1]
+    Y2 = G.random_tt(3, dims, ranks, scale="unit")
+    out = host(gpu_lib.round_rand(dev(Y2), 2, 1, seed=2))
+    ref = O.round_rand(Y2, 2, 1, seed=2)
+    assert O.rel_diff(out, ref) < 1e-11
+
+
+def test_deterministic(gpu_lib):
+    say("determinism")
+    dims, ranks = G.uniform_tt_shape(6, 30, 40)
+    Y = dev(G.random_tt(51, dims, ranks, scale="nominal"))
+    a = host(gpu_lib.round_rand(Y, 10, 4, seed=9))
+    b = host(gpu_lib.round_rand(Y, 10, 4, seed=9))
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------------ Algorithm 7
+
+@pytest.mark.parametrize("case", [
+    (2, 5, 6, [3, 4], 3, 1),
+    (4, 6, 9, [5, 3, 6, 4], 6, 2),
+])
+def test_sum_round_matches_oracle(gpu_lib, case):
+    s, N, I, Rs, t, p = case
+    say(f"sum {case}")
+    dims = [I] * N
+    tts = [G.random_tt(60 + j, dims, [1] + [Rs[j]] * (N - 1) + [1], scale="nominal")
+           for j in range(s)]
+    coeffs = G.sum_coefficients(9, s)
+    out = host(gpu_lib.sum_round([dev(x) for x in tts], coeffs, t, p, seed=4))
+    ref = O.round_sum_rand(tts, coeffs, t, p, seed=4)
+    assert O.ranks_of(out) == O.ranks_of(ref)
+    assert O.rel_diff(out, ref) < 1e-10
+
+
+def test_sum_round_small_workload_exact(gpu_lib):
+    say("sum A + A")
+    w = G.workload_small_sum()
+    out = host(gpu_lib.sum_round([dev(w["A"]), dev(w["A"])], None, w["target"], w["oversample"],
+                                 seed=w["sketch_seed"]))
+    twoA = [2.0 * w["A"][0]] + [c.copy() for c in w["A"][1:]]
+    assert O.rel_diff(out, twoA) <= 1e-12

@@ -384,7 +384,7 @@ def superdiagonal_tt(sigmas, N):
 
 
 def test_round_svd_eps_threshold_closed_form():
-    # Algorithm 2 line 3: eps = ||Y|| eps0 / sqrt(N-1).  With singular values
+    # Algorithm 2 threshold: eps = ||Y|| eps0 / sqrt(N-1).  With singular values
     # (1,1,1,a) at every bond, N=5, eps0=1e-3: eps = 8.66e-4 < a = 1.2e-3, so
     # rank 4 is kept; a threshold without the sqrt(N-1) would cut to 3.
     a = 1.2e-3
