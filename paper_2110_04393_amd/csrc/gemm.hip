@@ -15,8 +15,9 @@
 // cycles per SIMD on gfx950, so 2 fragment loads per 4 MFMAs keep the matrix
 // pipe fed without LDS staging.
 //
-// Output layout of a 16x16 block (MFMA D): lane l, register j holds row
-// 4 (l / 16) + j, column l % 16.
+// Output layout of a 16x16 block (MFMA D), lane l = r + 16 q, register j:
+// column r; row q + 4 j for v_mfma_f64_16x16x4f64 (measured on gfx950) and
+// 4 q + j for v_mfma_f32_16x16x4f32.
 //
 // Split-K: the K range is cut into chunks; each chunk writes its partial tile
 // and a second kernel adds the chunks in index order, so results are bitwise
@@ -39,6 +40,10 @@ template <>
 struct AccOf<float> {
   typedef f4_t type;
 };
+
+// row of register j of lane group q in a 16x16 accumulator block
+__device__ __forceinline__ int acc_row(double, int q, int j) { return q + 4 * j; }
+__device__ __forceinline__ int acc_row(float, int q, int j) { return 4 * q + j; }
 
 __device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm<T> g, TileMap tm) {
       if (col >= g.N) continue;
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int64_t row = m0 + 16 * i + 4 * q + jj;
+        const int64_t row = m0 + 16 * i + acc_row(T(0), q, jj);
         if (row >= g.M) continue;
         const T v = acc[i][j][jj];
         if (g.splits > 1) {
