@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of randomized TT-rounding (Randomize-then-Orthogonalize) on one
+MI355X.
+
+A step is one whole rounding of one synthetic TT already resident in HBM:
+sketch drawn on the device (Definition 3.1), partial contractions
+(Algorithm 3), left-to-right orthogonalisation sweep (Algorithm 5) and the
+right-to-left truncation to the target rank.  Default workload: N=30,
+I=100, rank 200, cores N(0,1)/sqrt(I R), sketch rank 60 (target 50 +
+oversampling 10), FP64.
+
+Prints one JSON line.  `value` is milliseconds per rounding (lower is
+better).  `roofline` covers the dominant kernel, timed with HIP events on its
+own launch stream during a second pass over the same steps.  `cpu_baseline`
+times the FP64 numpy oracle on the host on whole roundings of the same input.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3}  # dense MFMA TFLOP/s (MI355X datasheet)
+HBM_PEAK_GBS = 8000.0
+METRIC = "ms per randomized TT-rounding + %MFMA peak; mixed-prec vs FP64 at tol"
+
+SITE_NAMES = {0: "wchain_z", 1: "wchain_w", 2: "sweep_y", 3: "sweep_m", 4: "sweep_next",
+              5: "trunc"}
+SITE_KERNEL = {0: "gemm_kernel (V(Y_n) W_n, partial contractions)",
+               4: "gemm_kernel (M_n H(Y_{n+1}), next core)"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def site_flops(site, dims, ranks, ell, summand_ranks=None):
+    """Algorithmic flops (2mnk per GEMM) of every launch from one call site."""
+    N = len(dims)
+    f = []
+    if site == 0:  # V(Y_n) W_n, n = N-1..2, per summand
+        srs = summand_ranks or [ranks]
+        for R in srs:
+            for n in range(N - 1, 1, -1):
+                f.append(2.0 * R[n - 1] * dims[n - 1] * R[n] * ell[n])
+    elif site == 4:  # M_n H(Y_{n+1}), n = 1..N-1, per summand
+        srs = summand_ranks or [ranks]
+        for n in range(1, N):
+            for R in srs:
+                f.append(2.0 * ell[n] * R[n] * dims[n] * R[n + 1])
+    else:
+        raise ValueError(site)
+    return f
+
+
+def make_workload(name):
+    import tt_inputs as G
+    if name == "single_tt":
+        w = G.workload_single_tt()
+        desc = ("single TT, N=30, I=100, rank 200, cores N(0,1)/sqrt(I*R); sketch rank 60 "
+                "(target 50 + oversample 10); truncated to rank 50")
+        return dict(kind="single", inputs=w["X"], target=w["target"], over=w["oversample"],
+                    seed=w["sketch_seed"], desc=desc)
+    if name == "small_sum":
+        w = G.workload_small_sum()
+        return dict(kind="single", inputs=w["X"], target=w["target"], over=w["oversample"],
+                    seed=w["sketch_seed"],
+                    desc="A+A assembled (N=8, I=10, rank 10 -> formal 20), sketch 15, rank 10")
+    if name == "gmres_sum":
+        w = G.workload_gmres_sum()
+        return dict(kind="sum", inputs=w["summands"], coeffs=w["coeffs"], target=w["target"],
+                    over=w["oversample"], seed=w["sketch_seed"],
+                    desc="sum of 20 TTs, N=16, I=128, rank 20 each (formal 400), "
+                         "coefficients U(-1,1), sketch 70, rank 60")
+    raise ValueError(name)
+
+
+def cpu_baseline(wl, gpu_out, budget_s=12.0, max_reps=5):
+    """The FP64 oracle on the host's cores: whole roundings of the same input."""
+    import numpy as np
+
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    times = []
+    ref = None
+    t_all = time.perf_counter()
+    while len(times) < max_reps and (time.perf_counter() - t_all) < budget_s:
+        t0 = time.perf_counter()
+        if wl["kind"] == "single":
+            ref = O.round_rand(wl["inputs"], wl["target"], wl["over"], seed=wl["seed"])
+        else:
+            ref = O.round_sum_rand(wl["inputs"], wl["coeffs"], wl["target"], wl["over"],
+                                   seed=wl["seed"])
+        times.append(time.perf_counter() - t0)
+    err = O.rel_diff([np.asarray(c) for c in gpu_out], ref)
+    med = statistics.median(times) * 1e3
+    return dict(value=round(med, 3), unit="ms", cores=int(cores), kind="oracle",
+                sample=f"{len(times)} whole roundings of the benchmark input "
+                       f"(median; {sum(times):.1f} s of CPU work)"), err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="single_tt",
+                    choices=["single_tt", "gmres_sum", "small_sum"])
+    ap.add_argument("--prec", default="f64", choices=["f64"])
+    ap.add_argument("--site", type=int, default=None,
+                    help="call site whose kernel the roofline covers (default: dominant)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the rounding "
+              "path has no multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2110_04393_amd as tt
+    from paper_2110_04393_amd import _lib as L
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    if wl["kind"] == "single":
+        cores = [torch.from_numpy(c).to(dev) for c in wl["inputs"]]
+        dims = [int(c.shape[1]) for c in cores]
+        ranks = [1] + [int(c.shape[2]) for c in cores]
+        plan = tt.RoundPlan(dims, ranks, wl["target"], wl["over"], args.prec, dev)
+        summand_ranks = None
+
+        def step():
+            return plan.run(cores, seed=wl["seed"])
+    else:
+        summ = [[torch.from_numpy(c).to(dev) for c in t] for t in wl["inputs"]]
+        dims = [int(c.shape[1]) for c in summ[0]]
+        summand_ranks = [[1] + [int(c.shape[2]) for c in t] for t in summ]
+        plan = tt.RoundPlan(dims, None, wl["target"], wl["over"], args.prec, dev,
+                            summand_ranks=summand_ranks)
+        ranks = plan.ranks
+
+        def step():
+            return plan.run_sum(summ, wl["coeffs"], seed=wl["seed"])
+
+    ell = plan.sketch_ranks
+    log(f"workload: {wl['desc']}; sketch ranks {ell[:4]}..., out ranks {plan.out_ranks[:4]}...")
+    log(f"workspace {plan.ws_bytes / 2**20:.1f} MiB")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # ---- timed region: exactly K steps
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f})")
+
+    # ---- per-site kernel timing (second pass, same steps)
+    import ctypes
+    site_ms = {}
+    for site in (0, 4):
+        L.check(L.lib().tt_timing_start(site, 64 * args.steps))
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        tot = ctypes.c_double(0)
+        cnt = ctypes.c_int32(0)
+        L.check(L.lib().tt_timing_stop(ctypes.byref(tot), ctypes.byref(cnt)))
+        fl = site_flops(site, dims, ranks, ell, summand_ranks)
+        site_ms[site] = (tot.value, cnt.value, sum(fl) * args.steps)
+        log(f"site {SITE_NAMES[site]}: {cnt.value} launches, {tot.value / max(cnt.value, 1) * 1e3:.1f} us avg, "
+            f"{sum(fl) * args.steps / (tot.value * 1e-3) / 1e12 if tot.value else 0:.2f} TFLOP/s")
+    site = args.site if args.site is not None else max(site_ms, key=lambda k: site_ms[k][0])
+    tot_ms, cnt, flops = site_ms[site]
+    achieved = flops / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
+    peak = PEAK[args.prec]
+    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(achieved / peak, 4), traffic=None,
+                    kernel=SITE_KERNEL.get(site, SITE_NAMES[site]),
+                    launches_per_step=cnt // max(args.steps, 1),
+                    avg_launch_us=round(tot_ms / max(cnt, 1) * 1e3, 2),
+                    flops_per_step=flops / args.steps)
+
+    out = [c.detach().cpu().numpy() for c in step()]
+    torch.cuda.synchronize()
+
+    res = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "N": len(dims), "I": dims[0],
+                   "rank": max(ranks), "sketch_rank": max(ell), "target_rank": wl["target"],
+                   "precision": args.prec},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        cb, err = cpu_baseline(wl, out, budget_s=args.cpu_budget)
+        res["cpu_baseline"] = cb
+        res["accuracy"] = {"rel_err_vs_fp64_oracle": float(f"{err:.3e}")}
+        log(f"oracle: {cb['value']} ms/rounding on {cb['cores']} threads; GPU rel err {err:.2e}")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

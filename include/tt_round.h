@@ -196,6 +196,26 @@ TT_API int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t
                  int32_t prec, void *const *out_cores, void *workspace,
                  size_t ws_bytes, void *stream);
 
+/*
+ * Kernel timing (instrumentation, off by default).  tt_timing_start arms a
+ * recorder for one call site of the rounding path: every later launch from
+ * that site is bracketed by a pair of HIP events recorded on the launch
+ * stream (up to `capacity` launches).  tt_timing_stop waits for the events,
+ * writes the summed launch time in milliseconds and the launch count, and
+ * disarms the recorder.  Sites: see tt_timing_site.  Not thread-safe: one
+ * recorder per process.
+ */
+typedef enum {
+  TT_SITE_WCHAIN_Z = 0,    /* V(Z_n) = V(Y_n) W_n            (Algorithm 3)   */
+  TT_SITE_WCHAIN_W = 1,    /* W_{n-1} = H(Z_n) H(R_n)^T      (Algorithm 3)   */
+  TT_SITE_SWEEP_Y = 2,     /* Y_n = Z_n W_n                  (Algorithm 5)   */
+  TT_SITE_SWEEP_M = 3,     /* M_n = Q^T Z_n                  (Algorithm 5)   */
+  TT_SITE_SWEEP_NEXT = 4,  /* H(X_{n+1}) = M_n H(Y_{n+1})    (Algorithm 5)   */
+  TT_SITE_TRUNC = 5        /* truncation GEMMs                               */
+} tt_timing_site;
+TT_API int tt_timing_start(int32_t site, int32_t capacity);
+TT_API int tt_timing_stop(double *total_ms, int32_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,8 +90,16 @@ struct Ctx {
   size_t partial_cap = 0;
 };
 
+// Opt-in launch timer (tt_timing_start / tt_timing_stop).
+struct Timer {
+  int site = -1;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+  size_t used = 0;
+};
+Timer g_timer;
+
 template <typename T>
-int gemm(Ctx &c, Gemm<T> g) {
+int gemm(Ctx &c, Gemm<T> g, int site = -1) {
   const int sp = (g.batch > 1) ? 1 : gemm_pick_splits(g.M, g.N, g.K);
   const size_t need = sp > 1 ? (size_t)sp * g.M * g.N : 0;
   c.partial_need = std::max(c.partial_need, need);
@@ -99,7 +107,14 @@ int gemm(Ctx &c, Gemm<T> g) {
   if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split-K buffer too small");
   g.splits = sp;
   g.partial = reinterpret_cast<T *>(c.partial);
-  return gemm_run<T>(g, c.s);
+  const bool timed = site >= 0 && site == g_timer.site && g_timer.used + 2 <= g_timer.ev.size();
+  if (timed) TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used], c.s));
+  TTR_TRY(gemm_run<T>(g, c.s));
+  if (timed) {
+    TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used + 1], c.s));
+    g_timer.used += 2;
+  }
+  return TT_OK;
 }
 
 // Problem description shared by single-TT and sum rounding.  A single TT is
@@ -170,7 +185,7 @@ int wchain(Ctx &c, int N, const int64_t *dims, const int64_t *R, const T *const 
     g.M = R[N - 1];
     g.N = L[N - 1];
     g.K = I;
-    TTR_TRY(gemm(c, g));
+    TTR_TRY(gemm(c, g, TT_SITE_WCHAIN_W));
   }
   for (int n = N - 1; n >= 2; --n) {
     const int64_t I = dims[n - 1];
@@ -186,7 +201,7 @@ int wchain(Ctx &c, int N, const int64_t *dims, const int64_t *R, const T *const 
     g.M = R[n - 1] * I;
     g.N = L[n];
     g.K = R[n];
-    TTR_TRY(gemm(c, g));
+    TTR_TRY(gemm(c, g, TT_SITE_WCHAIN_Z));
     Gemm<T> h;  // W_{n-1} = H(Z_n) H(Sk_n)^T
     h.A = zc;
     h.lda = I * L[n];
@@ -199,7 +214,7 @@ int wchain(Ctx &c, int N, const int64_t *dims, const int64_t *R, const T *const 
     h.M = R[n - 1];
     h.N = L[n - 1];
     h.K = I * L[n];
-    TTR_TRY(gemm(c, h));
+    TTR_TRY(gemm(c, h, TT_SITE_WCHAIN_W));
   }
   return TT_OK;
 }
@@ -300,7 +315,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     g.M = m;
     g.N = L[n];
     g.K = Rs[n];
-    TTR_TRY(gemm(c, g));
+    TTR_TRY(gemm(c, g, TT_SITE_SWEEP_Y));
     qs.partial = c.partial;
     if (!c.dry) TTR_TRY(qr_thin<T>(ys, xs[n], m, L[n], qs, c.s));
     Gemm<T> h;  // M_n = Q^T Z_n
@@ -315,7 +330,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     h.M = L[n];
     h.N = Rs[n];
     h.K = m;
-    TTR_TRY(gemm(c, h));
+    TTR_TRY(gemm(c, h, TT_SITE_SWEEP_M));
     // next core
     const int64_t I1 = dims[n];
     const bool last = (n + 1 == N);
@@ -351,7 +366,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
         k.sB = rj1;
         k.sC = Rs[n + 1];
       }
-      TTR_TRY(gemm(c, k));
+      TTR_TRY(gemm(c, k, TT_SITE_SWEEP_NEXT));
       offm += rj;
       offn += rj1;
     }
@@ -377,7 +392,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     g.M = lr;
     g.N = lr;
     g.K = cols;
-    TTR_TRY(gemm(c, g));
+    TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
     if (!c.dry) {
       TTR_TRY(sym_eig(gbuf, lam, U, lr, c.s));
       TTR_TRY(trunc_factors<T>(lam, U, lr, k, Pf, Sf, tails + n - 1, c.s));
@@ -394,7 +409,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     h.M = k;
     h.N = cols;
     h.K = lr;
-    TTR_TRY(gemm(c, h));
+    TTR_TRY(gemm(c, h, TT_SITE_TRUNC));
     Gemm<T> p;  // X_{n-1} <- X_{n-1} x_3 (U s)
     const int64_t rows = L[n - 2] * dims[n - 2];
     p.A = xs[n - 1];
@@ -409,7 +424,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     p.M = rows;
     p.N = k;
     p.K = lr;
-    TTR_TRY(gemm(c, p));
+    TTR_TRY(gemm(c, p, TT_SITE_TRUNC));
     hsrc = dst;
     rr = k;
   }
@@ -593,6 +608,35 @@ int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks
   return round_common(s, N, dims, ranks, cores, coeffs, dtype, target_rank, oversample, true,
                       sketch_seed, nullptr, nullptr, prec, out_cores, workspace, ws_bytes,
                       stream);
+}
+
+int tt_timing_start(int32_t site, int32_t capacity) {
+  if (site < TT_SITE_WCHAIN_Z || site > TT_SITE_TRUNC) return fail(TT_EINVAL, "unknown site");
+  if (capacity < 1 || capacity > (1 << 20)) return fail(TT_EINVAL, "capacity out of range");
+  for (hipEvent_t e : g_timer.ev) (void)hipEventDestroy(e);
+  g_timer.ev.assign(2 * (size_t)capacity, nullptr);
+  for (hipEvent_t &e : g_timer.ev) TTR_HIP(hipEventCreate(&e));
+  g_timer.used = 0;
+  g_timer.site = site;
+  return TT_OK;
+}
+
+int tt_timing_stop(double *total_ms, int32_t *launches) {
+  if (!total_ms || !launches) return fail(TT_EINVAL, "null output");
+  double t = 0.0;
+  for (size_t i = 0; i + 1 < g_timer.used; i += 2) {
+    TTR_HIP(hipEventSynchronize(g_timer.ev[i + 1]));
+    float ms = 0.f;
+    TTR_HIP(hipEventElapsedTime(&ms, g_timer.ev[i], g_timer.ev[i + 1]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int32_t)(g_timer.used / 2);
+  for (hipEvent_t e : g_timer.ev) (void)hipEventDestroy(e);
+  g_timer.ev.clear();
+  g_timer.used = 0;
+  g_timer.site = -1;
+  return TT_OK;
 }
 
 int tt_partial_contractions_rl_workspace(int32_t N, const int64_t *dims, const int64_t *ranks_x,
