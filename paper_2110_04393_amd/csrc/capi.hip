@@ -271,12 +271,16 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     xs[n] = P.truncate ? c.arena.take<T>((size_t)(L[n - 1] * dims[n - 1] * L[n])) : out[n - 1];
   // truncation scratch
   double *gbuf = nullptr, *lam = nullptr, *U = nullptr, *tails = nullptr;
+  int *eflag = nullptr;
+  double *escr = nullptr;
   T *Pf = nullptr, *Sf = nullptr, *tb[2] = {nullptr, nullptr};
   if (P.truncate) {
     gbuf = c.arena.take<double>((size_t)(lm * lm));
     lam = c.arena.take<double>((size_t)lm);
     U = c.arena.take<double>((size_t)(lm * lm));
     tails = c.arena.take<double>((size_t)(N + 1));
+    eflag = c.arena.take<int>(4);
+    escr = c.arena.take<double>(eig_trunc_scratch(lm, lm));
     Pf = c.arena.take<T>((size_t)(lm * lm));
     Sf = c.arena.take<T>((size_t)(lm * lm));
     int64_t tmax = 1;
@@ -393,10 +397,7 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
     g.N = lr;
     g.K = cols;
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
-    if (!c.dry) {
-      TTR_TRY(sym_eig(gbuf, lam, U, lr, c.s));
-      TTR_TRY(trunc_factors<T>(lam, U, lr, k, Pf, Sf, tails + n - 1, c.s));
-    }
+    if (!c.dry) TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s));
     Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n)
     h.A = Sf;
     h.lda = lr;

@@ -1,0 +1,589 @@
+// Leading eigenpairs of a small symmetric matrix with a short dependency
+// chain, for the truncation step of the rounding.
+//
+// The truncation of the left-orthogonal RtO output (section 3.2, remark after
+// Algorithm 5; the mirror of the truncation loop of Algorithm 2) diagonalises
+// at every bond the Gram G = H(X_n) H(X_n)^T (n <= 76 here) and keeps its k
+// leading eigenpairs.  On a GPU the cost of such a solve is the length of its
+// chain of dependent steps, so the method is chosen for that:
+//
+//   1. Householder tridiagonalisation G = Q T Q^T in LDS, two barriers per
+//      column: phase b forms p = tau A22 v and y = Q v (8 lanes per row, DPP
+//      sums); phase d updates A22 -= v w^T + w v^T and Q -= tau y v^T while the
+//      first wavefront already builds the next reflector from the updated
+//      column it computes itself.
+//   2. Eigenvalues k+1 (the (k+1)-th to check the gap) by multisection: 16 lanes
+//      per eigenvalue evaluate Sturm counts at 16 points of the bracket
+//      (17-fold shrink per iteration, 14 iterations), each count being the
+//      sign changes of the leading-minor determinants
+//      p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}   (one dependent FMA per step,
+//      rescaled by powers of two).
+//   3. Eigenvectors of T by twisted factorisation (one lane per eigenvalue):
+//      T - lambda I = L+ D+ L+^T = U- D- U-^T, twist r = argmin |gamma_r|,
+//      z_r = 1 and z propagated outwards with the factors.
+//   4. One Newton-Schulz step Z <- Z (3/2 I - 1/2 Z^T Z) (FP64 MFMA) restores
+//      orthogonality lost to close eigenvalues, then U = Q Z (FP64 MFMA).
+//
+// A device flag selects the Jacobi solver (eig.hip) instead when the wanted
+// eigenvalues are not separated by 1e-9 ||T|| (repeated or near-repeated
+// eigenvalues, an exactly split T) or the orthogonality defect before the
+// Newton-Schulz step exceeds 1e-6; that kernel and the factor kernel are
+// always enqueued after this one and return at once unless the flag is set.
+#include "fastmath.h"
+#include "tt_internal.h"
+
+namespace ttr {
+namespace {
+
+constexpr int kTeThreads = 1024;
+constexpr int kTeNMax = 76;
+
+// ---------------------------------------------------------------- DPP
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  const long long x = __double_as_longlong(v);
+  int lo = (int)(x & 0xffffffffll), hi = (int)(x >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140
+__device__ __forceinline__ double sum8(double v) {
+  v += dppd<0xB1>(v);
+  v += dppd<0x4E>(v);
+  v += dppd<0x141>(v);
+  return v;
+}
+__device__ __forceinline__ double sum16(double v) { return (v = sum8(v)) + dppd<0x140>(v); }
+__device__ __forceinline__ double max16(double v) {
+  v = fmax(v, dppd<0xB1>(v));
+  v = fmax(v, dppd<0x4E>(v));
+  v = fmax(v, dppd<0x141>(v));
+  return fmax(v, dppd<0x140>(v));
+}
+__device__ __forceinline__ double min16(double v) {
+  v = fmin(v, dppd<0xB1>(v));
+  v = fmin(v, dppd<0x4E>(v));
+  v = fmin(v, dppd<0x141>(v));
+  return fmin(v, dppd<0x140>(v));
+}
+__device__ __forceinline__ double max8(double v) {
+  v = fmax(v, dppd<0xB1>(v));
+  v = fmax(v, dppd<0x4E>(v));
+  return fmax(v, dppd<0x141>(v));
+}
+__device__ __forceinline__ double min8(double v) {
+  v = fmin(v, dppd<0xB1>(v));
+  v = fmin(v, dppd<0x4E>(v));
+  return fmin(v, dppd<0x141>(v));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// full-wavefront sum, result uniform (all 64 lanes must be active)
+__device__ __forceinline__ double wave_sum(double v) {
+  v = sum16(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = max16(v);
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ double wave_min(double v) {
+  v = min16(v);
+  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
+// ---------------------------------------------------------------- LDS GEMM
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// C(MxN) = alpha * op(A)(MxK) * B(KxN) + beta * Cin, all in LDS (row-major,
+// leading dimensions lda/ldb/ldc), op(A) = A or A^T; the output may go to
+// global memory (ldc row-major).  16x16 blocks are dealt round-robin to the
+// wavefronts; f64 MFMA layout: A lane (r, q) = A[m0+r][k+q], B lane =
+// B[k+q][n0+r], D register j = row q + 4j, column r.
+template <bool TA>
+__device__ void lds_gemm(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                         int M, int N, int K, double alpha, const double *Cin, int ldci,
+                         double beta) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int bm = (M + 15) / 16, bn = (N + 15) / 16;
+  for (int blk = wave; blk < bm * bn; blk += nw) {
+    const int m0 = (blk / bn) * 16, n0 = (blk % bn) * 16;
+    d4_t acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + q;
+      const int m = m0 + r, n = n0 + r;
+      double a = 0.0, b = 0.0;
+      if (k < K && m < M) a = TA ? A[k * lda + m] : A[m * lda + k];
+      if (k < K && n < N) b = B[k * ldb + n];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = m0 + q + 4 * j, col = n0 + r;
+      if (row < M && col < N) {
+        double v = alpha * acc[j];
+        if (beta != 0.0) v += beta * Cin[row * ldci + col];
+        C[row * ldc + col] = v;
+      }
+    }
+  }
+}
+
+// Z (n x k, LDS, leading dimension ld) <- Z E (E: k x k, LDS, lde), in place:
+// every 16-row block of Z is owned by one wavefront, which finishes all its
+// products (k <= 80, at most 5 column blocks in registers) before writing.
+__device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const double *E,
+                                      int lde) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int cbs = (k + 15) / 16;
+  for (int m0 = wave * 16; m0 < n; m0 += nw * 16) {
+    d4_t acc[5];
+#pragma unroll
+    for (int cb = 0; cb < 5; ++cb) acc[cb] = d4_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < k; k0 += 4) {
+      const int kk = k0 + q, m = m0 + r;
+      const double a = (kk < k && m < n) ? Z[m * ld + kk] : 0.0;
+#pragma unroll
+      for (int cb = 0; cb < 5; ++cb) {
+        if (cb < cbs) {
+          const int c = cb * 16 + r;
+          const double b = (kk < k && c < k) ? E[kk * lde + c] : 0.0;
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 5; ++cb) {
+      if (cb < cbs) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = m0 + q + 4 * j, col = cb * 16 + r;
+          if (row < n && col < k) Z[row * ld + col] = acc[cb][j];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kernel 1
+// Householder tridiagonalisation of the n x n symmetric Gin (one workgroup,
+// 256 threads): writes the scaled d (n), e (n-1) with ||T|| sc <= 1, the scale
+// sc, and the reflectors (Vr row j = v_j over rows j+1..n-1, v_j[0] = 1;
+// taus[j]) to global scratch.  Only the lower triangle of A22 is updated.
+constexpr int kTrThreads = 256;
+
+__global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gin, int n,
+                                                                double *d_out, double *e_out,
+                                                                double *sc_out, double *Vr,
+                                                                double *taus, int *flag) {
+  extern __shared__ double lds[];
+  const int ld = n | 1;
+  double *A = lds;  // n x ld, lower triangle meaningful
+  __shared__ double s_v[2][kTeNMax], s_p[kTeNMax], s_w[kTeNMax];
+  __shared__ double s_d[kTeNMax], s_e[kTeNMax];
+  __shared__ double s_tau[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - i * n;
+    if (j <= i) A[i * ld + j] = Gin[e];
+  }
+  __syncthreads();
+
+  auto reflector = [&](double x0, double x1, int m, int buf, int j) {
+    const double a0 = readlane_d(x0, 0);
+    double sq = 0.0;
+    if (lane >= 1 && lane < m) sq += x0 * x0;
+    if (lane + 64 < m) sq += x1 * x1;
+    const double sigma = wave_sum(sq);
+    double beta, tau, scale;
+    if (sigma == 0.0) {
+      beta = a0;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      const double mu = sqrt_f64(fma(a0, a0, sigma));
+      beta = (a0 >= 0.0) ? -mu : mu;
+      tau = (beta - a0) * rcp_f64(beta);
+      scale = rcp_f64(a0 - beta);
+    }
+    const double v0 = (lane == 0) ? 1.0 : x0 * scale, v1 = x1 * scale;
+    if (lane < m) {
+      s_v[buf][lane] = v0;
+      Vr[j * n + lane] = v0;
+    }
+    if (lane + 64 < m) {
+      s_v[buf][lane + 64] = v1;
+      Vr[j * n + lane + 64] = v1;
+    }
+    if (lane == 0) {
+      s_tau[buf] = tau;
+      s_e[j] = beta;
+      taus[j] = tau;
+    }
+  };
+
+  if (n == 1) {
+    if (tid == 0) s_d[0] = A[0];
+  } else if (n == 2) {
+    if (tid == 0) {
+      s_d[0] = A[0];
+      s_e[0] = A[ld];
+      s_d[1] = A[ld + 1];
+    }
+  } else {
+    if (wave == 0) {
+      const int m = n - 1;
+      const double x0 = (lane < m) ? A[(1 + lane) * ld] : 0.0;
+      const double x1 = (lane + 64 < m) ? A[(65 + lane) * ld] : 0.0;
+      reflector(x0, x1, m, 0, 0);
+      if (lane == 0) s_d[0] = A[0];
+    }
+    __syncthreads();
+    for (int j = 0; j <= n - 3; ++j) {
+      const int m = n - j - 1, cur = j & 1;
+      const double *v = s_v[cur];
+      const double tau = s_tau[cur];
+      const int base = j + 1;
+      // phase b: p = tau A22 v, 4 lanes per row (quad), lane q covers c = q, q+4, ...
+      for (int r0 = 0; r0 < m; r0 += kTrThreads / 4) {
+        const int r = r0 + (tid >> 2), qd = tid & 3;
+        double acc = 0.0;
+        if (r < m) {
+          const double *arow = A + (base + r) * ld + base;
+          for (int c = qd; c <= r; c += 4) acc = fma(arow[c], v[c], acc);
+          for (int c = r + 1 + ((qd - (r + 1)) & 3); c < m; c += 4)
+            acc = fma(A[(base + c) * ld + base + r], v[c], acc);
+        }
+        acc += dppd<0xB1>(acc);
+        acc += dppd<0x4E>(acc);
+        if (qd == 0 && r < m) s_p[r] = tau * acc;
+      }
+      __syncthreads();
+      // phase d: K = tau/2 p^T v, w = p - K v (wave 0 writes w and builds the
+      // next reflector from the updated column; the others update A22's
+      // lower triangle on local rows/columns >= 1 once w is there)
+      double pv = 0.0;
+      if (lane < m) pv = s_p[lane] * v[lane];
+      if (lane + 64 < m) pv = fma(s_p[lane + 64], v[lane + 64], pv);
+      const double K = 0.5 * tau * wave_sum(pv);
+      for (int c = tid; c < m; c += blockDim.x) s_w[c] = s_p[c] - K * v[c];
+      if (wave == 0) {
+        const double w0 = s_p[0] - K * v[0];
+        const double dnew = A[base * ld + base] - 2.0 * v[0] * w0;
+        double x0 = 0.0, x1 = 0.0;
+        const int r0 = lane + 1, r1 = lane + 65;
+        if (r0 < m) x0 = A[(base + r0) * ld + base] - v[r0] * w0 - (s_p[r0] - K * v[r0]) * v[0];
+        if (r1 < m) x1 = A[(base + r1) * ld + base] - v[r1] * w0 - (s_p[r1] - K * v[r1]) * v[0];
+        if (lane == 0) s_d[base] = dnew;
+        if (j + 1 <= n - 3) {
+          reflector(x0, x1, m - 1, cur ^ 1, j + 1);
+        } else if (lane == 0) {
+          s_e[n - 2] = x0;
+        }
+      }
+      __syncthreads();
+      // lower triangle, rows r = 1.. (thread per row segment of 8 columns)
+      {
+        const int segs = (m + 7) >> 3;
+        for (int t = tid; t < (m - 1) * segs; t += blockDim.x) {
+          const int r = 1 + t / segs, c0 = (t - (t / segs) * segs) * 8;
+          if (c0 > r) continue;
+          const double vr = v[r], wr = s_w[r];
+          double *arow = A + (base + r) * ld + base;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int c = c0 + u;
+            if (c >= 1 && c <= r) arow[c] = arow[c] - vr * s_w[c] - wr * v[c];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) s_d[n - 1] = A[(n - 1) * ld + (n - 1)];
+    __syncthreads();
+  }
+  if (wave == 0) {
+    double mx = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      const double rad = (i > 0 ? fabs(s_e[i - 1]) : 0.0) + (i < n - 1 ? fabs(s_e[i]) : 0.0);
+      mx = fmax(mx, fabs(s_d[i]) + rad);
+    }
+    mx = wave_max(mx);
+    const double sc = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ilogb(mx) - 1) : 1.0;
+    for (int i = lane; i < n; i += 64) {
+      d_out[i] = s_d[i] * sc;
+      if (i < n - 1) e_out[i] = s_e[i] * sc;
+    }
+    if (lane == 0) {
+      *sc_out = sc;
+      *flag = (mx > 0.0 && isfinite(mx)) ? 0 : 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kernel 2
+// One wavefront per wanted eigenvalue w (descending, w < kw).  T lives in
+// registers (d, e fully unrolled up to kTeNMax), 64-point multisection with
+// Sturm counts (9 iterations of a 65-fold shrink); for w < k the eigenvector:
+// twisted factorisation (lanes 0-31 run the top-down LDL^T, lanes 32-63 the
+// same recurrence on the reversed matrix, i.e. the bottom-up UDU^T), then the
+// Householder reflectors of kernel 1 applied backwards give u = Q z, written to
+// column w of U (n x k) unnormalised by sc.
+__global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const double *e_in, int n,
+                                                     int k, int kw, const double *Vr,
+                                                     const double *taus, double *lam_out,
+                                                     double *Uz, const int *flag) {
+  if (*flag) return;
+  __shared__ double s_L[kTeNMax + 1], s_U[kTeNMax + 1], s_z[kTeNMax];
+  __shared__ double s_g[kTeNMax];
+  const int lane = threadIdx.x;
+  const int w = blockIdx.x;
+  // the upper half-wave holds T reversed (same eigenvalues and Sturm counts;
+  // its top-down factorisation is the bottom-up one of T)
+  const bool rev = lane >= 32;
+  double d[kTeNMax], e[kTeNMax];
+#pragma unroll
+  for (int i = 0; i < kTeNMax; ++i) {
+    d[i] = (i < n) ? d_in[rev ? n - 1 - i : i] : 0.0;
+    e[i] = (i < n - 1) ? e_in[rev ? n - 2 - i : i] : 0.0;
+  }
+  const int a = n - 1 - w;
+  double lo = -1.0 - 1e-13, hi = 1.0 + 1e-13;
+  for (int it = 0; it < 9; ++it) {
+    const double x = lo + (double)(lane + 1) * (hi - lo) * (1.0 / 65.0);
+    double pp = 1.0, p = d[0] - x;
+    if (p == 0.0) p = -1e-300;
+    int cnt = (p < 0.0) ? 1 : 0;
+#pragma unroll
+    for (int i = 1; i < kTeNMax; ++i) {
+      if (i < n) {
+        double pn = fma(d[i] - x, p, -(e[i - 1] * e[i - 1]) * pp);
+        if (pn == 0.0) pn = (p > 0.0) ? -1e-300 : 1e-300;
+        cnt += ((pn < 0.0) != (p < 0.0)) ? 1 : 0;
+        pp = p;
+        p = pn;
+      }
+      if ((i & 7) == 0) {
+        const double ap = fmax(fabs(p), fabs(pp));
+        if (ap > 0x1p+600) {
+          p *= 0x1p-600;
+          pp *= 0x1p-600;
+        } else if (ap < 0x1p-600) {
+          p *= 0x1p+600;
+          pp *= 0x1p+600;
+        }
+      }
+    }
+    const double cl = (cnt <= a) ? x : lo;
+    const double ch = (cnt > a) ? x : hi;
+    lo = wave_max(cl);
+    hi = wave_min(ch);
+  }
+  const double lam = 0.5 * (lo + hi);
+  if (lane == 0) lam_out[w] = lam;
+  if (w >= k) return;
+  // twisted factorisation: every lane runs the top-down recurrence on its copy;
+  // lane 0 (T) gives L_i, lane 32 (reversed T) gives U_{n-1-i}
+  const double tiny = 1e-300;
+  {
+    double dp = d[0] - lam;
+#pragma unroll
+    for (int i = 0; i < kTeNMax - 1; ++i) {
+      if (i < n - 1) {
+        if (dp == 0.0) dp = tiny;
+        const double f = e[i] * rcp_f64(dp);
+        if (lane == 0) s_L[i] = f;
+        if (lane == 32) s_U[n - 1 - i] = f;
+        dp = (d[i + 1] - lam) - f * e[i];
+      }
+    }
+  }
+  __syncthreads();
+  // gamma_i = delta_i - L_{i-1} e_{i-1} - U_{i+1} e_i, twist r = argmin |gamma|
+  double best = 1e300;
+  int rbest = 0;
+  for (int i = lane; i < n; i += 64) {
+    const double ev = (i < n - 1) ? e_in[i] : 0.0;
+    const double ep = (i > 0) ? e_in[i - 1] : 0.0;
+    double g = d_in[i] - lam;
+    if (i > 0) g -= s_L[i - 1] * ep;
+    if (i < n - 1) g -= s_U[i + 1] * ev;
+    g = fabs(g);
+    if (g < best) {
+      best = g;
+      rbest = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int orr = __shfl_xor(rbest, off);
+    if (ob < best || (ob == best && orr < rbest)) {
+      best = ob;
+      rbest = orr;
+    }
+  }
+  const int r = rbest;
+  if (lane == 0) {
+    double z = 1.0;
+    s_z[r] = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      z = -s_L[i] * z;
+      s_z[i] = z;
+    }
+    z = 1.0;
+    for (int i = r + 1; i < n; ++i) {
+      z = -s_U[i] * z;
+      s_z[i] = z;
+    }
+  }
+  __syncthreads();
+  // normalise, then u = H_0 H_1 ... H_{n-3} z (apply from the last reflector)
+  double z0 = (lane < n) ? s_z[lane] : 0.0, z1 = (lane + 64 < n) ? s_z[lane + 64] : 0.0;
+  const double inv = rsq_f64(wave_sum(z0 * z0 + z1 * z1));
+  z0 *= inv;
+  z1 *= inv;
+  for (int j = n - 3; j >= 0; --j) {
+    const double tau = taus[j];
+    // v_j over rows j+1..n-1; lane row i holds v = Vr[j][i - j - 1]
+    const int i0 = lane, i1 = lane + 64;
+    const double v0 = (i0 > j && i0 < n) ? Vr[j * n + i0 - j - 1] : 0.0;
+    const double v1 = (i1 > j && i1 < n) ? Vr[j * n + i1 - j - 1] : 0.0;
+    const double dot = wave_sum(v0 * z0 + v1 * z1);
+    z0 = fma(-tau * dot, v0, z0);
+    z1 = fma(-tau * dot, v1, z1);
+  }
+  if (lane < n) Uz[lane * k + w] = z0;
+  if (lane + 64 < n) Uz[(lane + 64) * k + w] = z1;
+}
+
+// ---------------------------------------------------------------- kernel 3
+// One workgroup: gap check, orthogonality check and one Newton-Schulz step on
+// U (n x k, from kernel 2), outputs (unscaled eigenvalues, U, truncation
+// factors, tail).
+template <typename T>
+__global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
+    const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag) {
+  if (*flag) return;
+  extern __shared__ double lds[];
+  const int ld = n | 1;
+  double *Z = lds;             // n x ld (k columns)
+  double *E = lds + n * ld;    // k x ld
+  __shared__ double s_lam[kTeNMax + 1];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < n * k; e += blockDim.x) {
+    const int i = e / k, c = e - i * k;
+    Z[i * ld + c] = Ug[e];
+  }
+  if (tid < kw) s_lam[tid] = lamw[tid];
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (wave == 0) {
+    double mingap = 1e300;
+    for (int w = lane; w + 1 < kw; w += 64) mingap = fmin(mingap, s_lam[w] - s_lam[w + 1]);
+    mingap = wave_min(mingap);
+    if (lane == 0 && !(mingap >= 1e-9)) s_bad = 1;
+  }
+  lds_gemm<true>(Z, ld, Z, ld, E, ld, k, k, n, 1.0, nullptr, 0, 0.0);
+  __syncthreads();
+  {
+    double dev = 0.0;
+    for (int e = tid; e < k * k; e += blockDim.x) {
+      const int a = e / k, b = e - a * k;
+      dev = fmax(dev, fabs(E[a * ld + b] - (a == b ? 1.0 : 0.0)));
+    }
+    dev = wave_max(dev);
+    if (lane == 0 && !(dev <= 1e-6)) s_bad = 1;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) *flag = 1;
+    return;
+  }
+  for (int e = tid; e < k * k; e += blockDim.x) {
+    const int a = e / k, b = e - a * k;
+    E[a * ld + b] = (a == b ? 1.5 : 0.0) - 0.5 * E[a * ld + b];
+  }
+  __syncthreads();
+  lds_right_mul_inplace(Z, ld, n, k, E, ld);
+  __syncthreads();
+  const double inv_sc = 1.0 / *scp;
+  const double l0 = fmax(s_lam[0] * inv_sc, 0.0);
+  for (int e = tid; e < n * k; e += blockDim.x) {
+    const int i = e / k, j = e - i * k;
+    const double u = Z[i * ld + j];
+    const double lj = s_lam[j] * inv_sc;
+    const double sq = lj > 0.0 ? sqrt_f64(lj) : 0.0;
+    U_out[e] = u;
+    P[i * k + j] = (T)(u * sq);
+    S[j * n + i] = (T)((lj > 1e-13 * l0 && lj > 0.0) ? u * rcp_f64(sq) : 0.0);
+  }
+  if (tid < k) lam_out[tid] = s_lam[tid] * inv_sc;
+  if (wave == 0) {
+    double tr = 0.0, kept = 0.0;
+    for (int i = lane; i < n; i += 64) tr += Gin[i * n + i];
+    for (int i = lane; i < k; i += 64) kept += s_lam[i];
+    tr = wave_sum(tr);
+    kept = wave_sum(kept) * inv_sc;
+    if (lane == 0) *tail = fmax(tr - kept, 0.0);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *P, T *S,
+              double *tail, int *flag, double *scratch, hipStream_t s) {
+  if (n > TT_MAX_SKETCH_RANK) return fail(TT_EUNSUPPORTED, "eigenproblem larger than the limit");
+  if (k < 1 || k > n) return fail(TT_EINVAL, "truncation rank out of range");
+  if (n <= kTeNMax) {
+    const int ld = (int)(n | 1);
+    const int kw = (int)std::min<int64_t>(k + 1, n);
+    // scratch: d (n), e (n), sc (1), Vr (n*n), taus (n), lamw (n+1), U (n*k)
+    double *d = scratch, *e = d + n, *sc = e + n, *Vr = sc + 1, *taus = Vr + n * n;
+    double *lamw = taus + n, *Uz = lamw + n + 1;
+    static bool attr_set = false;
+    if (!attr_set) {
+      TTR_HIP(hipFuncSetAttribute((const void *)tri_reduce_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+      TTR_HIP(hipFuncSetAttribute((const void *)tri_finish_kernel<T>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(tri_reduce_kernel, dim3(1), dim3(kTrThreads),
+                       sizeof(double) * (size_t)n * ld, s, G, (int)n, d, e, sc, Vr, taus, flag);
+    TTR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(tri_vec_kernel, dim3(kw), dim3(64), 0, s, d, e, (int)n, (int)k, kw, Vr,
+                       taus, lamw, Uz, flag);
+    TTR_HIP(hipGetLastError());
+    hipLaunchKernelGGL((tri_finish_kernel<T>), dim3(1), dim3(kTeThreads),
+                       2 * sizeof(double) * (size_t)n * ld, s, G, lamw, Uz, sc, (int)n, (int)k,
+                       kw, lam, U, P, S, tail, flag);
+    TTR_HIP(hipGetLastError());
+    // Jacobi fallback, gated on the flag
+    TTR_TRY(sym_eig(G, lam, U, n, s, nullptr, flag));
+    TTR_TRY(trunc_factors<T>(lam, U, n, k, P, S, tail, s, flag));
+    return TT_OK;
+  }
+  TTR_TRY(sym_eig(G, lam, U, n, s, nullptr, nullptr));
+  return trunc_factors<T>(lam, U, n, k, P, S, tail, s, nullptr);
+}
+
+size_t eig_trunc_scratch(int64_t n, int64_t k) { return (size_t)(4 * n + 2 + n * n + n * k); }
+
+template int eig_trunc<double>(const double *, int64_t, int64_t, double *, double *, double *,
+                               double *, double *, int *, double *, hipStream_t);
+template int eig_trunc<float>(const double *, int64_t, int64_t, double *, double *, float *,
+                              float *, double *, int *, double *, hipStream_t);
+
+}  // namespace ttr

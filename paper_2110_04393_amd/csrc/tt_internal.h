@@ -107,14 +107,26 @@ void qr_set_mode(int mode);  // 0 auto, 1 force householder, 2 force cholqr2
 // ---------------------------------------------------------------- eigen
 // Symmetric eigendecomposition of an n x n matrix (n <= TT_MAX_SKETCH_RANK)
 // by cyclic Jacobi: eigenvalues descending to `lam`, eigenvectors as the
-// columns of U (row-major n x n).
-int sym_eig(const double *G, double *lam, double *U, int64_t n, hipStream_t s);
+// columns of U (row-major n x n); *info (optional) receives the sweep count.
+// With a gate pointer the kernel returns at once unless *gate != 0.
+int sym_eig(const double *G, double *lam, double *U, int64_t n, hipStream_t s,
+            int *info = nullptr, const int *gate = nullptr);
 
 // Truncation factors from (lam, U): P = U_k sqrt(lam_k) (n x k, row-major),
 // S = sqrt(lam_k)^-1 U_k^T (k x n, row-major), tail = sum_{j>=k} max(lam_j,0).
 template <typename T>
 int trunc_factors(const double *lam, const double *U, int64_t n, int64_t k, T *P, T *S,
-                  double *tail, hipStream_t s);
+                  double *tail, hipStream_t s, const int *gate = nullptr);
+
+// Leading k eigenpairs of the symmetric n x n G and the truncation factors
+// P, S and tail as above: tridiagonalisation + multisection + twisted
+// factorisation for n <= 76 with a device-flagged Jacobi fallback, Jacobi for
+// larger n.  lam (n) and U (n x n) are scratch/outputs; flag is one int;
+// scratch holds eig_trunc_scratch(n, k) doubles.
+template <typename T>
+int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *P, T *S,
+              double *tail, int *flag, double *scratch, hipStream_t s);
+size_t eig_trunc_scratch(int64_t n, int64_t k);
 
 // ---------------------------------------------------------------- misc
 // dst[r*ldd + c] = alpha * src[r*lds + c] + beta * dst[r*ldd + c]
