@@ -27,13 +27,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6, "f32": 157.3}  # dense MFMA TFLOP/s (MI355X datasheet)
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s (MI355X datasheet)
 HBM_PEAK_GBS = 8000.0
+# arithmetic of each call site per mode (partial contractions / sweep)
+SITE_MATH = {"f64": ("f64", "f64"), "f32": ("f32", "f32"), "bf16": ("bf16", "f32")}
+STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
 METRIC = "ms per randomized TT-rounding + %MFMA peak; mixed-prec vs FP64 at tol"
 
 SITE_NAMES = {0: "wchain_z", 1: "wchain_w", 2: "sweep_y", 3: "sweep_m", 4: "sweep_next",
               5: "trunc"}
 SITE_KERNEL = {0: "gemm_kernel (V(Y_n) W_n, partial contractions)",
+               1: "gemm_kernel (H(Z_n) H(Sk_n)^T, partial contractions)",
+               2: "gemm_kernel (Z_n W_n, sketch of the sweep)",
+               3: "gemm_kernel (Q^T Z_n, projection)",
                4: "gemm_kernel (M_n H(Y_{n+1}), next core)"}
 
 
@@ -41,23 +47,46 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def site_flops(site, dims, ranks, ell, summand_ranks=None):
-    """Algorithmic flops (2mnk per GEMM) of every launch from one call site."""
+def site_launches(site, dims, ell, summand_ranks):
+    """(M, N, K) of every launch from one call site, in launch order."""
     N = len(dims)
-    f = []
-    if site == 0:  # V(Y_n) W_n, n = N-1..2, per summand
-        srs = summand_ranks or [ranks]
-        for R in srs:
-            for n in range(N - 1, 1, -1):
-                f.append(2.0 * R[n - 1] * dims[n - 1] * R[n] * ell[n])
-    elif site == 4:  # M_n H(Y_{n+1}), n = 1..N-1, per summand
-        srs = summand_ranks or [ranks]
+    Rs = [1] + [sum(R[n] for R in summand_ranks) for n in range(1, N)] + [1]
+    out = []
+    if site == 0:  # V(Z_n) = V(Y_n) W_n, n = N-1..2, per summand
+        for n in range(N - 1, 1, -1):
+            for R in summand_ranks:
+                out.append((R[n - 1] * dims[n - 1], ell[n], R[n]))
+    elif site == 1:  # W_{N-1}, then W_{n-1} = H(Z_n) H(Sk_n)^T
+        for R in summand_ranks:
+            out.append((R[N - 1], ell[N - 1], dims[N - 1]))
+        for n in range(N - 1, 1, -1):
+            for R in summand_ranks:
+                out.append((R[n - 1], ell[n - 1], dims[n - 1] * ell[n]))
+    elif site == 2:  # Y_n = Z_n W_n
         for n in range(1, N):
-            for R in srs:
-                f.append(2.0 * ell[n] * R[n] * dims[n] * R[n + 1])
+            out.append((ell[n - 1] * dims[n - 1], ell[n], Rs[n]))
+    elif site == 3:  # M_n = Q^T Z_n
+        for n in range(1, N):
+            out.append((ell[n], Rs[n], ell[n - 1] * dims[n - 1]))
+    elif site == 4:  # M_n H(Y_{n+1}), per summand
+        for n in range(1, N):
+            for R in summand_ranks:
+                out.append((ell[n], dims[n] * R[n + 1], R[n]))
     else:
         raise ValueError(site)
-    return f
+    return out
+
+
+def site_flops(site, dims, ell, summand_ranks):
+    """Algorithmic flops (2 M N K per product) of one step's launches."""
+    return sum(2.0 * m * n * k for m, n, k in site_launches(site, dims, ell, summand_ranks))
+
+
+def site_bytes(site, dims, ell, summand_ranks, elem):
+    """Algorithmic HBM bytes of one step's launches: each operand read once,
+    the result written once (elem bytes per value)."""
+    return sum(float(elem) * (m * k + k * n + m * n)
+               for m, n, k in site_launches(site, dims, ell, summand_ranks))
 
 
 def make_workload(name):
@@ -67,6 +96,13 @@ def make_workload(name):
         desc = ("single TT, N=30, I=100, rank 200, cores N(0,1)/sqrt(I*R); sketch rank 60 "
                 "(target 50 + oversample 10); truncated to rank 50")
         return dict(kind="single", inputs=w["X"], target=w["target"], over=w["oversample"],
+                    seed=w["sketch_seed"], desc=desc)
+    if name == "single_tt_lowrank":
+        w = G.workload_single_tt()
+        X = G.near_low_rank_tt(G.INPUT_SEED_BASE + 1, [100] * 30, 40, 160, 1e-6)
+        desc = ("near-low-rank single TT, N=30, I=100, X1 rank 40 + 1e-6 X2 rank 160 (formal "
+                "200), cores N(0,1)/sqrt(I*r); sketch rank 60; truncated to rank 50")
+        return dict(kind="single", inputs=X, target=w["target"], over=w["oversample"],
                     seed=w["sketch_seed"], desc=desc)
     if name == "small_sum":
         w = G.workload_small_sum()
@@ -116,8 +152,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_tt",
-                    choices=["single_tt", "gmres_sum", "small_sum"])
-    ap.add_argument("--prec", default="f64", choices=["f64"])
+                    choices=["single_tt", "single_tt_lowrank", "gmres_sum", "small_sum"])
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--no-f64-compare", action="store_true",
+                    help="with --prec f32/bf16: skip timing the FP64 path for the speedup")
     ap.add_argument("--site", type=int, default=None,
                     help="call site whose kernel the roofline covers (default: dominant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,7 +167,8 @@ def main():
               "path has no multi-GPU mode in this build", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import ctypes
+
     import torch
 
     import paper_2110_04393_amd as tt
@@ -141,77 +180,99 @@ def main():
     torch.cuda.set_device(0)
     wl = make_workload(args.workload)
     dev = torch.device("cuda:0")
-    if wl["kind"] == "single":
-        cores = [torch.from_numpy(c).to(dev) for c in wl["inputs"]]
-        dims = [int(c.shape[1]) for c in cores]
-        ranks = [1] + [int(c.shape[2]) for c in cores]
-        plan = tt.RoundPlan(dims, ranks, wl["target"], wl["over"], args.prec, dev)
-        summand_ranks = None
 
-        def step():
-            return plan.run(cores, seed=wl["seed"])
-    else:
-        summ = [[torch.from_numpy(c).to(dev) for c in t] for t in wl["inputs"]]
-        dims = [int(c.shape[1]) for c in summ[0]]
-        summand_ranks = [[1] + [int(c.shape[2]) for c in t] for t in summ]
-        plan = tt.RoundPlan(dims, None, wl["target"], wl["over"], args.prec, dev,
-                            summand_ranks=summand_ranks)
-        ranks = plan.ranks
+    def build(prec):
+        """Plan, device inputs in the mode's storage type, and one step."""
+        store = tt.STORAGE[prec]
+        if wl["kind"] == "single":
+            cores = [torch.from_numpy(c).to(dev).to(store) for c in wl["inputs"]]
+            dims = [int(c.shape[1]) for c in cores]
+            ranks = [1] + [int(c.shape[2]) for c in cores]
+            plan = tt.RoundPlan(dims, ranks, wl["target"], wl["over"], prec, dev)
+            sr = [ranks]
 
-        def step():
-            return plan.run_sum(summ, wl["coeffs"], seed=wl["seed"])
+            def step():
+                return plan.run(cores, seed=wl["seed"])
+        else:
+            summ = [[torch.from_numpy(c).to(dev).to(store) for c in t] for t in wl["inputs"]]
+            dims = [int(c.shape[1]) for c in summ[0]]
+            sr = [[1] + [int(c.shape[2]) for c in t] for t in summ]
+            plan = tt.RoundPlan(dims, None, wl["target"], wl["over"], prec, dev,
+                                summand_ranks=sr)
 
+            def step():
+                return plan.run_sum(summ, wl["coeffs"], seed=wl["seed"])
+        return plan, step, dims, sr
+
+    def timed(step, steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return ev0.elapsed_time(ev1) / steps, wall * 1e3 / steps
+
+    plan, step, dims, summand_ranks = build(args.prec)
     ell = plan.sketch_ranks
-    log(f"workload: {wl['desc']}; sketch ranks {ell[:4]}..., out ranks {plan.out_ranks[:4]}...")
+    ranks = plan.ranks
+    log(f"workload: {wl['desc']}; precision {args.prec}; sketch ranks {ell[:4]}..., "
+        f"out ranks {plan.out_ranks[:4]}...")
     log(f"workspace {plan.ws_bytes / 2**20:.1f} MiB")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
+    # ---- timed region: exactly K steps after W warmup steps
+    ms_per_step, wall_ms = timed(step, args.steps, args.warmup)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall_ms:.3f})")
 
-    # ---- timed region: exactly K steps
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f})")
-
-    # ---- per-site kernel timing (second pass, same steps)
-    import ctypes
+    # ---- per-site kernel timing (second pass, same steps, HIP events on the
+    # launch stream around every launch of the site)
+    wmath, smath = SITE_MATH[args.prec]
     site_ms = {}
-    for site in (0, 4):
-        L.check(L.lib().tt_timing_start(site, 64 * args.steps))
+    for site in (0, 1, 2, 3, 4):
+        L.check(L.lib().tt_timing_start(site, 4096 * args.steps))
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         tot = ctypes.c_double(0)
         cnt = ctypes.c_int32(0)
         L.check(L.lib().tt_timing_stop(ctypes.byref(tot), ctypes.byref(cnt)))
-        fl = site_flops(site, dims, ranks, ell, summand_ranks)
-        site_ms[site] = (tot.value, cnt.value, sum(fl) * args.steps)
-        log(f"site {SITE_NAMES[site]}: {cnt.value} launches, {tot.value / max(cnt.value, 1) * 1e3:.1f} us avg, "
-            f"{sum(fl) * args.steps / (tot.value * 1e-3) / 1e12 if tot.value else 0:.2f} TFLOP/s")
+        fl = site_flops(site, dims, ell, summand_ranks) * args.steps
+        site_ms[site] = (tot.value, cnt.value, fl)
+        log(f"site {SITE_NAMES[site]}: {cnt.value // args.steps} launches/step, "
+            f"{tot.value / max(cnt.value, 1) * 1e3:.1f} us avg, {tot.value / args.steps:.3f} ms/step, "
+            f"{fl / (tot.value * 1e-3) / 1e12 if tot.value else 0:.2f} TFLOP/s")
     site = args.site if args.site is not None else max(site_ms, key=lambda k: site_ms[k][0])
     tot_ms, cnt, flops = site_ms[site]
-    achieved = flops / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
-    peak = PEAK[args.prec]
-    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=None,
-                    kernel=SITE_KERNEL.get(site, SITE_NAMES[site]),
+    math_dt = wmath if site in (0, 1) else smath
+    per_launch_us = tot_ms / max(cnt, 1) * 1e3
+    if math_dt == "bf16":
+        # bandwidth-bound at these shapes: algorithmic bytes against HBM peak
+        nbytes = site_bytes(site, dims, ell, summand_ranks, STORE_BYTES[args.prec]) * args.steps
+        achieved = nbytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                        bytes_per_step=nbytes / args.steps)
+    else:
+        achieved = flops / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
+        peak = PEAK[math_dt]
+        roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=None,
+                        flops_per_step=flops / args.steps)
+    roofline.update(kernel=SITE_KERNEL[site], math=math_dt,
                     launches_per_step=cnt // max(args.steps, 1),
-                    avg_launch_us=round(tot_ms / max(cnt, 1) * 1e3, 2),
-                    flops_per_step=flops / args.steps)
+                    avg_launch_us=round(per_launch_us, 2),
+                    site_ms_per_step={SITE_NAMES[k]: round(v[0] / args.steps, 4)
+                                      for k, v in site_ms.items()})
 
-    out = [c.detach().cpu().numpy() for c in step()]
+    out = [c.detach().double().cpu().numpy() for c in step()]
     torch.cuda.synchronize()
 
     res = {
@@ -232,6 +293,14 @@ def main():
                    "precision": args.prec},
         "roofline": roofline,
     }
+    if args.prec != "f64" and not args.no_f64_compare:
+        del plan, step
+        _, step64, _, _ = build("f64")
+        ms64, _ = timed(step64, args.steps, args.warmup)
+        out64 = [c.detach().cpu().numpy() for c in step64()]
+        torch.cuda.synchronize()
+        res["f64_gpu"] = {"ms_per_step": round(ms64, 4), "speedup": round(ms64 / ms_per_step, 3)}
+        log(f"FP64 GPU path: {ms64:.3f} ms/step; {args.prec} speedup {ms64 / ms_per_step:.2f}x")
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(wl, out, budget_s=args.cpu_budget)
         res["cpu_baseline"] = cb

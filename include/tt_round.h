@@ -27,7 +27,16 @@
  *   last non-OK status of the calling thread.
  * Precision.  `dtype` is the storage type of the cores (TT_F64 or TT_F32);
  *   `prec` the arithmetic mode (TT_PREC_F64 needs TT_F64 storage,
- *   TT_PREC_F32 and TT_PREC_MIXED_BF16 need TT_F32 storage).
+ *   TT_PREC_F32 and TT_PREC_MIXED_BF16 need TT_F32 storage; a mismatch is
+ *   TT_EINVAL).  In the FP32 modes the Gram matrices of the thin QR and of
+ *   the truncation are accumulated in FP64 from the FP32 operands and
+ *   factorised in FP64, and every partial contraction W_n is rescaled by a
+ *   power of two as soon as it is formed (the QR of Y_n = Z_n W_n, hence the
+ *   result, is invariant under positive scalings of W_n; the rescaling keeps
+ *   long trains inside the FP32 exponent range).  TT_PREC_MIXED_BF16 draws
+ *   the sketch in BF16 (see tt_make_sketch) and runs the partial
+ *   contractions on the BF16 MFMA with FP32 accumulation; the sweep and the
+ *   truncation stay in FP32.
  */
 #ifndef TT_ROUND_H
 #define TT_ROUND_H
@@ -54,7 +63,11 @@ typedef enum {
   TT_EUNSUPPORTED = -5  /* valid request outside the implemented limits          */
 } tt_status;
 
-typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
+typedef enum {
+  TT_F64 = 0,
+  TT_F32 = 1,
+  TT_BF16 = 2  /* bfloat16; only as the output of tt_make_sketch */
+} tt_dtype;
 
 typedef enum {
   TT_PREC_F64 = 0,        /* all arithmetic in FP64 (MFMA f64)                    */
@@ -109,7 +122,9 @@ TT_API int tt_round_rand_workspace(int32_t N, const int64_t *dims, const int64_t
  * divided by sqrt(l_{n-1} I_n l_n).  mix is the SplitMix64 output function,
  * gamma = 0x9E3779B97F4A7C15.
  *   cores[N]   device pointers of the caller's output cores (dtype storage;
- *              TT_F32 rounds the FP64 value to nearest)
+ *              TT_F32 rounds the FP64 value to nearest even, TT_BF16 rounds
+ *              that FP32 value to nearest even, which is the sketch the
+ *              TT_PREC_MIXED_BF16 mode draws)
  */
 TT_API int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims,
                    const int64_t *sketch_ranks, int32_t dtype, void *const *cores,
@@ -121,18 +136,24 @@ TT_API int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims,
  * W_{N-1} = H(X_N) H(Y_N)^T and, for n = N-1..2, V(Z_n) = V(X_n) W_n,
  * W_{n-1} = H(Z_n) H(Y_n)^T.
  *   X: N cores with ranks_x[N+1];  Y: N cores with ranks_y[N+1]; same dims.
+ *   prec        TT_PREC_F64: X, Y, W in FP64, FP64 MFMA.  TT_PREC_F32: FP32
+ *               storage and MFMA.  TT_PREC_MIXED_BF16: FP32 storage, every
+ *               operand rounded to BF16 (nearest even) as it enters the BF16
+ *               MFMA, FP32 accumulation.  No renormalisation: W_n is returned
+ *               as defined.
  *   W_out[N-1]  device pointers; W_out[n-1] receives W_n as a row-major
  *               ranks_x[n] x ranks_y[n] matrix (n = 1..N-1).
- * FP64 storage and arithmetic (dtype must be TT_F64).  Needs N >= 2.
+ * Needs N >= 2.
  */
 TT_API int tt_partial_contractions_rl_workspace(int32_t N, const int64_t *dims,
-                                         const int64_t *ranks_x, const int64_t *ranks_y,
-                                         size_t *bytes);
+                                                const int64_t *ranks_x,
+                                                const int64_t *ranks_y, int32_t prec,
+                                                size_t *bytes);
 TT_API int tt_partial_contractions_rl(int32_t N, const int64_t *dims,
-                               const int64_t *ranks_x, const void *const *x_cores,
-                               const int64_t *ranks_y, const void *const *y_cores,
-                               void *const *W_out, void *workspace, size_t ws_bytes,
-                               void *stream);
+                                      const int64_t *ranks_x, const void *const *x_cores,
+                                      const int64_t *ranks_y, const void *const *y_cores,
+                                      int32_t prec, void *const *W_out, void *workspace,
+                                      size_t ws_bytes, void *stream);
 
 /*
  * Randomized TT-rounding, Randomize-then-Orthogonalize (Algorithm 5).

@@ -36,6 +36,10 @@ Readings taken where the paper is silent (each also listed in the design notes):
 * eps-truncation is absolute: keep the smallest k >= 1 with
   sqrt(sum_{j>k} s_j^2) <= eps0 ||Y|| / sqrt(N-1), capped by max_rank.
 * Sum coefficients multiply each summand's first core.
+* Reduced-precision modes are compared with this FP64 oracle run on the same
+  inputs and on the same sketch values: the FP32 sketch is the FP64 draw
+  rounded to nearest-even FP32, the BF16 sketch is that FP32 value rounded
+  to nearest-even bfloat16 (round_f32, round_bf16).
 """
 from __future__ import annotations
 
@@ -170,6 +174,22 @@ def gaussian_stream(key, count):
     z[0::2] = rad * np.cos(th)
     z[1::2] = rad * np.sin(th)
     return z[:count]
+
+
+def round_f32(x):
+    """Nearest-even FP32 value of each entry, returned in float64."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(x):
+    """Reading of the BF16 sketch: each FP64 value rounded to nearest-even
+    FP32, then to nearest-even bfloat16 (8 significant bits), returned in
+    float64 (finite inputs)."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    keep = (u >> np.uint64(16)) & np.uint64(1)          # lowest kept bit
+    u = ((u + np.uint64(0x7FFF) + keep) >> np.uint64(16)) << np.uint64(16)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(f.shape)
 
 
 def make_sketch(seed, dims, sketch_ranks):

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libttround.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tt_round.h")
 
 TT_OK, TT_EINVAL, TT_ENOMEM, TT_EHIP, TT_ENUMERIC, TT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-TT_F64, TT_F32 = 0, 1
+TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 TT_PREC_F64, TT_PREC_F32, TT_PREC_MIXED_BF16 = 0, 1, 2
 
 _STATUS_NAMES = {0: "TT_OK", -1: "TT_EINVAL", -2: "TT_ENOMEM", -3: "TT_EHIP",
@@ -41,9 +41,10 @@ _SIGS = {
     "tt_round_rand_plan": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i64, P_i64, P_i64]),
     "tt_round_rand_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i64, c_i32, P_size]),
     "tt_make_sketch": (ctypes.c_int, [c_u64, c_i32, P_i64, P_i64, c_i32, P_vp, vp]),
-    "tt_partial_contractions_rl_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, P_i64, P_size]),
-    "tt_partial_contractions_rl": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, P_i64, P_vp, P_vp,
-                                                  vp, c_size, vp]),
+    "tt_partial_contractions_rl_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, P_i64, c_i32,
+                                                            P_size]),
+    "tt_partial_contractions_rl": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, P_i64, P_vp, c_i32,
+                                                  P_vp, vp, c_size, vp]),
     "tt_round_rand": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64, c_u64,
                                      c_i32, P_vp, vp, c_size, vp]),
     "tt_round_rand_with_sketch": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64,

@@ -13,7 +13,9 @@ import torch
 from . import _lib as L
 
 _PREC = {"f64": L.TT_PREC_F64, "f32": L.TT_PREC_F32, "bf16": L.TT_PREC_MIXED_BF16}
-_DTYPE = {torch.float64: L.TT_F64, torch.float32: L.TT_F32}
+_DTYPE = {torch.float64: L.TT_F64, torch.float32: L.TT_F32, torch.bfloat16: L.TT_BF16}
+# storage type of the cores in each arithmetic mode
+STORAGE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
 
 
 def _stream_handle(stream=None):
@@ -52,7 +54,7 @@ def _check_cores(cores, what="cores"):
         prev = int(c.shape[2])
     if prev != 1:
         raise ValueError(f"{what}: last rank must be 1")
-    if dt not in _DTYPE:
+    if dt not in (torch.float64, torch.float32):
         raise ValueError(f"{what}: dtype must be float64 or float32")
 
 
@@ -105,9 +107,10 @@ def make_sketch(seed: int, dims, sketch_ranks, dtype=torch.float64, device="cuda
     return cores
 
 
-def partial_contractions_rl(X, Y, stream=None):
+def partial_contractions_rl(X, Y, prec="f64", stream=None):
     """W_n = H(X_{n+1:N}) H(Y_{n+1:N})^T, n = 1..N-1 (Algorithm 3); returns a
-    list indexed by n with entry 0 = None."""
+    list indexed by n with entry 0 = None.  X and Y in the storage type of
+    `prec` (float64 for "f64", float32 for "f32" and "bf16")."""
     import ctypes
     _check_cores(X, "X")
     _check_cores(Y, "Y")
@@ -115,17 +118,20 @@ def partial_contractions_rl(X, Y, stream=None):
     dy, ry = _shape_of(Y)
     if dims != dy:
         raise ValueError("X and Y must share mode sizes")
+    if X[0].dtype != STORAGE[prec] or Y[0].dtype != STORAGE[prec]:
+        raise ValueError(f"prec {prec!r} needs {STORAGE[prec]} cores")
     N = len(dims)
     dev = X[0].device
-    W = [None] + [torch.empty((rx[n], ry[n]), dtype=torch.float64, device=dev)
+    W = [None] + [torch.empty((rx[n], ry[n]), dtype=STORAGE[prec], device=dev)
                   for n in range(1, N)]
     b = ctypes.c_size_t(0)
     L.check(L.lib().tt_partial_contractions_rl_workspace(N, L.i64_array(dims), L.i64_array(rx),
-                                                         L.i64_array(ry), ctypes.byref(b)))
+                                                         L.i64_array(ry), _PREC[prec],
+                                                         ctypes.byref(b)))
     ws = _workspace(b.value, dev)
     L.check(L.lib().tt_partial_contractions_rl(
         N, L.i64_array(dims), L.i64_array(rx), L.ptr_array([c.data_ptr() for c in X]),
-        L.i64_array(ry), L.ptr_array([c.data_ptr() for c in Y]),
+        L.i64_array(ry), L.ptr_array([c.data_ptr() for c in Y]), _PREC[prec],
         L.ptr_array([w.data_ptr() for w in W[1:]]), ctypes.c_void_p(ws.data_ptr()),
         ws.numel(), _stream_handle(stream)))
     return W
@@ -136,7 +142,11 @@ class RoundPlan:
     (the timed benchmark loop allocates nothing)."""
 
     def __init__(self, dims, ranks, target_rank, oversample=0, prec="f64", device="cuda",
-                 dtype=torch.float64, summand_ranks=None):
+                 dtype=None, summand_ranks=None):
+        if prec not in _PREC:
+            raise ValueError(f"unknown prec {prec!r}")
+        if dtype is None:
+            dtype = STORAGE[prec]
         self.dims = [int(d) for d in dims]
         self.N = len(self.dims)
         self.target = int(target_rank)
@@ -218,7 +228,7 @@ def round_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0, prec
     new output cores (clones)."""
     _check_cores(cores)
     dims, ranks = _shape_of(cores)
-    p = RoundPlan(dims, ranks, target_rank, oversample, prec, cores[0].device, cores[0].dtype)
+    p = RoundPlan(dims, ranks, target_rank, oversample, prec, cores[0].device)
     return [c.clone() for c in p.run(cores, seed=seed, sketch=sketch, stream=stream)]
 
 
@@ -227,5 +237,5 @@ def sum_round(summands, coeffs, target_rank: int, oversample: int = 0, seed: int
     """Rounding of sum_j coeffs[j] * summands[j] (Algorithm 7)."""
     dims, _ = _shape_of(summands[0])
     p = RoundPlan(dims, None, target_rank, oversample, prec, summands[0][0].device,
-                  summands[0][0].dtype, summand_ranks=[_shape_of(t)[1] for t in summands])
+                  summand_ranks=[_shape_of(t)[1] for t in summands])
     return [c.clone() for c in p.run_sum(summands, coeffs, seed=seed, stream=stream)]

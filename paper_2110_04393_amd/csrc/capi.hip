@@ -64,12 +64,46 @@ void plan_ranks(int N, const int64_t *dims, const int64_t *R, int64_t target, in
   for (int n = 1; n < N; ++n) out[n] = std::min(target, ell[n]);
 }
 
-int prec_supported(int32_t dtype, int32_t prec) {
-  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "unknown dtype");
-  if (prec < TT_PREC_F64 || prec > TT_PREC_MIXED_BF16) return fail(TT_EINVAL, "unknown prec");
-  if (dtype == TT_F64 && prec == TT_PREC_F64) return TT_OK;
-  return fail(TT_EUNSUPPORTED, "only TT_F64 storage with TT_PREC_F64 is implemented");
+// Arithmetic of one rounding.  F64: everything in FP64.  F32: FP32 storage
+// and MFMA, FP64 Gram matrices (thin QR and truncation) and Cholesky/eigen
+// solves.  MIXED_BF16: as F32, but the partial contractions (Algorithm 3) run
+// on the BF16 MFMA with FP32 accumulation against a BF16 sketch.  Non-FP64
+// modes renormalise each W_n by a power of two (exact; keeps the chain inside
+// the FP32 exponent range for long trains).
+struct Prec {
+  DType store = DType::F64;  // cores, W_n, sweep buffers, outputs
+  DType wmath = DType::F64;  // partial-contraction MFMA arithmetic
+  DType sk = DType::F64;     // sketch storage inside the rounding
+  bool renorm = false;
+};
+
+int prec_cfg(int32_t prec, Prec &p) {
+  switch (prec) {
+    case TT_PREC_F64:
+      p = Prec{DType::F64, DType::F64, DType::F64, false};
+      return TT_OK;
+    case TT_PREC_F32:
+      p = Prec{DType::F32, DType::F32, DType::F32, true};
+      return TT_OK;
+    case TT_PREC_MIXED_BF16:
+      p = Prec{DType::F32, DType::BF16, DType::BF16, true};
+      return TT_OK;
+    default:
+      return fail(TT_EINVAL, "unknown prec");
+  }
 }
+
+int check_dtype(int32_t dtype, const Prec &p) {
+  if (dtype == TT_BF16) return fail(TT_EUNSUPPORTED, "BF16 storage of TT cores is not supported");
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "unknown dtype");
+  if (dtype != (int32_t)p.store)
+    return fail(TT_EINVAL, p.store == DType::F64 ? "TT_PREC_F64 needs TT_F64 storage"
+                                                 : "TT_PREC_F32 and TT_PREC_MIXED_BF16 need "
+                                                   "TT_F32 storage");
+  return TT_OK;
+}
+
+size_t dtype_bytes(DType t) { return t == DType::F64 ? 8 : (t == DType::F32 ? 4 : 2); }
 
 void read_env() {
   const char *q = std::getenv("TT_QR");
@@ -85,9 +119,9 @@ struct Ctx {
   bool dry = true;
   Arena arena;
   hipStream_t s = nullptr;
-  size_t partial_need = 0;  // elements
-  double *partial = nullptr;
-  size_t partial_cap = 0;
+  size_t partial_need = 0;  // bytes of split-K partials
+  void *partial = nullptr;
+  size_t partial_cap = 0;   // bytes
 };
 
 // Opt-in launch timer (tt_timing_start / tt_timing_stop).
@@ -98,23 +132,26 @@ struct Timer {
 };
 Timer g_timer;
 
-template <typename T>
-int gemm(Ctx &c, Gemm<T> g, int site = -1) {
+int gemm(Ctx &c, GemmX g, int site = -1) {
   const int sp = (g.batch > 1) ? 1 : gemm_pick_splits(g.M, g.N, g.K);
-  const size_t need = sp > 1 ? (size_t)sp * g.M * g.N : 0;
+  const size_t need = sp > 1 ? (size_t)sp * g.M * g.N * gemm_acc_bytes(g.math) : 0;
   c.partial_need = std::max(c.partial_need, need);
   if (c.dry) return TT_OK;
   if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split-K buffer too small");
   g.splits = sp;
-  g.partial = reinterpret_cast<T *>(c.partial);
+  g.partial = c.partial;
   const bool timed = site >= 0 && site == g_timer.site && g_timer.used + 2 <= g_timer.ev.size();
   if (timed) TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used], c.s));
-  TTR_TRY(gemm_run<T>(g, c.s));
+  TTR_TRY(gemmx_run(g, c.s));
   if (timed) {
     TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used + 1], c.s));
     g_timer.used += 2;
   }
   return TT_OK;
+}
+template <typename T>
+int gemm(Ctx &c, const Gemm<T> &g, int site = -1) {
+  return gemm(c, g.x(), site);
 }
 
 // Problem description shared by single-TT and sum rounding.  A single TT is
@@ -162,68 +199,87 @@ int make_problem(Problem &P, int s, int N, const int64_t *dims, const int64_t *r
 }
 
 // ---------------------------------------------------------------- W chain
-// W[n] (n = 1..N-1) = H(Y_{n+1:N}) H(Sk_{n+1:N})^T, row-major R_n x L_n with
-// leading dimension ldw[n] (its column count) at the given pointer.
+// Partial contractions of s TTs Y^(j) (cores Y[j*N + n], ranks R[j]) with one
+// sketch TT (cores Sk, ranks L): W^(j)_n = H(Y^(j)_{n+1:N}) H(Sk_{n+1:N})^T for
+// n = 1..N-1, written into the stacked W[n] (rows of summand j start at
+// sum_{i<j} R[i][n], leading dimension L[n]).  Level by level (all summands of
+// level n before level n-1), so that with `renorm` every level is scaled by
+// one power of two common to all summands.
 template <typename T>
-int wchain(Ctx &c, int N, const int64_t *dims, const int64_t *R, const T *const *Y,
-           const int64_t *L, const T *const *Sk, T *const *W) {
-  T *zc = nullptr;
+int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s,
+           const int64_t *const *R, const T *const *Y, const int64_t *L,
+           const void *const *Sk, T *const *W) {
   int64_t zmax = 0;
-  for (int n = 2; n <= N - 1; ++n) zmax = std::max(zmax, R[n - 1] * dims[n - 1] * L[n]);
-  zc = c.arena.take<T>((size_t)zmax);
-  {
-    Gemm<T> g;  // W_{N-1} = H(Y_N) H(Sk_N)^T
-    const int64_t I = dims[N - 1];
-    g.A = Y[N - 1];
-    g.lda = I;
+  for (int j = 0; j < s; ++j)
+    for (int n = 2; n <= N - 1; ++n) zmax = std::max(zmax, R[j][n - 1] * dims[n - 1] * L[n]);
+  T *zc = c.arena.take<T>((size_t)zmax);
+  auto wrow = [&](int j, int n) {  // first row of summand j in the stacked W[n]
+    int64_t off = 0;
+    for (int i = 0; i < j; ++i) off += R[i][n];
+    return W[n] ? W[n] + off * L[n] : nullptr;
+  };
+  auto rows = [&](int n) {
+    int64_t r = 0;
+    for (int j = 0; j < s; ++j) r += R[j][n];
+    return r;
+  };
+  // W_{n-1} (or W_{N-1} from the last core) = H(A) H(Sk_n)^T, A: M x K rows
+  auto sk_product = [&](const T *A, int64_t M, int64_t K, int core, T *C, int64_t ncols) {
+    GemmX g;
+    g.A = A;
+    g.lda = K;
     g.a_kc = true;
-    g.B = Sk[N - 1];
-    g.ldb = I;
+    g.ta = p.store;
+    g.B = Sk[core];
+    g.ldb = K;
     g.b_kc = true;
-    g.C = W[N - 1];
-    g.ldc = L[N - 1];
-    g.M = R[N - 1];
-    g.N = L[N - 1];
-    g.K = I;
-    TTR_TRY(gemm(c, g, TT_SITE_WCHAIN_W));
-  }
+    g.tb = p.sk;
+    g.C = C;
+    g.ldc = ncols;
+    g.tc = p.store;
+    g.M = M;
+    g.N = ncols;
+    g.K = K;
+    g.math = p.wmath;
+    return gemm(c, g, TT_SITE_WCHAIN_W);
+  };
+  for (int j = 0; j < s; ++j)
+    TTR_TRY(sk_product(Y[(size_t)j * N + N - 1], R[j][N - 1], dims[N - 1], N - 1,
+                       wrow(j, N - 1), L[N - 1]));
+  if (renorm && !c.dry) TTR_TRY(scale_pow2<T>(W[N - 1], rows(N - 1) * L[N - 1], c.s));
   for (int n = N - 1; n >= 2; --n) {
     const int64_t I = dims[n - 1];
-    Gemm<T> g;  // V(Z_n) = V(Y_n) W_n
-    g.A = Y[n - 1];
-    g.lda = R[n];
-    g.a_kc = true;
-    g.B = W[n];
-    g.ldb = L[n];
-    g.b_kc = false;
-    g.C = zc;
-    g.ldc = L[n];
-    g.M = R[n - 1] * I;
-    g.N = L[n];
-    g.K = R[n];
-    TTR_TRY(gemm(c, g, TT_SITE_WCHAIN_Z));
-    Gemm<T> h;  // W_{n-1} = H(Z_n) H(Sk_n)^T
-    h.A = zc;
-    h.lda = I * L[n];
-    h.a_kc = true;
-    h.B = Sk[n - 1];
-    h.ldb = I * L[n];
-    h.b_kc = true;
-    h.C = W[n - 1];
-    h.ldc = L[n - 1];
-    h.M = R[n - 1];
-    h.N = L[n - 1];
-    h.K = I * L[n];
-    TTR_TRY(gemm(c, h, TT_SITE_WCHAIN_W));
+    for (int j = 0; j < s; ++j) {
+      GemmX g;  // V(Z_n) = V(Y_n) W_n
+      g.A = Y[(size_t)j * N + n - 1];
+      g.lda = R[j][n];
+      g.a_kc = true;
+      g.ta = p.store;
+      g.B = wrow(j, n);
+      g.ldb = L[n];
+      g.b_kc = false;
+      g.tb = p.store;
+      g.C = zc;
+      g.ldc = L[n];
+      g.tc = p.store;
+      g.M = R[j][n - 1] * I;
+      g.N = L[n];
+      g.K = R[j][n];
+      g.math = p.wmath;
+      TTR_TRY(gemm(c, g, TT_SITE_WCHAIN_Z));
+      TTR_TRY(sk_product(zc, R[j][n - 1], I * L[n], n - 1, wrow(j, n - 1), L[n - 1]));
+    }
+    if (renorm && !c.dry) TTR_TRY(scale_pow2<T>(W[n - 1], rows(n - 1) * L[n - 1], c.s));
   }
   return TT_OK;
 }
 
 // ---------------------------------------------------------------- rounding
-// Y: s summands, cores Y[j*N + n].  Sk: sketch cores.  out: output cores.
+// Y: s summands, cores Y[j*N + n].  Sk: sketch cores (p.sk storage).
+// out: output cores.
 template <typename T>
-int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
-               T *const *out) {
+int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
+               const void *const *Sk, T *const *out) {
   const int N = P.N, s = P.s;
   const int64_t *dims = P.dims.data();
   const std::vector<int64_t> &L = P.ell;
@@ -232,14 +288,10 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
   // ---- W chains: stacked W_n = [W^(1)_n; ...; W^(s)_n], (sum_j R^(j)_n) x l_n
   std::vector<T *> W(N, nullptr);
   for (int n = 1; n <= N - 1; ++n) W[n] = c.arena.take<T>((size_t)(Rs[n] * L[n]));
-  for (int j = 0; j < s; ++j) {
-    std::vector<T *> Wj(N, nullptr);
-    for (int n = 1; n <= N - 1; ++n) {
-      int64_t off = 0;
-      for (int i = 0; i < j; ++i) off += P.R[i][n];
-      Wj[n] = W[n] ? W[n] + off * L[n] : nullptr;
-    }
-    TTR_TRY(wchain<T>(c, N, dims, P.R[j].data(), Y + (size_t)j * N, L.data(), Sk, Wj.data()));
+  {
+    std::vector<const int64_t *> Rj(s);
+    for (int j = 0; j < s; ++j) Rj[j] = P.R[j].data();
+    TTR_TRY(wchain<T>(c, p, p.renorm, N, dims, s, Rj.data(), Y, L.data(), Sk, W.data()));
   }
 
   // ---- buffers of the sweep
@@ -258,11 +310,12 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
   const int64_t lm = P.max_ell;
   qs.gram = c.arena.take<double>((size_t)std::max(lm * lm, 2 * lm));
   qs.rinv = c.arena.take<double>((size_t)std::max(lm * lm, 2 * lm));
-  qs.q1 = c.arena.take<double>((size_t)ys_max * sizeof(T) / sizeof(double) + 1);
+  if (sizeof(T) == 4) qs.rinv_f = c.arena.take<float>((size_t)(lm * lm));
+  qs.q1 = c.arena.take<T>((size_t)ys_max);
   qs.flag = c.arena.take<int>(4);
-  // the QR's own split-K Gram uses the shared partial buffer
+  // the QR's own split-K Gram (FP64 accumulator) uses the shared partial buffer
   for (int n = 1; n <= N - 1; ++n) {
-    const size_t need = qr_partial_elems(L[n - 1] * dims[n - 1], L[n]);
+    const size_t need = qr_partial_elems(L[n - 1] * dims[n - 1], L[n]) * sizeof(double);
     c.partial_need = std::max(c.partial_need, need);
   }
   // sweep output: straight into `out` unless a truncation follows
@@ -384,18 +437,22 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
   int64_t rr = 1;  // right rank of the current core
   for (int n = N; n >= 2; --n) {
     const int64_t lr = L[n - 1], k = P.out[n - 1], cols = dims[n - 1] * rr;
-    Gemm<T> g;  // G = H H^T (FP64 accumulate; T = double here)
+    GemmX g;  // G = H H^T, FP64 arithmetic and result whatever the storage
     g.A = hsrc;
     g.lda = cols;
     g.a_kc = true;
+    g.ta = p.store;
     g.B = hsrc;
     g.ldb = cols;
     g.b_kc = true;
-    g.C = reinterpret_cast<T *>(gbuf);
+    g.tb = p.store;
+    g.C = gbuf;
     g.ldc = lr;
+    g.tc = DType::F64;
     g.M = lr;
     g.N = lr;
     g.K = cols;
+    g.math = DType::F64;
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
     if (!c.dry) TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s));
     Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n)
@@ -432,11 +489,11 @@ int round_exec(Ctx &c, const Problem &P, const T *const *Y, const T *const *Sk,
   return TT_OK;
 }
 
-template <typename T>
-int sketch_exec(Ctx &c, const Problem &P, std::vector<T *> &Sk) {
+// Sketch cores in the workspace, in the mode's sketch storage type.
+int sketch_exec(Ctx &c, const Problem &P, const Prec &p, std::vector<void *> &Sk) {
   Sk.assign(P.N, nullptr);
   for (int n = 0; n < P.N; ++n)
-    Sk[n] = c.arena.take<T>((size_t)(P.ell[n] * P.dims[n] * P.ell[n + 1]));
+    Sk[n] = c.arena.take<char>((size_t)(P.ell[n] * P.dims[n] * P.ell[n + 1]) * dtype_bytes(p.sk));
   return TT_OK;
 }
 
@@ -447,7 +504,7 @@ int run_with_workspace(void *workspace, size_t ws_bytes, hipStream_t s, F body) 
   Ctx dry;
   dry.dry = true;
   TTR_TRY(body(dry));
-  const size_t partial_bytes = (dry.partial_need * sizeof(double) + 255) & ~size_t(255);
+  const size_t partial_bytes = (dry.partial_need + 255) & ~size_t(255);
   const size_t need = partial_bytes + dry.arena.off;
   if (!workspace && need > 0) return fail(TT_EINVAL, "null workspace");
   if (ws_bytes < need)
@@ -458,7 +515,7 @@ int run_with_workspace(void *workspace, size_t ws_bytes, hipStream_t s, F body) 
   real.dry = false;
   real.s = s;
   real.arena.base = static_cast<char *>(workspace);
-  real.partial = real.arena.take<double>(dry.partial_need);
+  real.partial = real.arena.take<char>(dry.partial_need);
   real.partial_cap = dry.partial_need;
   real.arena.off = partial_bytes;
   return body(real);
@@ -470,7 +527,7 @@ int measure_workspace(F body, size_t *bytes) {
   Ctx dry;
   dry.dry = true;
   TTR_TRY(body(dry));
-  *bytes = ((dry.partial_need * sizeof(double) + 255) & ~size_t(255)) + dry.arena.off;
+  *bytes = ((dry.partial_need + 255) & ~size_t(255)) + dry.arena.off;
   return TT_OK;
 }
 
@@ -510,18 +567,26 @@ int tt_sum_round_workspace(int32_t s, int32_t N, const int64_t *dims, const int6
                            size_t *bytes) {
   Problem P;
   TTR_TRY(make_problem(P, s, N, dims, ranks, target_rank, oversample, nullptr));
-  if (prec != TT_PREC_F64) return fail(TT_EUNSUPPORTED, "only TT_PREC_F64 is implemented");
+  Prec pc;
+  TTR_TRY(prec_cfg(prec, pc));
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
   if (N == 1) {
     *bytes = 0;
     return TT_OK;
   }
   return measure_workspace(
-      [&](Ctx &c) {
-        std::vector<double *> Sk;
-        TTR_TRY(sketch_exec<double>(c, P, Sk));
-        std::vector<const double *> Y((size_t)s * N, nullptr);
-        std::vector<double *> out(N, nullptr);
-        return round_exec<double>(c, P, Y.data(), (const double *const *)Sk.data(), out.data());
+      [&](Ctx &c) -> int {
+        std::vector<void *> Sk;
+        TTR_TRY(sketch_exec(c, P, pc, Sk));
+        if (pc.store == DType::F64) {
+          std::vector<const double *> Y((size_t)s * N, nullptr);
+          std::vector<double *> out(N, nullptr);
+          return round_exec<double>(c, P, pc, Y.data(), (const void *const *)Sk.data(),
+                                    out.data());
+        }
+        std::vector<const float *> Y((size_t)s * N, nullptr);
+        std::vector<float *> out(N, nullptr);
+        return round_exec<float>(c, P, pc, Y.data(), (const void *const *)Sk.data(), out.data());
       },
       bytes);
 }
@@ -530,11 +595,57 @@ int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims, const int64_t 
                    int32_t dtype, void *const *cores, void *stream) {
   TTR_TRY(check_shape(N, dims, sketch_ranks, "tt_make_sketch"));
   TTR_TRY(check_ptrs(N, cores, "tt_make_sketch"));
-  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_EINVAL, "unknown dtype");
+  if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16)
+    return fail(TT_EINVAL, "unknown dtype");
   return sketch_generate(seed, N, dims, sketch_ranks, dtype, cores, (hipStream_t)stream);
 }
 
-static int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+}  // extern "C"
+
+namespace ttr {
+namespace {
+
+template <typename T>
+int round_typed(const Problem &P, const Prec &pc, const void *const *cores, bool gen,
+                       uint64_t seed, const void *const *sketch_cores, void *const *out_cores,
+                       void *workspace, size_t ws_bytes, hipStream_t st) {
+  const int N = P.N, s = P.s;
+  if (N == 1) {
+    // a single core: the (weighted) sum itself
+    const int64_t cnt = P.dims[0];
+    T *dst = (T *)out_cores[0];
+    for (int j = 0; j < s; ++j)
+      TTR_TRY(copy2d<T>(dst, cnt, (const T *)cores[j], cnt, 1, cnt, P.coeffs[j],
+                        j == 0 ? 0.0 : 1.0, st));
+    return TT_OK;
+  }
+  const T *const *Y = (const T *const *)cores;
+  T *const *out = (T *const *)out_cores;
+  return run_with_workspace(workspace, ws_bytes, st, [&](Ctx &c) -> int {
+    std::vector<void *> Skw;
+    TTR_TRY(sketch_exec(c, P, pc, Skw));  // same layout with a given sketch
+    std::vector<const void *> Sk(N, nullptr);
+    if (gen) {
+      if (!c.dry)
+        TTR_TRY(sketch_generate(seed, N, P.dims.data(), P.ell.data(), (int)pc.sk,
+                                (void *const *)Skw.data(), c.s));
+      for (int n = 0; n < N; ++n) Sk[n] = Skw[n];
+    } else if (pc.sk == pc.store) {
+      for (int n = 0; n < N; ++n) Sk[n] = sketch_cores[n];
+    } else {
+      // caller's FP32 sketch rounded to the BF16 the partial contractions read
+      for (int n = 0; n < N; ++n) {
+        if (!c.dry)
+          TTR_TRY(round_to_bf16((__bf16 *)Skw[n], (const float *)sketch_cores[n],
+                                P.ell[n] * P.dims[n] * P.ell[n + 1], c.s));
+        Sk[n] = Skw[n];
+      }
+    }
+    return round_exec<T>(c, P, pc, Y, Sk.data(), out);
+  });
+}
+
+int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
                         const void *const *cores, const double *coeffs, int32_t dtype,
                         int64_t target_rank, int64_t oversample, bool gen, uint64_t seed,
                         const int64_t *sketch_ranks, const void *const *sketch_cores,
@@ -543,10 +654,11 @@ static int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t
   read_env();
   Problem P;
   TTR_TRY(make_problem(P, s, N, dims, ranks, target_rank, oversample, coeffs));
-  TTR_TRY(prec_supported(dtype, prec));
+  Prec pc;
+  TTR_TRY(prec_cfg(prec, pc));
+  TTR_TRY(check_dtype(dtype, pc));
   TTR_TRY(check_ptrs(s * N, cores, "input cores"));
   TTR_TRY(check_ptrs(N, out_cores, "output cores"));
-  hipStream_t st = (hipStream_t)stream;
   if (!gen) {
     if (!sketch_ranks) return fail(TT_EINVAL, "null sketch ranks");
     for (int n = 0; n <= N; ++n)
@@ -554,34 +666,18 @@ static int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t
         return fail(TT_EINVAL, "sketch ranks differ from the plan's sketch ranks");
     TTR_TRY(check_ptrs(N, sketch_cores, "sketch cores"));
   }
-  if (N == 1) {
-    // a single core: the (weighted) sum itself
-    const int64_t cnt = dims[0];
-    double *dst = (double *)out_cores[0];
-    for (int j = 0; j < s; ++j)
-      TTR_TRY(copy2d<double>(dst, cnt, (const double *)cores[j], cnt, 1, cnt, P.coeffs[j],
-                             j == 0 ? 0.0 : 1.0, st));
-    return TT_OK;
-  }
-  const double *const *Y = (const double *const *)cores;
-  double *const *out = (double *const *)out_cores;
-  return run_with_workspace(workspace, ws_bytes, st, [&](Ctx &c) -> int {
-    std::vector<double *> Skw;
-    std::vector<const double *> Sk(N, nullptr);
-    if (gen) {
-      TTR_TRY(sketch_exec<double>(c, P, Skw));
-      if (!c.dry) {
-        TTR_TRY(sketch_generate(seed, N, dims, P.ell.data(), TT_F64, (void *const *)Skw.data(),
-                                c.s));
-      }
-      for (int n = 0; n < N; ++n) Sk[n] = Skw[n];
-    } else {
-      TTR_TRY(sketch_exec<double>(c, P, Skw));  // keep the layout identical to the query
-      for (int n = 0; n < N; ++n) Sk[n] = (const double *)sketch_cores[n];
-    }
-    return round_exec<double>(c, P, Y, Sk.data(), out);
-  });
+  hipStream_t st = (hipStream_t)stream;
+  if (pc.store == DType::F64)
+    return round_typed<double>(P, pc, cores, gen, seed, sketch_cores, out_cores, workspace,
+                               ws_bytes, st);
+  return round_typed<float>(P, pc, cores, gen, seed, sketch_cores, out_cores, workspace,
+                            ws_bytes, st);
 }
+
+}  // namespace
+}  // namespace ttr
+
+extern "C" {
 
 int tt_round_rand(int32_t N, const int64_t *dims, const int64_t *ranks, const void *const *cores,
                   int32_t dtype, int64_t target_rank, int64_t oversample, uint64_t sketch_seed,
@@ -641,34 +737,47 @@ int tt_timing_stop(double *total_ms, int32_t *launches) {
 }
 
 int tt_partial_contractions_rl_workspace(int32_t N, const int64_t *dims, const int64_t *ranks_x,
-                                         const int64_t *ranks_y, size_t *bytes) {
+                                         const int64_t *ranks_y, int32_t prec, size_t *bytes) {
   TTR_TRY(check_shape(N, dims, ranks_x, "X"));
   TTR_TRY(check_shape(N, dims, ranks_y, "Y"));
   if (N < 2) return fail(TT_EINVAL, "partial contractions need N >= 2");
+  Prec pc;
+  TTR_TRY(prec_cfg(prec, pc));
+  pc.sk = pc.store;
   return measure_workspace(
-      [&](Ctx &c) {
-        std::vector<const double *> X(N, nullptr), Yc(N, nullptr);
-        std::vector<double *> W(N, nullptr);
-        return wchain<double>(c, N, dims, ranks_x, X.data(), ranks_y, Yc.data(), W.data());
+      [&](Ctx &c) -> int {
+        std::vector<void *> W(N, nullptr), X(N, nullptr);
+        std::vector<const void *> Yc(N, nullptr);
+        if (pc.store == DType::F64)
+          return wchain<double>(c, pc, false, N, dims, 1, &ranks_x, (const double *const *)X.data(),
+                                ranks_y, Yc.data(), (double *const *)W.data());
+        return wchain<float>(c, pc, false, N, dims, 1, &ranks_x, (const float *const *)X.data(),
+                             ranks_y, Yc.data(), (float *const *)W.data());
       },
       bytes);
 }
 
 int tt_partial_contractions_rl(int32_t N, const int64_t *dims, const int64_t *ranks_x,
                                const void *const *x_cores, const int64_t *ranks_y,
-                               const void *const *y_cores, void *const *W_out, void *workspace,
-                               size_t ws_bytes, void *stream) {
+                               const void *const *y_cores, int32_t prec, void *const *W_out,
+                               void *workspace, size_t ws_bytes, void *stream) {
   TTR_TRY(check_shape(N, dims, ranks_x, "X"));
   TTR_TRY(check_shape(N, dims, ranks_y, "Y"));
   if (N < 2) return fail(TT_EINVAL, "partial contractions need N >= 2");
+  Prec pc;
+  TTR_TRY(prec_cfg(prec, pc));
+  pc.sk = pc.store;
   TTR_TRY(check_ptrs(N, x_cores, "X cores"));
   TTR_TRY(check_ptrs(N, y_cores, "Y cores"));
   TTR_TRY(check_ptrs(N - 1, W_out, "W"));
-  std::vector<double *> W(N, nullptr);
-  for (int n = 1; n <= N - 1; ++n) W[n] = (double *)W_out[n - 1];
-  return run_with_workspace(workspace, ws_bytes, (hipStream_t)stream, [&](Ctx &c) {
-    return wchain<double>(c, N, dims, ranks_x, (const double *const *)x_cores, ranks_y,
-                          (const double *const *)y_cores, W.data());
+  std::vector<void *> W(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) W[n] = W_out[n - 1];
+  return run_with_workspace(workspace, ws_bytes, (hipStream_t)stream, [&](Ctx &c) -> int {
+    if (pc.store == DType::F64)
+      return wchain<double>(c, pc, false, N, dims, 1, &ranks_x, (const double *const *)x_cores,
+                            ranks_y, y_cores, (double *const *)W.data());
+    return wchain<float>(c, pc, false, N, dims, 1, &ranks_x, (const float *const *)x_cores,
+                         ranks_y, y_cores, (float *const *)W.data());
   });
 }
 

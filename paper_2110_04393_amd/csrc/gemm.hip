@@ -1,27 +1,34 @@
-// Dense contractions on the CDNA4 matrix cores (v_mfma_*_16x16x4).
+// Dense contractions on the CDNA4 matrix cores.
 //
 // Every contraction of the method (partial contractions of Algorithm 3, the
 // sketch product, projection and next-core product of Algorithm 5, Gram
-// matrices) is C = alpha * A B + beta * C with A and B read through strides.
+// matrices, truncation products) is C = alpha * A B + beta * C with A and B
+// read through strides, in one of three arithmetic modes:
+//   f64   v_mfma_f64_16x16x4f64
+//   f32   v_mfma_f32_16x16x4f32
+//   bf16  v_mfma_f32_16x16x32_bf16 (operands rounded to bf16 to nearest even,
+//         fp32 accumulation)
+// and with f64, f32 or bf16 storage of each operand (converted in registers).
 //
 // Work decomposition.  A wavefront owns a (16 TM) x (16 TN) output tile made
 // of 16x16 MFMA blocks; a workgroup is 4 wavefronts arranged WM x WN.  The K
-// loop runs in chunks of 16: for MFMA step s (0..3) lane l = r + 16 q
-// contributes A(m0 + r, k0 + 4q + s) and B(k0 + 4q + s, n0 + r).  Summing over
-// s then covers k0 .. k0+15 exactly once; the permuted K order lets a lane
-// read 4 consecutive K values of a K-contiguous operand from one cache line,
-// and an M/N-contiguous operand is read by 16 lanes as one 128-byte line.
-// Operands stream from HBM/L2 straight into registers: one f64 MFMA takes 64
-// cycles per SIMD on gfx950, so 2 fragment loads per 4 MFMAs keep the matrix
-// pipe fed without LDS staging.
+// loop runs in chunks of 4*CPL: lane l = r + 16 q supplies A(m0 + r, k) and
+// B(k, n0 + r) for k in [k0 + CPL q, k0 + CPL q + CPL), CPL = 4 for the x4
+// instructions (one value per MFMA, 4 MFMAs per chunk) and 8 for bf16 (eight
+// values packed into one MFMA).  Over the chunk every k is used exactly once,
+// so the permuted order is harmless, and a K-contiguous operand is read as
+// CPL consecutive values per lane while an M/N-contiguous one is read by 16
+// lanes as one cache line.  Operands stream from HBM/L2 into registers: one
+// f64 MFMA occupies the matrix pipe for 64 cycles on gfx950, so the fragment
+// loads of a chunk hide behind the previous chunk's MFMAs without LDS.
 //
-// Output layout of a 16x16 block (MFMA D), lane l = r + 16 q, register j:
-// column r; row q + 4 j for v_mfma_f64_16x16x4f64 (measured on gfx950) and
-// 4 q + j for v_mfma_f32_16x16x4f32.
+// Accumulator layout of a 16x16 block, lane l = r + 16 q, register j:
+// column r; row q + 4 j for the f64 instruction and 4 q + j for the f32 and
+// bf16 ones (both measured on gfx950).
 //
 // Split-K: the K range is cut into chunks; each chunk writes its partial tile
-// and a second kernel adds the chunks in index order, so results are bitwise
-// reproducible (no float atomics).
+// in the accumulator type and a second kernel adds the chunks in index order,
+// so results are bitwise reproducible (no float atomics).
 #include "tt_internal.h"
 
 namespace ttr {
@@ -29,37 +36,75 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-template <typename T>
-struct AccOf;
-template <>
-struct AccOf<double> {
-  typedef d4_t type;
+struct MathF64 {
+  typedef double in_t;
+  typedef d4_t acc_t;
+  typedef double part_t;
+  static constexpr int CPL = 4;
+  __device__ static int row(int q, int j) { return q + 4 * j; }
+  __device__ static acc_t mma(const in_t (&a)[CPL], const in_t (&b)[CPL], acc_t c) {
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
 };
-template <>
-struct AccOf<float> {
-  typedef f4_t type;
+struct MathF32 {
+  typedef float in_t;
+  typedef f4_t acc_t;
+  typedef float part_t;
+  static constexpr int CPL = 4;
+  __device__ static int row(int q, int j) { return 4 * q + j; }
+  __device__ static acc_t mma(const in_t (&a)[CPL], const in_t (&b)[CPL], acc_t c) {
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
+};
+struct MathBF16 {
+  typedef float in_t;
+  typedef f4_t acc_t;
+  typedef float part_t;
+  static constexpr int CPL = 8;
+  __device__ static int row(int q, int j) { return 4 * q + j; }
+  __device__ static acc_t mma(const in_t (&a)[CPL], const in_t (&b)[CPL], acc_t c) {
+    bf8_t x, y;
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) {
+      x[s] = (__bf16)a[s];
+      y[s] = (__bf16)b[s];
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+  }
 };
 
-// row of register j of lane group q in a 16x16 accumulator block
-__device__ __forceinline__ int acc_row(double, int q, int j) { return q + 4 * j; }
-__device__ __forceinline__ int acc_row(float, int q, int j) { return 4 * q + j; }
-
-__device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+template <typename To, typename From>
+__device__ __forceinline__ To cvt(From v) {
+  return (To)v;
 }
-__device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+template <>
+__device__ __forceinline__ float cvt<float, __bf16>(__bf16 v) {
+  return (float)v;
+}
+template <>
+__device__ __forceinline__ double cvt<double, __bf16>(__bf16 v) {
+  return (double)(float)v;
 }
 
 struct TileMap {
   int64_t tiles_m, tiles_n, kchunk;
 };
 
-template <typename T, bool AKC, bool BKC, int TM, int TN, int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_kernel(Gemm<T> g, TileMap tm) {
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
   static_assert(WM * WN == 4, "4 wavefronts per workgroup");
-  typedef typename AccOf<T>::type acc_t;
+  typedef typename MT::acc_t acc_t;
+  typedef typename MT::in_t in_t;
+  typedef typename MT::part_t part_t;
+  constexpr int CPL = MT::CPL;
+  constexpr int CHUNK = 4 * CPL;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int wm = wave % WM, wn = wave / WM;
@@ -70,9 +115,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm<T> g, TileMap tm) {
   wg /= tm.tiles_m;
   const int64_t split = (g.batch > 1) ? 0 : wg;
   const int64_t bidx = (g.batch > 1) ? wg : 0;
-  const T *gA = g.A + bidx * g.sA;
-  const T *gB = g.B + bidx * g.sB;
-  T *gC = g.C + bidx * g.sC;
+  const TA *gA = static_cast<const TA *>(g.A) + bidx * g.sA;
+  const TB *gB = static_cast<const TB *>(g.B) + bidx * g.sB;
+  TC *gC = static_cast<TC *>(g.C) + bidx * g.sC;
 
   const int64_t m0 = (tm_wg * WM + wm) * (16 * TM);
   const int64_t n0 = (tn_wg * WN + wn) * (16 * TN);
@@ -87,52 +132,51 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm<T> g, TileMap tm) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  // per-lane base pointers at k = 4q
-  const T *pa[TM];
-  const T *pb[TN];
+  // per-lane base pointers at k = CPL q
+  const TA *pa[TM];
+  const TB *pb[TN];
   bool rowok[TM], colok[TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int64_t m = m0 + 16 * i + r;
     rowok[i] = m < g.M;
     const int64_t mm = rowok[i] ? m : 0;
-    pa[i] = AKC ? gA + mm * g.lda + 4 * q : gA + (int64_t)(4 * q) * g.lda + mm;
+    pa[i] = AKC ? gA + mm * g.lda + CPL * q : gA + (int64_t)(CPL * q) * g.lda + mm;
   }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int64_t n = n0 + 16 * j + r;
     colok[j] = n < g.N;
     const int64_t nn = colok[j] ? n : 0;
-    pb[j] = BKC ? gB + nn * g.ldb + 4 * q : gB + (int64_t)(4 * q) * g.ldb + nn;
+    pb[j] = BKC ? gB + nn * g.ldb + CPL * q : gB + (int64_t)(CPL * q) * g.ldb + nn;
   }
 
-  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
-    T a[TM][4], b[TN][4];
-    const bool kfull = (k0 + 16 <= kend);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += CHUNK) {
+    in_t a[TM][CPL], b[TN][CPL];
+    const bool kfull = (k0 + CHUNK <= kend);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t k = k0 + 4 * q + s;
+    for (int s = 0; s < CPL; ++s) {
+      const int64_t k = k0 + CPL * q + s;
       const bool kok = kfull || (k < kend);
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const T *p = AKC ? pa[i] + k0 + s : pa[i] + (k0 + s) * g.lda;
-        a[i][s] = (kok && rowok[i]) ? *p : T(0);
+        const TA *p = AKC ? pa[i] + k0 + s : pa[i] + (k0 + s) * g.lda;
+        a[i][s] = (kok && rowok[i]) ? cvt<in_t>(*p) : in_t(0);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const T *p = BKC ? pb[j] + k0 + s : pb[j] + (k0 + s) * g.ldb;
-        b[j][s] = (kok && colok[j]) ? *p : T(0);
+        const TB *p = BKC ? pb[j] + k0 + s : pb[j] + (k0 + s) * g.ldb;
+        b[j][s] = (kok && colok[j]) ? cvt<in_t>(*p) : in_t(0);
       }
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+      for (int j = 0; j < TN; ++j) acc[i][j] = MT::mma(a[i], b[j], acc[i][j]);
   }
 
   // store
+  part_t *part = static_cast<part_t *>(g.partial);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -141,29 +185,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm<T> g, TileMap tm) {
       if (col >= g.N) continue;
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const int64_t row = m0 + 16 * i + acc_row(T(0), q, jj);
+        const int64_t row = m0 + 16 * i + MT::row(q, jj);
         if (row >= g.M) continue;
-        const T v = acc[i][j][jj];
+        const part_t v = acc[i][j][jj];
         if (g.splits > 1) {
-          g.partial[(split * g.M + row) * g.N + col] = v;
+          part[(split * g.M + row) * g.N + col] = v;
         } else {
-          T *c = gC + row * g.ldc + col;
-          *c = (g.beta != T(0)) ? g.alpha * v + g.beta * *c : g.alpha * v;
+          TC *c = gC + row * g.ldc + col;
+          const double out = (g.beta != 0.0)
+                                 ? g.alpha * (double)v + g.beta * cvt<double>(*c)
+                                 : g.alpha * (double)v;
+          *c = (TC)out;
         }
       }
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(Gemm<T> g) {
+template <typename TP, typename TC>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmX g) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = g.M * g.N;
   if (idx >= total) return;
-  T s = 0;
-  for (int p = 0; p < g.splits; ++p) s += g.partial[p * total + idx];
+  const TP *part = static_cast<const TP *>(g.partial);
+  TP s = 0;
+  for (int p = 0; p < g.splits; ++p) s += part[p * total + idx];
   const int64_t row = idx / g.N, col = idx - row * g.N;
-  T *c = g.C + row * g.ldc + col;
-  *c = (g.beta != T(0)) ? g.alpha * s + g.beta * *c : g.alpha * s;
+  TC *c = static_cast<TC *>(g.C) + row * g.ldc + col;
+  const double out = (g.beta != 0.0) ? g.alpha * (double)s + g.beta * cvt<double>(*c)
+                                      : g.alpha * (double)s;
+  *c = (TC)out;
 }
 
 struct Variant {
@@ -193,23 +243,67 @@ int pick_variant(int64_t M, int64_t N) {
   return best;
 }
 
-template <typename T, bool AKC, bool BKC, int TM, int TN, int WM, int WN>
-void launch_v(const Gemm<T> &g, const TileMap &tm, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_kernel<T, AKC, BKC, TM, TN, WM, WN>), dim3((unsigned)grid), dim3(256),
-                     0, s, g, tm);
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC>
+void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s) {
+  const dim3 gr((unsigned)grid), bl(256);
+  switch (v) {
+    case 0:
+      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 1, 1, 1, 4>), gr, bl, 0, s, g, tm);
+      break;
+    case 1:
+      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 1>), gr, bl, 0, s, g, tm);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 2>), gr, bl, 0, s, g, tm);
+      break;
+    default:
+      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>), gr, bl, 0, s, g, tm);
+      break;
+  }
 }
 
-template <typename T, bool AKC, bool BKC>
-void launch_layout(int v, const Gemm<T> &g, const TileMap &tm, int64_t grid, hipStream_t s) {
-  switch (v) {
-    case 0: launch_v<T, AKC, BKC, 1, 1, 1, 4>(g, tm, grid, s); break;
-    case 1: launch_v<T, AKC, BKC, 1, 1, 4, 1>(g, tm, grid, s); break;
-    case 2: launch_v<T, AKC, BKC, 1, 1, 2, 2>(g, tm, grid, s); break;
-    default: launch_v<T, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s); break;
+template <class MT, typename TA, typename TB, typename TC>
+void launch_types(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s) {
+  if (g.a_kc) {
+    if (g.b_kc) launch_layout<MT, TA, TB, TC, true, true>(v, g, tm, grid, s);
+    else launch_layout<MT, TA, TB, TC, true, false>(v, g, tm, grid, s);
+  } else {
+    if (g.b_kc) launch_layout<MT, TA, TB, TC, false, true>(v, g, tm, grid, s);
+    else launch_layout<MT, TA, TB, TC, false, false>(v, g, tm, grid, s);
+  }
+}
+
+constexpr int tkey(DType m, DType a, DType b, DType c) {
+  return ((int)m << 6) | ((int)a << 4) | ((int)b << 2) | (int)c;
+}
+
+// the type combinations the rounding uses
+bool dispatch(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s) {
+  using D = DType;
+  switch (tkey(g.math, g.ta, g.tb, g.tc)) {
+    case tkey(D::F64, D::F64, D::F64, D::F64):
+      launch_types<MathF64, double, double, double>(v, g, tm, grid, s);
+      return true;
+    case tkey(D::F64, D::F32, D::F32, D::F64):
+      launch_types<MathF64, float, float, double>(v, g, tm, grid, s);
+      return true;
+    case tkey(D::F32, D::F32, D::F32, D::F32):
+      launch_types<MathF32, float, float, float>(v, g, tm, grid, s);
+      return true;
+    case tkey(D::BF16, D::F32, D::F32, D::F32):
+      launch_types<MathBF16, float, float, float>(v, g, tm, grid, s);
+      return true;
+    case tkey(D::BF16, D::F32, D::BF16, D::F32):
+      launch_types<MathBF16, float, __bf16, float>(v, g, tm, grid, s);
+      return true;
+    default:
+      return false;
   }
 }
 
 }  // namespace
+
+int gemm_chunk(DType math) { return math == DType::BF16 ? 32 : 16; }
 
 int gemm_pick_splits(int64_t M, int64_t N, int64_t K) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
@@ -220,53 +314,54 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t want = 512;  // workgroups: 2 per CU
   if (wgs >= want / 2) return 1;
   int64_t sp = (want + wgs - 1) / wgs;
-  const int64_t max_by_k = std::max<int64_t>(1, K / 128);  // >= 8 K-chunks each
+  const int64_t max_by_k = std::max<int64_t>(1, K / 128);  // >= 4 K-chunks each
   sp = std::min(sp, max_by_k);
   sp = std::min<int64_t>(sp, 256);
   return (int)std::max<int64_t>(1, sp);
 }
 
-template <typename T>
-int gemm_run(const Gemm<T> &g, hipStream_t s) {
+size_t gemm_acc_bytes(DType math) { return math == DType::F64 ? 8 : 4; }
+
+int gemmx_run(const GemmX &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return TT_OK;
-  if (g.K <= 0) {
-    return fail(TT_EINVAL, "gemm with K <= 0");
-  }
+  if (g.K <= 0) return fail(TT_EINVAL, "gemm with K <= 0");
+  if (g.batch > 1 && g.splits > 1) return fail(TT_EINVAL, "batched split-K gemm");
+  if (g.batch < 1) return TT_OK;
   const int v = pick_variant(g.M, g.N);
   const int64_t bm = 16 * kVariants[v].tm * kVariants[v].wm;
   const int64_t bn = 16 * kVariants[v].tn * kVariants[v].wn;
   TileMap tm;
   tm.tiles_m = (g.M + bm - 1) / bm;
   tm.tiles_n = (g.N + bn - 1) / bn;
-  if (g.batch > 1 && g.splits > 1) return fail(TT_EINVAL, "batched split-K gemm");
-  if (g.batch < 1) return TT_OK;
   const int splits = std::max(1, g.splits);
+  const int chunk = gemm_chunk(g.math);
   int64_t kchunk = (g.K + splits - 1) / splits;
-  kchunk = (kchunk + 15) / 16 * 16;
+  kchunk = (kchunk + chunk - 1) / chunk * chunk;
   const int64_t used_splits = (g.K + kchunk - 1) / kchunk;
-  Gemm<T> gg = g;
+  GemmX gg = g;
   gg.splits = (int)used_splits;
   tm.kchunk = kchunk;
   if (gg.splits > 1 && gg.partial == nullptr) return fail(TT_EINVAL, "split-K without buffer");
   const int64_t grid = tm.tiles_m * tm.tiles_n * (g.batch > 1 ? g.batch : used_splits);
-  if (g.a_kc) {
-    if (g.b_kc) launch_layout<T, true, true>(v, gg, tm, grid, s);
-    else launch_layout<T, true, false>(v, gg, tm, grid, s);
-  } else {
-    if (g.b_kc) launch_layout<T, false, true>(v, gg, tm, grid, s);
-    else launch_layout<T, false, false>(v, gg, tm, grid, s);
-  }
+  if (!dispatch(v, gg, tm, grid, s)) return fail(TT_EINVAL, "internal: gemm type combination");
   TTR_HIP(hipGetLastError());
   if (gg.splits > 1) {
     const int64_t total = g.M * g.N;
-    hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256),
-                       0, s, gg);
+    const dim3 gr((unsigned)((total + 255) / 256)), bl(256);
+    if (g.math == DType::F64) {
+      if (g.tc == DType::F64)
+        hipLaunchKernelGGL((splitk_reduce_kernel<double, double>), gr, bl, 0, s, gg);
+      else
+        hipLaunchKernelGGL((splitk_reduce_kernel<double, float>), gr, bl, 0, s, gg);
+    } else {
+      if (g.tc == DType::F64)
+        hipLaunchKernelGGL((splitk_reduce_kernel<float, double>), gr, bl, 0, s, gg);
+      else
+        hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), gr, bl, 0, s, gg);
+    }
     TTR_HIP(hipGetLastError());
   }
   return TT_OK;
 }
-
-template int gemm_run<double>(const Gemm<double> &, hipStream_t);
-template int gemm_run<float>(const Gemm<float> &, hipStream_t);
 
 }  // namespace ttr

@@ -59,10 +59,14 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchTable t) {
       double *o = static_cast<double *>(t.ptr[c]);
       o[e] = z0;
       if (e + 1 < t.count[c]) o[e + 1] = z1;
-    } else {
+    } else if (t.dtype == TT_F32) {
       float *o = static_cast<float *>(t.ptr[c]);
       o[e] = (float)z0;
       if (e + 1 < t.count[c]) o[e + 1] = (float)z1;
+    } else {  // BF16: rounded to FP32, then to BF16 (both to nearest even)
+      __bf16 *o = static_cast<__bf16 *>(t.ptr[c]);
+      o[e] = bf16_rne((float)z0);
+      if (e + 1 < t.count[c]) o[e + 1] = bf16_rne((float)z1);
     }
   }
 }

@@ -36,7 +36,8 @@ constexpr int kCholMaxOwn = 10;  // upper-triangle entries per thread: 96*97/2 <
 // flag overwritten, else or-ed) and is replaced by the original diagonal so
 // that the results stay finite.
 __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G, double *Rinv,
-                                                                int n, int *flag, int or_flag) {
+                                                                float *Rinv_f, int n, int *flag,
+                                                                int or_flag) {
   extern __shared__ double lds[];
   const int ld = n | 1;          // odd stride: fewer LDS bank conflicts
   double *A = lds;               // n x ld, working matrix, later B
@@ -107,7 +108,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G,
   }
   for (int e = tid; e < n * n; e += blockDim.x) {
     const int i = e / n, c = e - i * n;
-    Rinv[e] = (c >= i) ? A[i * ld + c] * rcp_f64(R[i * ld + i]) : 0.0;
+    const double x = (c >= i) ? A[i * ld + c] * rcp_f64(R[i * ld + i]) : 0.0;
+    Rinv[e] = x;
+    if (Rinv_f) Rinv_f[e] = (float)x;
   }
   if (tid == 0) {
     if (or_flag) {
@@ -238,7 +241,8 @@ size_t qr_partial_elems(int64_t m, int64_t n) {
   return sp > 1 ? (size_t)sp * n * n : 0;
 }
 
-static int chol_inv(const double *G, double *Rinv, int n, int *flag, int or_flag, hipStream_t s) {
+static int chol_inv(const double *G, double *Rinv, float *Rinv_f, int n, int *flag, int or_flag,
+                    hipStream_t s) {
   const size_t lds = 2 * sizeof(double) * (size_t)n * (size_t)(n | 1);
   static bool attr_set = false;
   if (!attr_set) {
@@ -246,8 +250,8 @@ static int chol_inv(const double *G, double *Rinv, int n, int *flag, int or_flag
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
     attr_set = true;
   }
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kCholThreads), lds, s, G, Rinv, n, flag,
-                     or_flag);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kCholThreads), lds, s, G, Rinv, Rinv_f, n,
+                     flag, or_flag);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
@@ -282,33 +286,37 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   if (householder_only)
     return householder<T>(Y, Q, reinterpret_cast<T *>(ws.q1), ws.rinv, ws.rinv + n, m, n,
                           ws.flag, 1, s);
-  static_assert(sizeof(T) == 8, "CholeskyQR2 path is FP64 here");
+  const bool f32 = sizeof(T) == 4;
   T *q1 = reinterpret_cast<T *>(ws.q1);
-  T *partial = reinterpret_cast<T *>(ws.partial);
+  const T *rinv_t = f32 ? reinterpret_cast<const T *>(ws.rinv_f) : reinterpret_cast<const T *>(ws.rinv);
   for (int pass = 0; pass < 2; ++pass) {
     const T *src = pass == 0 ? Y : q1;
     T *dst = pass == 0 ? q1 : Q;
-    Gemm<T> g;  // G = src^T src
+    GemmX g;  // G = src^T src, accumulated in FP64
     g.A = src;
     g.lda = n;
     g.a_kc = false;
+    g.ta = DTypeOf<T>::value;
     g.B = src;
     g.ldb = n;
     g.b_kc = false;
+    g.tb = DTypeOf<T>::value;
     g.C = ws.gram;
     g.ldc = n;
+    g.tc = DType::F64;
+    g.math = DType::F64;
     g.M = n;
     g.N = n;
     g.K = m;
     g.splits = gemm_pick_splits(n, n, m);
-    g.partial = partial;
-    TTR_TRY(gemm_run<T>(g, s));
-    TTR_TRY(chol_inv(ws.gram, ws.rinv, (int)n, ws.flag, pass, s));
-    Gemm<T> h;  // dst = src Rinv
+    g.partial = ws.partial;
+    TTR_TRY(gemmx_run(g, s));
+    TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
+    Gemm<T> h;  // dst = src Rinv, in the storage precision
     h.A = src;
     h.lda = n;
     h.a_kc = true;
-    h.B = ws.rinv;
+    h.B = rinv_t;
     h.ldb = n;
     h.b_kc = false;
     h.C = dst;
@@ -325,5 +333,6 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
 
 template int qr_thin<double>(const double *, double *, int64_t, int64_t, QrScratch &,
                              hipStream_t);
+template int qr_thin<float>(const float *, float *, int64_t, int64_t, QrScratch &, hipStream_t);
 
 }  // namespace ttr

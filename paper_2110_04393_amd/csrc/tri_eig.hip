@@ -55,7 +55,10 @@ __device__ __forceinline__ double sum8(double v) {
   v += dppd<0x141>(v);
   return v;
 }
-__device__ __forceinline__ double sum16(double v) { return (v = sum8(v)) + dppd<0x140>(v); }
+__device__ __forceinline__ double sum16(double v) {
+  v = sum8(v);
+  return v + dppd<0x140>(v);
+}
 __device__ __forceinline__ double max16(double v) {
   v = fmax(v, dppd<0xB1>(v));
   v = fmax(v, dppd<0x4E>(v));
@@ -344,7 +347,6 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
                                                      double *Uz, const int *flag) {
   if (*flag) return;
   __shared__ double s_L[kTeNMax + 1], s_U[kTeNMax + 1], s_z[kTeNMax];
-  __shared__ double s_g[kTeNMax];
   const int lane = threadIdx.x;
   const int w = blockIdx.x;
   // the upper half-wave holds T reversed (same eigenvalues and Sturm counts;

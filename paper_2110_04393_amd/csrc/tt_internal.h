@@ -53,12 +53,58 @@ struct Arena {
 };
 
 // ---------------------------------------------------------------- GEMM
+enum class DType : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+template <typename T>
+struct DTypeOf;
+template <>
+struct DTypeOf<double> {
+  static constexpr DType value = DType::F64;
+};
+template <>
+struct DTypeOf<float> {
+  static constexpr DType value = DType::F32;
+};
+template <>
+struct DTypeOf<__bf16> {
+  static constexpr DType value = DType::BF16;
+};
+
 // C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n), C row-major (ldc).
 // A(m,k) = a_kc ? A[m*lda + k] : A[k*lda + m]
 // B(k,n) = b_kc ? B[n*ldb + k] : B[k*ldb + n]
-// With splits > 1 the K range is cut into `splits` chunks whose partial
-// products go to `partial` (splits*M*N elements) and are summed in chunk
-// order by a second kernel (deterministic).
+// ta/tb/tc: storage types; math: MFMA arithmetic (F64, F32 or BF16 with F32
+// accumulation).  With splits > 1 the K range is cut into chunks whose
+// partial products (accumulator type) go to `partial` (splits*M*N elements)
+// and are summed in chunk order by a second kernel (deterministic).
+struct GemmX {
+  const void *A = nullptr;
+  int64_t lda = 0;
+  bool a_kc = true;
+  DType ta = DType::F64;
+  const void *B = nullptr;
+  int64_t ldb = 0;
+  bool b_kc = false;
+  DType tb = DType::F64;
+  void *C = nullptr;
+  int64_t ldc = 0;
+  DType tc = DType::F64;
+  int64_t M = 0, N = 0, K = 0;
+  double alpha = 1, beta = 0;
+  DType math = DType::F64;
+  int splits = 1;
+  void *partial = nullptr;
+  // batch of independent products: operand pointers advance by sA/sB/sC
+  // elements per batch entry (split-K is not combined with batching)
+  int64_t batch = 1;
+  int64_t sA = 0, sB = 0, sC = 0;
+};
+
+int gemm_pick_splits(int64_t M, int64_t N, int64_t K);
+size_t gemm_acc_bytes(DType math);
+int gemmx_run(const GemmX &g, hipStream_t s);
+
+// same-type convenience form
 template <typename T>
 struct Gemm {
   const T *A = nullptr;
@@ -73,17 +119,50 @@ struct Gemm {
   T alpha = 1, beta = 0;
   int splits = 1;
   T *partial = nullptr;
-  // batch of independent products: operand pointers advance by sA/sB/sC per
-  // batch entry (split-K is not combined with batching)
   int64_t batch = 1;
   int64_t sA = 0, sB = 0, sC = 0;
+  GemmX x() const {
+    GemmX g;
+    g.A = A;
+    g.lda = lda;
+    g.a_kc = a_kc;
+    g.ta = DTypeOf<T>::value;
+    g.B = B;
+    g.ldb = ldb;
+    g.b_kc = b_kc;
+    g.tb = DTypeOf<T>::value;
+    g.C = C;
+    g.ldc = ldc;
+    g.tc = DTypeOf<T>::value;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.math = DTypeOf<T>::value;
+    g.splits = splits;
+    g.partial = partial;
+    g.batch = batch;
+    g.sA = sA;
+    g.sB = sB;
+    g.sC = sC;
+    return g;
+  }
 };
-
-// Number of K chunks chosen for a problem (0 = let the planner decide);
-// returns the partial-buffer element count needed.
-int gemm_pick_splits(int64_t M, int64_t N, int64_t K);
 template <typename T>
-int gemm_run(const Gemm<T> &g, hipStream_t s);
+int gemm_run(const Gemm<T> &g, hipStream_t s) {
+  return gemmx_run(g.x(), s);
+}
+
+// Round a finite FP32 value to the nearest bfloat16, ties to even, in integer
+// arithmetic on its bits (the compiler may not fuse it with an earlier
+// FP64 -> FP32 rounding, which would change the result at double-rounding
+// ties).
+__device__ inline __bf16 bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
+}
 
 // ---------------------------------------------------------------- sketch
 int sketch_generate(uint64_t seed, int N, const int64_t *dims, const int64_t *sranks,
@@ -92,10 +171,13 @@ int sketch_generate(uint64_t seed, int N, const int64_t *dims, const int64_t *sr
 // ---------------------------------------------------------------- QR
 // Thin QR of the m x n row-major matrix Y (n <= TT_MAX_SKETCH_RANK, m >= n),
 // Q written row-major m x n to Q (may not alias Y), diag(R) >= 0.
+// The Gram matrix and its Cholesky factor are always FP64; with FP32 storage
+// R^-1 is also written rounded to FP32 (rinv_f) for the Q = Y R^-1 product.
 struct QrScratch {
   double *gram = nullptr;      // n*n
-  double *rinv = nullptr;      // n*n
-  double *q1 = nullptr;        // m*n (T)
+  double *rinv = nullptr;      // max(n*n, 2n)
+  float *rinv_f = nullptr;     // n*n (FP32 storage only)
+  void *q1 = nullptr;          // m*n elements of the storage type
   int *flag = nullptr;         // 1 int
   void *partial = nullptr;     // split-K partials
 };
@@ -133,5 +215,12 @@ size_t eig_trunc_scratch(int64_t n, int64_t k);
 template <typename T>
 int copy2d(T *dst, int64_t ldd, const T *src, int64_t lds, int64_t rows, int64_t cols,
            double alpha, double beta, hipStream_t s);
+
+// x <- x * 2^-floor(log2 max|x|) (exact; one workgroup, count small)
+template <typename T>
+int scale_pow2(T *x, int64_t count, hipStream_t s);
+
+// dst = RNE_bf16(src)
+int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);
 
 }  // namespace ttr

@@ -394,3 +394,36 @@ def test_round_svd_eps_threshold_closed_form():
     X, ranks, tails = O.round_svd(Y, 2.0 * a * 2 / math.sqrt(3 + a * a))
     assert ranks == [1, 3, 3, 3, 3, 1]
     assert sum(tails) == pytest.approx(a * a, rel=1e-10)
+
+
+def test_round_bf16_hand_values():
+    # 8 significant bits: spacing 2^-7 on [1, 2); ties go to the even neighbour
+    x = np.array([1.0, 1 + 2**-8, 1 + 3 * 2**-8, 1 + 2**-8 + 2**-20, -(1 + 2**-8 + 2**-20),
+                  3.0, 0.0, 2**-130, 65504.0, 1 + 2**-7])
+    want = np.array([1.0, 1.0, 1 + 2**-6, 1 + 2**-7, -(1 + 2**-7), 3.0, 0.0, 2**-130,
+                     65536.0, 1 + 2**-7])
+    np.testing.assert_array_equal(O.round_bf16(x), want)
+
+
+def test_round_bf16_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-20, 20, 20000),
+                        O.round_f32(rng.standard_normal(2000))])
+    t = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O.round_bf16(x), t)
+    # two-step reading: the FP32 rounding comes first
+    np.testing.assert_array_equal(O.round_bf16(x), O.round_bf16(O.round_f32(x)))
+
+
+def test_rto_invariant_under_power_of_two_scaling_of_W():
+    # the reduced-precision modes renormalise each W_n by a power of two; the
+    # RtO output must not depend on it (Q of Z_n W_n is scale invariant)
+    X = G.random_tt(77, [5, 6, 4, 5, 3], [1, 4, 6, 5, 3, 1])
+    sk = O.make_sketch(78, O.dims_of(X), [1, 3, 4, 4, 3, 1])
+    W = O.partial_contractions_rl(X, sk)
+    Ws = [None] + [w * 2.0 ** (-17 * n) for n, w in enumerate(W) if n > 0]
+    A = O.rto_sweep(X, W)
+    B = O.rto_sweep(X, Ws)
+    for a, b in zip(A, B):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)

@@ -162,6 +162,17 @@ def perturbed_tt(seed, N, I, R, eps):
     return block_sum([X1, X2], [1.0, eps]), X1, X2
 
 
+def near_low_rank_tt(seed, dims, r_low, r_high, eps):
+    """X = X1 + eps * X2: X1 a random TT of uniform rank r_low, X2 of rank
+    r_high (cores N(0,1)/sqrt(I r), so that both have norm about 1/sqrt(r)),
+    as one TT of formal rank r_low + r_high.  Rounding to a target >= r_low
+    is then exact up to O(eps)."""
+    N = len(dims)
+    X1 = random_tt(seed, dims, [1] + [r_low] * (N - 1) + [1], scale="nominal")
+    X2 = random_tt(seed + 1, dims, [1] + [r_high] * (N - 1) + [1], scale="nominal")
+    return block_sum([X1, X2], [1.0, eps])
+
+
 def batched_specs(seed=0, B=64):
     """Shapes of the ragged batch: per item N ~ U{8..24}, one I in
     {16,32,64,128,256}, rank R ~ U{8..128}, target R//2, oversample
