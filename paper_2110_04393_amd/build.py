@@ -27,6 +27,9 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-munsafe-fp-atomics",
+    # the small factorisation kernels unroll their step loops completely so
+    # that per-thread matrix slices stay in registers
+    "-mllvm", "-pragma-unroll-threshold=500000",
 ]
 
 

@@ -322,6 +322,19 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t K) {
 
 size_t gemm_acc_bytes(DType math) { return math == DType::F64 ? 8 : 4; }
 
+static int64_t split_kchunk(const GemmX &g) {
+  const int splits = std::max(1, g.splits);
+  const int chunk = gemm_chunk(g.math);
+  int64_t kchunk = (g.K + splits - 1) / splits;
+  return (kchunk + chunk - 1) / chunk * chunk;
+}
+
+int gemm_used_splits(const GemmX &g) {
+  if (g.K <= 0 || g.batch > 1) return 1;
+  const int64_t kchunk = split_kchunk(g);
+  return (int)((g.K + kchunk - 1) / kchunk);
+}
+
 int gemmx_run(const GemmX &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return TT_OK;
   if (g.K <= 0) return fail(TT_EINVAL, "gemm with K <= 0");
@@ -333,10 +346,7 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
   TileMap tm;
   tm.tiles_m = (g.M + bm - 1) / bm;
   tm.tiles_n = (g.N + bn - 1) / bn;
-  const int splits = std::max(1, g.splits);
-  const int chunk = gemm_chunk(g.math);
-  int64_t kchunk = (g.K + splits - 1) / splits;
-  kchunk = (kchunk + chunk - 1) / chunk * chunk;
+  const int64_t kchunk = split_kchunk(g);
   const int64_t used_splits = (g.K + kchunk - 1) / kchunk;
   GemmX gg = g;
   gg.splits = (int)used_splits;
@@ -345,7 +355,7 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
   const int64_t grid = tm.tiles_m * tm.tiles_n * (g.batch > 1 ? g.batch : used_splits);
   if (!dispatch(v, gg, tm, grid, s)) return fail(TT_EINVAL, "internal: gemm type combination");
   TTR_HIP(hipGetLastError());
-  if (gg.splits > 1) {
+  if (gg.splits > 1 && !g.defer_reduce) {
     const int64_t total = g.M * g.N;
     const dim3 gr((unsigned)((total + 255) / 256)), bl(256);
     if (g.math == DType::F64) {

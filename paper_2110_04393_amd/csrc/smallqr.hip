@@ -20,97 +20,248 @@ namespace {
 
 int g_qr_mode = 0;  // 0 auto, 1 householder, 2 cholqr2
 
-constexpr int kCholThreads = 512;
-constexpr int kCholMaxOwn = 10;  // upper-triangle entries per thread: 96*97/2 <= 512*10
+// Upper Cholesky G = R^T R of the n x n FP64 matrix G (row-major,
+// n <= NMAX), then Rinv = R^{-1} (upper triangular, row-major; with FP32
+// storage also rounded to Rinv_f), by one workgroup of four wavefronts.
+// With nsplit > 0, G is the sum (in index order) of nsplit split-K partial
+// products part[p n^2 + e], so the Gram GEMM needs no reduction kernel.
+//
+// Lane c owns column c (and c + 64 when NMAX > 64); wavefront w owns the
+// row block [w NMAX/4, (w+1) NMAX/4) of those columns, in registers.  Both
+// factorisations are blocked by these row blocks:
+// * Cholesky, block J = 0..3: wavefront J factorises its (already updated)
+//   rows one pivot at a time, broadcasting values across its lanes with
+//   readlane (no LDS, no barrier):
+//     R[j][c] = A[j][c] / sqrt(d_j),  A[i][c] -= A[j][i] A[j][c] / d_j  (i in block J, i > j),
+//   publishes the block rows of R to LDS, and after one barrier the
+//   wavefronts below apply the block's rank-NMAX/4 update
+//     A[i][c] -= sum_{j in J} R[j][i] R[j][c].
+// * Inverse, block J = 3..0, right-looking on B = I:
+//     X[j] = B[j] / R[j][j] (row j of R^{-1}),  B[i] -= R[i][j] X[j]  (i < j),
+//   inside block J by its wavefront alone, then the block rows of X are
+//   published and the wavefronts above subtract their contribution.
+// Every loop is unrolled so that register indices are compile-time
+// constants.  A pivot d_j that is not finite or not above 1e-14 of the
+// original diagonal entry raises the flag (or_flag = 0: flag overwritten,
+// else or-ed) and is replaced by the original diagonal (1 if that is not
+// positive) so that the results stay finite.
+constexpr int kCholThreads = 256;
 
-// One workgroup: upper Cholesky G = R^T R of the n x n matrix G (row-major,
-// global, n <= 96), then Rinv = R^{-1} (upper triangular, row-major, global).
-// Every thread owns a fixed set of upper-triangle positions (i, k), so a step
-// is one pass over owned entries and one barrier:
-//   Cholesky step j:  A[i][k] -= A[j][i] A[j][k] / d_j   (j < i <= k),
-//                     R[j][k]  = A[j][k] / sqrt(d_j)      (k >= j),
-//   inverse step j (j = n-1..0, B = I initially):
-//                     B[i][c] -= R[i][j] B[j][c] / R[j][j] (i < j <= c),
-// and R^{-1}[i][c] = B[i][c] / R[i][i].  A pivot d_j that is not finite or not
-// above 1e-14 of the original diagonal entry raises the flag (or_flag = 0:
-// flag overwritten, else or-ed) and is replaced by the original diagonal so
-// that the results stay finite.
-__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G, double *Rinv,
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G, const double *part,
+                                                                int nsplit, double *Rinv,
                                                                 float *Rinv_f, int n, int *flag,
                                                                 int or_flag) {
-  extern __shared__ double lds[];
-  const int ld = n | 1;          // odd stride: fewer LDS bank conflicts
-  double *A = lds;               // n x ld, working matrix, later B
-  double *R = lds + n * ld;      // n x ld
-  __shared__ double s_d0[96];    // original diagonal (pivot test)
+  constexpr int NC = (NMAX + 63) / 64;  // column slots per lane
+  constexpr int RW = NMAX / 4;          // rows per wavefront (one block)
+  static_assert(NMAX % 4 == 0, "rows split over four wavefronts");
+  extern __shared__ double s_R[];       // NMAX x NMAX: G staging, then strict upper R
+  __shared__ double s_X[RW * NC * 64];  // published block rows of R^{-1}
+  __shared__ double s_d0[NMAX];
+  __shared__ double s_rdi[NMAX];        // 1 / R[j][j]
   __shared__ int s_bad;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, k = e - i * n;
-    A[i * ld + k] = G[e];
-    R[i * ld + k] = 0.0;
-  }
-  for (int j = tid; j < n; j += blockDim.x) s_d0[j] = G[j * n + j];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t nn = (int64_t)n * n;
+  // G (summing the split-K partials in index order) staged through LDS;
+  // 16 elements per thread, two partials per round: 32 loads in flight
   if (tid == 0) s_bad = 0;
-  // owned upper-triangle entries, enumerated row by row
-  int own_i[kCholMaxOwn], own_k[kCholMaxOwn];
-  int nown = 0;
-  {
-    const int tri = n * (n + 1) / 2;
-    int i = 0, rowstart = 0;  // row i covers indices [rowstart, rowstart + n - i)
-    for (int e = tid; e < tri && nown < kCholMaxOwn; e += blockDim.x) {
-      while (e >= rowstart + (n - i)) {
-        rowstart += n - i;
-        ++i;
+  for (int e0 = tid; e0 < n * n; e0 += 16 * kCholThreads) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = 0.0;
+    if (nsplit > 0) {
+      int p = 0;
+      for (; p + 1 < nsplit; p += 2) {
+        double w0[16], w1[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int e = min(e0 + k * kCholThreads, n * n - 1);
+          w0[k] = part[p * nn + e];
+          w1[k] = part[(p + 1) * nn + e];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = (v[k] + w0[k]) + w1[k];
       }
-      own_i[nown] = i;
-      own_k[nown] = i + (e - rowstart);
-      ++nown;
+      if (p < nsplit) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] += part[p * nn + min(e0 + k * kCholThreads, n * n - 1)];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = G[min(e0 + k * kCholThreads, n * n - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = e0 + k * kCholThreads;
+      if (e < n * n) s_R[e] = v[k];
     }
   }
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double d = A[j * ld + j];
-    const double d0 = s_d0[j];
-    const bool bad = !(d > 1e-14 * d0) || !(d0 > 0.0) || !isfinite(d);
-    if (bad) d = (d0 > 0.0 && isfinite(d0)) ? d0 : 1.0;
-    if (bad && tid == 0) s_bad = 1;
-    const double inv_r = rsq_f64(d);
-    const double inv_d = inv_r * inv_r;
+  for (int i = tid; i < n; i += kCholThreads) s_d0[i] = s_R[i * n + i];
+  double a[NC][RW];
 #pragma unroll
-    for (int t = 0; t < kCholMaxOwn; ++t) {
-      if (t >= nown) break;
-      const int i = own_i[t], k = own_k[t];
-      if (i == j) {
-        R[j * ld + k] = (k == j) ? d * inv_r : A[j * ld + k] * inv_r;
-      } else if (i > j) {
-        A[i * ld + k] -= A[j * ld + i] * A[j * ld + k] * inv_d;
+  for (int sl = 0; sl < NC; ++sl) {
+    const int col = lane + 64 * sl;
+    const int cc = min(col, n - 1);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int i = RW * wave + r;
+      const double v = s_R[min(i, n - 1) * n + cc];
+      a[sl][r] = (i < n && col < n) ? v : 0.0;
+    }
+  }
+  __syncthreads();  // staging reads done before R overwrites it; s_d0 ready
+  // ---- Cholesky
+#pragma unroll
+  for (int J = 0; J < 4; ++J) {
+    if (RW * J < n) {
+      if (wave == J) {
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          const int j = RW * J + r;
+          if (j < n) {
+            double d = lane_bcast(a[j / 64][r], j % 64);
+            const double d0 = s_d0[j];
+            if (!(d > 1e-14 * d0) || !(d0 > 0.0) || !isfinite(d)) {
+              d = (d0 > 0.0 && isfinite(d0)) ? d0 : 1.0;
+              bad = 1;
+            }
+            const double inv_r = rsq_f64(d);
+            const double inv_d = inv_r * inv_r;
+            double rv[NC], f[NC];
+#pragma unroll
+            for (int sl = 0; sl < NC; ++sl) {
+              const int col = lane + 64 * sl;
+              rv[sl] = a[sl][r];
+              f[sl] = (col > j) ? rv[sl] * inv_d : 0.0;
+              a[sl][r] = (col == j) ? d * inv_r : ((col > j) ? rv[sl] * inv_r : 0.0);
+            }
+#pragma unroll
+            for (int r2 = 0; r2 < RW; ++r2) {
+              if (r2 > r) {
+                const int i = RW * J + r2;
+                const double c = lane_bcast(rv[i / 64], i % 64);  // A[j][i]
+#pragma unroll
+                for (int sl = 0; sl < NC; ++sl) a[sl][r2] -= c * f[sl];
+              }
+            }
+            if (lane == 0) s_rdi[j] = inv_r;
+          }
+        }
+        if (bad && lane == 0) s_bad = 1;
+        // block rows of R, strictly upper part
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          const int j = RW * J + r;
+#pragma unroll
+          for (int sl = 0; sl < NC; ++sl) {
+            const int col = lane + 64 * sl;
+            if (col < NMAX) s_R[j * NMAX + col] = (col > j) ? a[sl][r] : 0.0;
+          }
+        }
+      }
+      __syncthreads();
+      if (wave > J) {
+        // A[i][c] -= sum_{j in J} R[j][i] R[j][c]; R[j][i] read per lane and
+        // broadcast with readlane
+        double rjc[RW][NC], rji[RW];
+#pragma unroll
+        for (int jj = 0; jj < RW; ++jj) {
+          const int j = RW * J + jj;
+#pragma unroll
+          for (int sl = 0; sl < NC; ++sl) rjc[jj][sl] = s_R[j * NMAX + min(lane + 64 * sl, NMAX - 1)];
+          rji[jj] = s_R[j * NMAX + RW * wave + (lane % RW)];
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+#pragma unroll
+          for (int jj = 0; jj < RW; ++jj) {
+            const double c = lane_bcast(rji[jj], r);  // R[j][RW wave + r]
+#pragma unroll
+            for (int sl = 0; sl < NC; ++sl) a[sl][r] -= c * rjc[jj][sl];
+          }
+        }
       }
     }
-    __syncthreads();
   }
-  // B = I on the owned upper triangle (A is free now)
+  // ---- inverse: rows of B = I held like A's
 #pragma unroll
-  for (int t = 0; t < kCholMaxOwn; ++t) {
-    if (t >= nown) break;
-    A[own_i[t] * ld + own_k[t]] = (own_i[t] == own_k[t]) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = n - 1; j >= 1; --j) {
-    const double inv_rjj = rcp_f64(R[j * ld + j]);
+  for (int sl = 0; sl < NC; ++sl)
 #pragma unroll
-    for (int t = 0; t < kCholMaxOwn; ++t) {
-      if (t >= nown) break;
-      const int i = own_i[t], c = own_k[t];
-      if (i < j && c >= j) A[i * ld + c] -= R[i * ld + j] * A[j * ld + c] * inv_rjj;
+    for (int r = 0; r < RW; ++r) a[sl][r] = (RW * wave + r == lane + 64 * sl) ? 1.0 : 0.0;
+  __syncthreads();  // R and 1/R[j][j] complete
+#pragma unroll
+  for (int J = 3; J >= 0; --J) {
+    if (RW * J < n) {
+      if (wave == J) {
+#pragma unroll
+        for (int r = RW - 1; r >= 0; --r) {
+          const int j = RW * J + r;
+          if (j < n) {
+            const double inv = s_rdi[j];
+            double x[NC];
+#pragma unroll
+            for (int sl = 0; sl < NC; ++sl) {
+              x[sl] = a[sl][r] * inv;
+              a[sl][r] = x[sl];
+            }
+#pragma unroll
+            for (int r2 = 0; r2 < RW; ++r2) {
+              if (r2 < r) {
+                const double rij = s_R[(RW * J + r2) * NMAX + j];  // R[i][j]
+#pragma unroll
+                for (int sl = 0; sl < NC; ++sl) a[sl][r2] -= rij * x[sl];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int sl = 0; sl < NC; ++sl) s_X[r * (NC * 64) + lane + 64 * sl] = a[sl][r];
+      }
+      __syncthreads();
+      if (wave < J) {
+        // B[i][c] -= sum_{j in J} R[i][j] X[j][c]
+        double xj[RW][NC];
+#pragma unroll
+        for (int jj = 0; jj < RW; ++jj)
+#pragma unroll
+          for (int sl = 0; sl < NC; ++sl) xj[jj][sl] = s_X[jj * (NC * 64) + lane + 64 * sl];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          const double *rrow = s_R + (RW * wave + r) * NMAX + RW * J;
+#pragma unroll
+          for (int jj = 0; jj < RW; ++jj) {
+            const double rij = rrow[jj];
+#pragma unroll
+            for (int sl = 0; sl < NC; ++sl) a[sl][r] -= rij * xj[jj][sl];
+          }
+        }
+      }
+      __syncthreads();  // s_X is rewritten by the next block
     }
-    __syncthreads();
   }
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, c = e - i * n;
-    const double x = (c >= i) ? A[i * ld + c] * rcp_f64(R[i * ld + i]) : 0.0;
-    Rinv[e] = x;
-    if (Rinv_f) Rinv_f[e] = (float)x;
+#pragma unroll
+  for (int sl = 0; sl < NC; ++sl) {
+    const int col = lane + 64 * sl;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int i = RW * wave + r;
+      if (i < n && col < n) {
+        const double x = (i <= col) ? a[sl][r] : 0.0;
+        Rinv[(int64_t)i * n + col] = x;
+        if (Rinv_f) Rinv_f[(int64_t)i * n + col] = (float)x;
+      }
+    }
   }
   if (tid == 0) {
     if (or_flag) {
@@ -241,19 +392,30 @@ size_t qr_partial_elems(int64_t m, int64_t n) {
   return sp > 1 ? (size_t)sp * n * n : 0;
 }
 
-static int chol_inv(const double *G, double *Rinv, float *Rinv_f, int n, int *flag, int or_flag,
-                    hipStream_t s) {
-  const size_t lds = 2 * sizeof(double) * (size_t)n * (size_t)(n | 1);
+template <int NMAX>
+static int chol_inv_launch(const double *G, const double *part, int nsplit, double *Rinv,
+                           float *Rinv_f, int n, int *flag, int or_flag, hipStream_t s) {
+  const size_t lds = sizeof(double) * NMAX * NMAX;
   static bool attr_set = false;
   if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)chol_inv_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
+    TTR_HIP(hipFuncSetAttribute((const void *)chol_inv_kernel<NMAX>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = true;
   }
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kCholThreads), lds, s, G, Rinv, Rinv_f, n,
-                     flag, or_flag);
+  hipLaunchKernelGGL((chol_inv_kernel<NMAX>), dim3(1), dim3(kCholThreads), lds, s, G, part, nsplit, Rinv,
+                     Rinv_f, n, flag, or_flag);
   TTR_HIP(hipGetLastError());
   return TT_OK;
+}
+
+// Cholesky + inverse of the n x n Gram (n <= TT_MAX_SKETCH_RANK); nsplit > 0:
+// the Gram is the sum of nsplit split-K partials in `part`.
+static int chol_inv(const double *G, const double *part, int nsplit, double *Rinv, float *Rinv_f,
+                    int n, int *flag, int or_flag, hipStream_t s) {
+  if (n <= 32) return chol_inv_launch<32>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag, s);
+  if (n <= 64) return chol_inv_launch<64>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag, s);
+  if (n <= 96) return chol_inv_launch<96>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag, s);
+  return fail(TT_EUNSUPPORTED, "Cholesky of a Gram matrix wider than 96");
 }
 
 constexpr int64_t kHhLdsElems = 10000;  // 2 * m * n doubles must fit in LDS
@@ -310,8 +472,11 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     g.K = m;
     g.splits = gemm_pick_splits(n, n, m);
     g.partial = ws.partial;
+    g.defer_reduce = true;  // the Cholesky kernel sums the partials
     TTR_TRY(gemmx_run(g, s));
-    TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
+    const int nsp = gemm_used_splits(g);
+    TTR_TRY(chol_inv(ws.gram, (const double *)ws.partial, nsp > 1 ? nsp : 0, ws.rinv,
+                     f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
     Gemm<T> h;  // dst = src Rinv, in the storage precision
     h.A = src;
     h.lda = n;

@@ -98,9 +98,14 @@ struct GemmX {
   // elements per batch entry (split-K is not combined with batching)
   int64_t batch = 1;
   int64_t sA = 0, sB = 0, sC = 0;
+  // split-K only: leave the partials for the consumer (no reduction kernel,
+  // C untouched); gemm_used_splits() tells how many there are
+  bool defer_reduce = false;
 };
 
 int gemm_pick_splits(int64_t M, int64_t N, int64_t K);
+// number of split-K partials gemmx_run writes for g (1 = none, C written)
+int gemm_used_splits(const GemmX &g);
 size_t gemm_acc_bytes(DType math);
 int gemmx_run(const GemmX &g, hipStream_t s);
 
