@@ -218,6 +218,39 @@ TT_API int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t
                  size_t ws_bytes, void *stream);
 
 /*
+ * Deterministic TT-rounding (Algorithms 1 and 2), the comparator of the
+ * randomized methods.  Algorithm 1 right-orthogonalises the input by thin
+ * QR factorisations from core N down to core 2; Algorithm 2 then sweeps left
+ * to right, replacing each core by the leading left singular vectors of its
+ * QR factor and carrying s_k V_k^T into the next core.  The singular pairs
+ * come from the FP64 Gram of the core's vertical unfolding (same left
+ * subspace and singular values as the R factor).
+ * Rank rule (section 2, Algorithm 2; absolute threshold): with eps0 > 0 keep
+ * at bond n the smallest k >= 1 with sqrt(sum_{j>=k} s_j^2) <=
+ * eps0 ||Y|| / sqrt(N-1), capped by max_rank (max_rank <= 0: no cap); with
+ * eps0 = 0 keep k = min(max_rank, bound).  Then ||X - Y|| <= eps0 ||Y||.
+ * With eps0 > 0 every bond's rank is read back by the host: the call waits
+ * for `stream` once per core.  With eps0 = 0 it is asynchronous.
+ *   tt_round_svd_plan   host only: out_ranks[N+1] receives upper bounds of
+ *                       the output ranks (the shapes to allocate)
+ *   prec                TT_PREC_F64 (TT_F64 storage) or TT_PREC_F32 (TT_F32
+ *                       storage; Grams and eigenproblems in FP64)
+ *   out_cores[N]        caller buffers of at least the plan's sizes; core n
+ *                       is written C-contiguous with the actual ranks
+ *   out_ranks[N+1]      host, written with the actual ranks
+ * Limits: every bond rank after Algorithm 1 <= TT_MAX_SKETCH_RANK
+ * (TT_EUNSUPPORTED otherwise).
+ */
+TT_API int tt_round_svd_plan(int32_t N, const int64_t *dims, const int64_t *ranks,
+                             int64_t max_rank, int64_t *out_ranks);
+TT_API int tt_round_svd_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                  int64_t max_rank, int32_t prec, size_t *bytes);
+TT_API int tt_round_svd(int32_t N, const int64_t *dims, const int64_t *ranks,
+                        const void *const *cores, int32_t dtype, double eps0, int64_t max_rank,
+                        int32_t prec, void *const *out_cores, int64_t *out_ranks,
+                        void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Kernel timing (instrumentation, off by default).  tt_timing_start arms a
  * recorder for one call site of the rounding path: every later launch from
  * that site is bracketed by a pair of HIP events recorded on the launch

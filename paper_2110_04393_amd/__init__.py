@@ -5,5 +5,6 @@ built ``libttround.so`` (``python -m paper_2110_04393_amd.build``).
 """
 from ._lib import TTError, header_functions, lib  # noqa: F401
 from .api import (STORAGE, RoundPlan, make_sketch, partial_contractions_rl,  # noqa: F401
-                  plan, round_rand, round_rand_workspace, sum_round, sum_round_workspace,
+                  plan, round_rand, round_rand_workspace, round_svd, sum_round,
+                  sum_round_workspace,
                   version)

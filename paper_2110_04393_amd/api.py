@@ -222,6 +222,38 @@ class RoundPlan:
         return self.out
 
 
+def round_svd(cores, eps0: float = 0.0, max_rank: int = 0, prec: str = "f64", stream=None):
+    """Deterministic TT-rounding (Algorithms 1 and 2).  Returns the output
+    cores at their actual ranks (views of freshly allocated buffers)."""
+    import ctypes
+    _check_cores(cores)
+    if prec not in ("f64", "f32"):
+        raise ValueError("round_svd supports prec 'f64' and 'f32'")
+    if cores[0].dtype != STORAGE[prec]:
+        raise ValueError(f"prec {prec!r} needs {STORAGE[prec]} cores")
+    dims, ranks = _shape_of(cores)
+    N = len(dims)
+    bound = L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_round_svd_plan(N, L.i64_array(dims), L.i64_array(ranks), int(max_rank),
+                                      bound))
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_round_svd_workspace(N, L.i64_array(dims), L.i64_array(ranks),
+                                           int(max_rank), _PREC[prec], ctypes.byref(b)))
+    dev = cores[0].device
+    ws = _workspace(b.value, dev)
+    bufs = [torch.empty(bound[n] * dims[n] * bound[n + 1], dtype=cores[0].dtype, device=dev)
+            for n in range(N)]
+    out_r = L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_round_svd(N, L.i64_array(dims), L.i64_array(ranks),
+                                 L.ptr_array([c.data_ptr() for c in cores]), _DTYPE[cores[0].dtype],
+                                 float(eps0), int(max_rank), _PREC[prec],
+                                 L.ptr_array([x.data_ptr() for x in bufs]), out_r,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 _stream_handle(stream)))
+    r = [out_r[n] for n in range(N + 1)]
+    return [bufs[n][: r[n] * dims[n] * r[n + 1]].view(r[n], dims[n], r[n + 1]) for n in range(N)]
+
+
 def round_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0, prec: str = "f64",
                sketch: Optional[list] = None, stream=None):
     """Randomize-then-Orthogonalize rounding (Algorithm 5) of a TT; returns

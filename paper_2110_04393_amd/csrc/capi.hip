@@ -11,6 +11,7 @@
 //      next core M_n H(Y_{n+1}) (per summand for sums)
 //   4. right-to-left truncation when an output rank is below the sketch rank
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 
@@ -489,6 +490,271 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   return TT_OK;
 }
 
+// ---------------------------------------------------------------- TT-SVD
+// Deterministic rounding: Algorithm 1 (right-to-left orthogonalisation)
+// followed by Algorithm 2 (left-to-right truncation).
+//
+// Algorithm 1, core n = N..2: with H = H(X_n) (c x m, m = I_n r_n):
+//   m >= c: thin QR of H^T (transposed into a tall panel) gives Q; the new
+//           core is Q^T, and R^T = H Q is carried into X_{n-1};
+//   m <  c: the rank drops to m; the new core is the identity and H itself
+//           is carried into X_{n-1} (an exact gauge change).
+// Algorithm 2, core n = 1..N-1: with A = V(X_n) (m x c), the SVD of the QR
+// factor R of A has the right singular vectors and singular values of the
+// Gram A^T A = R^T R; with its leading eigenpairs (V_k, s_k^2):
+//   V(X_n) <- A V_k s_k^-1 (= Q U_k),   H(X_{n+1}) <- s_k V_k^T H(X_{n+1}),
+// so no explicit Q is formed.  The rank is fixed (k = min(max_rank, c, m))
+// or chosen on the device by the eps rule and read back by the host.
+struct SvdPlan {
+  int N = 0;
+  std::vector<int64_t> dims, R;   // input ranks
+  std::vector<int64_t> rr;        // ranks after Algorithm 1
+  std::vector<int64_t> kmax;      // output rank bounds
+  int64_t max_rank = 0;
+  int64_t max_c = 1;              // widest Gram / QR panel
+};
+
+int make_svd_plan(SvdPlan &P, int N, const int64_t *dims, const int64_t *ranks,
+                  int64_t max_rank) {
+  TTR_TRY(check_shape(N, dims, ranks, "tt_round_svd"));
+  P.N = N;
+  P.dims.assign(dims, dims + N);
+  P.R.assign(ranks, ranks + N + 1);
+  P.max_rank = max_rank;
+  P.rr.assign(N + 1, 1);
+  for (int n = N; n >= 2; --n) P.rr[n - 1] = std::min(P.R[n - 1], dims[n - 1] * P.rr[n]);
+  P.kmax.assign(N + 1, 1);
+  P.max_c = 1;
+  for (int n = 1; n <= N - 1; ++n) {
+    int64_t k = std::min(P.rr[n], P.kmax[n - 1] * dims[n - 1]);
+    if (max_rank > 0) k = std::min(k, max_rank);
+    P.kmax[n] = k;
+    P.max_c = std::max(P.max_c, P.rr[n]);
+  }
+  for (int n = N; n >= 2; --n)
+    if (dims[n - 1] * P.rr[n] >= P.R[n - 1]) P.max_c = std::max(P.max_c, P.R[n - 1]);
+  if (N > 1 && P.max_c > TT_MAX_SKETCH_RANK)
+    return fail(TT_EUNSUPPORTED, "tt_round_svd: a bond rank above TT_MAX_SKETCH_RANK");
+  return TT_OK;
+}
+
+template <typename T>
+int svd_exec(Ctx &c, const SvdPlan &P, const T *const *Y, double eps0, T *const *out,
+             int64_t *out_ranks) {
+  const int N = P.N;
+  const int64_t *dims = P.dims.data();
+  const DType dt = DTypeOf<T>::value;
+  int64_t core_max = 1, pan_max = 1;
+  for (int n = 0; n < N; ++n) {
+    core_max = std::max(core_max, P.R[n] * dims[n] * P.R[n + 1]);
+    pan_max = std::max(pan_max, P.R[n] * dims[n] * P.R[n + 1]);
+  }
+  std::vector<T *> xs(N + 1, nullptr);
+  for (int n = 1; n <= N; ++n) xs[n] = c.arena.take<T>((size_t)core_max);
+  T *spare = c.arena.take<T>((size_t)core_max);
+  T *pan = c.arena.take<T>((size_t)pan_max);
+  T *qb = c.arena.take<T>((size_t)core_max);
+  const int64_t lc = P.max_c;
+  T *rt = c.arena.take<T>((size_t)(lc * lc));
+  T *cbuf = c.arena.take<T>((size_t)(lc * lc));
+  double *gbuf = c.arena.take<double>((size_t)(lc * lc));
+  double *lam = c.arena.take<double>((size_t)lc + 1);
+  double *U = c.arena.take<double>((size_t)(lc * lc));
+  T *Pf = c.arena.take<T>((size_t)(lc * lc));
+  T *Sf = c.arena.take<T>((size_t)(lc * lc));
+  double *tails = c.arena.take<double>((size_t)N + 1);
+  double *dnorm = c.arena.take<double>(1);
+  int *eflag = c.arena.take<int>(4);
+  int *dk = c.arena.take<int>((size_t)N + 1);
+  double *escr = c.arena.take<double>(eig_trunc_scratch(lc, lc));
+  QrScratch qs;
+  qs.gram = c.arena.take<double>((size_t)std::max(lc * lc, 2 * lc));
+  qs.rinv = c.arena.take<double>((size_t)std::max(lc * lc, 2 * lc));
+  if (sizeof(T) == 4) qs.rinv_f = c.arena.take<float>((size_t)(lc * lc));
+  qs.q1 = c.arena.take<T>((size_t)pan_max);
+  qs.flag = c.arena.take<int>(4);
+
+  // working copies of the cores
+  for (int n = 1; n <= N; ++n)
+    if (!c.dry)
+      TTR_TRY(copy2d<T>(xs[n], 1, Y[n - 1], 1, P.R[n - 1] * dims[n - 1] * P.R[n], 1, 1.0, 0.0,
+                        c.s));
+  std::vector<int64_t> left(P.R.begin(), P.R.end());  // current bond ranks
+  // ---- Algorithm 1
+  for (int n = N; n >= 2; --n) {
+    const int64_t cc = left[n - 1], I = dims[n - 1], m = I * P.rr[n];
+    const int64_t rows_prev = left[n - 2] * dims[n - 2];
+    if (m >= cc) {
+      c.partial_need = std::max(c.partial_need, qr_partial_elems(m, cc) * sizeof(double));
+      if (!c.dry) {
+        TTR_TRY(transpose<T>(pan, xs[n], cc, m, c.s));  // H^T: m x cc
+        qs.partial = c.partial;
+        TTR_TRY(qr_thin<T>(pan, qb, m, cc, qs, c.s));
+      }
+      Gemm<T> g;  // R^T = H Q  (cc x cc)
+      g.A = xs[n];
+      g.lda = m;
+      g.a_kc = true;
+      g.B = qb;
+      g.ldb = cc;
+      g.b_kc = false;
+      g.C = rt;
+      g.ldc = cc;
+      g.M = cc;
+      g.N = cc;
+      g.K = m;
+      TTR_TRY(gemm(c, g));
+      if (!c.dry) TTR_TRY(transpose<T>(xs[n], qb, m, cc, c.s));  // new core: Q^T
+      Gemm<T> h;  // V(X_{n-1}) <- V(X_{n-1}) R^T
+      h.A = xs[n - 1];
+      h.lda = cc;
+      h.a_kc = true;
+      h.B = rt;
+      h.ldb = cc;
+      h.b_kc = false;
+      h.C = spare;
+      h.ldc = cc;
+      h.M = rows_prev;
+      h.N = cc;
+      h.K = cc;
+      TTR_TRY(gemm(c, h));
+      std::swap(xs[n - 1], spare);
+      left[n - 1] = cc;
+    } else {
+      Gemm<T> h;  // V(X_{n-1}) <- V(X_{n-1}) H(X_n), core n <- I (m x m)
+      h.A = xs[n - 1];
+      h.lda = cc;
+      h.a_kc = true;
+      h.B = xs[n];
+      h.ldb = m;
+      h.b_kc = false;
+      h.C = spare;
+      h.ldc = m;
+      h.M = rows_prev;
+      h.N = m;
+      h.K = cc;
+      TTR_TRY(gemm(c, h));
+      std::swap(xs[n - 1], spare);
+      if (!c.dry) TTR_TRY(fill_identity<T>(xs[n], m, c.s));
+      left[n - 1] = m;
+    }
+  }
+  // ||Y|| = ||X_1||_F once the other cores are orthonormal
+  if (!c.dry && eps0 > 0.0) TTR_TRY(frob_norm<T>(xs[1], dims[0] * left[1], dnorm, c.s));
+  // ---- Algorithm 2
+  std::vector<int64_t> k(N + 1, 1);
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t cc = left[n], m = k[n - 1] * dims[n - 1];
+    const int64_t kcap = std::min(P.kmax[n], m);
+    GemmX g;  // Gram A^T A (cc x cc), FP64
+    g.A = xs[n];
+    g.lda = cc;
+    g.a_kc = false;
+    g.ta = dt;
+    g.B = xs[n];
+    g.ldb = cc;
+    g.b_kc = false;
+    g.tb = dt;
+    g.C = gbuf;
+    g.ldc = cc;
+    g.tc = DType::F64;
+    g.M = cc;
+    g.N = cc;
+    g.K = m;
+    g.math = DType::F64;
+    TTR_TRY(gemm(c, g));
+    const int64_t keig = eps0 > 0.0 ? cc : kcap;
+    if (!c.dry) TTR_TRY(eig_trunc<T>(gbuf, cc, keig, lam, U, Pf, Sf, tails + n, eflag, escr, c.s));
+    int64_t kn = kcap;
+    if (eps0 > 0.0 && !c.dry) {
+      TTR_TRY(select_rank(lam, (int)cc, dnorm, eps0, N, (int)kcap, dk + n, tails + n, c.s));
+      int hk = 0;
+      TTR_HIP(hipMemcpyAsync(&hk, dk + n, sizeof(int), hipMemcpyDeviceToHost, c.s));
+      TTR_HIP(hipStreamSynchronize(c.s));
+      if (hk < 1 || hk > kcap) return fail(TT_ENUMERIC, "tt_round_svd: invalid truncation rank");
+      kn = hk;
+    }
+    k[n] = kn;
+    // B = A S_k^T (m x kn); B = Q' R' (thin QR, restores orthonormality lost
+    // to the squared conditioning of the Gram); V(X_n) <- Q';
+    // H(X_{n+1}) <- (R' P_k^T) H(X_{n+1})
+    const int64_t cols = dims[n] * left[n + 1];
+    auto issue = [&](int64_t kk) -> int {
+      Gemm<T> a;
+      a.A = xs[n];
+      a.lda = cc;
+      a.a_kc = true;
+      a.B = Sf;
+      a.ldb = cc;
+      a.b_kc = true;
+      a.C = spare;
+      a.ldc = kk;
+      a.M = m;
+      a.N = kk;
+      a.K = cc;
+      TTR_TRY(gemm(c, a));
+      c.partial_need = std::max(c.partial_need, qr_partial_elems(m, kk) * sizeof(double));
+      if (!c.dry) {
+        qs.partial = c.partial;
+        TTR_TRY(qr_thin<T>(spare, qb, m, kk, qs, c.s));
+      }
+      Gemm<T> r;  // R' = Q'^T B (kk x kk)
+      r.A = qb;
+      r.lda = kk;
+      r.a_kc = false;
+      r.B = spare;
+      r.ldb = kk;
+      r.b_kc = false;
+      r.C = rt;
+      r.ldc = kk;
+      r.M = kk;
+      r.N = kk;
+      r.K = m;
+      TTR_TRY(gemm(c, r));
+      Gemm<T> q;  // C = R' P_k^T (kk x cc)
+      q.A = rt;
+      q.lda = kk;
+      q.a_kc = true;
+      q.B = Pf;
+      q.ldb = keig;
+      q.b_kc = true;
+      q.C = cbuf;
+      q.ldc = cc;
+      q.M = kk;
+      q.N = cc;
+      q.K = kk;
+      TTR_TRY(gemm(c, q));
+      Gemm<T> b;  // H(X_{n+1}) <- C H(X_{n+1})  (kk x cols)
+      b.A = cbuf;
+      b.lda = cc;
+      b.a_kc = true;
+      b.B = xs[n + 1];
+      b.ldb = cols;
+      b.b_kc = false;
+      b.C = spare;
+      b.ldc = cols;
+      b.M = kk;
+      b.N = cols;
+      b.K = cc;
+      return gemm(c, b);
+    };
+    if (c.dry) {
+      for (int64_t kk = 1; kk <= kcap; ++kk) TTR_TRY(issue(kk));  // any eps rank
+    } else {
+      TTR_TRY(issue(kn));
+      std::swap(xs[n], qb);     // Q' is the new core n
+      std::swap(xs[n + 1], spare);
+    }
+  }
+  for (int n = 1; n <= N; ++n) {
+    const int64_t cnt = k[n - 1] * dims[n - 1] * (n == N ? 1 : k[n]);
+    if (!c.dry) TTR_TRY(copy2d<T>(out[n - 1], 1, xs[n], 1, cnt, 1, 1.0, 0.0, c.s));
+  }
+  if (out_ranks)
+    for (int n = 0; n <= N; ++n) out_ranks[n] = k[n];
+  return TT_OK;
+}
+
 // Sketch cores in the workspace, in the mode's sketch storage type.
 int sketch_exec(Ctx &c, const Problem &P, const Prec &p, std::vector<void *> &Sk) {
   Sk.assign(P.N, nullptr);
@@ -705,6 +971,84 @@ int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks
   return round_common(s, N, dims, ranks, cores, coeffs, dtype, target_rank, oversample, true,
                       sketch_seed, nullptr, nullptr, prec, out_cores, workspace, ws_bytes,
                       stream);
+}
+
+int tt_round_svd_plan(int32_t N, const int64_t *dims, const int64_t *ranks, int64_t max_rank,
+                      int64_t *out_ranks) {
+  if (!out_ranks) return fail(TT_EINVAL, "null out_ranks");
+  SvdPlan P;
+  TTR_TRY(make_svd_plan(P, N, dims, ranks, max_rank));
+  for (int n = 0; n <= N; ++n) out_ranks[n] = (N == 1) ? 1 : P.kmax[n];
+  return TT_OK;
+}
+
+static int svd_prec(int32_t prec, DType &store) {
+  if (prec == TT_PREC_F64) store = DType::F64;
+  else if (prec == TT_PREC_F32) store = DType::F32;
+  else if (prec == TT_PREC_MIXED_BF16)
+    return fail(TT_EUNSUPPORTED, "tt_round_svd has no mixed-precision mode");
+  else return fail(TT_EINVAL, "unknown prec");
+  return TT_OK;
+}
+
+int tt_round_svd_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                           int64_t max_rank, int32_t prec, size_t *bytes) {
+  SvdPlan P;
+  TTR_TRY(make_svd_plan(P, N, dims, ranks, max_rank));
+  DType st;
+  TTR_TRY(svd_prec(prec, st));
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  if (N == 1) {
+    *bytes = 0;
+    return TT_OK;
+  }
+  return measure_workspace(
+      [&](Ctx &c) -> int {
+        if (st == DType::F64) {
+          std::vector<const double *> Y(N, nullptr);
+          std::vector<double *> out(N, nullptr);
+          return svd_exec<double>(c, P, Y.data(), 1.0, out.data(), nullptr);
+        }
+        std::vector<const float *> Y(N, nullptr);
+        std::vector<float *> out(N, nullptr);
+        return svd_exec<float>(c, P, Y.data(), 1.0, out.data(), nullptr);
+      },
+      bytes);
+}
+
+int tt_round_svd(int32_t N, const int64_t *dims, const int64_t *ranks, const void *const *cores,
+                 int32_t dtype, double eps0, int64_t max_rank, int32_t prec,
+                 void *const *out_cores, int64_t *out_ranks, void *workspace, size_t ws_bytes,
+                 void *stream) {
+  read_env();
+  SvdPlan P;
+  TTR_TRY(make_svd_plan(P, N, dims, ranks, max_rank));
+  DType st;
+  TTR_TRY(svd_prec(prec, st));
+  if (dtype != (int32_t)st) return fail(TT_EINVAL, "dtype does not match the precision mode");
+  if (!(eps0 >= 0.0) || !std::isfinite(eps0)) return fail(TT_EINVAL, "eps0 must be finite and >= 0");
+  if (!out_ranks) return fail(TT_EINVAL, "null out_ranks");
+  TTR_TRY(check_ptrs(N, cores, "input cores"));
+  TTR_TRY(check_ptrs(N, out_cores, "output cores"));
+  hipStream_t sm = (hipStream_t)stream;
+  if (N == 1) {
+    const int64_t cnt = dims[0];
+    if (st == DType::F64)
+      TTR_TRY(copy2d<double>((double *)out_cores[0], 1, (const double *)cores[0], 1, cnt, 1, 1.0,
+                             0.0, sm));
+    else
+      TTR_TRY(copy2d<float>((float *)out_cores[0], 1, (const float *)cores[0], 1, cnt, 1, 1.0,
+                            0.0, sm));
+    out_ranks[0] = out_ranks[1] = 1;
+    return TT_OK;
+  }
+  return run_with_workspace(workspace, ws_bytes, sm, [&](Ctx &c) -> int {
+    if (st == DType::F64)
+      return svd_exec<double>(c, P, (const double *const *)cores, eps0, (double *const *)out_cores,
+                              c.dry ? nullptr : out_ranks);
+    return svd_exec<float>(c, P, (const float *const *)cores, eps0, (float *const *)out_cores,
+                           c.dry ? nullptr : out_ranks);
+  });
 }
 
 int tt_timing_start(int32_t site, int32_t capacity) {

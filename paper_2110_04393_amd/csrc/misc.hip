@@ -54,7 +54,114 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(__bf16 *dst, const float *
     dst[e] = bf16_rne(src[e]);
 }
 
+// dst (cols x rows) = src (rows x cols)^T, both row-major, 32 x 32 tiles
+// through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(T *dst, const T *src, int64_t rows,
+                                                        int64_t cols) {
+  __shared__ T tile[32][33];
+  const int64_t tiles_c = (cols + 31) / 32;
+  const int64_t r0 = (blockIdx.x / tiles_c) * 32, c0 = (blockIdx.x % tiles_c) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) dst[c * rows + r] = tile[tx][k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void identity_kernel(T *dst, int64_t m) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (e / m == e % m) ? T(1) : T(0);
+}
+
+// out = ||x||_F in FP64, one workgroup, fixed summation order.
+template <typename T>
+__global__ __launch_bounds__(256) void frob_kernel(const T *x, int64_t count, double *out) {
+  __shared__ double s_part[4];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < count; e += 256) {
+    const double v = (double)x[e];
+    acc = fma(v, v, acc);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = sqrt(((s_part[0] + s_part[1]) + s_part[2]) + s_part[3]);
+}
+
+// Rank of the eps-truncation: the smallest k >= 1 with
+// sum_{j >= k} max(lam_j, 0) <= (eps0 * norm)^2 / (N - 1), capped by kmax;
+// lam descending.  Also writes that tail.
+__global__ void select_rank_kernel(const double *lam, int n, const double *norm, double eps0,
+                                   int N, int kmax, int *k_out, double *tail_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double eps = eps0 * (*norm);
+  const double thr = eps * eps / (double)(N - 1);
+  double tail = 0.0;
+  int k = n;
+  for (int j = n - 1; j >= 1; --j) {  // tail after keeping j values
+    const double t = tail + fmax(lam[j], 0.0);
+    if (!(t <= thr)) break;
+    tail = t;
+    k = j;
+  }
+  if (k > kmax) {
+    k = kmax;
+    tail = 0.0;
+    for (int j = k; j < n; ++j) tail += fmax(lam[j], 0.0);
+  }
+  *k_out = k;
+  *tail_out = tail;
+}
+
 }  // namespace
+
+template <typename T>
+int transpose(T *dst, const T *src, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return TT_OK;
+  const int64_t blocks = ((rows + 31) / 32) * ((cols + 31) / 32);
+  hipLaunchKernelGGL((transpose_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, dst, src, rows,
+                     cols);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int transpose<double>(double *, const double *, int64_t, int64_t, hipStream_t);
+template int transpose<float>(float *, const float *, int64_t, int64_t, hipStream_t);
+
+template <typename T>
+int fill_identity(T *dst, int64_t m, hipStream_t s) {
+  if (m <= 0) return TT_OK;
+  const int64_t blocks = std::min<int64_t>((m * m + 255) / 256, 4096);
+  hipLaunchKernelGGL((identity_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, dst, m);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int fill_identity<double>(double *, int64_t, hipStream_t);
+template int fill_identity<float>(float *, int64_t, hipStream_t);
+
+template <typename T>
+int frob_norm(const T *x, int64_t count, double *out, hipStream_t s) {
+  hipLaunchKernelGGL((frob_kernel<T>), dim3(1), dim3(256), 0, s, x, count, out);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int frob_norm<double>(const double *, int64_t, double *, hipStream_t);
+template int frob_norm<float>(const float *, int64_t, double *, hipStream_t);
+
+int select_rank(const double *lam, int n, const double *norm, double eps0, int N, int kmax,
+                int *k_out, double *tail_out, hipStream_t s) {
+  hipLaunchKernelGGL(select_rank_kernel, dim3(1), dim3(64), 0, s, lam, n, norm, eps0, N, kmax,
+                     k_out, tail_out);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
 
 template <typename T>
 int scale_pow2(T *x, int64_t count, hipStream_t s) {

@@ -228,4 +228,18 @@ int scale_pow2(T *x, int64_t count, hipStream_t s);
 // dst = RNE_bf16(src)
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);
 
+// dst (cols x rows) = src (rows x cols)^T, row-major
+template <typename T>
+int transpose(T *dst, const T *src, int64_t rows, int64_t cols, hipStream_t s);
+// dst = I (m x m)
+template <typename T>
+int fill_identity(T *dst, int64_t m, hipStream_t s);
+// *out = ||x||_F (FP64, deterministic)
+template <typename T>
+int frob_norm(const T *x, int64_t count, double *out, hipStream_t s);
+// eps-truncation rank from descending eigenvalues lam of a Gram matrix:
+// smallest k >= 1 with sum_{j>=k} lam_j <= (eps0 norm)^2/(N-1), capped by kmax
+int select_rank(const double *lam, int n, const double *norm, double eps0, int N, int kmax,
+                int *k_out, double *tail_out, hipStream_t s);
+
 }  // namespace ttr

@@ -87,3 +87,44 @@ def test_sketch_rejects_bad_shape():
     st = L.lib().tt_make_sketch(1, 2, L.i64_array([3, 3]), L.i64_array([1, 2, 2]), 0,
                                 L.ptr_array([1, 2]), None)
     assert st == L.TT_EINVAL
+
+
+def test_round_svd_plan_bounds_oracle_ranks():
+    import oracle as O
+    import tt_inputs as G
+    for dims, ranks, k in [([5, 6, 4, 5, 3, 4], [1, 5, 8, 8, 6, 4, 1], 4),
+                           ([3, 4, 5, 3], [1, 3, 8, 6, 1], 0),
+                           ([7, 9], [1, 7, 1], 2)]:
+        N = len(dims)
+        out = L.i64_array([0] * (N + 1))
+        L.check(L.lib().tt_round_svd_plan(N, L.i64_array(dims), L.i64_array(ranks), k, out))
+        bound = [out[i] for i in range(N + 1)]
+        Y = G.random_tt(3, dims, ranks)
+        _, rr, _ = O.round_svd(Y, 0.0, k if k > 0 else None)
+        assert bound[0] == bound[N] == 1
+        assert all(r <= b for r, b in zip(rr, bound)), (rr, bound)
+        if k > 0:
+            assert rr == bound  # fixed rank: the bound is attained
+
+
+def test_round_svd_rejects_bad_arguments():
+    dims, ranks = [4, 4, 4], [1, 2, 2, 1]
+    ptrs = L.ptr_array([1, 1, 1])
+    outr = L.i64_array([0] * 4)
+    lib = L.lib()
+    st = lib.tt_round_svd(3, L.i64_array(dims), L.i64_array(ranks), ptrs, L.TT_F64, -1.0, 0,
+                          L.TT_PREC_F64, ptrs, outr, None, 0, None)
+    assert st == L.TT_EINVAL
+    st = lib.tt_round_svd(3, L.i64_array(dims), L.i64_array(ranks), ptrs, L.TT_F32, 0.0, 0,
+                          L.TT_PREC_F64, ptrs, outr, None, 0, None)
+    assert st == L.TT_EINVAL
+    b = L.c_size(0)
+    import ctypes
+    st = lib.tt_round_svd_workspace(3, L.i64_array(dims), L.i64_array(ranks), 0,
+                                    L.TT_PREC_MIXED_BF16, ctypes.byref(b))
+    assert st == L.TT_EUNSUPPORTED
+    # a bond wider than the small-panel limit
+    st = lib.tt_round_svd_workspace(3, L.i64_array([200, 200, 200]),
+                                    L.i64_array([1, 150, 150, 1]), 0, L.TT_PREC_F64,
+                                    ctypes.byref(b))
+    assert st == L.TT_EUNSUPPORTED
