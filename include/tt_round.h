@@ -218,6 +218,33 @@ TT_API int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t
                  size_t ws_bytes, void *stream);
 
 /*
+ * Reverse mode (vector-Jacobian product) of tt_round_rand for roundings
+ * without truncation (every out rank equals its sketch rank), single TT,
+ * sketch fixed by `sketch_seed` (not differentiated).  Algorithm 5 is
+ * recomputed forward (the partial contractions W_n are recomputed, never
+ * kept between calls), then run in reverse: the next-core product, the
+ * projection M_n = Q^T Z_n, the thin QR (adjoint with R unused:
+ * dY = (dQ + Q copyltu(-dQ^T Q)) R^{-T}, copyltu(A) = tril(A) +
+ * tril(A, -1)^T), the sketch product Y_n = Z_n W_n, and finally the partial
+ * contractions of Algorithm 3.
+ *   cores       input TT (as for tt_round_rand)
+ *   grad_out[N] device cotangents of the output cores (out-rank shapes)
+ *   grad_in[N]  device buffers of the input core shapes, overwritten with
+ *               the gradient
+ *   prec        TT_PREC_F64 (TT_F64) or TT_PREC_F32 (TT_F32)
+ * Returns TT_EUNSUPPORTED when the rounding truncates (target_rank below a
+ * sketch rank) or for TT_PREC_MIXED_BF16.
+ */
+TT_API int tt_round_rand_backward_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                            int64_t target_rank, int64_t oversample,
+                                            int32_t prec, size_t *bytes);
+TT_API int tt_round_rand_backward(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                  const void *const *cores, int32_t dtype, int64_t target_rank,
+                                  int64_t oversample, uint64_t sketch_seed, int32_t prec,
+                                  const void *const *grad_out, void *const *grad_in,
+                                  void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Deterministic TT-rounding (Algorithms 1 and 2), the comparator of the
  * randomized methods.  Algorithm 1 right-orthogonalises the input by thin
  * QR factorisations from core N down to core 2; Algorithm 2 then sweeps left

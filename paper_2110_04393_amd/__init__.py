@@ -8,3 +8,4 @@ from .api import (STORAGE, RoundPlan, make_sketch, partial_contractions_rl,  # n
                   plan, round_rand, round_rand_workspace, round_svd, sum_round,
                   sum_round_workspace,
                   version)
+from .autograd import round_rand_ad, round_rand_backward  # noqa: F401,E402

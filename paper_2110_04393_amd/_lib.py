@@ -55,6 +55,10 @@ _SIGS = {
     "tt_round_svd_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i32, P_size]),
     "tt_round_svd": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_dbl, c_i64, c_i32, P_vp,
                                     P_i64, vp, c_size, vp]),
+    "tt_round_rand_backward_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i64, c_i32,
+                                                        P_size]),
+    "tt_round_rand_backward": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64, c_u64,
+                                              c_i32, P_vp, P_vp, vp, c_size, vp]),
     "tt_timing_start": (ctypes.c_int, [c_i32, c_i32]),
     "tt_timing_stop": (ctypes.c_int, [P_dbl, ctypes.POINTER(c_i32)]),
     "tt_sum_round": (ctypes.c_int, [c_i32, c_i32, P_i64, P_i64, P_vp, P_dbl, c_i32, c_i64, c_i64,

@@ -209,7 +209,7 @@ int make_problem(Problem &P, int s, int N, const int64_t *dims, const int64_t *r
 template <typename T>
 int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s,
            const int64_t *const *R, const T *const *Y, const int64_t *L,
-           const void *const *Sk, T *const *W) {
+           const void *const *Sk, T *const *W, double *factors = nullptr) {
   int64_t zmax = 0;
   for (int j = 0; j < s; ++j)
     for (int n = 2; n <= N - 1; ++n) zmax = std::max(zmax, R[j][n - 1] * dims[n - 1] * L[n]);
@@ -247,7 +247,9 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
   for (int j = 0; j < s; ++j)
     TTR_TRY(sk_product(Y[(size_t)j * N + N - 1], R[j][N - 1], dims[N - 1], N - 1,
                        wrow(j, N - 1), L[N - 1]));
-  if (renorm && !c.dry) TTR_TRY(scale_pow2<T>(W[N - 1], rows(N - 1) * L[N - 1], c.s));
+  if (renorm && !c.dry)
+    TTR_TRY(scale_pow2<T>(W[N - 1], rows(N - 1) * L[N - 1], c.s,
+                          factors ? factors + N - 1 : nullptr));
   for (int n = N - 1; n >= 2; --n) {
     const int64_t I = dims[n - 1];
     for (int j = 0; j < s; ++j) {
@@ -270,7 +272,9 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
       TTR_TRY(gemm(c, g, TT_SITE_WCHAIN_Z));
       TTR_TRY(sk_product(zc, R[j][n - 1], I * L[n], n - 1, wrow(j, n - 1), L[n - 1]));
     }
-    if (renorm && !c.dry) TTR_TRY(scale_pow2<T>(W[n - 1], rows(n - 1) * L[n - 1], c.s));
+    if (renorm && !c.dry)
+      TTR_TRY(scale_pow2<T>(W[n - 1], rows(n - 1) * L[n - 1], c.s,
+                            factors ? factors + n - 1 : nullptr));
   }
   return TT_OK;
 }
@@ -488,6 +492,344 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     rr = k;
   }
   return TT_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+// Reverse mode of Randomize-then-Orthogonalize without truncation (single
+// TT, sketch fixed).  The forward pass is recomputed first (W chain,
+// including its power-of-two factors in the FP32 mode, and the sweep, whose
+// current cores Z_n, factors Q_n, M_n and R_n^{-1} stay in the workspace).
+// Then, with dX~_N = the cotangent of the last output core and n = N-1..1:
+//   dM_n = dH(X~_{n+1}) H(Y_{n+1})^T          dH(Y_{n+1})  = M_n^T dH(X~_{n+1})
+//   dQ   = dO_n + Z_n dM_n^T                   dZ_n         = Q_n dM_n
+//   dY_n = (dQ + Q_n copyltu(-dQ^T Q_n)) R_n^{-T}     (QR adjoint, R unused)
+//   dZ_n += dY_n W_n^T                         dW_n         = Z_n^T dY_n
+// and dX~_n = dZ_n (dY_1 = dZ_1).  Finally the W chain in reverse, n = 1..N-2:
+//   dZc = f_n dW_n H(S_{n+1}),  dV(Y_{n+1}) += dV(Zc) W_{n+1}^T,
+//   dW_{n+1} += V(Y_{n+1})^T dV(Zc),   and dH(Y_N) += f_{N-1} dW_{N-1} H(S_N)
+// (f_n: the power-of-two factor applied to W_n, 1 in FP64).
+template <typename T>
+int backward_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
+                  const void *const *Sk, const T *const *gout, T *const *gin) {
+  const int N = P.N;
+  const int64_t *dims = P.dims.data();
+  const std::vector<int64_t> &L = P.ell;
+  const std::vector<int64_t> &R = P.R[0];
+  // ---- forward recomputation
+  std::vector<T *> W(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) W[n] = c.arena.take<T>((size_t)(R[n] * L[n]));
+  double *fac = c.arena.take<double>((size_t)N + 1);
+  {
+    const int64_t *Rp = R.data();
+    TTR_TRY(wchain<T>(c, p, p.renorm, N, dims, 1, &Rp, Y, L.data(), Sk, W.data(), fac));
+  }
+  std::vector<T *> xt(N + 1, nullptr), q(N, nullptr), mm(N, nullptr);
+  std::vector<double *> rinv(N, nullptr);
+  std::vector<float *> rinvf(N, nullptr);
+  int64_t m_max = 1, x_max = 1, l_max = 1, r_max = 1;
+  for (int n = 1; n <= N; ++n) {
+    x_max = std::max(x_max, L[n - 1] * dims[n - 1] * R[n]);
+    l_max = std::max(l_max, L[n]);
+    r_max = std::max(r_max, R[n]);
+    if (n <= N - 1) m_max = std::max(m_max, L[n - 1] * dims[n - 1]);
+  }
+  xt[1] = const_cast<T *>(Y[0]);
+  for (int n = 2; n <= N; ++n) xt[n] = c.arena.take<T>((size_t)(L[n - 1] * dims[n - 1] * R[n]));
+  for (int n = 1; n <= N - 1; ++n) {
+    q[n] = c.arena.take<T>((size_t)(L[n - 1] * dims[n - 1] * L[n]));
+    mm[n] = c.arena.take<T>((size_t)(L[n] * R[n]));
+    rinv[n] = c.arena.take<double>((size_t)(L[n] * L[n]));
+    if (sizeof(T) == 4) rinvf[n] = c.arena.take<float>((size_t)(L[n] * L[n]));
+  }
+  T *ys = c.arena.take<T>((size_t)(m_max * l_max));
+  double *gram = c.arena.take<double>((size_t)(l_max * l_max));
+  int *cflag = c.arena.take<int>(4);
+  QrScratch qs;
+  qs.gram = c.arena.take<double>((size_t)std::max(l_max * l_max, 2 * l_max));
+  qs.rinv = c.arena.take<double>((size_t)std::max(l_max * l_max, 2 * l_max));
+  if (sizeof(T) == 4) qs.rinv_f = c.arena.take<float>((size_t)(l_max * l_max));
+  qs.q1 = c.arena.take<T>((size_t)(m_max * l_max));
+  qs.flag = c.arena.take<int>(4);
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t m = L[n - 1] * dims[n - 1];
+    Gemm<T> g;  // Y_n = Z_n W_n
+    g.A = xt[n];
+    g.lda = R[n];
+    g.a_kc = true;
+    g.B = W[n];
+    g.ldb = L[n];
+    g.b_kc = false;
+    g.C = ys;
+    g.ldc = L[n];
+    g.M = m;
+    g.N = L[n];
+    g.K = R[n];
+    TTR_TRY(gemm(c, g));
+    c.partial_need = std::max(c.partial_need, qr_partial_elems(m, L[n]) * sizeof(double));
+    if (!c.dry) {
+      qs.partial = c.partial;
+      TTR_TRY(qr_thin<T>(ys, q[n], m, L[n], qs, c.s));
+    }
+    GemmX gr;  // FP64 Gram of Y_n, Cholesky -> R_n^{-1}
+    gr.A = ys;
+    gr.lda = L[n];
+    gr.a_kc = false;
+    gr.ta = p.store;
+    gr.B = ys;
+    gr.ldb = L[n];
+    gr.b_kc = false;
+    gr.tb = p.store;
+    gr.C = gram;
+    gr.ldc = L[n];
+    gr.tc = DType::F64;
+    gr.M = L[n];
+    gr.N = L[n];
+    gr.K = m;
+    gr.math = DType::F64;
+    TTR_TRY(gemm(c, gr));
+    if (!c.dry) TTR_TRY(chol_inverse(gram, L[n], rinv[n], rinvf[n], cflag, c.s));
+    Gemm<T> h;  // M_n = Q^T Z_n
+    h.A = q[n];
+    h.lda = L[n];
+    h.a_kc = false;
+    h.B = xt[n];
+    h.ldb = R[n];
+    h.b_kc = false;
+    h.C = mm[n];
+    h.ldc = R[n];
+    h.M = L[n];
+    h.N = R[n];
+    h.K = m;
+    TTR_TRY(gemm(c, h));
+    const int64_t cols = dims[n] * R[n + 1];
+    Gemm<T> k;  // H(X~_{n+1}) = M_n H(Y_{n+1})
+    k.A = mm[n];
+    k.lda = R[n];
+    k.a_kc = true;
+    k.B = Y[n];
+    k.ldb = cols;
+    k.b_kc = false;
+    k.C = xt[n + 1];
+    k.ldc = cols;
+    k.M = L[n];
+    k.N = cols;
+    k.K = R[n];
+    TTR_TRY(gemm(c, k));
+  }
+  // ---- reverse sweep
+  T *dxb[2] = {c.arena.take<T>((size_t)x_max), c.arena.take<T>((size_t)x_max)};
+  T *dM = c.arena.take<T>((size_t)(l_max * r_max));
+  T *dQ = c.arena.take<T>((size_t)(m_max * l_max));
+  T *dYs = c.arena.take<T>((size_t)(m_max * l_max));
+  T *Mq = c.arena.take<T>((size_t)(l_max * l_max));
+  T *Cq = c.arena.take<T>((size_t)(l_max * l_max));
+  std::vector<T *> dW(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) dW[n] = c.arena.take<T>((size_t)(R[n] * L[n]));
+  const T *dX = gout[N - 1];
+  for (int n = N - 1; n >= 1; --n) {
+    const int64_t m = L[n - 1] * dims[n - 1], cols = dims[n] * R[n + 1];
+    const int64_t ln = L[n], rn = R[n];
+    Gemm<T> a;  // dM = dH(X~_{n+1}) H(Y_{n+1})^T
+    a.A = dX;
+    a.lda = cols;
+    a.a_kc = true;
+    a.B = Y[n];
+    a.ldb = cols;
+    a.b_kc = true;
+    a.C = dM;
+    a.ldc = rn;
+    a.M = ln;
+    a.N = rn;
+    a.K = cols;
+    TTR_TRY(gemm(c, a));
+    Gemm<T> b;  // dH(Y_{n+1}) = M_n^T dH(X~_{n+1})
+    b.A = mm[n];
+    b.lda = rn;
+    b.a_kc = false;
+    b.B = dX;
+    b.ldb = cols;
+    b.b_kc = false;
+    b.C = gin[n];
+    b.ldc = cols;
+    b.M = rn;
+    b.N = cols;
+    b.K = ln;
+    TTR_TRY(gemm(c, b));
+    if (!c.dry) TTR_TRY(copy2d<T>(dQ, 1, gout[n - 1], 1, m * ln, 1, 1.0, 0.0, c.s));
+    Gemm<T> d;  // dQ += Z_n dM^T
+    d.A = xt[n];
+    d.lda = rn;
+    d.a_kc = true;
+    d.B = dM;
+    d.ldb = rn;
+    d.b_kc = true;
+    d.C = dQ;
+    d.ldc = ln;
+    d.M = m;
+    d.N = ln;
+    d.K = rn;
+    d.beta = T(1);
+    TTR_TRY(gemm(c, d));
+    T *dZ = (n == 1) ? gin[0] : dxb[n & 1];
+    Gemm<T> e;  // dZ = Q_n dM
+    e.A = q[n];
+    e.lda = ln;
+    e.a_kc = true;
+    e.B = dM;
+    e.ldb = rn;
+    e.b_kc = false;
+    e.C = dZ;
+    e.ldc = rn;
+    e.M = m;
+    e.N = rn;
+    e.K = ln;
+    TTR_TRY(gemm(c, e));
+    Gemm<T> f;  // Mq = dQ^T Q
+    f.A = dQ;
+    f.lda = ln;
+    f.a_kc = false;
+    f.B = q[n];
+    f.ldb = ln;
+    f.b_kc = false;
+    f.C = Mq;
+    f.ldc = ln;
+    f.M = ln;
+    f.N = ln;
+    f.K = m;
+    TTR_TRY(gemm(c, f));
+    if (!c.dry) TTR_TRY(copyltu<T>(Cq, Mq, ln, -1.0, c.s));
+    Gemm<T> g;  // dQ += Q copyltu(-dQ^T Q)
+    g.A = q[n];
+    g.lda = ln;
+    g.a_kc = true;
+    g.B = Cq;
+    g.ldb = ln;
+    g.b_kc = false;
+    g.C = dQ;
+    g.ldc = ln;
+    g.M = m;
+    g.N = ln;
+    g.K = ln;
+    g.beta = T(1);
+    TTR_TRY(gemm(c, g));
+    GemmX hx;  // dY_n = dQ R^{-T}
+    hx.A = dQ;
+    hx.lda = ln;
+    hx.a_kc = true;
+    hx.ta = p.store;
+    hx.B = (sizeof(T) == 4) ? (const void *)rinvf[n] : (const void *)rinv[n];
+    hx.ldb = ln;
+    hx.b_kc = true;
+    hx.tb = p.store;
+    hx.C = dYs;
+    hx.ldc = ln;
+    hx.tc = p.store;
+    hx.M = m;
+    hx.N = ln;
+    hx.K = ln;
+    hx.math = p.store;
+    TTR_TRY(gemm(c, hx));
+    Gemm<T> i2;  // dZ += dY_n W_n^T
+    i2.A = dYs;
+    i2.lda = ln;
+    i2.a_kc = true;
+    i2.B = W[n];
+    i2.ldb = ln;
+    i2.b_kc = true;
+    i2.C = dZ;
+    i2.ldc = rn;
+    i2.M = m;
+    i2.N = rn;
+    i2.K = ln;
+    i2.beta = T(1);
+    TTR_TRY(gemm(c, i2));
+    Gemm<T> j2;  // dW_n = Z_n^T dY_n
+    j2.A = xt[n];
+    j2.lda = rn;
+    j2.a_kc = false;
+    j2.B = dYs;
+    j2.ldb = ln;
+    j2.b_kc = false;
+    j2.C = dW[n];
+    j2.ldc = ln;
+    j2.M = rn;
+    j2.N = ln;
+    j2.K = m;
+    TTR_TRY(gemm(c, j2));
+    dX = dZ;
+  }
+  // ---- reverse W chain
+  int64_t zc_max = 1;
+  for (int n = 1; n <= N - 2; ++n) zc_max = std::max(zc_max, R[n] * dims[n] * L[n + 1]);
+  T *dZc = c.arena.take<T>((size_t)zc_max);
+  for (int n = 1; n <= N - 2; ++n) {
+    if (p.renorm && !c.dry) TTR_TRY(scale_dev<T>(dW[n], R[n] * L[n], fac + n, c.s));
+    const int64_t I = dims[n];
+    GemmX a;  // dZc (R_n x I L_{n+1}) = dW_n H(S_{n+1})
+    a.A = dW[n];
+    a.lda = L[n];
+    a.a_kc = true;
+    a.ta = p.store;
+    a.B = Sk[n];
+    a.ldb = I * L[n + 1];
+    a.b_kc = false;
+    a.tb = p.sk;
+    a.C = dZc;
+    a.ldc = I * L[n + 1];
+    a.tc = p.store;
+    a.M = R[n];
+    a.N = I * L[n + 1];
+    a.K = L[n];
+    a.math = p.wmath;
+    TTR_TRY(gemm(c, a));
+    Gemm<T> b;  // dV(Y_{n+1}) += dV(Zc) W_{n+1}^T
+    b.A = dZc;
+    b.lda = L[n + 1];
+    b.a_kc = true;
+    b.B = W[n + 1];
+    b.ldb = L[n + 1];
+    b.b_kc = true;
+    b.C = gin[n];
+    b.ldc = R[n + 1];
+    b.M = R[n] * I;
+    b.N = R[n + 1];
+    b.K = L[n + 1];
+    b.beta = T(1);
+    TTR_TRY(gemm(c, b));
+    Gemm<T> d;  // dW_{n+1} += V(Y_{n+1})^T dV(Zc)
+    d.A = Y[n];
+    d.lda = R[n + 1];
+    d.a_kc = false;
+    d.B = dZc;
+    d.ldb = L[n + 1];
+    d.b_kc = false;
+    d.C = dW[n + 1];
+    d.ldc = L[n + 1];
+    d.M = R[n + 1];
+    d.N = L[n + 1];
+    d.K = R[n] * I;
+    d.beta = T(1);
+    TTR_TRY(gemm(c, d));
+  }
+  if (p.renorm && !c.dry) TTR_TRY(scale_dev<T>(dW[N - 1], R[N - 1] * L[N - 1], fac + N - 1, c.s));
+  GemmX z;  // dH(Y_N) += dW_{N-1} H(S_N)
+  z.A = dW[N - 1];
+  z.lda = L[N - 1];
+  z.a_kc = true;
+  z.ta = p.store;
+  z.B = Sk[N - 1];
+  z.ldb = dims[N - 1];
+  z.b_kc = false;
+  z.tb = p.sk;
+  z.C = gin[N - 1];
+  z.ldc = dims[N - 1];
+  z.tc = p.store;
+  z.M = R[N - 1];
+  z.N = dims[N - 1];
+  z.K = L[N - 1];
+  z.beta = 1.0;
+  z.math = p.wmath;
+  return gemm(c, z);
 }
 
 // ---------------------------------------------------------------- TT-SVD
@@ -1048,6 +1390,86 @@ int tt_round_svd(int32_t N, const int64_t *dims, const int64_t *ranks, const voi
                               c.dry ? nullptr : out_ranks);
     return svd_exec<float>(c, P, (const float *const *)cores, eps0, (float *const *)out_cores,
                            c.dry ? nullptr : out_ranks);
+  });
+}
+
+static int backward_prec(int32_t prec, Prec &pc) {
+  TTR_TRY(prec_cfg(prec, pc));
+  if (prec == TT_PREC_MIXED_BF16)
+    return fail(TT_EUNSUPPORTED, "the adjoint supports TT_PREC_F64 and TT_PREC_F32");
+  return TT_OK;
+}
+
+int tt_round_rand_backward_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                     int64_t target_rank, int64_t oversample, int32_t prec,
+                                     size_t *bytes) {
+  Problem P;
+  TTR_TRY(make_problem(P, 1, N, dims, ranks, target_rank, oversample, nullptr));
+  Prec pc;
+  TTR_TRY(backward_prec(prec, pc));
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  if (P.truncate)
+    return fail(TT_EUNSUPPORTED, "the adjoint covers roundings without truncation");
+  if (N == 1) {
+    *bytes = 0;
+    return TT_OK;
+  }
+  return measure_workspace(
+      [&](Ctx &c) -> int {
+        std::vector<void *> Sk;
+        TTR_TRY(sketch_exec(c, P, pc, Sk));
+        if (pc.store == DType::F64) {
+          std::vector<const double *> Y(N, nullptr), go(N, nullptr);
+          std::vector<double *> gi(N, nullptr);
+          return backward_exec<double>(c, P, pc, Y.data(), (const void *const *)Sk.data(),
+                                       go.data(), gi.data());
+        }
+        std::vector<const float *> Y(N, nullptr), go(N, nullptr);
+        std::vector<float *> gi(N, nullptr);
+        return backward_exec<float>(c, P, pc, Y.data(), (const void *const *)Sk.data(), go.data(),
+                                    gi.data());
+      },
+      bytes);
+}
+
+int tt_round_rand_backward(int32_t N, const int64_t *dims, const int64_t *ranks,
+                           const void *const *cores, int32_t dtype, int64_t target_rank,
+                           int64_t oversample, uint64_t sketch_seed, int32_t prec,
+                           const void *const *grad_out, void *const *grad_in, void *workspace,
+                           size_t ws_bytes, void *stream) {
+  read_env();
+  Problem P;
+  TTR_TRY(make_problem(P, 1, N, dims, ranks, target_rank, oversample, nullptr));
+  Prec pc;
+  TTR_TRY(backward_prec(prec, pc));
+  TTR_TRY(check_dtype(dtype, pc));
+  if (P.truncate)
+    return fail(TT_EUNSUPPORTED, "the adjoint covers roundings without truncation");
+  TTR_TRY(check_ptrs(N, cores, "input cores"));
+  TTR_TRY(check_ptrs(N, grad_out, "output cotangents"));
+  TTR_TRY(check_ptrs(N, grad_in, "input gradients"));
+  hipStream_t st = (hipStream_t)stream;
+  if (N == 1) {
+    const int64_t cnt = dims[0];
+    if (pc.store == DType::F64)
+      return copy2d<double>((double *)grad_in[0], 1, (const double *)grad_out[0], 1, cnt, 1, 1.0,
+                            0.0, st);
+    return copy2d<float>((float *)grad_in[0], 1, (const float *)grad_out[0], 1, cnt, 1, 1.0, 0.0,
+                         st);
+  }
+  return run_with_workspace(workspace, ws_bytes, st, [&](Ctx &c) -> int {
+    std::vector<void *> Skw;
+    TTR_TRY(sketch_exec(c, P, pc, Skw));
+    if (!c.dry)
+      TTR_TRY(sketch_generate(sketch_seed, N, P.dims.data(), P.ell.data(), (int)pc.sk,
+                              (void *const *)Skw.data(), c.s));
+    if (pc.store == DType::F64)
+      return backward_exec<double>(c, P, pc, (const double *const *)cores,
+                                   (const void *const *)Skw.data(),
+                                   (const double *const *)grad_out, (double *const *)grad_in);
+    return backward_exec<float>(c, P, pc, (const float *const *)cores,
+                                (const void *const *)Skw.data(), (const float *const *)grad_out,
+                                (float *const *)grad_in);
   });
 }
 

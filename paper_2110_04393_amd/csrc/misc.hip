@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void copy2d_kernel(T *dst, int64_t ldd, const 
 constexpr int kScaleThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kScaleThreads) void scale_pow2_kernel(T *x, int64_t count) {
+__global__ __launch_bounds__(kScaleThreads) void scale_pow2_kernel(T *x, int64_t count,
+                                                                   double *fout) {
   __shared__ float s_max[kScaleThreads / 64];
   const int tid = threadIdx.x;
   float m = 0.f;
@@ -40,11 +41,35 @@ __global__ __launch_bounds__(kScaleThreads) void scale_pow2_kernel(T *x, int64_t
   __syncthreads();
   m = 0.f;
   for (int w = 0; w < kScaleThreads / 64; ++w) m = fmaxf(m, s_max[w]);
-  if (!(m > 0.f) || !isfinite(m)) return;
+  if (!(m > 0.f) || !isfinite(m)) {
+    if (fout && tid == 0) *fout = 1.0;
+    return;
+  }
   int ex = 0;
   frexpf(m, &ex);  // m = f 2^ex, f in [0.5, 1): floor(log2 m) = ex - 1
   const T f = (T)ldexp(1.0, 1 - ex);
   for (int64_t e = tid; e < count; e += kScaleThreads) x[e] *= f;
+  if (fout && tid == 0) *fout = (double)f;
+}
+
+// x *= *f (a factor that lives on the device)
+template <typename T>
+__global__ __launch_bounds__(256) void scale_dev_kernel(T *x, int64_t count, const double *f) {
+  const T v = (T)*f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] *= v;
+}
+
+// C = tril(M) + tril(M, -1)^T for the k x k row-major M (symmetric copy of
+// the lower triangle), scaled by alpha
+template <typename T>
+__global__ __launch_bounds__(256) void copyltu_kernel(T *C, const T *M, int64_t k, double alpha) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < k * k;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / k, j = e - i * k;
+    C[e] = (T)(alpha * (double)((i >= j) ? M[e] : M[j * k + i]));
+  }
 }
 
 __global__ __launch_bounds__(256) void to_bf16_kernel(__bf16 *dst, const float *src,
@@ -164,14 +189,36 @@ int select_rank(const double *lam, int n, const double *norm, double eps0, int N
 }
 
 template <typename T>
-int scale_pow2(T *x, int64_t count, hipStream_t s) {
+int scale_pow2(T *x, int64_t count, hipStream_t s, double *fout) {
   if (count <= 0) return TT_OK;
-  hipLaunchKernelGGL((scale_pow2_kernel<T>), dim3(1), dim3(kScaleThreads), 0, s, x, count);
+  hipLaunchKernelGGL((scale_pow2_kernel<T>), dim3(1), dim3(kScaleThreads), 0, s, x, count, fout);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
-template int scale_pow2<float>(float *, int64_t, hipStream_t);
-template int scale_pow2<double>(double *, int64_t, hipStream_t);
+template int scale_pow2<float>(float *, int64_t, hipStream_t, double *);
+template int scale_pow2<double>(double *, int64_t, hipStream_t, double *);
+
+template <typename T>
+int scale_dev(T *x, int64_t count, const double *f, hipStream_t s) {
+  if (count <= 0) return TT_OK;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL((scale_dev_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, x, count, f);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int scale_dev<float>(float *, int64_t, const double *, hipStream_t);
+template int scale_dev<double>(double *, int64_t, const double *, hipStream_t);
+
+template <typename T>
+int copyltu(T *C, const T *M, int64_t k, double alpha, hipStream_t s) {
+  if (k <= 0) return TT_OK;
+  const int64_t blocks = std::min<int64_t>((k * k + 255) / 256, 4096);
+  hipLaunchKernelGGL((copyltu_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, C, M, k, alpha);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int copyltu<float>(float *, const float *, int64_t, double, hipStream_t);
+template int copyltu<double>(double *, const double *, int64_t, double, hipStream_t);
 
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s) {
   if (count <= 0) return TT_OK;

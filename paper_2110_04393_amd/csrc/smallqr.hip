@@ -418,6 +418,11 @@ static int chol_inv(const double *G, const double *part, int nsplit, double *Rin
   return fail(TT_EUNSUPPORTED, "Cholesky of a Gram matrix wider than 96");
 }
 
+int chol_inverse(const double *G, int64_t n, double *Rinv, float *Rinv_f, int *flag,
+                 hipStream_t s) {
+  return chol_inv(G, nullptr, 0, Rinv, Rinv_f, (int)n, flag, 0, s);
+}
+
 constexpr int64_t kHhLdsElems = 10000;  // 2 * m * n doubles must fit in LDS
 
 template <typename T>

@@ -190,6 +190,11 @@ size_t qr_partial_elems(int64_t m, int64_t n);
 template <typename T>
 int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s);
 void qr_set_mode(int mode);  // 0 auto, 1 force householder, 2 force cholqr2
+// R^{-1} of the upper Cholesky factor of the n x n FP64 matrix G (n <= 96),
+// row-major; Rinv_f (optional) receives it rounded to FP32; *flag = 1 on a
+// pivot breakdown
+int chol_inverse(const double *G, int64_t n, double *Rinv, float *Rinv_f, int *flag,
+                 hipStream_t s);
 
 // ---------------------------------------------------------------- eigen
 // Symmetric eigendecomposition of an n x n matrix (n <= TT_MAX_SKETCH_RANK)
@@ -221,9 +226,16 @@ template <typename T>
 int copy2d(T *dst, int64_t ldd, const T *src, int64_t lds, int64_t rows, int64_t cols,
            double alpha, double beta, hipStream_t s);
 
-// x <- x * 2^-floor(log2 max|x|) (exact; one workgroup, count small)
+// x <- x * 2^-floor(log2 max|x|) (exact; one workgroup, count small); the
+// factor applied (1 if none) goes to *fout when fout is not null
 template <typename T>
-int scale_pow2(T *x, int64_t count, hipStream_t s);
+int scale_pow2(T *x, int64_t count, hipStream_t s, double *fout = nullptr);
+// x *= *f, f on the device
+template <typename T>
+int scale_dev(T *x, int64_t count, const double *f, hipStream_t s);
+// C = alpha (tril(M) + tril(M, -1)^T), k x k row-major
+template <typename T>
+int copyltu(T *C, const T *M, int64_t k, double alpha, hipStream_t s);
 
 // dst = RNE_bf16(src)
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);

@@ -427,3 +427,57 @@ def test_rto_invariant_under_power_of_two_scaling_of_W():
     B = O.rto_sweep(X, Ws)
     for a, b in zip(A, B):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- adjoint oracle
+
+def _adjoint_case(seed, N=5, I=4, R=5, ell=3):
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    Y = G.random_tt(seed, dims, ranks, scale="nominal")
+    ellv, _ = O.plan_ranks(dims, ranks, ell, 0)
+    S = O.make_sketch(seed + 1, dims, ellv)
+    return Y, S, ell
+
+
+def test_adjoint_oracle_forward_matches_numpy_oracle():
+    torch = pytest.importorskip("torch")
+    from oracle.tt_adjoint import rto_torch
+    for seed in (3, 4):
+        Y, S, ell = _adjoint_case(seed)
+        ref = O.round_rand(Y, ell, 0, sketch=S, truncate=False)
+        out = rto_torch([torch.tensor(c) for c in Y], [torch.tensor(c) for c in S])
+        for a, b in zip(out, ref):
+            np.testing.assert_allclose(a.numpy(), b, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_adjoint_oracle_matches_central_differences(seed):
+    # directional derivative of sum_n <G_n, out_n(Y)> from the numpy forward
+    pytest.importorskip("torch")
+    from oracle.tt_adjoint import rto_vjp
+    Y, S, ell = _adjoint_case(seed, N=4, I=5, R=6, ell=3)
+    rng = np.random.default_rng(seed + 10)
+    ref = O.round_rand(Y, ell, 0, sketch=S, truncate=False)
+    Gc = [rng.standard_normal(c.shape) for c in ref]
+    D = [rng.standard_normal(c.shape) for c in Y]
+
+    def f(t):
+        out = O.round_rand([y + t * d for y, d in zip(Y, D)], ell, 0, sketch=S, truncate=False)
+        return sum(float(np.sum(g * o)) for g, o in zip(Gc, out))
+
+    h = 1e-6
+    fd = (f(h) - f(-h)) / (2 * h)
+    grads = rto_vjp(Y, S, Gc)
+    an = sum(float(np.sum(g * d)) for g, d in zip(grads, D))
+    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_tt_inner_torch_matches_full_tensor():
+    torch = pytest.importorskip("torch")
+    from oracle.tt_adjoint import loss_round_minus_target, tt_inner_torch
+    A = tiny_tt(7)
+    B = tiny_tt(8)
+    ip = float(tt_inner_torch([torch.tensor(c) for c in A], [torch.tensor(c) for c in B]))
+    assert abs(ip - float(np.sum(O.full(A) * O.full(B)))) <= 1e-12 * max(1.0, abs(ip))
+    ls = float(loss_round_minus_target([torch.tensor(c) for c in A], [torch.tensor(c) for c in B]))
+    assert abs(ls - float(np.sum((O.full(A) - O.full(B)) ** 2))) <= 1e-10 * max(1.0, ls)
