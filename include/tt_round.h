@@ -278,6 +278,52 @@ TT_API int tt_round_svd(int32_t N, const int64_t *dims, const int64_t *ranks,
                         void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Batched randomized rounding: B independent TTs (any orders >= 2, mode
+ * sizes and ranks; sketch ranks <= 76) rounded by Algorithm 5 with the same
+ * truncation as tt_round_rand, in lock step: every step of the method is
+ * one grouped launch over all TTs still active at that step.  Shapes and
+ * pointers are fixed at creation; tt_batch_run then replays the sequence
+ * (one hipGraph launch with TT_BATCH_GRAPH).  With TT_BATCH_AUTOTUNE the
+ * tile shape of every grouped GEMM is chosen at creation by timing each
+ * variant on the batch (this never changes results).  The thin QR is always
+ * CholeskyQR2 with the device-flagged Householder fallback.
+ *   orders[B]                 N_i
+ *   dims[sum N_i]             mode sizes, TT after TT
+ *   ranks[sum (N_i + 1)]      ranks, TT after TT
+ *   target_ranks[B], oversample[B], seeds[B]   per TT, as in tt_round_rand
+ *   cores[sum N_i]            device input cores, TT after TT (read at every run)
+ *   out_cores[sum N_i]        device output cores at tt_round_rand_plan's
+ *                             out ranks, TT after TT (written at every run)
+ *   workspace, ws_bytes       >= tt_batch_workspace(...); the first part
+ *                             holds the launch tables (uploaded at creation
+ *                             with a synchronous copy) and must not be
+ *                             modified while the batch exists
+ *   flags                     TT_BATCH_GRAPH | TT_BATCH_AUTOTUNE
+ *   stream                    creation runs (autotuning, warm-up) go there
+ * tt_batch_create waits for the device (uploads, tuning, capture); run is
+ * asynchronous.  The handle owns host memory and, with TT_BATCH_GRAPH, a
+ * graph and a capture stream; tt_batch_destroy frees them.
+ */
+typedef struct tt_batch_s *tt_batch;
+#define TT_BATCH_GRAPH 1
+#define TT_BATCH_AUTOTUNE 2
+TT_API int tt_batch_workspace(int32_t B, const int32_t *orders, const int64_t *dims,
+                              const int64_t *ranks, const int64_t *target_ranks,
+                              const int64_t *oversample, int32_t prec, size_t *bytes);
+TT_API int tt_batch_create(int32_t B, const int32_t *orders, const int64_t *dims,
+                           const int64_t *ranks, const int64_t *target_ranks,
+                           const int64_t *oversample, const uint64_t *seeds, int32_t dtype,
+                           int32_t prec, const void *const *cores, void *const *out_cores,
+                           void *workspace, size_t ws_bytes, int32_t flags, void *stream,
+                           tt_batch *batch);
+TT_API int tt_batch_run(tt_batch batch, void *stream);
+/* launches per run, grouped GEMMs, and how many of them use each of the four
+ * tile variants (16x64, 64x16, 32x32, 64x64 outputs per workgroup) */
+TT_API int tt_batch_info(tt_batch batch, int32_t *launches, int32_t *gemm_groups,
+                         int32_t *variant_count);
+TT_API int tt_batch_destroy(tt_batch batch);
+
+/*
  * Kernel timing (instrumentation, off by default).  tt_timing_start arms a
  * recorder for one call site of the rounding path: every later launch from
  * that site is bracketed by a pair of HIP events recorded on the launch

@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "tt_round.h")
 TT_OK, TT_EINVAL, TT_ENOMEM, TT_EHIP, TT_ENUMERIC, TT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 TT_PREC_F64, TT_PREC_F32, TT_PREC_MIXED_BF16 = 0, 1, 2
+TT_BATCH_GRAPH, TT_BATCH_AUTOTUNE = 1, 2
 
 _STATUS_NAMES = {0: "TT_OK", -1: "TT_EINVAL", -2: "TT_ENOMEM", -3: "TT_EHIP",
                  -4: "TT_ENUMERIC", -5: "TT_EUNSUPPORTED"}
@@ -59,6 +60,15 @@ _SIGS = {
                                                         P_size]),
     "tt_round_rand_backward": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64, c_u64,
                                               c_i32, P_vp, P_vp, vp, c_size, vp]),
+    "tt_batch_workspace": (ctypes.c_int, [c_i32, ctypes.POINTER(c_i32), P_i64, P_i64, P_i64, P_i64,
+                                          c_i32, P_size]),
+    "tt_batch_create": (ctypes.c_int, [c_i32, ctypes.POINTER(c_i32), P_i64, P_i64, P_i64, P_i64,
+                                       ctypes.POINTER(c_u64), c_i32, c_i32, P_vp, P_vp, vp, c_size,
+                                       c_i32, vp, P_vp]),
+    "tt_batch_run": (ctypes.c_int, [vp, vp]),
+    "tt_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                                     ctypes.POINTER(c_i32)]),
+    "tt_batch_destroy": (ctypes.c_int, [vp]),
     "tt_timing_start": (ctypes.c_int, [c_i32, c_i32]),
     "tt_timing_stop": (ctypes.c_int, [P_dbl, ctypes.POINTER(c_i32)]),
     "tt_sum_round": (ctypes.c_int, [c_i32, c_i32, P_i64, P_i64, P_vp, P_dbl, c_i32, c_i64, c_i64,

@@ -271,3 +271,80 @@ def sum_round(summands, coeffs, target_rank: int, oversample: int = 0, seed: int
     p = RoundPlan(dims, None, target_rank, oversample, prec, summands[0][0].device,
                   summand_ranks=[_shape_of(t)[1] for t in summands])
     return [c.clone() for c in p.run_sum(summands, coeffs, seed=seed, stream=stream)]
+
+
+class BatchPlan:
+    """Many independent roundings in lock step (tt_batch_*): one grouped
+    launch per step of the method, optionally one hipGraph for the whole
+    batch and autotuned GEMM tiles.  Inputs are the device cores given at
+    construction (read at every run); outputs are preallocated."""
+
+    def __init__(self, tts, targets, oversamples, seeds, prec="f32", graph=True, autotune=True,
+                 stream=None):
+        import ctypes
+        if prec not in _PREC:
+            raise ValueError(f"unknown prec {prec!r}")
+        B = len(tts)
+        if not (len(targets) == len(oversamples) == len(seeds) == B):
+            raise ValueError("targets, oversamples and seeds need one entry per TT")
+        self.tts = [list(t) for t in tts]
+        for t in self.tts:
+            _check_cores(t)
+            if t[0].dtype != STORAGE[prec]:
+                raise ValueError(f"prec {prec!r} needs {STORAGE[prec]} cores")
+        dev = self.tts[0][0].device
+        orders, dims, ranks = [], [], []
+        self.out = []
+        for t, tr, ov in zip(self.tts, targets, oversamples):
+            d, r = _shape_of(t)
+            orders.append(len(d))
+            dims += d
+            ranks += r
+            _, outr = plan(d, r, tr, ov)
+            self.out.append([torch.empty((outr[n], d[n], outr[n + 1]), dtype=STORAGE[prec],
+                                         device=dev) for n in range(len(d))])
+        self._orders = (ctypes.c_int32 * B)(*orders)
+        self._dims = L.i64_array(dims)
+        self._ranks = L.i64_array(ranks)
+        self._targets = L.i64_array(targets)
+        self._over = L.i64_array(oversamples)
+        self._seeds = (ctypes.c_uint64 * B)(*[int(s) & ((1 << 64) - 1) for s in seeds])
+        b = ctypes.c_size_t(0)
+        L.check(L.lib().tt_batch_workspace(B, self._orders, self._dims, self._ranks, self._targets,
+                                           self._over, _PREC[prec], ctypes.byref(b)))
+        self.ws_bytes = int(b.value)
+        self.workspace = _workspace(self.ws_bytes, dev)
+        flags = (L.TT_BATCH_GRAPH if graph else 0) | (L.TT_BATCH_AUTOTUNE if autotune else 0)
+        self._cores = L.ptr_array([c.data_ptr() for t in self.tts for c in t])
+        self._outp = L.ptr_array([c.data_ptr() for t in self.out for c in t])
+        h = ctypes.c_void_p(0)
+        L.check(L.lib().tt_batch_create(B, self._orders, self._dims, self._ranks, self._targets,
+                                        self._over, self._seeds, _DTYPE[STORAGE[prec]],
+                                        _PREC[prec], self._cores, self._outp,
+                                        ctypes.c_void_p(self.workspace.data_ptr()),
+                                        self.workspace.numel(), flags, _stream_handle(stream),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        L.check(L.lib().tt_batch_run(self._h, _stream_handle(stream)))
+        return self.out
+
+    def info(self):
+        import ctypes
+        la, gg = ctypes.c_int32(0), ctypes.c_int32(0)
+        vc = (ctypes.c_int32 * 4)()
+        L.check(L.lib().tt_batch_info(self._h, ctypes.byref(la), ctypes.byref(gg), vc))
+        return {"launches_per_run": la.value, "grouped_gemms": gg.value,
+                "tile_variants": {"16x64": vc[0], "64x16": vc[1], "32x32": vc[2], "64x64": vc[3]}}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().tt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,8 +27,6 @@ int fail(int status, const std::string &msg) {
   return status;
 }
 
-namespace {
-
 // ---------------------------------------------------------------- validation
 
 int check_shape(int32_t N, const int64_t *dims, const int64_t *ranks, const char *what) {
@@ -64,19 +62,6 @@ void plan_ranks(int N, const int64_t *dims, const int64_t *R, int64_t target, in
   out.assign(N + 1, 1);
   for (int n = 1; n < N; ++n) out[n] = std::min(target, ell[n]);
 }
-
-// Arithmetic of one rounding.  F64: everything in FP64.  F32: FP32 storage
-// and MFMA, FP64 Gram matrices (thin QR and truncation) and Cholesky/eigen
-// solves.  MIXED_BF16: as F32, but the partial contractions (Algorithm 3) run
-// on the BF16 MFMA with FP32 accumulation against a BF16 sketch.  Non-FP64
-// modes renormalise each W_n by a power of two (exact; keeps the chain inside
-// the FP32 exponent range for long trains).
-struct Prec {
-  DType store = DType::F64;  // cores, W_n, sweep buffers, outputs
-  DType wmath = DType::F64;  // partial-contraction MFMA arithmetic
-  DType sk = DType::F64;     // sketch storage inside the rounding
-  bool renorm = false;
-};
 
 int prec_cfg(int32_t prec, Prec &p) {
   switch (prec) {
@@ -155,19 +140,6 @@ int gemm(Ctx &c, const Gemm<T> &g, int site = -1) {
   return gemm(c, g.x(), site);
 }
 
-// Problem description shared by single-TT and sum rounding.  A single TT is
-// a sum with s = 1.
-struct Problem {
-  int N = 0, s = 1;
-  std::vector<int64_t> dims;
-  std::vector<std::vector<int64_t>> R;  // per summand, N+1 ranks
-  std::vector<int64_t> Rsum;            // formal ranks
-  std::vector<int64_t> ell, out;
-  std::vector<double> coeffs;
-  bool truncate = false;
-  int64_t max_ell = 1;
-};
-
 int make_problem(Problem &P, int s, int N, const int64_t *dims, const int64_t *ranks,
                  int64_t target, int64_t over, const double *coeffs) {
   if (s < 1) return fail(TT_EINVAL, "need at least one summand");
@@ -198,6 +170,8 @@ int make_problem(Problem &P, int s, int N, const int64_t *dims, const int64_t *r
     return fail(TT_EUNSUPPORTED, "sketch rank above TT_MAX_SKETCH_RANK");
   return TT_OK;
 }
+
+namespace {
 
 // ---------------------------------------------------------------- W chain
 // Partial contractions of s TTs Y^(j) (cores Y[j*N + n], ranks R[j]) with one

@@ -43,7 +43,7 @@ __device__ inline void round_pair(int t, int k, int np, int &p, int &q) {
   q = max(a, b);
 }
 
-__global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const double *Gin, double *lam,
+__device__ __forceinline__ void jacobi_eig_kernel_body(const double *Gin, double *lam,
                                                                  double *Uout, int n,
                                                                  int *info, const int *gate) {
   if (gate && *gate == 0) return;
@@ -181,8 +181,14 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const double *G
   (void)offmax;
 }
 
+__global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const double *Gin, double *lam,
+                                                                 double *Uout, int n,
+                                                                 int *info, const int *gate) {
+  jacobi_eig_kernel_body(Gin, lam, Uout, n, info, gate);
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void trunc_factors_kernel(const double *lam, const double *U,
+__device__ __forceinline__ void trunc_factors_kernel_body(const double *lam, const double *U,
                                                             int n, int k, T *P, T *S,
                                                             double *tail, const int *gate) {
   if (gate && *gate == 0) return;
@@ -201,6 +207,26 @@ __global__ __launch_bounds__(256) void trunc_factors_kernel(const double *lam, c
     for (int j = k; j < n; ++j) t += fmax(lam[j], 0.0);
     *tail = t;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trunc_factors_kernel(const double *lam, const double *U,
+                                                            int n, int k, T *P, T *S,
+                                                            double *tail, const int *gate) {
+  trunc_factors_kernel_body<T>(lam, U, n, k, P, S, tail, gate);
+}
+
+// grouped forms, gated per entry on the eigen-solver flag
+__global__ __launch_bounds__(kEigThreads) void jacobi_group_kernel(const EigGroupDesc *tab) {
+  const EigGroupDesc &e = tab[blockIdx.x];
+  jacobi_eig_kernel_body(e.G, e.lam, e.U, e.n, nullptr, e.flag);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trunc_factors_group_kernel(const EigGroupDesc *tab) {
+  const EigGroupDesc &e = tab[blockIdx.x];
+  trunc_factors_kernel_body<T>(e.lam, e.U, e.n, e.k, static_cast<T *>(e.P),
+                               static_cast<T *>(e.S), e.tail, e.flag);
 }
 
 }  // namespace
@@ -235,5 +261,28 @@ template int trunc_factors<double>(const double *, const double *, int64_t, int6
                                    double *, double *, hipStream_t, const int *);
 template int trunc_factors<float>(const double *, const double *, int64_t, int64_t, float *,
                                   float *, double *, hipStream_t, const int *);
+
+int jacobi_group_run(const EigGroupDesc *d_tab, int count, int nmax, hipStream_t s) {
+  const int np = (nmax + 1) & ~1;
+  const size_t lds = 2 * sizeof(double) * (size_t)np * (size_t)(np + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)jacobi_group_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(jacobi_group_kernel, dim3(count), dim3(kEigThreads), lds, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+template <typename T>
+int trunc_factors_group_run(const EigGroupDesc *d_tab, int count, hipStream_t s) {
+  hipLaunchKernelGGL((trunc_factors_group_kernel<T>), dim3(count), dim3(256), 0, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int trunc_factors_group_run<double>(const EigGroupDesc *, int, hipStream_t);
+template int trunc_factors_group_run<float>(const EigGroupDesc *, int, hipStream_t);
 
 }  // namespace ttr

@@ -98,7 +98,7 @@ struct TileMap {
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
+__device__ __forceinline__ void gemm_body(const GemmX &g, const TileMap &tm, int64_t wg) {
   static_assert(WM * WN == 4, "4 wavefronts per workgroup");
   typedef typename MT::acc_t acc_t;
   typedef typename MT::in_t in_t;
@@ -108,7 +108,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int wm = wave % WM, wn = wave / WM;
-  int64_t wg = blockIdx.x;
   const int64_t tn_wg = wg % tm.tiles_n;
   wg /= tm.tiles_n;
   const int64_t tm_wg = wg % tm.tiles_m;
@@ -201,6 +200,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
     }
 }
 
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
+  gemm_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, blockIdx.x);
+}
+
+// Grouped form: one launch over several independent products (same types,
+// layouts and tile shape, any sizes).  Workgroup b belongs to the entry with
+// the largest wg_begin <= b.
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupEntry *tab, int count) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].wg_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmGroupEntry &e = tab[lo];
+  TileMap tm;
+  tm.tiles_m = e.tiles_m;
+  tm.tiles_n = e.tiles_n;
+  tm.kchunk = e.kchunk;
+  gemm_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(e.g, tm, b - e.wg_begin);
+}
+
 template <typename TP, typename TC>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmX g) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,33 +269,47 @@ int pick_variant(int64_t M, int64_t N) {
   return best;
 }
 
-template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC>
-void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s) {
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+void launch_one(const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
+                const GemmGroupEntry *tab, int count) {
   const dim3 gr((unsigned)grid), bl(256);
+  if (tab)
+    hipLaunchKernelGGL((gemm_group_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>), gr, bl, 0, s,
+                       tab, count);
+  else
+    hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>), gr, bl, 0, s, g,
+                       tm);
+}
+
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC>
+void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
+                   const GemmGroupEntry *tab, int count) {
   switch (v) {
     case 0:
-      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 1, 1, 1, 4>), gr, bl, 0, s, g, tm);
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 1, 4>(g, tm, grid, s, tab, count);
       break;
     case 1:
-      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 1>), gr, bl, 0, s, g, tm);
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 1>(g, tm, grid, s, tab, count);
       break;
     case 2:
-      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 2>), gr, bl, 0, s, g, tm);
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 2>(g, tm, grid, s, tab, count);
       break;
     default:
-      hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>), gr, bl, 0, s, g, tm);
+      launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
       break;
   }
 }
 
 template <class MT, typename TA, typename TB, typename TC>
-void launch_types(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s) {
+void launch_types(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
+                  const GemmGroupEntry *tab, int count) {
   if (g.a_kc) {
-    if (g.b_kc) launch_layout<MT, TA, TB, TC, true, true>(v, g, tm, grid, s);
-    else launch_layout<MT, TA, TB, TC, true, false>(v, g, tm, grid, s);
+    if (g.b_kc) launch_layout<MT, TA, TB, TC, true, true>(v, g, tm, grid, s, tab, count);
+    else launch_layout<MT, TA, TB, TC, true, false>(v, g, tm, grid, s, tab, count);
   } else {
-    if (g.b_kc) launch_layout<MT, TA, TB, TC, false, true>(v, g, tm, grid, s);
-    else launch_layout<MT, TA, TB, TC, false, false>(v, g, tm, grid, s);
+    if (g.b_kc) launch_layout<MT, TA, TB, TC, false, true>(v, g, tm, grid, s, tab, count);
+    else launch_layout<MT, TA, TB, TC, false, false>(v, g, tm, grid, s, tab, count);
   }
 }
 
@@ -278,23 +318,24 @@ constexpr int tkey(DType m, DType a, DType b, DType c) {
 }
 
 // the type combinations the rounding uses
-bool dispatch(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s) {
+bool dispatch(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
+              const GemmGroupEntry *tab = nullptr, int count = 0) {
   using D = DType;
   switch (tkey(g.math, g.ta, g.tb, g.tc)) {
     case tkey(D::F64, D::F64, D::F64, D::F64):
-      launch_types<MathF64, double, double, double>(v, g, tm, grid, s);
+      launch_types<MathF64, double, double, double>(v, g, tm, grid, s, tab, count);
       return true;
     case tkey(D::F64, D::F32, D::F32, D::F64):
-      launch_types<MathF64, float, float, double>(v, g, tm, grid, s);
+      launch_types<MathF64, float, float, double>(v, g, tm, grid, s, tab, count);
       return true;
     case tkey(D::F32, D::F32, D::F32, D::F32):
-      launch_types<MathF32, float, float, float>(v, g, tm, grid, s);
+      launch_types<MathF32, float, float, float>(v, g, tm, grid, s, tab, count);
       return true;
     case tkey(D::BF16, D::F32, D::F32, D::F32):
-      launch_types<MathBF16, float, float, float>(v, g, tm, grid, s);
+      launch_types<MathBF16, float, float, float>(v, g, tm, grid, s, tab, count);
       return true;
     case tkey(D::BF16, D::F32, D::BF16, D::F32):
-      launch_types<MathBF16, float, __bf16, float>(v, g, tm, grid, s);
+      launch_types<MathBF16, float, __bf16, float>(v, g, tm, grid, s, tab, count);
       return true;
     default:
       return false;
@@ -371,6 +412,42 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
     }
     TTR_HIP(hipGetLastError());
   }
+  return TT_OK;
+}
+
+int gemm_variant_count() { return 4; }
+
+void gemm_variant_tile(int v, int64_t *bm, int64_t *bn) {
+  *bm = 16 * kVariants[v].tm * kVariants[v].wm;
+  *bn = 16 * kVariants[v].tn * kVariants[v].wn;
+}
+
+int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e) {
+  if (g.M <= 0 || g.N <= 0) return fail(TT_EINVAL, "grouped gemm with an empty product");
+  if (g.K <= 0) return fail(TT_EINVAL, "grouped gemm with K <= 0");
+  if (g.batch > 1) return fail(TT_EINVAL, "grouped gemm entries are single products");
+  int64_t bm, bn;
+  gemm_variant_tile(v, &bm, &bn);
+  e->g = g;
+  e->g.splits = 1;
+  e->g.partial = nullptr;
+  e->tiles_m = (g.M + bm - 1) / bm;
+  e->tiles_n = (g.N + bn - 1) / bn;
+  const int chunk = gemm_chunk(g.math);
+  e->kchunk = (g.K + chunk - 1) / chunk * chunk;
+  e->wg_begin = wg_begin;
+  return TT_OK;
+}
+
+int64_t gemm_group_wgs(const GemmGroupEntry &e) { return e.tiles_m * e.tiles_n; }
+
+int gemm_group_run(const GemmX &rep, int v, const GemmGroupEntry *d_tab, int count,
+                   int64_t total_wgs, hipStream_t s) {
+  if (count <= 0 || total_wgs <= 0) return TT_OK;
+  TileMap tm{};
+  if (!dispatch(v, rep, tm, total_wgs, s, d_tab, count))
+    return fail(TT_EINVAL, "internal: gemm type combination");
+  TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 

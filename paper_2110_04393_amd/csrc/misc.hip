@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void copy2d_kernel(T *dst, int64_t ldd, const 
 constexpr int kScaleThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kScaleThreads) void scale_pow2_kernel(T *x, int64_t count,
+__device__ __forceinline__ void scale_pow2_kernel_body(T *x, int64_t count,
                                                                    double *fout) {
   __shared__ float s_max[kScaleThreads / 64];
   const int tid = threadIdx.x;
@@ -50,6 +50,12 @@ __global__ __launch_bounds__(kScaleThreads) void scale_pow2_kernel(T *x, int64_t
   const T f = (T)ldexp(1.0, 1 - ex);
   for (int64_t e = tid; e < count; e += kScaleThreads) x[e] *= f;
   if (fout && tid == 0) *fout = (double)f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScaleThreads) void scale_pow2_kernel(T *x, int64_t count,
+                                                                   double *fout) {
+  scale_pow2_kernel_body<T>(x, count, fout);
 }
 
 // x *= *f (a factor that lives on the device)
@@ -144,6 +150,12 @@ __global__ void select_rank_kernel(const double *lam, int n, const double *norm,
   }
   *k_out = k;
   *tail_out = tail;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScaleThreads) void scale_pow2_group_kernel(const ScaleGroupDesc *tab) {
+  const ScaleGroupDesc &e = tab[blockIdx.x];
+  scale_pow2_kernel_body<T>(static_cast<T *>(e.x), e.count, e.fout);
 }
 
 }  // namespace
@@ -244,5 +256,15 @@ template int copy2d<double>(double *, int64_t, const double *, int64_t, int64_t,
                             double, hipStream_t);
 template int copy2d<float>(float *, int64_t, const float *, int64_t, int64_t, int64_t, double,
                            double, hipStream_t);
+
+template <typename T>
+int scale_pow2_group(const ScaleGroupDesc *d_tab, int count, hipStream_t s) {
+  if (count <= 0) return TT_OK;
+  hipLaunchKernelGGL((scale_pow2_group_kernel<T>), dim3(count), dim3(kScaleThreads), 0, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int scale_pow2_group<double>(const ScaleGroupDesc *, int, hipStream_t);
+template int scale_pow2_group<float>(const ScaleGroupDesc *, int, hipStream_t);
 
 }  // namespace ttr

@@ -55,7 +55,7 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G, const double *part,
+__device__ __forceinline__ void chol_inv_kernel_body(const double *G, const double *part,
                                                                 int nsplit, double *Rinv,
                                                                 float *Rinv_f, int n, int *flag,
                                                                 int or_flag) {
@@ -272,6 +272,14 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G,
   }
 }
 
+template <int NMAX>
+__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G, const double *part,
+                                                                int nsplit, double *Rinv,
+                                                                float *Rinv_f, int n, int *flag,
+                                                                int or_flag) {
+  chol_inv_kernel_body<NMAX>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag);
+}
+
 // One workgroup Householder QR of the m x n row-major Y into Q (m x n), with
 // `work` (m x n) as global scratch and `rdiag` (n) / `tau` (n) scratch.  Runs
 // only if always != 0 or *flag != 0.  With use_lds the panel and Q live in
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G,
 constexpr int kHhThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kHhThreads) void householder_kernel(const T *Y, T *Q, T *work_g,
+__device__ __forceinline__ void householder_kernel_body(const T *Y, T *Q, T *work_g,
                                                                  double *rdiag, double *tau,
                                                                  int64_t m, int n,
                                                                  const int *flag, int always,
@@ -381,6 +389,29 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T *Y, T *
     const T v = (rdiag[c] < 0.0) ? -Qw[e] : Qw[e];
     Q[e] = v;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kHhThreads) void householder_kernel(const T *Y, T *Q, T *work_g,
+                                                                 double *rdiag, double *tau,
+                                                                 int64_t m, int n,
+                                                                 const int *flag, int always,
+                                                                 int use_lds) {
+  householder_kernel_body<T>(Y, Q, work_g, rdiag, tau, m, n, flag, always, use_lds);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kCholThreads) void chol_group_kernel(const CholGroupDesc *tab) {
+  const CholGroupDesc &e = tab[blockIdx.x];
+  chol_inv_kernel_body<NMAX>(e.G, nullptr, 0, e.Rinv, e.Rinv_f, e.n, e.flag, e.or_flag);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kHhThreads) void householder_group_kernel(const HhGroupDesc *tab) {
+  const HhGroupDesc &e = tab[blockIdx.x];
+  householder_kernel_body<T>(static_cast<const T *>(e.Y), static_cast<T *>(e.Q),
+                             static_cast<T *>(e.work), e.rdiag, e.tau, e.m, e.n, e.flag, e.always,
+                             e.use_lds);
 }
 
 }  // namespace
@@ -504,5 +535,60 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
 template int qr_thin<double>(const double *, double *, int64_t, int64_t, QrScratch &,
                              hipStream_t);
 template int qr_thin<float>(const float *, float *, int64_t, int64_t, QrScratch &, hipStream_t);
+
+template <int NMAX>
+static int chol_group_launch(const CholGroupDesc *d_tab, int count, hipStream_t s) {
+  const size_t lds = sizeof(double) * NMAX * NMAX;
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)chol_group_kernel<NMAX>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((chol_group_kernel<NMAX>), dim3(count), dim3(kCholThreads), lds, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+int chol_group_run(const CholGroupDesc *d_tab, int count, int nmax, hipStream_t s) {
+  if (count <= 0) return TT_OK;
+  if (nmax <= 32) return chol_group_launch<32>(d_tab, count, s);
+  if (nmax <= 64) return chol_group_launch<64>(d_tab, count, s);
+  if (nmax <= 96) return chol_group_launch<96>(d_tab, count, s);
+  return fail(TT_EUNSUPPORTED, "Cholesky of a Gram matrix wider than 96");
+}
+
+size_t hh_group_desc(const void *Y, void *Q, int64_t m, int64_t n, QrScratch &ws, int always,
+                     size_t elem, HhGroupDesc *d) {
+  const bool lds = (m * n <= kHhLdsElems);
+  d->Y = Y;
+  d->Q = Q;
+  d->work = ws.q1;
+  d->rdiag = ws.rinv;
+  d->tau = ws.rinv + n;
+  d->m = m;
+  d->n = (int)n;
+  d->flag = ws.flag;
+  d->always = always;
+  d->use_lds = lds ? 1 : 0;
+  return lds ? 2 * elem * (size_t)(m * n) : 0;
+}
+
+template <typename T>
+int householder_group_run(const HhGroupDesc *d_tab, int count, size_t lds_bytes, hipStream_t s) {
+  if (count <= 0) return TT_OK;
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)householder_group_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((householder_group_kernel<T>), dim3(count), dim3(kHhThreads), lds_bytes, s,
+                     d_tab);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int householder_group_run<double>(const HhGroupDesc *, int, size_t, hipStream_t);
+template int householder_group_run<float>(const HhGroupDesc *, int, size_t, hipStream_t);
 
 }  // namespace ttr

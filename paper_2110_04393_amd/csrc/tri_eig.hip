@@ -183,7 +183,7 @@ __device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const dou
 // taus[j]) to global scratch.  Only the lower triangle of A22 is updated.
 constexpr int kTrThreads = 256;
 
-__global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gin, int n,
+__device__ __forceinline__ void tri_reduce_kernel_body(const double *Gin, int n,
                                                                 double *d_out, double *e_out,
                                                                 double *sc_out, double *Vr,
                                                                 double *taus, int *flag) {
@@ -333,6 +333,13 @@ __global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gi
   }
 }
 
+__global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gin, int n,
+                                                                double *d_out, double *e_out,
+                                                                double *sc_out, double *Vr,
+                                                                double *taus, int *flag) {
+  tri_reduce_kernel_body(Gin, n, d_out, e_out, sc_out, Vr, taus, flag);
+}
+
 // ---------------------------------------------------------------- kernel 2
 // One wavefront per wanted eigenvalue w (descending, w < kw).  T lives in
 // registers (d, e fully unrolled up to kTeNMax), 64-point multisection with
@@ -341,14 +348,14 @@ __global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gi
 // same recurrence on the reversed matrix, i.e. the bottom-up UDU^T), then the
 // Householder reflectors of kernel 1 applied backwards give u = Q z, written to
 // column w of U (n x k) unnormalised by sc.
-__global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const double *e_in, int n,
+__device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const double *e_in, int n,
                                                      int k, int kw, const double *Vr,
                                                      const double *taus, double *lam_out,
-                                                     double *Uz, const int *flag) {
+                                                     double *Uz, const int *flag, int w_block) {
   if (*flag) return;
   __shared__ double s_L[kTeNMax + 1], s_U[kTeNMax + 1], s_z[kTeNMax];
   const int lane = threadIdx.x;
-  const int w = blockIdx.x;
+  const int w = w_block;
   // the upper half-wave holds T reversed (same eigenvalues and Sturm counts;
   // its top-down factorisation is the bottom-up one of T)
   const bool rev = lane >= 32;
@@ -467,12 +474,19 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
   if (lane + 64 < n) Uz[(lane + 64) * k + w] = z1;
 }
 
+__global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const double *e_in, int n,
+                                                     int k, int kw, const double *Vr,
+                                                     const double *taus, double *lam_out,
+                                                     double *Uz, const int *flag) {
+  tri_vec_kernel_body(d_in, e_in, n, k, kw, Vr, taus, lam_out, Uz, flag, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- kernel 3
 // One workgroup: gap check, orthogonality check and one Newton-Schulz step on
 // U (n x k, from kernel 2), outputs (unscaled eigenvalues, U, truncation
 // factors, tail).
 template <typename T>
-__global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
+__device__ __forceinline__ void tri_finish_kernel_body(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
     int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag) {
   if (*flag) return;
@@ -541,6 +555,31 @@ __global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
+    const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag) {
+  tri_finish_kernel_body<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, flag);
+}
+
+__global__ __launch_bounds__(kTrThreads) void tri_reduce_group_kernel(const EigGroupDesc *tab) {
+  const EigGroupDesc &e = tab[blockIdx.x];
+  tri_reduce_kernel_body(e.G, e.n, e.d, e.e, e.sc, e.Vr, e.taus, e.flag);
+}
+
+__global__ __launch_bounds__(64) void tri_vec_group_kernel(const EigGroupDesc *tab) {
+  const EigGroupDesc &e = tab[blockIdx.y];
+  if ((int)blockIdx.x >= e.kw) return;
+  tri_vec_kernel_body(e.d, e.e, e.n, e.k, e.kw, e.Vr, e.taus, e.lamw, e.Uz, e.flag, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTeThreads) void tri_finish_group_kernel(const EigGroupDesc *tab) {
+  const EigGroupDesc &e = tab[blockIdx.x];
+  tri_finish_kernel_body<T>(e.G, e.lamw, e.Uz, e.sc, e.n, e.k, e.kw, e.lam, e.U,
+                            static_cast<T *>(e.P), static_cast<T *>(e.S), e.tail, e.flag);
+}
+
 }  // namespace
 
 template <typename T>
@@ -587,5 +626,59 @@ template int eig_trunc<double>(const double *, int64_t, int64_t, double *, doubl
                                double *, double *, int *, double *, hipStream_t);
 template int eig_trunc<float>(const double *, int64_t, int64_t, double *, double *, float *,
                               float *, double *, int *, double *, hipStream_t);
+
+bool eig_group_desc(const double *G, int64_t n, int64_t k, double *lam, double *U, void *P,
+                    void *S, double *tail, int *flag, double *scratch, EigGroupDesc *d) {
+  if (n > kTeNMax) return false;
+  d->G = G;
+  d->n = (int)n;
+  d->k = (int)k;
+  d->kw = (int)std::min<int64_t>(k + 1, n);
+  d->d = scratch;
+  d->e = d->d + n;
+  d->sc = d->e + n;
+  d->Vr = d->sc + 1;
+  d->taus = d->Vr + n * n;
+  d->lamw = d->taus + n;
+  d->Uz = d->lamw + n + 1;
+  d->lam = lam;
+  d->U = U;
+  d->P = P;
+  d->S = S;
+  d->tail = tail;
+  d->flag = flag;
+  return true;
+}
+
+int jacobi_group_run(const EigGroupDesc *d_tab, int count, int nmax, hipStream_t s);
+template <typename T>
+int trunc_factors_group_run(const EigGroupDesc *d_tab, int count, hipStream_t s);
+
+template <typename T>
+int eig_trunc_group(const EigGroupDesc *d_tab, int count, int nmax, int kwmax, hipStream_t s) {
+  if (count <= 0) return TT_OK;
+  if (nmax > kTeNMax) return fail(TT_EUNSUPPORTED, "grouped eigenproblem larger than the limit");
+  const int ld = nmax | 1;
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)tri_reduce_group_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+    TTR_HIP(hipFuncSetAttribute((const void *)tri_finish_group_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(tri_reduce_group_kernel, dim3(count), dim3(kTrThreads),
+                     sizeof(double) * (size_t)nmax * ld, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(tri_vec_group_kernel, dim3(kwmax, count), dim3(64), 0, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((tri_finish_group_kernel<T>), dim3(count), dim3(kTeThreads),
+                     2 * sizeof(double) * (size_t)nmax * ld, s, d_tab);
+  TTR_HIP(hipGetLastError());
+  TTR_TRY(jacobi_group_run(d_tab, count, nmax, s));
+  return trunc_factors_group_run<T>(d_tab, count, s);
+}
+template int eig_trunc_group<double>(const EigGroupDesc *, int, int, int, hipStream_t);
+template int eig_trunc_group<float>(const EigGroupDesc *, int, int, int, hipStream_t);
 
 }  // namespace ttr

@@ -103,6 +103,22 @@ struct GemmX {
   bool defer_reduce = false;
 };
 
+// One entry of a grouped GEMM launch (device table): the product, its tile
+// grid for the launch's tile variant and its first workgroup.
+struct GemmGroupEntry {
+  GemmX g;
+  int64_t tiles_m = 0, tiles_n = 0, kchunk = 0;
+  int64_t wg_begin = 0;
+};
+int gemm_variant_count();
+void gemm_variant_tile(int v, int64_t *bm, int64_t *bn);
+int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e);
+int64_t gemm_group_wgs(const GemmGroupEntry &e);
+// launches count products (table in device memory) in one grid of total_wgs
+// workgroups; rep gives the common types and layouts
+int gemm_group_run(const GemmX &rep, int v, const GemmGroupEntry *d_tab, int count,
+                   int64_t total_wgs, hipStream_t s);
+
 int gemm_pick_splits(int64_t M, int64_t N, int64_t K);
 // number of split-K partials gemmx_run writes for g (1 = none, C written)
 int gemm_used_splits(const GemmX &g);
@@ -169,6 +185,44 @@ __device__ inline __bf16 bf16_rne(float f) {
   return __builtin_bit_cast(__bf16, (uint16_t)(u >> 16));
 }
 
+// ---------------------------------------------------------------- problems
+// Arithmetic of one rounding.  F64: everything in FP64.  F32: FP32 storage
+// and MFMA, FP64 Gram matrices (thin QR and truncation) and Cholesky/eigen
+// solves.  MIXED_BF16: as F32, but the partial contractions (Algorithm 3) run
+// on the BF16 MFMA with FP32 accumulation against a BF16 sketch.  Non-FP64
+// modes renormalise each W_n by a power of two (exact; keeps the chain inside
+// the FP32 exponent range for long trains).
+struct Prec {
+  DType store = DType::F64;  // cores, W_n, sweep buffers, outputs
+  DType wmath = DType::F64;  // partial-contraction MFMA arithmetic
+  DType sk = DType::F64;     // sketch storage inside the rounding
+  bool renorm = false;
+};
+
+// Problem description shared by single-TT and sum rounding.  A single TT is
+// a sum with s = 1.
+struct Problem {
+  int N = 0, s = 1;
+  std::vector<int64_t> dims;
+  std::vector<std::vector<int64_t>> R;  // per summand, N+1 ranks
+  std::vector<int64_t> Rsum;            // formal ranks
+  std::vector<int64_t> ell, out;
+  std::vector<double> coeffs;
+  bool truncate = false;
+  int64_t max_ell = 1;
+};
+
+int check_shape(int32_t N, const int64_t *dims, const int64_t *ranks, const char *what);
+int check_ptrs(int32_t N, const void *const *p, const char *what);
+void plan_ranks(int N, const int64_t *dims, const int64_t *R, int64_t target, int64_t over,
+                std::vector<int64_t> &ell, std::vector<int64_t> &out);
+int prec_cfg(int32_t prec, Prec &p);
+int check_dtype(int32_t dtype, const Prec &p);
+size_t dtype_bytes(DType t);
+void read_env();
+int make_problem(Problem &P, int s, int N, const int64_t *dims, const int64_t *ranks,
+                 int64_t target, int64_t over, const double *coeffs);
+
 // ---------------------------------------------------------------- sketch
 int sketch_generate(uint64_t seed, int N, const int64_t *dims, const int64_t *sranks,
                     int dtype, void *const *cores, hipStream_t s);
@@ -196,6 +250,36 @@ void qr_set_mode(int mode);  // 0 auto, 1 force householder, 2 force cholqr2
 int chol_inverse(const double *G, int64_t n, double *Rinv, float *Rinv_f, int *flag,
                  hipStream_t s);
 
+// Grouped forms of the one-workgroup kernels: one launch, one workgroup (or
+// a fixed set of them) per entry of a device table.
+struct CholGroupDesc {
+  const double *G;
+  double *Rinv;
+  float *Rinv_f;
+  int n;
+  int *flag;
+  int or_flag;
+};
+int chol_group_run(const CholGroupDesc *d_tab, int count, int nmax, hipStream_t s);
+
+struct HhGroupDesc {
+  const void *Y;
+  void *Q;
+  void *work;
+  double *rdiag, *tau;
+  int64_t m;
+  int n;
+  const int *flag;
+  int always;
+  int use_lds;
+};
+// fills the scratch assignment of one panel (m x n) exactly as qr_thin's
+// Householder path does; returns the LDS bytes it needs
+size_t hh_group_desc(const void *Y, void *Q, int64_t m, int64_t n, QrScratch &ws, int always,
+                     size_t elem, HhGroupDesc *d);
+template <typename T>
+int householder_group_run(const HhGroupDesc *d_tab, int count, size_t lds_bytes, hipStream_t s);
+
 // ---------------------------------------------------------------- eigen
 // Symmetric eigendecomposition of an n x n matrix (n <= TT_MAX_SKETCH_RANK)
 // by cyclic Jacobi: eigenvalues descending to `lam`, eigenvectors as the
@@ -220,6 +304,22 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
               double *tail, int *flag, double *scratch, hipStream_t s);
 size_t eig_trunc_scratch(int64_t n, int64_t k);
 
+struct EigGroupDesc {
+  const double *G;
+  int n, k, kw;
+  double *d, *e, *sc, *Vr, *taus, *lamw, *Uz;
+  double *lam, *U;
+  void *P, *S;
+  double *tail;
+  int *flag;
+};
+// descriptor of one eig_trunc problem (same scratch layout); false when the
+// problem is outside the grouped fast path (n > 76)
+bool eig_group_desc(const double *G, int64_t n, int64_t k, double *lam, double *U, void *P,
+                    void *S, double *tail, int *flag, double *scratch, EigGroupDesc *d);
+template <typename T>
+int eig_trunc_group(const EigGroupDesc *d_tab, int count, int nmax, int kwmax, hipStream_t s);
+
 // ---------------------------------------------------------------- misc
 // dst[r*ldd + c] = alpha * src[r*lds + c] + beta * dst[r*ldd + c]
 template <typename T>
@@ -230,6 +330,13 @@ int copy2d(T *dst, int64_t ldd, const T *src, int64_t lds, int64_t rows, int64_t
 // factor applied (1 if none) goes to *fout when fout is not null
 template <typename T>
 int scale_pow2(T *x, int64_t count, hipStream_t s, double *fout = nullptr);
+struct ScaleGroupDesc {
+  void *x;
+  int64_t count;
+  double *fout;
+};
+template <typename T>
+int scale_pow2_group(const ScaleGroupDesc *d_tab, int count, hipStream_t s);
 // x *= *f, f on the device
 template <typename T>
 int scale_dev(T *x, int64_t count, const double *f, hipStream_t s);

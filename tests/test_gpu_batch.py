@@ -1,0 +1,158 @@
+"""Batched rounding (tt_batch_*): every TT of the batch against the FP64 oracle
+on the same inputs and sketch values; replays and autotuning must not change
+the results.
+
+Tolerances: FP64 <= 1e-10 relative (as the single-TT path); FP32 <= 1e-4
+relative (FP32 storage and MFMA with FP64 Gram/Cholesky; the oracle gets
+the FP32-rounded inputs and sketch).  The full 64-TT workload is checked
+element-wise against the oracle on its smallest TTs (the oracle needs
+minutes for the largest), and on every TT through properties that hold at
+any size: finite cores, right-orthogonal cores 2..N, and agreement with the
+single-TT GPU path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tt_inputs as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(cores, dtype):
+    return [torch.from_numpy(np.ascontiguousarray(c)).to(dtype).cuda() for c in cores]
+
+
+def host(cores):
+    torch.cuda.synchronize()
+    return [c.detach().cpu().double().numpy() for c in cores]
+
+
+def right_orth_dev(cores):
+    d = 0.0
+    for c in cores[1:]:
+        Hn = c.reshape(c.shape[0], -1)
+        d = max(d, float(np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max()))
+    return d
+
+
+SMALL = [  # (N, I, R, target, oversample)
+    (3, 4, 3, 2, 1), (5, 6, 7, 3, 2), (7, 5, 9, 4, 3), (4, 12, 12, 6, 2), (6, 3, 5, 2, 2),
+    (2, 9, 6, 3, 3),
+]
+
+
+def small_batch(dtype_np):
+    tts, specs = [], []
+    for b, (N, I, R, t, o) in enumerate(SMALL):
+        dims, ranks = G.uniform_tt_shape(N, I, R)
+        X = G.random_tt(500 + b, dims, ranks, scale="nominal")
+        if dtype_np == np.float32:
+            X = [O.round_f32(c) for c in X]
+        tts.append(X)
+        specs.append(dict(target=t, oversample=o, seed=600 + b))
+    return tts, specs
+
+
+def oracle_item(X, spec, prec):
+    dims, ranks = O.dims_of(X), O.ranks_of(X)
+    ell, _ = O.plan_ranks(dims, ranks, spec["target"], spec["oversample"])
+    sk = O.make_sketch(spec["seed"], dims, ell)
+    if prec == "f32":
+        sk = [O.round_f32(c) for c in sk]
+    return O.round_rand(X, spec["target"], spec["oversample"], sketch=sk)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_small_batch_vs_oracle(gpu_lib, prec, graph):
+    say(f"small batch {prec} graph={graph}")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    tts, specs = small_batch(np.float64 if prec == "f64" else np.float32)
+    dtt = [dev(X, dt) for X in tts]
+    bp = gpu_lib.BatchPlan(dtt, [s["target"] for s in specs], [s["oversample"] for s in specs],
+                           [s["seed"] for s in specs], prec=prec, graph=graph, autotune=True)
+    outs = [host(o) for o in bp.run()]
+    tol = 1e-10 if prec == "f64" else 1e-4
+    for X, spec, out in zip(tts, specs, outs):
+        ref = oracle_item(X, spec, prec)
+        assert O.ranks_of(out) == O.ranks_of(ref)
+        err = O.rel_diff(out, ref)
+        assert err <= tol, (spec, err)
+    # a second run replays the same work: bitwise identical
+    outs2 = [host(o) for o in bp.run()]
+    for a, b in zip(outs, outs2):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    print(bp.info())
+    bp.close()
+
+
+def test_autotune_does_not_change_results(gpu_lib):
+    say("autotune invariance")
+    tts, specs = small_batch(np.float64)
+    dtt = [dev(X, torch.float64) for X in tts]
+    args = ([s["target"] for s in specs], [s["oversample"] for s in specs],
+            [s["seed"] for s in specs])
+    a = gpu_lib.BatchPlan(dtt, *args, prec="f64", graph=False, autotune=False)
+    oa = [host(o) for o in a.run()]
+    b = gpu_lib.BatchPlan(dtt, *args, prec="f64", graph=True, autotune=True)
+    ob = [host(o) for o in b.run()]
+    for x, y in zip(oa, ob):
+        for u, v in zip(x, y):
+            np.testing.assert_array_equal(u, v)
+    a.close()
+    b.close()
+
+
+def test_batched_workload_64_fp32(gpu_lib):
+    # 64 TTs: N ~ U{8..24}, I in {16,...,256}, R ~ U{8..128}, target R//2,
+    # oversample min(10, R - target); FP32; one graph, autotuned tiles
+    specs = G.batched_specs(0, 64)
+    say("batched workload: 64 TTs, FP32")
+    tts_np, dtt = [], []
+    for s in specs:
+        dims, ranks = G.uniform_tt_shape(s["N"], s["I"], s["R"])
+        X = [c.astype(np.float32) for c in G.random_tt(s["input_seed"], dims, ranks,
+                                                        scale="nominal")]
+        tts_np.append(X)
+        dtt.append([torch.from_numpy(c).cuda() for c in X])
+    bp = gpu_lib.BatchPlan(dtt, [s["target"] for s in specs], [s["oversample"] for s in specs],
+                           [s["sketch_seed"] for s in specs], prec="f32", graph=True,
+                           autotune=True)
+    outs = [host(o) for o in bp.run()]
+    print(bp.info())
+    # properties on every TT, and agreement with the single-TT GPU path
+    worst_orth, worst_single = 0.0, 0.0
+    for s, X, Xd, out in zip(specs, tts_np, dtt, outs):
+        assert all(np.all(np.isfinite(c)) for c in out)
+        worst_orth = max(worst_orth, right_orth_dev(out))
+        single = host(gpu_lib.round_rand(Xd, s["target"], s["oversample"], seed=s["sketch_seed"],
+                                         prec="f32"))
+        worst_single = max(worst_single, O.rel_diff(out, single))
+    print(f"worst right-orthogonality {worst_orth:.2e}; worst batch-vs-single {worst_single:.2e}")
+    assert worst_orth <= 1e-3
+    # both are FP32 computations of a flat-spectrum rounding (first-order
+    # sensitive to rounding); the batch always uses CholeskyQR2, the single
+    # path Householder on small panels
+    assert worst_single <= 3e-3
+    # element-wise oracle parity on the smallest TTs
+    size = [s["N"] * s["I"] * s["R"] ** 2 for s in specs]
+    for b in np.argsort(size)[:4]:
+        s = specs[b]
+        X = [c.astype(np.float64) for c in tts_np[b]]
+        ref = oracle_item(X, dict(target=s["target"], oversample=s["oversample"],
+                                  seed=s["sketch_seed"]), "f32")
+        err = O.rel_diff(outs[b], ref)
+        print(f"item {b} N={s['N']} I={s['I']} R={s['R']}: rel err vs oracle {err:.2e}")
+        assert O.ranks_of(outs[b]) == O.ranks_of(ref)
+        assert err <= 1e-4
+    bp.close()
