@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_tt",
-                    choices=["single_tt", "single_tt_lowrank", "gmres_sum", "small_sum"])
+                    choices=["single_tt", "single_tt_lowrank", "gmres_sum", "small_sum", "batched"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-f64-compare", action="store_true",
                     help="with --prec f32/bf16: skip timing the FP64 path for the speedup")
@@ -178,6 +178,8 @@ def main():
         log("bench.py needs a GPU")
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args)
     wl = make_workload(args.workload)
     dev = torch.device("cuda:0")
 
@@ -306,6 +308,116 @@ def main():
         res["cpu_baseline"] = cb
         res["accuracy"] = {"rel_err_vs_fp64_oracle": float(f"{err:.3e}")}
         log(f"oracle: {cb['value']} ms/rounding on {cb['cores']} threads; GPU rel err {err:.2e}")
+    print(json.dumps(res), flush=True)
+
+
+def batch_flops(spec, ell):
+    """RtO flops of one TT of the batch (2 M N K per product, same shapes as
+    the single-TT path: partial contractions, sweep products, truncation)."""
+    N, I, R = spec["N"], spec["I"], spec["R"]
+    dims = [I] * N
+    ranks = [1] + [R] * (N - 1) + [1]
+    f = sum(site_flops(k, dims, ell, [ranks]) for k in range(5))
+    return f
+
+
+def bench_batched(args):
+    """64 independent roundings (N ~ U{8..24}, I in {16..256}, R ~ U{8..128},
+    target R//2) in one graph launch; FP32 unless --prec says otherwise."""
+    import numpy as np
+    import torch
+
+    import paper_2110_04393_amd as tt
+    import tt_inputs as G
+    prec = args.prec if args.prec != "f64" else "f32"
+    if args.prec == "f64" and "--prec" in sys.argv:
+        prec = "f64"
+    dt = tt.STORAGE[prec]
+    specs = G.batched_specs(0, 64)
+    tts_np, tts = [], []
+    for s in specs:
+        dims, ranks = G.uniform_tt_shape(s["N"], s["I"], s["R"])
+        X = G.random_tt(s["input_seed"], dims, ranks, scale="nominal")
+        tts_np.append(X)
+        tts.append([torch.from_numpy(c).to("cuda:0").to(dt) for c in X])
+    targets = [s["target"] for s in specs]
+    overs = [s["oversample"] for s in specs]
+    seeds = [s["sketch_seed"] for s in specs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        bp = tt.BatchPlan(tts, targets, overs, seeds, prec=prec, graph=True, autotune=True,
+                          stream=stream)
+        torch.cuda.synchronize()
+        create_s = time.perf_counter() - t0
+        info = bp.info()
+        log(f"batch plan: {info}, workspace {bp.ws_bytes / 2**20:.0f} MiB, "
+            f"created in {create_s:.2f} s")
+        for _ in range(args.warmup):
+            bp.run(stream)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            bp.run(stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        batch_ms = ev0.elapsed_time(ev1) / args.steps
+        # the same 64 roundings one after another through the single-TT path
+        plans = [tt.RoundPlan([int(c.shape[1]) for c in t], [1] + [int(c.shape[2]) for c in t],
+                              tr, ov, prec, "cuda:0") for t, tr, ov in zip(tts, targets, overs)]
+        for p, t, sd in zip(plans, tts, seeds):
+            p.run(t, seed=sd, stream=stream)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for p, t, sd in zip(plans, tts, seeds):
+            p.run(t, seed=sd, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        seq_ms = ev0.elapsed_time(ev1)
+    flops = 0.0
+    for s, p in zip(specs, plans):
+        flops += batch_flops(s, p.sketch_ranks)
+    achieved = flops / (batch_ms * 1e-3) / 1e12
+    peak = PEAK[prec if prec != "bf16" else "f32"]
+    log(f"batch of 64: {batch_ms:.3f} ms ({batch_ms / 64:.4f} ms per rounding); "
+        f"sequential single-TT path {seq_ms:.3f} ms; {achieved:.2f} TFLOP/s")
+    res = {
+        "metric": METRIC, "value": round(batch_ms / 64, 5), "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(batch_ms, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "64 independent roundings, N~U{8..24}, I in {16,32,64,128,256}, "
+                               "R~U{8..128}, target R//2, oversample min(10,R-target); one "
+                               "hipGraph launch per batch, autotuned GEMM tiles",
+                   "batch": 64, "precision": prec},
+        "batch": {"ms_per_batch": round(batch_ms, 4), "sequential_single_tt_ms": round(seq_ms, 3),
+                  "speedup_vs_sequential": round(seq_ms / batch_ms, 2),
+                  "plan_create_s": round(create_s, 2), **info},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "whole batched run (all grouped launches)",
+                     "flops_per_step": flops},
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count() or 1
+        t_all = time.perf_counter()
+        done = 0
+        while done < 64 and time.perf_counter() - t_all < args.cpu_budget:
+            s = specs[done]
+            O.round_rand(tts_np[done], s["target"], s["oversample"], seed=s["sketch_seed"])
+            done += 1
+        el = time.perf_counter() - t_all
+        res["cpu_baseline"] = {"value": round(el * 1e3 / max(done, 1), 3), "unit": "ms",
+                               "cores": int(cores), "kind": "oracle",
+                               "sample": f"TTs 0..{done - 1} of the batch in order ({el:.1f} s), "
+                                         "ms per rounding"}
     print(json.dumps(res), flush=True)
 
 

@@ -40,6 +40,8 @@ struct Op {
   std::vector<GemmX> gx;
   int variant = 3;
   int64_t total_wgs = 0;
+  bool reduce = false;  // some entry is split over K
+  int64_t max_mn = 0;
   // OP_CHOL / OP_EIG: largest n; OP_EIG: largest kw; OP_HH: LDS bytes
   int nmax = 0, kwmax = 0;
   size_t lds = 0;
@@ -67,6 +69,9 @@ struct Item {
   double *tg = nullptr, *lam = nullptr, *U = nullptr, *tails = nullptr, *escr = nullptr;
   int *eflag = nullptr;
   void *Pf = nullptr, *Sf = nullptr, *tb[2] = {nullptr, nullptr};
+  // split-K partials of this item's grouped products
+  void *part = nullptr;
+  size_t part_need = 0;
 };
 
 size_t elem_bytes(DType t) { return t == DType::F64 ? 8 : (t == DType::F32 ? 4 : 2); }
@@ -161,6 +166,22 @@ GemmX mk(const Prec &p, DType math, const void *A, int64_t lda, bool akc, DType 
   return g;
 }
 
+// Long contractions are split over K into the item's partial buffer.
+GemmX split(Item &it, GemmX g) {
+  const int sp = gemm_group_splits(g);
+  if (sp > 1) {
+    g.splits = sp;
+    g.partial = it.part;
+    it.part_need = std::max(it.part_need, (size_t)sp * g.M * g.N * gemm_acc_bytes(g.math));
+  }
+  return g;
+}
+
+template <typename... A>
+GemmX mks(Item &it, A &&...args) {
+  return split(it, mk(std::forward<A>(args)...));
+}
+
 // Builds the op list; table offsets are assigned by assign_tables().
 int build_ops(Batch &b) {
   const Prec &p = b.pc;
@@ -174,6 +195,10 @@ int build_ops(Batch &b) {
     o.kind = OP_GEMM;
     o.gx = std::move(g);
     o.count = (int)o.gx.size();
+    for (const GemmX &x : o.gx) {
+      if (x.splits > 1) o.reduce = true;
+      o.max_mn = std::max(o.max_mn, x.M * x.N);
+    }
     ops.push_back(std::move(o));
   };
   // sketches
@@ -193,16 +218,16 @@ int build_ops(Batch &b) {
       const int64_t *dims = it.P.dims.data();
       const std::vector<int64_t> &L = it.P.ell, &R = it.P.R[0];
       if (s == 0) {
-        w.push_back(mk(p, p.wmath, it.Y[N - 1], dims[N - 1], true, st, it.Sk[N - 1], dims[N - 1],
+        w.push_back(mks(it, p, p.wmath, it.Y[N - 1], dims[N - 1], true, st, it.Sk[N - 1], dims[N - 1],
                        true, p.sk, it.W[N - 1], L[N - 1], st, R[N - 1], L[N - 1], dims[N - 1]));
         sc.scale.push_back({it.W[N - 1], R[N - 1] * L[N - 1], it.fac + N - 1});
       } else {
         const int n = N - s;
         if (n < 2) continue;
         const int64_t I = dims[n - 1];
-        z.push_back(mk(p, p.wmath, it.Y[n - 1], R[n], true, st, it.W[n], L[n], false, st, it.zc,
+        z.push_back(mks(it, p, p.wmath, it.Y[n - 1], R[n], true, st, it.W[n], L[n], false, st, it.zc,
                        L[n], st, R[n - 1] * I, L[n], R[n]));
-        w.push_back(mk(p, p.wmath, it.zc, I * L[n], true, st, it.Sk[n - 1], I * L[n], true, p.sk,
+        w.push_back(mks(it, p, p.wmath, it.zc, I * L[n], true, st, it.Sk[n - 1], I * L[n], true, p.sk,
                        it.W[n - 1], L[n - 1], st, R[n - 1], L[n - 1], I * L[n]));
         sc.scale.push_back({it.W[n - 1], R[n - 1] * L[n - 1], it.fac + n - 1});
       }
@@ -228,17 +253,17 @@ int build_ops(Batch &b) {
       const int64_t m = L[n - 1] * dims[n - 1], ln = L[n];
       const void *cur = (n == 1) ? it.Y[0] : it.xb[(n - 1) & 1];
       void *dst = (n + 1 == N) ? it.xs[N] : it.xb[n & 1];
-      gy.push_back(mk(p, st, cur, R[n], true, st, it.W[n], ln, false, st, it.ys, ln, st, m, ln,
+      gy.push_back(mks(it, p, st, cur, R[n], true, st, it.W[n], ln, false, st, it.ys, ln, st, m, ln,
                       R[n]));
       const void *rinv_t = (st == DType::F32) ? (const void *)it.rinv_f : (const void *)it.rinv;
-      g1.push_back(mk(p, DType::F64, it.ys, ln, false, st, it.ys, ln, false, st, it.gram, ln,
+      g1.push_back(mks(it, p, DType::F64, it.ys, ln, false, st, it.ys, ln, false, st, it.gram, ln,
                       DType::F64, ln, ln, m));
       c1.chol.push_back({it.gram, it.rinv, it.rinv_f, (int)ln, it.qflag, 0});
-      q1.push_back(mk(p, st, it.ys, ln, true, st, rinv_t, ln, false, st, it.q1, ln, st, m, ln, ln));
-      g2.push_back(mk(p, DType::F64, it.q1, ln, false, st, it.q1, ln, false, st, it.gram, ln,
+      q1.push_back(mks(it, p, st, it.ys, ln, true, st, rinv_t, ln, false, st, it.q1, ln, st, m, ln, ln));
+      g2.push_back(mks(it, p, DType::F64, it.q1, ln, false, st, it.q1, ln, false, st, it.gram, ln,
                       DType::F64, ln, ln, m));
       c2.chol.push_back({it.gram, it.rinv, it.rinv_f, (int)ln, it.qflag, 1});
-      q2.push_back(mk(p, st, it.q1, ln, true, st, rinv_t, ln, false, st, it.xs[n], ln, st, m, ln,
+      q2.push_back(mks(it, p, st, it.q1, ln, true, st, rinv_t, ln, false, st, it.xs[n], ln, st, m, ln,
                       ln));
       QrScratch qs;
       qs.gram = it.gram;
@@ -251,10 +276,10 @@ int build_ops(Batch &b) {
       hh.hh.push_back(d);
       hh.lds = std::max(hh.lds, need);
       c1.nmax = c2.nmax = std::max(c1.nmax, (int)ln);
-      gm.push_back(mk(p, st, it.xs[n], ln, false, st, cur, R[n], false, st, it.mbuf, R[n], st, ln,
+      gm.push_back(mks(it, p, st, it.xs[n], ln, false, st, cur, R[n], false, st, it.mbuf, R[n], st, ln,
                       R[n], m));
       const int64_t cols = dims[n] * R[n + 1];
-      gn.push_back(mk(p, st, it.mbuf, R[n], true, st, it.Y[n], cols, false, st, dst, cols, st, ln,
+      gn.push_back(mks(it, p, st, it.mbuf, R[n], true, st, it.Y[n], cols, false, st, dst, cols, st, ln,
                       cols, R[n]));
     }
     if (gy.empty()) continue;
@@ -286,7 +311,7 @@ int build_ops(Batch &b) {
       const int64_t rr = (n == N) ? 1 : it.P.out[n];
       const int64_t lr = L[n - 1], k = it.P.out[n - 1], cols = dims[n - 1] * rr;
       const void *hsrc = (n == N) ? it.xs[N] : it.tb[(n + 1) & 1];
-      gg.push_back(mk(p, DType::F64, hsrc, cols, true, st, hsrc, cols, true, st, it.tg, lr,
+      gg.push_back(mks(it, p, DType::F64, hsrc, cols, true, st, hsrc, cols, true, st, it.tg, lr,
                       DType::F64, lr, lr, cols));
       EigGroupDesc d;
       if (!eig_group_desc(it.tg, lr, k, it.lam, it.U, it.Pf, it.Sf, it.tails + n - 1, it.eflag,
@@ -295,11 +320,11 @@ int build_ops(Batch &b) {
       eg.eig.push_back(d);
       eg.nmax = std::max(eg.nmax, (int)lr);
       eg.kwmax = std::max(eg.kwmax, d.kw);
-      gs.push_back(mk(p, st, it.Sf, lr, true, st, hsrc, cols, false, st, it.out[n - 1], cols, st, k,
+      gs.push_back(mks(it, p, st, it.Sf, lr, true, st, hsrc, cols, false, st, it.out[n - 1], cols, st, k,
                       cols, lr));
       const int64_t rows = L[n - 2] * dims[n - 2];
       void *dst = (n - 1 == 1) ? it.out[0] : it.tb[n & 1];
-      gp.push_back(mk(p, st, it.xs[n - 1], lr, true, st, it.Pf, k, false, st, dst, k, st, rows, k,
+      gp.push_back(mks(it, p, st, it.xs[n - 1], lr, true, st, it.Pf, k, false, st, dst, k, st, rows, k,
                       lr));
     }
     if (gg.empty()) continue;
@@ -376,8 +401,11 @@ int launch_op(Batch &b, const Op &o, hipStream_t s) {
                              (void *const *)it.Sk.data(), s);
     }
     case OP_GEMM:
-      return gemm_group_run(o.gx[0], o.variant, (const GemmGroupEntry *)tab, o.count, o.total_wgs,
-                            s);
+      TTR_TRY(gemm_group_run(o.gx[0], o.variant, (const GemmGroupEntry *)tab, o.count,
+                             o.total_wgs, s));
+      if (o.reduce)
+        TTR_TRY(gemm_group_reduce(o.gx[0], (const GemmGroupEntry *)tab, o.count, o.max_mn, s));
+      return TT_OK;
     case OP_CHOL: return chol_group_run((const CholGroupDesc *)tab, o.count, o.nmax, s);
     case OP_HH:
       return f32 ? householder_group_run<float>((const HhGroupDesc *)tab, o.count, o.lds, s)
@@ -474,7 +502,8 @@ struct BatchArgs {
   const int64_t *dims = nullptr, *ranks = nullptr, *target = nullptr, *over = nullptr;
 };
 
-int make_items(Batch &b, const BatchArgs &a, char *base, size_t *item_bytes) {
+int make_items(Batch &b, const BatchArgs &a, char *base, size_t *item_bytes,
+               const std::vector<size_t> *needs) {
   if (a.B < 1) return fail(TT_EINVAL, "batch needs at least one TT");
   if (!a.orders || !a.dims || !a.ranks || !a.target || !a.over)
     return fail(TT_EINVAL, "null batch description array");
@@ -491,6 +520,7 @@ int make_items(Batch &b, const BatchArgs &a, char *base, size_t *item_bytes) {
     for (int n = 0; n <= N; ++n)
       if (it.P.ell[n] > 76) return fail(TT_EUNSUPPORTED, "batched rounding: sketch rank above 76");
     layout_item(it, b.pc, arena);
+    if (needs) it.part = take_bytes(arena, (*needs)[i]);
     it.Y.assign(N, nullptr);  // filled by tt_batch_create
     it.out.assign(N, nullptr);
     doff += N;
@@ -512,16 +542,18 @@ struct tt_batch_s {
 
 namespace {
 
+// Two passes: the first sizes the launch tables and every item's split-K
+// partial buffer, the second lays the items out behind the tables.
 int batch_layout(Batch &b, const BatchArgs &a, char *base, size_t *total) {
   size_t item_bytes = 0;
-  TTR_TRY(make_items(b, a, nullptr, &item_bytes));
+  TTR_TRY(make_items(b, a, nullptr, &item_bytes, nullptr));
   b.ops.clear();
   TTR_TRY(build_ops(b));
   b.table_bytes = assign_tables(b);
-  if (base) {
-    b.ops.clear();
-    TTR_TRY(make_items(b, a, base + b.table_bytes, &item_bytes));
-  }
+  std::vector<size_t> needs;
+  for (const Item &it : b.items) needs.push_back(it.part_need);
+  b.ops.clear();
+  TTR_TRY(make_items(b, a, base ? base + b.table_bytes : nullptr, &item_bytes, &needs));
   *total = b.table_bytes + item_bytes;
   return TT_OK;
 }
@@ -585,7 +617,7 @@ int tt_batch_create(int32_t B, const int32_t *orders, const int64_t *dims, const
   if (flags & TT_BATCH_AUTOTUNE) TTR_TRY(autotune(b, st));
   TTR_TRY(upload_tables(b));
   b.launches = 0;
-  for (const Op &o : b.ops) b.launches += (o.kind == OP_EIG) ? 5 : 1;
+  for (const Op &o : b.ops) b.launches += (o.kind == OP_EIG) ? 5 : (o.reduce ? 2 : 1);
   if (flags & TT_BATCH_GRAPH) {
     // one eager pass (first-use kernel attributes are set outside capture)
     TTR_TRY(run_ops(b, st));

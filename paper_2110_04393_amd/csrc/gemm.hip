@@ -242,6 +242,23 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmX g) {
   *c = (TC)out;
 }
 
+template <typename TP, typename TC>
+__global__ __launch_bounds__(256) void splitk_group_reduce_kernel(const GemmGroupEntry *tab) {
+  const GemmX &g = tab[blockIdx.y].g;
+  if (g.splits <= 1) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = g.M * g.N;
+  if (idx >= total) return;
+  const TP *part = static_cast<const TP *>(g.partial);
+  TP s = 0;
+  for (int p = 0; p < g.splits; ++p) s += part[p * total + idx];
+  const int64_t row = idx / g.N, col = idx - row * g.N;
+  TC *c = static_cast<TC *>(g.C) + row * g.ldc + col;
+  const double out = (g.beta != 0.0) ? g.alpha * (double)s + g.beta * cvt<double>(*c)
+                                      : g.alpha * (double)s;
+  *c = (TC)out;
+}
+
 struct Variant {
   int tm, tn, wm, wn;
 };
@@ -422,6 +439,13 @@ void gemm_variant_tile(int v, int64_t *bm, int64_t *bn) {
   *bn = 16 * kVariants[v].tn * kVariants[v].wn;
 }
 
+int gemm_group_splits(const GemmX &g) {
+  // bound the K range of one workgroup (~512) so that long contractions of
+  // small outputs (Gram matrices, projections) spread over many workgroups
+  if (g.K <= 1024) return 1;
+  return (int)std::min<int64_t>(64, (g.K + 511) / 512);
+}
+
 int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e) {
   if (g.M <= 0 || g.N <= 0) return fail(TT_EINVAL, "grouped gemm with an empty product");
   if (g.K <= 0) return fail(TT_EINVAL, "grouped gemm with K <= 0");
@@ -429,17 +453,42 @@ int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e) 
   int64_t bm, bn;
   gemm_variant_tile(v, &bm, &bn);
   e->g = g;
-  e->g.splits = 1;
-  e->g.partial = nullptr;
   e->tiles_m = (g.M + bm - 1) / bm;
   e->tiles_n = (g.N + bn - 1) / bn;
   const int chunk = gemm_chunk(g.math);
-  e->kchunk = (g.K + chunk - 1) / chunk * chunk;
+  const int sp = (g.partial && g.splits > 1) ? g.splits : 1;
+  int64_t kc = (g.K + sp - 1) / sp;
+  kc = (kc + chunk - 1) / chunk * chunk;
+  e->kchunk = kc;
+  e->g.splits = (int)((g.K + kc - 1) / kc);
+  if (e->g.splits <= 1) {
+    e->g.splits = 1;
+    e->g.partial = nullptr;
+  }
   e->wg_begin = wg_begin;
   return TT_OK;
 }
 
-int64_t gemm_group_wgs(const GemmGroupEntry &e) { return e.tiles_m * e.tiles_n; }
+int64_t gemm_group_wgs(const GemmGroupEntry &e) { return e.tiles_m * e.tiles_n * e.g.splits; }
+
+int gemm_group_reduce(const GemmX &rep, const GemmGroupEntry *d_tab, int count, int64_t max_mn,
+                      hipStream_t s) {
+  if (count <= 0 || max_mn <= 0) return TT_OK;
+  const dim3 gr((unsigned)((max_mn + 255) / 256), (unsigned)count), bl(256);
+  if (rep.math == DType::F64) {
+    if (rep.tc == DType::F64)
+      hipLaunchKernelGGL((splitk_group_reduce_kernel<double, double>), gr, bl, 0, s, d_tab);
+    else
+      hipLaunchKernelGGL((splitk_group_reduce_kernel<double, float>), gr, bl, 0, s, d_tab);
+  } else {
+    if (rep.tc == DType::F64)
+      hipLaunchKernelGGL((splitk_group_reduce_kernel<float, double>), gr, bl, 0, s, d_tab);
+    else
+      hipLaunchKernelGGL((splitk_group_reduce_kernel<float, float>), gr, bl, 0, s, d_tab);
+  }
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
 
 int gemm_group_run(const GemmX &rep, int v, const GemmGroupEntry *d_tab, int count,
                    int64_t total_wgs, hipStream_t s) {

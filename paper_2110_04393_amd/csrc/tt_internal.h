@@ -112,7 +112,12 @@ struct GemmGroupEntry {
 };
 int gemm_variant_count();
 void gemm_variant_tile(int v, int64_t *bm, int64_t *bn);
+// split count for a grouped product (entries carry g.splits and g.partial;
+// the partials of entries with splits > 1 are summed by gemm_group_reduce)
+int gemm_group_splits(const GemmX &g);
 int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e);
+int gemm_group_reduce(const GemmX &rep, const GemmGroupEntry *d_tab, int count, int64_t max_mn,
+                      hipStream_t s);
 int64_t gemm_group_wgs(const GemmGroupEntry &e);
 // launches count products (table in device memory) in one grid of total_wgs
 // workgroups; rep gives the common types and layouts
