@@ -483,7 +483,7 @@ int default_variants(Batch &b) {
     double cost = 1e300;
     for (int v = 0; v < gemm_variant_count(); ++v) {
       int64_t bm, bn;
-      gemm_variant_tile(v, &bm, &bn);
+      gemm_variant_tile(o.gx[0].math, v, &bm, &bn);
       const double c = double((bestM + bm - 1) / bm * bm) * double((bestN + bn - 1) / bn * bn) *
                        (1.0 + 1e-3 * v);
       if (c < cost) {

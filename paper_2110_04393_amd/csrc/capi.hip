@@ -119,7 +119,7 @@ struct Timer {
 Timer g_timer;
 
 int gemm(Ctx &c, GemmX g, int site = -1) {
-  const int sp = (g.batch > 1) ? 1 : gemm_pick_splits(g.M, g.N, g.K);
+  const int sp = (g.batch > 1) ? 1 : gemm_pick_splits(g.M, g.N, g.K, g.math);
   const size_t need = sp > 1 ? (size_t)sp * g.M * g.N * gemm_acc_bytes(g.math) : 0;
   c.partial_need = std::max(c.partial_need, need);
   if (c.dry) return TT_OK;

@@ -27,7 +27,8 @@
 // bf16 ones (both measured on gfx950).
 //
 // Split-K: the K range is cut into chunks; each chunk writes its partial tile
-// in the accumulator type and a second kernel adds the chunks in index order,
+// in the accumulator type and a second kernel adds the chunks in a fixed
+// order (groups of eight in index order, then the group sums in index order),
 // so results are bitwise reproducible (no float atomics).
 #include "tt_internal.h"
 
@@ -49,6 +50,9 @@ struct MathF64 {
     for (int s = 0; s < CPL; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
     return c;
   }
+  __device__ static acc_t mma1(in_t a, in_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
 };
 struct MathF32 {
   typedef float in_t;
@@ -60,6 +64,9 @@ struct MathF32 {
 #pragma unroll
     for (int s = 0; s < CPL; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
     return c;
+  }
+  __device__ static acc_t mma1(in_t a, in_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
 struct MathBF16 {
@@ -96,31 +103,19 @@ struct TileMap {
   int64_t tiles_m, tiles_n, kchunk;
 };
 
-template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
-__device__ __forceinline__ void gemm_body(const GemmX &g, const TileMap &tm, int64_t wg) {
-  static_assert(WM * WN == 4, "4 wavefronts per workgroup");
+constexpr int kSplitGroup = 8;
+
+// one wavefront's (16 TM) x (16 TN) tile of the register-streaming body
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN>
+__device__ __forceinline__ void gemm_body_wave(const GemmX &g, const TileMap &tm, int64_t split,
+                                               const TA *gA, const TB *gB, TC *gC, int64_t m0,
+                                               int64_t n0) {
   typedef typename MT::acc_t acc_t;
   typedef typename MT::in_t in_t;
   typedef typename MT::part_t part_t;
   constexpr int CPL = MT::CPL;
   constexpr int CHUNK = 4 * CPL;
-  const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int wm = wave % WM, wn = wave / WM;
-  const int64_t tn_wg = wg % tm.tiles_n;
-  wg /= tm.tiles_n;
-  const int64_t tm_wg = wg % tm.tiles_m;
-  wg /= tm.tiles_m;
-  const int64_t split = (g.batch > 1) ? 0 : wg;
-  const int64_t bidx = (g.batch > 1) ? wg : 0;
-  const TA *gA = static_cast<const TA *>(g.A) + bidx * g.sA;
-  const TB *gB = static_cast<const TB *>(g.B) + bidx * g.sB;
-  TC *gC = static_cast<TC *>(g.C) + bidx * g.sC;
-
-  const int64_t m0 = (tm_wg * WM + wm) * (16 * TM);
-  const int64_t n0 = (tn_wg * WN + wn) * (16 * TN);
-  if (m0 >= g.M || n0 >= g.N) return;  // no barriers below
   const int64_t kbeg = split * tm.kchunk;
   const int64_t kend = min(g.K, kbeg + tm.kchunk);
   const int r = lane & 15, q = lane >> 4;
@@ -202,8 +197,243 @@ __device__ __forceinline__ void gemm_body(const GemmX &g, const TileMap &tm, int
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN>
+__device__ __forceinline__ void gemm_body(const GemmX &g, const TileMap &tm, int64_t wg) {
+  static_assert(WM * WN == 4, "4 wavefronts per workgroup");
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int64_t tn_wg = wg % tm.tiles_n;
+  wg /= tm.tiles_n;
+  const int64_t tm_wg = wg % tm.tiles_m;
+  wg /= tm.tiles_m;
+  const int64_t split = (g.batch > 1) ? 0 : wg;
+  const int64_t bidx = (g.batch > 1) ? wg : 0;
+  const TA *gA = static_cast<const TA *>(g.A) + bidx * g.sA;
+  const TB *gB = static_cast<const TB *>(g.B) + bidx * g.sB;
+  TC *gC = static_cast<TC *>(g.C) + bidx * g.sC;
+
+  const int64_t m0 = (tm_wg * WM + wm) * (16 * TM);
+  const int64_t n0 = (tn_wg * WN + wn) * (16 * TN);
+  if (m0 < g.M && n0 < g.N)
+    gemm_body_wave<MT, TA, TB, TC, AKC, BKC, TM, TN>(g, tm, split, gA, gB, gC, m0, n0);
+}
+
+// Four consecutive elements from a 16-byte aligned address as vector loads,
+// converted to the MFMA input type.
+template <typename To>
+__device__ __forceinline__ void load4(const double *p, To (&o)[4]) {
+  typedef double d2_t __attribute__((ext_vector_type(2)));
+  const d2_t x = *reinterpret_cast<const d2_t *>(p);
+  const d2_t y = *reinterpret_cast<const d2_t *>(p + 2);
+  o[0] = (To)x[0];
+  o[1] = (To)x[1];
+  o[2] = (To)y[0];
+  o[3] = (To)y[1];
+}
+template <typename To>
+__device__ __forceinline__ void load4(const float *p, To (&o)[4]) {
+  const f4_t x = *reinterpret_cast<const f4_t *>(p);
+  o[0] = (To)x[0];
+  o[1] = (To)x[1];
+  o[2] = (To)x[2];
+  o[3] = (To)x[3];
+}
+template <typename To>
+__device__ __forceinline__ void load4(const __bf16 *p, To (&o)[4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) o[s] = (To)(float)p[s];
+}
+
+// LDS-staged form for the x4 instructions (f64, f32).  The workgroup tile
+// BM x BN = (16 TM WM) x (16 TN WN) advances over K in steps of BK = 32:
+// all 256 threads load the A (BM x BK) and B (BK x BN) tiles with
+// coalesced reads (4 consecutive elements of the contiguous dimension per
+// thread), convert them to the MFMA type and store them k-major in LDS
+// (As[k][m], Bs[k][n]); every wavefront then reads its fragments
+// (A(m0 + r, k + q), B(k + q, n0 + r), lane = r + 16 q) from LDS, so each
+// operand element is fetched from memory once per workgroup.  The next tile
+// is loaded into registers while the current one feeds the MFMAs (two LDS
+// buffers, one barrier per step).  A row padding (8 doubles, 16 floats)
+// spreads the four k-rows of a fragment read over the LDS banks, so a read
+// takes the minimum number of passes.
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+__device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm, int64_t wg) {
+  static_assert(WM * WN == 4, "4 wavefronts per workgroup");
+  static_assert(MT::CPL == 4, "x4 MFMA instructions");
+  typedef typename MT::acc_t acc_t;
+  typedef typename MT::in_t in_t;
+  typedef typename MT::part_t part_t;
+  constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = 32;
+  constexpr int PAD = sizeof(in_t) == 8 ? 8 : 16;
+  constexpr int RA = BM * BK / 1024, RB = BN * BK / 1024;  // 4-element groups per thread
+  static_assert(BM % 64 == 0 && BN % 64 == 0, "tiles are multiples of 64");
+  __shared__ in_t As[2][BK][BM + PAD];
+  __shared__ in_t Bs[2][BK][BN + PAD];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wm = wave % WM, wn = wave / WM;
+  const int64_t tn_wg = wg % tm.tiles_n;
+  wg /= tm.tiles_n;
+  const int64_t tm_wg = wg % tm.tiles_m;
+  wg /= tm.tiles_m;
+  const int64_t split = (g.batch > 1) ? 0 : wg;
+  const int64_t bidx = (g.batch > 1) ? wg : 0;
+  const TA *gA = static_cast<const TA *>(g.A) + bidx * g.sA;
+  const TB *gB = static_cast<const TB *>(g.B) + bidx * g.sB;
+  TC *gC = static_cast<TC *>(g.C) + bidx * g.sC;
+  const int64_t M0 = tm_wg * BM, N0 = tn_wg * BN;
+  const int64_t kbeg = split * tm.kchunk;
+  const int64_t kend = min(g.K, kbeg + tm.kchunk);
+  const int r = lane & 15, q = lane >> 4;
+
+  // ---- global -> registers: thread t owns RA (RB) groups of 4 consecutive
+  // elements along the operand's contiguous dimension
+  in_t ra[RA][4], rb[RB][4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < RA; ++u) {
+      const int t = tid + 256 * u;
+      int64_t m, k;
+      if (AKC) {  // 4 consecutive k of row m
+        m = M0 + t / (BK / 4);
+        k = k0 + 4 * (t % (BK / 4));
+      } else {    // 4 consecutive m of row k
+        k = k0 + t / (BM / 4);
+        m = M0 + 4 * (t % (BM / 4));
+      }
+      const TA *p = AKC ? gA + m * g.lda + k : gA + k * g.lda + m;
+      const bool full = AKC ? (m < g.M && k + 3 < kend) : (k < kend && m + 3 < g.M);
+      if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        load4(p, ra[u]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const bool ok = AKC ? (m < g.M && k + s < kend) : (k < kend && m + s < g.M);
+          ra[u][s] = ok ? cvt<in_t>(p[s]) : in_t(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int t = tid + 256 * u;
+      int64_t n, k;
+      if (BKC) {
+        n = N0 + t / (BK / 4);
+        k = k0 + 4 * (t % (BK / 4));
+      } else {
+        k = k0 + t / (BN / 4);
+        n = N0 + 4 * (t % (BN / 4));
+      }
+      const TB *p = BKC ? gB + n * g.ldb + k : gB + k * g.ldb + n;
+      const bool full = BKC ? (n < g.N && k + 3 < kend) : (k < kend && n + 3 < g.N);
+      if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        load4(p, rb[u]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const bool ok = BKC ? (n < g.N && k + s < kend) : (k < kend && n + s < g.N);
+          rb[u][s] = ok ? cvt<in_t>(p[s]) : in_t(0);
+        }
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < RA; ++u) {
+      const int t = tid + 256 * u;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (AKC) As[buf][4 * (t % (BK / 4)) + s][t / (BK / 4)] = ra[u][s];
+        else As[buf][t / (BM / 4)][4 * (t % (BM / 4)) + s] = ra[u][s];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int t = tid + 256 * u;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (BKC) Bs[buf][4 * (t % (BK / 4)) + s][t / (BK / 4)] = rb[u][s];
+        else Bs[buf][t / (BN / 4)][4 * (t % (BN / 4)) + s] = rb[u][s];
+      }
+    }
+  };
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  const int am = wm * 16 * TM + r, bn = wn * 16 * TN + r;
+
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      in_t a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[buf][kk + q][am + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + q][bn + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MT::mma1(a[i], b[j], acc[i][j]);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // ---- store
+  const int64_t m0 = M0 + wm * 16 * TM, n0 = N0 + wn * 16 * TN;
+  part_t *part = static_cast<part_t *>(g.partial);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t col = n0 + 16 * j + r;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int64_t row = m0 + 16 * i + MT::row(q, jj);
+        if (row >= g.M) continue;
+        const part_t v = acc[i][j][jj];
+        if (g.splits > 1) {
+          part[(split * g.M + row) * g.N + col] = v;
+        } else {
+          TC *c = gC + row * g.ldc + col;
+          const double out = (g.beta != 0.0)
+                                 ? g.alpha * (double)v + g.beta * cvt<double>(*c)
+                                 : g.alpha * (double)v;
+          *c = (TC)out;
+        }
+      }
+    }
+}
+
+// the LDS-staged body for the x4 instructions, the register-streaming one
+// for bf16
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+__device__ __forceinline__ void gemm_any_body(const GemmX &g, const TileMap &tm, int64_t wg) {
+  if constexpr (MT::CPL == 4)
+    gemm_lds_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
+  else
+    gemm_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
+}
+
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
-  gemm_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, blockIdx.x);
+  gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, blockIdx.x);
 }
 
 // Grouped form: one launch over several independent products (same types,
@@ -224,60 +454,91 @@ __global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupEntry *t
   tm.tiles_m = e.tiles_m;
   tm.tiles_n = e.tiles_n;
   tm.kchunk = e.kchunk;
-  gemm_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(e.g, tm, b - e.wg_begin);
+  gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(e.g, tm, b - e.wg_begin);
+}
+
+// Sum of the split-K partials into C: 32 output elements per workgroup, the
+// eight wavefront-quarters each summing whole groups of eight partials (all
+// loads of a group in flight), then the group sums added in index order.
+// Entry blockIdx.y of the table (or the single product g).
+constexpr int kRedElems = 32;
+constexpr int kRedMaxGroups = 32;  // 256 partials
+
+template <typename TP, typename TC>
+__device__ __forceinline__ void splitk_reduce_body(const GemmX &g) {
+  __shared__ TP s_gs[kRedMaxGroups][kRedElems];
+  const int P = g.splits;
+  const int G = (P + kSplitGroup - 1) / kSplitGroup;
+  const int64_t total = g.M * g.N;
+  const int t = threadIdx.x & (kRedElems - 1), part_of = threadIdx.x / kRedElems;
+  const int64_t idx = (int64_t)blockIdx.x * kRedElems + t;
+  const bool ok = idx < total;
+  const TP *part = static_cast<const TP *>(g.partial);
+  for (int grp = part_of; grp < G; grp += 256 / kRedElems) {
+    TP v[kSplitGroup];
+#pragma unroll
+    for (int u = 0; u < kSplitGroup; ++u) {
+      const int p = grp * kSplitGroup + u;
+      v[u] = (ok && p < P) ? part[(int64_t)p * total + idx] : TP(0);
+    }
+    TP gs = TP(0);
+#pragma unroll
+    for (int u = 0; u < kSplitGroup; ++u) gs += v[u];
+    s_gs[grp][t] = gs;
+  }
+  __syncthreads();
+  if (part_of != 0 || !ok) return;
+  TP acc = s_gs[0][t];
+  if (G > 1) {
+    acc = TP(0);
+    for (int grp = 0; grp < G; ++grp) acc += s_gs[grp][t];
+  }
+  const int64_t row = idx / g.N, col = idx - row * g.N;
+  TC *c = static_cast<TC *>(g.C) + row * g.ldc + col;
+  const double out = (g.beta != 0.0) ? g.alpha * (double)acc + g.beta * cvt<double>(*c)
+                                     : g.alpha * (double)acc;
+  *c = (TC)out;
 }
 
 template <typename TP, typename TC>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmX g) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = g.M * g.N;
-  if (idx >= total) return;
-  const TP *part = static_cast<const TP *>(g.partial);
-  TP s = 0;
-  for (int p = 0; p < g.splits; ++p) s += part[p * total + idx];
-  const int64_t row = idx / g.N, col = idx - row * g.N;
-  TC *c = static_cast<TC *>(g.C) + row * g.ldc + col;
-  const double out = (g.beta != 0.0) ? g.alpha * (double)s + g.beta * cvt<double>(*c)
-                                      : g.alpha * (double)s;
-  *c = (TC)out;
+  splitk_reduce_body<TP, TC>(g);
 }
 
 template <typename TP, typename TC>
 __global__ __launch_bounds__(256) void splitk_group_reduce_kernel(const GemmGroupEntry *tab) {
   const GemmX &g = tab[blockIdx.y].g;
-  if (g.splits <= 1) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = g.M * g.N;
-  if (idx >= total) return;
-  const TP *part = static_cast<const TP *>(g.partial);
-  TP s = 0;
-  for (int p = 0; p < g.splits; ++p) s += part[p * total + idx];
-  const int64_t row = idx / g.N, col = idx - row * g.N;
-  TC *c = static_cast<TC *>(g.C) + row * g.ldc + col;
-  const double out = (g.beta != 0.0) ? g.alpha * (double)s + g.beta * cvt<double>(*c)
-                                      : g.alpha * (double)s;
-  *c = (TC)out;
+  if (g.splits <= 1 || (int64_t)blockIdx.x * kRedElems >= g.M * g.N) return;
+  splitk_reduce_body<TP, TC>(g);
 }
 
 struct Variant {
   int tm, tn, wm, wn;
 };
-constexpr Variant kVariants[] = {
-    {1, 1, 1, 4},  // 16 x 64
-    {1, 1, 4, 1},  // 64 x 16
-    {1, 1, 2, 2},  // 32 x 32
-    {2, 2, 2, 2},  // 64 x 64
-};
+// LDS-staged body (f64, f32): 64x64, 128x64, 64x128, 128x128 outputs per
+// workgroup; register-streaming body (bf16): 16x64, 64x16, 32x32, 64x64
+constexpr Variant kVarLds[] = {{2, 2, 2, 2}, {2, 4, 4, 1}, {4, 2, 1, 4}, {4, 4, 2, 2}};
+constexpr Variant kVarReg[] = {{1, 1, 1, 4}, {1, 1, 4, 1}, {1, 1, 2, 2}, {2, 2, 2, 2}};
 
-int pick_variant(int64_t M, int64_t N) {
+const Variant &variant_of(DType math, int v) {
+  return math == DType::BF16 ? kVarReg[v] : kVarLds[v];
+}
+
+void tile_of(DType math, int v, int64_t *bm, int64_t *bn) {
+  const Variant &x = variant_of(math, v);
+  *bm = 16 * x.tm * x.wm;
+  *bn = 16 * x.tn * x.wn;
+}
+
+int pick_variant(int64_t M, int64_t N, DType math) {
   // least padded work; ties go to the smaller tile (more workgroups)
   int best = 0;
   double best_cost = 1e300;
   for (int v = 0; v < 4; ++v) {
-    const int64_t bm = 16 * kVariants[v].tm * kVariants[v].wm;
-    const int64_t bn = 16 * kVariants[v].tn * kVariants[v].wn;
+    int64_t bm, bn;
+    tile_of(math, v, &bm, &bn);
     const double cost = double((M + bm - 1) / bm * bm) * double((N + bn - 1) / bn * bn) *
-                        (1.0 + 1e-3 * v);
+                        (1.0 + 1e-3 * (double)(bm * bn));
     if (cost < best_cost) {
       best_cost = cost;
       best = v;
@@ -302,19 +563,36 @@ void launch_one(const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC>
 void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
                    const GemmGroupEntry *tab, int count) {
-  switch (v) {
-    case 0:
-      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 1, 4>(g, tm, grid, s, tab, count);
-      break;
-    case 1:
-      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 1>(g, tm, grid, s, tab, count);
-      break;
-    case 2:
-      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 2>(g, tm, grid, s, tab, count);
-      break;
-    default:
-      launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
-      break;
+  if constexpr (MT::CPL == 4) {
+    switch (v) {
+      case 0:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
+        break;
+      case 1:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 4, 4, 1>(g, tm, grid, s, tab, count);
+        break;
+      case 2:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 4, 2, 1, 4>(g, tm, grid, s, tab, count);
+        break;
+      default:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 4, 4, 2, 2>(g, tm, grid, s, tab, count);
+        break;
+    }
+  } else {
+    switch (v) {
+      case 0:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 1, 4>(g, tm, grid, s, tab, count);
+        break;
+      case 1:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 1>(g, tm, grid, s, tab, count);
+        break;
+      case 2:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 2>(g, tm, grid, s, tab, count);
+        break;
+      default:
+        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
+        break;
+    }
   }
 }
 
@@ -363,11 +641,13 @@ bool dispatch(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_
 
 int gemm_chunk(DType math) { return math == DType::BF16 ? 32 : 16; }
 
-int gemm_pick_splits(int64_t M, int64_t N, int64_t K) {
+
+
+int gemm_pick_splits(int64_t M, int64_t N, int64_t K, DType math) {
   if (M <= 0 || N <= 0 || K <= 0) return 1;
-  const int v = pick_variant(M, N);
-  const int64_t bm = 16 * kVariants[v].tm * kVariants[v].wm;
-  const int64_t bn = 16 * kVariants[v].tn * kVariants[v].wn;
+  const int v = pick_variant(M, N, math);
+  int64_t bm, bn;
+  tile_of(math, v, &bm, &bn);
   const int64_t wgs = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
   const int64_t want = 512;  // workgroups: 2 per CU
   if (wgs >= want / 2) return 1;
@@ -398,9 +678,9 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
   if (g.K <= 0) return fail(TT_EINVAL, "gemm with K <= 0");
   if (g.batch > 1 && g.splits > 1) return fail(TT_EINVAL, "batched split-K gemm");
   if (g.batch < 1) return TT_OK;
-  const int v = pick_variant(g.M, g.N);
-  const int64_t bm = 16 * kVariants[v].tm * kVariants[v].wm;
-  const int64_t bn = 16 * kVariants[v].tn * kVariants[v].wn;
+  const int v = pick_variant(g.M, g.N, g.math);
+  int64_t bm, bn;
+  tile_of(g.math, v, &bm, &bn);
   TileMap tm;
   tm.tiles_m = (g.M + bm - 1) / bm;
   tm.tiles_n = (g.N + bn - 1) / bn;
@@ -410,12 +690,13 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
   gg.splits = (int)used_splits;
   tm.kchunk = kchunk;
   if (gg.splits > 1 && gg.partial == nullptr) return fail(TT_EINVAL, "split-K without buffer");
+  if (gg.splits > kRedMaxGroups * kSplitGroup) return fail(TT_EINVAL, "internal: too many K splits");
   const int64_t grid = tm.tiles_m * tm.tiles_n * (g.batch > 1 ? g.batch : used_splits);
   if (!dispatch(v, gg, tm, grid, s)) return fail(TT_EINVAL, "internal: gemm type combination");
   TTR_HIP(hipGetLastError());
-  if (gg.splits > 1 && !g.defer_reduce) {
+  if (gg.splits > 1) {
     const int64_t total = g.M * g.N;
-    const dim3 gr((unsigned)((total + 255) / 256)), bl(256);
+    const dim3 gr((unsigned)((total + kRedElems - 1) / kRedElems)), bl(256);
     if (g.math == DType::F64) {
       if (g.tc == DType::F64)
         hipLaunchKernelGGL((splitk_reduce_kernel<double, double>), gr, bl, 0, s, gg);
@@ -434,10 +715,7 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
 
 int gemm_variant_count() { return 4; }
 
-void gemm_variant_tile(int v, int64_t *bm, int64_t *bn) {
-  *bm = 16 * kVariants[v].tm * kVariants[v].wm;
-  *bn = 16 * kVariants[v].tn * kVariants[v].wn;
-}
+void gemm_variant_tile(DType math, int v, int64_t *bm, int64_t *bn) { tile_of(math, v, bm, bn); }
 
 int gemm_group_splits(const GemmX &g) {
   // bound the K range of one workgroup (~512) so that long contractions of
@@ -451,7 +729,7 @@ int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e) 
   if (g.K <= 0) return fail(TT_EINVAL, "grouped gemm with K <= 0");
   if (g.batch > 1) return fail(TT_EINVAL, "grouped gemm entries are single products");
   int64_t bm, bn;
-  gemm_variant_tile(v, &bm, &bn);
+  gemm_variant_tile(g.math, v, &bm, &bn);
   e->g = g;
   e->tiles_m = (g.M + bm - 1) / bm;
   e->tiles_n = (g.N + bn - 1) / bn;
@@ -465,6 +743,7 @@ int gemm_group_fill(const GemmX &g, int v, int64_t wg_begin, GemmGroupEntry *e) 
     e->g.splits = 1;
     e->g.partial = nullptr;
   }
+  if (e->g.splits > kRedMaxGroups * kSplitGroup) return fail(TT_EINVAL, "internal: too many K splits");
   e->wg_begin = wg_begin;
   return TT_OK;
 }
@@ -474,7 +753,7 @@ int64_t gemm_group_wgs(const GemmGroupEntry &e) { return e.tiles_m * e.tiles_n *
 int gemm_group_reduce(const GemmX &rep, const GemmGroupEntry *d_tab, int count, int64_t max_mn,
                       hipStream_t s) {
   if (count <= 0 || max_mn <= 0) return TT_OK;
-  const dim3 gr((unsigned)((max_mn + 255) / 256), (unsigned)count), bl(256);
+  const dim3 gr((unsigned)((max_mn + kRedElems - 1) / kRedElems), (unsigned)count), bl(256);
   if (rep.math == DType::F64) {
     if (rep.tc == DType::F64)
       hipLaunchKernelGGL((splitk_group_reduce_kernel<double, double>), gr, bl, 0, s, d_tab);

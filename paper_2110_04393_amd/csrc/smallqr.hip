@@ -14,6 +14,7 @@
 // sign-normalised afterwards so that diag(R) >= 0 (zero counts as +).
 #include "fastmath.h"
 #include "tt_internal.h"
+#include "wave.h"
 
 namespace ttr {
 namespace {
@@ -23,246 +24,111 @@ int g_qr_mode = 0;  // 0 auto, 1 householder, 2 cholqr2
 // Upper Cholesky G = R^T R of the n x n FP64 matrix G (row-major,
 // n <= NMAX), then Rinv = R^{-1} (upper triangular, row-major; with FP32
 // storage also rounded to Rinv_f), by one workgroup of four wavefronts.
-// With nsplit > 0, G is the sum (in index order) of nsplit split-K partial
-// products part[p n^2 + e], so the Gram GEMM needs no reduction kernel.
 //
-// Lane c owns column c (and c + 64 when NMAX > 64); wavefront w owns the
-// row block [w NMAX/4, (w+1) NMAX/4) of those columns, in registers.  Both
-// factorisations are blocked by these row blocks:
-// * Cholesky, block J = 0..3: wavefront J factorises its (already updated)
-//   rows one pivot at a time, broadcasting values across its lanes with
-//   readlane (no LDS, no barrier):
-//     R[j][c] = A[j][c] / sqrt(d_j),  A[i][c] -= A[j][i] A[j][c] / d_j  (i in block J, i > j),
-//   publishes the block rows of R to LDS, and after one barrier the
-//   wavefronts below apply the block's rank-NMAX/4 update
-//     A[i][c] -= sum_{j in J} R[j][i] R[j][c].
-// * Inverse, block J = 3..0, right-looking on B = I:
-//     X[j] = B[j] / R[j][j] (row j of R^{-1}),  B[i] -= R[i][j] X[j]  (i < j),
-//   inside block J by its wavefront alone, then the block rows of X are
-//   published and the wavefronts above subtract their contribution.
-// Every loop is unrolled so that register indices are compile-time
-// constants.  A pivot d_j that is not finite or not above 1e-14 of the
-// original diagonal entry raises the flag (or_flag = 0: flag overwritten,
-// else or-ed) and is replaced by the original diagonal (1 if that is not
-// positive) so that the results stay finite.
+// Right-looking elimination on the augmented rows [G | I]: step j scales row
+// j by 1/sqrt(d_j) (d_j its current diagonal entry), which makes its left
+// part row j of R, and subtracts R[j][i] times it from every row i > j.  The
+// left block ends as R and the right block as R^{-T} (the same row
+// operations turn G into R = R^{-T} G), so Rinv is the transpose of the right
+// block.  Row i = 16 a + ty lives in wavefront a % 4, spread over the lane
+// quad 4 ty .. 4 ty + 3 (lane tq holds augmented columns tq + 4 b), so the
+// quad owning row j scales it alone and publishes it through LDS: one
+// barrier per step.  Steps are unrolled at compile time, and only the
+// columns still live at step j (left j..n-1, right 0..j) are touched.
+//
+// A pivot d_j that is not finite or not above 1e-14 of the original diagonal
+// entry raises the flag (or_flag = 0: flag overwritten, else or-ed) and is
+// replaced by the original diagonal (1 if that is not positive) so that the
+// results stay finite.
 constexpr int kCholThreads = 256;
 
-__device__ __forceinline__ double lane_bcast(double v, int l) {
-  const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 template <int NMAX>
-__device__ __forceinline__ void chol_inv_kernel_body(const double *G, const double *part,
-                                                                int nsplit, double *Rinv,
-                                                                float *Rinv_f, int n, int *flag,
-                                                                int or_flag) {
-  constexpr int NC = (NMAX + 63) / 64;  // column slots per lane
-  constexpr int RW = NMAX / 4;          // rows per wavefront (one block)
-  static_assert(NMAX % 4 == 0, "rows split over four wavefronts");
-  extern __shared__ double s_R[];       // NMAX x NMAX: G staging, then strict upper R
-  __shared__ double s_X[RW * NC * 64];  // published block rows of R^{-1}
+__device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Rinv,
+                                                     float *Rinv_f, int n, int *flag,
+                                                     int or_flag) {
+  constexpr int NB = NMAX / 2;      // augmented column slots per lane (2 NMAX columns)
+  constexpr int NBL = NMAX / 4;     // slots of the left block
+  constexpr int NA = NMAX / 16;     // row blocks
+  constexpr int NS = (NA + 3) / 4;  // row slots per lane
+  static_assert(NMAX % 16 == 0, "rows in blocks of 16");
+  __shared__ double s_row[2][2 * NMAX];  // augmented column c at (c % 4) NB + c / 4
   __shared__ double s_d0[NMAX];
-  __shared__ double s_rdi[NMAX];        // 1 / R[j][j]
   __shared__ int s_bad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t nn = (int64_t)n * n;
-  // G (summing the split-K partials in index order) staged through LDS;
-  // 16 elements per thread, two partials per round: 32 loads in flight
-  if (tid == 0) s_bad = 0;
-  for (int e0 = tid; e0 < n * n; e0 += 16 * kCholThreads) {
-    double v[16];
+  const int ty = lane >> 2, tq = lane & 3;
+
+  double X[NS][NB];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = 0.0;
-    if (nsplit > 0) {
-      int p = 0;
-      for (; p + 1 < nsplit; p += 2) {
-        double w0[16], w1[16];
+  for (int sl = 0; sl < NS; ++sl) {
+    const int i = 16 * (wave + 4 * sl) + ty;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int e = min(e0 + k * kCholThreads, n * n - 1);
-          w0[k] = part[p * nn + e];
-          w1[k] = part[(p + 1) * nn + e];
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = (v[k] + w0[k]) + w1[k];
+    for (int b = 0; b < NB; ++b) {
+      const int c = tq + 4 * b;
+      double v = 0.0;
+      if (b < NBL) {
+        if (i < n && c < n) v = (i >= c) ? G[i * n + c] : G[c * n + i];
+      } else {
+        v = (c - NMAX == i) ? 1.0 : 0.0;
       }
-      if (p < nsplit) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] += part[p * nn + min(e0 + k * kCholThreads, n * n - 1)];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = G[min(e0 + k * kCholThreads, n * n - 1)];
+      X[sl][b] = v;
     }
+  }
+  for (int i = tid; i < n; i += kCholThreads) s_d0[i] = G[i * n + i];
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  int bad = 0;
+
+  static_for<0, NMAX>([&](auto jc) __attribute__((always_inline)) {
+    constexpr int j = decltype(jc)::value;
+    if (j >= n) return;
+    constexpr int buf = j & 1;
+    constexpr int js = (j / 16) / 4, jw = (j / 16) % 4;
+    constexpr int blo = j / 4, bhi = NBL + j / 4;  // live slots: [blo, NBL) and [NBL, bhi]
+    if (wave == jw && ty == j % 16) {
+      double d = quad_bcast<j % 4>(X[js][j / 4]);
+      const double d0 = s_d0[j];
+      if (!(d > 1e-14 * d0) || !(d0 > 0.0) || !isfinite(d)) {
+        d = (d0 > 0.0 && isfinite(d0)) ? d0 : 1.0;
+        bad = 1;
+      }
+      const double r = rsq_f64(d);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = e0 + k * kCholThreads;
-      if (e < n * n) s_R[e] = v[k];
+      for (int b = blo; b <= bhi; ++b) {
+        const int c = tq + 4 * b;
+        double x = X[js][b] * r;
+        if (b < NBL && c == j) x = d * r;  // R[j][j] = sqrt(d)
+        if (b < NBL && c < j) x = 0.0;
+        X[js][b] = x;
+        s_row[buf][tq * NB + b] = x;
+      }
+    }
+    __syncthreads();
+    static_for<0, NS>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int sl = decltype(sc)::value;
+      if (16 * (wave + 4 * sl) + 15 > j && 16 * (wave + 4 * sl) < NMAX) {
+        const int i = 16 * (wave + 4 * sl) + ty;
+        const double f = (i > j) ? s_row[buf][(i & 3) * NB + (i >> 2)] : 0.0;  // R[j][i]
+#pragma unroll
+        for (int b = blo; b <= bhi; ++b) X[sl][b] = fma(-f, s_row[buf][tq * NB + b], X[sl][b]);
+      }
+    });
+  });
+  if (bad) s_bad = 1;
+  // Rinv[c][i] = B[i][c] (right block, lower triangular)
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int i = 16 * (wave + 4 * sl) + ty;
+#pragma unroll
+    for (int b = NBL; b < NB; ++b) {
+      const int c = tq + 4 * b - NMAX;
+      if (i < n && c < n) {
+        const double x = (c <= i) ? X[sl][b] : 0.0;
+        Rinv[(int64_t)c * n + i] = x;
+        if (Rinv_f) Rinv_f[(int64_t)c * n + i] = (float)x;
+      }
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += kCholThreads) s_d0[i] = s_R[i * n + i];
-  double a[NC][RW];
-#pragma unroll
-  for (int sl = 0; sl < NC; ++sl) {
-    const int col = lane + 64 * sl;
-    const int cc = min(col, n - 1);
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int i = RW * wave + r;
-      const double v = s_R[min(i, n - 1) * n + cc];
-      a[sl][r] = (i < n && col < n) ? v : 0.0;
-    }
-  }
-  __syncthreads();  // staging reads done before R overwrites it; s_d0 ready
-  // ---- Cholesky
-#pragma unroll
-  for (int J = 0; J < 4; ++J) {
-    if (RW * J < n) {
-      if (wave == J) {
-        int bad = 0;
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          const int j = RW * J + r;
-          if (j < n) {
-            double d = lane_bcast(a[j / 64][r], j % 64);
-            const double d0 = s_d0[j];
-            if (!(d > 1e-14 * d0) || !(d0 > 0.0) || !isfinite(d)) {
-              d = (d0 > 0.0 && isfinite(d0)) ? d0 : 1.0;
-              bad = 1;
-            }
-            const double inv_r = rsq_f64(d);
-            const double inv_d = inv_r * inv_r;
-            double rv[NC], f[NC];
-#pragma unroll
-            for (int sl = 0; sl < NC; ++sl) {
-              const int col = lane + 64 * sl;
-              rv[sl] = a[sl][r];
-              f[sl] = (col > j) ? rv[sl] * inv_d : 0.0;
-              a[sl][r] = (col == j) ? d * inv_r : ((col > j) ? rv[sl] * inv_r : 0.0);
-            }
-#pragma unroll
-            for (int r2 = 0; r2 < RW; ++r2) {
-              if (r2 > r) {
-                const int i = RW * J + r2;
-                const double c = lane_bcast(rv[i / 64], i % 64);  // A[j][i]
-#pragma unroll
-                for (int sl = 0; sl < NC; ++sl) a[sl][r2] -= c * f[sl];
-              }
-            }
-            if (lane == 0) s_rdi[j] = inv_r;
-          }
-        }
-        if (bad && lane == 0) s_bad = 1;
-        // block rows of R, strictly upper part
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          const int j = RW * J + r;
-#pragma unroll
-          for (int sl = 0; sl < NC; ++sl) {
-            const int col = lane + 64 * sl;
-            if (col < NMAX) s_R[j * NMAX + col] = (col > j) ? a[sl][r] : 0.0;
-          }
-        }
-      }
-      __syncthreads();
-      if (wave > J) {
-        // A[i][c] -= sum_{j in J} R[j][i] R[j][c]; R[j][i] read per lane and
-        // broadcast with readlane
-        double rjc[RW][NC], rji[RW];
-#pragma unroll
-        for (int jj = 0; jj < RW; ++jj) {
-          const int j = RW * J + jj;
-#pragma unroll
-          for (int sl = 0; sl < NC; ++sl) rjc[jj][sl] = s_R[j * NMAX + min(lane + 64 * sl, NMAX - 1)];
-          rji[jj] = s_R[j * NMAX + RW * wave + (lane % RW)];
-        }
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-#pragma unroll
-          for (int jj = 0; jj < RW; ++jj) {
-            const double c = lane_bcast(rji[jj], r);  // R[j][RW wave + r]
-#pragma unroll
-            for (int sl = 0; sl < NC; ++sl) a[sl][r] -= c * rjc[jj][sl];
-          }
-        }
-      }
-    }
-  }
-  // ---- inverse: rows of B = I held like A's
-#pragma unroll
-  for (int sl = 0; sl < NC; ++sl)
-#pragma unroll
-    for (int r = 0; r < RW; ++r) a[sl][r] = (RW * wave + r == lane + 64 * sl) ? 1.0 : 0.0;
-  __syncthreads();  // R and 1/R[j][j] complete
-#pragma unroll
-  for (int J = 3; J >= 0; --J) {
-    if (RW * J < n) {
-      if (wave == J) {
-#pragma unroll
-        for (int r = RW - 1; r >= 0; --r) {
-          const int j = RW * J + r;
-          if (j < n) {
-            const double inv = s_rdi[j];
-            double x[NC];
-#pragma unroll
-            for (int sl = 0; sl < NC; ++sl) {
-              x[sl] = a[sl][r] * inv;
-              a[sl][r] = x[sl];
-            }
-#pragma unroll
-            for (int r2 = 0; r2 < RW; ++r2) {
-              if (r2 < r) {
-                const double rij = s_R[(RW * J + r2) * NMAX + j];  // R[i][j]
-#pragma unroll
-                for (int sl = 0; sl < NC; ++sl) a[sl][r2] -= rij * x[sl];
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < RW; ++r)
-#pragma unroll
-          for (int sl = 0; sl < NC; ++sl) s_X[r * (NC * 64) + lane + 64 * sl] = a[sl][r];
-      }
-      __syncthreads();
-      if (wave < J) {
-        // B[i][c] -= sum_{j in J} R[i][j] X[j][c]
-        double xj[RW][NC];
-#pragma unroll
-        for (int jj = 0; jj < RW; ++jj)
-#pragma unroll
-          for (int sl = 0; sl < NC; ++sl) xj[jj][sl] = s_X[jj * (NC * 64) + lane + 64 * sl];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          const double *rrow = s_R + (RW * wave + r) * NMAX + RW * J;
-#pragma unroll
-          for (int jj = 0; jj < RW; ++jj) {
-            const double rij = rrow[jj];
-#pragma unroll
-            for (int sl = 0; sl < NC; ++sl) a[sl][r] -= rij * xj[jj][sl];
-          }
-        }
-      }
-      __syncthreads();  // s_X is rewritten by the next block
-    }
-  }
-#pragma unroll
-  for (int sl = 0; sl < NC; ++sl) {
-    const int col = lane + 64 * sl;
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int i = RW * wave + r;
-      if (i < n && col < n) {
-        const double x = (i <= col) ? a[sl][r] : 0.0;
-        Rinv[(int64_t)i * n + col] = x;
-        if (Rinv_f) Rinv_f[(int64_t)i * n + col] = (float)x;
-      }
-    }
-  }
   if (tid == 0) {
     if (or_flag) {
       if (s_bad) *flag = 1;
@@ -273,11 +139,10 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, const doub
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double *G, const double *part,
-                                                                int nsplit, double *Rinv,
+__global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_inv_kernel(const double *G, double *Rinv,
                                                                 float *Rinv_f, int n, int *flag,
                                                                 int or_flag) {
-  chol_inv_kernel_body<NMAX>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag);
+  chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, or_flag);
 }
 
 // One workgroup Householder QR of the m x n row-major Y into Q (m x n), with
@@ -401,9 +266,9 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T *Y, T *
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kCholThreads) void chol_group_kernel(const CholGroupDesc *tab) {
+__global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_group_kernel(const CholGroupDesc *tab) {
   const CholGroupDesc &e = tab[blockIdx.x];
-  chol_inv_kernel_body<NMAX>(e.G, nullptr, 0, e.Rinv, e.Rinv_f, e.n, e.flag, e.or_flag);
+  chol_inv_kernel_body<NMAX>(e.G, e.Rinv, e.Rinv_f, e.n, e.flag, e.or_flag);
 }
 
 template <typename T>
@@ -419,39 +284,31 @@ __global__ __launch_bounds__(kHhThreads) void householder_group_kernel(const HhG
 void qr_set_mode(int mode) { g_qr_mode = mode; }
 
 size_t qr_partial_elems(int64_t m, int64_t n) {
-  const int sp = gemm_pick_splits(n, n, m);
+  const int sp = gemm_pick_splits(n, n, m, DType::F64);
   return sp > 1 ? (size_t)sp * n * n : 0;
 }
 
 template <int NMAX>
-static int chol_inv_launch(const double *G, const double *part, int nsplit, double *Rinv,
-                           float *Rinv_f, int n, int *flag, int or_flag, hipStream_t s) {
-  const size_t lds = sizeof(double) * NMAX * NMAX;
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)chol_inv_kernel<NMAX>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((chol_inv_kernel<NMAX>), dim3(1), dim3(kCholThreads), lds, s, G, part, nsplit, Rinv,
-                     Rinv_f, n, flag, or_flag);
+static int chol_inv_launch(const double *G, double *Rinv, float *Rinv_f, int n, int *flag,
+                           int or_flag, hipStream_t s) {
+  hipLaunchKernelGGL((chol_inv_kernel<NMAX>), dim3(1), dim3(kCholThreads), 0, s, G, Rinv, Rinv_f,
+                     n, flag, or_flag);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 
-// Cholesky + inverse of the n x n Gram (n <= TT_MAX_SKETCH_RANK); nsplit > 0:
-// the Gram is the sum of nsplit split-K partials in `part`.
-static int chol_inv(const double *G, const double *part, int nsplit, double *Rinv, float *Rinv_f,
-                    int n, int *flag, int or_flag, hipStream_t s) {
-  if (n <= 32) return chol_inv_launch<32>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag, s);
-  if (n <= 64) return chol_inv_launch<64>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag, s);
-  if (n <= 96) return chol_inv_launch<96>(G, part, nsplit, Rinv, Rinv_f, n, flag, or_flag, s);
+// Cholesky + inverse of the n x n Gram (n <= TT_MAX_SKETCH_RANK)
+static int chol_inv(const double *G, double *Rinv, float *Rinv_f, int n, int *flag, int or_flag,
+                    hipStream_t s) {
+  if (n <= 32) return chol_inv_launch<32>(G, Rinv, Rinv_f, n, flag, or_flag, s);
+  if (n <= 64) return chol_inv_launch<64>(G, Rinv, Rinv_f, n, flag, or_flag, s);
+  if (n <= 96) return chol_inv_launch<96>(G, Rinv, Rinv_f, n, flag, or_flag, s);
   return fail(TT_EUNSUPPORTED, "Cholesky of a Gram matrix wider than 96");
 }
 
 int chol_inverse(const double *G, int64_t n, double *Rinv, float *Rinv_f, int *flag,
                  hipStream_t s) {
-  return chol_inv(G, nullptr, 0, Rinv, Rinv_f, (int)n, flag, 0, s);
+  return chol_inv(G, Rinv, Rinv_f, (int)n, flag, 0, s);
 }
 
 constexpr int64_t kHhLdsElems = 10000;  // 2 * m * n doubles must fit in LDS
@@ -506,13 +363,10 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     g.M = n;
     g.N = n;
     g.K = m;
-    g.splits = gemm_pick_splits(n, n, m);
+    g.splits = gemm_pick_splits(n, n, m, DType::F64);
     g.partial = ws.partial;
-    g.defer_reduce = true;  // the Cholesky kernel sums the partials
     TTR_TRY(gemmx_run(g, s));
-    const int nsp = gemm_used_splits(g);
-    TTR_TRY(chol_inv(ws.gram, (const double *)ws.partial, nsp > 1 ? nsp : 0, ws.rinv,
-                     f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
+    TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
     Gemm<T> h;  // dst = src Rinv, in the storage precision
     h.A = src;
     h.lda = n;
@@ -538,14 +392,7 @@ template int qr_thin<float>(const float *, float *, int64_t, int64_t, QrScratch 
 
 template <int NMAX>
 static int chol_group_launch(const CholGroupDesc *d_tab, int count, hipStream_t s) {
-  const size_t lds = sizeof(double) * NMAX * NMAX;
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)chol_group_kernel<NMAX>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((chol_group_kernel<NMAX>), dim3(count), dim3(kCholThreads), lds, s, d_tab);
+  hipLaunchKernelGGL((chol_group_kernel<NMAX>), dim3(count), dim3(kCholThreads), 0, s, d_tab);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }

@@ -31,6 +31,7 @@
 // always enqueued after this one and return at once unless the flag is set.
 #include "fastmath.h"
 #include "tt_internal.h"
+#include "wave.h"
 
 namespace ttr {
 namespace {
@@ -39,14 +40,6 @@ constexpr int kTeThreads = 1024;
 constexpr int kTeNMax = 76;
 
 // ---------------------------------------------------------------- DPP
-template <int CTRL>
-__device__ __forceinline__ double dppd(double v) {
-  const long long x = __double_as_longlong(v);
-  int lo = (int)(x & 0xffffffffll), hi = (int)(x >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 // quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
 // row_half_mirror = 0x141, row_mirror = 0x140
 __device__ __forceinline__ double sum8(double v) {
@@ -177,143 +170,163 @@ __device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const dou
 }
 
 // ---------------------------------------------------------------- kernel 1
-// Householder tridiagonalisation of the n x n symmetric Gin (one workgroup,
-// 256 threads): writes the scaled d (n), e (n-1) with ||T|| sc <= 1, the scale
-// sc, and the reflectors (Vr row j = v_j over rows j+1..n-1, v_j[0] = 1;
-// taus[j]) to global scratch.  Only the lower triangle of A22 is updated.
+// Householder tridiagonalisation of the n x n symmetric Gin (n <= NMAX, one
+// workgroup of four wavefronts, the matrix in registers).  Row i = 16 a + ty
+// belongs to wavefront a % 4 and is spread over the lane quad 4 ty .. 4 ty + 3:
+// lane tq holds the columns c = tq + 4 b.  The matrix is kept exactly
+// symmetric (the rank-2 update rounds both products before adding them), so
+// column j of step j is row j and the quad owning it builds the reflector
+// alone; p = tau A v is a quad reduction within the owners of each row.  Per
+// column the wavefronts exchange v, then p and the partial sums of p^T v,
+// through LDS: two barriers.  Writes the scaled d (n), e (n-1) with
+// ||T|| sc <= 1, the scale sc, and the reflectors (Vr row j = v_j over rows
+// j+1..n-1, v_j[0] = 1; taus[j]) to global scratch.
 constexpr int kTrThreads = 256;
 
-__device__ __forceinline__ void tri_reduce_kernel_body(const double *Gin, int n,
-                                                                double *d_out, double *e_out,
-                                                                double *sc_out, double *Vr,
-                                                                double *taus, int *flag) {
-  extern __shared__ double lds[];
-  const int ld = n | 1;
-  double *A = lds;  // n x ld, lower triangle meaningful
-  __shared__ double s_v[2][kTeNMax], s_p[kTeNMax], s_w[kTeNMax];
-  __shared__ double s_d[kTeNMax], s_e[kTeNMax];
-  __shared__ double s_tau[2];
+// a - (vi wc + wi vc) with both products rounded: the same bits for (i, c)
+// and (c, i)
+__device__ __forceinline__ double sym_update(double a, double vi, double wc, double wi,
+                                             double vc) {
+#pragma clang fp contract(off)
+  return a - (vi * wc + wi * vc);
+}
+
+template <int NMAX>
+__device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double *d_out,
+                                                double *e_out, double *sc_out, double *Vr,
+                                                double *taus, int *flag) {
+  constexpr int NB = NMAX / 4;       // column slots per lane
+  constexpr int NA = NMAX / 16;      // row blocks
+  constexpr int NS = (NA + 3) / 4;   // row slots per lane
+  __shared__ double s_v[2][NMAX], s_p[2][NMAX];  // entry c at (c % 4) NB + c / 4
+  __shared__ double s_q[2][4], s_tau[2];
+  __shared__ double s_d[NMAX], s_e[NMAX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ty = lane >> 2, tq = lane & 3;
 
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e - i * n;
-    if (j <= i) A[i * ld + j] = Gin[e];
-  }
-  __syncthreads();
-
-  auto reflector = [&](double x0, double x1, int m, int buf, int j) {
-    const double a0 = readlane_d(x0, 0);
-    double sq = 0.0;
-    if (lane >= 1 && lane < m) sq += x0 * x0;
-    if (lane + 64 < m) sq += x1 * x1;
-    const double sigma = wave_sum(sq);
-    double beta, tau, scale;
-    if (sigma == 0.0) {
-      beta = a0;
-      tau = 0.0;
-      scale = 0.0;
-    } else {
-      const double mu = sqrt_f64(fma(a0, a0, sigma));
-      beta = (a0 >= 0.0) ? -mu : mu;
-      tau = (beta - a0) * rcp_f64(beta);
-      scale = rcp_f64(a0 - beta);
-    }
-    const double v0 = (lane == 0) ? 1.0 : x0 * scale, v1 = x1 * scale;
-    if (lane < m) {
-      s_v[buf][lane] = v0;
-      Vr[j * n + lane] = v0;
-    }
-    if (lane + 64 < m) {
-      s_v[buf][lane + 64] = v1;
-      Vr[j * n + lane + 64] = v1;
-    }
-    if (lane == 0) {
-      s_tau[buf] = tau;
-      s_e[j] = beta;
-      taus[j] = tau;
-    }
-  };
-
-  if (n == 1) {
-    if (tid == 0) s_d[0] = A[0];
-  } else if (n == 2) {
-    if (tid == 0) {
-      s_d[0] = A[0];
-      s_e[0] = A[ld];
-      s_d[1] = A[ld + 1];
-    }
-  } else {
-    if (wave == 0) {
-      const int m = n - 1;
-      const double x0 = (lane < m) ? A[(1 + lane) * ld] : 0.0;
-      const double x1 = (lane + 64 < m) ? A[(65 + lane) * ld] : 0.0;
-      reflector(x0, x1, m, 0, 0);
-      if (lane == 0) s_d[0] = A[0];
-    }
-    __syncthreads();
-    for (int j = 0; j <= n - 3; ++j) {
-      const int m = n - j - 1, cur = j & 1;
-      const double *v = s_v[cur];
-      const double tau = s_tau[cur];
-      const int base = j + 1;
-      // phase b: p = tau A22 v, 4 lanes per row (quad), lane q covers c = q, q+4, ...
-      for (int r0 = 0; r0 < m; r0 += kTrThreads / 4) {
-        const int r = r0 + (tid >> 2), qd = tid & 3;
-        double acc = 0.0;
-        if (r < m) {
-          const double *arow = A + (base + r) * ld + base;
-          for (int c = qd; c <= r; c += 4) acc = fma(arow[c], v[c], acc);
-          for (int c = r + 1 + ((qd - (r + 1)) & 3); c < m; c += 4)
-            acc = fma(A[(base + c) * ld + base + r], v[c], acc);
-        }
-        acc += dppd<0xB1>(acc);
-        acc += dppd<0x4E>(acc);
-        if (qd == 0 && r < m) s_p[r] = tau * acc;
-      }
-      __syncthreads();
-      // phase d: K = tau/2 p^T v, w = p - K v (wave 0 writes w and builds the
-      // next reflector from the updated column; the others update A22's
-      // lower triangle on local rows/columns >= 1 once w is there)
-      double pv = 0.0;
-      if (lane < m) pv = s_p[lane] * v[lane];
-      if (lane + 64 < m) pv = fma(s_p[lane + 64], v[lane + 64], pv);
-      const double K = 0.5 * tau * wave_sum(pv);
-      for (int c = tid; c < m; c += blockDim.x) s_w[c] = s_p[c] - K * v[c];
-      if (wave == 0) {
-        const double w0 = s_p[0] - K * v[0];
-        const double dnew = A[base * ld + base] - 2.0 * v[0] * w0;
-        double x0 = 0.0, x1 = 0.0;
-        const int r0 = lane + 1, r1 = lane + 65;
-        if (r0 < m) x0 = A[(base + r0) * ld + base] - v[r0] * w0 - (s_p[r0] - K * v[r0]) * v[0];
-        if (r1 < m) x1 = A[(base + r1) * ld + base] - v[r1] * w0 - (s_p[r1] - K * v[r1]) * v[0];
-        if (lane == 0) s_d[base] = dnew;
-        if (j + 1 <= n - 3) {
-          reflector(x0, x1, m - 1, cur ^ 1, j + 1);
-        } else if (lane == 0) {
-          s_e[n - 2] = x0;
-        }
-      }
-      __syncthreads();
-      // lower triangle, rows r = 1.. (thread per row segment of 8 columns)
-      {
-        const int segs = (m + 7) >> 3;
-        for (int t = tid; t < (m - 1) * segs; t += blockDim.x) {
-          const int r = 1 + t / segs, c0 = (t - (t / segs) * segs) * 8;
-          if (c0 > r) continue;
-          const double vr = v[r], wr = s_w[r];
-          double *arow = A + (base + r) * ld + base;
+  double A[NS][NB];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int c = c0 + u;
-            if (c >= 1 && c <= r) arow[c] = arow[c] - vr * s_w[c] - wr * v[c];
-          }
+  for (int sl = 0; sl < NS; ++sl) {
+    const int i = 16 * (wave + 4 * sl) + ty;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int c = tq + 4 * b;
+      A[sl][b] = (i < n && c < n) ? (i >= c ? Gin[i * n + c] : Gin[c * n + i]) : 0.0;
+    }
+  }
+  if (n <= 2) {
+    if (tid == 0) {
+      s_d[0] = Gin[0];
+      if (n == 2) {
+        s_e[0] = Gin[n];
+        s_d[1] = Gin[n + 1];
+      }
+    }
+  }
+  static_for<0, NMAX - 2>([&](auto jc) __attribute__((always_inline)) {
+    constexpr int j = decltype(jc)::value;
+    if (j > n - 3) return;
+    constexpr int buf = j & 1;
+    constexpr int js = (j / 16) / 4, jw = (j / 16) % 4;
+    // ---- phase 1: the quad owning row j (= column j) builds the reflector
+    if (wave == jw && ty == j % 16) {
+      double sq = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (4 * b + 3 >= j + 2) {
+          const int c = tq + 4 * b;
+          if (c >= j + 2) sq = fma(A[js][b], A[js][b], sq);
         }
       }
-      __syncthreads();
+      const double sigma = quad_sum(sq);
+      const double a0 = quad_bcast<(j + 1) % 4>(A[js][(j + 1) / 4]);
+      const double djj = quad_bcast<j % 4>(A[js][j / 4]);
+      double beta, tau, scale;
+      if (sigma == 0.0) {
+        beta = a0;
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        const double mu = sqrt_f64(fma(a0, a0, sigma));
+        beta = (a0 >= 0.0) ? -mu : mu;
+        tau = (beta - a0) * rcp_f64(beta);
+        scale = rcp_f64(a0 - beta);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int c = tq + 4 * b;
+        const double v = (c == j + 1) ? 1.0 : ((c > j + 1) ? A[js][b] * scale : 0.0);
+        s_v[buf][tq * NB + b] = v;
+        if (c > j && c < n) Vr[j * n + c - j - 1] = v;
+      }
+      if (tq == 0) {
+        s_tau[buf] = tau;
+        taus[j] = tau;
+        s_e[j] = beta;
+        s_d[j] = djj;
+      }
     }
-    if (tid == 0) s_d[n - 1] = A[(n - 1) * ld + (n - 1)];
     __syncthreads();
-  }
+    // ---- phase 2: p = tau A v (rows of this lane quad), partial p^T v
+    const double tau = s_tau[buf];
+    double vc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) vc[b] = s_v[buf][tq * NB + b];
+    double vr[NS], pr[NS];
+    double qpart = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int i = 16 * (wave + 4 * sl) + ty;
+      vr[sl] = 0.0;
+      pr[sl] = 0.0;
+      if (16 * (wave + 4 * sl) + 15 > j && 16 * (wave + 4 * sl) < NMAX) {
+        vr[sl] = s_v[buf][(i & 3) * NB + (i >> 2)];
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (4 * b + 3 > j) acc = fma(A[sl][b], vc[b], acc);
+        pr[sl] = tau * quad_sum(acc);
+        if (tq == 0) {
+          s_p[buf][(i & 3) * NB + (i >> 2)] = pr[sl];
+          qpart = fma(pr[sl], vr[sl], qpart);
+        }
+      }
+    }
+    const double qw = wave_sum(qpart);
+    if (lane == 0) s_q[buf][wave] = qw;
+    __syncthreads();
+    // ---- phase 3: w = p - K v, A -= v w^T + w v^T on the live part
+    const double K = 0.5 * tau * ((s_q[buf][0] + s_q[buf][1]) + (s_q[buf][2] + s_q[buf][3]));
+    double wc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) wc[b] = (4 * b + 3 > j) ? s_p[buf][tq * NB + b] - K * vc[b] : 0.0;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      if (16 * (wave + 4 * sl) + 15 > j && 16 * (wave + 4 * sl) < NMAX) {
+        const double wr = pr[sl] - K * vr[sl];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (4 * b + 3 > j) A[sl][b] = sym_update(A[sl][b], vr[sl], wc[b], wr, vc[b]);
+      }
+    }
+    if (j == n - 3) {
+      // the trailing 2 x 2 block: rows j+1 and j+2
+      constexpr int r1 = j + 1, r2 = j + 2;
+      if (wave == (r1 / 16) % 4 && ty == r1 % 16) {
+        const double dd = quad_bcast<(j + 1) % 4>(A[(r1 / 16) / 4][(j + 1) / 4]);
+        const double ee = quad_bcast<(j + 2) % 4>(A[(r1 / 16) / 4][(j + 2) / 4]);
+        if (tq == 0) {
+          s_d[r1] = dd;
+          s_e[r1] = ee;
+        }
+      }
+      if (wave == (r2 / 16) % 4 && ty == r2 % 16) {
+        const double dd = quad_bcast<(j + 2) % 4>(A[(r2 / 16) / 4][(j + 2) / 4]);
+        if (tq == 0) s_d[r2] = dd;
+      }
+    }
+  });
+  __syncthreads();
   if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < n; i += 64) {
@@ -333,11 +346,12 @@ __device__ __forceinline__ void tri_reduce_kernel_body(const double *Gin, int n,
   }
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gin, int n,
                                                                 double *d_out, double *e_out,
                                                                 double *sc_out, double *Vr,
                                                                 double *taus, int *flag) {
-  tri_reduce_kernel_body(Gin, n, d_out, e_out, sc_out, Vr, taus, flag);
+  tri_reduce_body<NMAX>(Gin, n, d_out, e_out, sc_out, Vr, taus, flag);
 }
 
 // ---------------------------------------------------------------- kernel 2
@@ -354,8 +368,10 @@ __device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const do
                                                      double *Uz, const int *flag, int w_block) {
   if (*flag) return;
   __shared__ double s_L[kTeNMax + 1], s_U[kTeNMax + 1], s_z[kTeNMax];
+  __shared__ double s_V[kTeNMax * kTeNMax];  // reflectors, staged once: s_V[j n + i - j - 1]
   const int lane = threadIdx.x;
   const int w = w_block;
+  for (int e = lane; e < (n - 2) * n; e += 64) s_V[e] = Vr[e];
   // the upper half-wave holds T reversed (same eigenvalues and Sturm counts;
   // its top-down factorisation is the bottom-up one of T)
   const bool rev = lane >= 32;
@@ -464,8 +480,8 @@ __device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const do
     const double tau = taus[j];
     // v_j over rows j+1..n-1; lane row i holds v = Vr[j][i - j - 1]
     const int i0 = lane, i1 = lane + 64;
-    const double v0 = (i0 > j && i0 < n) ? Vr[j * n + i0 - j - 1] : 0.0;
-    const double v1 = (i1 > j && i1 < n) ? Vr[j * n + i1 - j - 1] : 0.0;
+    const double v0 = (i0 > j && i0 < n) ? s_V[j * n + i0 - j - 1] : 0.0;
+    const double v1 = (i1 > j && i1 < n) ? s_V[j * n + i1 - j - 1] : 0.0;
     const double dot = wave_sum(v0 * z0 + v1 * z1);
     z0 = fma(-tau * dot, v0, z0);
     z1 = fma(-tau * dot, v1, z1);
@@ -562,9 +578,10 @@ __global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
   tri_finish_kernel_body<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, flag);
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(kTrThreads) void tri_reduce_group_kernel(const EigGroupDesc *tab) {
   const EigGroupDesc &e = tab[blockIdx.x];
-  tri_reduce_kernel_body(e.G, e.n, e.d, e.e, e.sc, e.Vr, e.taus, e.flag);
+  tri_reduce_body<NMAX>(e.G, e.n, e.d, e.e, e.sc, e.Vr, e.taus, e.flag);
 }
 
 __global__ __launch_bounds__(64) void tri_vec_group_kernel(const EigGroupDesc *tab) {
@@ -595,14 +612,16 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
     double *lamw = taus + n, *Uz = lamw + n + 1;
     static bool attr_set = false;
     if (!attr_set) {
-      TTR_HIP(hipFuncSetAttribute((const void *)tri_reduce_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
       TTR_HIP(hipFuncSetAttribute((const void *)tri_finish_kernel<T>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
       attr_set = true;
     }
-    hipLaunchKernelGGL(tri_reduce_kernel, dim3(1), dim3(kTrThreads),
-                       sizeof(double) * (size_t)n * ld, s, G, (int)n, d, e, sc, Vr, taus, flag);
+    if (n <= 64)
+      hipLaunchKernelGGL(tri_reduce_kernel<64>, dim3(1), dim3(kTrThreads), 0, s, G, (int)n, d, e,
+                         sc, Vr, taus, flag);
+    else
+      hipLaunchKernelGGL(tri_reduce_kernel<80>, dim3(1), dim3(kTrThreads), 0, s, G, (int)n, d, e,
+                         sc, Vr, taus, flag);
     TTR_HIP(hipGetLastError());
     hipLaunchKernelGGL(tri_vec_kernel, dim3(kw), dim3(64), 0, s, d, e, (int)n, (int)k, kw, Vr,
                        taus, lamw, Uz, flag);
@@ -661,14 +680,14 @@ int eig_trunc_group(const EigGroupDesc *d_tab, int count, int nmax, int kwmax, h
   const int ld = nmax | 1;
   static bool attr_set = false;
   if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)tri_reduce_group_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
     TTR_HIP(hipFuncSetAttribute((const void *)tri_finish_group_kernel<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
     attr_set = true;
   }
-  hipLaunchKernelGGL(tri_reduce_group_kernel, dim3(count), dim3(kTrThreads),
-                     sizeof(double) * (size_t)nmax * ld, s, d_tab);
+  if (nmax <= 64)
+    hipLaunchKernelGGL(tri_reduce_group_kernel<64>, dim3(count), dim3(kTrThreads), 0, s, d_tab);
+  else
+    hipLaunchKernelGGL(tri_reduce_group_kernel<80>, dim3(count), dim3(kTrThreads), 0, s, d_tab);
   TTR_HIP(hipGetLastError());
   hipLaunchKernelGGL(tri_vec_group_kernel, dim3(kwmax, count), dim3(64), 0, s, d_tab);
   TTR_HIP(hipGetLastError());

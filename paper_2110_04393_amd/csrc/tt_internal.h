@@ -98,9 +98,6 @@ struct GemmX {
   // elements per batch entry (split-K is not combined with batching)
   int64_t batch = 1;
   int64_t sA = 0, sB = 0, sC = 0;
-  // split-K only: leave the partials for the consumer (no reduction kernel,
-  // C untouched); gemm_used_splits() tells how many there are
-  bool defer_reduce = false;
 };
 
 // One entry of a grouped GEMM launch (device table): the product, its tile
@@ -111,7 +108,7 @@ struct GemmGroupEntry {
   int64_t wg_begin = 0;
 };
 int gemm_variant_count();
-void gemm_variant_tile(int v, int64_t *bm, int64_t *bn);
+void gemm_variant_tile(DType math, int v, int64_t *bm, int64_t *bn);
 // split count for a grouped product (entries carry g.splits and g.partial;
 // the partials of entries with splits > 1 are summed by gemm_group_reduce)
 int gemm_group_splits(const GemmX &g);
@@ -124,7 +121,7 @@ int64_t gemm_group_wgs(const GemmGroupEntry &e);
 int gemm_group_run(const GemmX &rep, int v, const GemmGroupEntry *d_tab, int count,
                    int64_t total_wgs, hipStream_t s);
 
-int gemm_pick_splits(int64_t M, int64_t N, int64_t K);
+int gemm_pick_splits(int64_t M, int64_t N, int64_t K, DType math);
 // number of split-K partials gemmx_run writes for g (1 = none, C written)
 int gemm_used_splits(const GemmX &g);
 size_t gemm_acc_bytes(DType math);
