@@ -198,8 +198,11 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
   constexpr int NB = NMAX / 4;       // column slots per lane
   constexpr int NA = NMAX / 16;      // row blocks
   constexpr int NS = (NA + 3) / 4;   // row slots per lane
-  __shared__ double s_v[2][NMAX], s_p[2][NMAX];  // entry c at (c % 4) NB + c / 4
-  __shared__ double s_q[2][4], s_tau[2];
+  // reflector j at s_V[j], p of step j at s_p[j & 1]; entry c at (c % 4) NB + c / 4.
+  // The reflectors, taus, d and e reach global memory only after the loop:
+  // a barrier waits for the workgroup's outstanding global stores.
+  __shared__ double s_V[NMAX][NMAX], s_p[2][NMAX];
+  __shared__ double s_q[2][4], s_tau[NMAX];
   __shared__ double s_d[NMAX], s_e[NMAX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ty = lane >> 2, tq = lane & 3;
@@ -255,23 +258,20 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int c = tq + 4 * b;
-        const double v = (c == j + 1) ? 1.0 : ((c > j + 1) ? A[js][b] * scale : 0.0);
-        s_v[buf][tq * NB + b] = v;
-        if (c > j && c < n) Vr[j * n + c - j - 1] = v;
+        s_V[j][tq * NB + b] = (c == j + 1) ? 1.0 : ((c > j + 1) ? A[js][b] * scale : 0.0);
       }
       if (tq == 0) {
-        s_tau[buf] = tau;
-        taus[j] = tau;
+        s_tau[j] = tau;
         s_e[j] = beta;
         s_d[j] = djj;
       }
     }
     __syncthreads();
     // ---- phase 2: p = tau A v (rows of this lane quad), partial p^T v
-    const double tau = s_tau[buf];
+    const double tau = s_tau[j];
     double vc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) vc[b] = s_v[buf][tq * NB + b];
+    for (int b = 0; b < NB; ++b) vc[b] = s_V[j][tq * NB + b];
     double vr[NS], pr[NS];
     double qpart = 0.0;
 #pragma unroll
@@ -280,7 +280,7 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
       vr[sl] = 0.0;
       pr[sl] = 0.0;
       if (16 * (wave + 4 * sl) + 15 > j && 16 * (wave + 4 * sl) < NMAX) {
-        vr[sl] = s_v[buf][(i & 3) * NB + (i >> 2)];
+        vr[sl] = s_V[j][(i & 3) * NB + (i >> 2)];
         double acc = 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -327,6 +327,12 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
     }
   });
   __syncthreads();
+  // reflectors (Vr row j = v_j over rows j+1..n-1) and taus
+  for (int e = tid; e < (n - 2) * n; e += kTrThreads) {
+    const int j = e / n, r = e - j * n, c = r + j + 1;
+    if (c < n) Vr[e] = s_V[j][(c & 3) * NB + (c >> 2)];
+  }
+  for (int j = tid; j < n - 2; j += kTrThreads) taus[j] = s_tau[j];
   if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < n; i += 64) {
@@ -355,59 +361,78 @@ __global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gi
 }
 
 // ---------------------------------------------------------------- kernel 2
-// One wavefront per wanted eigenvalue w (descending, w < kw).  T lives in
-// registers (d, e fully unrolled up to kTeNMax), 64-point multisection with
-// Sturm counts (9 iterations of a 65-fold shrink); for w < k the eigenvector:
-// twisted factorisation (lanes 0-31 run the top-down LDL^T, lanes 32-63 the
-// same recurrence on the reversed matrix, i.e. the bottom-up UDU^T), then the
-// Householder reflectors of kernel 1 applied backwards give u = Q z, written to
-// column w of U (n x k) unnormalised by sc.
-__device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const double *e_in, int n,
-                                                     int k, int kw, const double *Vr,
-                                                     const double *taus, double *lam_out,
-                                                     double *Uz, const int *flag, int w_block) {
+// One wavefront per wanted eigenvalue w (descending, w < kw).  T (n <= NMAX)
+// is staged in LDS and padded to NMAX with d = 4, e = 0: T is scaled to
+// ||T|| <= 1, so the padding only adds eigenvalues at 4, outside every
+// bracket, and every recurrence runs a fixed, unrolled number of steps
+// without branches.
+//  * eigenvalue: 64-point multisection of [-1, 1] (9 iterations of a 65-fold
+//    shrink); lane l counts the sign changes of the leading-minor
+//    determinants p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} at its point
+//    (a zero p_i takes the sign opposite to p_{i-1}), rescaled by a power of
+//    two every 8 steps;
+//  * for w < k the eigenvector: twisted factorisation (lanes 0-31 the
+//    top-down LDL^T, lanes 32-63 the same recurrence on the reversed matrix,
+//    i.e. the bottom-up UDU^T), twist r = argmin |gamma_r|, z from products
+//    of the factors (log-step scans), then the Householder reflectors of
+//    kernel 1 applied backwards give u = Q z, written to column w of U (n x k)
+//    unnormalised by sc.
+constexpr double kTiny = 1e-300;
+
+template <int NMAX>
+__device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e_in, int n, int k,
+                                             const double *Vr, const double *taus,
+                                             double *lam_out, double *Uz, const int *flag,
+                                             int w) {
   if (*flag) return;
-  __shared__ double s_L[kTeNMax + 1], s_U[kTeNMax + 1], s_z[kTeNMax];
-  __shared__ double s_V[kTeNMax * kTeNMax];  // reflectors, staged once: s_V[j n + i - j - 1]
+  __shared__ double s_d[NMAX + 1], s_e[NMAX + 1], s_e2[NMAX + 1];
+  __shared__ double s_L[NMAX + 1], s_U[NMAX + 1], s_z[NMAX];
+  __shared__ double s_V[NMAX * NMAX];  // reflectors: s_V[j n + i - j - 1]
+  __shared__ double s_tau[NMAX];
+  __shared__ double s_sc[2][2][128];   // scan buffers (lower, upper factors)
   const int lane = threadIdx.x;
-  const int w = w_block;
-  for (int e = lane; e < (n - 2) * n; e += 64) s_V[e] = Vr[e];
-  // the upper half-wave holds T reversed (same eigenvalues and Sturm counts;
-  // its top-down factorisation is the bottom-up one of T)
-  const bool rev = lane >= 32;
-  double d[kTeNMax], e[kTeNMax];
-#pragma unroll
-  for (int i = 0; i < kTeNMax; ++i) {
-    d[i] = (i < n) ? d_in[rev ? n - 1 - i : i] : 0.0;
-    e[i] = (i < n - 1) ? e_in[rev ? n - 2 - i : i] : 0.0;
+  for (int i = lane; i <= NMAX; i += 64) {
+    const double dv = (i < n) ? d_in[i] : 4.0;
+    const double ev = (i < n - 1) ? e_in[i] : 0.0;
+    s_d[i] = dv;
+    s_e[i] = ev;
+    s_e2[i] = ev * ev;
   }
+  {
+    // reflectors and taus, eight loads in flight per lane
+    const int total = (n - 2) * n;
+    for (int e0 = lane; e0 < total; e0 += 8 * 64) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = (e0 + 64 * u < total) ? Vr[e0 + 64 * u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + 64 * u < total) s_V[e0 + 64 * u] = t[u];
+    }
+    for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
+  }
+  __syncthreads();
+
   const int a = n - 1 - w;
   double lo = -1.0 - 1e-13, hi = 1.0 + 1e-13;
   for (int it = 0; it < 9; ++it) {
     const double x = lo + (double)(lane + 1) * (hi - lo) * (1.0 / 65.0);
-    double pp = 1.0, p = d[0] - x;
-    if (p == 0.0) p = -1e-300;
+    double pp = 1.0, p = s_d[0] - x;
+    if (p == 0.0) p = -kTiny;
     int cnt = (p < 0.0) ? 1 : 0;
-#pragma unroll
-    for (int i = 1; i < kTeNMax; ++i) {
-      if (i < n) {
-        double pn = fma(d[i] - x, p, -(e[i - 1] * e[i - 1]) * pp);
-        if (pn == 0.0) pn = (p > 0.0) ? -1e-300 : 1e-300;
-        cnt += ((pn < 0.0) != (p < 0.0)) ? 1 : 0;
-        pp = p;
-        p = pn;
+    static_for<1, NMAX>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int i = decltype(ic)::value;
+      double pn = fma(s_d[i] - x, p, -s_e2[i - 1] * pp);
+      pn = (pn == 0.0) ? ((p > 0.0) ? -kTiny : kTiny) : pn;
+      cnt += (int)((unsigned)(__double2hiint(pn) ^ __double2hiint(p)) >> 31);
+      pp = p;
+      p = pn;
+      if constexpr (i % 8 == 0) {
+        const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p), fabs(pp)));
+        p = ldexp(p, -ex);
+        pp = ldexp(pp, -ex);
       }
-      if ((i & 7) == 0) {
-        const double ap = fmax(fabs(p), fabs(pp));
-        if (ap > 0x1p+600) {
-          p *= 0x1p-600;
-          pp *= 0x1p-600;
-        } else if (ap < 0x1p-600) {
-          p *= 0x1p+600;
-          pp *= 0x1p+600;
-        }
-      }
-    }
+    });
     const double cl = (cnt <= a) ? x : lo;
     const double ch = (cnt > a) ? x : hi;
     lo = wave_max(cl);
@@ -416,32 +441,33 @@ __device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const do
   const double lam = 0.5 * (lo + hi);
   if (lane == 0) lam_out[w] = lam;
   if (w >= k) return;
-  // twisted factorisation: every lane runs the top-down recurrence on its copy;
-  // lane 0 (T) gives L_i, lane 32 (reversed T) gives U_{n-1-i}
-  const double tiny = 1e-300;
+  // twisted factorisation: lanes 0-31 run the top-down recurrence on T, lanes
+  // 32-63 on T reversed; lane 0 gives L_i, lane 32 gives U_{n-1-i}
+  const bool rev = lane >= 32;
+  auto dd = [&](int i) { return rev ? ((i < n) ? s_d[n - 1 - i] : 4.0) : s_d[i]; };
+  auto ee = [&](int i) { return rev ? ((i < n - 1) ? s_e[n - 2 - i] : 0.0) : s_e[i]; };
   {
-    double dp = d[0] - lam;
-#pragma unroll
-    for (int i = 0; i < kTeNMax - 1; ++i) {
+    double dp = dd(0) - lam;
+    static_for<0, NMAX - 1>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int i = decltype(ic)::value;
+      if (dp == 0.0) dp = kTiny;
+      const double ei = ee(i);
+      const double f = ei * rcp_f64(dp);
       if (i < n - 1) {
-        if (dp == 0.0) dp = tiny;
-        const double f = e[i] * rcp_f64(dp);
         if (lane == 0) s_L[i] = f;
         if (lane == 32) s_U[n - 1 - i] = f;
-        dp = (d[i + 1] - lam) - f * e[i];
       }
-    }
+      dp = (dd(i + 1) - lam) - f * ei;
+    });
   }
   __syncthreads();
   // gamma_i = delta_i - L_{i-1} e_{i-1} - U_{i+1} e_i, twist r = argmin |gamma|
   double best = 1e300;
   int rbest = 0;
   for (int i = lane; i < n; i += 64) {
-    const double ev = (i < n - 1) ? e_in[i] : 0.0;
-    const double ep = (i > 0) ? e_in[i - 1] : 0.0;
-    double g = d_in[i] - lam;
-    if (i > 0) g -= s_L[i - 1] * ep;
-    if (i < n - 1) g -= s_U[i + 1] * ev;
+    double g = s_d[i] - lam;
+    if (i > 0) g -= s_L[i - 1] * s_e[i - 1];
+    if (i < n - 1) g -= s_U[i + 1] * s_e[i];
     g = fabs(g);
     if (g < best) {
       best = g;
@@ -457,17 +483,37 @@ __device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const do
     }
   }
   const int r = rbest;
-  if (lane == 0) {
-    double z = 1.0;
-    s_z[r] = 1.0;
-    for (int i = r - 1; i >= 0; --i) {
-      z = -s_L[i] * z;
-      s_z[i] = z;
+  // z_r = 1, z_i = prod_{k=i}^{r-1} (-L_k) below the twist and
+  // prod_{k=r+1}^{i} (-U_k) above it: a suffix and a prefix product over
+  // 128 slots (lane l holds slots l and l + 64), log-step scans through LDS
+  {
+    double lo_f[2], up_f[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      lo_f[h] = (i < r) ? -s_L[i] : 1.0;
+      up_f[h] = (i > r && i < n) ? -s_U[i] : 1.0;
+      s_sc[0][0][i] = lo_f[h];
+      s_sc[0][1][i] = up_f[h];
     }
-    z = 1.0;
-    for (int i = r + 1; i < n; ++i) {
-      z = -s_U[i] * z;
-      s_z[i] = z;
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 7; ++st) {
+      const int off = 1 << st, src = st & 1, dst = src ^ 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i + off < 128) lo_f[h] *= s_sc[src][0][i + off];
+        if (i - off >= 0) up_f[h] *= s_sc[src][1][i - off];
+        s_sc[dst][0][i] = lo_f[h];
+        s_sc[dst][1][i] = up_f[h];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i < n) s_z[i] = (i < r) ? lo_f[h] : ((i > r) ? up_f[h] : 1.0);
     }
   }
   __syncthreads();
@@ -477,7 +523,7 @@ __device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const do
   z0 *= inv;
   z1 *= inv;
   for (int j = n - 3; j >= 0; --j) {
-    const double tau = taus[j];
+    const double tau = s_tau[j];
     // v_j over rows j+1..n-1; lane row i holds v = Vr[j][i - j - 1]
     const int i0 = lane, i1 = lane + 64;
     const double v0 = (i0 > j && i0 < n) ? s_V[j * n + i0 - j - 1] : 0.0;
@@ -490,11 +536,12 @@ __device__ __forceinline__ void tri_vec_kernel_body(const double *d_in, const do
   if (lane + 64 < n) Uz[(lane + 64) * k + w] = z1;
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const double *e_in, int n,
-                                                     int k, int kw, const double *Vr,
-                                                     const double *taus, double *lam_out,
-                                                     double *Uz, const int *flag) {
-  tri_vec_kernel_body(d_in, e_in, n, k, kw, Vr, taus, lam_out, Uz, flag, blockIdx.x);
+                                                     int k, const double *Vr, const double *taus,
+                                                     double *lam_out, double *Uz,
+                                                     const int *flag) {
+  tri_vec_body<NMAX>(d_in, e_in, n, k, Vr, taus, lam_out, Uz, flag, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- kernel 3
@@ -584,10 +631,11 @@ __global__ __launch_bounds__(kTrThreads) void tri_reduce_group_kernel(const EigG
   tri_reduce_body<NMAX>(e.G, e.n, e.d, e.e, e.sc, e.Vr, e.taus, e.flag);
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(64) void tri_vec_group_kernel(const EigGroupDesc *tab) {
   const EigGroupDesc &e = tab[blockIdx.y];
   if ((int)blockIdx.x >= e.kw) return;
-  tri_vec_kernel_body(e.d, e.e, e.n, e.k, e.kw, e.Vr, e.taus, e.lamw, e.Uz, e.flag, blockIdx.x);
+  tri_vec_body<NMAX>(e.d, e.e, e.n, e.k, e.Vr, e.taus, e.lamw, e.Uz, e.flag, blockIdx.x);
 }
 
 template <typename T>
@@ -623,8 +671,12 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
       hipLaunchKernelGGL(tri_reduce_kernel<80>, dim3(1), dim3(kTrThreads), 0, s, G, (int)n, d, e,
                          sc, Vr, taus, flag);
     TTR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(tri_vec_kernel, dim3(kw), dim3(64), 0, s, d, e, (int)n, (int)k, kw, Vr,
-                       taus, lamw, Uz, flag);
+    if (n <= 64)
+      hipLaunchKernelGGL(tri_vec_kernel<64>, dim3(kw), dim3(64), 0, s, d, e, (int)n, (int)k, Vr,
+                         taus, lamw, Uz, flag);
+    else
+      hipLaunchKernelGGL(tri_vec_kernel<80>, dim3(kw), dim3(64), 0, s, d, e, (int)n, (int)k, Vr,
+                         taus, lamw, Uz, flag);
     TTR_HIP(hipGetLastError());
     hipLaunchKernelGGL((tri_finish_kernel<T>), dim3(1), dim3(kTeThreads),
                        2 * sizeof(double) * (size_t)n * ld, s, G, lamw, Uz, sc, (int)n, (int)k,
@@ -689,7 +741,10 @@ int eig_trunc_group(const EigGroupDesc *d_tab, int count, int nmax, int kwmax, h
   else
     hipLaunchKernelGGL(tri_reduce_group_kernel<80>, dim3(count), dim3(kTrThreads), 0, s, d_tab);
   TTR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(tri_vec_group_kernel, dim3(kwmax, count), dim3(64), 0, s, d_tab);
+  if (nmax <= 64)
+    hipLaunchKernelGGL(tri_vec_group_kernel<64>, dim3(kwmax, count), dim3(64), 0, s, d_tab);
+  else
+    hipLaunchKernelGGL(tri_vec_group_kernel<80>, dim3(kwmax, count), dim3(64), 0, s, d_tab);
   TTR_HIP(hipGetLastError());
   hipLaunchKernelGGL((tri_finish_group_kernel<T>), dim3(count), dim3(kTeThreads),
                      2 * sizeof(double) * (size_t)nmax * ld, s, d_tab);
