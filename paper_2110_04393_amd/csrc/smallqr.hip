@@ -2,10 +2,13 @@
 //
 // Fast path: CholeskyQR2 in FP64.  G = Y^T Y (MFMA, split-K), G = R^T R by a
 // one-workgroup Cholesky that also forms R^{-1}, Q1 = Y R^{-1} (MFMA); the same
-// again on Q1.  Both Cholesky factors have positive diagonals, so the final
-// R = R2 R1 has diag(R) > 0, the normalisation the rest of the method uses.
+// again on Q1 (whose Gram is within rounding of I, so that its factor is
+// usually taken to first order).  Both Cholesky factors have positive
+// diagonals, so the final R = R2 R1 has diag(R) > 0, the normalisation the
+// rest of the method uses.
 //
-// Robust path: Householder QR in one workgroup, used for small panels and,
+// Robust path: Householder QR in one workgroup, used for panels of at most 8
+// columns and,
 // without a host round trip, whenever a Cholesky pivot falls below
 // 1e-14 of its original diagonal entry (the sketch is numerically rank
 // deficient, e.g. rounding A+A with a sketch wider than the rank).  The
@@ -40,7 +43,16 @@ int g_qr_mode = 0;  // 0 auto, 1 householder, 2 cholqr2
 // entry raises the flag (or_flag = 0: flag overwritten, else or-ed) and is
 // replaced by the original diagonal (1 if that is not positive) so that the
 // results stay finite.
+//
+// The second pass of CholeskyQR2 (or_flag = 1) factors G = Q1^T Q1 = I + E
+// with E of the order of cond(Y)^2 u.  When max |E_ij| <= 2^-30 the factor is
+// taken to first order, R = I + F with F = triu(E) - diag(E)/2 (then
+// R^T R = I + E + F^T F), and R^{-1} = I - F; both drop terms of order
+// |E|^2 <= (n 2^-30)^2, below 1e-14 for n <= 96, so Q = Q1 (I - F) agrees
+// with the exact CholeskyQR2 factor to rounding.  Larger E takes the
+// factorisation below.
 constexpr int kCholThreads = 256;
+constexpr double kNearIdentity = 0x1p-30;
 
 template <int NMAX>
 __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Rinv,
@@ -57,6 +69,33 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ty = lane >> 2, tq = lane & 3;
 
+  if (or_flag) {
+    // second pass: first-order factor when G is within 2^-30 of I
+    __shared__ double s_emax[4];
+    double em = 0.0;
+    for (int e = tid; e < n * n; e += kCholThreads) {
+      const int i = e / n, c = e - i * n;
+      em = fmax(em, fabs(G[e] - (i == c ? 1.0 : 0.0)));
+    }
+    em = fmax(em, __shfl_xor(em, 32));
+    em = fmax(em, __shfl_xor(em, 16));
+    em = fmax(em, __shfl_xor(em, 8));
+    em = fmax(em, __shfl_xor(em, 4));
+    em = fmax(em, __shfl_xor(em, 2));
+    em = fmax(em, __shfl_xor(em, 1));
+    if (lane == 0) s_emax[wave] = em;
+    __syncthreads();
+    const double emax = fmax(fmax(s_emax[0], s_emax[1]), fmax(s_emax[2], s_emax[3]));
+    if (emax <= kNearIdentity) {  // also false for NaN
+      for (int e = tid; e < n * n; e += kCholThreads) {
+        const int i = e / n, c = e - i * n;
+        const double x = (i == c) ? 1.0 - 0.5 * (G[e] - 1.0) : ((i < c) ? -G[e] : 0.0);
+        Rinv[e] = x;
+        if (Rinv_f) Rinv_f[e] = (float)x;
+      }
+      return;
+    }
+  }
   double X[NS][NB];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
@@ -334,8 +373,7 @@ template <typename T>
 int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s) {
   if (n > TT_MAX_SKETCH_RANK) return fail(TT_EUNSUPPORTED, "QR panel wider than the limit");
   if (m < n) return fail(TT_EINVAL, "thin QR needs m >= n");
-  const bool small = (m * n <= kHhLdsElems);
-  const bool householder_only = (g_qr_mode == 1) || (g_qr_mode == 0 && small);
+  const bool householder_only = (g_qr_mode == 1) || (g_qr_mode == 0 && n <= 8);
   // Householder scratch: rdiag = rinv[0..n), tau = rinv[n..2n) (rinv holds
   // max(n*n, 2n) doubles); work = q1.
   if (householder_only)

@@ -386,7 +386,9 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
                                              int w) {
   if (*flag) return;
   __shared__ double s_d[NMAX + 1], s_e[NMAX + 1], s_e2[NMAX + 1];
-  __shared__ double s_L[NMAX + 1], s_U[NMAX + 1], s_z[NMAX];
+  __shared__ double s_dr[NMAX + 1], s_er[NMAX + 1];  // T reversed, same padding
+  __shared__ double s_f[2][NMAX];  // L_i (top-down), U_{n-1-i} (bottom-up)
+  __shared__ double s_z[NMAX];
   __shared__ double s_V[NMAX * NMAX];  // reflectors: s_V[j n + i - j - 1]
   __shared__ double s_tau[NMAX];
   __shared__ double s_sc[2][2][128];   // scan buffers (lower, upper factors)
@@ -397,6 +399,8 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
     s_d[i] = dv;
     s_e[i] = ev;
     s_e2[i] = ev * ev;
+    s_dr[i] = (i < n) ? d_in[n - 1 - i] : 4.0;
+    s_er[i] = (i < n - 1) ? e_in[n - 2 - i] : 0.0;
   }
   {
     // reflectors and taus, eight loads in flight per lane
@@ -444,30 +448,30 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   // twisted factorisation: lanes 0-31 run the top-down recurrence on T, lanes
   // 32-63 on T reversed; lane 0 gives L_i, lane 32 gives U_{n-1-i}
   const bool rev = lane >= 32;
-  auto dd = [&](int i) { return rev ? ((i < n) ? s_d[n - 1 - i] : 4.0) : s_d[i]; };
-  auto ee = [&](int i) { return rev ? ((i < n - 1) ? s_e[n - 2 - i] : 0.0) : s_e[i]; };
   {
-    double dp = dd(0) - lam;
+    const double *D = rev ? s_dr : s_d;
+    const double *E = rev ? s_er : s_e;
+    double *F = s_f[rev ? 1 : 0];
+    const bool writer = (lane & 31) == 0;
+    double dp = D[0] - lam;
     static_for<0, NMAX - 1>([&](auto ic) __attribute__((always_inline)) {
       constexpr int i = decltype(ic)::value;
       if (dp == 0.0) dp = kTiny;
-      const double ei = ee(i);
+      const double ei = E[i];
       const double f = ei * rcp_f64(dp);
-      if (i < n - 1) {
-        if (lane == 0) s_L[i] = f;
-        if (lane == 32) s_U[n - 1 - i] = f;
-      }
-      dp = (dd(i + 1) - lam) - f * ei;
+      if (writer) F[i] = f;
+      dp = (D[i + 1] - lam) - f * ei;
     });
   }
   __syncthreads();
+  // L_i = s_f[0][i], U_i = s_f[1][n-1-i]
   // gamma_i = delta_i - L_{i-1} e_{i-1} - U_{i+1} e_i, twist r = argmin |gamma|
   double best = 1e300;
   int rbest = 0;
   for (int i = lane; i < n; i += 64) {
     double g = s_d[i] - lam;
-    if (i > 0) g -= s_L[i - 1] * s_e[i - 1];
-    if (i < n - 1) g -= s_U[i + 1] * s_e[i];
+    if (i > 0) g -= s_f[0][i - 1] * s_e[i - 1];
+    if (i < n - 1) g -= s_f[1][n - 2 - i] * s_e[i];
     g = fabs(g);
     if (g < best) {
       best = g;
@@ -491,8 +495,8 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = lane + 64 * h;
-      lo_f[h] = (i < r) ? -s_L[i] : 1.0;
-      up_f[h] = (i > r && i < n) ? -s_U[i] : 1.0;
+      lo_f[h] = (i < r) ? -s_f[0][i] : 1.0;
+      up_f[h] = (i > r && i < n) ? -s_f[1][n - 1 - i] : 1.0;
       s_sc[0][0][i] = lo_f[h];
       s_sc[0][1][i] = up_f[h];
     }
