@@ -287,6 +287,7 @@ class BatchPlan:
         B = len(tts)
         if not (len(targets) == len(oversamples) == len(seeds) == B):
             raise ValueError("targets, oversamples and seeds need one entry per TT")
+        self.prec = prec
         self.tts = [list(t) for t in tts]
         for t in self.tts:
             _check_cores(t)
@@ -335,8 +336,10 @@ class BatchPlan:
         la, gg = ctypes.c_int32(0), ctypes.c_int32(0)
         vc = (ctypes.c_int32 * 4)()
         L.check(L.lib().tt_batch_info(self._h, ctypes.byref(la), ctypes.byref(gg), vc))
+        names = (("32x64", "64x32", "64x64", "128x128") if self.prec in ("f64", "f32")
+                 else ("v0", "v1", "v2", "v3"))
         return {"launches_per_run": la.value, "grouped_gemms": gg.value,
-                "tile_variants": {"16x64": vc[0], "64x16": vc[1], "32x32": vc[2], "64x64": vc[3]}}
+                "tile_variants": dict(zip(names, (vc[0], vc[1], vc[2], vc[3])))}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

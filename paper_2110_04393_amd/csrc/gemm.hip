@@ -244,29 +244,40 @@ __device__ __forceinline__ void load4(const __bf16 *p, To (&o)[4]) {
 }
 
 // LDS-staged form for the x4 instructions (f64, f32).  The workgroup tile
-// BM x BN = (16 TM WM) x (16 TN WN) advances over K in steps of BK = 32:
-// all 256 threads load the A (BM x BK) and B (BK x BN) tiles with
-// coalesced reads (4 consecutive elements of the contiguous dimension per
-// thread), convert them to the MFMA type and store them k-major in LDS
-// (As[k][m], Bs[k][n]); every wavefront then reads its fragments
-// (A(m0 + r, k + q), B(k + q, n0 + r), lane = r + 16 q) from LDS, so each
-// operand element is fetched from memory once per workgroup.  The next tile
-// is loaded into registers while the current one feeds the MFMAs (two LDS
+// BM x BN = (16 TM WM) x (16 TN WN) (WM x WN wavefronts) advances over K in
+// steps of BK (16 for the eight-wavefront tiles, 32 otherwise): all threads
+// load the A (BM x BK) and B (BK x BN) tiles with coalesced reads (4
+// consecutive elements of the contiguous dimension per thread), convert them
+// to the MFMA type and store them k-major in LDS (As[k][m], Bs[k][n]); every
+// wavefront then reads all its fragments of the step (A(m0 + r, k + q),
+// B(k + q, n0 + r), lane = r + 16 q) before its MFMAs, so each operand
+// element is fetched from memory once per workgroup.  The next tile is
+// loaded into registers while the current one feeds the MFMAs (two LDS
 // buffers, one barrier per step).  A row padding (8 doubles, 16 floats)
-// spreads the four k-rows of a fragment read over the LDS banks, so a read
-// takes the minimum number of passes.
+// spreads the four k-rows of a fragment read over the LDS banks.
+//
+// The f64 MFMA issues at about one instruction per 140 cycles from a single
+// wavefront and needs several wavefronts per SIMD to approach its peak
+// (measured on gfx950), so the tiles for outputs with a side of at most 64
+// (most of the method's products) are 32 x 64 and 64 x 32 with eight
+// 16 x 16 wavefronts: more workgroups and more wavefronts per CU.
+template <int WM, int WN>
+constexpr int lds_bk() {
+  return WM * WN == 8 ? 16 : 32;
+}
+
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN>
 __device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm, int64_t wg) {
-  static_assert(WM * WN == 4, "4 wavefronts per workgroup");
   static_assert(MT::CPL == 4, "x4 MFMA instructions");
   typedef typename MT::acc_t acc_t;
   typedef typename MT::in_t in_t;
   typedef typename MT::part_t part_t;
-  constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = 32;
+  constexpr int T = 64 * WM * WN;
+  constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = lds_bk<WM, WN>();
   constexpr int PAD = sizeof(in_t) == 8 ? 8 : 16;
-  constexpr int RA = BM * BK / 1024, RB = BN * BK / 1024;  // 4-element groups per thread
-  static_assert(BM % 64 == 0 && BN % 64 == 0, "tiles are multiples of 64");
+  constexpr int GA = BM * BK / 4, GB = BN * BK / 4;  // 4-element groups per tile
+  constexpr int RA = (GA + T - 1) / T, RB = (GB + T - 1) / T;
   __shared__ in_t As[2][BK][BM + PAD];
   __shared__ in_t Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
@@ -287,53 +298,57 @@ __device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm,
   const int64_t kend = min(g.K, kbeg + tm.kchunk);
   const int r = lane & 15, q = lane >> 4;
 
-  // ---- global -> registers: thread t owns RA (RB) groups of 4 consecutive
-  // elements along the operand's contiguous dimension
+  // ---- global -> registers: thread t owns groups t, t + T, ... of 4
+  // consecutive elements along the operand's contiguous dimension
   in_t ra[RA][4], rb[RB][4];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int u = 0; u < RA; ++u) {
-      const int t = tid + 256 * u;
-      int64_t m, k;
-      if (AKC) {  // 4 consecutive k of row m
-        m = M0 + t / (BK / 4);
-        k = k0 + 4 * (t % (BK / 4));
-      } else {    // 4 consecutive m of row k
-        k = k0 + t / (BM / 4);
-        m = M0 + 4 * (t % (BM / 4));
-      }
-      const TA *p = AKC ? gA + m * g.lda + k : gA + k * g.lda + m;
-      const bool full = AKC ? (m < g.M && k + 3 < kend) : (k < kend && m + 3 < g.M);
-      if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-        load4(p, ra[u]);
-      } else {
+      const int t = tid + T * u;
+      if (t < GA) {
+        int64_t m, k;
+        if (AKC) {  // 4 consecutive k of row m
+          m = M0 + t / (BK / 4);
+          k = k0 + 4 * (t % (BK / 4));
+        } else {    // 4 consecutive m of row k
+          k = k0 + t / (BM / 4);
+          m = M0 + 4 * (t % (BM / 4));
+        }
+        const TA *p = AKC ? gA + m * g.lda + k : gA + k * g.lda + m;
+        const bool full = AKC ? (m < g.M && k + 3 < kend) : (k < kend && m + 3 < g.M);
+        if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+          load4(p, ra[u]);
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const bool ok = AKC ? (m < g.M && k + s < kend) : (k < kend && m + s < g.M);
-          ra[u][s] = ok ? cvt<in_t>(p[s]) : in_t(0);
+          for (int s = 0; s < 4; ++s) {
+            const bool ok = AKC ? (m < g.M && k + s < kend) : (k < kend && m + s < g.M);
+            ra[u][s] = ok ? cvt<in_t>(p[s]) : in_t(0);
+          }
         }
       }
     }
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
-      const int t = tid + 256 * u;
-      int64_t n, k;
-      if (BKC) {
-        n = N0 + t / (BK / 4);
-        k = k0 + 4 * (t % (BK / 4));
-      } else {
-        k = k0 + t / (BN / 4);
-        n = N0 + 4 * (t % (BN / 4));
-      }
-      const TB *p = BKC ? gB + n * g.ldb + k : gB + k * g.ldb + n;
-      const bool full = BKC ? (n < g.N && k + 3 < kend) : (k < kend && n + 3 < g.N);
-      if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-        load4(p, rb[u]);
-      } else {
+      const int t = tid + T * u;
+      if (t < GB) {
+        int64_t n, k;
+        if (BKC) {
+          n = N0 + t / (BK / 4);
+          k = k0 + 4 * (t % (BK / 4));
+        } else {
+          k = k0 + t / (BN / 4);
+          n = N0 + 4 * (t % (BN / 4));
+        }
+        const TB *p = BKC ? gB + n * g.ldb + k : gB + k * g.ldb + n;
+        const bool full = BKC ? (n < g.N && k + 3 < kend) : (k < kend && n + 3 < g.N);
+        if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+          load4(p, rb[u]);
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const bool ok = BKC ? (n < g.N && k + s < kend) : (k < kend && n + s < g.N);
-          rb[u][s] = ok ? cvt<in_t>(p[s]) : in_t(0);
+          for (int s = 0; s < 4; ++s) {
+            const bool ok = BKC ? (n < g.N && k + s < kend) : (k < kend && n + s < g.N);
+            rb[u][s] = ok ? cvt<in_t>(p[s]) : in_t(0);
+          }
         }
       }
     }
@@ -341,20 +356,24 @@ __device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm,
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < RA; ++u) {
-      const int t = tid + 256 * u;
+      const int t = tid + T * u;
+      if (t < GA) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        if (AKC) As[buf][4 * (t % (BK / 4)) + s][t / (BK / 4)] = ra[u][s];
-        else As[buf][t / (BM / 4)][4 * (t % (BM / 4)) + s] = ra[u][s];
+        for (int s = 0; s < 4; ++s) {
+          if (AKC) As[buf][4 * (t % (BK / 4)) + s][t / (BK / 4)] = ra[u][s];
+          else As[buf][t / (BM / 4)][4 * (t % (BM / 4)) + s] = ra[u][s];
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
-      const int t = tid + 256 * u;
+      const int t = tid + T * u;
+      if (t < GB) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        if (BKC) Bs[buf][4 * (t % (BK / 4)) + s][t / (BK / 4)] = rb[u][s];
-        else Bs[buf][t / (BN / 4)][4 * (t % (BN / 4)) + s] = rb[u][s];
+        for (int s = 0; s < 4; ++s) {
+          if (BKC) Bs[buf][4 * (t % (BK / 4)) + s][t / (BK / 4)] = rb[u][s];
+          else Bs[buf][t / (BN / 4)][4 * (t % (BN / 4)) + s] = rb[u][s];
+        }
       }
     }
   };
@@ -375,18 +394,20 @@ __device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm,
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) load(k0 + BK);
+    in_t a[BK / 4][TM], b[BK / 4][TN];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      in_t a[TM], b[TN];
+    for (int kk = 0; kk < BK / 4; ++kk) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[buf][kk + q][am + 16 * i];
+      for (int i = 0; i < TM; ++i) a[kk][i] = As[buf][4 * kk + q][am + 16 * i];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + q][bn + 16 * j];
+      for (int j = 0; j < TN; ++j) b[kk][j] = Bs[buf][4 * kk + q][bn + 16 * j];
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MT::mma1(a[i], b[j], acc[i][j]);
-    }
+        for (int j = 0; j < TN; ++j) acc[i][j] = MT::mma1(a[kk][i], b[kk][j], acc[i][j]);
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -432,7 +453,7 @@ __device__ __forceinline__ void gemm_any_body(const GemmX &g, const TileMap &tm,
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmX g, TileMap tm) {
   gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, blockIdx.x);
 }
 
@@ -441,7 +462,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmX g, TileMap tm) {
 // the largest wg_begin <= b.
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupEntry *tab, int count) {
+__global__ __launch_bounds__(64 * WM * WN) void gemm_group_kernel(const GemmGroupEntry *tab, int count) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -515,9 +536,10 @@ __global__ __launch_bounds__(256) void splitk_group_reduce_kernel(const GemmGrou
 struct Variant {
   int tm, tn, wm, wn;
 };
-// LDS-staged body (f64, f32): 64x64, 128x64, 64x128, 128x128 outputs per
-// workgroup; register-streaming body (bf16): 16x64, 64x16, 32x32, 64x64
-constexpr Variant kVarLds[] = {{2, 2, 2, 2}, {2, 4, 4, 1}, {4, 2, 1, 4}, {4, 4, 2, 2}};
+// LDS-staged body (f64, f32): 32x64, 64x32 (eight wavefronts), 64x64,
+// 128x128 outputs per workgroup; register-streaming body (bf16): 16x64,
+// 64x16, 32x32, 64x64
+constexpr Variant kVarLds[] = {{1, 1, 2, 4}, {1, 1, 4, 2}, {2, 2, 2, 2}, {4, 4, 2, 2}};
 constexpr Variant kVarReg[] = {{1, 1, 1, 4}, {1, 1, 4, 1}, {1, 1, 2, 2}, {2, 2, 2, 2}};
 
 const Variant &variant_of(DType math, int v) {
@@ -551,7 +573,7 @@ template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, i
           int WM, int WN>
 void launch_one(const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
                 const GemmGroupEntry *tab, int count) {
-  const dim3 gr((unsigned)grid), bl(256);
+  const dim3 gr((unsigned)grid), bl(64 * WM * WN);
   if (tab)
     hipLaunchKernelGGL((gemm_group_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>), gr, bl, 0, s,
                        tab, count);
@@ -566,13 +588,13 @@ void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipSt
   if constexpr (MT::CPL == 4) {
     switch (v) {
       case 0:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
+        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 4>(g, tm, grid, s, tab, count);
         break;
       case 1:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 4, 4, 1>(g, tm, grid, s, tab, count);
+        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 2>(g, tm, grid, s, tab, count);
         break;
       case 2:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 4, 2, 1, 4>(g, tm, grid, s, tab, count);
+        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
         break;
       default:
         launch_one<MT, TA, TB, TC, AKC, BKC, 4, 4, 2, 2>(g, tm, grid, s, tab, count);
