@@ -376,13 +376,32 @@ def bench_batched(args):
         ev1.record(stream)
         torch.cuda.synchronize()
         seq_ms = ev0.elapsed_time(ev1)
+        # the plain FP64 form: the same roundings in FP64 through the single-TT path
+        seq64_ms = None
+        if prec != "f64":
+            tts64 = [[c.double() for c in t] for t in tts]
+            plans64 = [tt.RoundPlan([int(c.shape[1]) for c in t],
+                                    [1] + [int(c.shape[2]) for c in t], tr, ov, "f64", "cuda:0")
+                       for t, tr, ov in zip(tts64, targets, overs)]
+            for p, t, sd in zip(plans64, tts64, seeds):
+                p.run(t, seed=sd, stream=stream)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for p, t, sd in zip(plans64, tts64, seeds):
+                p.run(t, seed=sd, stream=stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            seq64_ms = ev0.elapsed_time(ev1)
+            del plans64, tts64
     flops = 0.0
     for s, p in zip(specs, plans):
         flops += batch_flops(s, p.sketch_ranks)
     achieved = flops / (batch_ms * 1e-3) / 1e12
     peak = PEAK[prec if prec != "bf16" else "f32"]
     log(f"batch of 64: {batch_ms:.3f} ms ({batch_ms / 64:.4f} ms per rounding); "
-        f"sequential single-TT path {seq_ms:.3f} ms; {achieved:.2f} TFLOP/s")
+        f"sequential single-TT path {seq_ms:.3f} ms"
+        + (f", FP64 sequential {seq64_ms:.3f} ms" if seq64_ms else "")
+        + f"; {achieved:.2f} TFLOP/s")
     res = {
         "metric": METRIC, "value": round(batch_ms / 64, 5), "unit": "ms",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -394,6 +413,8 @@ def bench_batched(args):
                    "batch": 64, "precision": prec},
         "batch": {"ms_per_batch": round(batch_ms, 4), "sequential_single_tt_ms": round(seq_ms, 3),
                   "speedup_vs_sequential": round(seq_ms / batch_ms, 2),
+                  "sequential_single_tt_f64_ms": round(seq64_ms, 3) if seq64_ms else None,
+                  "speedup_vs_f64_sequential": round(seq64_ms / batch_ms, 2) if seq64_ms else None,
                   "plan_create_s": round(create_s, 2), **info},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,

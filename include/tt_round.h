@@ -326,12 +326,14 @@ TT_API int tt_batch_destroy(tt_batch batch);
 
 /*
  * Kernel timing (instrumentation, off by default).  tt_timing_start arms a
- * recorder for one call site of the rounding path: every later launch from
+ * recorder for one call site of the rounding path: every later product from
  * that site is bracketed by a pair of HIP events recorded on the launch
- * stream (up to `capacity` launches).  tt_timing_stop waits for the events,
- * writes the summed launch time in milliseconds and the launch count, and
- * disarms the recorder.  Sites: see tt_timing_site.  Not thread-safe: one
- * recorder per process.
+ * stream (up to `capacity` products); a product that overwrites its output
+ * (beta = 0) is launched 8 times back to back inside the pair, with the
+ * same operands, and counts as the average of the 8.  tt_timing_stop waits
+ * for the events, writes the summed time of one execution of every timed
+ * product in milliseconds and the product count, and disarms the recorder.
+ * Sites: see tt_timing_site.  Not thread-safe: one recorder per process.
  */
 typedef enum {
   TT_SITE_WCHAIN_Z = 0,    /* V(Z_n) = V(Y_n) W_n            (Algorithm 3)   */

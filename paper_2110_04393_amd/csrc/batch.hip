@@ -617,7 +617,7 @@ int tt_batch_create(int32_t B, const int32_t *orders, const int64_t *dims, const
   if (flags & TT_BATCH_AUTOTUNE) TTR_TRY(autotune(b, st));
   TTR_TRY(upload_tables(b));
   b.launches = 0;
-  for (const Op &o : b.ops) b.launches += (o.kind == OP_EIG) ? 5 : (o.reduce ? 2 : 1);
+  for (const Op &o : b.ops) b.launches += (o.kind == OP_EIG) ? 3 : (o.reduce ? 2 : 1);
   if (flags & TT_BATCH_GRAPH) {
     // one eager pass (first-use kernel attributes are set outside capture)
     TTR_TRY(run_ops(b, st));

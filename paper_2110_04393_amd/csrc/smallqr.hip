@@ -45,14 +45,15 @@ int g_qr_mode = 0;  // 0 auto, 1 householder, 2 cholqr2
 // results stay finite.
 //
 // The second pass of CholeskyQR2 (or_flag = 1) factors G = Q1^T Q1 = I + E
-// with E of the order of cond(Y)^2 u.  When max |E_ij| <= 2^-30 the factor is
+// with E of the order of cond(Y)^2 u.  When max |E_ij| <= tol the factor is
 // taken to first order, R = I + F with F = triu(E) - diag(E)/2 (then
 // R^T R = I + E + F^T F), and R^{-1} = I - F; both drop terms of order
-// |E|^2 <= (n 2^-30)^2, below 1e-14 for n <= 96, so Q = Q1 (I - F) agrees
-// with the exact CholeskyQR2 factor to rounding.  Larger E takes the
-// factorisation below.
+// |E|^2 <= (n tol)^2, so Q = Q1 (I - F) agrees with the exact CholeskyQR2
+// factor to rounding: tol = 2^-30 with FP64 storage ((96 tol)^2 < 1e-14),
+// 2^-17 with FP32 storage (Rinv_f given; (96 tol)^2 < 7e-7, about ten FP32
+// roundings).  Larger E takes the factorisation below.
 constexpr int kCholThreads = 256;
-constexpr double kNearIdentity = 0x1p-30;
+constexpr double kNearIdentity = 0x1p-30, kNearIdentityF32 = 0x1p-17;
 
 template <int NMAX>
 __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Rinv,
@@ -86,7 +87,7 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
     if (lane == 0) s_emax[wave] = em;
     __syncthreads();
     const double emax = fmax(fmax(s_emax[0], s_emax[1]), fmax(s_emax[2], s_emax[3]));
-    if (emax <= kNearIdentity) {  // also false for NaN
+    if (emax <= (Rinv_f ? kNearIdentityF32 : kNearIdentity)) {  // also false for NaN
       for (int e = tid; e < n * n; e += kCholThreads) {
         const int i = e / n, c = e - i * n;
         const double x = (i == c) ? 1.0 - 0.5 * (G[e] - 1.0) : ((i < c) ? -G[e] : 0.0);

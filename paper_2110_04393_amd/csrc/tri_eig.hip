@@ -30,6 +30,7 @@
 // Newton-Schulz step exceeds 1e-6; that kernel and the factor kernel are
 // always enqueued after this one and return at once unless the flag is set.
 #include "fastmath.h"
+#include "jacobi.h"
 #include "tt_internal.h"
 #include "wave.h"
 
@@ -552,11 +553,11 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
 // One workgroup: gap check, orthogonality check and one Newton-Schulz step on
 // U (n x k, from kernel 2), outputs (unscaled eigenvalues, U, truncation
 // factors, tail).
+// Returns false (all threads alike, outputs untouched) when a check fails.
 template <typename T>
-__device__ __forceinline__ void tri_finish_kernel_body(
+__device__ __forceinline__ bool tri_finish_part(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
-    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag) {
-  if (*flag) return;
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail) {
   extern __shared__ double lds[];
   const int ld = n | 1;
   double *Z = lds;             // n x ld (k columns)
@@ -589,10 +590,7 @@ __device__ __forceinline__ void tri_finish_kernel_body(
     if (lane == 0 && !(dev <= 1e-6)) s_bad = 1;
   }
   __syncthreads();
-  if (s_bad) {
-    if (tid == 0) *flag = 1;
-    return;
-  }
+  if (s_bad) return false;
   for (int e = tid; e < k * k; e += blockDim.x) {
     const int a = e / k, b = e - a * k;
     E[a * ld + b] = (a == b ? 1.5 : 0.0) - 0.5 * E[a * ld + b];
@@ -620,13 +618,33 @@ __device__ __forceinline__ void tri_finish_kernel_body(
     kept = wave_sum(kept) * inv_sc;
     if (lane == 0) *tail = fmax(tr - kept, 0.0);
   }
+  return true;
+}
+
+// Kernel 3 with its fallback: when the tridiagonal solver flagged trouble
+// (non-finite T, close eigenvalues, lost orthogonality) the same workgroup
+// diagonalises G by cyclic Jacobi and forms the truncation factors from it;
+// the flag then stays set.
+template <typename T>
+__device__ __forceinline__ void tri_finish_kernel_body(
+    const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force) {
+  if (!force && *flag == 0 &&
+      tri_finish_part<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail))
+    return;
+  __syncthreads();
+  jacobi_eig_kernel_body(Gin, lam_out, U_out, n, nullptr, nullptr);
+  __syncthreads();
+  trunc_factors_kernel_body<T>(lam_out, U_out, n, k, P, S, tail, nullptr);
+  if (threadIdx.x == 0) *flag = 1;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
-    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag) {
-  tri_finish_kernel_body<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, flag);
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force) {
+  tri_finish_kernel_body<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, flag,
+                            force);
 }
 
 template <int NMAX>
@@ -643,13 +661,24 @@ __global__ __launch_bounds__(64) void tri_vec_group_kernel(const EigGroupDesc *t
 }
 
 template <typename T>
-__global__ __launch_bounds__(kTeThreads) void tri_finish_group_kernel(const EigGroupDesc *tab) {
+__global__ __launch_bounds__(kTeThreads) void tri_finish_group_kernel(const EigGroupDesc *tab, int force) {
   const EigGroupDesc &e = tab[blockIdx.x];
   tri_finish_kernel_body<T>(e.G, e.lamw, e.Uz, e.sc, e.n, e.k, e.kw, e.lam, e.U,
-                            static_cast<T *>(e.P), static_cast<T *>(e.S), e.tail, e.flag);
+                            static_cast<T *>(e.P), static_cast<T *>(e.S), e.tail, e.flag, force);
 }
 
 }  // namespace
+
+static int g_eig_mode = 0;  // 0 tridiagonal solver (Jacobi on its failure), 1 Jacobi always
+
+void eig_set_mode(int mode) { g_eig_mode = mode; }
+
+// dynamic LDS of the finish kernel: Z and E of kernel 3, or G and V of the
+// Jacobi fallback, whichever is larger
+static size_t finish_lds(int n) {
+  const int ld = n | 1, np = (n + 1) & ~1;
+  return sizeof(double) * std::max<size_t>(2 * (size_t)n * ld, 2 * (size_t)np * (np + 1));
+}
 
 template <typename T>
 int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *P, T *S,
@@ -657,7 +686,6 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
   if (n > TT_MAX_SKETCH_RANK) return fail(TT_EUNSUPPORTED, "eigenproblem larger than the limit");
   if (k < 1 || k > n) return fail(TT_EINVAL, "truncation rank out of range");
   if (n <= kTeNMax) {
-    const int ld = (int)(n | 1);
     const int kw = (int)std::min<int64_t>(k + 1, n);
     // scratch: d (n), e (n), sc (1), Vr (n*n), taus (n), lamw (n+1), U (n*k)
     double *d = scratch, *e = d + n, *sc = e + n, *Vr = sc + 1, *taus = Vr + n * n;
@@ -682,13 +710,9 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
       hipLaunchKernelGGL(tri_vec_kernel<80>, dim3(kw), dim3(64), 0, s, d, e, (int)n, (int)k, Vr,
                          taus, lamw, Uz, flag);
     TTR_HIP(hipGetLastError());
-    hipLaunchKernelGGL((tri_finish_kernel<T>), dim3(1), dim3(kTeThreads),
-                       2 * sizeof(double) * (size_t)n * ld, s, G, lamw, Uz, sc, (int)n, (int)k,
-                       kw, lam, U, P, S, tail, flag);
+    hipLaunchKernelGGL((tri_finish_kernel<T>), dim3(1), dim3(kTeThreads), finish_lds((int)n), s, G,
+                       lamw, Uz, sc, (int)n, (int)k, kw, lam, U, P, S, tail, flag, g_eig_mode);
     TTR_HIP(hipGetLastError());
-    // Jacobi fallback, gated on the flag
-    TTR_TRY(sym_eig(G, lam, U, n, s, nullptr, flag));
-    TTR_TRY(trunc_factors<T>(lam, U, n, k, P, S, tail, s, flag));
     return TT_OK;
   }
   TTR_TRY(sym_eig(G, lam, U, n, s, nullptr, nullptr));
@@ -725,15 +749,10 @@ bool eig_group_desc(const double *G, int64_t n, int64_t k, double *lam, double *
   return true;
 }
 
-int jacobi_group_run(const EigGroupDesc *d_tab, int count, int nmax, hipStream_t s);
-template <typename T>
-int trunc_factors_group_run(const EigGroupDesc *d_tab, int count, hipStream_t s);
-
 template <typename T>
 int eig_trunc_group(const EigGroupDesc *d_tab, int count, int nmax, int kwmax, hipStream_t s) {
   if (count <= 0) return TT_OK;
   if (nmax > kTeNMax) return fail(TT_EUNSUPPORTED, "grouped eigenproblem larger than the limit");
-  const int ld = nmax | 1;
   static bool attr_set = false;
   if (!attr_set) {
     TTR_HIP(hipFuncSetAttribute((const void *)tri_finish_group_kernel<T>,
@@ -750,11 +769,10 @@ int eig_trunc_group(const EigGroupDesc *d_tab, int count, int nmax, int kwmax, h
   else
     hipLaunchKernelGGL(tri_vec_group_kernel<80>, dim3(kwmax, count), dim3(64), 0, s, d_tab);
   TTR_HIP(hipGetLastError());
-  hipLaunchKernelGGL((tri_finish_group_kernel<T>), dim3(count), dim3(kTeThreads),
-                     2 * sizeof(double) * (size_t)nmax * ld, s, d_tab);
+  hipLaunchKernelGGL((tri_finish_group_kernel<T>), dim3(count), dim3(kTeThreads), finish_lds(nmax),
+                     s, d_tab, g_eig_mode);
   TTR_HIP(hipGetLastError());
-  TTR_TRY(jacobi_group_run(d_tab, count, nmax, s));
-  return trunc_factors_group_run<T>(d_tab, count, s);
+  return TT_OK;
 }
 template int eig_trunc_group<double>(const EigGroupDesc *, int, int, int, hipStream_t);
 template int eig_trunc_group<float>(const EigGroupDesc *, int, int, int, hipStream_t);

@@ -246,6 +246,8 @@ size_t qr_partial_elems(int64_t m, int64_t n);
 template <typename T>
 int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s);
 void qr_set_mode(int mode);  // 0 auto, 1 force householder, 2 force cholqr2
+// truncation eigensolver: 0 tridiagonal (Jacobi when it fails), 1 Jacobi always
+void eig_set_mode(int mode);
 // R^{-1} of the upper Cholesky factor of the n x n FP64 matrix G (n <= 96),
 // row-major; Rinv_f (optional) receives it rounded to FP32; *flag = 1 on a
 // pivot breakdown

@@ -119,14 +119,18 @@ def test_rto_cores_match_oracle(gpu_lib, case, qr, monkeypatch):
         assert np.abs(Vn.T @ Vn - np.eye(Vn.shape[1])).max() < 1e-12
 
 
+@pytest.mark.parametrize("eig", ["auto", "jacobi"])
 @pytest.mark.parametrize("case", [
     (6, 9, 12, 5, 3),
     (5, 40, 50, 20, 6),
     (3, 7, 5, 2, 1),
 ])
-def test_rto_truncated_matches_oracle(gpu_lib, case):
+def test_rto_truncated_matches_oracle(gpu_lib, case, eig, monkeypatch):
+    # eig = "jacobi" takes the fallback branch of the fused finish kernel
     N, I, R, t, p = case
-    say(f"RtO truncated {case}")
+    say(f"RtO truncated {case} eig={eig}")
+    if eig != "auto":
+        monkeypatch.setenv("TT_EIG", eig)
     dims, ranks = G.uniform_tt_shape(N, I, R)
     Y = G.random_tt(31 + N, dims, ranks, scale="nominal")
     out = host(gpu_lib.round_rand(dev(Y), t, p, seed=5))
