@@ -234,15 +234,15 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
     constexpr int js = (j / 16) / 4, jw = (j / 16) % 4;
     // ---- phase 1: the quad owning row j (= column j) builds the reflector
     if (wave == jw && ty == j % 16) {
-      double sq = 0.0;
+      double sq[4] = {0.0, 0.0, 0.0, 0.0};  // four independent chains
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         if (4 * b + 3 >= j + 2) {
           const int c = tq + 4 * b;
-          if (c >= j + 2) sq = fma(A[js][b], A[js][b], sq);
+          if (c >= j + 2) sq[b & 3] = fma(A[js][b], A[js][b], sq[b & 3]);
         }
       }
-      const double sigma = quad_sum(sq);
+      const double sigma = quad_sum((sq[0] + sq[1]) + (sq[2] + sq[3]));
       const double a0 = quad_bcast<(j + 1) % 4>(A[js][(j + 1) / 4]);
       const double djj = quad_bcast<j % 4>(A[js][j / 4]);
       double beta, tau, scale;
@@ -282,11 +282,11 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
       pr[sl] = 0.0;
       if (16 * (wave + 4 * sl) + 15 > j && 16 * (wave + 4 * sl) < NMAX) {
         vr[sl] = s_V[j][(i & 3) * NB + (i >> 2)];
-        double acc = 0.0;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          if (4 * b + 3 > j) acc = fma(A[sl][b], vc[b], acc);
-        pr[sl] = tau * quad_sum(acc);
+          if (4 * b + 3 > j) acc[b & 3] = fma(A[sl][b], vc[b], acc[b & 3]);
+        pr[sl] = tau * quad_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
         if (tq == 0) {
           s_p[buf][(i & 3) * NB + (i >> 2)] = pr[sl];
           qpart = fma(pr[sl], vr[sl], qpart);
