@@ -34,6 +34,14 @@ SITE_MATH = {"f64": ("f64", "f64"), "f32": ("f32", "f32"), "bf16": ("bf16", "f32
 STORE_BYTES = {"f64": 8, "f32": 4, "bf16": 4}
 METRIC = "ms per randomized TT-rounding + %MFMA peak; mixed-prec vs FP64 at tol"
 
+# HBM bytes per launch of the roofline kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over this script's default
+# run, each scaled by what the same counter reads for a plain 256 MiB device
+# copy (FETCH_SIZE counts half of the copy's reads: x 2.0; WRITE_SIZE x 1.0).
+# Source: profiles/gemm_vyw_single_tt_N30_I100_R200_fp64_pmc_traffic.md.
+# Valid for the kernel as measured there; anything else reports null.
+MEASURED_TRAFFIC = {("single_tt", "f64", 0): {"read_bytes": 33.49e6, "write_bytes": 9.60e6}}
+
 SITE_NAMES = {0: "wchain_z", 1: "wchain_w", 2: "sweep_y", 3: "sweep_m", 4: "sweep_next",
               5: "trunc"}
 SITE_KERNEL = {0: "gemm_kernel (V(Y_n) W_n, partial contractions)",
@@ -118,7 +126,7 @@ def make_workload(name):
     raise ValueError(name)
 
 
-def cpu_baseline(wl, gpu_out, budget_s=12.0, max_reps=5):
+def cpu_baseline(wl, gpu_out, budget_s=12.0, max_reps=30):
     """The FP64 oracle on the host's cores: whole roundings of the same input."""
     import numpy as np
 
@@ -157,10 +165,24 @@ def main():
     ap.add_argument("--no-f64-compare", action="store_true",
                     help="with --prec f32/bf16: skip timing the FP64 path for the speedup")
     ap.add_argument("--site", type=int, default=None,
-                    help="call site whose kernel the roofline covers (default: dominant)")
+                    help="call site whose kernel the roofline covers (default: 0, V(Y_n) W_n)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * 2**20 // 8
+        src = torch.randn(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB ten times ({n * 8} bytes read and written each)")
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the rounding "
@@ -251,7 +273,9 @@ def main():
         log(f"site {SITE_NAMES[site]}: {cnt.value // args.steps} launches/step, "
             f"{tot.value / max(cnt.value, 1) * 1e3:.1f} us avg, {tot.value / args.steps:.3f} ms/step, "
             f"{fl / (tot.value * 1e-3) / 1e12 if tot.value else 0:.2f} TFLOP/s")
-    site = args.site if args.site is not None else max(site_ms, key=lambda k: site_ms[k][0])
+    # the roofline covers the partial contraction V(Y_n) W_n unless --site says otherwise (it
+    # and the next-core product are the two largest contractions, within a few per cent)
+    site = args.site if args.site is not None else 0
     tot_ms, cnt, flops = site_ms[site]
     math_dt = wmath if site in (0, 1) else smath
     per_launch_us = tot_ms / max(cnt, 1) * 1e3
@@ -268,6 +292,13 @@ def main():
         roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                         frac=round(achieved / peak, 4), traffic=None,
                         flops_per_step=flops / args.steps)
+    mt = MEASURED_TRAFFIC.get((args.workload, args.prec, site))
+    if mt:
+        roofline["traffic"] = mt["read_bytes"] + mt["write_bytes"]
+        roofline["traffic_detail"] = dict(mt, unit="bytes per launch",
+                                          algorithmic_bytes=site_bytes(site, dims, ell,
+                                                                       summand_ranks, 8)
+                                          / max(cnt // max(args.steps, 1), 1))
     roofline.update(kernel=SITE_KERNEL[site], math=math_dt,
                     launches_per_step=cnt // max(args.steps, 1),
                     avg_launch_us=round(per_launch_us, 2),
@@ -301,7 +332,11 @@ def main():
         ms64, _ = timed(step64, args.steps, args.warmup)
         out64 = [c.detach().cpu().numpy() for c in step64()]
         torch.cuda.synchronize()
-        res["f64_gpu"] = {"ms_per_step": round(ms64, 4), "speedup": round(ms64 / ms_per_step, 3)}
+        # core-by-core relative difference to the FP64 GPU result (same gauge)
+        num = sum(float(((a - b) ** 2).sum()) for a, b in zip(out, out64))
+        den = sum(float((b ** 2).sum()) for b in out64)
+        res["f64_gpu"] = {"ms_per_step": round(ms64, 4), "speedup": round(ms64 / ms_per_step, 3),
+                          "core_rel_diff": float(f"{math.sqrt(num / max(den, 1e-300)):.3e}")}
         log(f"FP64 GPU path: {ms64:.3f} ms/step; {args.prec} speedup {ms64 / ms_per_step:.2f}x")
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(wl, out, budget_s=args.cpu_budget)
