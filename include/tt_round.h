@@ -318,8 +318,8 @@ TT_API int tt_batch_create(int32_t B, const int32_t *orders, const int64_t *dims
                            tt_batch *batch);
 TT_API int tt_batch_run(tt_batch batch, void *stream);
 /* launches per run, grouped GEMMs, and how many of them use each of the four
- * tile variants: outputs per workgroup 32x64, 64x32, 64x64, 128x128 for FP64
- * and FP32 arithmetic, 16x64, 64x16, 32x32, 64x64 for BF16 arithmetic */
+ * tile variants: outputs per workgroup 32x64, 64x32, 64x64, 128x128 (the
+ * same table for every arithmetic) */
 TT_API int tt_batch_info(tt_batch batch, int32_t *launches, int32_t *gemm_groups,
                          int32_t *variant_count);
 TT_API int tt_batch_destroy(tt_batch batch);

@@ -336,8 +336,7 @@ class BatchPlan:
         la, gg = ctypes.c_int32(0), ctypes.c_int32(0)
         vc = (ctypes.c_int32 * 4)()
         L.check(L.lib().tt_batch_info(self._h, ctypes.byref(la), ctypes.byref(gg), vc))
-        names = (("32x64", "64x32", "64x64", "128x128") if self.prec in ("f64", "f32")
-                 else ("v0", "v1", "v2", "v3"))
+        names = ("32x64", "64x32", "64x64", "128x128")
         return {"launches_per_run": la.value, "grouped_gemms": gg.value,
                 "tile_variants": dict(zip(names, (vc[0], vc[1], vc[2], vc[3])))}
 

@@ -8,19 +8,15 @@
 //   f32   v_mfma_f32_16x16x4f32
 //   bf16  v_mfma_f32_16x16x32_bf16 (operands rounded to bf16 to nearest even,
 //         fp32 accumulation)
-// and with f64, f32 or bf16 storage of each operand (converted in registers).
+// and with f64, f32 or bf16 storage of each operand (converted as the tiles
+// are staged).
 //
 // Work decomposition.  A wavefront owns a (16 TM) x (16 TN) output tile made
-// of 16x16 MFMA blocks; a workgroup is 4 wavefronts arranged WM x WN.  The K
-// loop runs in chunks of 4*CPL: lane l = r + 16 q supplies A(m0 + r, k) and
-// B(k, n0 + r) for k in [k0 + CPL q, k0 + CPL q + CPL), CPL = 4 for the x4
-// instructions (one value per MFMA, 4 MFMAs per chunk) and 8 for bf16 (eight
-// values packed into one MFMA).  Over the chunk every k is used exactly once,
-// so the permuted order is harmless, and a K-contiguous operand is read as
-// CPL consecutive values per lane while an M/N-contiguous one is read by 16
-// lanes as one cache line.  Operands stream from HBM/L2 into registers: one
-// f64 MFMA occupies the matrix pipe for 64 cycles on gfx950, so the fragment
-// loads of a chunk hide behind the previous chunk's MFMAs without LDS.
+// of 16x16 MFMA blocks; a workgroup is WM x WN wavefronts.  Operand tiles are
+// staged through LDS (see the bodies below); lane l = r + 16 q supplies
+// A(m0 + r, k) and B(k, n0 + r) for its k of the instruction: k0 + q for the
+// x4 instructions (one value per MFMA), k0 + 8 q .. 8 q + 7 for bf16 (eight
+// values packed into one MFMA).
 //
 // Accumulator layout of a 16x16 block, lane l = r + 16 q, register j:
 // column r; row q + 4 j for the f64 instruction and 4 q + j for the f32 and
@@ -45,11 +41,6 @@ struct MathF64 {
   typedef double part_t;
   static constexpr int CPL = 4;
   __device__ static int row(int q, int j) { return q + 4 * j; }
-  __device__ static acc_t mma(const in_t (&a)[CPL], const in_t (&b)[CPL], acc_t c) {
-#pragma unroll
-    for (int s = 0; s < CPL; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
-    return c;
-  }
   __device__ static acc_t mma1(in_t a, in_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -60,11 +51,6 @@ struct MathF32 {
   typedef float part_t;
   static constexpr int CPL = 4;
   __device__ static int row(int q, int j) { return 4 * q + j; }
-  __device__ static acc_t mma(const in_t (&a)[CPL], const in_t (&b)[CPL], acc_t c) {
-#pragma unroll
-    for (int s = 0; s < CPL; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
-    return c;
-  }
   __device__ static acc_t mma1(in_t a, in_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -75,15 +61,6 @@ struct MathBF16 {
   typedef float part_t;
   static constexpr int CPL = 8;
   __device__ static int row(int q, int j) { return 4 * q + j; }
-  __device__ static acc_t mma(const in_t (&a)[CPL], const in_t (&b)[CPL], acc_t c) {
-    bf8_t x, y;
-#pragma unroll
-    for (int s = 0; s < CPL; ++s) {
-      x[s] = (__bf16)a[s];
-      y[s] = (__bf16)b[s];
-    }
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
-  }
 };
 
 template <typename To, typename From>
@@ -104,118 +81,6 @@ struct TileMap {
 };
 
 constexpr int kSplitGroup = 8;
-
-// one wavefront's (16 TM) x (16 TN) tile of the register-streaming body
-template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN>
-__device__ __forceinline__ void gemm_body_wave(const GemmX &g, const TileMap &tm, int64_t split,
-                                               const TA *gA, const TB *gB, TC *gC, int64_t m0,
-                                               int64_t n0) {
-  typedef typename MT::acc_t acc_t;
-  typedef typename MT::in_t in_t;
-  typedef typename MT::part_t part_t;
-  constexpr int CPL = MT::CPL;
-  constexpr int CHUNK = 4 * CPL;
-  const int lane = threadIdx.x & 63;
-  const int64_t kbeg = split * tm.kchunk;
-  const int64_t kend = min(g.K, kbeg + tm.kchunk);
-  const int r = lane & 15, q = lane >> 4;
-
-  acc_t acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-
-  // per-lane base pointers at k = CPL q
-  const TA *pa[TM];
-  const TB *pb[TN];
-  bool rowok[TM], colok[TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    const int64_t m = m0 + 16 * i + r;
-    rowok[i] = m < g.M;
-    const int64_t mm = rowok[i] ? m : 0;
-    pa[i] = AKC ? gA + mm * g.lda + CPL * q : gA + (int64_t)(CPL * q) * g.lda + mm;
-  }
-#pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int64_t n = n0 + 16 * j + r;
-    colok[j] = n < g.N;
-    const int64_t nn = colok[j] ? n : 0;
-    pb[j] = BKC ? gB + nn * g.ldb + CPL * q : gB + (int64_t)(CPL * q) * g.ldb + nn;
-  }
-
-  for (int64_t k0 = kbeg; k0 < kend; k0 += CHUNK) {
-    in_t a[TM][CPL], b[TN][CPL];
-    const bool kfull = (k0 + CHUNK <= kend);
-#pragma unroll
-    for (int s = 0; s < CPL; ++s) {
-      const int64_t k = k0 + CPL * q + s;
-      const bool kok = kfull || (k < kend);
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const TA *p = AKC ? pa[i] + k0 + s : pa[i] + (k0 + s) * g.lda;
-        a[i][s] = (kok && rowok[i]) ? cvt<in_t>(*p) : in_t(0);
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const TB *p = BKC ? pb[j] + k0 + s : pb[j] + (k0 + s) * g.ldb;
-        b[j][s] = (kok && colok[j]) ? cvt<in_t>(*p) : in_t(0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = MT::mma(a[i], b[j], acc[i][j]);
-  }
-
-  // store
-  part_t *part = static_cast<part_t *>(g.partial);
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int64_t col = n0 + 16 * j + r;
-      if (col >= g.N) continue;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int64_t row = m0 + 16 * i + MT::row(q, jj);
-        if (row >= g.M) continue;
-        const part_t v = acc[i][j][jj];
-        if (g.splits > 1) {
-          part[(split * g.M + row) * g.N + col] = v;
-        } else {
-          TC *c = gC + row * g.ldc + col;
-          const double out = (g.beta != 0.0)
-                                 ? g.alpha * (double)v + g.beta * cvt<double>(*c)
-                                 : g.alpha * (double)v;
-          *c = (TC)out;
-        }
-      }
-    }
-}
-
-template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
-__device__ __forceinline__ void gemm_body(const GemmX &g, const TileMap &tm, int64_t wg) {
-  static_assert(WM * WN == 4, "4 wavefronts per workgroup");
-  const int wave = threadIdx.x >> 6;
-  const int wm = wave % WM, wn = wave / WM;
-  const int64_t tn_wg = wg % tm.tiles_n;
-  wg /= tm.tiles_n;
-  const int64_t tm_wg = wg % tm.tiles_m;
-  wg /= tm.tiles_m;
-  const int64_t split = (g.batch > 1) ? 0 : wg;
-  const int64_t bidx = (g.batch > 1) ? wg : 0;
-  const TA *gA = static_cast<const TA *>(g.A) + bidx * g.sA;
-  const TB *gB = static_cast<const TB *>(g.B) + bidx * g.sB;
-  TC *gC = static_cast<TC *>(g.C) + bidx * g.sC;
-
-  const int64_t m0 = (tm_wg * WM + wm) * (16 * TM);
-  const int64_t n0 = (tn_wg * WN + wn) * (16 * TN);
-  if (m0 < g.M && n0 < g.N)
-    gemm_body_wave<MT, TA, TB, TC, AKC, BKC, TM, TN>(g, tm, split, gA, gB, gC, m0, n0);
-}
 
 // Four consecutive elements from a 16-byte aligned address as vector loads,
 // converted to the MFMA input type.
@@ -440,15 +305,195 @@ __device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm,
     }
 }
 
-// the LDS-staged body for the x4 instructions, the register-streaming one
-// for bf16
+// LDS-staged form for the bf16 instruction (v_mfma_f32_16x16x32_bf16: lane
+// r + 16 q holds 8 consecutive k, 8 q .. 8 q + 7, of A row r and B column r).
+// The tiles are rounded to bf16 (nearest even) as they are staged and kept
+// k-contiguous per row of A and per column of B (As[m][k], Bs[n][k], rows
+// of 32 + 8 values), so a fragment is one 16-byte LDS read; one MFMA step
+// per BK = 32.  A k step's eight products of a lane are summed inside one
+// instruction, so the accumulation order differs from the x4 forms.
+template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
+          int WM, int WN>
+__device__ __forceinline__ void gemm_lds_bf16_body(const GemmX &g, const TileMap &tm,
+                                                   int64_t wg) {
+  static_assert(MT::CPL == 8, "bf16 instruction");
+  typedef typename MT::acc_t acc_t;
+  typedef typename MT::part_t part_t;
+  constexpr int T = 64 * WM * WN;
+  constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = 32, LDK = BK + 8;
+  constexpr int GA = BM * BK / 4, GB = BN * BK / 4;
+  constexpr int RA = (GA + T - 1) / T, RB = (GB + T - 1) / T;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN][LDK];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wm = wave % WM, wn = wave / WM;
+  const int64_t tn_wg = wg % tm.tiles_n;
+  wg /= tm.tiles_n;
+  const int64_t tm_wg = wg % tm.tiles_m;
+  wg /= tm.tiles_m;
+  const int64_t split = (g.batch > 1) ? 0 : wg;
+  const int64_t bidx = (g.batch > 1) ? wg : 0;
+  const TA *gA = static_cast<const TA *>(g.A) + bidx * g.sA;
+  const TB *gB = static_cast<const TB *>(g.B) + bidx * g.sB;
+  TC *gC = static_cast<TC *>(g.C) + bidx * g.sC;
+  const int64_t M0 = tm_wg * BM, N0 = tn_wg * BN;
+  const int64_t kbeg = split * tm.kchunk;
+  const int64_t kend = min(g.K, kbeg + tm.kchunk);
+  const int r = lane & 15, q = lane >> 4;
+
+  float ra[RA][4], rb[RB][4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < RA; ++u) {
+      const int t = tid + T * u;
+      if (t < GA) {
+        int64_t m, k;
+        if (AKC) {
+          m = M0 + t / (BK / 4);
+          k = k0 + 4 * (t % (BK / 4));
+        } else {
+          k = k0 + t / (BM / 4);
+          m = M0 + 4 * (t % (BM / 4));
+        }
+        const TA *p = AKC ? gA + m * g.lda + k : gA + k * g.lda + m;
+        const bool full = AKC ? (m < g.M && k + 3 < kend) : (k < kend && m + 3 < g.M);
+        if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+          load4(p, ra[u]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const bool ok = AKC ? (m < g.M && k + s < kend) : (k < kend && m + s < g.M);
+            ra[u][s] = ok ? cvt<float>(p[s]) : 0.f;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int t = tid + T * u;
+      if (t < GB) {
+        int64_t n, k;
+        if (BKC) {
+          n = N0 + t / (BK / 4);
+          k = k0 + 4 * (t % (BK / 4));
+        } else {
+          k = k0 + t / (BN / 4);
+          n = N0 + 4 * (t % (BN / 4));
+        }
+        const TB *p = BKC ? gB + n * g.ldb + k : gB + k * g.ldb + n;
+        const bool full = BKC ? (n < g.N && k + 3 < kend) : (k < kend && n + 3 < g.N);
+        if (full && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+          load4(p, rb[u]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const bool ok = BKC ? (n < g.N && k + s < kend) : (k < kend && n + s < g.N);
+            rb[u][s] = ok ? cvt<float>(p[s]) : 0.f;
+          }
+        }
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < RA; ++u) {
+      const int t = tid + T * u;
+      if (t < GA) {
+        if (AKC) {
+          const int m = t / (BK / 4), k = 4 * (t % (BK / 4));
+#pragma unroll
+          for (int s = 0; s < 4; ++s) As[buf][m][k + s] = (__bf16)ra[u][s];
+        } else {
+          const int k = t / (BM / 4), m = 4 * (t % (BM / 4));
+#pragma unroll
+          for (int s = 0; s < 4; ++s) As[buf][m + s][k] = (__bf16)ra[u][s];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int t = tid + T * u;
+      if (t < GB) {
+        if (BKC) {
+          const int n = t / (BK / 4), k = 4 * (t % (BK / 4));
+#pragma unroll
+          for (int s = 0; s < 4; ++s) Bs[buf][n][k + s] = (__bf16)rb[u][s];
+        } else {
+          const int k = t / (BN / 4), n = 4 * (t % (BN / 4));
+#pragma unroll
+          for (int s = 0; s < 4; ++s) Bs[buf][n + s][k] = (__bf16)rb[u][s];
+        }
+      }
+    }
+  };
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  const int am = wm * 16 * TM + r, bn = wn * 16 * TN + r;
+
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
+    bf8_t a[TM], b[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const bf8_t *>(&As[buf][am + 16 * i][8 * q]);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const bf8_t *>(&Bs[buf][bn + 16 * j][8 * q]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  const int64_t m0 = M0 + wm * 16 * TM, n0 = N0 + wn * 16 * TN;
+  part_t *part = static_cast<part_t *>(g.partial);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t col = n0 + 16 * j + r;
+      if (col >= g.N) continue;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int64_t row = m0 + 16 * i + MT::row(q, jj);
+        if (row >= g.M) continue;
+        const part_t v = acc[i][j][jj];
+        if (g.splits > 1) {
+          part[(split * g.M + row) * g.N + col] = v;
+        } else {
+          TC *c = gC + row * g.ldc + col;
+          const double out = (g.beta != 0.0)
+                                 ? g.alpha * (double)v + g.beta * cvt<double>(*c)
+                                 : g.alpha * (double)v;
+          *c = (TC)out;
+        }
+      }
+    }
+}
+
+// the body for the x4 instructions or the bf16 one
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN>
 __device__ __forceinline__ void gemm_any_body(const GemmX &g, const TileMap &tm, int64_t wg) {
   if constexpr (MT::CPL == 4)
     gemm_lds_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
   else
-    gemm_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
+    gemm_lds_bf16_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
 }
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
@@ -536,14 +581,13 @@ __global__ __launch_bounds__(256) void splitk_group_reduce_kernel(const GemmGrou
 struct Variant {
   int tm, tn, wm, wn;
 };
-// LDS-staged body (f64, f32): 32x64, 64x32 (eight wavefronts), 64x64,
-// 128x128 outputs per workgroup; register-streaming body (bf16): 16x64,
-// 64x16, 32x32, 64x64
+// Output tile per workgroup, every arithmetic: 32x64, 64x32 (eight
+// wavefronts each), 64x64, 128x128 (four wavefronts each)
 constexpr Variant kVarLds[] = {{1, 1, 2, 4}, {1, 1, 4, 2}, {2, 2, 2, 2}, {4, 4, 2, 2}};
-constexpr Variant kVarReg[] = {{1, 1, 1, 4}, {1, 1, 4, 1}, {1, 1, 2, 2}, {2, 2, 2, 2}};
 
 const Variant &variant_of(DType math, int v) {
-  return math == DType::BF16 ? kVarReg[v] : kVarLds[v];
+  (void)math;  // one table for every arithmetic
+  return kVarLds[v];
 }
 
 void tile_of(DType math, int v, int64_t *bm, int64_t *bn) {
@@ -585,36 +629,19 @@ void launch_one(const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC>
 void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
                    const GemmGroupEntry *tab, int count) {
-  if constexpr (MT::CPL == 4) {
-    switch (v) {
-      case 0:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 4>(g, tm, grid, s, tab, count);
-        break;
-      case 1:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 2>(g, tm, grid, s, tab, count);
-        break;
-      case 2:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
-        break;
-      default:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 4, 4, 2, 2>(g, tm, grid, s, tab, count);
-        break;
-    }
-  } else {
-    switch (v) {
-      case 0:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 1, 4>(g, tm, grid, s, tab, count);
-        break;
-      case 1:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 1>(g, tm, grid, s, tab, count);
-        break;
-      case 2:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 2>(g, tm, grid, s, tab, count);
-        break;
-      default:
-        launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
-        break;
-    }
+  switch (v) {
+    case 0:
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 4>(g, tm, grid, s, tab, count);
+      break;
+    case 1:
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 2>(g, tm, grid, s, tab, count);
+      break;
+    case 2:
+      launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
+      break;
+    default:
+      launch_one<MT, TA, TB, TC, AKC, BKC, 4, 4, 2, 2>(g, tm, grid, s, tab, count);
+      break;
   }
 }
 
