@@ -43,33 +43,45 @@ METRIC = "ms per randomized TT-rounding + %MFMA peak; mixed-prec vs FP64 at tol"
 MEASURED_TRAFFIC = {("single_tt", "f64", 0): {"read_bytes": 33.49e6, "write_bytes": 9.60e6}}
 
 SITE_NAMES = {0: "wchain_z", 1: "wchain_w", 2: "sweep_y", 3: "sweep_m", 4: "sweep_next",
-              5: "trunc"}
+              5: "trunc", 6: "wchain_fused"}
 SITE_KERNEL = {0: "gemm_kernel (V(Y_n) W_n, partial contractions)",
                1: "gemm_kernel (H(Z_n) H(Sk_n)^T, partial contractions)",
                2: "gemm_kernel (Z_n W_n, sketch of the sweep)",
                3: "gemm_kernel (Q^T Z_n, projection)",
-               4: "gemm_kernel (M_n H(Y_{n+1}), next core)"}
+               4: "gemm_kernel (M_n H(Y_{n+1}), next core)",
+               6: "wfuse_kernel (H(V(Y_n) W_n) H(Sk_n)^T in one kernel, partial contractions)"}
+WCHAIN_SITES = (0, 1, 6)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def site_launches(site, dims, ell, summand_ranks):
-    """(M, N, K) of every launch from one call site, in launch order."""
+def site_launches(site, dims, ell, summand_ranks, fused=False):
+    """(M, N, K) of every product from one call site, in launch order.  With
+    `fused` the interior levels of the W chain are one kernel each (site 6,
+    two products per launch) and sites 0 and 1 keep only the rest."""
     N = len(dims)
     Rs = [1] + [sum(R[n] for R in summand_ranks) for n in range(1, N)] + [1]
     out = []
     if site == 0:  # V(Z_n) = V(Y_n) W_n, n = N-1..2, per summand
         for n in range(N - 1, 1, -1):
             for R in summand_ranks:
-                out.append((R[n - 1] * dims[n - 1], ell[n], R[n]))
+                if not fused:
+                    out.append((R[n - 1] * dims[n - 1], ell[n], R[n]))
     elif site == 1:  # W_{N-1}, then W_{n-1} = H(Z_n) H(Sk_n)^T
         for R in summand_ranks:
             out.append((R[N - 1], ell[N - 1], dims[N - 1]))
         for n in range(N - 1, 1, -1):
             for R in summand_ranks:
-                out.append((R[n - 1], ell[n - 1], dims[n - 1] * ell[n]))
+                if not fused:
+                    out.append((R[n - 1], ell[n - 1], dims[n - 1] * ell[n]))
+    elif site == 6:  # both products of an interior level, per summand
+        for n in range(N - 1, 1, -1):
+            for R in summand_ranks:
+                if fused:
+                    out.append((R[n - 1] * dims[n - 1], ell[n], R[n]))
+                    out.append((R[n - 1], ell[n - 1], dims[n - 1] * ell[n]))
     elif site == 2:  # Y_n = Z_n W_n
         for n in range(1, N):
             out.append((ell[n - 1] * dims[n - 1], ell[n], Rs[n]))
@@ -85,16 +97,25 @@ def site_launches(site, dims, ell, summand_ranks):
     return out
 
 
-def site_flops(site, dims, ell, summand_ranks):
+def site_flops(site, dims, ell, summand_ranks, fused=False):
     """Algorithmic flops (2 M N K per product) of one step's launches."""
-    return sum(2.0 * m * n * k for m, n, k in site_launches(site, dims, ell, summand_ranks))
+    return sum(2.0 * m * n * k
+               for m, n, k in site_launches(site, dims, ell, summand_ranks, fused))
 
 
-def site_bytes(site, dims, ell, summand_ranks, elem):
+def site_bytes(site, dims, ell, summand_ranks, elem, fused=False):
     """Algorithmic HBM bytes of one step's launches: each operand read once,
-    the result written once (elem bytes per value)."""
-    return sum(float(elem) * (m * k + k * n + m * n)
-               for m, n, k in site_launches(site, dims, ell, summand_ranks))
+    the result written once (elem bytes per value).  A fused level reads
+    Y_n, W_n and Sk_n and writes W_{n-1}; Z_n never reaches memory."""
+    if site != 6:
+        return sum(float(elem) * (m * k + k * n + m * n)
+                   for m, n, k in site_launches(site, dims, ell, summand_ranks, fused))
+    pr = site_launches(site, dims, ell, summand_ranks, fused)
+    tot = 0.0
+    for (m1, n1, k1), (m2, n2, k2) in zip(pr[0::2], pr[1::2]):
+        # (R0 I, L1, R1) then (R0, L0, I L1): Y + W + Sk + W_{n-1}
+        tot += float(elem) * (m1 * k1 + k1 * n1 + k2 * n2 + m2 * n2)
+    return tot
 
 
 def make_workload(name):
@@ -260,7 +281,8 @@ def main():
     # launch stream around every launch of the site)
     wmath, smath = SITE_MATH[args.prec]
     site_ms = {}
-    for site in (0, 1, 2, 3, 4):
+    fused = False
+    for site in (6, 0, 1, 2, 3, 4):
         L.check(L.lib().tt_timing_start(site, 4096 * args.steps))
         for _ in range(args.steps):
             step()
@@ -268,20 +290,25 @@ def main():
         tot = ctypes.c_double(0)
         cnt = ctypes.c_int32(0)
         L.check(L.lib().tt_timing_stop(ctypes.byref(tot), ctypes.byref(cnt)))
-        fl = site_flops(site, dims, ell, summand_ranks) * args.steps
+        if site == 6:
+            fused = cnt.value > 0
+            if not fused:
+                continue
+        fl = site_flops(site, dims, ell, summand_ranks, fused) * args.steps
         site_ms[site] = (tot.value, cnt.value, fl)
         log(f"site {SITE_NAMES[site]}: {cnt.value // args.steps} launches/step, "
             f"{tot.value / max(cnt.value, 1) * 1e3:.1f} us avg, {tot.value / args.steps:.3f} ms/step, "
             f"{fl / (tot.value * 1e-3) / 1e12 if tot.value else 0:.2f} TFLOP/s")
-    # the roofline covers the partial contraction V(Y_n) W_n unless --site says otherwise (it
-    # and the next-core product are the two largest contractions, within a few per cent)
-    site = args.site if args.site is not None else 0
+    # the roofline covers the partial contractions of one interior level (the fused kernel,
+    # else V(Y_n) W_n) unless --site says otherwise: the largest contractions of the method
+    site = args.site if args.site is not None else (6 if fused else 0)
     tot_ms, cnt, flops = site_ms[site]
-    math_dt = wmath if site in (0, 1) else smath
+    math_dt = wmath if site in WCHAIN_SITES else smath
     per_launch_us = tot_ms / max(cnt, 1) * 1e3
     if math_dt == "bf16":
         # bandwidth-bound at these shapes: algorithmic bytes against HBM peak
-        nbytes = site_bytes(site, dims, ell, summand_ranks, STORE_BYTES[args.prec]) * args.steps
+        nbytes = site_bytes(site, dims, ell, summand_ranks, STORE_BYTES[args.prec],
+                            fused) * args.steps
         achieved = nbytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
@@ -297,7 +324,7 @@ def main():
         roofline["traffic"] = mt["read_bytes"] + mt["write_bytes"]
         roofline["traffic_detail"] = dict(mt, unit="bytes per launch",
                                           algorithmic_bytes=site_bytes(site, dims, ell,
-                                                                       summand_ranks, 8)
+                                                                       summand_ranks, 8, fused)
                                           / max(cnt // max(args.steps, 1), 1))
     roofline.update(kernel=SITE_KERNEL[site], math=math_dt,
                     launches_per_step=cnt // max(args.steps, 1),

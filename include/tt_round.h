@@ -341,7 +341,9 @@ typedef enum {
   TT_SITE_SWEEP_Y = 2,     /* Y_n = Z_n W_n                  (Algorithm 5)   */
   TT_SITE_SWEEP_M = 3,     /* M_n = Q^T Z_n                  (Algorithm 5)   */
   TT_SITE_SWEEP_NEXT = 4,  /* H(X_{n+1}) = M_n H(Y_{n+1})    (Algorithm 5)   */
-  TT_SITE_TRUNC = 5        /* truncation GEMMs                               */
+  TT_SITE_TRUNC = 5,       /* truncation GEMMs                               */
+  TT_SITE_WCHAIN_FUSED = 6 /* W_{n-1} = H(V(Y_n) W_n) H(R_n)^T in one kernel
+                              (its split sum not included)  (Algorithm 3)  */
 } tt_timing_site;
 TT_API int tt_timing_start(int32_t site, int32_t capacity);
 TT_API int tt_timing_stop(double *total_ms, int32_t *launches);

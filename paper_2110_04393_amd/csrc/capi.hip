@@ -91,7 +91,12 @@ int check_dtype(int32_t dtype, const Prec &p) {
 
 size_t dtype_bytes(DType t) { return t == DType::F64 ? 8 : (t == DType::F32 ? 4 : 2); }
 
+// W-chain levels: fused kernel where it fits (0) or always two products (1)
+static int g_wchain_mode = 0;
+
 void read_env() {
+  const char *w = std::getenv("TT_WCHAIN");
+  g_wchain_mode = (w && !std::strcmp(w, "gemm")) ? 1 : 0;
   const char *q = std::getenv("TT_QR");
   if (!q) qr_set_mode(0);
   else if (!std::strcmp(q, "householder")) qr_set_mode(1);
@@ -122,6 +127,22 @@ struct Timer {
 constexpr int kTimingRepeats = 8;
 Timer g_timer;
 
+// run(): the launches of one product; timed when the recorder is armed for
+// its site.  Back-to-back repeats of the same product amortise the event
+// overhead; only products that overwrite their output can be repeated.
+template <class Run>
+int timed_launch(Ctx &c, int site, bool repeatable, Run run) {
+  const bool timed = site >= 0 && site == g_timer.site && g_timer.used + 2 <= g_timer.ev.size();
+  if (!timed) return run();
+  const int reps = repeatable ? kTimingRepeats : 1;
+  TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used], c.s));
+  for (int r = 0; r < reps; ++r) TTR_TRY(run());
+  TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used + 1], c.s));
+  g_timer.reps.push_back(reps);
+  g_timer.used += 2;
+  return TT_OK;
+}
+
 int gemm(Ctx &c, GemmX g, int site = -1) {
   const int sp = (g.batch > 1) ? 1 : gemm_pick_splits(g.M, g.N, g.K, g.math);
   const size_t need = sp > 1 ? (size_t)sp * g.M * g.N * gemm_acc_bytes(g.math) : 0;
@@ -130,20 +151,7 @@ int gemm(Ctx &c, GemmX g, int site = -1) {
   if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split-K buffer too small");
   g.splits = sp;
   g.partial = c.partial;
-  const bool timed = site >= 0 && site == g_timer.site && g_timer.used + 2 <= g_timer.ev.size();
-  if (timed) {
-    // back-to-back repeats of the same product amortise the event overhead;
-    // only products that overwrite C (beta = 0) can be repeated
-    const int reps = (g.beta == 0.0) ? kTimingRepeats : 1;
-    TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used], c.s));
-    for (int r = 0; r < reps; ++r) TTR_TRY(gemmx_run(g, c.s));
-    TTR_HIP(hipEventRecord(g_timer.ev[g_timer.used + 1], c.s));
-    g_timer.reps.push_back(reps);
-    g_timer.used += 2;
-  } else {
-    TTR_TRY(gemmx_run(g, c.s));
-  }
-  return TT_OK;
+  return timed_launch(c, site, g.beta == 0.0, [&] { return gemmx_run(g, c.s); });
 }
 template <typename T>
 int gemm(Ctx &c, const Gemm<T> &g, int site = -1) {
@@ -237,6 +245,32 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
   for (int n = N - 1; n >= 2; --n) {
     const int64_t I = dims[n - 1];
     for (int j = 0; j < s; ++j) {
+      WFuse f;  // W_{n-1} = H(V(Y_n) W_n) H(Sk_n)^T in one kernel
+      f.Y = Y[(size_t)j * N + n - 1];
+      f.W = wrow(j, n);
+      f.Sk = Sk[n - 1];
+      f.C = wrow(j, n - 1);
+      f.t = DTypeOf<T>::value;
+      f.R0 = R[j][n - 1];
+      f.I = I;
+      f.R1 = R[j][n];
+      f.L1 = L[n];
+      f.L0 = L[n - 1];
+      // the dry pass sizes the split buffer for both forms (the core's
+      // alignment, which the fused kernel needs, is known only at run time)
+      const bool fusable = g_wchain_mode == 0 && p.wmath == f.t && p.sk == f.t &&
+                           wfuse_supported(f);
+      if (fusable) {
+        const size_t need = (size_t)wfuse_partial_elems(f) * sizeof(T);
+        c.partial_need = std::max(c.partial_need, need);
+        if (!c.dry && reinterpret_cast<uintptr_t>(f.Y) % 16 == 0) {
+          if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split buffer too small");
+          TTR_TRY(timed_launch(c, TT_SITE_WCHAIN_FUSED, true,
+                               [&] { return wfuse_run(f, c.partial, c.partial_cap, c.s); }));
+          TTR_TRY(wfuse_sum(f, c.partial, c.s));
+          continue;
+        }
+      }
       GemmX g;  // V(Z_n) = V(Y_n) W_n
       g.A = Y[(size_t)j * N + n - 1];
       g.lda = R[j][n];
@@ -1093,6 +1127,7 @@ int sketch_exec(Ctx &c, const Problem &P, const Prec &p, std::vector<void *> &Sk
 // the partial buffer first in the workspace.
 template <typename F>
 int run_with_workspace(void *workspace, size_t ws_bytes, hipStream_t s, F body) {
+  read_env();  // the query and the run see the same path choices
   Ctx dry;
   dry.dry = true;
   TTR_TRY(body(dry));
@@ -1116,6 +1151,7 @@ int run_with_workspace(void *workspace, size_t ws_bytes, hipStream_t s, F body) 
 template <typename F>
 int measure_workspace(F body, size_t *bytes) {
   if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  read_env();
   Ctx dry;
   dry.dry = true;
   TTR_TRY(body(dry));
@@ -1458,7 +1494,7 @@ int tt_round_rand_backward(int32_t N, const int64_t *dims, const int64_t *ranks,
 }
 
 int tt_timing_start(int32_t site, int32_t capacity) {
-  if (site < TT_SITE_WCHAIN_Z || site > TT_SITE_TRUNC) return fail(TT_EINVAL, "unknown site");
+  if (site < TT_SITE_WCHAIN_Z || site > TT_SITE_WCHAIN_FUSED) return fail(TT_EINVAL, "unknown site");
   if (capacity < 1 || capacity > (1 << 20)) return fail(TT_EINVAL, "capacity out of range");
   for (hipEvent_t e : g_timer.ev) (void)hipEventDestroy(e);
   g_timer.ev.assign(2 * (size_t)capacity, nullptr);
@@ -1493,6 +1529,7 @@ int tt_partial_contractions_rl_workspace(int32_t N, const int64_t *dims, const i
   TTR_TRY(check_shape(N, dims, ranks_x, "X"));
   TTR_TRY(check_shape(N, dims, ranks_y, "Y"));
   if (N < 2) return fail(TT_EINVAL, "partial contractions need N >= 2");
+  read_env();
   Prec pc;
   TTR_TRY(prec_cfg(prec, pc));
   pc.sk = pc.store;
@@ -1516,6 +1553,7 @@ int tt_partial_contractions_rl(int32_t N, const int64_t *dims, const int64_t *ra
   TTR_TRY(check_shape(N, dims, ranks_x, "X"));
   TTR_TRY(check_shape(N, dims, ranks_y, "Y"));
   if (N < 2) return fail(TT_EINVAL, "partial contractions need N >= 2");
+  read_env();
   Prec pc;
   TTR_TRY(prec_cfg(prec, pc));
   pc.sk = pc.store;

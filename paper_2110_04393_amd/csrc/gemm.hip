@@ -743,22 +743,28 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
   const int64_t grid = tm.tiles_m * tm.tiles_n * (g.batch > 1 ? g.batch : used_splits);
   if (!dispatch(v, gg, tm, grid, s)) return fail(TT_EINVAL, "internal: gemm type combination");
   TTR_HIP(hipGetLastError());
-  if (gg.splits > 1) {
-    const int64_t total = g.M * g.N;
-    const dim3 gr((unsigned)((total + kRedElems - 1) / kRedElems)), bl(256);
-    if (g.math == DType::F64) {
-      if (g.tc == DType::F64)
-        hipLaunchKernelGGL((splitk_reduce_kernel<double, double>), gr, bl, 0, s, gg);
-      else
-        hipLaunchKernelGGL((splitk_reduce_kernel<double, float>), gr, bl, 0, s, gg);
-    } else {
-      if (g.tc == DType::F64)
-        hipLaunchKernelGGL((splitk_reduce_kernel<float, double>), gr, bl, 0, s, gg);
-      else
-        hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), gr, bl, 0, s, gg);
-    }
-    TTR_HIP(hipGetLastError());
+  if (gg.splits > 1) TTR_TRY(gemm_reduce_splits(gg, s));
+  return TT_OK;
+}
+
+int gemm_reduce_splits(const GemmX &g, hipStream_t s) {
+  if (g.splits <= 1 || g.M <= 0 || g.N <= 0) return TT_OK;
+  if (!g.partial) return fail(TT_EINVAL, "internal: split sum without partials");
+  if (g.splits > kRedMaxGroups * kSplitGroup) return fail(TT_EINVAL, "internal: too many K splits");
+  const int64_t total = g.M * g.N;
+  const dim3 gr((unsigned)((total + kRedElems - 1) / kRedElems)), bl(256);
+  if (g.math == DType::F64) {
+    if (g.tc == DType::F64)
+      hipLaunchKernelGGL((splitk_reduce_kernel<double, double>), gr, bl, 0, s, g);
+    else
+      hipLaunchKernelGGL((splitk_reduce_kernel<double, float>), gr, bl, 0, s, g);
+  } else {
+    if (g.tc == DType::F64)
+      hipLaunchKernelGGL((splitk_reduce_kernel<float, double>), gr, bl, 0, s, g);
+    else
+      hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), gr, bl, 0, s, g);
   }
+  TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 

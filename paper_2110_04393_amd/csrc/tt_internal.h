@@ -126,6 +126,29 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t K, DType math);
 int gemm_used_splits(const GemmX &g);
 size_t gemm_acc_bytes(DType math);
 int gemmx_run(const GemmX &g, hipStream_t s);
+// C = alpha * (sum of the g.splits partials [split][M][N] in g.partial) +
+// beta * C, summed in a fixed order (accumulator type of g.math)
+int gemm_reduce_splits(const GemmX &g, hipStream_t s);
+
+// One level of the W chain (Algorithm 3) in one kernel:
+// C = H(V(Y) W) H(Sk)^T for Y (R0 x I x R1), W (R1 x L1, ld L1),
+// Sk (L0 x I x L1), C (R0 x L0, ld L0), all of type t (F64 or F32, which is
+// also the arithmetic).  wfuse_supported tells whether the shapes fit the
+// kernel (R1 a multiple of 4, L1 and L0 at most 128, W_n^T within the LDS);
+// the core Y must also be 16-byte aligned.  wfuse_partial_elems is the split
+// buffer it needs (elements of t).
+// wfuse_run launches the kernel (C itself, or the splits of C into partial);
+// wfuse_sum then adds the splits into C (nothing to do with one split).
+struct WFuse {
+  const void *Y = nullptr, *W = nullptr, *Sk = nullptr;
+  void *C = nullptr;
+  DType t = DType::F64;
+  int64_t R0 = 0, I = 0, R1 = 0, L1 = 0, L0 = 0;
+};
+bool wfuse_supported(const WFuse &f);
+int64_t wfuse_partial_elems(const WFuse &f);
+int wfuse_run(const WFuse &f, void *partial, size_t partial_bytes, hipStream_t s);
+int wfuse_sum(const WFuse &f, void *partial, hipStream_t s);
 
 // same-type convenience form
 template <typename T>

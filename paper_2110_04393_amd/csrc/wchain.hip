@@ -1,0 +1,449 @@
+// One level of the partial contractions of Algorithm 3 in a single kernel.
+//
+// For one TT Y (core n: R0 x I x R1), one sketch core Sk_n (L0 x I x L1) and
+// W_n (R1 x L1) it computes
+//   W_{n-1}(a, b) = sum_i sum_c Z(a, i, c) Sk_n(b, i, c),
+//   Z(a, i, c)    = sum_k Y_n(a, i, k) W_n(k, c),
+// i.e. W_{n-1} = H(V(Y_n) W_n) H(Sk_n)^T (the two products of one step of
+// the recursion that defines W_n), without writing Z = V(Y_n) W_n to memory.
+//
+// Work decomposition.  A unit is (16 consecutive a, one i): its Z block is
+// 16 x L1.  A workgroup owns one 16-row a-block and a range of i; it holds
+// W_n^T in LDS (all of it: L1 rows, R1 columns) and has ncb = ceil(L1 / 16)
+// wavefronts per unit lane (one per 16-wide c-block) and one or two unit
+// lanes.  Per unit, the wavefront of c-block cb
+//   1. forms Z^T(c-block, a-block) = W^T(c-block, :) Y_i^T (:, a-block) with
+//      the x4 MFMA instruction (W^T fragments from LDS, Y fragments straight
+//      from memory, four 16-wide k-chunks in flight per lane),
+//   2. multiplies its accumulator, still in registers, by Sk_n(:, i, c-block)^T
+//      into the running W_{n-1}(a-block, :) accumulator.
+// Step 2 needs lane (r, q) of the accumulator to hold Z(a0 + r, c) for four
+// consecutive c: the accumulator of the f32 instruction holds rows 4 q + j
+// already; for the f64 instruction (rows q + 4 j) the W^T rows are staged in
+// the permuted order m -> 4 (m % 4) + m / 4, which gives the same property.
+// At the end the wavefronts' accumulators are summed in LDS in a fixed order
+// and written as one split of the result (summed over the i-ranges by the
+// split-K reduction of the GEMM module) or directly when there is one range.
+#include <algorithm>
+
+#include "tt_internal.h"
+#include "wave.h"
+
+namespace ttr {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+struct FuseF64 {
+  typedef double T;
+  typedef d4_t acc_t;
+  __device__ static acc_t mma(T a, T b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator row of register j in lane quad q
+  __device__ static int row(int q, int j) { return q + 4 * j; }
+  // c offset (within a 16-block) staged in W^T row m
+  __host__ __device__ static int perm(int m) { return 4 * (m & 3) + (m >> 2); }
+  __device__ static void store4(T *p, const T (&v)[4]) {
+    *reinterpret_cast<d2_t *>(p) = d2_t{v[0], v[1]};
+    *reinterpret_cast<d2_t *>(p + 2) = d2_t{v[2], v[3]};
+  }
+  __device__ static void load4(const T *p, T (&o)[4]) {
+    const d2_t x = *reinterpret_cast<const d2_t *>(p);
+    const d2_t y = *reinterpret_cast<const d2_t *>(p + 2);
+    o[0] = x[0];
+    o[1] = x[1];
+    o[2] = y[0];
+    o[3] = y[1];
+  }
+};
+struct FuseF32 {
+  typedef float T;
+  typedef f4_t acc_t;
+  __device__ static acc_t mma(T a, T b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int q, int j) { return 4 * q + j; }
+  __host__ __device__ static int perm(int m) { return m; }
+  __device__ static void store4(T *p, const T (&v)[4]) {
+    *reinterpret_cast<f4_t *>(p) = f4_t{v[0], v[1], v[2], v[3]};
+  }
+  __device__ static void load4(const T *p, T (&o)[4]) {
+    const f4_t x = *reinterpret_cast<const f4_t *>(p);
+    o[0] = x[0];
+    o[1] = x[1];
+    o[2] = x[2];
+    o[3] = x[3];
+  }
+};
+
+struct WFuseArgs {
+  const void *Y, *W, *Sk;
+  void *out;  // W_{n-1} (ld L0) with one i-range, else partials [groups][R0][L0]
+  int64_t R0, I, R1, L1, L0;
+  int64_t nablk, ipg;
+  int nch, ncb, nbb, uln, ldk;
+  int direct;
+};
+
+extern __shared__ __attribute__((aligned(16))) unsigned char wf_lds[];
+
+// Operands are read with raw buffer loads: a lane whose fragment lies outside
+// the operand passes an offset beyond the buffer's size and reads zeros, so
+// every lane issues the same loads (no branches, and the waits on the
+// in-order load counter stay exact).
+constexpr uint32_t kOutside = 0x80000000u;  // beyond every buffer (< 2 GiB)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  // dword 3: 32-bit data format, as for untyped loads on gfx9-class parts
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&o)[4]) {
+  const u4_t x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  const u4_t y = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+  const d2_t a = __builtin_bit_cast(d2_t, x), b = __builtin_bit_cast(d2_t, y);
+  o[0] = a[0];
+  o[1] = a[1];
+  o[2] = b[0];
+  o[3] = b[1];
+}
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4]) {
+  const f4_t a = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  o[0] = a[0];
+  o[1] = a[1];
+  o[2] = a[2];
+  o[3] = a[3];
+}
+__device__ __forceinline__ double bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+constexpr int kWfThreads = 512;
+
+template <class F, int NCB, int NBB, bool VS>
+__global__ __launch_bounds__(kWfThreads) void wfuse_kernel(const WFuseArgs p) {
+  typedef typename F::T T;
+  typedef typename F::acc_t acc_t;
+  constexpr int ULN = 8 / NCB;  // unit lanes
+  // staged Y rows: 16 values + one 16-byte step, which spreads a fragment
+  // read over the LDS banks and keeps rows 16-byte aligned
+  constexpr int YR = 16 + 16 / (int)sizeof(T);
+  constexpr int POS = 16 * YR;  // values of one staged position (16 rows)
+  T *Wt = reinterpret_cast<T *>(wf_lds);
+  const T *Y = static_cast<const T *>(p.Y);
+  const T *W = static_cast<const T *>(p.W);
+  const T *Sk = static_cast<const T *>(p.Sk);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r = lane & 15, q = lane >> 4;
+  const int cb = wave % NCB, ul = wave / NCB;
+  const int64_t ab = blockIdx.x % p.nablk, grp = blockIdx.x / p.nablk;
+  const int64_t a0 = 16 * ab;
+  const int64_t ib = grp * p.ipg, ie = min(p.I, ib + p.ipg);
+  const int rows = 16 * NCB, kp = 16 * p.nch;
+  const int nch = p.nch;
+  // staged Y: per unit lane two buffers of NCB positions, after W^T
+  T *Ys = Wt + rows * p.ldk + ul * 2 * NCB * POS;
+
+  // units of this lane: i = ib + ul, ib + ul + ULN, ... (< ie)
+  const int64_t left = ie - ib - ul;
+  const int nu = left > 0 ? (int)((left + ULN - 1) / ULN) : 0;
+  // the chunks of a unit are padded to nchp, a multiple of 8 (so of NCB):
+  // a batch is NCB consecutive positions of one unit, position NCB g + w of
+  // batch g is loaded by wavefront w of the lane
+  const int nchp = (nch + 7) / 8 * 8;
+  const int bpu = nchp / NCB;  // batches per unit
+  const int64_t arow = a0 + r;
+  const bool arow_ok = arow < p.R0;
+  constexpr uint32_t es = sizeof(T);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y, (uint32_t)(p.R0 * p.I * p.R1 * es));
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(Sk, (uint32_t)(p.L0 * p.I * p.L1 * es));
+
+  // Y fragment of this wavefront's position in batch g: lane (r, q) holds
+  // Y(a0 + r, i, 16 c + 4 q + t); R1 is a multiple of 4, so the four values
+  // are all inside the row or all outside (chunks c >= nch, units u >= nu
+  // and rows beyond R0 read zeros).  Offsets fit in 32 bits.
+  const uint32_t R1 = (uint32_t)p.R1, L1 = (uint32_t)p.L1, I = (uint32_t)p.I;
+  const uint32_t y_lane = ((uint32_t)arow * I * R1 + 4 * q) * es;
+  auto loady = [&](int g, T(&v)[4]) __attribute__((always_inline)) {
+    const int u = g / bpu, c = (g - u * bpu) * NCB + cb;
+    const uint32_t i = (uint32_t)(ib + ul) + (uint32_t)u * ULN;
+    const bool ok = arow_ok && u < nu && c < nch && 16 * c + 4 * q < (int)R1;
+    bload4(ry, ok ? y_lane + (i * R1 + 16 * c) * es : kOutside, v);
+  };
+  // the wavefront's staged position of buffer b: row r, values 4 q .. 4 q + 3
+  auto stagey = [&](int b, const T(&v)[4]) __attribute__((always_inline)) {
+    F::store4(Ys + (b * NCB + cb) * POS + r * YR + 4 * q, v);
+  };
+  // Sk fragments of unit u: lane (r, q) holds Sk(16 bb + r, i, cc + j)
+  const int cc = 16 * cb + 4 * q;  // first c of this lane's P2 k-slots
+  const uint32_t s_lane = ((uint32_t)r * I * L1 + cc) * es;
+  auto loadsk = [&](int u, T(&v)[NBB][4]) __attribute__((always_inline)) {
+    const uint32_t i = (uint32_t)(ib + ul) + (uint32_t)u * ULN;
+#pragma unroll
+    for (int bb = 0; bb < NBB; ++bb) {
+      const bool bok = u < nu && 16 * bb + r < p.L0;
+      const uint32_t off = s_lane + (16 * bb * I + i) * L1 * es;
+      if constexpr (VS) {
+        // L1 is a multiple of 4: the four values are inside the row or not
+        bload4(rs, bok && cc < (int)L1 ? off : kOutside, v[bb]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          v[bb][j] = bload1(rs, bok && cc + j < (int)L1 ? off + j * es : kOutside, T(0));
+      }
+    }
+  };
+
+  // batches 0 and 1 and the first unit's Sk fragments go out first
+  T yr[2][4];
+  T sk[NBB][4];
+  loady(0, yr[0]);
+  loady(1, yr[1]);
+  loadsk(0, sk);
+
+  // W^T into LDS: row m holds column 16 (m / 16) + perm(m % 16) of W_n,
+  // zero beyond R1 and L1 (so padded k and c contribute nothing); sixteen
+  // loads per thread in flight before their LDS stores
+  {
+    const __amdgpu_buffer_rsrc_t rw = make_rsrc(W, (uint32_t)(p.R1 * p.L1 * es));
+    constexpr int kBatch = 16;
+    const int n = rows * kp, step = blockDim.x;
+    for (int e0 = tid; e0 < n; e0 += kBatch * step) {
+      T v[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int e = e0 + b * step;
+        const int k = e / rows, m = e - k * rows;
+        const int c = 16 * (m >> 4) + F::perm(m & 15);
+        const bool ok = e < n && k < p.R1 && c < p.L1;
+        v[b] = bload1(rw, ok ? (uint32_t)(((int64_t)k * p.L1 + c) * es) : kOutside, T(0));
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int e = e0 + b * step;
+        const int k = e / rows, m = e - k * rows;
+        if (e < n) Wt[m * p.ldk + k] = v[b];
+      }
+    }
+  }
+  stagey(0, yr[0]);
+  __syncthreads();
+
+  acc_t acc1[2], acc2[NBB];
+  acc1[0] = acc1[1] = acc_t{0, 0, 0, 0};
+#pragma unroll
+  for (int bb = 0; bb < NBB; ++bb) acc2[bb] = acc_t{0, 0, 0, 0};
+  const T *wrow = Wt + (16 * cb + r) * p.ldk + 4 * q;
+  const T *yfrag = Ys + r * YR + 4 * q;
+
+  // Batch g (buffer g % 2): issue the loads of batch g + 2 into the
+  // registers of batch g (already staged), run the NCB positions of batch g
+  // from LDS, stage batch g + 1 into the other buffer, barrier.  Each unit
+  // ends with its Sk product.  All wavefronts run the same number of
+  // batches (units past the lane's last read zeros), so the barriers match.
+  const int nbw = (int)((p.ipg + ULN - 1) / ULN) * bpu;  // batches of every lane
+  int g = 0;
+  for (int u = 0; u * bpu < nbw; ++u) {
+    for (int bi = 0; bi < bpu; ++bi, ++g) {
+      const int b = g & 1;
+      if (b == 0) loady(g + 2, yr[0]); else loady(g + 2, yr[1]);
+      static_for<0, NCB>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
+        const int c = bi * NCB + s;
+        if (c < nch) {
+          T w[4], y[4];
+          F::load4(wrow + 16 * c, w);
+          F::load4(yfrag + (b * NCB + s) * POS, y);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc1[t & 1] = F::mma(w[t], y[t], acc1[t & 1]);
+        }
+      });
+      if (b == 0) stagey(1, yr[1]); else stagey(0, yr[0]);
+      __syncthreads();
+    }
+    // unit complete: Z(a0 + r, i, cc + j) = register j of the sum; b-blocks
+    // beyond L0 multiply zeros
+    const acc_t z = acc1[0] + acc1[1];
+    acc1[0] = acc1[1] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int bb = 0; bb < NBB; ++bb) acc2[bb] = F::mma(z[j], sk[bb][j], acc2[bb]);
+    loadsk(u + 1, sk);
+  }
+
+  // sum of the wavefronts' W_{n-1}(a-block, :) in wavefront order
+  __syncthreads();
+  T *red = reinterpret_cast<T *>(wf_lds);
+  const int ncol = 16 * p.nbb;
+#pragma unroll
+  for (int bb = 0; bb < NBB; ++bb)
+    if (bb < p.nbb) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[(wave * 16 + F::row(q, j)) * ncol + 16 * bb + r] = acc2[bb][j];
+    }
+  __syncthreads();
+  const int waves = blockDim.x >> 6;
+  T *out = static_cast<T *>(p.out);
+  for (int e = tid; e < 16 * p.L0; e += blockDim.x) {
+    const int rr = e / (int)p.L0, col = e - rr * (int)p.L0;
+    const int64_t a = a0 + rr;
+    if (a >= p.R0) continue;
+    T acc = T(0);
+    for (int w = 0; w < waves; ++w) acc += red[(w * 16 + rr) * ncol + col];
+    if (p.direct)
+      out[a * p.L0 + col] = acc;
+    else
+      out[(grp * p.R0 + a) * p.L0 + col] = acc;
+  }
+}
+
+// gfx950: 160 KiB of LDS per workgroup; two wavefronts per SIMD at most
+// (the kernel's register budget), i.e. eight per CU
+constexpr size_t kMaxLds = 160 * 1024;
+constexpr int kCUs = 256;
+constexpr int kWavesPerCU = 8;
+
+struct WFusePlan {
+  WFuseArgs a{};
+  int64_t groups = 1;
+  size_t lds = 0;
+  int threads = 0;
+  int nbb_t = 4;
+};
+
+bool plan(const WFuse &f, WFusePlan &pl) {
+  if (f.t != DType::F64 && f.t != DType::F32) return false;
+  if (f.R0 <= 0 || f.I <= 0 || f.R1 <= 0 || f.L1 <= 0 || f.L0 <= 0) return false;
+  if (f.L1 > 128 || f.L0 > 128) return false;
+  if (f.R1 % 4 != 0) return false;  // Y fragments are whole 4-vectors
+  const size_t es = f.t == DType::F64 ? 8 : 4;
+  // buffer loads address Y and Sk_n with 32-bit offsets below 2^31
+  if ((double)f.R0 * f.I * f.R1 * es >= 2147483648.0) return false;
+  if ((double)f.L0 * f.I * f.L1 * es >= 2147483648.0) return false;
+  if ((double)f.R1 * f.L1 * es >= 2147483648.0) return false;
+  WFuseArgs &a = pl.a;
+  a.R0 = f.R0;
+  a.I = f.I;
+  a.R1 = f.R1;
+  a.L1 = f.L1;
+  a.L0 = f.L0;
+  a.nch = (int)((f.R1 + 15) / 16);
+  // c-blocks padded to 4 (L1 <= 64) or 8: eight wavefronts, 4 x 2 or 8 x 1
+  a.ncb = f.L1 <= 64 ? 4 : 8;
+  a.nbb = (int)((f.L0 + 15) / 16);
+  a.uln = 8 / a.ncb;
+  // row padding of W^T: one 16-byte step per row spreads the rows of a
+  // fragment read over the LDS banks; rows stay 16-byte aligned
+  a.ldk = 16 * a.nch + (int)(16 / es);
+  const int waves = 8;
+  const size_t ypos = (size_t)16 * (16 + 16 / es);  // one staged Y position
+  const size_t stage = ((size_t)16 * a.ncb * a.ldk + (size_t)16 * ypos) * es;
+  const size_t red = (size_t)waves * 16 * 16 * a.nbb * es;
+  pl.lds = std::max(stage, red);
+  if (pl.lds > kMaxLds) return false;
+  pl.threads = 64 * waves;
+  pl.nbb_t = a.nbb <= 4 ? 4 : 8;
+  a.nablk = (f.R0 + 15) / 16;
+  const int64_t per_cu = std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)(kMaxLds / pl.lds), kWavesPerCU / waves));
+  // at most 256 i-ranges (the split sum's limit)
+  int64_t g = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(f.I, 256),
+                                                     kCUs * per_cu / a.nablk));
+  a.ipg = (f.I + g - 1) / g;
+  g = (f.I + a.ipg - 1) / a.ipg;
+  pl.groups = g;
+  a.direct = g == 1;
+  return true;
+}
+
+template <class F, int NCB, int NBB, bool VS>
+int launch(const WFusePlan &pl, hipStream_t s) {
+  static bool attr = false;
+  if (!attr && pl.lds > 64 * 1024) {
+    // dynamic LDS above 64 KiB is opted into once per kernel
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&wfuse_kernel<F, NCB, NBB, VS>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    attr = true;
+  }
+  const dim3 gr((unsigned)(pl.a.nablk * pl.groups)), bl((unsigned)pl.threads);
+  hipLaunchKernelGGL((wfuse_kernel<F, NCB, NBB, VS>), gr, bl, pl.lds, s, pl.a);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+template <class F>
+int dispatch_fuse(const WFusePlan &pl, bool vs, hipStream_t s) {
+  if (pl.a.ncb == 4) {
+    if (pl.nbb_t == 4) return vs ? launch<F, 4, 4, true>(pl, s) : launch<F, 4, 4, false>(pl, s);
+    return vs ? launch<F, 4, 8, true>(pl, s) : launch<F, 4, 8, false>(pl, s);
+  }
+  if (pl.nbb_t == 4) return vs ? launch<F, 8, 4, true>(pl, s) : launch<F, 8, 4, false>(pl, s);
+  return vs ? launch<F, 8, 8, true>(pl, s) : launch<F, 8, 8, false>(pl, s);
+}
+
+}  // namespace
+
+bool wfuse_supported(const WFuse &f) {
+  WFusePlan pl;
+  return plan(f, pl);
+}
+
+int64_t wfuse_partial_elems(const WFuse &f) {
+  WFusePlan pl;
+  if (!plan(f, pl) || pl.groups == 1) return 0;
+  return pl.groups * f.R0 * f.L0;
+}
+
+int wfuse_run(const WFuse &f, void *partial, size_t partial_bytes, hipStream_t s) {
+  WFusePlan pl;
+  if (!plan(f, pl)) return fail(TT_EINVAL, "internal: fused W-chain level not supported");
+  const size_t es = f.t == DType::F64 ? 8 : 4;
+  WFuseArgs &a = pl.a;
+  if (reinterpret_cast<uintptr_t>(f.Y) % 16 != 0)
+    return fail(TT_EINVAL, "internal: fused W chain needs a 16-byte aligned core");
+  a.Y = f.Y;
+  a.W = f.W;
+  a.Sk = f.Sk;
+  if (a.direct) {
+    a.out = f.C;
+  } else {
+    if (!partial || partial_bytes < (size_t)(pl.groups * f.R0 * f.L0) * es)
+      return fail(TT_EINVAL, "internal: split buffer too small for the fused W chain");
+    a.out = partial;
+  }
+  // Sk_n fragments as 16-byte vectors when its rows keep that alignment
+  const bool vs = f.L1 % 4 == 0 && reinterpret_cast<uintptr_t>(f.Sk) % 16 == 0;
+  int st;
+  if (f.t == DType::F64)
+    st = dispatch_fuse<FuseF64>(pl, vs, s);
+  else
+    st = dispatch_fuse<FuseF32>(pl, vs, s);
+  return st;
+}
+
+int wfuse_sum(const WFuse &f, void *partial, hipStream_t s) {
+  WFusePlan pl;
+  if (!plan(f, pl)) return fail(TT_EINVAL, "internal: fused W-chain level not supported");
+  if (pl.a.direct) return TT_OK;
+  GemmX g;  // the i-range splits, summed in a fixed order
+  g.C = f.C;
+  g.ldc = f.L0;
+  g.tc = f.t;
+  g.M = f.R0;
+  g.N = f.L0;
+  g.K = 1;
+  g.math = f.t;
+  g.splits = (int)pl.groups;
+  g.partial = partial;
+  return gemm_reduce_splits(g, s);
+}
+
+}  // namespace ttr

@@ -60,15 +60,26 @@ def test_device_sketch_float32(gpu_lib):
 
 # ------------------------------------------------------------------ Algorithm 3
 
+@pytest.mark.parametrize("mode", ["fused", "gemm"])
 @pytest.mark.parametrize("case", [
     (5, 3, 4, 3),      # tiny
     (6, 17, 37, 21),   # ragged tiles
     (4, 100, 200, 60),  # workload-sized cores
     (2, 5, 3, 2),      # N = 2
+    (4, 7, 33, 70),    # five c-blocks, one unit lane, odd R (element loads)
+    (3, 300, 16, 128),  # widest sketch rank, i-ranges capped at 256
+    (4, 5, 300, 64),   # W_n^T fills most of the LDS
+    (3, 4, 300, 100),  # W_n^T too large for the LDS: two products
+    (5, 9, 36, 70),    # five c-blocks, ragged sketch rank, R a multiple of 4
+    (4, 3, 8, 17),     # one k-chunk per unit, ragged a-block
 ])
-def test_partial_contractions_match_oracle(gpu_lib, case):
+def test_partial_contractions_match_oracle(gpu_lib, case, mode, monkeypatch):
+    # mode "fused": interior levels in one kernel where the shapes allow it;
+    # "gemm": always the two products V(Y_n) W_n, then H(Z_n) H(Sk_n)^T
+    if mode == "gemm":
+        monkeypatch.setenv("TT_WCHAIN", "gemm")
     N, I, R, l = case
-    say(f"W chain N={N} I={I} R={R} l={l}")
+    say(f"W chain {mode} N={N} I={I} R={R} l={l}")
     dims, ranks = G.uniform_tt_shape(N, I, R)
     X = G.random_tt(11, dims, ranks, scale="nominal")
     Y = G.random_tt(12, dims, [1] + [l] * (N - 1) + [1], scale="def31")

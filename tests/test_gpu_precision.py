@@ -66,10 +66,14 @@ def test_bf16_sketch_matches_oracle(gpu_lib):
 
 # ------------------------------------------------------------------ W chain
 
-@pytest.mark.parametrize("case", [(5, 3, 4, 3), (6, 17, 37, 21), (4, 100, 200, 60)])
-def test_wchain_f32(gpu_lib, case):
+@pytest.mark.parametrize("mode", ["fused", "gemm"])
+@pytest.mark.parametrize("case", [(5, 3, 4, 3), (6, 17, 37, 21), (4, 100, 200, 60),
+                                  (4, 9, 30, 75)])
+def test_wchain_f32(gpu_lib, case, mode, monkeypatch):
+    if mode == "gemm":
+        monkeypatch.setenv("TT_WCHAIN", "gemm")
     N, I, R, l = case
-    say(f"W chain f32 N={N} I={I} R={R} l={l}")
+    say(f"W chain f32 {mode} N={N} I={I} R={R} l={l}")
     dims, ranks = G.uniform_tt_shape(N, I, R)
     X = f32(G.random_tt(11, dims, ranks, scale="nominal"))
     Y = f32(G.random_tt(12, dims, [1] + [l] * (N - 1) + [1], scale="def31"))
