@@ -143,7 +143,16 @@ __global__ __launch_bounds__(kWfThreads) void wfuse_kernel(const WFuseArgs p) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int r = lane & 15, q = lane >> 4;
   const int cb = wave % NCB, ul = wave / NCB;
-  const int64_t ab = blockIdx.x % p.nablk, grp = blockIdx.x / p.nablk;
+  // Workgroup b runs on XCD b % 8 (round-robin dispatch); each XCD takes a
+  // contiguous run of the (i-range, a-block) tiles, so the a-blocks of one
+  // i-range, which share Sk_n(:, i-range, :), mostly share one L2.
+  int tile;
+  {
+    const int nwg = gridDim.x, b = blockIdx.x;
+    const int per = nwg / 8, extra = nwg % 8, x = b % 8;
+    tile = x * per + min(x, extra) + b / 8;
+  }
+  const int64_t ab = tile % p.nablk, grp = tile / p.nablk;
   const int64_t a0 = 16 * ab;
   const int64_t ib = grp * p.ipg, ie = min(p.I, ib + p.ipg);
   const int rows = 16 * NCB, kp = 16 * p.nch;
