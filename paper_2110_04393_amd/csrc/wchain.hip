@@ -25,6 +25,7 @@
 // and written as one split of the result (summed over the i-ranges by the
 // split-K reduction of the GEMM module) or directly when there is one range.
 #include <algorithm>
+#include <type_traits>
 
 #include "tt_internal.h"
 #include "wave.h"
@@ -124,13 +125,10 @@ __device__ __forceinline__ float bload1(__amdgpu_buffer_rsrc_t r, uint32_t off, 
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-constexpr int kWfThreads = 512;
-
-template <class F, int NCB, int NBB, bool VS>
-__global__ __launch_bounds__(kWfThreads) void wfuse_kernel(const WFuseArgs p) {
+template <class F, int NCB, int NBB, int ULN, bool VS>
+__global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p) {
   typedef typename F::T T;
   typedef typename F::acc_t acc_t;
-  constexpr int ULN = 8 / NCB;  // unit lanes
   // staged Y rows: 16 values + one 16-byte step, which spreads a fragment
   // read over the LDS banks and keeps rows 16-byte aligned
   constexpr int YR = 16 + 16 / (int)sizeof(T);
@@ -314,11 +312,9 @@ __global__ __launch_bounds__(kWfThreads) void wfuse_kernel(const WFuseArgs p) {
   }
 }
 
-// gfx950: 160 KiB of LDS per workgroup; two wavefronts per SIMD at most
-// (the kernel's register budget), i.e. eight per CU
+// gfx950: 160 KiB of LDS per workgroup, 256 CUs
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr int kCUs = 256;
-constexpr int kWavesPerCU = 8;
 
 struct WFusePlan {
   WFuseArgs a{};
@@ -345,24 +341,45 @@ bool plan(const WFuse &f, WFusePlan &pl) {
   a.L1 = f.L1;
   a.L0 = f.L0;
   a.nch = (int)((f.R1 + 15) / 16);
-  // c-blocks padded to 4 (L1 <= 64) or 8: eight wavefronts, 4 x 2 or 8 x 1
+  // c-blocks padded to 4 (L1 <= 64) or 8, b-blocks to 4 or 8
   a.ncb = f.L1 <= 64 ? 4 : 8;
   a.nbb = (int)((f.L0 + 15) / 16);
-  a.uln = 8 / a.ncb;
+  pl.nbb_t = a.nbb <= 4 ? 4 : 8;
   // row padding of W^T: one 16-byte step per row spreads the rows of a
   // fragment read over the LDS banks; rows stay 16-byte aligned
   a.ldk = 16 * a.nch + (int)(16 / es);
-  const int waves = 8;
   const size_t ypos = (size_t)16 * (16 + 16 / es);  // one staged Y position
-  const size_t stage = ((size_t)16 * a.ncb * a.ldk + (size_t)16 * ypos) * es;
-  const size_t red = (size_t)waves * 16 * 16 * a.nbb * es;
-  pl.lds = std::max(stage, red);
-  if (pl.lds > kMaxLds) return false;
+  // unit lanes: as many as the registers allow (f64: three wavefronts per
+  // SIMD for four c- and four b-blocks, else two; f32: four), fewer if the
+  // LDS cannot hold the staged Y of all lanes
+  static const int kF64Ulns44[] = {3, 2, 1}, kF64Ulns48[] = {2, 1}, kF64Ulns8[] = {1},
+                   kF32Ulns4[] = {4, 2, 1}, kF32Ulns8[] = {2, 1};
+  const int *ulns;
+  int nulns;
+  if (f.t == DType::F64) {
+    if (a.ncb == 4 && pl.nbb_t == 4) ulns = kF64Ulns44, nulns = 3;
+    else if (a.ncb == 4) ulns = kF64Ulns48, nulns = 2;
+    else ulns = kF64Ulns8, nulns = 1;
+  } else {
+    if (a.ncb == 4) ulns = kF32Ulns4, nulns = 3;
+    else ulns = kF32Ulns8, nulns = 2;
+  }
+  int uln = 0;
+  for (int k = 0; k < nulns && !uln; ++k) {
+    const int u = ulns[k], waves = a.ncb * u;
+    const size_t stage = ((size_t)16 * a.ncb * a.ldk + (size_t)u * 2 * a.ncb * ypos) * es;
+    const size_t red = (size_t)waves * 16 * 16 * a.nbb * es;
+    pl.lds = std::max(stage, red);
+    if (pl.lds <= kMaxLds) uln = u;
+  }
+  if (!uln) return false;
+  a.uln = uln;
+  const int waves = a.ncb * uln;
   pl.threads = 64 * waves;
-  pl.nbb_t = a.nbb <= 4 ? 4 : 8;
   a.nablk = (f.R0 + 15) / 16;
+  const int cap = f.t == DType::F64 ? (uln == 3 ? 12 : 8) : 16;  // wavefronts per CU
   const int64_t per_cu = std::max<int64_t>(
-      1, std::min<int64_t>((int64_t)(kMaxLds / pl.lds), kWavesPerCU / waves));
+      1, std::min<int64_t>((int64_t)(kMaxLds / pl.lds), cap / waves));
   // at most 256 i-ranges (the split sum's limit)
   int64_t g = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(f.I, 256),
                                                      kCUs * per_cu / a.nablk));
@@ -373,29 +390,51 @@ bool plan(const WFuse &f, WFusePlan &pl) {
   return true;
 }
 
-template <class F, int NCB, int NBB, bool VS>
+template <class F, int NCB, int NBB, int ULN, bool VS>
 int launch(const WFusePlan &pl, hipStream_t s) {
   static bool attr = false;
   if (!attr && pl.lds > 64 * 1024) {
     // dynamic LDS above 64 KiB is opted into once per kernel
-    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&wfuse_kernel<F, NCB, NBB, VS>),
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&wfuse_kernel<F, NCB, NBB, ULN, VS>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
     attr = true;
   }
   const dim3 gr((unsigned)(pl.a.nablk * pl.groups)), bl((unsigned)pl.threads);
-  hipLaunchKernelGGL((wfuse_kernel<F, NCB, NBB, VS>), gr, bl, pl.lds, s, pl.a);
+  hipLaunchKernelGGL((wfuse_kernel<F, NCB, NBB, ULN, VS>), gr, bl, pl.lds, s, pl.a);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 
+// the unit-lane counts built for each shape (see plan)
+template <class F, int NCB, int NBB, int ULN>
+constexpr bool built() {
+  if (std::is_same<F, FuseF64>::value)
+    return NCB == 4 ? (NBB == 4 ? ULN <= 3 : ULN <= 2) : ULN == 1;
+  return NCB == 4 ? (ULN == 1 || ULN == 2 || ULN == 4) : ULN <= 2;
+}
+
+template <class F, int NCB, int NBB, int ULN>
+int launch_vs(const WFusePlan &pl, bool vs, hipStream_t s) {
+  if constexpr (built<F, NCB, NBB, ULN>())
+    return vs ? launch<F, NCB, NBB, ULN, true>(pl, s) : launch<F, NCB, NBB, ULN, false>(pl, s);
+  return fail(TT_EINVAL, "internal: fused W-chain shape not built");
+}
+
+template <class F, int NCB, int NBB>
+int dispatch_uln(const WFusePlan &pl, bool vs, hipStream_t s) {
+  switch (pl.a.uln) {
+    case 1: return launch_vs<F, NCB, NBB, 1>(pl, vs, s);
+    case 2: return launch_vs<F, NCB, NBB, 2>(pl, vs, s);
+    case 3: return launch_vs<F, NCB, NBB, 3>(pl, vs, s);
+    default: return launch_vs<F, NCB, NBB, 4>(pl, vs, s);
+  }
+}
+
 template <class F>
 int dispatch_fuse(const WFusePlan &pl, bool vs, hipStream_t s) {
-  if (pl.a.ncb == 4) {
-    if (pl.nbb_t == 4) return vs ? launch<F, 4, 4, true>(pl, s) : launch<F, 4, 4, false>(pl, s);
-    return vs ? launch<F, 4, 8, true>(pl, s) : launch<F, 4, 8, false>(pl, s);
-  }
-  if (pl.nbb_t == 4) return vs ? launch<F, 8, 4, true>(pl, s) : launch<F, 8, 4, false>(pl, s);
-  return vs ? launch<F, 8, 8, true>(pl, s) : launch<F, 8, 8, false>(pl, s);
+  if (pl.a.ncb == 4)
+    return pl.nbb_t == 4 ? dispatch_uln<F, 4, 4>(pl, vs, s) : dispatch_uln<F, 4, 8>(pl, vs, s);
+  return pl.nbb_t == 4 ? dispatch_uln<F, 8, 4>(pl, vs, s) : dispatch_uln<F, 8, 8>(pl, vs, s);
 }
 
 }  // namespace
