@@ -38,9 +38,9 @@ METRIC = "ms per randomized TT-rounding + %MFMA peak; mixed-prec vs FP64 at tol"
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over this script's default
 # run, each scaled by what the same counter reads for a plain 256 MiB device
 # copy (FETCH_SIZE counts half of the copy's reads: x 2.0; WRITE_SIZE x 1.0).
-# Source: profiles/gemm_vyw_single_tt_N30_I100_R200_fp64_pmc_traffic.md.
+# Source: profiles/wfuse_wchain_single_tt_N30_I100_R200_fp64_pmc_traffic.md.
 # Valid for the kernel as measured there; anything else reports null.
-MEASURED_TRAFFIC = {("single_tt", "f64", 0): {"read_bytes": 33.49e6, "write_bytes": 9.60e6}}
+MEASURED_TRAFFIC = {("single_tt", "f64", 6): {"read_bytes": 37.06e6, "write_bytes": 1.63e6}}
 
 SITE_NAMES = {0: "wchain_z", 1: "wchain_w", 2: "sweep_y", 3: "sweep_m", 4: "sweep_next",
               5: "trunc", 6: "wchain_fused"}
