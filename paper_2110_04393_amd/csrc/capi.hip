@@ -244,33 +244,39 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
                           factors ? factors + N - 1 : nullptr));
   for (int n = N - 1; n >= 2; --n) {
     const int64_t I = dims[n - 1];
+    // W_{n-1} = H(V(Y_n) W_n) H(Sk_n)^T for every summand in one kernel
+    WFuse f;
+    f.Sk = Sk[n - 1];
+    f.t = DTypeOf<T>::value;
+    f.I = I;
+    f.L1 = L[n];
+    f.L0 = L[n - 1];
     for (int j = 0; j < s; ++j) {
-      WFuse f;  // W_{n-1} = H(V(Y_n) W_n) H(Sk_n)^T in one kernel
-      f.Y = Y[(size_t)j * N + n - 1];
-      f.W = wrow(j, n);
-      f.Sk = Sk[n - 1];
-      f.C = wrow(j, n - 1);
-      f.t = DTypeOf<T>::value;
-      f.R0 = R[j][n - 1];
-      f.I = I;
-      f.R1 = R[j][n];
-      f.L1 = L[n];
-      f.L0 = L[n - 1];
-      // the dry pass sizes the split buffer for both forms (the core's
-      // alignment, which the fused kernel needs, is known only at run time)
-      const bool fusable = g_wchain_mode == 0 && p.wmath == f.t && p.sk == f.t &&
-                           wfuse_supported(f);
-      if (fusable) {
-        const size_t need = (size_t)wfuse_partial_elems(f) * sizeof(T);
-        c.partial_need = std::max(c.partial_need, need);
-        if (!c.dry && reinterpret_cast<uintptr_t>(f.Y) % 16 == 0) {
-          if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split buffer too small");
-          TTR_TRY(timed_launch(c, TT_SITE_WCHAIN_FUSED, true,
-                               [&] { return wfuse_run(f, c.partial, c.partial_cap, c.s); }));
-          TTR_TRY(wfuse_sum(f, c.partial, c.s));
-          continue;
-        }
+      WFuseItem it;
+      it.Y = Y[(size_t)j * N + n - 1];
+      it.W = wrow(j, n);
+      it.C = wrow(j, n - 1);
+      it.R0 = R[j][n - 1];
+      it.R1 = R[j][n];
+      f.items.push_back(it);
+    }
+    // the dry pass sizes the split buffer for both forms (the cores'
+    // alignment, which the fused kernel needs, is known only at run time)
+    const bool fusable =
+        g_wchain_mode == 0 && p.wmath == f.t && p.sk == f.t && wfuse_supported(f);
+    bool fused = false;
+    if (fusable) {
+      const size_t need = (size_t)wfuse_partial_elems(f) * sizeof(T);
+      c.partial_need = std::max(c.partial_need, need);
+      if (!c.dry && wfuse_aligned(f)) {
+        if (need > c.partial_cap) return fail(TT_EINVAL, "internal: split buffer too small");
+        TTR_TRY(timed_launch(c, TT_SITE_WCHAIN_FUSED, true,
+                             [&] { return wfuse_run(f, c.partial, c.partial_cap, c.s); }));
+        TTR_TRY(wfuse_sum(f, c.partial, c.s));
+        fused = true;
       }
+    }
+    for (int j = 0; j < s && !fused; ++j) {
       GemmX g;  // V(Z_n) = V(Y_n) W_n
       g.A = Y[(size_t)j * N + n - 1];
       g.lda = R[j][n];

@@ -130,22 +130,28 @@ int gemmx_run(const GemmX &g, hipStream_t s);
 // beta * C, summed in a fixed order (accumulator type of g.math)
 int gemm_reduce_splits(const GemmX &g, hipStream_t s);
 
-// One level of the W chain (Algorithm 3) in one kernel:
-// C = H(V(Y) W) H(Sk)^T for Y (R0 x I x R1), W (R1 x L1, ld L1),
-// Sk (L0 x I x L1), C (R0 x L0, ld L0), all of type t (F64 or F32, which is
-// also the arithmetic).  wfuse_supported tells whether the shapes fit the
-// kernel (R1 a multiple of 4, L1 and L0 at most 128, W_n^T within the LDS);
-// the core Y must also be 16-byte aligned.  wfuse_partial_elems is the split
-// buffer it needs (elements of t).
-// wfuse_run launches the kernel (C itself, or the splits of C into partial);
-// wfuse_sum then adds the splits into C (nothing to do with one split).
-struct WFuse {
-  const void *Y = nullptr, *W = nullptr, *Sk = nullptr;
+// One level of the W chain (Algorithm 3) for every summand in one kernel:
+// C_j = H(V(Y_j) W_j) H(Sk)^T for Y_j (R0_j x I x R1_j), W_j (R1_j x L1,
+// ld L1), Sk (L0 x I x L1), C_j (R0_j x L0, ld L0), all of type t (F64 or
+// F32, which is also the arithmetic).  wfuse_supported tells whether the
+// shapes fit the kernel (every R1_j a multiple of 4, L1 and L0 at most 128,
+// W_j^T within the LDS); wfuse_aligned whether every Y_j is 16-byte aligned,
+// which it also needs.  wfuse_partial_elems is the split buffer it needs
+// (elements of t).  wfuse_run launches the kernel (up to 24 summands per
+// launch) writing C_j or its i-range splits; wfuse_sum then adds the splits.
+struct WFuseItem {
+  const void *Y = nullptr, *W = nullptr;
   void *C = nullptr;
+  int64_t R0 = 0, R1 = 0;
+};
+struct WFuse {
+  const void *Sk = nullptr;
   DType t = DType::F64;
-  int64_t R0 = 0, I = 0, R1 = 0, L1 = 0, L0 = 0;
+  int64_t I = 0, L1 = 0, L0 = 0;
+  std::vector<WFuseItem> items;
 };
 bool wfuse_supported(const WFuse &f);
+bool wfuse_aligned(const WFuse &f);
 int64_t wfuse_partial_elems(const WFuse &f);
 int wfuse_run(const WFuse &f, void *partial, size_t partial_bytes, hipStream_t s);
 int wfuse_sum(const WFuse &f, void *partial, hipStream_t s);

@@ -80,13 +80,20 @@ struct FuseF32 {
   }
 };
 
+// One summand of a level: its core Y^(j)_n (R0 x I x R1), its rows of the
+// stacked W_n (R1 x L1, ld L1), where its W_(n-1) block or its splits go,
+// and the first of its tiles (a-block x i-range) in the launch.
+constexpr int kFuseMaxGroup = 24;
+struct WFuseEntry {
+  const void *Y, *W;
+  void *out;  // W_(n-1) rows (ld L0) with one i-range, else its splits [groups][R0][L0]
+  int32_t R0, R1, nch, ldk, nablk, tile0;
+};
 struct WFuseArgs {
-  const void *Y, *W, *Sk;
-  void *out;  // W_{n-1} (ld L0) with one i-range, else partials [groups][R0][L0]
-  int64_t R0, I, R1, L1, L0;
-  int64_t nablk, ipg;
-  int nch, ncb, nbb, uln, ldk;
-  int direct;
+  const void *Sk;
+  int64_t I, L1, L0, ipg;
+  int ncb, nbb, uln, direct, count;
+  WFuseEntry e[kFuseMaxGroup];
 };
 
 extern __shared__ __attribute__((aligned(16))) unsigned char wf_lds[];
@@ -134,8 +141,6 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
   constexpr int YR = 16 + 16 / (int)sizeof(T);
   constexpr int POS = 16 * YR;  // values of one staged position (16 rows)
   T *Wt = reinterpret_cast<T *>(wf_lds);
-  const T *Y = static_cast<const T *>(p.Y);
-  const T *W = static_cast<const T *>(p.W);
   const T *Sk = static_cast<const T *>(p.Sk);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -150,13 +155,22 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
     const int per = nwg / 8, extra = nwg % 8, x = b % 8;
     tile = x * per + min(x, extra) + b / 8;
   }
-  const int64_t ab = tile % p.nablk, grp = tile / p.nablk;
+  // the summand of this tile (tiles are numbered summand by summand)
+  int j = 0;
+  while (j + 1 < p.count && tile >= p.e[j + 1].tile0) ++j;
+  const WFuseEntry &ent = p.e[j];
+  const T *Y = static_cast<const T *>(ent.Y);
+  const T *W = static_cast<const T *>(ent.W);
+  const int64_t R0 = ent.R0, R1_ = ent.R1;
+  const int ldk = ent.ldk, nablk = ent.nablk;
+  tile -= ent.tile0;
+  const int64_t ab = tile % nablk, grp = tile / nablk;
   const int64_t a0 = 16 * ab;
   const int64_t ib = grp * p.ipg, ie = min(p.I, ib + p.ipg);
-  const int rows = 16 * NCB, kp = 16 * p.nch;
-  const int nch = p.nch;
+  const int rows = 16 * NCB, kp = 16 * ent.nch;
+  const int nch = ent.nch;
   // staged Y: per unit lane two buffers of NCB positions, after W^T
-  T *Ys = Wt + rows * p.ldk + ul * 2 * NCB * POS;
+  T *Ys = Wt + rows * ldk + ul * 2 * NCB * POS;
 
   // units of this lane: i = ib + ul, ib + ul + ULN, ... (< ie)
   const int64_t left = ie - ib - ul;
@@ -167,16 +181,16 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
   const int nchp = (nch + 7) / 8 * 8;
   const int bpu = nchp / NCB;  // batches per unit
   const int64_t arow = a0 + r;
-  const bool arow_ok = arow < p.R0;
+  const bool arow_ok = arow < R0;
   constexpr uint32_t es = sizeof(T);
-  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y, (uint32_t)(p.R0 * p.I * p.R1 * es));
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y, (uint32_t)(R0 * p.I * R1_ * es));
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(Sk, (uint32_t)(p.L0 * p.I * p.L1 * es));
 
   // Y fragment of this wavefront's position in batch g: lane (r, q) holds
   // Y(a0 + r, i, 16 c + 4 q + t); R1 is a multiple of 4, so the four values
   // are all inside the row or all outside (chunks c >= nch, units u >= nu
   // and rows beyond R0 read zeros).  Offsets fit in 32 bits.
-  const uint32_t R1 = (uint32_t)p.R1, L1 = (uint32_t)p.L1, I = (uint32_t)p.I;
+  const uint32_t R1 = (uint32_t)R1_, L1 = (uint32_t)p.L1, I = (uint32_t)p.I;
   const uint32_t y_lane = ((uint32_t)arow * I * R1 + 4 * q) * es;
   auto loady = [&](int g, T(&v)[4]) __attribute__((always_inline)) {
     const int u = g / bpu, c = (g - u * bpu) * NCB + cb;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
   // zero beyond R1 and L1 (so padded k and c contribute nothing); sixteen
   // loads per thread in flight before their LDS stores
   {
-    const __amdgpu_buffer_rsrc_t rw = make_rsrc(W, (uint32_t)(p.R1 * p.L1 * es));
+    const __amdgpu_buffer_rsrc_t rw = make_rsrc(W, (uint32_t)(R1_ * p.L1 * es));
     constexpr int kBatch = 16;
     const int n = rows * kp, step = blockDim.x;
     for (int e0 = tid; e0 < n; e0 += kBatch * step) {
@@ -229,14 +243,14 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
         const int e = e0 + b * step;
         const int k = e / rows, m = e - k * rows;
         const int c = 16 * (m >> 4) + F::perm(m & 15);
-        const bool ok = e < n && k < p.R1 && c < p.L1;
+        const bool ok = e < n && k < R1_ && c < p.L1;
         v[b] = bload1(rw, ok ? (uint32_t)(((int64_t)k * p.L1 + c) * es) : kOutside, T(0));
       }
 #pragma unroll
       for (int b = 0; b < kBatch; ++b) {
         const int e = e0 + b * step;
         const int k = e / rows, m = e - k * rows;
-        if (e < n) Wt[m * p.ldk + k] = v[b];
+        if (e < n) Wt[m * ldk + k] = v[b];
       }
     }
   }
@@ -247,7 +261,7 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
   acc1[0] = acc1[1] = acc_t{0, 0, 0, 0};
 #pragma unroll
   for (int bb = 0; bb < NBB; ++bb) acc2[bb] = acc_t{0, 0, 0, 0};
-  const T *wrow = Wt + (16 * cb + r) * p.ldk + 4 * q;
+  const T *wrow = Wt + (16 * cb + r) * ldk + 4 * q;
   const T *yfrag = Ys + r * YR + 4 * q;
 
   // Batch g (buffer g % 2): issue the loads of batch g + 2 into the
@@ -298,18 +312,42 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
     }
   __syncthreads();
   const int waves = blockDim.x >> 6;
-  T *out = static_cast<T *>(p.out);
+  T *out = static_cast<T *>(ent.out);
   for (int e = tid; e < 16 * p.L0; e += blockDim.x) {
     const int rr = e / (int)p.L0, col = e - rr * (int)p.L0;
     const int64_t a = a0 + rr;
-    if (a >= p.R0) continue;
+    if (a >= R0) continue;
     T acc = T(0);
     for (int w = 0; w < waves; ++w) acc += red[(w * 16 + rr) * ncol + col];
     if (p.direct)
       out[a * p.L0 + col] = acc;
     else
-      out[(grp * p.R0 + a) * p.L0 + col] = acc;
+      out[(grp * R0 + a) * p.L0 + col] = acc;
   }
+}
+
+// Sum of the i-range splits of every summand of a launch, in split order:
+// W_(n-1)(a, b) = sum_g split_g(a, b).  blockIdx.y is the summand.
+struct WSumEntry {
+  const void *part;
+  void *out;
+  int64_t elems;  // R0 * L0
+};
+struct WSumArgs {
+  int64_t groups;
+  int count;
+  WSumEntry e[kFuseMaxGroup];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void wfuse_sum_kernel(const WSumArgs a) {
+  const WSumEntry &e = a.e[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= e.elems) return;
+  const T *part = static_cast<const T *>(e.part);
+  T acc = part[idx];
+  for (int64_t g = 1; g < a.groups; ++g) acc += part[g * e.elems + idx];
+  static_cast<T *>(e.out)[idx] = acc;
 }
 
 // gfx950: 160 KiB of LDS per workgroup, 256 CUs
@@ -318,36 +356,43 @@ constexpr int kCUs = 256;
 
 struct WFusePlan {
   WFuseArgs a{};
-  int64_t groups = 1;
+  int64_t groups = 1, tiles = 0;
+  int64_t part_elems = 0;  // splits of all summands of the launch
   size_t lds = 0;
   int threads = 0;
   int nbb_t = 4;
 };
 
-bool plan(const WFuse &f, WFusePlan &pl) {
+// Plan of one launch over items [b, e) of the level.
+bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
   if (f.t != DType::F64 && f.t != DType::F32) return false;
-  if (f.R0 <= 0 || f.I <= 0 || f.R1 <= 0 || f.L1 <= 0 || f.L0 <= 0) return false;
+  if (e <= b || e - b > (size_t)kFuseMaxGroup) return false;
+  if (f.I <= 0 || f.L1 <= 0 || f.L0 <= 0) return false;
   if (f.L1 > 128 || f.L0 > 128) return false;
-  if (f.R1 % 4 != 0) return false;  // Y fragments are whole 4-vectors
   const size_t es = f.t == DType::F64 ? 8 : 4;
-  // buffer loads address Y and Sk_n with 32-bit offsets below 2^31
-  if ((double)f.R0 * f.I * f.R1 * es >= 2147483648.0) return false;
+  // buffer loads address Y, Sk_n and W_n with 32-bit offsets below 2^31
   if ((double)f.L0 * f.I * f.L1 * es >= 2147483648.0) return false;
-  if ((double)f.R1 * f.L1 * es >= 2147483648.0) return false;
+  int64_t r1max = 0;
+  for (size_t k = b; k < e; ++k) {
+    const WFuseItem &it = f.items[k];
+    if (it.R0 <= 0 || it.R1 <= 0) return false;
+    if (it.R1 % 4 != 0) return false;  // Y fragments are whole 4-vectors
+    if ((double)it.R0 * f.I * it.R1 * es >= 2147483648.0) return false;
+    if ((double)it.R1 * f.L1 * es >= 2147483648.0) return false;
+    r1max = std::max(r1max, it.R1);
+  }
   WFuseArgs &a = pl.a;
-  a.R0 = f.R0;
   a.I = f.I;
-  a.R1 = f.R1;
   a.L1 = f.L1;
   a.L0 = f.L0;
-  a.nch = (int)((f.R1 + 15) / 16);
   // c-blocks padded to 4 (L1 <= 64) or 8, b-blocks to 4 or 8
   a.ncb = f.L1 <= 64 ? 4 : 8;
   a.nbb = (int)((f.L0 + 15) / 16);
   pl.nbb_t = a.nbb <= 4 ? 4 : 8;
   // row padding of W^T: one 16-byte step per row spreads the rows of a
   // fragment read over the LDS banks; rows stay 16-byte aligned
-  a.ldk = 16 * a.nch + (int)(16 / es);
+  const int pad = (int)(16 / es);
+  const int64_t ldk_max = 16 * ((r1max + 15) / 16) + pad;
   const size_t ypos = (size_t)16 * (16 + 16 / es);  // one staged Y position
   // unit lanes: as many as the registers allow (f64: three wavefronts per
   // SIMD for four c- and four b-blocks, else two; f32: four), fewer if the
@@ -367,7 +412,7 @@ bool plan(const WFuse &f, WFusePlan &pl) {
   int uln = 0;
   for (int k = 0; k < nulns && !uln; ++k) {
     const int u = ulns[k], waves = a.ncb * u;
-    const size_t stage = ((size_t)16 * a.ncb * a.ldk + (size_t)u * 2 * a.ncb * ypos) * es;
+    const size_t stage = ((size_t)16 * a.ncb * ldk_max + (size_t)u * 2 * a.ncb * ypos) * es;
     const size_t red = (size_t)waves * 16 * 16 * a.nbb * es;
     pl.lds = std::max(stage, red);
     if (pl.lds <= kMaxLds) uln = u;
@@ -376,17 +421,35 @@ bool plan(const WFuse &f, WFusePlan &pl) {
   a.uln = uln;
   const int waves = a.ncb * uln;
   pl.threads = 64 * waves;
-  a.nablk = (f.R0 + 15) / 16;
+  // i-ranges: one count for all summands, about one wave of workgroups
+  int64_t nablk = 0;
+  for (size_t k = b; k < e; ++k) nablk += (f.items[k].R0 + 15) / 16;
   const int cap = f.t == DType::F64 ? (uln == 3 ? 12 : 8) : 16;  // wavefronts per CU
   const int64_t per_cu = std::max<int64_t>(
       1, std::min<int64_t>((int64_t)(kMaxLds / pl.lds), cap / waves));
-  // at most 256 i-ranges (the split sum's limit)
-  int64_t g = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(f.I, 256),
-                                                     kCUs * per_cu / a.nablk));
+  // at most 256 i-ranges
+  int64_t g = std::max<int64_t>(
+      1, std::min<int64_t>(std::min<int64_t>(f.I, 256), kCUs * per_cu / nablk));
   a.ipg = (f.I + g - 1) / g;
   g = (f.I + a.ipg - 1) / a.ipg;
   pl.groups = g;
   a.direct = g == 1;
+  a.count = (int)(e - b);
+  int64_t tile = 0, part = 0;
+  for (size_t k = b; k < e; ++k) {
+    const WFuseItem &it = f.items[k];
+    WFuseEntry &en = a.e[k - b];
+    en.R0 = (int32_t)it.R0;
+    en.R1 = (int32_t)it.R1;
+    en.nch = (int32_t)((it.R1 + 15) / 16);
+    en.ldk = 16 * en.nch + pad;
+    en.nablk = (int32_t)((it.R0 + 15) / 16);
+    en.tile0 = (int32_t)tile;
+    tile += (int64_t)en.nablk * g;
+    part += g == 1 ? 0 : g * it.R0 * f.L0;
+  }
+  pl.tiles = tile;
+  pl.part_elems = part;
   return true;
 }
 
@@ -399,7 +462,7 @@ int launch(const WFusePlan &pl, hipStream_t s) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
     attr = true;
   }
-  const dim3 gr((unsigned)(pl.a.nablk * pl.groups)), bl((unsigned)pl.threads);
+  const dim3 gr((unsigned)pl.tiles), bl((unsigned)pl.threads);
   hipLaunchKernelGGL((wfuse_kernel<F, NCB, NBB, ULN, VS>), gr, bl, pl.lds, s, pl.a);
   TTR_HIP(hipGetLastError());
   return TT_OK;
@@ -437,61 +500,89 @@ int dispatch_fuse(const WFusePlan &pl, bool vs, hipStream_t s) {
   return pl.nbb_t == 4 ? dispatch_uln<F, 8, 4>(pl, vs, s) : dispatch_uln<F, 8, 8>(pl, vs, s);
 }
 
+size_t elem_bytes(const WFuse &f) { return f.t == DType::F64 ? 8 : 4; }
+
 }  // namespace
 
 bool wfuse_supported(const WFuse &f) {
   WFusePlan pl;
-  return plan(f, pl);
+  for (size_t b = 0; b < f.items.size(); b += kFuseMaxGroup)
+    if (!plan(f, b, std::min(f.items.size(), b + kFuseMaxGroup), pl)) return false;
+  return !f.items.empty();
 }
 
 int64_t wfuse_partial_elems(const WFuse &f) {
+  // every launch of up to kFuseMaxGroup summands has its own part of the
+  // buffer, so that all the splits can be summed after all the launches
+  int64_t need = 0;
   WFusePlan pl;
-  if (!plan(f, pl) || pl.groups == 1) return 0;
-  return pl.groups * f.R0 * f.L0;
+  for (size_t b = 0; b < f.items.size(); b += kFuseMaxGroup)
+    if (plan(f, b, std::min(f.items.size(), b + kFuseMaxGroup), pl)) need += pl.part_elems;
+  return need;
 }
 
+bool wfuse_aligned(const WFuse &f) {
+  for (const WFuseItem &it : f.items)
+    if (reinterpret_cast<uintptr_t>(it.Y) % 16 != 0) return false;
+  return true;
+}
+
+// splits of summand k: after those of every earlier summand of the level
 int wfuse_run(const WFuse &f, void *partial, size_t partial_bytes, hipStream_t s) {
-  WFusePlan pl;
-  if (!plan(f, pl)) return fail(TT_EINVAL, "internal: fused W-chain level not supported");
-  const size_t es = f.t == DType::F64 ? 8 : 4;
-  WFuseArgs &a = pl.a;
-  if (reinterpret_cast<uintptr_t>(f.Y) % 16 != 0)
-    return fail(TT_EINVAL, "internal: fused W chain needs a 16-byte aligned core");
-  a.Y = f.Y;
-  a.W = f.W;
-  a.Sk = f.Sk;
-  if (a.direct) {
-    a.out = f.C;
-  } else {
-    if (!partial || partial_bytes < (size_t)(pl.groups * f.R0 * f.L0) * es)
-      return fail(TT_EINVAL, "internal: split buffer too small for the fused W chain");
-    a.out = partial;
-  }
+  if (!wfuse_aligned(f)) return fail(TT_EINVAL, "internal: fused W chain needs 16-byte aligned cores");
+  const size_t es = elem_bytes(f);
+  if ((size_t)wfuse_partial_elems(f) * es > partial_bytes || (!partial && partial_bytes == 0 &&
+                                                               wfuse_partial_elems(f) > 0))
+    return fail(TT_EINVAL, "internal: split buffer too small for the fused W chain");
   // Sk_n fragments as 16-byte vectors when its rows keep that alignment
   const bool vs = f.L1 % 4 == 0 && reinterpret_cast<uintptr_t>(f.Sk) % 16 == 0;
-  int st;
-  if (f.t == DType::F64)
-    st = dispatch_fuse<FuseF64>(pl, vs, s);
-  else
-    st = dispatch_fuse<FuseF32>(pl, vs, s);
-  return st;
+  int64_t part = 0;
+  for (size_t b = 0; b < f.items.size(); b += kFuseMaxGroup) {
+    const size_t e = std::min(f.items.size(), b + kFuseMaxGroup);
+    WFusePlan pl;
+    if (!plan(f, b, e, pl)) return fail(TT_EINVAL, "internal: fused W-chain level not supported");
+    WFuseArgs &a = pl.a;
+    a.Sk = f.Sk;
+    for (size_t k = b; k < e; ++k) {
+      WFuseEntry &en = a.e[k - b];
+      en.Y = f.items[k].Y;
+      en.W = f.items[k].W;
+      en.out = a.direct ? f.items[k].C : static_cast<char *>(partial) + part * es;
+      if (!a.direct) part += pl.groups * f.items[k].R0 * f.L0;
+    }
+    TTR_TRY(f.t == DType::F64 ? dispatch_fuse<FuseF64>(pl, vs, s) : dispatch_fuse<FuseF32>(pl, vs, s));
+  }
+  return TT_OK;
 }
 
 int wfuse_sum(const WFuse &f, void *partial, hipStream_t s) {
-  WFusePlan pl;
-  if (!plan(f, pl)) return fail(TT_EINVAL, "internal: fused W-chain level not supported");
-  if (pl.a.direct) return TT_OK;
-  GemmX g;  // the i-range splits, summed in a fixed order
-  g.C = f.C;
-  g.ldc = f.L0;
-  g.tc = f.t;
-  g.M = f.R0;
-  g.N = f.L0;
-  g.K = 1;
-  g.math = f.t;
-  g.splits = (int)pl.groups;
-  g.partial = partial;
-  return gemm_reduce_splits(g, s);
+  const size_t es = elem_bytes(f);
+  int64_t part = 0;
+  for (size_t b = 0; b < f.items.size(); b += kFuseMaxGroup) {
+    const size_t e = std::min(f.items.size(), b + kFuseMaxGroup);
+    WFusePlan pl;
+    if (!plan(f, b, e, pl)) return fail(TT_EINVAL, "internal: fused W-chain level not supported");
+    if (pl.a.direct) continue;
+    WSumArgs sa{};
+    sa.groups = pl.groups;
+    sa.count = (int)(e - b);
+    int64_t maxe = 0;
+    for (size_t k = b; k < e; ++k) {
+      WSumEntry &se = sa.e[k - b];
+      se.part = static_cast<char *>(partial) + part * es;
+      se.out = f.items[k].C;
+      se.elems = f.items[k].R0 * f.L0;
+      maxe = std::max(maxe, se.elems);
+      part += pl.groups * se.elems;
+    }
+    const dim3 gr((unsigned)((maxe + 255) / 256), (unsigned)sa.count), bl(256);
+    if (f.t == DType::F64)
+      hipLaunchKernelGGL((wfuse_sum_kernel<double>), gr, bl, 0, s, sa);
+    else
+      hipLaunchKernelGGL((wfuse_sum_kernel<float>), gr, bl, 0, s, sa);
+    TTR_HIP(hipGetLastError());
+  }
+  return TT_OK;
 }
 
 }  // namespace ttr

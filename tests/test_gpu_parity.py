@@ -191,13 +191,21 @@ def test_deterministic(gpu_lib):
 
 # ------------------------------------------------------------------ Algorithm 7
 
+@pytest.mark.parametrize("mode", ["fused", "gemm"])
 @pytest.mark.parametrize("case", [
     (2, 5, 6, [3, 4], 3, 1),
     (4, 6, 9, [5, 3, 6, 4], 6, 2),
+    # every rank a multiple of 4: the W-chain levels of all summands in one
+    # fused launch
+    (3, 5, 7, [4, 8, 12], 6, 2),
+    # 26 summands: two fused launches per level (24 + 2)
+    (26, 4, 5, [4, 8] * 13, 6, 2),
 ])
-def test_sum_round_matches_oracle(gpu_lib, case):
+def test_sum_round_matches_oracle(gpu_lib, case, mode, monkeypatch):
+    if mode == "gemm":
+        monkeypatch.setenv("TT_WCHAIN", "gemm")
     s, N, I, Rs, t, p = case
-    say(f"sum {case}")
+    say(f"sum {mode} {case}")
     dims = [I] * N
     tts = [G.random_tt(60 + j, dims, [1] + [Rs[j]] * (N - 1) + [1], scale="nominal")
            for j in range(s)]
