@@ -248,6 +248,8 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
     WFuse f;
     f.Sk = Sk[n - 1];
     f.t = DTypeOf<T>::value;
+    f.math = p.wmath;
+    f.sk = p.sk;
     f.I = I;
     f.L1 = L[n];
     f.L0 = L[n - 1];
@@ -262,8 +264,7 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
     }
     // the dry pass sizes the split buffer for both forms (the cores'
     // alignment, which the fused kernel needs, is known only at run time)
-    const bool fusable =
-        g_wchain_mode == 0 && p.wmath == f.t && p.sk == f.t && wfuse_supported(f);
+    const bool fusable = g_wchain_mode == 0 && wfuse_supported(f);
     bool fused = false;
     if (fusable) {
       const size_t need = (size_t)wfuse_partial_elems(f) * sizeof(T);

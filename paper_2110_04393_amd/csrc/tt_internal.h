@@ -132,8 +132,9 @@ int gemm_reduce_splits(const GemmX &g, hipStream_t s);
 
 // One level of the W chain (Algorithm 3) for every summand in one kernel:
 // C_j = H(V(Y_j) W_j) H(Sk)^T for Y_j (R0_j x I x R1_j), W_j (R1_j x L1,
-// ld L1), Sk (L0 x I x L1), C_j (R0_j x L0, ld L0), all of type t (F64 or
-// F32, which is also the arithmetic).  wfuse_supported tells whether the
+// ld L1), Sk (L0 x I x L1), C_j (R0_j x L0, ld L0); F64 or F32 arithmetic on
+// operands of that type, or BF16 products with FP32 accumulation on FP32
+// cores and a BF16 or FP32 sketch.  wfuse_supported tells whether the
 // shapes fit the kernel (every R1_j a multiple of 4, L1 and L0 at most 128,
 // W_j^T within the LDS); wfuse_aligned whether every Y_j is 16-byte aligned,
 // which it also needs.  wfuse_partial_elems is the split buffer it needs
@@ -146,7 +147,9 @@ struct WFuseItem {
 };
 struct WFuse {
   const void *Sk = nullptr;
-  DType t = DType::F64;
+  DType t = DType::F64;     // storage of Y_j, W_j and C_j
+  DType math = DType::F64;  // arithmetic: t, or BF16 with FP32 storage
+  DType sk = DType::F64;    // storage of Sk: t (BF16 arithmetic: BF16 or FP32)
   int64_t I = 0, L1 = 0, L0 = 0;
   std::vector<WFuseItem> items;
 };

@@ -326,6 +326,219 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
   }
 }
 
+// BF16 form of the same kernel (mixed precision: cores and W in FP32
+// storage, the sketch in BF16 or FP32 storage, products on the BF16
+// instruction with FP32 accumulation).  Y and W_n are rounded to BF16 (nearest
+// even) as they are staged in LDS; a position is 32 values of k and one
+// v_mfma_f32_16x16x32_bf16, whose lane (r, q) holds 8 consecutive k,
+// 8 q .. 8 q + 7, of its row or column.  The FP32 accumulator already holds
+// rows 4 q + j, so W^T rows keep their order; the second product rounds
+// Z(a0 + r, cc + j) to BF16 and fills the lane's other four k-slots with
+// zeros (16 real k per instruction).
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short us4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bload1f(__amdgpu_buffer_rsrc_t r, uint32_t off, __bf16) {
+  const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+  return (float)__builtin_bit_cast(__bf16, v);
+}
+__device__ __forceinline__ float bload1f(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+// four consecutive sketch values (16 bytes of FP32 or 8 bytes of BF16)
+__device__ __forceinline__ void bload4f(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4],
+                                        float) {
+  const f4_t a = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  o[0] = a[0];
+  o[1] = a[1];
+  o[2] = a[2];
+  o[3] = a[3];
+}
+__device__ __forceinline__ void bload4f(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4],
+                                        __bf16) {
+  const u2_t x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  const us4_t h = __builtin_bit_cast(us4_t, x);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) o[t] = (float)__builtin_bit_cast(__bf16, (unsigned short)h[t]);
+}
+__device__ __forceinline__ bf8_t bf16_lo4(const float (&v)[4]) {
+  return bf8_t{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3],
+               (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+}
+
+template <int NCB, int NBB, int ULN, bool VS, typename TS>
+__global__ __launch_bounds__(64 * NCB * ULN) void wfuse_bf16_kernel(const WFuseArgs p) {
+  constexpr int YR = 40;        // staged Y row: 32 values + 16 bytes
+  constexpr int POS = 16 * YR;  // values of one staged position (16 rows)
+  __bf16 *Wt = reinterpret_cast<__bf16 *>(wf_lds);
+  const TS *Sk = static_cast<const TS *>(p.Sk);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r = lane & 15, q = lane >> 4;
+  const int cb = wave % NCB, ul = wave / NCB;
+  int tile;
+  {
+    const int nwg = gridDim.x, b = blockIdx.x;
+    const int per = nwg / 8, extra = nwg % 8, x = b % 8;
+    tile = x * per + min(x, extra) + b / 8;
+  }
+  int j = 0;
+  while (j + 1 < p.count && tile >= p.e[j + 1].tile0) ++j;
+  const WFuseEntry &ent = p.e[j];
+  const float *Y = static_cast<const float *>(ent.Y);
+  const float *W = static_cast<const float *>(ent.W);
+  const int64_t R0 = ent.R0, R1_ = ent.R1;
+  const int ldk = ent.ldk, nablk = ent.nablk;
+  tile -= ent.tile0;
+  const int64_t ab = tile % nablk, grp = tile / nablk;
+  const int64_t a0 = 16 * ab;
+  const int64_t ib = grp * p.ipg, ie = min(p.I, ib + p.ipg);
+  const int rows = 16 * NCB, nch = ent.nch, kp = 32 * nch;
+  __bf16 *Ys = Wt + rows * ldk + ul * 2 * NCB * POS;
+
+  const int64_t left = ie - ib - ul;
+  const int nu = left > 0 ? (int)((left + ULN - 1) / ULN) : 0;
+  const int nchp = (nch + 7) / 8 * 8;
+  const int bpu = nchp / NCB;
+  const int64_t arow = a0 + r;
+  const bool arow_ok = arow < R0;
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(Y, (uint32_t)(R0 * p.I * R1_ * 4));
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(Sk, (uint32_t)(p.L0 * p.I * p.L1 * sizeof(TS)));
+  const uint32_t R1 = (uint32_t)R1_, L1 = (uint32_t)p.L1, I = (uint32_t)p.I;
+  const uint32_t y_lane = ((uint32_t)arow * I * R1 + 8 * q) * 4;
+  // Y of this wavefront's position in batch g: Y(a0 + r, i, 32 c + 8 q + t),
+  // as two 4-vectors (R1 is a multiple of 4)
+  auto loady = [&](int g, float(&v)[8]) __attribute__((always_inline)) {
+    const int u = g / bpu, c = (g - u * bpu) * NCB + cb;
+    const uint32_t i = (uint32_t)(ib + ul) + (uint32_t)u * ULN;
+    const int k = 32 * c + 8 * q;
+    const bool ok = arow_ok && u < nu && c < nch;
+    const uint32_t off = y_lane + (i * R1 + 32 * c) * 4;
+    const f4_t lo = __builtin_bit_cast(
+        f4_t, __builtin_amdgcn_raw_buffer_load_b128(ry, ok && k < (int)R1 ? off : kOutside, 0, 0));
+    const f4_t hi = __builtin_bit_cast(
+        f4_t,
+        __builtin_amdgcn_raw_buffer_load_b128(ry, ok && k + 4 < (int)R1 ? off + 16 : kOutside, 0, 0));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      v[t] = lo[t];
+      v[t + 4] = hi[t];
+    }
+  };
+  auto stagey = [&](int b, const float(&v)[8]) __attribute__((always_inline)) {
+    *reinterpret_cast<bf8_t *>(Ys + (b * NCB + cb) * POS + r * YR + 8 * q) =
+        bf8_t{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3],
+              (__bf16)v[4], (__bf16)v[5], (__bf16)v[6], (__bf16)v[7]};
+  };
+  const int cc = 16 * cb + 4 * q;
+  const uint32_t s_lane = ((uint32_t)r * I * L1 + cc) * (uint32_t)sizeof(TS);
+  auto loadsk = [&](int u, float(&v)[NBB][4]) __attribute__((always_inline)) {
+    const uint32_t i = (uint32_t)(ib + ul) + (uint32_t)u * ULN;
+#pragma unroll
+    for (int bb = 0; bb < NBB; ++bb) {
+      const bool bok = u < nu && 16 * bb + r < p.L0;
+      const uint32_t off = s_lane + (16 * bb * I + i) * L1 * (uint32_t)sizeof(TS);
+      if constexpr (VS) {
+        bload4f(rs, bok && cc < (int)L1 ? off : kOutside, v[bb], TS(0));
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          v[bb][t] = bload1f(rs, bok && cc + t < (int)L1 ? off + t * (uint32_t)sizeof(TS) : kOutside,
+                             TS(0));
+      }
+    }
+  };
+
+  float yr[2][8];
+  float sk[NBB][4];
+  loady(0, yr[0]);
+  loady(1, yr[1]);
+  loadsk(0, sk);
+  // W^T into LDS (row m = column m of W_n), rounded to BF16, zero beyond R1
+  // and L1
+  {
+    const __amdgpu_buffer_rsrc_t rw = make_rsrc(W, (uint32_t)(R1_ * p.L1 * 4));
+    constexpr int kBatch = 16;
+    const int n = rows * kp, step = blockDim.x;
+    for (int e0 = tid; e0 < n; e0 += kBatch * step) {
+      float v[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int e = e0 + b * step;
+        const int k = e / rows, m = e - k * rows;
+        const bool ok = e < n && k < R1_ && m < p.L1;
+        v[b] = bload1(rw, ok ? (uint32_t)(((int64_t)k * p.L1 + m) * 4) : kOutside, 0.f);
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int e = e0 + b * step;
+        const int k = e / rows, m = e - k * rows;
+        if (e < n) Wt[m * ldk + k] = (__bf16)v[b];
+      }
+    }
+  }
+  stagey(0, yr[0]);
+  __syncthreads();
+
+  f4_t acc1[2], acc2[NBB];
+  acc1[0] = acc1[1] = f4_t{0, 0, 0, 0};
+#pragma unroll
+  for (int bb = 0; bb < NBB; ++bb) acc2[bb] = f4_t{0, 0, 0, 0};
+  const __bf16 *wrow = Wt + (16 * cb + r) * ldk + 8 * q;
+  const __bf16 *yfrag = Ys + r * YR + 8 * q;
+  const int nbw = (int)((p.ipg + ULN - 1) / ULN) * bpu;
+  int g = 0;
+  for (int u = 0; u * bpu < nbw; ++u) {
+    for (int bi = 0; bi < bpu; ++bi, ++g) {
+      const int b = g & 1;
+      if (b == 0) loady(g + 2, yr[0]); else loady(g + 2, yr[1]);
+      static_for<0, NCB>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
+        const int c = bi * NCB + s;
+        if (c < nch) {
+          const bf8_t w = *reinterpret_cast<const bf8_t *>(wrow + 32 * c);
+          const bf8_t y = *reinterpret_cast<const bf8_t *>(yfrag + (b * NCB + s) * POS);
+          acc1[s & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, y, acc1[s & 1], 0, 0, 0);
+        }
+      });
+      if (b == 0) stagey(1, yr[1]); else stagey(0, yr[0]);
+      __syncthreads();
+    }
+    const f4_t zs = acc1[0] + acc1[1];
+    acc1[0] = acc1[1] = f4_t{0, 0, 0, 0};
+    const float zv[4] = {zs[0], zs[1], zs[2], zs[3]};
+    const bf8_t z = bf16_lo4(zv);
+#pragma unroll
+    for (int bb = 0; bb < NBB; ++bb)
+      acc2[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(z, bf16_lo4(sk[bb]), acc2[bb], 0, 0, 0);
+    loadsk(u + 1, sk);
+  }
+
+  __syncthreads();
+  float *red = reinterpret_cast<float *>(wf_lds);
+  const int ncol = 16 * p.nbb;
+#pragma unroll
+  for (int bb = 0; bb < NBB; ++bb)
+    if (bb < p.nbb) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) red[(wave * 16 + 4 * q + jj) * ncol + 16 * bb + r] = acc2[bb][jj];
+    }
+  __syncthreads();
+  const int waves = blockDim.x >> 6;
+  float *out = static_cast<float *>(ent.out);
+  for (int e = tid; e < 16 * p.L0; e += blockDim.x) {
+    const int rr = e / (int)p.L0, col = e - rr * (int)p.L0;
+    const int64_t a = a0 + rr;
+    if (a >= R0) continue;
+    float acc = 0.f;
+    for (int w = 0; w < waves; ++w) acc += red[(w * 16 + rr) * ncol + col];
+    if (p.direct)
+      out[a * p.L0 + col] = acc;
+    else
+      out[(grp * R0 + a) * p.L0 + col] = acc;
+  }
+}
+
 // Sum of the i-range splits of every summand of a launch, in split order:
 // W_(n-1)(a, b) = sum_g split_g(a, b).  blockIdx.y is the summand.
 struct WSumEntry {
@@ -365,13 +578,22 @@ struct WFusePlan {
 
 // Plan of one launch over items [b, e) of the level.
 bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
-  if (f.t != DType::F64 && f.t != DType::F32) return false;
+  const bool bf = f.math == DType::BF16;
+  if (bf) {
+    if (f.t != DType::F32 || (f.sk != DType::BF16 && f.sk != DType::F32)) return false;
+  } else {
+    if ((f.t != DType::F64 && f.t != DType::F32) || f.math != f.t || f.sk != f.t) return false;
+  }
   if (e <= b || e - b > (size_t)kFuseMaxGroup) return false;
   if (f.I <= 0 || f.L1 <= 0 || f.L0 <= 0) return false;
   if (f.L1 > 128 || f.L0 > 128) return false;
-  const size_t es = f.t == DType::F64 ? 8 : 4;
+  const size_t es = f.t == DType::F64 ? 8 : 4;  // storage of Y, W, C
+  const size_t ss = f.sk == DType::BF16 ? 2 : es;  // storage of the sketch
+  // staged values in LDS: the arithmetic type
+  const size_t ls = bf ? 2 : es;
+  const int kc = bf ? 32 : 16;  // k per position
   // buffer loads address Y, Sk_n and W_n with 32-bit offsets below 2^31
-  if ((double)f.L0 * f.I * f.L1 * es >= 2147483648.0) return false;
+  if ((double)f.L0 * f.I * f.L1 * ss >= 2147483648.0) return false;
   int64_t r1max = 0;
   for (size_t k = b; k < e; ++k) {
     const WFuseItem &it = f.items[k];
@@ -389,19 +611,23 @@ bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
   a.ncb = f.L1 <= 64 ? 4 : 8;
   a.nbb = (int)((f.L0 + 15) / 16);
   pl.nbb_t = a.nbb <= 4 ? 4 : 8;
-  // row padding of W^T: one 16-byte step per row spreads the rows of a
-  // fragment read over the LDS banks; rows stay 16-byte aligned
-  const int pad = (int)(16 / es);
-  const int64_t ldk_max = 16 * ((r1max + 15) / 16) + pad;
-  const size_t ypos = (size_t)16 * (16 + 16 / es);  // one staged Y position
+  // row padding of W^T and of the staged Y: one 16-byte step per row spreads
+  // the rows of a fragment read over the LDS banks; rows stay 16-byte aligned
+  const int pad = (int)(16 / ls);
+  const int64_t ldk_max = kc * ((r1max + kc - 1) / kc) + pad;
+  const size_t ypos = (size_t)16 * (kc + pad);  // one staged Y position
   // unit lanes: as many as the registers allow (f64: three wavefronts per
-  // SIMD for four c- and four b-blocks, else two; f32: four), fewer if the
-  // LDS cannot hold the staged Y of all lanes
+  // SIMD for four c- and four b-blocks, else two; f32 and bf16: four), fewer
+  // if the LDS cannot hold the staged Y of all lanes
   static const int kF64Ulns44[] = {3, 2, 1}, kF64Ulns48[] = {2, 1}, kF64Ulns8[] = {1},
-                   kF32Ulns4[] = {4, 2, 1}, kF32Ulns8[] = {2, 1};
+                   kF32Ulns4[] = {4, 2, 1}, kF32Ulns8[] = {2, 1}, kBfUlns[] = {4, 2, 1};
   const int *ulns;
   int nulns;
-  if (f.t == DType::F64) {
+  if (bf) {
+    // one size per shape: 16 wavefronts, 8 with eight b-blocks
+    ulns = kBfUlns + (a.ncb == 4 ? 0 : 1) + (pl.nbb_t == 4 ? 0 : 1);
+    nulns = 1;
+  } else if (f.t == DType::F64) {
     if (a.ncb == 4 && pl.nbb_t == 4) ulns = kF64Ulns44, nulns = 3;
     else if (a.ncb == 4) ulns = kF64Ulns48, nulns = 2;
     else ulns = kF64Ulns8, nulns = 1;
@@ -409,11 +635,12 @@ bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
     if (a.ncb == 4) ulns = kF32Ulns4, nulns = 3;
     else ulns = kF32Ulns8, nulns = 2;
   }
+  const size_t acc_bytes = f.t == DType::F64 ? 8 : 4;
   int uln = 0;
   for (int k = 0; k < nulns && !uln; ++k) {
     const int u = ulns[k], waves = a.ncb * u;
-    const size_t stage = ((size_t)16 * a.ncb * ldk_max + (size_t)u * 2 * a.ncb * ypos) * es;
-    const size_t red = (size_t)waves * 16 * 16 * a.nbb * es;
+    const size_t stage = ((size_t)16 * a.ncb * ldk_max + (size_t)u * 2 * a.ncb * ypos) * ls;
+    const size_t red = (size_t)waves * 16 * 16 * a.nbb * acc_bytes;
     pl.lds = std::max(stage, red);
     if (pl.lds <= kMaxLds) uln = u;
   }
@@ -424,7 +651,8 @@ bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
   // i-ranges: one count for all summands, about one wave of workgroups
   int64_t nablk = 0;
   for (size_t k = b; k < e; ++k) nablk += (f.items[k].R0 + 15) / 16;
-  const int cap = f.t == DType::F64 ? (uln == 3 ? 12 : 8) : 16;  // wavefronts per CU
+  // wavefronts per CU the registers allow
+  const int cap = bf ? (pl.nbb_t == 4 ? 16 : 12) : f.t == DType::F64 ? (uln == 3 ? 12 : 8) : 16;
   const int64_t per_cu = std::max<int64_t>(
       1, std::min<int64_t>((int64_t)(kMaxLds / pl.lds), cap / waves));
   // at most 256 i-ranges
@@ -441,8 +669,8 @@ bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
     WFuseEntry &en = a.e[k - b];
     en.R0 = (int32_t)it.R0;
     en.R1 = (int32_t)it.R1;
-    en.nch = (int32_t)((it.R1 + 15) / 16);
-    en.ldk = 16 * en.nch + pad;
+    en.nch = (int32_t)((it.R1 + kc - 1) / kc);
+    en.ldk = kc * en.nch + pad;
     en.nablk = (int32_t)((it.R0 + 15) / 16);
     en.tile0 = (int32_t)tile;
     tile += (int64_t)en.nablk * g;
@@ -451,6 +679,33 @@ bool plan(const WFuse &f, size_t b, size_t e, WFusePlan &pl) {
   pl.tiles = tile;
   pl.part_elems = part;
   return true;
+}
+
+template <int NCB, int NBB, int ULN, bool VS, typename TS>
+int launch_bf16(const WFusePlan &pl, hipStream_t s) {
+  static bool attr = false;
+  if (!attr && pl.lds > 64 * 1024) {
+    TTR_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&wfuse_bf16_kernel<NCB, NBB, ULN, VS, TS>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    attr = true;
+  }
+  const dim3 gr((unsigned)pl.tiles), bl((unsigned)pl.threads);
+  hipLaunchKernelGGL((wfuse_bf16_kernel<NCB, NBB, ULN, VS, TS>), gr, bl, pl.lds, s, pl.a);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+template <int NCB, int NBB, int ULN, typename TS>
+int launch_bf16_vs(const WFusePlan &pl, bool vs, hipStream_t s) {
+  return vs ? launch_bf16<NCB, NBB, ULN, true, TS>(pl, s) : launch_bf16<NCB, NBB, ULN, false, TS>(pl, s);
+}
+
+template <typename TS>
+int dispatch_bf16(const WFusePlan &pl, bool vs, hipStream_t s) {
+  if (pl.a.ncb == 4)
+    return pl.nbb_t == 4 ? launch_bf16_vs<4, 4, 4, TS>(pl, vs, s) : launch_bf16_vs<4, 8, 2, TS>(pl, vs, s);
+  return pl.nbb_t == 4 ? launch_bf16_vs<8, 4, 2, TS>(pl, vs, s) : launch_bf16_vs<8, 8, 1, TS>(pl, vs, s);
 }
 
 template <class F, int NCB, int NBB, int ULN, bool VS>
@@ -534,8 +789,9 @@ int wfuse_run(const WFuse &f, void *partial, size_t partial_bytes, hipStream_t s
   if ((size_t)wfuse_partial_elems(f) * es > partial_bytes || (!partial && partial_bytes == 0 &&
                                                                wfuse_partial_elems(f) > 0))
     return fail(TT_EINVAL, "internal: split buffer too small for the fused W chain");
-  // Sk_n fragments as 16-byte vectors when its rows keep that alignment
-  const bool vs = f.L1 % 4 == 0 && reinterpret_cast<uintptr_t>(f.Sk) % 16 == 0;
+  // Sk_n fragments as 4-vectors when its rows keep that alignment
+  const size_t ss = f.sk == DType::BF16 ? 2 : es;
+  const bool vs = f.L1 % 4 == 0 && reinterpret_cast<uintptr_t>(f.Sk) % (4 * ss) == 0;
   int64_t part = 0;
   for (size_t b = 0; b < f.items.size(); b += kFuseMaxGroup) {
     const size_t e = std::min(f.items.size(), b + kFuseMaxGroup);
@@ -550,7 +806,10 @@ int wfuse_run(const WFuse &f, void *partial, size_t partial_bytes, hipStream_t s
       en.out = a.direct ? f.items[k].C : static_cast<char *>(partial) + part * es;
       if (!a.direct) part += pl.groups * f.items[k].R0 * f.L0;
     }
-    TTR_TRY(f.t == DType::F64 ? dispatch_fuse<FuseF64>(pl, vs, s) : dispatch_fuse<FuseF32>(pl, vs, s));
+    if (f.math == DType::BF16)
+      TTR_TRY(f.sk == DType::BF16 ? dispatch_bf16<__bf16>(pl, vs, s) : dispatch_bf16<float>(pl, vs, s));
+    else
+      TTR_TRY(f.t == DType::F64 ? dispatch_fuse<FuseF64>(pl, vs, s) : dispatch_fuse<FuseF32>(pl, vs, s));
   }
   return TT_OK;
 }

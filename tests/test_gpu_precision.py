@@ -101,9 +101,16 @@ def test_wchain_bf16_last_level(gpu_lib, IR):
     assert err <= 1e-5, err
 
 
-def test_wchain_bf16_chain(gpu_lib):
-    N, I, R, l = 6, 40, 30, 20
-    say(f"W chain bf16 N={N} I={I} R={R} l={l}")
+@pytest.mark.parametrize("mode", ["fused", "gemm"])
+@pytest.mark.parametrize("case", [(6, 40, 30, 20), (6, 40, 32, 20), (5, 17, 36, 70),
+                                  (4, 100, 200, 60)])
+def test_wchain_bf16_chain(gpu_lib, case, mode, monkeypatch):
+    # R = 30: always the two products; R a multiple of 4: one fused kernel
+    # per level (four or eight c-blocks) unless mode is "gemm"
+    if mode == "gemm":
+        monkeypatch.setenv("TT_WCHAIN", "gemm")
+    N, I, R, l = case
+    say(f"W chain bf16 {mode} N={N} I={I} R={R} l={l}")
     dims, ranks = G.uniform_tt_shape(N, I, R)
     X = f32(G.random_tt(31, dims, ranks, scale="nominal"))
     Y = f32(G.random_tt(32, dims, [1] + [l] * (N - 1) + [1], scale="def31"))
@@ -117,6 +124,29 @@ def test_wchain_bf16_chain(gpu_lib):
     print("bf16 W chain errors per level", ["%.2e" % e for e in errs])
     assert max(errs) <= 3e-2
     assert max(errs) >= 1e-5  # the operands really went through bf16
+
+
+@pytest.mark.parametrize("case", [(6, 40, 32, 20), (5, 17, 36, 70), (4, 100, 200, 60),
+                                  (3, 9, 8, 17)])
+def test_wchain_bf16_fused_matches_two_products(gpu_lib, case, monkeypatch):
+    # both forms round Y_n, W_n, V(Y_n) W_n and the sketch to bf16 and
+    # accumulate in fp32; they differ in the order of the fp32 sums only.
+    # That order moves a Z entry by ~1e-5 relative after cancellation, so a
+    # fraction p ~ 1e-5 / 2^-8 of the Z entries round to the neighbouring
+    # bf16 value; each such entry is off by 2^-8, which moves a level by
+    # about sqrt(p) 2^-8 ~ 2e-4 (compounding over the levels).  A wrong index
+    # or a dropped block gives O(1) differences.
+    N, I, R, l = case
+    say(f"W chain bf16 fused vs two products N={N} I={I} R={R} l={l}")
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    X = dev(f32(G.random_tt(41, dims, ranks, scale="nominal")), torch.float32)
+    Y = dev(f32(G.random_tt(42, dims, [1] + [l] * (N - 1) + [1], scale="def31")), torch.float32)
+    Wf = [w.double().cpu().numpy() for w in gpu_lib.partial_contractions_rl(X, Y, prec="bf16")[1:]]
+    monkeypatch.setenv("TT_WCHAIN", "gemm")
+    Wg = [w.double().cpu().numpy() for w in gpu_lib.partial_contractions_rl(X, Y, prec="bf16")[1:]]
+    for n, (a, b) in enumerate(zip(Wf, Wg), start=1):
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        assert err <= 2e-3, (n, err)
 
 
 # ------------------------------------------------------------------ rounding
