@@ -97,6 +97,8 @@ static int g_wchain_mode = 0;
 void read_env() {
   const char *w = std::getenv("TT_WCHAIN");
   g_wchain_mode = (w && !std::strcmp(w, "gemm")) ? 1 : 0;
+  const char *gm = std::getenv("TT_GRAM");
+  gram_set_mode((gm && !std::strcmp(gm, "gemm")) ? 1 : 0);
   const char *q = std::getenv("TT_QR");
   if (!q) qr_set_mode(0);
   else if (!std::strcmp(q, "householder")) qr_set_mode(1);
@@ -467,6 +469,16 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   int64_t rr = 1;  // right rank of the current core
   for (int n = N; n >= 2; --n) {
     const int64_t lr = L[n - 1], k = P.out[n - 1], cols = dims[n - 1] * rr;
+    if (gram_supported(lr, cols))  // both forms size the split buffer
+      c.partial_need = std::max(c.partial_need, gram_partial_elems(lr, cols) * sizeof(double));
+    if (gram_enabled(lr, cols)) {
+      // G = H H^T: the panel H^T is stored transposed (rows of H)
+      if (!c.dry)
+        TTR_TRY(timed_launch(c, TT_SITE_TRUNC, true, [&] {
+          return gram_run(hsrc, p.store, true, cols, lr, cols, gbuf, lr, c.partial, c.partial_cap,
+                          c.s);
+        }));
+    } else {
     GemmX g;  // G = H H^T, FP64 arithmetic and result whatever the storage
     g.A = hsrc;
     g.lda = cols;
@@ -484,6 +496,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     g.K = cols;
     g.math = DType::F64;
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
+    }
     if (!c.dry) TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s));
     Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n)
     h.A = Sf;

@@ -1,0 +1,174 @@
+// Gram matrices of tall panels in FP64: G = A^T A for the thin QR of the
+// sweep (Algorithm 5, CholeskyQR with an FP64 Gram) and G = H H^T for the
+// truncation (the mirror of Algorithm 2's loop), n <= 128 columns.
+//
+// A workgroup takes a chunk of kChunk rows of the panel (k), stages it in LDS
+// as FP64 with one batch of loads (all in flight together), and forms the
+// upper-triangle 16 x 16 blocks of the chunk's contribution with the f64
+// MFMA; each block is written with its mirror, so every split is a full
+// n x n matrix.  The splits are added in a fixed order by the split sum of
+// the GEMM module (bitwise reproducible), or written to G directly when the
+// panel has one chunk.
+#include <algorithm>
+
+#include "tt_internal.h"
+
+namespace ttr {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kChunk = 64;        // panel rows per workgroup
+constexpr int kGramThreads = 256;  // four wavefronts
+constexpr int kMaxN = 128;
+
+// A(k, m) of the panel: AKC = false: A is K x n row-major (leading dimension
+// lda); AKC = true: the panel is stored transposed, n x K row-major (H of a
+// core, rows of length lda).
+template <typename TA, bool AKC>
+__global__ __launch_bounds__(kGramThreads) void gram_kernel(const TA *A, int64_t lda, int n,
+                                                            int64_t K, double *out, int direct,
+                                                            int64_t ldg) {
+  extern __shared__ __attribute__((aligned(16))) double gs[];  // [kChunk][ld]
+  const int ld = ((n + 15) / 16) * 16 + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t k0 = (int64_t)blockIdx.x * kChunk;
+  const int nk = (int)min<int64_t>(kChunk, K - k0);
+  const int np = ((n + 15) / 16) * 16;
+
+  // stage rows k0 .. k0 + kChunk (zero beyond K and beyond n)
+  constexpr int kPer = kChunk * kMaxN / kGramThreads;  // values per thread, at most
+  const int total = kChunk * np;
+  double v[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int e = tid + t * kGramThreads;
+    int k, m;
+    if (AKC) {  // consecutive threads along k (contiguous in memory)
+      m = e / kChunk;
+      k = e - m * kChunk;
+    } else {  // consecutive threads along m
+      k = e / np;
+      m = e - k * np;
+    }
+    const bool ok = e < total && k < nk && m < n;
+    v[t] = ok ? (double)(AKC ? A[(int64_t)m * lda + k0 + k] : A[(k0 + k) * lda + m]) : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int e = tid + t * kGramThreads;
+    if (e < total) {
+      int k, m;
+      if (AKC) {
+        m = e / kChunk;
+        k = e - m * kChunk;
+      } else {
+        k = e / np;
+        m = e - k * np;
+      }
+      gs[k * ld + m] = v[t];
+    }
+  }
+  __syncthreads();
+
+  // upper-triangle blocks (I <= J) dealt round-robin to the wavefronts
+  const int nb = np / 16, nblk = nb * (nb + 1) / 2;
+  for (int blk = wave; blk < nblk; blk += kGramThreads / 64) {
+    int I = 0, rem = blk;
+    while (rem >= nb - I) {
+      rem -= nb - I;
+      ++I;
+    }
+    const int J = I + rem;
+    d4_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const double *pa = gs + q * ld + 16 * I + r;
+    const double *pb = gs + q * ld + 16 * J + r;
+#pragma unroll 4
+    for (int kk = 0; kk < kChunk; kk += 8) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk * ld], pb[kk * ld], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[(kk + 4) * ld], pb[(kk + 4) * ld], acc1,
+                                                 0, 0, 0);
+    }
+    const d4_t acc = acc0 + acc1;
+    // lane (r, q), register j: G(16 I + q + 4 j, 16 J + r)
+    double *o = direct ? out : out + (int64_t)blockIdx.x * n * n;
+    const int64_t ldo = direct ? ldg : n;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 16 * I + q + 4 * j, col = 16 * J + r;
+      if (row < n && col < n) {
+        o[row * ldo + col] = acc[j];
+        if (I != J) o[col * ldo + row] = acc[j];
+      }
+    }
+  }
+}
+
+int64_t chunks_of(int64_t K) { return (K + kChunk - 1) / kChunk; }
+
+template <typename TA, bool AKC>
+int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t ldg,
+           void *partial, hipStream_t s) {
+  const int64_t nc = chunks_of(K);
+  const int ld = (int)(((n + 15) / 16) * 16 + 2);
+  const size_t lds = (size_t)kChunk * ld * sizeof(double);
+  static bool attr = false;
+  if (!attr && lds > 64 * 1024) {
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_kernel<TA, AKC>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr = true;
+  }
+  const bool direct = nc == 1;
+  hipLaunchKernelGGL((gram_kernel<TA, AKC>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
+                     static_cast<const TA *>(A), lda, (int)n, K,
+                     direct ? G : static_cast<double *>(partial), direct ? 1 : 0, ldg);
+  TTR_HIP(hipGetLastError());
+  if (!direct) {
+    GemmX g;  // the chunk splits, summed in a fixed order
+    g.C = G;
+    g.ldc = ldg;
+    g.tc = DType::F64;
+    g.M = n;
+    g.N = n;
+    g.K = 1;
+    g.math = DType::F64;
+    g.splits = (int)nc;
+    g.partial = partial;
+    TTR_TRY(gemm_reduce_splits(g, s));
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+static int g_gram_mode = 0;  // 0: this kernel where supported, 1: split-K GEMM
+
+void gram_set_mode(int mode) { g_gram_mode = mode; }
+
+bool gram_supported(int64_t n, int64_t K) {
+  return n >= 1 && n <= kMaxN && K >= 1 && chunks_of(K) <= 256;
+}
+
+bool gram_enabled(int64_t n, int64_t K) { return g_gram_mode == 0 && gram_supported(n, K); }
+
+size_t gram_partial_elems(int64_t n, int64_t K) {
+  const int64_t nc = chunks_of(K);
+  return nc > 1 ? (size_t)(nc * n * n) : 0;
+}
+
+int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t K, double *G,
+             int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s) {
+  if (!gram_supported(n, K)) return fail(TT_EINVAL, "internal: Gram shape not supported");
+  if (gram_partial_elems(n, K) * sizeof(double) > partial_bytes)
+    return fail(TT_EINVAL, "internal: split buffer too small for the Gram");
+  if (ta == DType::F64)
+    return a_kc ? launch<double, true>(A, lda, n, K, G, ldg, partial, s)
+                : launch<double, false>(A, lda, n, K, G, ldg, partial, s);
+  if (ta == DType::F32)
+    return a_kc ? launch<float, true>(A, lda, n, K, G, ldg, partial, s)
+                : launch<float, false>(A, lda, n, K, G, ldg, partial, s);
+  return fail(TT_EINVAL, "internal: Gram storage type");
+}
+
+}  // namespace ttr

@@ -16,6 +16,8 @@
 // enqueued and returns at once unless the flag is set.  Householder columns are
 // sign-normalised afterwards so that diag(R) >= 0 (zero counts as +).
 #include "fastmath.h"
+#include <algorithm>
+
 #include "tt_internal.h"
 #include "wave.h"
 
@@ -324,8 +326,11 @@ __global__ __launch_bounds__(kHhThreads) void householder_group_kernel(const HhG
 void qr_set_mode(int mode) { g_qr_mode = mode; }
 
 size_t qr_partial_elems(int64_t m, int64_t n) {
+  // the Gram kernel's chunk splits or the split-K GEMM's partials, whichever
+  // the Gram takes (both sizes, so that the choice can change between calls)
   const int sp = gemm_pick_splits(n, n, m, DType::F64);
-  return sp > 1 ? (size_t)sp * n * n : 0;
+  const size_t gemm_need = sp > 1 ? (size_t)sp * n * n : 0;
+  return std::max(gemm_need, gram_supported(n, m) ? gram_partial_elems(n, m) : (size_t)0);
 }
 
 template <int NMAX>
@@ -386,6 +391,10 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   for (int pass = 0; pass < 2; ++pass) {
     const T *src = pass == 0 ? Y : q1;
     T *dst = pass == 0 ? q1 : Q;
+    if (gram_enabled(n, m)) {
+      TTR_TRY(gram_run(src, DTypeOf<T>::value, false, n, n, m, ws.gram, n, ws.partial,
+                       gram_partial_elems(n, m) * sizeof(double), s));
+    } else {
     GemmX g;  // G = src^T src, accumulated in FP64
     g.A = src;
     g.lda = n;
@@ -405,6 +414,7 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     g.splits = gemm_pick_splits(n, n, m, DType::F64);
     g.partial = ws.partial;
     TTR_TRY(gemmx_run(g, s));
+    }
     TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
     Gemm<T> h;  // dst = src Rinv, in the storage precision
     h.A = src;

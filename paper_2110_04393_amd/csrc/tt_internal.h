@@ -275,6 +275,17 @@ struct QrScratch {
   void *partial = nullptr;     // split-K partials
 };
 size_t qr_partial_elems(int64_t m, int64_t n);
+// FP64 Gram of a tall panel: G = A^T A (n x n, ld ldg) for A(k, m) stored
+// K x n row-major (a_kc false, leading dimension lda) or n x K row-major
+// (a_kc true); n <= 128, K <= 16384 (gram_supported).  Needs
+// gram_partial_elems doubles of split buffer when K > 64.  gram_set_mode(1)
+// makes the callers use the split-K GEMM instead.
+bool gram_supported(int64_t n, int64_t K);
+size_t gram_partial_elems(int64_t n, int64_t K);
+int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t K, double *G,
+             int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s);
+void gram_set_mode(int mode);
+bool gram_enabled(int64_t n, int64_t K);
 template <typename T>
 int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s);
 void qr_set_mode(int mode);  // 0 auto, 1 force householder, 2 force cholqr2

@@ -107,18 +107,23 @@ def test_small_sum_workload_exact(gpu_lib):
     assert O.rel_diff(out, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("qr", ["auto", "householder", "cholqr2"])
+@pytest.mark.parametrize("qr", ["auto", "householder", "cholqr2", "cholqr2-gemm-gram"])
 @pytest.mark.parametrize("case", [
     (6, 9, 12, 7, 0),     # small: Householder panels
     (5, 40, 50, 23, 0),   # ragged, CholeskyQR2 panels
     (4, 64, 64, 32, 0),
+    (3, 170, 100, 96, 0),  # a 96-column panel of 16320 rows: 255 Gram chunks
 ])
 def test_rto_cores_match_oracle(gpu_lib, case, qr, monkeypatch):
-    # without truncation the output is unique (diag R >= 0): compare core by core
+    # without truncation the output is unique (diag R >= 0): compare core by core;
+    # "cholqr2-gemm-gram" forms the FP64 Gram with the split-K GEMM instead of
+    # the panel-Gram kernel
     N, I, R, t, p = case
     say(f"RtO cores {case} qr={qr}")
     if qr != "auto":
-        monkeypatch.setenv("TT_QR", qr)
+        monkeypatch.setenv("TT_QR", "cholqr2" if qr.startswith("cholqr2") else qr)
+    if qr == "cholqr2-gemm-gram":
+        monkeypatch.setenv("TT_GRAM", "gemm")
     dims, ranks = G.uniform_tt_shape(N, I, R)
     Y = G.random_tt(21 + N, dims, ranks, scale="nominal")
     out = host(gpu_lib.round_rand(dev(Y), t, p, seed=77))
@@ -130,18 +135,21 @@ def test_rto_cores_match_oracle(gpu_lib, case, qr, monkeypatch):
         assert np.abs(Vn.T @ Vn - np.eye(Vn.shape[1])).max() < 1e-12
 
 
-@pytest.mark.parametrize("eig", ["auto", "jacobi"])
+@pytest.mark.parametrize("eig", ["auto", "jacobi", "gemm-gram"])
 @pytest.mark.parametrize("case", [
     (6, 9, 12, 5, 3),
     (5, 40, 50, 20, 6),
     (3, 7, 5, 2, 1),
 ])
 def test_rto_truncated_matches_oracle(gpu_lib, case, eig, monkeypatch):
-    # eig = "jacobi" takes the fallback branch of the fused finish kernel
+    # eig = "jacobi" takes the fallback branch of the fused finish kernel;
+    # "gemm-gram" forms every FP64 Gram with the split-K GEMM
     N, I, R, t, p = case
     say(f"RtO truncated {case} eig={eig}")
-    if eig != "auto":
+    if eig == "jacobi":
         monkeypatch.setenv("TT_EIG", eig)
+    if eig == "gemm-gram":
+        monkeypatch.setenv("TT_GRAM", "gemm")
     dims, ranks = G.uniform_tt_shape(N, I, R)
     Y = G.random_tt(31 + N, dims, ranks, scale="nominal")
     out = host(gpu_lib.round_rand(dev(Y), t, p, seed=5))
