@@ -5,8 +5,9 @@
 // A workgroup takes a chunk of kChunk rows of the panel (k), stages it in LDS
 // as FP64 with one batch of loads (all in flight together), and forms the
 // upper-triangle 16 x 16 blocks of the chunk's contribution with the f64
-// MFMA; each block is written with its mirror, so every split is a full
-// n x n matrix.  The splits are added in a fixed order by the split sum of
+// MFMA, one block per wavefront at a time (sixteen wavefronts: the MFMA chain
+// of a block is the latency to hide); each block is written with its mirror,
+// so every split is a full n x n matrix.  The splits are added in a fixed order by the split sum of
 // the GEMM module (bitwise reproducible), or written to G directly when the
 // panel has one chunk.
 #include <algorithm>
@@ -19,7 +20,7 @@ namespace {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = 64;        // panel rows per workgroup
-constexpr int kGramThreads = 256;  // four wavefronts
+constexpr int kGramThreads = 1024;  // sixteen wavefronts
 constexpr int kMaxN = 128;
 
 // A(k, m) of the panel: AKC = false: A is K x n row-major (leading dimension
