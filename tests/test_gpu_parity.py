@@ -72,6 +72,10 @@ def test_device_sketch_float32(gpu_lib):
     (3, 4, 300, 100),  # W_n^T too large for the LDS: two products
     (5, 9, 36, 70),    # five c-blocks, ragged sketch rank, R a multiple of 4
     (4, 3, 8, 17),     # one k-chunk per unit, ragged a-block
+    (4, 1, 4, 1),      # one mode index, sketch rank 1
+    (5, 2, 4, 3),      # R = 4: one partial k-chunk
+    (3, 2, 8, 96),     # widest sketch rank the rounding allows (eight c- and b-blocks)
+    (3, 37, 96, 5),    # six a-blocks, l = 5
 ])
 def test_partial_contractions_match_oracle(gpu_lib, case, mode, monkeypatch):
     # mode "fused": interior levels in one kernel where the shapes allow it;

@@ -68,7 +68,7 @@ def test_bf16_sketch_matches_oracle(gpu_lib):
 
 @pytest.mark.parametrize("mode", ["fused", "gemm"])
 @pytest.mark.parametrize("case", [(5, 3, 4, 3), (6, 17, 37, 21), (4, 100, 200, 60),
-                                  (4, 9, 30, 75)])
+                                  (4, 9, 30, 75), (4, 9, 32, 75), (4, 1, 4, 1)])
 def test_wchain_f32(gpu_lib, case, mode, monkeypatch):
     if mode == "gemm":
         monkeypatch.setenv("TT_WCHAIN", "gemm")
@@ -127,7 +127,7 @@ def test_wchain_bf16_chain(gpu_lib, case, mode, monkeypatch):
 
 
 @pytest.mark.parametrize("case", [(6, 40, 32, 20), (5, 17, 36, 70), (4, 100, 200, 60),
-                                  (3, 9, 8, 17)])
+                                  (3, 9, 8, 17), (4, 1, 4, 1), (3, 2, 8, 96)])
 def test_wchain_bf16_fused_matches_two_products(gpu_lib, case, monkeypatch):
     # both forms round Y_n, W_n, V(Y_n) W_n and the sketch to bf16 and
     # accumulate in fp32; they differ in the order of the fp32 sums only.
