@@ -364,13 +364,51 @@ def main():
         den = sum(float((b ** 2).sum()) for b in out64)
         res["f64_gpu"] = {"ms_per_step": round(ms64, 4), "speedup": round(ms64 / ms_per_step, 3),
                           "core_rel_diff": float(f"{math.sqrt(num / max(den, 1e-300)):.3e}")}
-        log(f"FP64 GPU path: {ms64:.3f} ms/step; {args.prec} speedup {ms64 / ms_per_step:.2f}x")
+        # gauge-free quality of both roundings: ||X - Y|| / ||Y|| from TT inner
+        # products (FP64 partial contractions through the library)
+        terms = ([(1.0, wl["inputs"])] if wl["kind"] == "single"
+                 else list(zip(wl["coeffs"], wl["inputs"])))
+        e_mode, k_mode = rounding_error(tt, out, terms, dev)
+        e_64, k_64 = rounding_error(tt, out64, terms, dev)
+        res["f64_gpu"].update(rounding_rel_err=float(f"{e_mode:.6e}"),
+                              rounding_rel_err_f64=float(f"{e_64:.6e}"),
+                              kept_norm2=float(f"{k_mode:.6e}"),
+                              kept_norm2_f64=float(f"{k_64:.6e}"))
+        log(f"FP64 GPU path: {ms64:.3f} ms/step; {args.prec} speedup {ms64 / ms_per_step:.2f}x; "
+            f"||X - Y||/||Y||: {args.prec} {e_mode:.6e}, f64 {e_64:.6e}; kept part of ||Y||^2: "
+            f"{args.prec} {k_mode:.6e}, f64 {k_64:.6e}")
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(wl, out, budget_s=args.cpu_budget)
         res["cpu_baseline"] = cb
         res["accuracy"] = {"rel_err_vs_fp64_oracle": float(f"{err:.3e}")}
         log(f"oracle: {cb['value']} ms/rounding on {cb['cores']} threads; GPU rel err {err:.2e}")
     print(json.dumps(res), flush=True)
+
+
+def tt_inner(tt, A, B):
+    """<A, B> of two TTs (device FP64 cores, same mode sizes) from the
+    library's partial contractions: W_1 = H(A_{2:N}) H(B_{2:N})^T, then the
+    first cores."""
+    import torch
+    if len(A) == 1:
+        return float((A[0] * B[0]).sum())
+    W = tt.partial_contractions_rl(A, B, prec="f64")
+    torch.cuda.synchronize()
+    return float(((A[0][0] @ W[1]) * B[0][0]).sum())
+
+
+def rounding_error(tt, X, terms, dev):
+    """(||X - Y|| / ||Y||, (2 <X, Y> - <X, X>) / <Y, Y>) for Y = sum_j c_j Y_j
+    (numpy cores); the second is the part of ||Y||^2 the rounding keeps,
+    accurate also when the first is close to 1."""
+    import torch
+    D = lambda cores: [torch.from_numpy(c).to(dev).double() for c in cores]
+    Xd = D(X)
+    Ys = [(c, D(Y)) for c, Y in terms]
+    xx = tt_inner(tt, Xd, Xd)
+    xy = sum(c * tt_inner(tt, Xd, Y) for c, Y in Ys)
+    yy = sum(ci * cj * tt_inner(tt, Yi, Yj) for ci, Yi in Ys for cj, Yj in Ys)
+    return math.sqrt(max(xx - 2.0 * xy + yy, 0.0) / yy), (2.0 * xy - xx) / yy
 
 
 def batch_flops(spec, ell):
