@@ -1,6 +1,7 @@
-// One level of the partial contractions of Algorithm 3 in a single kernel.
+// One level of the partial contractions of Algorithm 3 in a single kernel,
+// for every summand of a sum (Algorithm 7) at once.
 //
-// For one TT Y (core n: R0 x I x R1), one sketch core Sk_n (L0 x I x L1) and
+// For a TT Y (core n: R0 x I x R1), the sketch core Sk_n (L0 x I x L1) and
 // W_n (R1 x L1) it computes
 //   W_{n-1}(a, b) = sum_i sum_c Z(a, i, c) Sk_n(b, i, c),
 //   Z(a, i, c)    = sum_k Y_n(a, i, k) W_n(k, c),
@@ -8,22 +9,27 @@
 // the recursion that defines W_n), without writing Z = V(Y_n) W_n to memory.
 //
 // Work decomposition.  A unit is (16 consecutive a, one i): its Z block is
-// 16 x L1.  A workgroup owns one 16-row a-block and a range of i; it holds
-// W_n^T in LDS (all of it: L1 rows, R1 columns) and has ncb = ceil(L1 / 16)
-// wavefronts per unit lane (one per 16-wide c-block) and one or two unit
-// lanes.  Per unit, the wavefront of c-block cb
+// 16 x L1.  A workgroup owns one 16-row a-block of one summand and a range of
+// i; it holds that summand's W_n^T in LDS (all of it: L1 rows, R1 columns).
+// Its wavefronts form NCB c-block columns (4 for L1 <= 64, else 8; blocks
+// past L1 are zero) x ULN unit lanes; a lane takes the units i, i + ULN, ...
+// of the range.  Per unit, the wavefront of c-block cb
 //   1. forms Z^T(c-block, a-block) = W^T(c-block, :) Y_i^T (:, a-block) with
-//      the x4 MFMA instruction (W^T fragments from LDS, Y fragments straight
-//      from memory, four 16-wide k-chunks in flight per lane),
+//      the x4 MFMA instruction of the arithmetic (W^T fragments from LDS, Y
+//      staged through LDS: in each batch of NCB 16-wide k-chunks every
+//      wavefront of the lane loads one chunk with raw buffer loads and all of
+//      them read it after one barrier; the next batch is in flight meanwhile),
 //   2. multiplies its accumulator, still in registers, by Sk_n(:, i, c-block)^T
-//      into the running W_{n-1}(a-block, :) accumulator.
+//      into the running W_{n-1}(a-block, :) accumulator (the Sk fragments of a
+//      unit are loaded while the previous unit runs).
 // Step 2 needs lane (r, q) of the accumulator to hold Z(a0 + r, c) for four
 // consecutive c: the accumulator of the f32 instruction holds rows 4 q + j
 // already; for the f64 instruction (rows q + 4 j) the W^T rows are staged in
 // the permuted order m -> 4 (m % 4) + m / 4, which gives the same property.
 // At the end the wavefronts' accumulators are summed in LDS in a fixed order
-// and written as one split of the result (summed over the i-ranges by the
-// split-K reduction of the GEMM module) or directly when there is one range.
+// and written as one i-range split of the result (added in split order by
+// wfuse_sum_kernel) or directly when there is one range.  The BF16 form
+// (wfuse_bf16_kernel) follows the same plan with the bf16 instruction.
 #include <algorithm>
 #include <type_traits>
 
