@@ -1,6 +1,8 @@
 // Thin QR of tall-skinny sketches (Algorithm 5 / Algorithm 7: QR of Y_n).
 //
-// Fast path: CholeskyQR2 in FP64.  G = Y^T Y (MFMA, split-K), G = R^T R by a
+// Fast path: CholeskyQR2 in FP64.  G = Y^T Y (the panel-Gram kernel, MFMA over
+// 64-row chunks and a split sum; the split-K GEMM for panels it does not
+// take), G = R^T R by a
 // one-workgroup Cholesky that also forms R^{-1}, Q1 = Y R^{-1} (MFMA); the same
 // again on Q1 (whose Gram is within rounding of I, so that its factor is
 // usually taken to first order).  Both Cholesky factors have positive
@@ -8,8 +10,7 @@
 // rest of the method uses.
 //
 // Robust path: Householder QR in one workgroup, used for panels of at most 8
-// columns and,
-// without a host round trip, whenever a Cholesky pivot falls below
+// columns and, without a host round trip, whenever a Cholesky pivot falls below
 // 1e-14 of its original diagonal entry (the sketch is numerically rank
 // deficient, e.g. rounding A+A with a sketch wider than the rank).  The
 // Cholesky kernels raise a device flag; the Householder kernel is always
