@@ -126,20 +126,20 @@ __device__ __forceinline__ void load4(const __bf16 *p, To (&o)[4]) {
 // (measured on gfx950), so the tiles for outputs with a side of at most 64
 // (most of the method's products) are 32 x 64 and 64 x 32 with eight
 // 16 x 16 wavefronts: more workgroups and more wavefronts per CU.
-template <int WM, int WN>
+template <int WM, int WN, int BKO>
 constexpr int lds_bk() {
-  return WM * WN == 8 ? 16 : 32;
+  return BKO ? BKO : (WM * WN == 8 ? 16 : 32);
 }
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
+          int WM, int WN, int BKO>
 __device__ __forceinline__ void gemm_lds_body(const GemmX &g, const TileMap &tm, int64_t wg) {
   static_assert(MT::CPL == 4, "x4 MFMA instructions");
   typedef typename MT::acc_t acc_t;
   typedef typename MT::in_t in_t;
   typedef typename MT::part_t part_t;
   constexpr int T = 64 * WM * WN;
-  constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = lds_bk<WM, WN>();
+  constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = lds_bk<WM, WN, BKO>();
   constexpr int PAD = sizeof(in_t) == 8 ? 8 : 16;
   constexpr int GA = BM * BK / 4, GB = BN * BK / 4;  // 4-element groups per tile
   constexpr int RA = (GA + T - 1) / T, RB = (GB + T - 1) / T;
@@ -488,25 +488,25 @@ __device__ __forceinline__ void gemm_lds_bf16_body(const GemmX &g, const TileMap
 
 // the body for the x4 instructions or the bf16 one
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
+          int WM, int WN, int BKO>
 __device__ __forceinline__ void gemm_any_body(const GemmX &g, const TileMap &tm, int64_t wg) {
   if constexpr (MT::CPL == 4)
-    gemm_lds_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
+    gemm_lds_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>(g, tm, wg);
   else
     gemm_lds_bf16_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, wg);
 }
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
+          int WM, int WN, int BKO>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmX g, TileMap tm) {
-  gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(g, tm, blockIdx.x);
+  gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>(g, tm, blockIdx.x);
 }
 
 // Grouped form: one launch over several independent products (same types,
 // layouts and tile shape, any sizes).  Workgroup b belongs to the entry with
 // the largest wg_begin <= b.
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
+          int WM, int WN, int BKO>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_group_kernel(const GemmGroupEntry *tab, int count) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = count - 1;
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_group_kernel(const GemmGrou
   tm.tiles_m = e.tiles_m;
   tm.tiles_n = e.tiles_n;
   tm.kchunk = e.kchunk;
-  gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>(e.g, tm, b - e.wg_begin);
+  gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>(e.g, tm, b - e.wg_begin);
 }
 
 // Sum of the split-K partials into C: 32 output elements per workgroup, the
@@ -582,8 +582,14 @@ struct Variant {
   int tm, tn, wm, wn;
 };
 // Output tile per workgroup, every arithmetic: 32x64, 64x32 (eight
-// wavefronts each), 64x64, 128x128 (four wavefronts each)
-constexpr Variant kVarLds[] = {{1, 1, 2, 4}, {1, 1, 4, 2}, {2, 2, 2, 2}, {4, 4, 2, 2}};
+// wavefronts each, K steps of 16), 64x64, 128x128 (four wavefronts each, K
+// steps of 32); variants 4 and 5 are the eight-wavefront tiles with K steps
+// of 32, which the single path takes for grids of at most kDeepGrid
+// workgroups (half the steps, and occupancy matters less in a grid that
+// does not fill the CUs twice)
+constexpr Variant kVarLds[] = {{1, 1, 2, 4}, {1, 1, 4, 2}, {2, 2, 2, 2},
+                               {4, 4, 2, 2}, {1, 1, 2, 4}, {1, 1, 4, 2}};
+constexpr int64_t kDeepGrid = 320;
 
 const Variant &variant_of(DType math, int v) {
   (void)math;  // one table for every arithmetic
@@ -614,16 +620,16 @@ int pick_variant(int64_t M, int64_t N, DType math) {
 }
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
-          int WM, int WN>
+          int WM, int WN, int BKO = 0>
 void launch_one(const GemmX &g, const TileMap &tm, int64_t grid, hipStream_t s,
                 const GemmGroupEntry *tab, int count) {
   const dim3 gr((unsigned)grid), bl(64 * WM * WN);
   if (tab)
-    hipLaunchKernelGGL((gemm_group_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>), gr, bl, 0, s,
-                       tab, count);
+    hipLaunchKernelGGL((gemm_group_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>), gr, bl,
+                       0, s, tab, count);
   else
-    hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN>), gr, bl, 0, s, g,
-                       tm);
+    hipLaunchKernelGGL((gemm_kernel<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>), gr, bl, 0, s,
+                       g, tm);
 }
 
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC>
@@ -638,6 +644,12 @@ void launch_layout(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipSt
       break;
     case 2:
       launch_one<MT, TA, TB, TC, AKC, BKC, 2, 2, 2, 2>(g, tm, grid, s, tab, count);
+      break;
+    case 4:
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 2, 4, 32>(g, tm, grid, s, tab, count);
+      break;
+    case 5:
+      launch_one<MT, TA, TB, TC, AKC, BKC, 1, 1, 4, 2, 32>(g, tm, grid, s, tab, count);
       break;
     default:
       launch_one<MT, TA, TB, TC, AKC, BKC, 4, 4, 2, 2>(g, tm, grid, s, tab, count);
@@ -741,7 +753,8 @@ int gemmx_run(const GemmX &g, hipStream_t s) {
   if (gg.splits > 1 && gg.partial == nullptr) return fail(TT_EINVAL, "split-K without buffer");
   if (gg.splits > kRedMaxGroups * kSplitGroup) return fail(TT_EINVAL, "internal: too many K splits");
   const int64_t grid = tm.tiles_m * tm.tiles_n * (g.batch > 1 ? g.batch : used_splits);
-  if (!dispatch(v, gg, tm, grid, s)) return fail(TT_EINVAL, "internal: gemm type combination");
+  const int vv = (v <= 1 && grid <= kDeepGrid && g.math != DType::BF16) ? v + 4 : v;
+  if (!dispatch(vv, gg, tm, grid, s)) return fail(TT_EINVAL, "internal: gemm type combination");
   TTR_HIP(hipGetLastError());
   if (gg.splits > 1) TTR_TRY(gemm_reduce_splits(gg, s));
   return TT_OK;
