@@ -2,7 +2,7 @@
 // sweep (Algorithm 5, CholeskyQR with an FP64 Gram) and G = H H^T for the
 // truncation (the mirror of Algorithm 2's loop), n <= 128 columns.
 //
-// A workgroup takes a chunk of kChunk rows of the panel (k), stages it in LDS
+// A workgroup takes a chunk of 32 or 64 rows of the panel (k), stages it in LDS
 // as FP64 with one batch of loads (all in flight together), and forms the
 // upper-triangle 16 x 16 blocks of the chunk's contribution with the f64
 // MFMA, one block per wavefront at a time (sixteen wavefronts: the MFMA chain
@@ -19,14 +19,15 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kChunk = 64;        // panel rows per workgroup
+// panel rows per workgroup: 32, or 64 for panels of more than 256 x 32 rows
+// (the split sum takes at most 256 splits)
 constexpr int kGramThreads = 1024;  // sixteen wavefronts
 constexpr int kMaxN = 128;
 
 // A(k, m) of the panel: AKC = false: A is K x n row-major (leading dimension
 // lda); AKC = true: the panel is stored transposed, n x K row-major (H of a
 // core, rows of length lda).
-template <typename TA, bool AKC>
+template <typename TA, bool AKC, int kChunk>
 __global__ __launch_bounds__(kGramThreads) void gram_kernel(const TA *A, int64_t lda, int n,
                                                             int64_t K, double *out, int direct,
                                                             int64_t ldg) {
@@ -106,22 +107,23 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const TA *A, int64_t
   }
 }
 
-int64_t chunks_of(int64_t K) { return (K + kChunk - 1) / kChunk; }
+int chunk_rows(int64_t K) { return (K + 31) / 32 <= 256 ? 32 : 64; }
+int64_t chunks_of(int64_t K) { return (K + chunk_rows(K) - 1) / chunk_rows(K); }
 
-template <typename TA, bool AKC>
+template <typename TA, bool AKC, int kChunk>
 int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t ldg,
            void *partial, hipStream_t s) {
-  const int64_t nc = chunks_of(K);
+  const int64_t nc = (K + kChunk - 1) / kChunk;
   const int ld = (int)(((n + 15) / 16) * 16 + 2);
   const size_t lds = (size_t)kChunk * ld * sizeof(double);
   static bool attr = false;
   if (!attr && lds > 64 * 1024) {
-    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_kernel<TA, AKC>),
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_kernel<TA, AKC, kChunk>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
   const bool direct = nc == 1;
-  hipLaunchKernelGGL((gram_kernel<TA, AKC>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
+  hipLaunchKernelGGL((gram_kernel<TA, AKC, kChunk>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
                      static_cast<const TA *>(A), lda, (int)n, K,
                      direct ? G : static_cast<double *>(partial), direct ? 1 : 0, ldg);
   TTR_HIP(hipGetLastError());
@@ -163,12 +165,21 @@ int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t
   if (!gram_supported(n, K)) return fail(TT_EINVAL, "internal: Gram shape not supported");
   if (gram_partial_elems(n, K) * sizeof(double) > partial_bytes)
     return fail(TT_EINVAL, "internal: split buffer too small for the Gram");
-  if (ta == DType::F64)
-    return a_kc ? launch<double, true>(A, lda, n, K, G, ldg, partial, s)
-                : launch<double, false>(A, lda, n, K, G, ldg, partial, s);
-  if (ta == DType::F32)
-    return a_kc ? launch<float, true>(A, lda, n, K, G, ldg, partial, s)
-                : launch<float, false>(A, lda, n, K, G, ldg, partial, s);
+  const bool c32 = chunk_rows(K) == 32;
+  if (ta == DType::F64) {
+    if (a_kc)
+      return c32 ? launch<double, true, 32>(A, lda, n, K, G, ldg, partial, s)
+                 : launch<double, true, 64>(A, lda, n, K, G, ldg, partial, s);
+    return c32 ? launch<double, false, 32>(A, lda, n, K, G, ldg, partial, s)
+               : launch<double, false, 64>(A, lda, n, K, G, ldg, partial, s);
+  }
+  if (ta == DType::F32) {
+    if (a_kc)
+      return c32 ? launch<float, true, 32>(A, lda, n, K, G, ldg, partial, s)
+                 : launch<float, true, 64>(A, lda, n, K, G, ldg, partial, s);
+    return c32 ? launch<float, false, 32>(A, lda, n, K, G, ldg, partial, s)
+               : launch<float, false, 64>(A, lda, n, K, G, ldg, partial, s);
+  }
   return fail(TT_EINVAL, "internal: Gram storage type");
 }
 
