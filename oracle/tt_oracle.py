@@ -14,6 +14,7 @@ rounding in the Tensor-Train format") step by step in its notation:
 * PartialContractionsRL (the W_n chain) ............. Algorithm 3, eq. (RLContraction)
 * random Gaussian TT sketch ......................... Definition 3.1
 * Randomize-then-Orthogonalize ...................... Algorithm 5
+* Two-Sided-Randomization (generalized Nystrom) ..... Algorithm 6, eq. (LnRn)
 * rounding a sum, Randomize-then-Orthogonalize ...... Algorithm 7
 * truncation of the left-orthogonal RtO output ...... section 3.2 (remark after
   Algorithm 5), run as the right-to-left mirror of Algorithm 2
@@ -36,6 +37,9 @@ Readings taken where the paper is silent (each also listed in the design notes):
 * eps-truncation is absolute: keep the smallest k >= 1 with
   sqrt(sum_{j>k} s_j^2) <= eps0 ||Y|| / sqrt(N-1), capped by max_rank.
 * Sum coefficients multiply each summand's first core.
+* Two-Sided-Randomization: l_n as above with no oversampling, right sketch
+  ranks rho_n = ceil(3 l_n / 2) capped by I_{n+1} ... I_N; the pseudo-inverse
+  of W^L_n W^R_n drops singular values at or below 1e-6 of the largest.
 * Reduced-precision modes are compared with this FP64 oracle run on the same
   inputs and on the same sketch values: the FP32 sketch is the FP64 draw
   rounded to nearest-even FP32, the BF16 sketch is that FP32 value rounded
@@ -428,6 +432,101 @@ def round_svd(Y, eps0=0.0, max_rank=None):
         nxt = (S[:k, None] * Vt[:k]) @ H(X[n + 1])
         X[n + 1] = nxt.reshape(k, X[n + 1].shape[1], X[n + 1].shape[2])
     return X, ranks_of(X), tails
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 6: Two-Sided-Randomization (generalized Nystrom, section 3.3)
+# ----------------------------------------------------------------------------
+
+# singular values of W^L_n W^R_n at or below this fraction of the largest are
+# treated as zero in the pseudo-inverse
+NYSTROM_RCOND = 1e-6
+
+
+def plan_two_sided_ranks(dims, ranks, target):
+    """Left sketch ranks l_n (the output ranks) and right sketch ranks rho_n.
+
+    l_n follows plan_ranks with no oversampling.  rho_n = ceil(3 l_n / 2)
+    (the choice the experiments of section 4 make for the right sketch,
+    after the generalized Nystrom recommendation of section 2.2), capped by
+    I_{n+1} ... I_N, the row count of Omega_n; rho_0 = rho_N = 1."""
+    N = len(dims)
+    ell, _ = plan_ranks(dims, ranks, target, 0)
+    big = 1 << 40
+    w = [1] * (N + 1)
+    for n in range(N - 1, 0, -1):
+        w[n] = min(big, int(dims[n]) * w[n + 1])
+    rho = [1] * (N + 1)
+    for n in range(1, N):
+        rho[n] = min((3 * ell[n] + 1) // 2, w[n])
+    return ell, rho
+
+
+def partial_contractions_lr(X, Y):
+    """Left-to-right partial contractions, the mirror of Algorithm 3:
+    W_n = V(Y_{1:n})^T V(X_{1:n}) (r^Y_n x r^X_n) for 1 <= n < N, as a list
+    indexed by n (entry 0 unused).  W_1 = V(Y_1)^T V(X_1), then for
+    n = 2 .. N-1:  Z = W_{n-1} H(X_n) read as V(Z) (r^Y_{n-1} I_n x r^X_n),
+    W_n = V(Y_n)^T V(Z).  With Y the left sketch L this is
+    W^L_n = Psi_n V(X_{1:n})."""
+    N = len(X)
+    W = [None] * N
+    if N < 2:
+        return W
+    W[1] = V(Y[0]).T @ V(X[0])
+    for n in range(2, N):  # 1-based core index n
+        Xn, Yn = X[n - 1], Y[n - 1]
+        Z = (W[n - 1] @ H(Xn)).reshape(W[n - 1].shape[0] * Xn.shape[1], Xn.shape[2])
+        W[n] = V(Yn).T @ Z
+    return W
+
+
+def nystrom_factors(WL, WR):
+    """Equation (LnRn): with the SVD W^L W^R = U S V^T,
+    L = W^R V (S^+)^(1/2) and R = (S^+)^(1/2) U^T W^L, where S^+ inverts the
+    singular values above NYSTROM_RCOND times the largest and zeroes the
+    rest.  Returns (L, R)."""
+    C = WL @ WR
+    U, S, Vt = np.linalg.svd(C, full_matrices=False)
+    h = np.zeros_like(S)
+    if S.size and S[0] > 0:
+        keep = S > NYSTROM_RCOND * S[0]
+        h[keep] = 1.0 / np.sqrt(S[keep])
+    Lf = (WR @ Vt.T) * h[None, :]
+    Rf = h[:, None] * (U.T @ WL)
+    return Lf, Rf
+
+
+def round_two_sided(Y, target, seed_left=None, seed_right=None, sketch_left=None,
+                    sketch_right=None):
+    """Two-Sided-Randomization rounding (Algorithm 6) of TT Y to ranks l_n.
+
+    Sketches L (ranks l_n) and R (ranks rho_n) are drawn from seed_left and
+    seed_right (Definition 3.1) or given.  W^L from the left, W^R from the
+    right (Algorithm 3), the factors of equation (LnRn) at every bond, then
+    every core independently: X_1 = V(Y_1) L_1, H(X_n) = R_{n-1} H(V(Y_n) L_n),
+    H(X_N) = R_{N-1} H(Y_N)."""
+    Y = [np.array(c, dtype=np.float64) for c in Y]
+    N = len(Y)
+    if N == 1:
+        return [Y[0].copy()]
+    dims, ranks = dims_of(Y), ranks_of(Y)
+    ell, rho = plan_two_sided_ranks(dims, ranks, target)
+    if sketch_left is None:
+        sketch_left = make_sketch(seed_left, dims, ell)
+    if sketch_right is None:
+        sketch_right = make_sketch(seed_right, dims, rho)
+    WL = partial_contractions_lr(Y, sketch_left)
+    WR = partial_contractions_rl(Y, sketch_right)
+    Lf, Rf = [None] * N, [None] * N
+    for n in range(1, N):
+        Lf[n], Rf[n] = nystrom_factors(WL[n], WR[n])
+    X = [(V(Y[0]) @ Lf[1]).reshape(1, dims[0], ell[1])]
+    for n in range(2, N):  # 1-based core index n
+        T = (V(Y[n - 1]) @ Lf[n]).reshape(ranks[n - 1], dims[n - 1], ell[n])
+        X.append((Rf[n - 1] @ H(T)).reshape(ell[n - 1], dims[n - 1], ell[n]))
+    X.append((Rf[N - 1] @ H(Y[N - 1])).reshape(ell[N - 1], dims[N - 1], 1))
+    return X
 
 
 # ----------------------------------------------------------------------------

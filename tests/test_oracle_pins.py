@@ -481,3 +481,104 @@ def test_tt_inner_torch_matches_full_tensor():
     assert abs(ip - float(np.sum(O.full(A) * O.full(B)))) <= 1e-12 * max(1.0, abs(ip))
     ls = float(loss_round_minus_target([torch.tensor(c) for c in A], [torch.tensor(c) for c in B]))
     assert abs(ls - float(np.sum((O.full(A) - O.full(B)) ** 2))) <= 1e-10 * max(1.0, ls)
+
+
+# ---------------------------------------------------------------- Algorithm 6
+
+def _left_interface(cores):
+    """V(X_{1:n}) of the first n cores by successive dense products,
+    (I_1 ... I_n) x r_n."""
+    M = cores[0].reshape(-1, cores[0].shape[2])
+    for c in cores[1:]:
+        M = (M @ c.reshape(c.shape[0], -1)).reshape(-1, c.shape[2])
+    return M
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_partial_contractions_lr_brute_force(seed):
+    # closed form W^L_n = Psi_n V(Y_{1:n}) with Psi_n = V(L_{1:n})^T
+    X = tiny_tt(seed, N=5, I=3, R=4)
+    L = G.random_tt(seed + 70, [3] * 5, [1, 2, 3, 3, 2, 1], scale="unit")
+    W = O.partial_contractions_lr(X, L)
+    for n in range(1, 5):
+        want = _left_interface(L[:n]).T @ _left_interface(X[:n])
+        np.testing.assert_allclose(W[n], want, rtol=1e-12, atol=1e-12)
+
+
+def test_partial_contractions_lr_norm():
+    # with both tensors equal, W_{N-1} contracted with the last cores is ||X||^2
+    X = tiny_tt(4, N=6, I=3, R=3)
+    W = O.partial_contractions_lr(X, X)
+    last = O.H(X[-1])
+    val = float(np.sum(W[5] * (last @ last.T)))
+    assert val == pytest.approx(float(np.sum(O.full(X) ** 2)), rel=1e-12)
+
+
+def test_plan_two_sided_ranks():
+    ell, rho = O.plan_two_sided_ranks([10] * 8, [1] + [20] * 7 + [1], 10)
+    assert ell == [1] + [10] * 7 + [1]
+    assert rho == [1] + [15] * 6 + [10, 1]  # rho_7 capped by I_8 = 10
+    ell, rho = O.plan_two_sided_ranks([100] * 4, [1, 200, 200, 200, 1], 60)
+    assert ell == [1, 60, 60, 60, 1] and rho == [1, 90, 90, 90, 1]
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_two_sided_order_two_is_matrix_nystrom(seed):
+    # N = 2: Algorithm 6 is the generalized Nystrom approximation of section 2.2,
+    # Y Omega (Psi Y Omega)^+ Psi Y, with Psi = V(L_1)^T and Omega = H(R_2)^T
+    dims, ranks = [9, 11], [1, 7, 1]
+    Y = G.random_tt(seed, dims, ranks, scale="unit")
+    ell, rho = O.plan_two_sided_ranks(dims, ranks, 4)
+    Ls = O.make_sketch(10 + seed, dims, ell)
+    Rs = O.make_sketch(20 + seed, dims, rho)
+    X = O.round_two_sided(Y, 4, sketch_left=Ls, sketch_right=Rs)
+    A = O.full(Y).reshape(9, 11)
+    Psi = Ls[0].reshape(9, ell[1]).T
+    Omega = Rs[1].reshape(rho[1], 11).T
+    want = A @ Omega @ np.linalg.pinv(Psi @ A @ Omega, rcond=O.NYSTROM_RCOND) @ Psi @ A
+    np.testing.assert_allclose(O.full(X).reshape(9, 11), want, rtol=0,
+                               atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_two_sided_equals_dense_bond_projectors(seed):
+    # section 3.3: X is Y with the bond projector W^R_n (W^L_n W^R_n)^+ W^L_n
+    # inserted at every bond; W^L_n, W^R_n formed densely from the sketches
+    dims, ranks = [3, 4, 3, 4], [1, 4, 5, 4, 1]
+    Y = G.random_tt(30 + seed, dims, ranks, scale="unit")
+    ell, rho = O.plan_two_sided_ranks(dims, ranks, 2)
+    Ls = O.make_sketch(40 + seed, dims, ell)
+    Rs = O.make_sketch(50 + seed, dims, rho)
+    X = O.round_two_sided(Y, 2, sketch_left=Ls, sketch_right=Rs)
+    proj = []
+    for n in range(1, 4):
+        WL = _left_interface(Ls[:n]).T @ _left_interface(Y[:n])
+        WR = O.full_with_left_rank(Y[n:]) @ O.full_with_left_rank(Rs[n:]).T
+        proj.append(WR @ np.linalg.pinv(WL @ WR, rcond=O.NYSTROM_RCOND) @ WL)
+    cores = [np.einsum("aib,bc->aic", Y[n], proj[n]) for n in range(3)] + [Y[3]]
+    want = O.full(cores)
+    np.testing.assert_allclose(O.full(X), want, rtol=0, atol=1e-12 * np.abs(want).max())
+    assert O.ranks_of(X) == ell
+
+
+def test_two_sided_exact_on_small_sum_workload():
+    # generalized Nystrom is exact when every unfolding rank is at most l_n:
+    # A + A (rank 10, formally 20) -> 2A, also with l_n above the rank
+    w = G.workload_small_sum()
+    twoA = [2.0 * w["A"][0]] + [c.copy() for c in w["A"][1:]]
+    for target, tol in [(10, 1e-11), (12, 1e-9)]:
+        X = O.round_two_sided(w["X"], target, seed_left=3, seed_right=4)
+        assert O.rel_diff(X, twoA) <= tol, target
+        assert O.ranks_of(X)[3] == target
+
+
+def test_two_sided_error_lower_bound():
+    # Eckart-Young at every bond: ||Y - X|| >= sqrt(sum_{k > l_n} s_k^2) of the
+    # n-th unfolding, since X has rank l_n there
+    Y = tiny_tt(8, N=5, I=3, R=5, scale="nominal")
+    X = O.round_two_sided(Y, 2, seed_left=1, seed_right=2)
+    T = O.full(Y)
+    err = O.rel_diff(X, Y) * O.tt_norm(Y)
+    for n in range(1, 5):
+        s = np.linalg.svd(T.reshape(3 ** n, -1), compute_uv=False)
+        assert err >= math.sqrt(float(np.sum(s[2:] ** 2))) * (1 - 1e-12)
