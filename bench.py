@@ -187,6 +187,9 @@ def main():
                     help="with --prec f32/bf16: skip timing the FP64 path for the speedup")
     ap.add_argument("--site", type=int, default=None,
                     help="call site whose kernel the roofline covers (default: 0, V(Y_n) W_n)")
+    ap.add_argument("--two-sided", action="store_true",
+                    help="single-TT FP64 workloads: also time Two-Sided-Randomization "
+                         "(Algorithm 6) to the same output ranks and compare the accuracy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -377,6 +380,24 @@ def main():
         log(f"FP64 GPU path: {ms64:.3f} ms/step; {args.prec} speedup {ms64 / ms_per_step:.2f}x; "
             f"||X - Y||/||Y||: {args.prec} {e_mode:.6e}, f64 {e_64:.6e}; kept part of ||Y||^2: "
             f"{args.prec} {k_mode:.6e}, f64 {k_64:.6e}")
+    if args.two_sided and wl["kind"] == "single" and args.prec == "f64":
+        cores = [torch.from_numpy(c).to(dev) for c in wl["inputs"]]
+        tsp = tt.TwoSidedPlan(dims, ranks, wl["target"], dev)
+        ms2, _ = timed(lambda: tsp.run(cores, wl["seed"], wl["seed"] + 1), args.steps,
+                       args.warmup)
+        out2 = [c.detach().cpu().numpy() for c in tsp.run(cores, wl["seed"], wl["seed"] + 1)]
+        terms = [(1.0, wl["inputs"])]
+        e2, k2 = rounding_error(tt, out2, terms, dev)
+        e1, k1 = rounding_error(tt, out, terms, dev)
+        res["two_sided"] = {"ms_per_step": round(ms2, 4), "left_ranks": max(tsp.left_ranks),
+                            "right_ranks": max(tsp.right_ranks),
+                            "rounding_rel_err": float(f"{e2:.6e}"),
+                            "kept_norm2": float(f"{k2:.6e}"),
+                            "rto_rounding_rel_err": float(f"{e1:.6e}"),
+                            "rto_kept_norm2": float(f"{k1:.6e}")}
+        log(f"two-sided (Algorithm 6): {ms2:.3f} ms/rounding to ranks {max(tsp.left_ranks)} "
+            f"(right sketch {max(tsp.right_ranks)}); ||X - Y||/||Y|| {e2:.6e} "
+            f"(RtO {e1:.6e}); kept part of ||Y||^2 {k2:.6e} (RtO {k1:.6e})")
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(wl, out, budget_s=args.cpu_budget)
         res["cpu_baseline"] = cb

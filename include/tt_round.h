@@ -278,6 +278,44 @@ TT_API int tt_round_svd(int32_t N, const int64_t *dims, const int64_t *ranks,
                         void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Two-Sided-Randomization (Algorithm 6, section 3.3; generalized Nystrom,
+ * section 2.2, equation (LnRn)) of the FP64 TT Y to ranks l_n.  A left
+ * Gaussian TT L (ranks l_n, seed_left) and a right one R (ranks rho_n,
+ * seed_right) are drawn as tt_make_sketch draws them; W^L_n =
+ * V(L_{1:n})^T V(Y_{1:n}) (l_n x R_n) and W^R_n = H(Y_{n+1:N}) H(R_{n+1:N})^T
+ * (R_n x rho_n) are the partial contractions from the left and from the
+ * right; at every bond, with W^L_n W^R_n = U S V^T, L_n = W^R_n V (S^+)^1/2 and
+ * R_n = (S^+)^1/2 U^T W^L_n, where S^+ inverts the singular values above 1e-6
+ * times the largest and zeroes the rest; then every core on its own:
+ * X_1 = V(Y_1) L_1, H(X_n) = R_{n-1} H(V(Y_n) L_n), H(X_N) = R_{N-1} H(Y_N).
+ * The output is not orthogonal.  The left singular vectors come from
+ * cyclic-Jacobi eigenpairs of FP64 Grams in two passes (C C^T with C =
+ * W^L W^R, then B B^T with B = U1^T C), which keeps the small singular
+ * values close to their own relative accuracy.
+ *   ranks: l_n as tt_round_rand_plan with oversample 0 (the output ranks);
+ *          rho_n = ceil(3 l_n / 2) capped by I_{n+1} ... I_N
+ *   tt_round_two_sided_plan  host only: left_ranks[N+1] = l_n,
+ *                            right_ranks[N+1] = rho_n
+ *   dtype        TT_F64 only (TT_EUNSUPPORTED otherwise)
+ *   cores[N]     device input cores, not modified
+ *   out_cores[N] device, core n l_{n-1} x I_n x l_n C-contiguous; must not
+ *                overlap the inputs or the workspace
+ *   workspace    device, 256-byte aligned, >= tt_round_two_sided_workspace
+ * Limits: l_n and rho_n <= TT_MAX_SKETCH_RANK (so target_rank <= 64 when
+ * the mode sizes do not cap rho_n), else TT_EUNSUPPORTED.  Asynchronous on
+ * `stream`.
+ */
+TT_API int tt_round_two_sided_plan(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                   int64_t target_rank, int64_t *left_ranks,
+                                   int64_t *right_ranks);
+TT_API int tt_round_two_sided_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                        int64_t target_rank, size_t *bytes);
+TT_API int tt_round_two_sided(int32_t N, const int64_t *dims, const int64_t *ranks,
+                              const void *const *cores, int32_t dtype, int64_t target_rank,
+                              uint64_t seed_left, uint64_t seed_right, void *const *out_cores,
+                              void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Batched randomized rounding: B independent TTs (any orders >= 2, mode
  * sizes and ranks; sketch ranks <= 76) rounded by Algorithm 5 with the same
  * truncation as tt_round_rand, in lock step: every step of the method is

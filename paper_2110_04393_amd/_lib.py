@@ -56,6 +56,10 @@ _SIGS = {
     "tt_round_svd_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i32, P_size]),
     "tt_round_svd": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_dbl, c_i64, c_i32, P_vp,
                                     P_i64, vp, c_size, vp]),
+    "tt_round_two_sided_plan": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, P_i64, P_i64]),
+    "tt_round_two_sided_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, P_size]),
+    "tt_round_two_sided": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_u64, c_u64,
+                                          P_vp, vp, c_size, vp]),
     "tt_round_rand_backward_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i64, c_i32,
                                                         P_size]),
     "tt_round_rand_backward": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64, c_u64,

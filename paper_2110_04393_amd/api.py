@@ -254,6 +254,67 @@ def round_svd(cores, eps0: float = 0.0, max_rank: int = 0, prec: str = "f64", st
     return [bufs[n][: r[n] * dims[n] * r[n + 1]].view(r[n], dims[n], r[n + 1]) for n in range(N)]
 
 
+def two_sided_plan(dims, ranks, target_rank: int):
+    """Left ranks l_n (the output ranks) and right sketch ranks rho_n of
+    tt_round_two_sided (host only)."""
+    N = len(dims)
+    lr, rr = L.i64_array([0] * (N + 1)), L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_round_two_sided_plan(N, L.i64_array(dims), L.i64_array(ranks),
+                                            int(target_rank), lr, rr))
+    return [lr[n] for n in range(N + 1)], [rr[n] for n in range(N + 1)]
+
+
+class TwoSidedPlan:
+    """Pre-sized outputs and workspace for repeated Two-Sided-Randomization
+    roundings (Algorithm 6) of one FP64 shape."""
+
+    def __init__(self, dims, ranks, target_rank, device="cuda"):
+        import ctypes
+        self.dims = [int(d) for d in dims]
+        self.ranks = [int(r) for r in ranks]
+        self.N = len(self.dims)
+        self.target = int(target_rank)
+        self.device = torch.device(device)
+        self.left_ranks, self.right_ranks = two_sided_plan(self.dims, self.ranks, self.target)
+        b = ctypes.c_size_t(0)
+        L.check(L.lib().tt_round_two_sided_workspace(self.N, L.i64_array(self.dims),
+                                                     L.i64_array(self.ranks), self.target,
+                                                     ctypes.byref(b)))
+        self.ws_bytes = int(b.value)
+        self.workspace = _workspace(self.ws_bytes, self.device)
+        lr = self.left_ranks
+        self.out = [torch.empty((lr[n], self.dims[n], lr[n + 1]), dtype=torch.float64,
+                                device=self.device) for n in range(self.N)]
+        self._out_ptrs = L.ptr_array([c.data_ptr() for c in self.out])
+        self._dims = L.i64_array(self.dims)
+        self._ranks = L.i64_array(self.ranks)
+
+    def run(self, cores, seed_left=0, seed_right=1, stream=None):
+        import ctypes
+        _check_cores(cores)
+        dims, ranks = _shape_of(cores)
+        if dims != self.dims or ranks != self.ranks:
+            raise ValueError("cores do not match the plan's shape")
+        if cores[0].dtype != torch.float64:
+            raise ValueError("two-sided rounding takes float64 cores")
+        L.check(L.lib().tt_round_two_sided(
+            self.N, self._dims, self._ranks, L.ptr_array([c.data_ptr() for c in cores]),
+            _DTYPE[cores[0].dtype], self.target, int(seed_left) & ((1 << 64) - 1),
+            int(seed_right) & ((1 << 64) - 1), self._out_ptrs,
+            ctypes.c_void_p(self.workspace.data_ptr()), self.ws_bytes, _stream_handle(stream)))
+        return self.out
+
+
+def round_two_sided(cores, target_rank: int, seed_left: int = 0, seed_right: int = 1,
+                    stream=None):
+    """Two-Sided-Randomization rounding (Algorithm 6) of an FP64 TT; returns
+    new output cores (clones) at ranks l_n."""
+    _check_cores(cores)
+    dims, ranks = _shape_of(cores)
+    p = TwoSidedPlan(dims, ranks, target_rank, cores[0].device)
+    return [c.clone() for c in p.run(cores, seed_left, seed_right, stream=stream)]
+
+
 def round_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0, prec: str = "f64",
                sketch: Optional[list] = None, stream=None):
     """Randomize-then-Orthogonalize rounding (Algorithm 5) of a TT; returns

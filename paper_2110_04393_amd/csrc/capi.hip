@@ -1322,6 +1322,168 @@ int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks
                             ws_bytes, st);
 }
 
+// ---------------------------------------------------------------- Algorithm 6
+// Two-Sided-Randomization (generalized Nystrom) in FP64.  Ranks: l_n from
+// plan_ranks with no oversampling (the output ranks), right sketch ranks
+// rho_n = ceil(3 l_n / 2) capped by I_{n+1} ... I_N.
+void plan_two_sided(int N, const int64_t *dims, const int64_t *R, int64_t target,
+                    std::vector<int64_t> &ell, std::vector<int64_t> &rho) {
+  std::vector<int64_t> out;
+  plan_ranks(N, dims, R, target, 0, ell, out);
+  const int64_t big = int64_t(1) << 40;
+  std::vector<int64_t> w(N + 1, 1);
+  for (int n = N - 1; n >= 1; --n) w[n] = std::min(big, dims[n] * w[n + 1]);
+  rho.assign(N + 1, 1);
+  for (int n = 1; n <= N - 1; ++n) rho[n] = std::min((3 * ell[n] + 1) / 2, w[n]);
+}
+
+constexpr double kNystromRcond = 1e-6;
+
+// Y (ranks R) -> X (ranks L) with left sketch SkL (ranks L) and right sketch
+// SkR (ranks P); every step is a GEMM except the eigensolve and the scaling.
+int two_sided_exec(Ctx &c, const Prec &p, int N, const int64_t *dims, const int64_t *R,
+                   const double *const *Y, const int64_t *L, const int64_t *P,
+                   const double *const *SkL, const double *const *SkR, double *const *out) {
+  typedef double T;
+  std::vector<T *> WR(N, nullptr), WL(N, nullptr), Lf(N, nullptr), Rf(N, nullptr);
+  int64_t lmax = 1, pmax = 1, zmax = 1, tmax = 1;
+  for (int n = 1; n <= N - 1; ++n) {
+    WR[n] = c.arena.take<T>((size_t)(R[n] * P[n]));
+    WL[n] = c.arena.take<T>((size_t)(L[n] * R[n]));
+    Lf[n] = c.arena.take<T>((size_t)(R[n] * L[n]));
+    Rf[n] = c.arena.take<T>((size_t)(L[n] * R[n]));
+    lmax = std::max(lmax, L[n]);
+    pmax = std::max(pmax, P[n]);
+    if (n >= 2) {
+      zmax = std::max(zmax, L[n - 1] * dims[n - 1] * R[n]);
+      tmax = std::max(tmax, R[n - 1] * dims[n - 1] * L[n]);
+    }
+  }
+  T *zb = c.arena.take<T>((size_t)zmax);
+  T *tb = c.arena.take<T>((size_t)tmax);
+  // per-bond slots (bond n in slot n - 1) of the factor computation, so
+  // that the eigensolves of all bonds run in one launch each
+  const int nbond = N - 1;
+  const int64_t sC = lmax * pmax, sG = lmax * lmax;
+  T *Cb = c.arena.take<T>((size_t)(sC * nbond));
+  T *Bb = c.arena.take<T>((size_t)(sC * nbond));
+  T *Gb = c.arena.take<T>((size_t)(sG * nbond));
+  T *lam = c.arena.take<T>((size_t)(lmax * nbond));
+  T *U1 = c.arena.take<T>((size_t)(sG * nbond));
+  T *U2 = c.arena.take<T>((size_t)(sG * nbond));
+  T *Ub = c.arena.take<T>((size_t)(sG * nbond));
+  T *A1 = c.arena.take<T>((size_t)(sG * nbond));
+  T *A2 = c.arena.take<T>((size_t)(sG * nbond));
+  T *Eb = c.arena.take<T>((size_t)(pmax * lmax));
+  std::vector<int> nl(nbond);
+  for (int n = 1; n <= N - 1; ++n) nl[n - 1] = (int)L[n];
+  auto mm = [&](const T *A, int64_t lda, bool a_kc, const T *B, int64_t ldb, bool b_kc, T *C,
+                int64_t ldc, int64_t M, int64_t Nn, int64_t K) {
+    Gemm<T> g;
+    g.A = A;
+    g.lda = lda;
+    g.a_kc = a_kc;
+    g.B = B;
+    g.ldb = ldb;
+    g.b_kc = b_kc;
+    g.C = C;
+    g.ldc = ldc;
+    g.M = M;
+    g.N = Nn;
+    g.K = K;
+    return gemm(c, g);
+  };
+
+  // ---- W^R_n = H(Y_{n+1:N}) H(SkR_{n+1:N})^T (Algorithm 3), R_n x rho_n
+  {
+    const int64_t *Rj[1] = {R};
+    TTR_TRY(wchain<T>(c, p, false, N, dims, 1, Rj, Y, P, (const void *const *)SkR, WR.data()));
+  }
+  // ---- W^L_n = V(SkL_{1:n})^T V(Y_{1:n}), l_n x R_n (the mirror of Algorithm 3)
+  TTR_TRY(mm(SkL[0], L[1], false, Y[0], R[1], false, WL[1], R[1], L[1], R[1], dims[0]));
+  for (int n = 2; n <= N - 1; ++n) {
+    const int64_t I = dims[n - 1];
+    // Z = W^L_{n-1} H(Y_n), read as V(Z): (l_{n-1} I_n) x R_n
+    TTR_TRY(mm(WL[n - 1], R[n - 1], true, Y[n - 1], I * R[n], false, zb, I * R[n], L[n - 1],
+               I * R[n], R[n - 1]));
+    // W^L_n = V(SkL_n)^T V(Z)
+    TTR_TRY(mm(SkL[n - 1], L[n], false, zb, R[n], false, WL[n], R[n], L[n], R[n],
+               L[n - 1] * I));
+  }
+  // ---- factors of equation (LnRn) at every bond.  Left singular vectors of
+  // C = W^L W^R in two passes: the eigenvectors U1 of C C^T, then those (U2)
+  // of B B^T with B = U1^T C, whose rows are already nearly orthogonal, so
+  // that Jacobi (with its relative test only) resolves the small singular
+  // values to their own relative accuracy instead of that of s_1^2;
+  // U = U1 U2, s^2 = eig(B B^T).
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t l = L[n], rho = P[n], r = R[n], o = n - 1;
+    TTR_TRY(mm(WL[n], r, true, WR[n], rho, false, Cb + o * sC, rho, l, rho, r));  // C
+    TTR_TRY(mm(Cb + o * sC, rho, true, Cb + o * sC, rho, true, Gb + o * sG, l, l, l, rho));
+  }
+  if (!c.dry) TTR_TRY(sym_eig_batch(Gb, sG, lam, lmax, U1, sG, nl.data(), nbond, false, c.s));
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t l = L[n], rho = P[n], o = n - 1;
+    TTR_TRY(mm(U1 + o * sG, l, false, Cb + o * sC, rho, false, Bb + o * sC, rho, l, rho,
+               l));  // B = U1^T C
+    TTR_TRY(mm(Bb + o * sC, rho, true, Bb + o * sC, rho, true, Gb + o * sG, l, l, l, rho));
+  }
+  if (!c.dry) TTR_TRY(sym_eig_batch(Gb, sG, lam, lmax, U2, sG, nl.data(), nbond, true, c.s));
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t l = L[n], rho = P[n], r = R[n], o = n - 1;
+    T *a1 = A1 + o * sG, *a2 = A2 + o * sG;
+    TTR_TRY(mm(U1 + o * sG, l, true, U2 + o * sG, l, false, Ub + o * sG, l, l, l, l));
+    if (!c.dry) TTR_TRY(nystrom_scale(lam + o * lmax, Ub + o * sG, l, kNystromRcond, a1, a2, c.s));
+    TTR_TRY(mm(Cb + o * sC, rho, false, a1, l, false, Eb, l, rho, l, l));  // E = C^T U diag(h/s)
+    TTR_TRY(mm(WR[n], rho, true, Eb, l, false, Lf[n], l, r, l, rho));     // L_n = W^R E
+    TTR_TRY(mm(a2, l, true, WL[n], r, false, Rf[n], r, l, r, l));         // R_n = diag(h) U^T W^L
+  }
+  // ---- cores, each independent of the others
+  TTR_TRY(mm(Y[0], R[1], true, Lf[1], L[1], false, out[0], L[1], dims[0], L[1], R[1]));
+  for (int n = 2; n <= N - 1; ++n) {
+    const int64_t I = dims[n - 1];
+    // V(T) = V(Y_n) L_n, then H(X_n) = R_{n-1} H(T)
+    TTR_TRY(mm(Y[n - 1], R[n], true, Lf[n], L[n], false, tb, L[n], R[n - 1] * I, L[n], R[n]));
+    TTR_TRY(mm(Rf[n - 1], R[n - 1], true, tb, I * L[n], false, out[n - 1], I * L[n], L[n - 1],
+               I * L[n], R[n - 1]));
+  }
+  TTR_TRY(mm(Rf[N - 1], R[N - 1], true, Y[N - 1], dims[N - 1], false, out[N - 1], dims[N - 1],
+             L[N - 1], dims[N - 1], R[N - 1]));
+  return TT_OK;
+}
+
+int two_sided_check(int32_t N, const int64_t *dims, const int64_t *ranks, int64_t target,
+                    std::vector<int64_t> &ell, std::vector<int64_t> &rho) {
+  TTR_TRY(check_shape(N, dims, ranks, "tt_round_two_sided"));
+  if (target < 1) return fail(TT_EINVAL, "target_rank must be >= 1");
+  plan_two_sided(N, dims, ranks, target, ell, rho);
+  for (int n = 0; n <= N; ++n)
+    if (N > 1 && (ell[n] > TT_MAX_SKETCH_RANK || rho[n] > TT_MAX_SKETCH_RANK))
+      return fail(TT_EUNSUPPORTED, "sketch rank above TT_MAX_SKETCH_RANK");
+  return TT_OK;
+}
+
+// Sketch cores in the workspace, then two_sided_exec.
+int two_sided_body(Ctx &c, int N, const int64_t *dims, const int64_t *ranks,
+                   const std::vector<int64_t> &ell, const std::vector<int64_t> &rho,
+                   const double *const *Y, uint64_t seed_l, uint64_t seed_r,
+                   double *const *out) {
+  Prec p;
+  TTR_TRY(prec_cfg(TT_PREC_F64, p));
+  std::vector<double *> SkL(N), SkR(N);
+  for (int n = 0; n < N; ++n) {
+    SkL[n] = c.arena.take<double>((size_t)(ell[n] * dims[n] * ell[n + 1]));
+    SkR[n] = c.arena.take<double>((size_t)(rho[n] * dims[n] * rho[n + 1]));
+  }
+  if (!c.dry) {
+    TTR_TRY(sketch_generate(seed_l, N, dims, ell.data(), TT_F64, (void *const *)SkL.data(), c.s));
+    TTR_TRY(sketch_generate(seed_r, N, dims, rho.data(), TT_F64, (void *const *)SkR.data(), c.s));
+  }
+  return two_sided_exec(c, p, N, dims, ranks, Y, ell.data(), rho.data(),
+                        (const double *const *)SkL.data(), (const double *const *)SkR.data(),
+                        out);
+}
+
 }  // namespace
 }  // namespace ttr
 
@@ -1588,6 +1750,59 @@ int tt_partial_contractions_rl(int32_t N, const int64_t *dims, const int64_t *ra
                             ranks_y, y_cores, (double *const *)W.data());
     return wchain<float>(c, pc, false, N, dims, 1, &ranks_x, (const float *const *)x_cores,
                          ranks_y, y_cores, (float *const *)W.data());
+  });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int tt_round_two_sided_plan(int32_t N, const int64_t *dims, const int64_t *ranks,
+                            int64_t target_rank, int64_t *left_ranks, int64_t *right_ranks) {
+  std::vector<int64_t> ell, rho;
+  TTR_TRY(two_sided_check(N, dims, ranks, target_rank, ell, rho));
+  if (!left_ranks || !right_ranks) return fail(TT_EINVAL, "null output arrays");
+  for (int n = 0; n <= N; ++n) {
+    left_ranks[n] = ell[n];
+    right_ranks[n] = rho[n];
+  }
+  return TT_OK;
+}
+
+int tt_round_two_sided_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                 int64_t target_rank, size_t *bytes) {
+  std::vector<int64_t> ell, rho;
+  TTR_TRY(two_sided_check(N, dims, ranks, target_rank, ell, rho));
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  if (N == 1) {
+    *bytes = 0;
+    return TT_OK;
+  }
+  std::vector<const double *> Y(N, nullptr);
+  std::vector<double *> out(N, nullptr);
+  return measure_workspace(
+      [&](Ctx &c) -> int {
+        return two_sided_body(c, N, dims, ranks, ell, rho, Y.data(), 0, 0, out.data());
+      },
+      bytes);
+}
+
+int tt_round_two_sided(int32_t N, const int64_t *dims, const int64_t *ranks,
+                       const void *const *cores, int32_t dtype, int64_t target_rank,
+                       uint64_t seed_left, uint64_t seed_right, void *const *out_cores,
+                       void *workspace, size_t ws_bytes, void *stream) {
+  std::vector<int64_t> ell, rho;
+  TTR_TRY(two_sided_check(N, dims, ranks, target_rank, ell, rho));
+  if (dtype != TT_F64) return fail(TT_EUNSUPPORTED, "two-sided rounding takes FP64 cores");
+  TTR_TRY(check_ptrs(N, cores, "input cores"));
+  TTR_TRY(check_ptrs(N, out_cores, "output cores"));
+  hipStream_t st = (hipStream_t)stream;
+  if (N == 1)
+    return copy2d<double>((double *)out_cores[0], dims[0], (const double *)cores[0], dims[0], 1,
+                          dims[0], 1.0, 0.0, st);
+  return run_with_workspace(workspace, ws_bytes, st, [&](Ctx &c) -> int {
+    return two_sided_body(c, N, dims, ranks, ell, rho, (const double *const *)cores, seed_left,
+                          seed_right, (double *const *)out_cores);
   });
 }
 

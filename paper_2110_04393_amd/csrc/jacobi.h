@@ -33,7 +33,8 @@ __device__ inline void round_pair(int t, int k, int np, int &p, int &q) {
 
 __device__ __forceinline__ void jacobi_eig_kernel_body(const double *Gin, double *lam,
                                                                  double *Uout, int n,
-                                                                 int *info, const int *gate) {
+                                                                 int *info, const int *gate,
+                                                                 bool relative = false) {
   if (gate && *gate == 0) return;
   extern __shared__ double lds[];
   const int np = (n + 1) & ~1;
@@ -75,8 +76,11 @@ __device__ __forceinline__ void jacobi_eig_kernel_body(const double *Gin, double
   // |apq| > floor_abs: couplings at the rounding level of the largest diagonal
   // entry (about n u max|G_ii|, the error of the Gram itself) are left alone,
   // otherwise the relative test cannot be met for small diagonal entries.
+  // With `relative` the floor is off: for a matrix whose entries carry their
+  // own relative accuracy (the Gram of nearly orthogonal rows), every
+  // coupling is rotated until the relative test holds.
   const double tol2 = 1e-30;
-  const double floor_abs = 1.2e-16 * (double)n * s_scale;
+  const double floor_abs = relative ? 0.0 : 1.2e-16 * (double)n * s_scale;
   int sweeps = 0;
   double offmax = 0.0;  // per pair-lane: largest relative coupling seen this sweep
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {

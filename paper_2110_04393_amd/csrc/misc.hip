@@ -78,6 +78,25 @@ __global__ __launch_bounds__(256) void copyltu_kernel(T *C, const T *M, int64_t 
   }
 }
 
+// Generalized Nystrom scalings from the eigenpairs (lam descending, U's
+// columns the eigenvectors, row-major n x n) of G = C C^T: with s = sqrt(lam)
+// the singular values of C, h_j = s_j^-1/2 for s_j > rcond s_1 (lam_j >
+// rcond^2 lam_1) and 0 otherwise; A1 = U diag(h_j / s_j), A2 = diag(h) U^T.
+__global__ __launch_bounds__(256) void nystrom_scale_kernel(const double *lam, const double *U,
+                                                            int n, double rcond2, double *A1,
+                                                            double *A2) {
+  const double top = lam[0];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - i * n;
+    const double lj = lam[j], li = lam[i];
+    const bool kj = top > 0.0 && lj > rcond2 * top, ki = top > 0.0 && li > rcond2 * top;
+    const double hj = kj ? 1.0 / sqrt(sqrt(lj)) : 0.0;  // s_j^-1/2
+    const double hi = ki ? 1.0 / sqrt(sqrt(li)) : 0.0;
+    A1[e] = kj ? U[e] * (hj / sqrt(lj)) : 0.0;  // (i, j): U_ij h_j / s_j
+    A2[e] = hi * U[j * n + i];                   // (i, j): h_i U_ji
+  }
+}
+
 __global__ __launch_bounds__(256) void to_bf16_kernel(__bf16 *dst, const float *src,
                                                       int64_t count) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -231,6 +250,15 @@ int copyltu(T *C, const T *M, int64_t k, double alpha, hipStream_t s) {
 }
 template int copyltu<float>(float *, const float *, int64_t, double, hipStream_t);
 template int copyltu<double>(double *, const double *, int64_t, double, hipStream_t);
+
+int nystrom_scale(const double *lam, const double *U, int64_t n, double rcond, double *A1,
+                  double *A2, hipStream_t s) {
+  if (n <= 0) return TT_OK;
+  hipLaunchKernelGGL(nystrom_scale_kernel, dim3(1), dim3(256), 0, s, lam, U, (int)n,
+                     rcond * rcond, A1, A2);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
 
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s) {
   if (count <= 0) return TT_OK;

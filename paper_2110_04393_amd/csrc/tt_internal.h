@@ -331,9 +331,18 @@ int householder_group_run(const HhGroupDesc *d_tab, int count, size_t lds_bytes,
 // Symmetric eigendecomposition of an n x n matrix (n <= TT_MAX_SKETCH_RANK)
 // by cyclic Jacobi: eigenvalues descending to `lam`, eigenvectors as the
 // columns of U (row-major n x n); *info (optional) receives the sweep count.
-// With a gate pointer the kernel returns at once unless *gate != 0.
+// With a gate pointer the kernel returns at once unless *gate != 0.  With
+// `relative` every off-diagonal entry is rotated until it is small relative
+// to its two diagonal entries (no absolute floor at the rounding level of
+// the largest one): for Grams of nearly orthogonal rows.
 int sym_eig(const double *G, double *lam, double *U, int64_t n, hipStream_t s,
-            int *info = nullptr, const int *gate = nullptr);
+            int *info = nullptr, const int *gate = nullptr, bool relative = false);
+
+// `count` independent sym_eig problems in one launch (one workgroup each):
+// problem b reads G + b sG and writes lam + b sl and U + b sU, order n[b]
+// (host array).
+int sym_eig_batch(const double *G, int64_t sG, double *lam, int64_t sl, double *U, int64_t sU,
+                  const int *n, int count, bool relative, hipStream_t s);
 
 // Truncation factors from (lam, U): P = U_k sqrt(lam_k) (n x k, row-major),
 // S = sqrt(lam_k)^-1 U_k^T (k x n, row-major), tail = sum_{j>=k} max(lam_j,0).
@@ -390,6 +399,13 @@ int scale_dev(T *x, int64_t count, const double *f, hipStream_t s);
 // C = alpha (tril(M) + tril(M, -1)^T), k x k row-major
 template <typename T>
 int copyltu(T *C, const T *M, int64_t k, double alpha, hipStream_t s);
+
+// Generalized Nystrom scalings (Algorithm 6, equation (LnRn)) from the
+// eigenpairs of G = C C^T (lam descending, U's columns the eigenvectors,
+// n x n row-major): with s_j = sqrt(lam_j) and h_j = s_j^-1/2 where
+// s_j > rcond s_1 (else 0), A1 = U diag(h_j / s_j) and A2 = diag(h) U^T.
+int nystrom_scale(const double *lam, const double *U, int64_t n, double rcond, double *A1,
+                  double *A2, hipStream_t s);
 
 // dst = RNE_bf16(src)
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);

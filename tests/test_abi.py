@@ -128,3 +128,29 @@ def test_round_svd_rejects_bad_arguments():
                                     L.i64_array([1, 150, 150, 1]), 0, L.TT_PREC_F64,
                                     ctypes.byref(b))
     assert st == L.TT_EUNSUPPORTED
+
+
+def test_two_sided_plan_matches_oracle():
+    rng = random.Random(7)
+    for _ in range(200):
+        N = rng.randint(2, 7)
+        dims = [rng.randint(1, 12) for _ in range(N)]
+        ranks = [1] + [rng.randint(1, 30) for _ in range(N - 1)] + [1]
+        t = rng.randint(1, 40)
+        assert tt.two_sided_plan(dims, ranks, t) == tuple(O.plan_two_sided_ranks(dims, ranks, t))
+
+
+def test_two_sided_workspace_and_limits():
+    b = ctypes.c_size_t(0)
+    dims, ranks = [100] * 4, [1, 200, 200, 200, 1]
+    L.check(L.lib().tt_round_two_sided_workspace(4, L.i64_array(dims), L.i64_array(ranks), 60,
+                                                 ctypes.byref(b)))
+    assert b.value > 0
+    # target 70 gives rho = 105 > 96
+    rc = L.lib().tt_round_two_sided_workspace(4, L.i64_array(dims), L.i64_array(ranks), 70,
+                                              ctypes.byref(b))
+    assert rc == -5
+    rc = L.lib().tt_round_two_sided(4, L.i64_array(dims), L.i64_array(ranks),
+                                    L.ptr_array([1, 2, 3, 4]), 1, 60, 0, 1,
+                                    L.ptr_array([5, 6, 7, 8]), None, 0, None)
+    assert rc == -5  # FP32 cores are refused before any launch
