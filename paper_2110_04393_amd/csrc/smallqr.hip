@@ -9,13 +9,19 @@
 // diagonals, so the final R = R2 R1 has diag(R) > 0, the normalisation the
 // rest of the method uses.
 //
+// Ill-conditioned panels: when a first-pass pivot falls below 1e-14 of its
+// original diagonal entry, chol_shift_kernel (always enqueued, a no-op
+// otherwise) factors G + s I instead, s = 11 (m n + n (n + 1)) u trace(G)
+// (shifted CholeskyQR, Fukaya et al. 2020), and sets flag bit 1; the second
+// pass runs as usual and a third CholeskyQR pass (cholqr_fix_kernel, a no-op
+// unless bit 1 is set) restores orthogonality to rounding.
+//
 // Robust path: Householder QR in one workgroup, used for panels of at most 8
-// columns and, without a host round trip, whenever a Cholesky pivot falls below
-// 1e-14 of its original diagonal entry (the sketch is numerically rank
-// deficient, e.g. rounding A+A with a sketch wider than the rank).  The
-// Cholesky kernels raise a device flag; the Householder kernel is always
-// enqueued and returns at once unless the flag is set.  Householder columns are
-// sign-normalised afterwards so that diag(R) >= 0 (zero counts as +).
+// columns and, without a host round trip, whenever a pivot still breaks down
+// (flag bit 0: the sketch is rank deficient, e.g. rounding A+A with a sketch
+// wider than the rank).  The Householder kernel is always enqueued and returns
+// at once unless that bit is set.  Householder columns are sign-normalised
+// afterwards so that diag(R) >= 0 (zero counts as +).
 #include "fastmath.h"
 #include <algorithm>
 
@@ -61,7 +67,8 @@ constexpr double kNearIdentity = 0x1p-30, kNearIdentityF32 = 0x1p-17;
 template <int NMAX>
 __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Rinv,
                                                      float *Rinv_f, int n, int *flag,
-                                                     int or_flag) {
+                                                     int or_flag, double sh = 0.0,
+                                                     int mark = 0) {
   constexpr int NB = NMAX / 2;      // augmented column slots per lane (2 NMAX columns)
   constexpr int NBL = NMAX / 4;     // slots of the left block
   constexpr int NA = NMAX / 16;     // row blocks
@@ -100,6 +107,7 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
       return;
     }
   }
+  // sh: shift added to the diagonal (shifted CholeskyQR), 0 otherwise
   double X[NS][NB];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
@@ -110,13 +118,14 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
       double v = 0.0;
       if (b < NBL) {
         if (i < n && c < n) v = (i >= c) ? G[i * n + c] : G[c * n + i];
+        if (i < n && c == i) v += sh;
       } else {
         v = (c - NMAX == i) ? 1.0 : 0.0;
       }
       X[sl][b] = v;
     }
   }
-  for (int i = tid; i < n; i += kCholThreads) s_d0[i] = G[i * n + i];
+  for (int i = tid; i < n; i += kCholThreads) s_d0[i] = G[i * n + i] + sh;
   if (tid == 0) s_bad = 0;
   __syncthreads();
   int bad = 0;
@@ -174,9 +183,10 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
   __syncthreads();
   if (tid == 0) {
     if (or_flag) {
-      if (s_bad) *flag = 1;
+      // after a shifted first pass (bit 1) the third pass judges the result
+      if (s_bad && !(*flag & 2)) *flag = *flag | 1;
     } else {
-      *flag = s_bad;
+      *flag = s_bad | mark;
     }
   }
 }
@@ -186,6 +196,136 @@ __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1,
                                                                 float *Rinv_f, int n, int *flag,
                                                                 int or_flag) {
   chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, or_flag);
+}
+
+// The first CholeskyQR pass again, on G + s I with s = shift_c trace(G) (the
+// trace bounds ||Y||_2^2), run only when that pass broke down (flag bit 0);
+// the flag then reads 2 (bit 1: a third pass is due), or 3 if even the
+// shifted matrix breaks down.
+template <int NMAX>
+__global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_shift_kernel(const double *G, double *Rinv,
+                                                                float *Rinv_f, int n, int *flag,
+                                                                double shift_c) {
+  if ((*flag & 1) == 0) return;
+  __shared__ double s_trace;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += G[i * n + i];
+    s_trace = t;
+  }
+  __syncthreads();
+  chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, 0, shift_c * s_trace, 2);
+}
+
+// Third CholeskyQR pass on Q (m x n row-major, n <= 96), in place, run only
+// when the first pass needed its shift (flag == 2): G = Q^T Q in FP64 from
+// chunks of 32 rows staged in LDS, G = R^T R and R^{-1} in LDS, then
+// Q <- Q R^{-1} chunk by chunk.  A pivot that is not above 1e-4 of its
+// diagonal entry (cond(Q)^2 too large for one pass to restore orthogonality
+// to rounding) sets flag bit 0, and the Householder kernel that follows
+// recomputes Q from Y.
+constexpr int kFixThreads = 1024, kFixRows = 32;
+constexpr int kFixPer = (96 * 97 / 2 + kFixThreads - 1) / kFixThreads;
+
+template <typename T>
+__global__ __launch_bounds__(kFixThreads) void cholqr_fix_kernel(T *Q, int64_t m, int n,
+                                                                 int *flag) {
+  if ((*flag & 3) != 2) return;
+  extern __shared__ double fx_lds[];
+  const int area = max(n * n, kFixRows * n);
+  double *A = fx_lds;         // chunk, then G and R (upper), then chunk again
+  double *B = fx_lds + area;  // chunk during the Gram, then R^{-1}
+  __shared__ double s_r, s_d0[96];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  const int npair = n * (n + 1) / 2;
+  double acc[kFixPer];
+  int pi[kFixPer], pj[kFixPer];
+#pragma unroll
+  for (int t = 0; t < kFixPer; ++t) {
+    const int e = tid + t * kFixThreads;
+    int i = 0, rem = e;
+    while (e < npair && rem >= n - i) {
+      rem -= n - i;
+      ++i;
+    }
+    pi[t] = i;
+    pj[t] = i + rem;
+    acc[t] = 0.0;
+  }
+  for (int64_t r0 = 0; r0 < m; r0 += kFixRows) {
+    const int nr = (int)min<int64_t>(kFixRows, m - r0);
+    __syncthreads();
+    for (int e = tid; e < kFixRows * n; e += kFixThreads) {
+      const int r = e / n, c = e - r * n;
+      B[e] = r < nr ? (double)Q[(r0 + r) * n + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kFixPer; ++t) {
+      if (tid + t * kFixThreads < npair) {
+        double a = acc[t];
+#pragma unroll 4
+        for (int r = 0; r < kFixRows; ++r) a = fma(B[r * n + pi[t]], B[r * n + pj[t]], a);
+        acc[t] = a;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kFixPer; ++t)
+    if (tid + t * kFixThreads < npair) A[pi[t] * n + pj[t]] = acc[t];
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int j = tid; j < n; j += kFixThreads) s_d0[j] = A[j * n + j];
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle: A = R^T R
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double d = A[j * n + j];
+      if (!(d > 1e-4 * s_d0[j]) || !isfinite(d)) {
+        s_bad = 1;
+        d = 1.0;
+      }
+      s_r = sqrt(d);
+      A[j * n + j] = s_r;
+    }
+    __syncthreads();
+    const double rj = s_r;
+    for (int c = j + 1 + tid; c < n; c += kFixThreads) A[j * n + c] /= rj;
+    __syncthreads();
+    const int w = n - j - 1;
+    for (int e = tid; e < w * w; e += kFixThreads) {
+      const int i = j + 1 + e / w, c = j + 1 + e % w;
+      if (c >= i) A[i * n + c] -= A[j * n + i] * A[j * n + c];
+    }
+    __syncthreads();
+  }
+  // R^{-1} (upper) by back substitution, one column per thread
+  for (int c = tid; c < n; c += kFixThreads) {
+    for (int j = n - 1; j > c; --j) B[j * n + c] = 0.0;
+    B[c * n + c] = 1.0 / A[c * n + c];
+    for (int j = c - 1; j >= 0; --j) {
+      double sum = 0.0;
+      for (int k = j + 1; k <= c; ++k) sum = fma(A[j * n + k], B[k * n + c], sum);
+      B[j * n + c] = -sum / A[j * n + j];
+    }
+  }
+  // Q <- Q R^{-1}
+  for (int64_t r0 = 0; r0 < m; r0 += kFixRows) {
+    const int nr = (int)min<int64_t>(kFixRows, m - r0);
+    __syncthreads();
+    for (int e = tid; e < nr * n; e += kFixThreads) A[e] = (double)Q[r0 * n + e];
+    __syncthreads();
+    for (int e = tid; e < nr * n; e += kFixThreads) {
+      const int r = e / n, c = e - r * n;
+      double sum = 0.0;
+      for (int k = 0; k <= c; ++k) sum = fma(A[r * n + k], B[k * n + c], sum);
+      Q[r0 * n + e] = (T)sum;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && s_bad) *flag = *flag | 1;
 }
 
 // One workgroup Householder QR of the m x n row-major Y into Q (m x n), with
@@ -201,7 +341,7 @@ __device__ __forceinline__ void householder_kernel_body(const T *Y, T *Q, T *wor
                                                                  int64_t m, int n,
                                                                  const int *flag, int always,
                                                                  int use_lds) {
-  if (!always && *flag == 0) return;
+  if (!always && (*flag & 1) == 0) return;
   extern __shared__ double hh_lds[];
   T *work = use_lds ? reinterpret_cast<T *>(hh_lds) : work_g;
   T *Qw = use_lds ? reinterpret_cast<T *>(hh_lds) + m * n : Q;
@@ -336,19 +476,23 @@ size_t qr_partial_elems(int64_t m, int64_t n) {
 
 template <int NMAX>
 static int chol_inv_launch(const double *G, double *Rinv, float *Rinv_f, int n, int *flag,
-                           int or_flag, hipStream_t s) {
+                           int or_flag, hipStream_t s, double shift_c) {
   hipLaunchKernelGGL((chol_inv_kernel<NMAX>), dim3(1), dim3(kCholThreads), 0, s, G, Rinv, Rinv_f,
                      n, flag, or_flag);
+  TTR_HIP(hipGetLastError());
+  if (shift_c > 0.0)
+    hipLaunchKernelGGL((chol_shift_kernel<NMAX>), dim3(1), dim3(kCholThreads), 0, s, G, Rinv,
+                       Rinv_f, n, flag, shift_c);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 
 // Cholesky + inverse of the n x n Gram (n <= TT_MAX_SKETCH_RANK)
 static int chol_inv(const double *G, double *Rinv, float *Rinv_f, int n, int *flag, int or_flag,
-                    hipStream_t s) {
-  if (n <= 32) return chol_inv_launch<32>(G, Rinv, Rinv_f, n, flag, or_flag, s);
-  if (n <= 64) return chol_inv_launch<64>(G, Rinv, Rinv_f, n, flag, or_flag, s);
-  if (n <= 96) return chol_inv_launch<96>(G, Rinv, Rinv_f, n, flag, or_flag, s);
+                    hipStream_t s, double shift_c = 0.0) {
+  if (n <= 32) return chol_inv_launch<32>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c);
+  if (n <= 64) return chol_inv_launch<64>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c);
+  if (n <= 96) return chol_inv_launch<96>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c);
   return fail(TT_EUNSUPPORTED, "Cholesky of a Gram matrix wider than 96");
 }
 
@@ -372,6 +516,22 @@ static int householder(const T *Y, T *Q, T *work, double *rdiag, double *tau, in
   const size_t bytes = lds ? 2 * sizeof(T) * (size_t)(m * n) : 0;
   hipLaunchKernelGGL((householder_kernel<T>), dim3(1), dim3(kHhThreads), bytes, s, Y, Q, work,
                      rdiag, tau, m, (int)n, flag, always, lds ? 1 : 0);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+template <typename T>
+static int cholqr_fix(T *Q, int64_t m, int64_t n, int *flag, hipStream_t s) {
+  if (n > 96) return fail(TT_EUNSUPPORTED, "QR panel wider than 96");
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
+    attr_set = true;
+  }
+  const size_t area = (size_t)std::max<int64_t>(n * n, kFixRows * n);
+  hipLaunchKernelGGL((cholqr_fix_kernel<T>), dim3(1), dim3(kFixThreads),
+                     2 * area * sizeof(double), s, Q, m, (int)n, flag);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
@@ -416,7 +576,12 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     g.partial = ws.partial;
     TTR_TRY(gemmx_run(g, s));
     }
-    TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s));
+    // first pass: shifted retry on breakdown, s = 11 (m n + n (n + 1)) u trace(G)
+    // with u the unit roundoff of the storage (shifted CholeskyQR3)
+    const double shift_c =
+        pass == 0 ? 11.0 * (double)(m * n + n * (n + 1)) * (f32 ? 0x1p-24 : 0x1p-53) : 0.0;
+    TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s,
+                     shift_c));
     Gemm<T> h;  // dst = src Rinv, in the storage precision
     h.A = src;
     h.lda = n;
@@ -431,8 +596,10 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     h.K = n;
     TTR_TRY(gemm_run<T>(h, s));
   }
-  // fallback (no-op unless a pivot broke down); q1 and rinv are free again
-  // once the GEMMs above have run (same stream).
+  // third pass when the first one was shifted (no-op otherwise), then the
+  // Householder fallback (no-op unless a pivot broke down); q1 and rinv are
+  // free again once the GEMMs above have run (same stream).
+  TTR_TRY(cholqr_fix<T>(Q, m, n, ws.flag, s));
   return householder<T>(Y, Q, q1, ws.rinv, ws.rinv + n, m, n, ws.flag, 0, s);
 }
 

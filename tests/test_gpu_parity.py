@@ -139,6 +139,28 @@ def test_rto_cores_match_oracle(gpu_lib, case, qr, monkeypatch):
         assert np.abs(Vn.T @ Vn - np.eye(Vn.shape[1])).max() < 1e-12
 
 
+@pytest.mark.parametrize("qr", ["auto", "householder"])
+@pytest.mark.parametrize("eps", [1e-6, 1e-9])
+def test_rto_near_low_rank_matches_oracle(gpu_lib, eps, qr, monkeypatch):
+    # X1 (rank 8) + eps X2: the sketched panels (l = 16) have 8 strong and 8
+    # weak columns, so the first CholeskyQR pass breaks down and is retried
+    # with its shift, and a third pass follows (forced Householder: the
+    # reference path on the GPU).  The truncation keeps the 8 strong
+    # directions, which the gap of 1/eps separates from the rest; the
+    # represented tensor is compared.
+    if qr == "householder":
+        monkeypatch.setenv("TT_QR", "householder")
+    say(f"RtO near-low-rank eps={eps} qr={qr}")
+    Y = G.near_low_rank_tt(123, [40] * 5, 8, 40, eps)
+    out = host(gpu_lib.round_rand(dev(Y), 8, 8, seed=3))
+    ref = O.round_rand(Y, 8, 8, seed=3)
+    assert O.ranks_of(out) == O.ranks_of(ref)
+    assert O.rel_diff(out, ref) < 1e-10
+    for c in out[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-10
+
+
 @pytest.mark.parametrize("eig", ["auto", "jacobi", "gemm-gram"])
 @pytest.mark.parametrize("case", [
     (6, 9, 12, 5, 3),
