@@ -210,7 +210,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the rounding "
-              "path has no multi-GPU mode in this build", file=sys.stderr)
+              "path has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     import ctypes

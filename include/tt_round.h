@@ -76,7 +76,7 @@ typedef enum {
                              in FP32, Gram/Cholesky and tails in FP64            */
 } tt_prec;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define TT_MAX_ORDER 512          /* N                                          */
 #define TT_MAX_SKETCH_RANK 96     /* l_n after clamping                         */
 

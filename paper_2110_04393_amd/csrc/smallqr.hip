@@ -183,7 +183,7 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
   __syncthreads();
   if (tid == 0) {
     if (or_flag) {
-      // after a shifted first pass (bit 1) the third pass judges the result
+      // after a shifted first pass (bit 1) the third pass decides
       if (s_bad && !(*flag & 2)) *flag = *flag | 1;
     } else {
       *flag = s_bad | mark;
