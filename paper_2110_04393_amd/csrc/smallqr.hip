@@ -13,7 +13,7 @@
 // original diagonal entry, chol_shift_kernel (always enqueued, a no-op
 // otherwise) factors G + s I instead, s = 11 (m n + n (n + 1)) u trace(G)
 // (shifted CholeskyQR, Fukaya et al. 2020), and sets flag bit 1; the second
-// pass runs as usual and a third CholeskyQR pass (cholqr_fix_kernel, a no-op
+// pass runs as usual and a third CholeskyQR pass (the cholqr_fix_* kernels, no-ops
 // unless bit 1 is set) restores orthogonality to rounding.
 //
 // Robust path: Householder QR in one workgroup, used for panels of at most 8
@@ -218,25 +218,35 @@ __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1,
 }
 
 // Third CholeskyQR pass on Q (m x n row-major, n <= 96), in place, run only
-// when the first pass needed its shift (flag == 2): G = Q^T Q in FP64 from
-// chunks of 32 rows staged in LDS, G = R^T R and R^{-1} in LDS, then
-// Q <- Q R^{-1} chunk by chunk.  A pivot that is not above 1e-4 of its
-// diagonal entry (cond(Q)^2 too large for one pass to restore orthogonality
-// to rounding) sets flag bit 0, and the Householder kernel that follows
-// recomputes Q from Y.
-constexpr int kFixThreads = 1024, kFixRows = 32;
+// when the first pass needed its shift (flag == 2), in three kernels that
+// return at once otherwise:
+//   fix_gram:  workgroup w forms the FP64 Gram of its rows (fix_rows(m) of
+//              them, staged 32 at a time in LDS) into part + w n n (upper
+//              triangle);
+//   fix_chol:  one workgroup adds the partial Grams in workgroup order,
+//              factors G = R^T R and writes R^{-1} to rinv; a pivot not above
+//              1e-4 of its diagonal entry (cond(Q)^2 too large for one pass
+//              to restore orthogonality to rounding) sets flag bit 0, and the
+//              Householder kernel that follows recomputes Q from Y;
+//   fix_apply: Q <- Q R^{-1}, the same rows per workgroup.
+constexpr int kFixThreads = 256, kFixRows = 32, kFixMaxGroups = 32;
 constexpr int kFixPer = (96 * 97 / 2 + kFixThreads - 1) / kFixThreads;
+constexpr int kFixCholThreads = 1024;
+
+int64_t fix_rows(int64_t m) {  // rows per workgroup: a multiple of 32, at most 32 groups
+  // (few workgroups: the launches are enqueued on every QR and are usually
+  // no-ops, whose cost grows with the grid)
+  const int64_t ch = (m + kFixRows - 1) / kFixRows;
+  return kFixRows * ((ch + kFixMaxGroups - 1) / kFixMaxGroups);
+}
 
 template <typename T>
-__global__ __launch_bounds__(kFixThreads) void cholqr_fix_kernel(T *Q, int64_t m, int n,
-                                                                 int *flag) {
+__global__ __launch_bounds__(kFixThreads) void cholqr_fix_gram_kernel(const T *Q, int64_t m, int n,
+                                                                      int64_t rows,
+                                                                      const int *flag,
+                                                                      double *part) {
   if ((*flag & 3) != 2) return;
-  extern __shared__ double fx_lds[];
-  const int area = max(n * n, kFixRows * n);
-  double *A = fx_lds;         // chunk, then G and R (upper), then chunk again
-  double *B = fx_lds + area;  // chunk during the Gram, then R^{-1}
-  __shared__ double s_r, s_d0[96];
-  __shared__ int s_bad;
+  __shared__ double B[kFixRows * 96];
   const int tid = threadIdx.x;
   const int npair = n * (n + 1) / 2;
   double acc[kFixPer];
@@ -253,13 +263,12 @@ __global__ __launch_bounds__(kFixThreads) void cholqr_fix_kernel(T *Q, int64_t m
     pj[t] = i + rem;
     acc[t] = 0.0;
   }
-  for (int64_t r0 = 0; r0 < m; r0 += kFixRows) {
-    const int nr = (int)min<int64_t>(kFixRows, m - r0);
+  const int64_t rbeg = (int64_t)blockIdx.x * rows, rend = min<int64_t>(m, rbeg + rows);
+  for (int64_t r0 = rbeg; r0 < rend; r0 += kFixRows) {
+    const int nr = (int)min<int64_t>(kFixRows, rend - r0);
     __syncthreads();
-    for (int e = tid; e < kFixRows * n; e += kFixThreads) {
-      const int r = e / n, c = e - r * n;
-      B[e] = r < nr ? (double)Q[(r0 + r) * n + c] : 0.0;
-    }
+    for (int e = tid; e < kFixRows * n; e += kFixThreads)
+      B[e] = e < nr * n ? (double)Q[r0 * n + e] : 0.0;
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < kFixPer; ++t) {
@@ -271,13 +280,33 @@ __global__ __launch_bounds__(kFixThreads) void cholqr_fix_kernel(T *Q, int64_t m
       }
     }
   }
-  __syncthreads();
+  double *P = part + (int64_t)blockIdx.x * n * n;
 #pragma unroll
   for (int t = 0; t < kFixPer; ++t)
-    if (tid + t * kFixThreads < npair) A[pi[t] * n + pj[t]] = acc[t];
+    if (tid + t * kFixThreads < npair) P[pi[t] * n + pj[t]] = acc[t];
+}
+
+__global__ __launch_bounds__(kFixCholThreads) void cholqr_fix_chol_kernel(int n, int groups,
+                                                                          const double *part,
+                                                                          double *rinv,
+                                                                          int *flag) {
+  if ((*flag & 3) != 2) return;
+  extern __shared__ double fx_lds[];
+  double *A = fx_lds;          // G, then R (upper)
+  double *B = fx_lds + n * n;  // R^{-1}
+  __shared__ double s_r, s_d0[96];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kFixCholThreads) {
+    const int i = e / n, j = e - i * n;
+    if (j < i) continue;
+    double a = 0.0;
+    for (int w = 0; w < groups; ++w) a += part[(int64_t)w * n * n + e];
+    A[e] = a;
+  }
   if (tid == 0) s_bad = 0;
   __syncthreads();
-  for (int j = tid; j < n; j += kFixThreads) s_d0[j] = A[j * n + j];
+  for (int j = tid; j < n; j += kFixCholThreads) s_d0[j] = A[j * n + j];
   __syncthreads();
   // right-looking Cholesky on the upper triangle: A = R^T R
   for (int j = 0; j < n; ++j) {
@@ -292,17 +321,17 @@ __global__ __launch_bounds__(kFixThreads) void cholqr_fix_kernel(T *Q, int64_t m
     }
     __syncthreads();
     const double rj = s_r;
-    for (int c = j + 1 + tid; c < n; c += kFixThreads) A[j * n + c] /= rj;
+    for (int c = j + 1 + tid; c < n; c += kFixCholThreads) A[j * n + c] /= rj;
     __syncthreads();
     const int w = n - j - 1;
-    for (int e = tid; e < w * w; e += kFixThreads) {
+    for (int e = tid; e < w * w; e += kFixCholThreads) {
       const int i = j + 1 + e / w, c = j + 1 + e % w;
       if (c >= i) A[i * n + c] -= A[j * n + i] * A[j * n + c];
     }
     __syncthreads();
   }
   // R^{-1} (upper) by back substitution, one column per thread
-  for (int c = tid; c < n; c += kFixThreads) {
+  for (int c = tid; c < n; c += kFixCholThreads) {
     for (int j = n - 1; j > c; --j) B[j * n + c] = 0.0;
     B[c * n + c] = 1.0 / A[c * n + c];
     for (int j = c - 1; j >= 0; --j) {
@@ -311,21 +340,35 @@ __global__ __launch_bounds__(kFixThreads) void cholqr_fix_kernel(T *Q, int64_t m
       B[j * n + c] = -sum / A[j * n + j];
     }
   }
-  // Q <- Q R^{-1}
-  for (int64_t r0 = 0; r0 < m; r0 += kFixRows) {
-    const int nr = (int)min<int64_t>(kFixRows, m - r0);
+  __syncthreads();
+  for (int e = tid; e < n * n; e += kFixCholThreads) rinv[e] = B[e];
+  if (tid == 0 && s_bad) *flag = *flag | 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFixThreads) void cholqr_fix_apply_kernel(T *Q, int64_t m, int n,
+                                                                       int64_t rows,
+                                                                       const double *rinv,
+                                                                       const int *flag) {
+  if ((*flag & 3) != 2) return;
+  extern __shared__ double fx_lds[];
+  double *X = fx_lds;          // R^{-1}, n x n
+  double *A = fx_lds + n * n;  // 32 rows of Q
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kFixThreads) X[e] = rinv[e];
+  const int64_t rbeg = (int64_t)blockIdx.x * rows, rend = min<int64_t>(m, rbeg + rows);
+  for (int64_t r0 = rbeg; r0 < rend; r0 += kFixRows) {
+    const int nr = (int)min<int64_t>(kFixRows, rend - r0);
     __syncthreads();
     for (int e = tid; e < nr * n; e += kFixThreads) A[e] = (double)Q[r0 * n + e];
     __syncthreads();
     for (int e = tid; e < nr * n; e += kFixThreads) {
       const int r = e / n, c = e - r * n;
       double sum = 0.0;
-      for (int k = 0; k <= c; ++k) sum = fma(A[r * n + k], B[k * n + c], sum);
+      for (int k = 0; k <= c; ++k) sum = fma(A[r * n + k], X[k * n + c], sum);
       Q[r0 * n + e] = (T)sum;
     }
   }
-  __syncthreads();
-  if (tid == 0 && s_bad) *flag = *flag | 1;
 }
 
 // One workgroup Householder QR of the m x n row-major Y into Q (m x n), with
@@ -471,7 +514,10 @@ size_t qr_partial_elems(int64_t m, int64_t n) {
   // the Gram takes (both sizes, so that the choice can change between calls)
   const int sp = gemm_pick_splits(n, n, m, DType::F64);
   const size_t gemm_need = sp > 1 ? (size_t)sp * n * n : 0;
-  return std::max(gemm_need, gram_supported(n, m) ? gram_partial_elems(n, m) : (size_t)0);
+  // and the partial Grams of the third pass (ill-conditioned panels)
+  const size_t fix_need = (size_t)(((m + fix_rows(m) - 1) / fix_rows(m)) * n * n);
+  return std::max(std::max(gemm_need, fix_need),
+                  gram_supported(n, m) ? gram_partial_elems(n, m) : (size_t)0);
 }
 
 template <int NMAX>
@@ -521,17 +567,31 @@ static int householder(const T *Y, T *Q, T *work, double *rdiag, double *tau, in
 }
 
 template <typename T>
-static int cholqr_fix(T *Q, int64_t m, int64_t n, int *flag, hipStream_t s) {
+static int cholqr_fix(T *Q, int64_t m, int64_t n, int *flag, double *part, size_t part_bytes,
+                      double *rinv, hipStream_t s) {
   if (n > 96) return fail(TT_EUNSUPPORTED, "QR panel wider than 96");
+  const int64_t rows = fix_rows(m);
+  const int64_t groups = (m + rows - 1) / rows;
+  if ((size_t)(groups * n * n) * sizeof(double) > part_bytes || !part)
+    return fail(TT_EINVAL, "internal: split buffer too small for the third QR pass");
   static bool attr_set = false;
   if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_kernel<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024));
+    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_chol_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
+    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_apply_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
     attr_set = true;
   }
-  const size_t area = (size_t)std::max<int64_t>(n * n, kFixRows * n);
-  hipLaunchKernelGGL((cholqr_fix_kernel<T>), dim3(1), dim3(kFixThreads),
-                     2 * area * sizeof(double), s, Q, m, (int)n, flag);
+  hipLaunchKernelGGL((cholqr_fix_gram_kernel<T>), dim3((unsigned)groups), dim3(kFixThreads), 0, s,
+                     Q, m, (int)n, rows, flag, part);
+  TTR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(cholqr_fix_chol_kernel, dim3(1), dim3(kFixCholThreads),
+                     2 * (size_t)(n * n) * sizeof(double), s, (int)n, (int)groups, part, rinv,
+                     flag);
+  TTR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((cholqr_fix_apply_kernel<T>), dim3((unsigned)groups), dim3(kFixThreads),
+                     (size_t)(n * n + kFixRows * n) * sizeof(double), s, Q, m, (int)n, rows,
+                     rinv, flag);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
@@ -599,7 +659,8 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   // third pass when the first one was shifted (no-op otherwise), then the
   // Householder fallback (no-op unless a pivot broke down); q1 and rinv are
   // free again once the GEMMs above have run (same stream).
-  TTR_TRY(cholqr_fix<T>(Q, m, n, ws.flag, s));
+  TTR_TRY(cholqr_fix<T>(Q, m, n, ws.flag, static_cast<double *>(ws.partial),
+                        qr_partial_elems(m, n) * sizeof(double), ws.rinv, s));
   return householder<T>(Y, Q, q1, ws.rinv, ws.rinv + n, m, n, ws.flag, 0, s);
 }
 
