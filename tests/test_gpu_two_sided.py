@@ -81,3 +81,22 @@ def test_two_sided_rejects_float32(gpu_lib):
     Y = [c.float() for c in dev(G.random_tt(1, dims, ranks, scale="unit"))]
     with pytest.raises((gpu_lib.TTError, ValueError)):
         gpu_lib.round_two_sided(Y, 2)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+@pytest.mark.parametrize("case", [
+    (5, 40, 8, 40, 8),    # l equal to the strong rank
+    (5, 40, 8, 40, 12),   # l above it: W^L W^R has small singular values
+    (4, 30, 10, 30, 10),
+])
+def test_two_sided_near_low_rank_matches_oracle(gpu_lib, case, eps):
+    # X1 + eps X2 (the kind of input of the paper's first experiment): the
+    # products W^L_n W^R_n span several orders of magnitude, which the two
+    # Jacobi passes resolve
+    N, I, rl, rh, t = case
+    say(f"two-sided near-low-rank {case} eps={eps}")
+    Y = G.near_low_rank_tt(321, [I] * N, rl, rh, eps)
+    out = host(gpu_lib.round_two_sided(dev(Y), t, seed_left=5, seed_right=6))
+    ref = O.round_two_sided(Y, t, seed_left=5, seed_right=6)
+    assert O.ranks_of(out) == O.ranks_of(ref)
+    assert O.rel_diff(out, ref) < 1e-10
