@@ -48,20 +48,35 @@ def _compile(src):
     return obj, warn
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src):
+    """True when the object of src is missing or older than src or any header."""
+    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+    if not os.path.exists(obj):
+        return True
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    heads.append(os.path.join(os.path.dirname(HERE), "include", "tt_round.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in [src, *heads] if os.path.exists(f))
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those whose object is stale)
+    and link the library."""
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    todo = [s for s in srcs if _stale(s)] if incremental else srcs
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(_compile, todo))
     if verbose:
         for obj, warn in results:
             if warn:
                 print(warn, file=sys.stderr)
+    objs = [os.path.join(BUILD, os.path.basename(s).replace(".hip", ".o")) for s in srcs]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *[o for o, _ in results],
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs,
            "-Wl,--no-undefined", "-Wl,-soname,libttround.so"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -71,4 +86,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

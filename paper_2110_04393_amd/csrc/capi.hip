@@ -307,6 +307,12 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
 }
 
 // ---------------------------------------------------------------- rounding
+// Kept eigenvalues of a truncation Gram below this fraction of the largest
+// (singular values below 1e-2 of the largest) take the second pass of
+// trunc_refine.hip; above it the first pass resolves the kept directions and
+// the new core rows to about 1e-12 (FP64).
+constexpr double kTruncRefineTau = 1e-4;
+
 // Y: s summands, cores Y[j*N + n].  Sk: sketch cores (p.sk storage).
 // out: output cores.
 template <typename T>
@@ -359,6 +365,22 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   int *eflag = nullptr;
   double *escr = nullptr;
   T *Pf = nullptr, *Sf = nullptr, *tb[2] = {nullptr, nullptr};
+  // second pass for kept directions far below the largest (FP64 storage)
+  const bool refine = P.truncate && sizeof(T) == 8;
+  int *ctl = nullptr, *nmask = nullptr;
+  double *U1 = nullptr, *G2 = nullptr, *rscr = nullptr;
+  T *Ff = nullptr, *Bb = nullptr;
+  if (refine) {
+    int64_t cmax = 1;
+    for (int n = 2; n <= N; ++n) cmax = std::max(cmax, dims[n - 1] * P.out[n]);
+    ctl = c.arena.take<int>(4);
+    nmask = c.arena.take<int>((size_t)lm);
+    U1 = c.arena.take<double>((size_t)(lm * lm));
+    G2 = c.arena.take<double>((size_t)(lm * lm));
+    rscr = c.arena.take<double>(trunc_refine_scratch(lm, lm));
+    Ff = c.arena.take<T>((size_t)(lm * lm));
+    Bb = c.arena.take<T>((size_t)(lm * cmax));
+  }
   if (P.truncate) {
     gbuf = c.arena.take<double>((size_t)(lm * lm));
     lam = c.arena.take<double>((size_t)lm);
@@ -497,8 +519,75 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     g.math = DType::F64;
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
     }
-    if (!c.dry) TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s));
-    Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n)
+    if (!c.dry)
+      TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s,
+                           refine ? ctl : nullptr, refine ? kTruncRefineTau : 0.0));
+    if (refine) {
+      // second pass (runs only when ctl[0] = 1, decided on the device)
+      if (!c.dry) TTR_TRY(trunc_refine_basis(U, lr, ctl, U1, c.s));
+      GemmX b;  // B = U1^T H(X_n)
+      b.A = U1;
+      b.lda = lr;
+      b.a_kc = false;
+      b.ta = DType::F64;
+      b.B = hsrc;
+      b.ldb = cols;
+      b.b_kc = false;
+      b.tb = p.store;
+      b.C = Bb;
+      b.ldc = cols;
+      b.tc = p.store;
+      b.M = lr;
+      b.N = cols;
+      b.K = lr;
+      b.math = DType::F64;
+      b.gate = ctl;
+      TTR_TRY(gemm(c, b, TT_SITE_TRUNC));
+      if (gram_enabled(lr, cols)) {  // G2 = B B^T
+        if (!c.dry)
+          TTR_TRY(gram_run(Bb, p.store, true, cols, lr, cols, G2, lr, c.partial, c.partial_cap,
+                           c.s, ctl));
+      } else {
+        GemmX g;
+        g.A = Bb;
+        g.lda = cols;
+        g.a_kc = true;
+        g.ta = p.store;
+        g.B = Bb;
+        g.ldb = cols;
+        g.b_kc = true;
+        g.tb = p.store;
+        g.C = G2;
+        g.ldc = lr;
+        g.tc = DType::F64;
+        g.M = lr;
+        g.N = lr;
+        g.K = cols;
+        g.math = DType::F64;
+        g.gate = ctl;
+        TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
+      }
+      if (!c.dry) TTR_TRY(trunc_refine_solve<T>(G2, U1, lr, k, ctl, nmask, rscr, Ff, Pf, c.s));
+      Gemm<T> f;  // H(X_n) <- F B (second pass)
+      f.A = Ff;
+      f.lda = lr;
+      f.a_kc = true;
+      f.B = Bb;
+      f.ldb = cols;
+      f.b_kc = false;
+      f.C = out[n - 1];
+      f.ldc = cols;
+      f.M = k;
+      f.N = cols;
+      f.K = lr;
+      GemmX fx = f.x();
+      fx.gate = ctl;
+      TTR_TRY(gemm(c, fx, TT_SITE_TRUNC));
+      // B is no longer needed: it holds the completion rows
+      if (!c.dry)
+        TTR_TRY(trunc_refine_complete<T>(out[n - 1], k, cols, ctl, nmask, Bb, rscr, c.s));
+    }
+    Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n) (first pass)
     h.A = Sf;
     h.lda = lr;
     h.a_kc = true;
@@ -510,7 +599,10 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     h.M = k;
     h.N = cols;
     h.K = lr;
-    TTR_TRY(gemm(c, h, TT_SITE_TRUNC));
+    GemmX hx = h.x();
+    hx.gate = ctl;  // (null without the second pass)
+    hx.gate_on = 0;
+    TTR_TRY(gemm(c, hx, TT_SITE_TRUNC));
     Gemm<T> p;  // X_{n-1} <- X_{n-1} x_3 (U s)
     const int64_t rows = L[n - 2] * dims[n - 2];
     p.A = xs[n - 1];

@@ -499,6 +499,7 @@ __device__ __forceinline__ void gemm_any_body(const GemmX &g, const TileMap &tm,
 template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, int TM, int TN,
           int WM, int WN, int BKO>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmX g, TileMap tm) {
+  if (gemm_gated_off(g)) return;
   gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>(g, tm, blockIdx.x);
 }
 
@@ -568,6 +569,7 @@ __device__ __forceinline__ void splitk_reduce_body(const GemmX &g) {
 
 template <typename TP, typename TC>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmX g) {
+  if (gemm_gated_off(g)) return;
   splitk_reduce_body<TP, TC>(g);
 }
 

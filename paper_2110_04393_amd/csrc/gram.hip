@@ -30,7 +30,8 @@ constexpr int kMaxN = 128;
 template <typename TA, bool AKC, int kChunk>
 __global__ __launch_bounds__(kGramThreads) void gram_kernel(const TA *A, int64_t lda, int n,
                                                             int64_t K, double *out, int direct,
-                                                            int64_t ldg) {
+                                                            int64_t ldg, const int *gate) {
+  if (gate && *gate == 0) return;
   extern __shared__ __attribute__((aligned(16))) double gs[];  // [kChunk][ld]
   const int ld = ((n + 15) / 16) * 16 + 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -112,7 +113,7 @@ int64_t chunks_of(int64_t K) { return (K + chunk_rows(K) - 1) / chunk_rows(K); }
 
 template <typename TA, bool AKC, int kChunk>
 int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t ldg,
-           void *partial, hipStream_t s) {
+           void *partial, hipStream_t s, const int *gate) {
   const int64_t nc = (K + kChunk - 1) / kChunk;
   const int ld = (int)(((n + 15) / 16) * 16 + 2);
   const size_t lds = (size_t)kChunk * ld * sizeof(double);
@@ -125,7 +126,7 @@ int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t 
   const bool direct = nc == 1;
   hipLaunchKernelGGL((gram_kernel<TA, AKC, kChunk>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
                      static_cast<const TA *>(A), lda, (int)n, K,
-                     direct ? G : static_cast<double *>(partial), direct ? 1 : 0, ldg);
+                     direct ? G : static_cast<double *>(partial), direct ? 1 : 0, ldg, gate);
   TTR_HIP(hipGetLastError());
   if (!direct) {
     GemmX g;  // the chunk splits, summed in a fixed order
@@ -138,6 +139,7 @@ int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t 
     g.math = DType::F64;
     g.splits = (int)nc;
     g.partial = partial;
+    g.gate = gate;
     TTR_TRY(gemm_reduce_splits(g, s));
   }
   return TT_OK;
@@ -161,24 +163,25 @@ size_t gram_partial_elems(int64_t n, int64_t K) {
 }
 
 int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t K, double *G,
-             int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s) {
+             int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s,
+             const int *gate) {
   if (!gram_supported(n, K)) return fail(TT_EINVAL, "internal: Gram shape not supported");
   if (gram_partial_elems(n, K) * sizeof(double) > partial_bytes)
     return fail(TT_EINVAL, "internal: split buffer too small for the Gram");
   const bool c32 = chunk_rows(K) == 32;
   if (ta == DType::F64) {
     if (a_kc)
-      return c32 ? launch<double, true, 32>(A, lda, n, K, G, ldg, partial, s)
-                 : launch<double, true, 64>(A, lda, n, K, G, ldg, partial, s);
-    return c32 ? launch<double, false, 32>(A, lda, n, K, G, ldg, partial, s)
-               : launch<double, false, 64>(A, lda, n, K, G, ldg, partial, s);
+      return c32 ? launch<double, true, 32>(A, lda, n, K, G, ldg, partial, s, gate)
+                 : launch<double, true, 64>(A, lda, n, K, G, ldg, partial, s, gate);
+    return c32 ? launch<double, false, 32>(A, lda, n, K, G, ldg, partial, s, gate)
+               : launch<double, false, 64>(A, lda, n, K, G, ldg, partial, s, gate);
   }
   if (ta == DType::F32) {
     if (a_kc)
-      return c32 ? launch<float, true, 32>(A, lda, n, K, G, ldg, partial, s)
-                 : launch<float, true, 64>(A, lda, n, K, G, ldg, partial, s);
-    return c32 ? launch<float, false, 32>(A, lda, n, K, G, ldg, partial, s)
-               : launch<float, false, 64>(A, lda, n, K, G, ldg, partial, s);
+      return c32 ? launch<float, true, 32>(A, lda, n, K, G, ldg, partial, s, gate)
+                 : launch<float, true, 64>(A, lda, n, K, G, ldg, partial, s, gate);
+    return c32 ? launch<float, false, 32>(A, lda, n, K, G, ldg, partial, s, gate)
+               : launch<float, false, 64>(A, lda, n, K, G, ldg, partial, s, gate);
   }
   return fail(TT_EINVAL, "internal: Gram storage type");
 }

@@ -557,7 +557,7 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
 template <typename T>
 __device__ __forceinline__ bool tri_finish_part(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
-    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail) {
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *ctl, double tau) {
   extern __shared__ double lds[];
   const int ld = n | 1;
   double *Z = lds;             // n x ld (k columns)
@@ -572,18 +572,29 @@ __device__ __forceinline__ bool tri_finish_part(
   if (tid < kw) s_lam[tid] = lamw[tid];
   if (tid == 0) s_bad = 0;
   __syncthreads();
+  // kept eigenvalues at or above tau lambda_1: the first pass resolves them;
+  // when some kept one is below, only those above enter the checks below and
+  // the second pass (trunc_refine.hip) forms the factors
+  int kc = k;
+  if (ctl) {
+    const double thr = tau * s_lam[0];
+    kc = 0;
+    while (kc < k && s_lam[kc] >= thr) ++kc;
+    if (tau <= 0.0 || kc == 0) kc = k;
+  }
+  const int kg = (kc < k) ? kc : kw;  // eigenvalues whose gaps are checked
   if (wave == 0) {
     double mingap = 1e300;
-    for (int w = lane; w + 1 < kw; w += 64) mingap = fmin(mingap, s_lam[w] - s_lam[w + 1]);
+    for (int w = lane; w + 1 < kg; w += 64) mingap = fmin(mingap, s_lam[w] - s_lam[w + 1]);
     mingap = wave_min(mingap);
     if (lane == 0 && !(mingap >= 1e-9)) s_bad = 1;
   }
-  lds_gemm<true>(Z, ld, Z, ld, E, ld, k, k, n, 1.0, nullptr, 0, 0.0);
+  lds_gemm<true>(Z, ld, Z, ld, E, ld, kc, kc, n, 1.0, nullptr, 0, 0.0);
   __syncthreads();
   {
     double dev = 0.0;
-    for (int e = tid; e < k * k; e += blockDim.x) {
-      const int a = e / k, b = e - a * k;
+    for (int e = tid; e < kc * kc; e += blockDim.x) {
+      const int a = e / kc, b = e - a * kc;
       dev = fmax(dev, fabs(E[a * ld + b] - (a == b ? 1.0 : 0.0)));
     }
     dev = wave_max(dev);
@@ -591,13 +602,19 @@ __device__ __forceinline__ bool tri_finish_part(
   }
   __syncthreads();
   if (s_bad) return false;
-  for (int e = tid; e < k * k; e += blockDim.x) {
-    const int a = e / k, b = e - a * k;
+  for (int e = tid; e < kc * kc; e += blockDim.x) {
+    const int a = e / kc, b = e - a * kc;
     E[a * ld + b] = (a == b ? 1.5 : 0.0) - 0.5 * E[a * ld + b];
   }
   __syncthreads();
-  lds_right_mul_inplace(Z, ld, n, k, E, ld);
+  lds_right_mul_inplace(Z, ld, n, kc, E, ld);
   __syncthreads();
+  if (ctl && tid == 0) {
+    ctl[0] = kc < k ? 1 : 0;
+    ctl[1] = kc;
+    ctl[2] = 0;
+    ctl[3] = k;
+  }
   const double inv_sc = 1.0 / *scp;
   const double l0 = fmax(s_lam[0] * inv_sc, 0.0);
   for (int e = tid; e < n * k; e += blockDim.x) {
@@ -628,23 +645,36 @@ __device__ __forceinline__ bool tri_finish_part(
 template <typename T>
 __device__ __forceinline__ void tri_finish_kernel_body(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
-    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force) {
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force,
+    int *ctl = nullptr, double tau = 0.0) {
   if (!force && *flag == 0 &&
-      tri_finish_part<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail))
+      tri_finish_part<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, ctl, tau))
     return;
   __syncthreads();
   jacobi_eig_kernel_body(Gin, lam_out, U_out, n, nullptr, nullptr);
   __syncthreads();
   trunc_factors_kernel_body<T>(lam_out, U_out, n, k, P, S, tail, nullptr);
-  if (threadIdx.x == 0) *flag = 1;
+  if (threadIdx.x == 0) {
+    *flag = 1;
+    if (ctl) {
+      int w = 0;
+      const double thr = tau * lam_out[0];
+      while (w < k && lam_out[w] >= thr) ++w;
+      ctl[0] = (tau > 0.0 && w > 0 && w < k) ? 1 : 0;
+      ctl[1] = w;
+      ctl[2] = 0;
+      ctl[3] = n;
+    }
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
-    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force) {
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force,
+    int *ctl, double tau) {
   tri_finish_kernel_body<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, flag,
-                            force);
+                            force, ctl, tau);
 }
 
 template <int NMAX>
@@ -682,7 +712,7 @@ static size_t finish_lds(int n) {
 
 template <typename T>
 int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *P, T *S,
-              double *tail, int *flag, double *scratch, hipStream_t s) {
+              double *tail, int *flag, double *scratch, hipStream_t s, int *ctl, double tau) {
   if (n > TT_MAX_SKETCH_RANK) return fail(TT_EUNSUPPORTED, "eigenproblem larger than the limit");
   if (k < 1 || k > n) return fail(TT_EINVAL, "truncation rank out of range");
   if (n <= kTeNMax) {
@@ -711,20 +741,22 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
                          taus, lamw, Uz, flag);
     TTR_HIP(hipGetLastError());
     hipLaunchKernelGGL((tri_finish_kernel<T>), dim3(1), dim3(kTeThreads), finish_lds((int)n), s, G,
-                       lamw, Uz, sc, (int)n, (int)k, kw, lam, U, P, S, tail, flag, g_eig_mode);
+                       lamw, Uz, sc, (int)n, (int)k, kw, lam, U, P, S, tail, flag, g_eig_mode,
+                       ctl, tau);
     TTR_HIP(hipGetLastError());
     return TT_OK;
   }
   TTR_TRY(sym_eig(G, lam, U, n, s, nullptr, nullptr));
+  if (ctl) TTR_TRY(trunc_refine_ctl(lam, n, k, tau, ctl, s));
   return trunc_factors<T>(lam, U, n, k, P, S, tail, s, nullptr);
 }
 
 size_t eig_trunc_scratch(int64_t n, int64_t k) { return (size_t)(4 * n + 2 + n * n + n * k); }
 
 template int eig_trunc<double>(const double *, int64_t, int64_t, double *, double *, double *,
-                               double *, double *, int *, double *, hipStream_t);
+                               double *, double *, int *, double *, hipStream_t, int *, double);
 template int eig_trunc<float>(const double *, int64_t, int64_t, double *, double *, float *,
-                              float *, double *, int *, double *, hipStream_t);
+                              float *, double *, int *, double *, hipStream_t, int *, double);
 
 bool eig_group_desc(const double *G, int64_t n, int64_t k, double *lam, double *U, void *P,
                     void *S, double *tail, int *flag, double *scratch, EigGroupDesc *d) {
