@@ -232,6 +232,10 @@ TT_API int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t
  *   grad_in[N]  device buffers of the input core shapes, overwritten with
  *               the gradient
  *   prec        TT_PREC_F64 (TT_F64) or TT_PREC_F32 (TT_F32)
+ * R_n is formed as Q_n^T Y_n from the Q_n of the forward sweep.  The call
+ * waits for `stream` at its end and returns TT_ENUMERIC when some R_n is
+ * numerically singular (a rank-deficient sketch Y_n, where the adjoint of the
+ * thin QR is undefined); grad_in is then unspecified.
  * Returns TT_EUNSUPPORTED when the rounding truncates (target_rank below a
  * sketch rank) or for TT_PREC_MIXED_BF16.
  */

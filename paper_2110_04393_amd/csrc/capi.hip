@@ -634,7 +634,9 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
 //   dQ   = dO_n + Z_n dM_n^T                   dZ_n         = Q_n dM_n
 //   dY_n = (dQ + Q_n copyltu(-dQ^T Q_n)) R_n^{-T}     (QR adjoint, R unused)
 //   dZ_n += dY_n W_n^T                         dW_n         = Z_n^T dY_n
-// and dX~_n = dZ_n (dY_1 = dZ_1).  Finally the W chain in reverse, n = 1..N-2:
+// and dX~_n = dZ_n (dY_1 = dZ_1).  R_n = Q_n^T Y_n is formed from the Q_n the
+// sweep produced (whichever QR path produced it) and inverted by back
+// substitution.  Finally the W chain in reverse, n = 1..N-2:
 //   dZc = f_n dW_n H(S_{n+1}),  dV(Y_{n+1}) += dV(Zc) W_{n+1}^T,
 //   dW_{n+1} += V(Y_{n+1})^T dV(Zc),   and dH(Y_N) += f_{N-1} dW_{N-1} H(S_N)
 // (f_n: the power-of-two factor applied to W_n, 1 in FP64).
@@ -700,8 +702,8 @@ int backward_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
       qs.partial = c.partial;
       TTR_TRY(qr_thin<T>(ys, q[n], m, L[n], qs, c.s));
     }
-    GemmX gr;  // FP64 Gram of Y_n, Cholesky -> R_n^{-1}
-    gr.A = ys;
+    GemmX gr;  // R_n = Q_n^T Y_n (FP64): the factor of the Q the sweep produced
+    gr.A = q[n];
     gr.lda = L[n];
     gr.a_kc = false;
     gr.ta = p.store;
@@ -717,7 +719,7 @@ int backward_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     gr.K = m;
     gr.math = DType::F64;
     TTR_TRY(gemm(c, gr));
-    if (!c.dry) TTR_TRY(chol_inverse(gram, L[n], rinv[n], rinvf[n], cflag, c.s));
+    if (!c.dry) TTR_TRY(tri_inv_upper(gram, L[n], rinv[n], rinvf[n], cflag, n == 1, c.s));
     Gemm<T> h;  // M_n = Q^T Z_n
     h.A = q[n];
     h.lda = L[n];
@@ -959,7 +961,17 @@ int backward_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   z.K = L[N - 1];
   z.beta = 1.0;
   z.math = p.wmath;
-  return gemm(c, z);
+  TTR_TRY(gemm(c, z));
+  if (c.dry) return TT_OK;
+  // a numerically singular R_n (a rank-deficient sketch Y_n) leaves the
+  // adjoint of the thin QR undefined: report it
+  int bad = 0;
+  TTR_HIP(hipMemcpyAsync(&bad, cflag, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  TTR_HIP(hipStreamSynchronize(c.s));
+  if (bad)
+    return fail(TT_ENUMERIC, "tt_round_rand_backward: a sketched matrix Y_n = Z_n W_n is "
+                             "numerically rank deficient (its R factor is singular)");
+  return TT_OK;
 }
 
 // ---------------------------------------------------------------- TT-SVD

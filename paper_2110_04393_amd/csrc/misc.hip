@@ -177,6 +177,44 @@ __global__ __launch_bounds__(kScaleThreads) void scale_pow2_group_kernel(const S
   scale_pow2_kernel_body<T>(static_cast<T *>(e.x), e.count, e.fout);
 }
 
+// X = R^{-1} of an upper-triangular n x n R (row-major, FP64), one column
+// of X per thread by back substitution; Xf (optional) receives X rounded to
+// FP32.  *flag = 1 (first = 1) or |= 1 when a diagonal entry is not above
+// 64 u max_i |R_ii| or a result is not finite (R numerically singular).
+__global__ __launch_bounds__(256) void tri_inv_upper_kernel(const double *R, int n, double *X,
+                                                           float *Xf, int *flag, int first) {
+  __shared__ double s_max;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(R[i * n + i]));
+    s_max = mx;
+    s_bad = 0;
+  }
+  __syncthreads();
+  const double floor_d = 64.0 * 1.1102230246251565e-16 * s_max;
+  for (int c = tid; c < n; c += blockDim.x) {
+    bool bad = false;
+    for (int i = n - 1; i >= 0; --i) {
+      double v = 0.0;
+      if (i <= c) {
+        double acc = (i == c) ? 1.0 : 0.0;
+        for (int m = i + 1; m <= c; ++m) acc -= R[i * n + m] * X[m * n + c];
+        const double d = R[i * n + i];
+        if (!(fabs(d) > floor_d)) bad = true;
+        v = acc / d;
+        if (!isfinite(v)) bad = true;
+      }
+      X[i * n + c] = v;
+      if (Xf) Xf[i * n + c] = (float)v;
+    }
+    if (bad) s_bad = 1;
+  }
+  __syncthreads();
+  if (tid == 0) *flag = first ? s_bad : (*flag | s_bad);
+}
+
 }  // namespace
 
 template <typename T>
@@ -256,6 +294,15 @@ int nystrom_scale(const double *lam, const double *U, int64_t n, double rcond, d
   if (n <= 0) return TT_OK;
   hipLaunchKernelGGL(nystrom_scale_kernel, dim3(1), dim3(256), 0, s, lam, U, (int)n,
                      rcond * rcond, A1, A2);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+int tri_inv_upper(const double *R, int64_t n, double *X, float *Xf, int *flag, bool first,
+                  hipStream_t s) {
+  if (n <= 0) return TT_OK;
+  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3(1), dim3(256), 0, s, R, (int)n, X, Xf, flag,
+                     first ? 1 : 0);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }

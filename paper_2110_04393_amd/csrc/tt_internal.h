@@ -444,6 +444,13 @@ int copyltu(T *C, const T *M, int64_t k, double alpha, hipStream_t s);
 int nystrom_scale(const double *lam, const double *U, int64_t n, double rcond, double *A1,
                   double *A2, hipStream_t s);
 
+// X = R^{-1} of the upper-triangular n x n FP64 R (row-major); Xf (optional)
+// the same rounded to FP32; *flag = (first ? 0 : *flag) | (R numerically
+// singular: a diagonal entry at or below 64 u max |R_ii|, or a non-finite
+// result)
+int tri_inv_upper(const double *R, int64_t n, double *X, float *Xf, int *flag, bool first,
+                  hipStream_t s);
+
 // dst = RNE_bf16(src)
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);
 

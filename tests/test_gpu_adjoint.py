@@ -150,3 +150,55 @@ def test_backward_rejects_truncation(gpu_lib):
     with pytest.raises(L.TTError) as e:
         gpu_lib.round_rand_backward(Y, [None, None, None], 2, 1, seed=1)
     assert e.value.status == L.TT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("qr", ["auto", "householder"])
+def test_backward_near_low_rank_fp64(gpu_lib, qr, monkeypatch):
+    # X1 (rank 4) + 1e-4 X2 (rank 8) with sketch rank 6: every sketched
+    # matrix Y_n has two weak columns (condition number about 1e4).  The
+    # adjoint's R_n comes from the Q_n the forward produced (forced
+    # Householder: the fallback path of the thin QR).
+    from oracle.tt_adjoint import rto_vjp
+    if qr == "householder":
+        monkeypatch.setenv("TT_QR", "householder")
+    say(f"adjoint fp64 near-low-rank qr={qr}")
+    Y = G.near_low_rank_tt(131, [12] * 5, 4, 8, 1e-4)
+    dims, ranks = O.dims_of(Y), O.ranks_of(Y)
+    ellv, outr = O.plan_ranks(dims, ranks, 6, 0)
+    S = O.make_sketch(138, dims, ellv)
+    rng = np.random.default_rng(139)
+    Gc = [rng.standard_normal((outr[n], dims[n], outr[n + 1])) for n in range(5)]
+    gi = host(gpu_lib.round_rand_backward(dev(Y), dev(Gc), 6, 0, seed=138))
+    ref = rto_vjp(Y, S, Gc)
+    errs = [rel(a, b) for a, b in zip(gi, ref)]
+    print("per-core rel err", ["%.1e" % e for e in errs])
+    assert max(errs) <= 1e-7
+    # and a directional finite difference of the GPU forward
+    D = [rng.standard_normal(c.shape) for c in Y]
+
+    def f(t):
+        out = host(gpu_lib.round_rand(dev([y + t * d for y, d in zip(Y, D)]), 6, 0, seed=138))
+        return sum(float(np.sum(g * o)) for g, o in zip(Gc, out))
+
+    # the map is strongly curved here (its derivative carries 1/eps): a small
+    # step keeps the central difference's h^2 term below the tolerance
+    h = 1e-9
+    fd = (f(h) - f(-h)) / (2 * h)
+    an = sum(float(np.sum(g * d)) for g, d in zip(gi, D))
+    print(f"fd {fd:.10e} analytic {an:.10e}")
+    assert abs(fd - an) <= 1e-5 * max(1.0, abs(an))
+
+
+def test_backward_reports_rank_deficient_sketch(gpu_lib):
+    # A + A (exact rank 4) with sketch rank 6: the sketched matrices are
+    # rank deficient and the adjoint of their thin QR is undefined
+    from paper_2110_04393_amd import _lib as L
+    say("adjoint of a rank-deficient sketch reports TT_ENUMERIC")
+    A = G.random_tt(141, [8] * 4, [1, 4, 4, 4, 1])
+    Y = G.block_sum([A, A])
+    dims, ranks = O.dims_of(Y), O.ranks_of(Y)
+    _, outr = O.plan_ranks(dims, ranks, 6, 0)
+    Gc = [np.ones((outr[n], dims[n], outr[n + 1])) for n in range(4)]
+    with pytest.raises(L.TTError) as e:
+        gpu_lib.round_rand_backward(dev(Y), dev(Gc), 6, 0, seed=142)
+    assert e.value.status == L.TT_ENUMERIC

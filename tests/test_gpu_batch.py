@@ -3,12 +3,10 @@ on the same inputs and sketch values; replays and autotuning must not change
 the results.
 
 Tolerances: FP64 <= 1e-10 relative (as the single-TT path); FP32 <= 1e-4
-relative (FP32 storage and MFMA with FP64 Gram/Cholesky; the oracle gets
-the FP32-rounded inputs and sketch).  The full 64-TT workload is checked
-element-wise against the oracle on its smallest TTs (the oracle needs
-minutes for the largest), and on every TT through properties that hold at
-any size: finite cores, right-orthogonal cores 2..N, and agreement with the
-single-TT GPU path.
+relative on inputs whose sketches capture their spectra (FP32 storage and
+MFMA with FP64 Gram/Cholesky; the oracle gets the FP32-rounded inputs and
+sketch).  The full 64-TT workload is compared with the oracle TT by TT in
+both precisions.
 """
 import sys
 
@@ -113,46 +111,57 @@ def test_autotune_does_not_change_results(gpu_lib):
     b.close()
 
 
-def test_batched_workload_64_fp32(gpu_lib):
-    # 64 TTs: N ~ U{8..24}, I in {16,...,256}, R ~ U{8..128}, target R//2,
-    # oversample min(10, R - target); FP32; one graph, autotuned tiles
+def batched_workload(dtype_np):
     specs = G.batched_specs(0, 64)
-    say("batched workload: 64 TTs, FP32")
-    tts_np, dtt = [], []
+    tts = []
     for s in specs:
         dims, ranks = G.uniform_tt_shape(s["N"], s["I"], s["R"])
-        X = [c.astype(np.float32) for c in G.random_tt(s["input_seed"], dims, ranks,
-                                                        scale="nominal")]
-        tts_np.append(X)
-        dtt.append([torch.from_numpy(c).cuda() for c in X])
+        X = G.random_tt(s["input_seed"], dims, ranks, scale="nominal")
+        if dtype_np == np.float32:
+            X = [O.round_f32(c) for c in X]
+        tts.append(X)
+    return specs, tts
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batched_workload_64_vs_oracle(gpu_lib, prec):
+    # 64 TTs: N ~ U{8..24}, I in {16,...,256}, R ~ U{8..128}, target R//2,
+    # oversample min(10, R - target); one graph, autotuned tiles.  Every TT
+    # against the oracle (FP32: given the FP32-rounded inputs and sketch).
+    # FP64 parity is 1e-10.  In FP32 these flat-spectrum roundings move with
+    # the rounding of the arithmetic to first order (no parity claim): the
+    # worst difference is reported and bounded by 1e-3 (measured 8.8e-5),
+    # the four smallest TTs by 1e-4.
+    say(f"batched workload: 64 TTs, {prec}")
+    dt = torch.float64 if prec == "f64" else torch.float32
+    specs, tts = batched_workload(np.float64 if prec == "f64" else np.float32)
+    dtt = [dev(X, dt) for X in tts]
     bp = gpu_lib.BatchPlan(dtt, [s["target"] for s in specs], [s["oversample"] for s in specs],
-                           [s["sketch_seed"] for s in specs], prec="f32", graph=True,
+                           [s["sketch_seed"] for s in specs], prec=prec, graph=True,
                            autotune=True)
     outs = [host(o) for o in bp.run()]
     print(bp.info())
-    # properties on every TT, and agreement with the single-TT GPU path
-    worst_orth, worst_single = 0.0, 0.0
-    for s, X, Xd, out in zip(specs, tts_np, dtt, outs):
-        assert all(np.all(np.isfinite(c)) for c in out)
-        worst_orth = max(worst_orth, right_orth_dev(out))
-        single = host(gpu_lib.round_rand(Xd, s["target"], s["oversample"], seed=s["sketch_seed"],
-                                         prec="f32"))
-        worst_single = max(worst_single, O.rel_diff(out, single))
-    print(f"worst right-orthogonality {worst_orth:.2e}; worst batch-vs-single {worst_single:.2e}")
-    assert worst_orth <= 1e-3
-    # both are FP32 computations of a flat-spectrum rounding (first-order
-    # sensitive to rounding); the batch always uses CholeskyQR2, the single
-    # path Householder on small panels
-    assert worst_single <= 3e-3
-    # element-wise oracle parity on the smallest TTs
-    size = [s["N"] * s["I"] * s["R"] ** 2 for s in specs]
-    for b in np.argsort(size)[:4]:
-        s = specs[b]
-        X = [c.astype(np.float64) for c in tts_np[b]]
-        ref = oracle_item(X, dict(target=s["target"], oversample=s["oversample"],
-                                  seed=s["sketch_seed"]), "f32")
-        err = O.rel_diff(outs[b], ref)
-        print(f"item {b} N={s['N']} I={s['I']} R={s['R']}: rel err vs oracle {err:.2e}")
-        assert O.ranks_of(outs[b]) == O.ranks_of(ref)
-        assert err <= 1e-4
     bp.close()
+    worst, worst_orth = 0.0, 0.0
+    errs = []
+    for b, (s, X, out) in enumerate(zip(specs, tts, outs)):
+        assert all(np.all(np.isfinite(c)) for c in out)
+        ref = oracle_item(X, dict(target=s["target"], oversample=s["oversample"],
+                                  seed=s["sketch_seed"]), prec)
+        assert O.ranks_of(out) == O.ranks_of(ref)
+        err = O.rel_diff(out, ref)
+        errs.append(err)
+        worst = max(worst, err)
+        worst_orth = max(worst_orth, right_orth_dev(out))
+    print(f"{prec}: worst rel err vs oracle {worst:.2e} (median {np.median(errs):.2e}); "
+          f"worst right-orthogonality {worst_orth:.2e}")
+    if prec == "f64":
+        assert worst <= 1e-10
+        assert worst_orth <= 1e-10
+    else:
+        assert worst <= 1e-3
+        assert worst_orth <= 1e-5
+        size = [s["N"] * s["I"] * s["R"] ** 2 for s in specs]
+        for b in np.argsort(size)[:4]:
+            assert errs[b] <= 1e-4, (b, errs[b])

@@ -212,7 +212,9 @@ def test_round_flat_spectrum_reported(gpu_lib, prec):
     ref = O.round_rand(X, target, over, sketch=sk)
     err = O.rel_diff(out, ref)
     print(f"{prec}: flat-spectrum rel err vs oracle {err:.3e}")
-    assert err <= (1e-3 if prec == "f32" else 0.5)
+    # measured: FP32 3.2e-6, BF16 4.7e-2 (the BF16 operands move W_n by
+    # about 2^-9 per level, and the output with it to first order)
+    assert err <= (1e-4 if prec == "f32" else 0.2)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
