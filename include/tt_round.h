@@ -182,6 +182,25 @@ TT_API int tt_round_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
                   void *const *out_cores, void *workspace, size_t ws_bytes,
                   void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): tt_round_rand with
+ * its workspace in a fixed device array of TT_NOALLOC_SCRATCH_BYTES owned by
+ * the library (one per GPU, held from the library's load on that GPU to the
+ * end of the process).  No device memory is allocated or freed by the call.
+ * Arguments, results and errors as tt_round_rand; TT_EUNSUPPORTED when
+ * tt_round_rand_workspace exceeds TT_NOALLOC_SCRATCH_BYTES.  Every call on a
+ * GPU uses that GPU's one array: calls that may overlap on one GPU (other
+ * host threads, unordered streams) race and must be serialised by the
+ * caller.  The array's device address is looked up on the first call on each
+ * device (the current device).
+ */
+#define TT_NOALLOC_SCRATCH_BYTES (256u << 20) /* 256 MiB per GPU */
+TT_API int tt_round_rand_noalloc(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                 const void *const *cores, int32_t dtype, int64_t target_rank,
+                                 int64_t oversample, uint64_t sketch_seed, int32_t prec,
+                                 void *const *out_cores, void *stream);
+
 /* As tt_round_rand with a caller-given sketch TT (device cores of shape
  * (sketch_ranks[n], dims[n], sketch_ranks[n+1]) in `dtype` storage).
  * sketch_ranks must equal the plan's sketch ranks. */

@@ -325,6 +325,31 @@ def round_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0, prec
     return [c.clone() for c in p.run(cores, seed=seed, sketch=sketch, stream=stream)]
 
 
+def round_rand_noalloc(cores, target_rank: int, oversample: int = 0, seed: int = 0,
+                       prec: str = "f64", out=None, stream=None):
+    """Randomize-then-Orthogonalize rounding through tt_round_rand_noalloc
+    (workspace in the library's fixed device array, nothing allocated by
+    the call).  `out`: preallocated output cores at the plan's out ranks
+    (allocated here when omitted); returns them."""
+    _check_cores(cores)
+    if prec not in _PREC:
+        raise ValueError(f"unknown prec {prec!r}")
+    dims, ranks = _shape_of(cores)
+    N = len(dims)
+    _, out_ranks = plan(dims, ranks, target_rank, oversample)
+    if out is None:
+        out = [torch.empty((out_ranks[n], dims[n], out_ranks[n + 1]), dtype=cores[0].dtype,
+                           device=cores[0].device) for n in range(N)]
+    for n, c in enumerate(out):
+        if tuple(c.shape) != (out_ranks[n], dims[n], out_ranks[n + 1]) or not c.is_contiguous():
+            raise ValueError("output cores do not match the plan's out ranks")
+    L.check(L.lib().tt_round_rand_noalloc(
+        N, L.i64_array(dims), L.i64_array(ranks), L.ptr_array([c.data_ptr() for c in cores]),
+        _DTYPE[cores[0].dtype], int(target_rank), int(oversample), int(seed) & ((1 << 64) - 1),
+        _PREC[prec], L.ptr_array([c.data_ptr() for c in out]), _stream_handle(stream)))
+    return out
+
+
 def sum_round(summands, coeffs, target_rank: int, oversample: int = 0, seed: int = 0,
               prec: str = "f64", stream=None):
     """Rounding of sum_j coeffs[j] * summands[j] (Algorithm 7)."""
