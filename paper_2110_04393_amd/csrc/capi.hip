@@ -368,7 +368,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   // second pass for kept directions far below the largest (FP64 storage)
   const bool refine = P.truncate && sizeof(T) == 8;
   int *ctl = nullptr, *nmask = nullptr;
-  double *U1 = nullptr, *G2 = nullptr, *rscr = nullptr;
+  double *U1 = nullptr, *G2 = nullptr, *rscr = nullptr, *cscr = nullptr;
   T *Ff = nullptr, *Bb = nullptr;
   if (refine) {
     int64_t cmax = 1;
@@ -380,6 +380,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     rscr = c.arena.take<double>(trunc_refine_scratch(lm, lm));
     Ff = c.arena.take<T>((size_t)(lm * lm));
     Bb = c.arena.take<T>((size_t)(lm * cmax));
+    cscr = c.arena.take<double>(trunc_complete_scratch(lm, cmax));
   }
   if (P.truncate) {
     gbuf = c.arena.take<double>((size_t)(lm * lm));
@@ -521,10 +522,9 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     }
     if (!c.dry)
       TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s,
-                           refine ? ctl : nullptr, refine ? kTruncRefineTau : 0.0));
+                           refine ? ctl : nullptr, refine ? kTruncRefineTau : 0.0, U1));
     if (refine) {
       // second pass (runs only when ctl[0] = 1, decided on the device)
-      if (!c.dry) TTR_TRY(trunc_refine_basis(U, lr, ctl, U1, c.s));
       GemmX b;  // B = U1^T H(X_n)
       b.A = U1;
       b.lda = lr;
@@ -568,26 +568,10 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
         TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
       }
       if (!c.dry) TTR_TRY(trunc_refine_solve<T>(G2, U1, lr, k, ctl, nmask, rscr, Ff, Pf, c.s));
-      Gemm<T> f;  // H(X_n) <- F B (second pass)
-      f.A = Ff;
-      f.lda = lr;
-      f.a_kc = true;
-      f.B = Bb;
-      f.ldb = cols;
-      f.b_kc = false;
-      f.C = out[n - 1];
-      f.ldc = cols;
-      f.M = k;
-      f.N = cols;
-      f.K = lr;
-      GemmX fx = f.x();
-      fx.gate = ctl;
-      TTR_TRY(gemm(c, fx, TT_SITE_TRUNC));
-      // B is no longer needed: it holds the completion rows
-      if (!c.dry)
-        TTR_TRY(trunc_refine_complete<T>(out[n - 1], k, cols, ctl, nmask, Bb, rscr, c.s));
     }
-    Gemm<T> h;  // H(X_n) <- s^-1 U^T H(X_n) (first pass)
+    // new core: H(X_n) <- s^-1 U^T H(X_n) (first pass), or F B when the
+    // second pass ran (operands chosen on the device, one launch)
+    Gemm<T> h;
     h.A = Sf;
     h.lda = lr;
     h.a_kc = true;
@@ -600,9 +584,15 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     h.N = cols;
     h.K = lr;
     GemmX hx = h.x();
-    hx.gate = ctl;  // (null without the second pass)
-    hx.gate_on = 0;
+    if (refine) {
+      hx.sel = ctl;
+      hx.A2 = Ff;
+      hx.B2 = Bb;
+    }
     TTR_TRY(gemm(c, hx, TT_SITE_TRUNC));
+    // orthonormal rows in place of directions with no information left
+    if (refine && !c.dry)
+      TTR_TRY(trunc_refine_complete<T>(out[n - 1], k, cols, ctl, nmask, cscr, c.s));
     Gemm<T> p;  // X_{n-1} <- X_{n-1} x_3 (U s)
     const int64_t rows = L[n - 2] * dims[n - 2];
     p.A = xs[n - 1];

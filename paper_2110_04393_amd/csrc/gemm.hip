@@ -500,6 +500,10 @@ template <class MT, typename TA, typename TB, typename TC, bool AKC, bool BKC, i
           int WM, int WN, int BKO>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(GemmX g, TileMap tm) {
   if (gemm_gated_off(g)) return;
+  if (g.sel && *g.sel) {
+    g.A = g.A2;
+    g.B = g.B2;
+  }
   gemm_any_body<MT, TA, TB, TC, AKC, BKC, TM, TN, WM, WN, BKO>(g, tm, blockIdx.x);
 }
 

@@ -549,6 +549,61 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
   tri_vec_body<NMAX>(d_in, e_in, n, k, Vr, taus, lam_out, Uz, flag, blockIdx.x);
 }
 
+// U1 (n x n, row-major, global) = Q of the full Householder QR of the first
+// w columns of Z (LDS, leading dimension ld; overwritten by the reflectors):
+// an orthonormal basis whose first w columns are +-Z[:, :w] and whose others
+// span their complement (the basis of the second truncation pass,
+// trunc_refine.hip).  All threads of the workgroup.
+__device__ void complement_basis(double *Z, int ld, int n, int w, double *U1) {
+  __shared__ double s_tau[kTeNMax + 1], s_dot[kTeNMax + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < w; ++j) {
+    if (wave == 0) {
+      double a = 0.0;
+      for (int i = j + lane; i < n; i += 64) a += Z[i * ld + j] * Z[i * ld + j];
+      const double nrm2 = wave_sum(a);
+      if (lane == 0) {
+        const double x0 = Z[j * ld + j];
+        const double nrm = sqrt(nrm2);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        const double vv = nrm2 - x0 * x0 + v0 * v0;
+        s_tau[j] = vv > 0.0 ? 2.0 / vv : 0.0;
+        Z[j * ld + j] = v0;
+      }
+    }
+    __syncthreads();
+    for (int c = j + 1 + wave; c < w; c += blockDim.x >> 6) {
+      double a = 0.0;
+      for (int i = j + lane; i < n; i += 64) a += Z[i * ld + j] * Z[i * ld + c];
+      a = wave_sum(a);
+      if (lane == 0) s_dot[c] = a;
+    }
+    __syncthreads();
+    for (int e = tid; e < (n - j) * (w - j - 1); e += blockDim.x) {
+      const int i = j + e / (w - j - 1), c = j + 1 + e % (w - j - 1);
+      Z[i * ld + c] -= s_tau[j] * Z[i * ld + j] * s_dot[c];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += blockDim.x) U1[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = w - 1; j >= 0; --j) {
+    for (int c = wave; c < n; c += blockDim.x >> 6) {
+      double a = 0.0;
+      for (int i = j + lane; i < n; i += 64) a += Z[i * ld + j] * U1[i * n + c];
+      a = wave_sum(a);
+      if (lane == 0) s_dot[c] = a;
+    }
+    __syncthreads();
+    for (int e = tid; e < (n - j) * n; e += blockDim.x) {
+      const int i = j + e / n, c = e % n;
+      U1[i * n + c] -= s_tau[j] * Z[i * ld + j] * s_dot[c];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- kernel 3
 // One workgroup: gap check, orthogonality check and one Newton-Schulz step on
 // U (n x k, from kernel 2), outputs (unscaled eigenvalues, U, truncation
@@ -557,7 +612,8 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
 template <typename T>
 __device__ __forceinline__ bool tri_finish_part(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
-    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *ctl, double tau) {
+    int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *ctl, double tau,
+    double *U1) {
   extern __shared__ double lds[];
   const int ld = n | 1;
   double *Z = lds;             // n x ld (k columns)
@@ -615,6 +671,8 @@ __device__ __forceinline__ bool tri_finish_part(
     ctl[2] = 0;
     ctl[3] = k;
   }
+  // the outputs below read Z; the basis of the second pass is built after
+  const bool second = ctl && kc < k;
   const double inv_sc = 1.0 / *scp;
   const double l0 = fmax(s_lam[0] * inv_sc, 0.0);
   for (int e = tid; e < n * k; e += blockDim.x) {
@@ -635,6 +693,10 @@ __device__ __forceinline__ bool tri_finish_part(
     kept = wave_sum(kept) * inv_sc;
     if (lane == 0) *tail = fmax(tr - kept, 0.0);
   }
+  if (second) {
+    __syncthreads();
+    complement_basis(Z, ld, n, kc, U1);
+  }
   return true;
 }
 
@@ -646,16 +708,19 @@ template <typename T>
 __device__ __forceinline__ void tri_finish_kernel_body(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
     int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force,
-    int *ctl = nullptr, double tau = 0.0) {
+    int *ctl = nullptr, double tau = 0.0, double *U1 = nullptr) {
   if (!force && *flag == 0 &&
-      tri_finish_part<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, ctl, tau))
+      tri_finish_part<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, ctl, tau,
+                         U1))
     return;
   __syncthreads();
   jacobi_eig_kernel_body(Gin, lam_out, U_out, n, nullptr, nullptr);
   __syncthreads();
   trunc_factors_kernel_body<T>(lam_out, U_out, n, k, P, S, tail, nullptr);
+  __shared__ int s_second;
   if (threadIdx.x == 0) {
     *flag = 1;
+    s_second = 0;
     if (ctl) {
       int w = 0;
       const double thr = tau * lam_out[0];
@@ -664,17 +729,22 @@ __device__ __forceinline__ void tri_finish_kernel_body(
       ctl[1] = w;
       ctl[2] = 0;
       ctl[3] = n;
+      s_second = ctl[0];
     }
   }
+  __syncthreads();
+  // the Jacobi eigenvectors are a full orthonormal basis already
+  if (s_second)
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) U1[e] = U_out[e];
 }
 
 template <typename T>
 __global__ __launch_bounds__(kTeThreads) void tri_finish_kernel(
     const double *Gin, const double *lamw, const double *Ug, const double *scp, int n, int k,
     int kw, double *lam_out, double *U_out, T *P, T *S, double *tail, int *flag, int force,
-    int *ctl, double tau) {
+    int *ctl, double tau, double *U1) {
   tri_finish_kernel_body<T>(Gin, lamw, Ug, scp, n, k, kw, lam_out, U_out, P, S, tail, flag,
-                            force, ctl, tau);
+                            force, ctl, tau, U1);
 }
 
 template <int NMAX>
@@ -712,7 +782,8 @@ static size_t finish_lds(int n) {
 
 template <typename T>
 int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *P, T *S,
-              double *tail, int *flag, double *scratch, hipStream_t s, int *ctl, double tau) {
+              double *tail, int *flag, double *scratch, hipStream_t s, int *ctl, double tau,
+              double *U1) {
   if (n > TT_MAX_SKETCH_RANK) return fail(TT_EUNSUPPORTED, "eigenproblem larger than the limit");
   if (k < 1 || k > n) return fail(TT_EINVAL, "truncation rank out of range");
   if (n <= kTeNMax) {
@@ -742,21 +813,23 @@ int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *
     TTR_HIP(hipGetLastError());
     hipLaunchKernelGGL((tri_finish_kernel<T>), dim3(1), dim3(kTeThreads), finish_lds((int)n), s, G,
                        lamw, Uz, sc, (int)n, (int)k, kw, lam, U, P, S, tail, flag, g_eig_mode,
-                       ctl, tau);
+                       ctl, tau, U1);
     TTR_HIP(hipGetLastError());
     return TT_OK;
   }
   TTR_TRY(sym_eig(G, lam, U, n, s, nullptr, nullptr));
-  if (ctl) TTR_TRY(trunc_refine_ctl(lam, n, k, tau, ctl, s));
+  if (ctl) TTR_TRY(trunc_refine_ctl(lam, U, n, k, tau, ctl, U1, s));
   return trunc_factors<T>(lam, U, n, k, P, S, tail, s, nullptr);
 }
 
 size_t eig_trunc_scratch(int64_t n, int64_t k) { return (size_t)(4 * n + 2 + n * n + n * k); }
 
 template int eig_trunc<double>(const double *, int64_t, int64_t, double *, double *, double *,
-                               double *, double *, int *, double *, hipStream_t, int *, double);
+                               double *, double *, int *, double *, hipStream_t, int *, double,
+                               double *);
 template int eig_trunc<float>(const double *, int64_t, int64_t, double *, double *, float *,
-                              float *, double *, int *, double *, hipStream_t, int *, double);
+                              float *, double *, int *, double *, hipStream_t, int *, double,
+                              double *);
 
 bool eig_group_desc(const double *G, int64_t n, int64_t k, double *lam, double *U, void *P,
                     void *S, double *tail, int *flag, double *scratch, EigGroupDesc *d) {

@@ -15,8 +15,8 @@
 // recovers that accuracy with two more contractions of H:
 //   1. U1 = [U_s | U_w]: U_s the w eigenvectors of the first pass above
 //      tau lambda_1 (accurate, separated from the rest), U_w an orthonormal
-//      basis of their complement (Householder QR of U_s, Q formed explicitly)
-//      .................................................. trunc_basis_kernel
+//      basis of their complement (Householder QR of U_s, Q formed explicitly;
+//      built by the first pass's finish kernel, tri_eig.hip)
 //   2. B = U1^T H (GEMM) and G2 = B B^T (FP64 Gram of B): the weak rows of B
 //      are formed and multiplied at their own scale
 //   3. eigenpairs of the weak block G2[w:, w:] (cyclic Jacobi, absolute
@@ -29,7 +29,7 @@
 //      Kept directions at the rounding level of B (no information left in
 //      them) get zero rows of F and columns of P, and the core receives
 //      orthonormal rows orthogonal to the others in their place
-//      ........................................... trunc_complete_kernel
+//      ............................. trunc_complete_prep/_rows_kernel
 // ctl[0] (1 = run this pass), ctl[1] = w and ctl[3] = the leading dimension
 // of the first pass's eigenvector array are written by the first pass; every
 // kernel here and the GEMMs of steps 2 and 4 return at once when ctl[0] = 0.
@@ -42,76 +42,12 @@
 namespace ttr {
 namespace {
 
-constexpr int kBasisThreads = 256;
 constexpr int kRefMaxN = TT_MAX_SKETCH_RANK;
 
-// U1 (n x n, row-major) = Q of the full Householder QR of U[:, :w] (U with
-// leading dimension ctl[3]); Q's first w columns are +-U[:, :w].
-__global__ __launch_bounds__(kBasisThreads) void trunc_basis_kernel(const double *U, int n,
-                                                                    const int *ctl, double *U1) {
-  if (ctl[0] == 0) return;
-  const int w = ctl[1], ldu = ctl[3];
-  // A (n x w, row stride kRefMaxN + 1): columns of U; reflector j below row j
-  extern __shared__ double lds_basis[];
-  auto A = [&](int i, int j) -> double & { return lds_basis[i * (kRefMaxN + 1) + j]; };
-  __shared__ double s_tau[kRefMaxN], s_dot[kRefMaxN];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * w; e += blockDim.x) {
-    const int i = e / w, j = e - i * w;
-    A(i, j) = U[i * ldu + j];
-  }
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    // reflector H_j = I - tau v v^T with v = x - alpha e_j, x = A[j:, j]
-    if (tid == 0) {
-      double nrm2 = 0.0;
-      for (int i = j; i < n; ++i) nrm2 += A(i, j) * A(i, j);
-      const double x0 = A(j, j);
-      const double nrm = sqrt(nrm2);
-      const double alpha = x0 >= 0.0 ? -nrm : nrm;
-      const double v0 = x0 - alpha;
-      const double vv = nrm2 - x0 * x0 + v0 * v0;
-      s_tau[j] = vv > 0.0 ? 2.0 / vv : 0.0;
-      A(j, j) = v0;  // the reflector occupies column j from row j on
-    }
-    __syncthreads();
-    // A[j:, c] -= tau v (v^T A[j:, c]) for the remaining columns
-    for (int c = j + 1 + tid; c < w; c += blockDim.x) {
-      double d = 0.0;
-      for (int i = j; i < n; ++i) d += A(i, j) * A(i, c);
-      s_dot[c] = d;
-    }
-    __syncthreads();
-    for (int e = tid; e < (n - j) * (w - j - 1); e += blockDim.x) {
-      const int i = j + e / (w - j - 1), c = j + 1 + e % (w - j - 1);
-      A(i, c) -= s_tau[j] * A(i, j) * s_dot[c];
-    }
-    __syncthreads();
-  }
-  // Q = H_0 H_1 ... H_{w-1} I, applied from the last reflector
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, c = e - i * n;
-    U1[e] = (i == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = w - 1; j >= 0; --j) {
-    for (int c = tid; c < n; c += blockDim.x) {
-      double d = 0.0;
-      for (int i = j; i < n; ++i) d += A(i, j) * U1[i * n + c];
-      s_dot[c] = d;
-    }
-    __syncthreads();
-    for (int e = tid; e < (n - j) * n; e += blockDim.x) {
-      const int i = j + e / n, c = e % n;
-      U1[i * n + c] -= s_tau[j] * A(i, j) * s_dot[c];
-    }
-    __syncthreads();
-  }
-}
-
-// Steps 3 of the header.  scratch: gw (n*n), lam2 (n), U2 (n*n), M1 (n*k),
-// Li (k*k), Q2 (n*k) doubles.  F (k x n) and P (n x k) are written in the
-// storage type T.  Dynamic LDS: the Jacobi solve's, at least (k*(k+1)) doubles.
+// Step 3 of the header.  scratch: gw (n*n), lam2 (n), U2 (n*n), M1 (n*k),
+// Q2 (n*k) doubles.  F (k x n) and P (n x k) are written in the storage type
+// T.  Dynamic LDS: the Jacobi solve's, at least k (2k + 1) doubles (the
+// Cholesky factor and its inverse).
 constexpr double kNullRel = 1e-26;
 
 template <typename T>
@@ -124,7 +60,7 @@ __global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *
   const int w = ctl[1];
   const int nw = n - w;
   double *gw = scratch, *lam2 = gw + n * n, *U2 = lam2 + n, *M1 = U2 + n * n;
-  double *Li = M1 + n * k, *Q2 = Li + k * k;
+  double *Q2 = M1 + n * k;
   const int tid = threadIdx.x;
   for (int e = tid; e < nw * nw; e += blockDim.x) {
     const int i = e / nw, j = e - i * nw;
@@ -152,7 +88,7 @@ __global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *
   __syncthreads();
   // Gt = T^T M1 (k x k) into LDS, ld k + 1
   const int ldl = k + 1;
-  double *L = lds;
+  double *L = lds, *Li = lds + k * ldl;  // Li: k x k, leading dimension k
   for (int e = tid; e < k * k; e += blockDim.x) {
     const int a = e / k, b = e - a * k;
     double acc = 0.0;
@@ -240,148 +176,183 @@ __global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *
   if (tid == 0) ctl[2] = s_null;
 }
 
-// Null rows of the new core C (k x cols; nullmask[j] = 1, the row is zero)
-// receive orthonormal rows orthogonal to the others: pseudo-random rows X
-// (a SplitMix64 hash of row and column, uniform in [-1, 1)), projected twice
-// on the orthogonal complement of C's rows (X <- X - (X C^T) C), then
-// orthonormalised among themselves (Cholesky of X X^T).  X lives in xs
-// (k x cols, storage T); sc holds 2 k^2 doubles.
-__device__ __forceinline__ double hash_unit(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return (double)(z >> 11) * 0x1.0p-52 - 1.0;
-}
-
+// Null rows of the new core C (k x cols, row-major; nullmask[j] = 1 marks a
+// zero row) receive orthonormal rows orthogonal to the others.  The good
+// rows are orthonormal, so for a unit vector e_i the residual
+// r = e_i - C^T C e_i = e_i - sum_j C(j, i) C_j is orthogonal to them with
+// no dot products to form, and |r|^2 = 1 - |C(:, i)|^2.  The first kernel
+// (one workgroup) takes the m columns i of smallest |C(:, i)| (their squares
+// sum to the number of good rows over cols >= k columns), forms the m x m
+// Gram of the residuals, delta_ab - C(:, i_a) .
+// C(:, i_b), its Cholesky factor L, and the coefficients W = L^-1 A,
+// A(a, j) = C(j, i_a); the second writes row a of the completion
+// sum_b L^-1(a, b) e_{i_b} - sum_j W(a, j) C_j, one column per thread.
+// sc: trunc_complete_scratch(k, cols) doubles.
 constexpr int kCompThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kCompThreads) void trunc_complete_kernel(T *C, int k, int64_t cols,
-                                                                      const int *ctl,
-                                                                      const int *nullmask, T *xs,
-                                                                      double *sc) {
+__global__ __launch_bounds__(kCompThreads) void trunc_complete_prep_kernel(
+    const T *C, int k, int64_t cols, const int *ctl, const int *nullmask, double *sc) {
   if (ctl[0] == 0 || ctl[2] == 0) return;
-  __shared__ int s_rows[kRefMaxN];
-  __shared__ int s_m;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nwaves = kCompThreads / 64;
-  if (tid == 0) {
-    int m = 0;
-    for (int j = 0; j < k; ++j)
-      if (nullmask[j]) s_rows[m++] = j;
-    s_m = m;
+  const int m = ctl[2];
+  double *cn = sc;                        // cols: squared column norms of the good rows
+  double *Li = cn + cols;                 // m x m
+  double *W = Li + m * m;                 // m x k
+  int *sel = reinterpret_cast<int *>(W + m * k);
+  double *s_g = W + m * k + m;            // m x m: the residuals' Gram, then its factor
+  __shared__ int s_sel[kRefMaxN];
+  const int tid = threadIdx.x;
+  for (int64_t c = tid; c < cols; c += kCompThreads) {
+    double a = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double v = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + c];
+      a += v * v;
+    }
+    cn[c] = a;
   }
   __syncthreads();
-  const int m = s_m;
-  double *coef = sc, *gx = sc + k * k;
-  for (int64_t e = tid; e < (int64_t)m * cols; e += kCompThreads) {
-    const int a = (int)(e / cols);
-    const int64_t c = e - (int64_t)a * cols;
-    xs[e] = (T)hash_unit(((uint64_t)s_rows[a] << 40) ^ (uint64_t)c);
-  }
-  __syncthreads();
-  for (int round = 0; round < 2; ++round) {
-    // coef(a, i) = X_a . C_i, one wavefront per pair
-    for (int pr = wave; pr < m * k; pr += nwaves) {
-      const int a = pr / k, i = pr - a * k;
-      double acc = 0.0;
-      for (int64_t c = lane; c < cols; c += 64)
-        acc += (double)xs[(int64_t)a * cols + c] * (double)C[(int64_t)i * cols + c];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      if (lane == 0) coef[a * k + i] = acc;
+  // the m columns of smallest norm, one block-wide argmin per pick (ties to
+  // the lower column)
+  __shared__ double s_bv[kCompThreads / 64];
+  __shared__ int64_t s_bi[kCompThreads / 64];
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int a = 0; a < m; ++a) {
+    double bv = 1e300;
+    int64_t bi = cols;
+    for (int64_t c = tid; c < cols; c += kCompThreads)
+      if (cn[c] < bv) {
+        bv = cn[c];
+        bi = c;
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int64_t oi = __shfl_xor(bi, off);
+      if (ov < bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_bv[wave] = bv;
+      s_bi[wave] = bi;
     }
     __syncthreads();
-    for (int64_t e = tid; e < (int64_t)m * cols; e += kCompThreads) {
-      const int a = (int)(e / cols);
-      const int64_t c = e - (int64_t)a * cols;
-      double x = (double)xs[e];
-      for (int i = 0; i < k; ++i) x -= coef[a * k + i] * (double)C[(int64_t)i * cols + c];
-      xs[e] = (T)x;
+    if (tid == 0) {
+      for (int w2 = 1; w2 < kCompThreads / 64; ++w2)
+        if (s_bv[w2] < s_bv[0] || (s_bv[w2] == s_bv[0] && s_bi[w2] < s_bi[0])) {
+          s_bv[0] = s_bv[w2];
+          s_bi[0] = s_bi[w2];
+        }
+      s_sel[a] = (int)s_bi[0];
+      cn[s_bi[0]] = 1e300;
     }
     __syncthreads();
   }
-  // X X^T = L L^T, X <- L^-1 X, written into the null rows of C
-  for (int pr = wave; pr < m * m; pr += nwaves) {
-    const int a = pr / m, b = pr - a * m;
-    double acc = 0.0;
-    if (b <= a) {
-      for (int64_t c = lane; c < cols; c += 64)
-        acc += (double)xs[(int64_t)a * cols + c] * (double)xs[(int64_t)b * cols + c];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  // Gram of the residuals, then its Cholesky factor in place (lower)
+  for (int e = tid; e < m * m; e += kCompThreads) {
+    const int a = e / m, b = e - a * m;
+    double g = (a == b) ? 1.0 : 0.0;
+    for (int j = 0; j < k; ++j) {
+      if (nullmask[j]) continue;
+      g -= (double)C[(int64_t)j * cols + s_sel[a]] * (double)C[(int64_t)j * cols + s_sel[b]];
     }
-    if (lane == 0 && b <= a) gx[a * m + b] = acc;
+    s_g[a * m + b] = g;
   }
   __syncthreads();
   if (tid == 0) {
     for (int j = 0; j < m; ++j) {
-      double d = gx[j * m + j];
-      for (int p = 0; p < j; ++p) d -= gx[j * m + p] * gx[j * m + p];
+      double d = s_g[j * m + j];
+      for (int p = 0; p < j; ++p) d -= s_g[j * m + p] * s_g[j * m + p];
       const double ljj = sqrt(fmax(d, 1e-300));
-      gx[j * m + j] = ljj;
+      s_g[j * m + j] = ljj;
       for (int i = j + 1; i < m; ++i) {
-        double v = gx[i * m + j];
-        for (int p = 0; p < j; ++p) v -= gx[i * m + p] * gx[j * m + p];
-        gx[i * m + j] = v / ljj;
+        double v = s_g[i * m + j];
+        for (int p = 0; p < j; ++p) v -= s_g[i * m + p] * s_g[j * m + p];
+        s_g[i * m + j] = v / ljj;
       }
     }
-    // invert in place into coef (lower triangular)
     for (int c = 0; c < m; ++c)
       for (int i = 0; i < m; ++i) {
         double acc = (i == c) ? 1.0 : 0.0;
-        for (int p = c; p < i; ++p) acc -= gx[i * m + p] * coef[p * m + c];
-        coef[i * m + c] = (i < c) ? 0.0 : acc / gx[i * m + i];
+        for (int p = c; p < i; ++p) acc -= s_g[i * m + p] * Li[p * m + c];
+        Li[i * m + c] = (i < c) ? 0.0 : acc / s_g[i * m + i];
       }
   }
   __syncthreads();
-  for (int64_t e = tid; e < (int64_t)m * cols; e += kCompThreads) {
-    const int a = (int)(e / cols);
-    const int64_t c = e - (int64_t)a * cols;
-    double x = 0.0;
-    for (int b = 0; b <= a; ++b) x += coef[a * m + b] * (double)xs[(int64_t)b * cols + c];
-    C[(int64_t)s_rows[a] * cols + c] = (T)x;
+  // W = Li A, A(a, j) = C(j, sel_a) over the good rows
+  for (int e = tid; e < m * k; e += kCompThreads) {
+    const int a = e / k, j = e - a * k;
+    double w = 0.0;
+    if (!nullmask[j])
+      for (int b = 0; b <= a; ++b) w += Li[a * m + b] * (double)C[(int64_t)j * cols + s_sel[b]];
+    W[e] = w;
+  }
+  for (int a = tid; a < m; a += kCompThreads) sel[a] = s_sel[a];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trunc_complete_rows_kernel(T *C, int k, int64_t cols,
+                                                                  const int *ctl,
+                                                                  const int *nullmask,
+                                                                  const double *sc) {
+  if (ctl[0] == 0 || ctl[2] == 0) return;
+  const int m = ctl[2];
+  const double *Li = sc + cols, *W = Li + m * m;
+  const int *sel = reinterpret_cast<const int *>(W + m * k);
+  __shared__ int s_rows[kRefMaxN];
+  if (threadIdx.x == 0) {
+    int a = 0;
+    for (int j = 0; j < k; ++j)
+      if (nullmask[j]) s_rows[a++] = j;
+  }
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double col[kRefMaxN];
+  for (int j = 0; j < k; ++j) col[j] = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + c];
+  for (int a = 0; a < m; ++a) {
+    double v = 0.0;
+    for (int b = 0; b <= a; ++b)
+      if (sel[b] == c) v += Li[a * m + b];
+    for (int j = 0; j < k; ++j) v -= W[a * k + j] * col[j];
+    C[(int64_t)s_rows[a] * cols + c] = (T)v;
   }
 }
 
-// ctl of the first pass from descending eigenvalues lam (for the solver
-// branch that has no split logic of its own); U's leading dimension is n
-__global__ void trunc_ctl_kernel(const double *lam, int n, int k, double tau, int *ctl) {
-  if (threadIdx.x != 0) return;
-  int w = 0;
-  const double thr = tau * lam[0];
-  while (w < k && lam[w] >= thr) ++w;
-  ctl[0] = (tau > 0.0 && w < k) ? 1 : 0;
-  ctl[1] = w;
-  ctl[2] = 0;
-  ctl[3] = n;
+// ctl of the first pass from descending eigenvalues lam and the full
+// eigenvector matrix U (n x n) of the solver branch that has no split logic
+// of its own; U1 = U (already a full orthonormal basis) when the second pass
+// runs
+__global__ void trunc_ctl_kernel(const double *lam, const double *U, int n, int k, double tau,
+                                 int *ctl, double *U1) {
+  __shared__ int s_second;
+  if (threadIdx.x == 0) {
+    int w = 0;
+    const double thr = tau * lam[0];
+    while (w < k && lam[w] >= thr) ++w;
+    ctl[0] = (tau > 0.0 && w > 0 && w < k) ? 1 : 0;
+    ctl[1] = w;
+    ctl[2] = 0;
+    ctl[3] = n;
+    s_second = ctl[0];
+  }
+  __syncthreads();
+  if (s_second)
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) U1[e] = U[e];
 }
 
 }  // namespace
 
-int trunc_refine_ctl(const double *lam, int64_t n, int64_t k, double tau, int *ctl,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(trunc_ctl_kernel, dim3(1), dim3(64), 0, s, lam, (int)n, (int)k, tau, ctl);
+int trunc_refine_ctl(const double *lam, const double *U, int64_t n, int64_t k, double tau,
+                     int *ctl, double *U1, hipStream_t s) {
+  hipLaunchKernelGGL(trunc_ctl_kernel, dim3(1), dim3(256), 0, s, lam, U, (int)n, (int)k, tau, ctl,
+                     U1);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 
 size_t trunc_refine_scratch(int64_t n, int64_t k) {
-  return (size_t)(n * n + n + n * n + n * k + k * k + n * k);
-}
-
-int trunc_refine_basis(const double *U, int64_t n, const int *ctl, double *U1, hipStream_t s) {
-  if (n > kRefMaxN) return fail(TT_EUNSUPPORTED, "refinement larger than the limit");
-  const size_t lds = sizeof(double) * (size_t)n * (kRefMaxN + 1);
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)trunc_basis_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(trunc_basis_kernel, dim3(1), dim3(kBasisThreads), lds, s, U, (int)n, ctl,
-                     U1);
-  TTR_HIP(hipGetLastError());
-  return TT_OK;
+  return (size_t)(n * n + n + n * n + n * k + n * k + 2 * k * k);
 }
 
 template <typename T>
@@ -390,7 +361,7 @@ int trunc_refine_solve(const double *G2, const double *U1, int64_t n, int64_t k,
   if (n > kRefMaxN || k < 1 || k > n) return fail(TT_EINVAL, "internal: refinement shape");
   const int np = (int)((n + 1) & ~1);
   const size_t lds = std::max<size_t>(2 * sizeof(double) * (size_t)np * (size_t)(np + 1),
-                                      sizeof(double) * (size_t)k * (size_t)(k + 1));
+                                      sizeof(double) * (size_t)k * (size_t)(2 * k + 1));
   static bool attr_set = false;
   if (!attr_set) {
     TTR_HIP(hipFuncSetAttribute((const void *)trunc_solve_kernel<T>,
@@ -405,17 +376,23 @@ int trunc_refine_solve(const double *G2, const double *U1, int64_t n, int64_t k,
 
 template <typename T>
 int trunc_refine_complete(T *C, int64_t k, int64_t cols, const int *ctl, const int *nullmask,
-                          T *xs, double *scratch, hipStream_t s) {
-  if (k > kRefMaxN) return fail(TT_EINVAL, "internal: completion shape");
-  hipLaunchKernelGGL((trunc_complete_kernel<T>), dim3(1), dim3(kCompThreads), 0, s, C, (int)k,
-                     cols, ctl, nullmask, xs, scratch);
+                          double *scratch, hipStream_t s) {
+  if (k > kRefMaxN || cols < k) return fail(TT_EINVAL, "internal: completion shape");
+  hipLaunchKernelGGL((trunc_complete_prep_kernel<T>), dim3(1), dim3(kCompThreads), 0, s, C,
+                     (int)k, cols, ctl, nullmask, scratch);
+  TTR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((trunc_complete_rows_kernel<T>), dim3((unsigned)((cols + 255) / 256)),
+                     dim3(256), 0, s, C, (int)k, cols, ctl, nullmask, scratch);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 template int trunc_refine_complete<double>(double *, int64_t, int64_t, const int *, const int *,
-                                           double *, double *, hipStream_t);
+                                           double *, hipStream_t);
 template int trunc_refine_complete<float>(float *, int64_t, int64_t, const int *, const int *,
-                                          float *, double *, hipStream_t);
+                                          double *, hipStream_t);
+size_t trunc_complete_scratch(int64_t k, int64_t cols) {
+  return (size_t)(cols + 2 * k * k + k * k + 2 * k);
+}
 
 template int trunc_refine_solve<double>(const double *, const double *, int64_t, int64_t, int *,
                                         int *, double *, double *, double *, hipStream_t);

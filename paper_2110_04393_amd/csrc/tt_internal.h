@@ -102,6 +102,10 @@ struct GemmX {
   // (*gate != 0) == (gate_on != 0) (decided on the device, no host sync)
   const int *gate = nullptr;
   int gate_on = 1;
+  // device operand selection: with `sel` set and *sel != 0 the product reads
+  // A2 and B2 (same types, shapes and layouts) instead of A and B
+  const int *sel = nullptr;
+  const void *A2 = nullptr, *B2 = nullptr;
 };
 __device__ inline bool gemm_gated_off(const GemmX &g) {
   return g.gate && ((*g.gate != 0) != (g.gate_on != 0));
@@ -368,34 +372,35 @@ int trunc_factors(const double *lam, const double *U, int64_t n, int64_t k, T *P
 // need the second pass of trunc_refine_*: ctl[0] = 1 when the smallest kept
 // eigenvalue is below tau times the largest, ctl[1] = the number w of kept
 // eigenvalues at or above that level (only their eigenvectors are then
-// checked and returned accurately), ctl[3] = the leading dimension of U.
+// checked and returned accurately), ctl[3] = the leading dimension of U,
+// and when ctl[0] = 1 it writes U1 (n x n): an orthonormal basis whose first
+// ctl[1] columns are those eigenvectors and the rest their complement.
 template <typename T>
 int eig_trunc(const double *G, int64_t n, int64_t k, double *lam, double *U, T *P, T *S,
               double *tail, int *flag, double *scratch, hipStream_t s, int *ctl = nullptr,
-              double tau = 0.0);
+              double tau = 0.0, double *U1 = nullptr);
 size_t eig_trunc_scratch(int64_t n, int64_t k);
 
 // Second pass of the truncation at one bond (kernels return at once unless
-// ctl[0] = 1): U1 = an orthonormal basis whose first ctl[1] columns are those
-// of U (ld ctl[3]) and the rest their complement; after the caller has formed
-// B = U1^T H and G2 = B B^T (FP64), trunc_refine_solve writes F (k x n) and
+// ctl[0] = 1): after the caller has formed B = U1^T H and G2 = B B^T (FP64)
+// from eig_trunc's U1, trunc_refine_solve writes F (k x n) and
 // P (n x k) with F B orthonormal rows spanning the k leading right singular
 // directions of H and P F B = H projected onto them; kept directions at the
 // rounding level of B get zero rows of F and zero columns of P, nullmask[j]
 // = 1 and ctl[2] = their count; trunc_refine_complete then writes
-// orthonormal rows into those rows of the core C = F B (xs: k x cols
-// elements of T, scratch: 2 k^2 doubles).  scratch of the solve:
+// orthonormal rows into those rows of the core C = F B (cols >= k;
+// scratch: trunc_complete_scratch doubles).  scratch of the solve:
 // trunc_refine_scratch doubles.  n <= TT_MAX_SKETCH_RANK.
-int trunc_refine_basis(const double *U, int64_t n, const int *ctl, double *U1, hipStream_t s);
 template <typename T>
 int trunc_refine_solve(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
                        int *nullmask, double *scratch, T *F, T *P, hipStream_t s);
 template <typename T>
 int trunc_refine_complete(T *C, int64_t k, int64_t cols, const int *ctl, const int *nullmask,
-                          T *xs, double *scratch, hipStream_t s);
+                          double *scratch, hipStream_t s);
+size_t trunc_complete_scratch(int64_t k, int64_t cols);
 size_t trunc_refine_scratch(int64_t n, int64_t k);
-int trunc_refine_ctl(const double *lam, int64_t n, int64_t k, double tau, int *ctl,
-                     hipStream_t s);
+int trunc_refine_ctl(const double *lam, const double *U, int64_t n, int64_t k, double tau,
+                     int *ctl, double *U1, hipStream_t s);
 
 struct EigGroupDesc {
   const double *G;
