@@ -17,7 +17,8 @@ rounding in the Tensor-Train format") step by step in its notation:
 * Two-Sided-Randomization (generalized Nystrom) ..... Algorithm 6, eq. (LnRn)
 * rounding a sum, Randomize-then-Orthogonalize ...... Algorithm 7
 * truncation of the left-orthogonal RtO output ...... section 3.2 (remark after
-  Algorithm 5), run as the right-to-left mirror of Algorithm 2
+  Algorithm 5), run as the right-to-left mirror of Algorithm 2; to fixed ranks
+  or to a tolerance (ranks not known in advance)
 
 Readings taken where the paper is silent (each also listed in the design notes):
 
@@ -327,6 +328,47 @@ def round_rand(Y, target, oversample=0, seed=None, sketch=None, truncate=True):
     if truncate and any(out_ranks[n] < ell[n] for n in range(N + 1)):
         X, _ = truncate_rl(X, out_ranks)
     return X
+
+
+def truncate_rl_eps(X, eps0, max_rank=None):
+    """Tolerance-driven truncation of a left-orthogonal TT (the section 3.2
+    remark after Algorithm 5: choose the sketch ranks large, then run the
+    truncation loop of Algorithm 2 with its threshold).  ||X|| is the
+    Frobenius norm of the last core (the others are left-orthogonal); with
+    eps = eps0 ||X|| / sqrt(N-1) (Algorithm 2), for n = N .. 2 the SVD of
+    H(X_n) keeps the smallest k >= 1 with sqrt(sum_{j>k} s_j^2) <= eps
+    (capped by max_rank), X_n <- V_k^T, X_{n-1} <- X_{n-1} x_3 (U_k S_k).
+    Then ||X_out - X||^2 = sum of the discarded s_j^2 <= eps0^2 ||X||^2.
+    Returns (cores, ranks, tails)."""
+    X = [np.array(c, dtype=np.float64) for c in X]
+    N = len(X)
+    tails = [0.0] * (N + 1)
+    if N == 1:
+        return X, ranks_of(X), tails
+    eps = eps0 * float(np.linalg.norm(X[-1])) / math.sqrt(N - 1)
+    for n in range(N - 1, 0, -1):
+        U, S, Vt = np.linalg.svd(H(X[n]), full_matrices=False)
+        k = _trunc_rank(S, eps, max_rank)
+        tails[n] = float(np.sum(S[k:] ** 2))
+        X[n] = Vt[:k].reshape(k, X[n].shape[1], X[n].shape[2])
+        prev = X[n - 1]
+        X[n - 1] = (V(prev) @ (U[:, :k] * S[:k])).reshape(prev.shape[0], prev.shape[1], k)
+    return X, ranks_of(X), tails
+
+
+def round_rand_eps(Y, max_rank, eps0, seed=None, sketch=None):
+    """Rounding to a tolerance with ranks not known in advance (section 3.2,
+    remark after Algorithm 5): Randomize-then-Orthogonalize with sketch ranks
+    from plan_ranks(target = max_rank, oversample = 0), then truncate_rl_eps.
+    Returns (cores, ranks, tails)."""
+    X = round_rand(Y, max_rank, 0, seed=seed, sketch=sketch, truncate=False)
+    return truncate_rl_eps(X, eps0)
+
+
+def round_sum_rand_eps(summands, coeffs, max_rank, eps0, seed=None, sketch=None):
+    """The same for a sum of TTs (Algorithm 7, then truncate_rl_eps)."""
+    X = round_sum_rand(summands, coeffs, max_rank, 0, seed=seed, sketch=sketch, truncate=False)
+    return truncate_rl_eps(X, eps0)
 
 
 # ----------------------------------------------------------------------------

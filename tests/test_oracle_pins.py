@@ -582,3 +582,60 @@ def test_two_sided_error_lower_bound():
     for n in range(1, 5):
         s = np.linalg.svd(T.reshape(3 ** n, -1), compute_uv=False)
         assert err >= math.sqrt(float(np.sum(s[2:] ** 2))) * (1 - 1e-12)
+
+
+# ---------------------------------------------------------------- tolerance-driven ranks
+
+def test_truncate_rl_eps_threshold_closed_form():
+    # singular values (1, 1, 1, a) at every bond of a left-orthogonal TT: the
+    # threshold eps = ||X|| eps0 / sqrt(N-1) keeps a exactly when eps < a
+    # (the closed form of the Algorithm 2 pin, from the right)
+    a = 1.2e-3
+    Y = superdiagonal_tt([1.0, 1.0, 1.0, a], 5)
+    X = O.rto_sweep(Y, O.partial_contractions_rl(Y, Y))  # left-orthogonal, exact
+    assert O.rel_diff(X, Y) < 1e-13
+    Z, ranks, tails = O.truncate_rl_eps(X, 1e-3)
+    assert ranks == [1, 4, 4, 4, 4, 1]
+    Z, ranks, tails = O.truncate_rl_eps(X, 2.0 * a * 2 / math.sqrt(3 + a * a))
+    assert ranks == [1, 3, 3, 3, 3, 1]
+    assert sum(tails) == pytest.approx(a * a, rel=1e-10)
+    assert O.rel_diff(Z, X) == pytest.approx(a / math.sqrt(3 + a * a), rel=1e-8)
+
+
+@pytest.mark.parametrize("eps0", [1e-2, 1e-5])
+def test_round_rand_eps_bound_and_dense_tt_svd(eps0):
+    # X1 (rank 3) + 1e-6 X2 (rank 4), sketch rank 9 > 7: RtO is exact to
+    # rounding, the tolerance truncation meets ||X - Xr|| <= eps0 ||Xr|| and
+    # keeps the same ranks as the deterministic TT-SVD with the same eps0
+    Y = G.near_low_rank_tt(7, [5] * 6, 3, 4, 1e-6)
+    Xr = O.round_rand(Y, 9, 0, seed=1, truncate=False)
+    assert O.rel_diff(Xr, Y) < 1e-12
+    X, ranks, tails = O.round_rand_eps(Y, 9, eps0, seed=1)
+    assert O.rel_diff(X, Xr) <= eps0 * (1 + 1e-12)
+    assert math.sqrt(sum(tails)) == pytest.approx(O.rel_diff(X, Xr) * O.tt_norm(Xr), rel=1e-6)
+    D, dranks, _ = O.round_svd(Y, eps0)
+    assert ranks == dranks
+    assert ranks == [1] + [3] * 5 + [1]
+    assert O.rel_diff(X, D) < 1e-5
+    # right-orthogonal cores 2..N
+    for c in X[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-12
+
+
+def test_round_rand_eps_zero_keeps_everything():
+    Y = tiny_tt(3, N=4, I=3, R=3)
+    X, ranks, tails = O.round_rand_eps(Y, 9, 0.0, seed=2)
+    Xr = O.round_rand(Y, 9, 0, seed=2, truncate=False)
+    assert ranks == O.ranks_of(Xr)
+    assert O.rel_diff(X, Xr) < 1e-13
+
+
+def test_round_sum_rand_eps_equals_assembled():
+    A = G.random_tt(11, [4] * 5, [1, 2, 2, 2, 2, 1])
+    B = G.random_tt(12, [4] * 5, [1, 2, 2, 2, 2, 1])
+    S = G.block_sum([A, B, A], [1.0, 0.5, -2.0])
+    X, ranks, _ = O.round_sum_rand_eps([A, B, A], [1.0, 0.5, -2.0], 8, 1e-10, seed=3)
+    Z, zr, _ = O.round_rand_eps(S, 8, 1e-10, seed=3)
+    assert ranks == zr == [1, 4, 4, 4, 4, 1]
+    assert O.rel_diff(X, S) < 1e-12
