@@ -237,6 +237,43 @@ TT_API int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t
                  size_t ws_bytes, void *stream);
 
 /*
+ * Rounding to a tolerance when the ranks are not known in advance (section
+ * 3.2, remark after Algorithm 5): Randomize-then-Orthogonalize (Algorithm 5,
+ * or Algorithm 7 for a sum) with the sketch ranks of tt_round_rand_plan
+ * (target_rank = max_rank, oversample = 0), then the truncation loop of
+ * Algorithm 2 with its threshold, run right to left on the left-orthogonal
+ * result X: eps = eps0 ||X|| / sqrt(N-1) (||X|| = ||X_N||_F); at bond n the
+ * smallest k >= 1 with sqrt(sum_{j>k} s_j^2) <= eps is kept, s_j the
+ * singular values of H(X_{n+1}) (from its FP64 Gram, as tt_round_rand's
+ * truncation).  Then ||X_out - X|| <= eps0 ||X||; how close X is to the
+ * input depends on the sketch ranks being large enough (the paper gives no
+ * a-priori bound).  eps0 = 0 keeps the sketch ranks (no truncation).
+ *   max_rank       the sketch rank l (the largest output rank)
+ *   eps0           in [0, 1)
+ *   out_cores[N]   caller buffers of at least the sketch-rank shapes
+ *                  (tt_round_rand_plan with max_rank, 0); core n is written
+ *                  C-contiguous with the chosen ranks
+ *   out_ranks[N+1] host, written with the chosen ranks
+ * The rank of every bond is read back by the host: the call waits for
+ * `stream` once per bond (eps0 > 0).  Sums: as tt_sum_round.
+ */
+TT_API int tt_round_rand_eps_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                       int64_t max_rank, int32_t prec, size_t *bytes);
+TT_API int tt_round_rand_eps(int32_t N, const int64_t *dims, const int64_t *ranks,
+                             const void *const *cores, int32_t dtype, int64_t max_rank,
+                             double eps0, uint64_t sketch_seed, int32_t prec,
+                             void *const *out_cores, int64_t *out_ranks, void *workspace,
+                             size_t ws_bytes, void *stream);
+TT_API int tt_sum_round_eps_workspace(int32_t s, int32_t N, const int64_t *dims,
+                                      const int64_t *ranks, int64_t max_rank, int32_t prec,
+                                      size_t *bytes);
+TT_API int tt_sum_round_eps(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                            const void *const *cores, const double *coeffs, int32_t dtype,
+                            int64_t max_rank, double eps0, uint64_t sketch_seed, int32_t prec,
+                            void *const *out_cores, int64_t *out_ranks, void *workspace,
+                            size_t ws_bytes, void *stream);
+
+/*
  * Reverse mode (vector-Jacobian product) of tt_round_rand for roundings
  * without truncation (every out rank equals its sketch rank), single TT,
  * sketch fixed by `sketch_seed` (not differentiated).  Algorithm 5 is

@@ -325,6 +325,81 @@ def round_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0, prec
     return [c.clone() for c in p.run(cores, seed=seed, sketch=sketch, stream=stream)]
 
 
+def _narrowed(out, dims, ranks):
+    """Views of the caller-sized output buffers at the ranks the library
+    chose (each core written C-contiguous from the start of its buffer)."""
+    return [out[n].view(-1)[:ranks[n] * dims[n] * ranks[n + 1]].view(ranks[n], dims[n],
+                                                                     ranks[n + 1])
+            for n in range(len(dims))]
+
+
+def round_rand_eps(cores, max_rank: int, eps0: float, seed: int = 0, prec: str = "f64",
+                   stream=None):
+    """Rounding to the tolerance eps0 with sketch ranks up to max_rank
+    (tt_round_rand_eps; section 3.2, remark after Algorithm 5).  Returns the
+    output cores at the chosen ranks."""
+    import ctypes
+    _check_cores(cores)
+    if prec not in _PREC:
+        raise ValueError(f"unknown prec {prec!r}")
+    dims, ranks = _shape_of(cores)
+    N = len(dims)
+    sr, _ = plan(dims, ranks, max_rank, 0)
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_round_rand_eps_workspace(N, L.i64_array(dims), L.i64_array(ranks),
+                                                int(max_rank), _PREC[prec], ctypes.byref(b)))
+    dev = cores[0].device
+    ws = _workspace(b.value, dev)
+    out = [torch.empty((sr[n], dims[n], sr[n + 1]), dtype=cores[0].dtype, device=dev)
+           for n in range(N)]
+    got = L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_round_rand_eps(
+        N, L.i64_array(dims), L.i64_array(ranks), L.ptr_array([c.data_ptr() for c in cores]),
+        _DTYPE[cores[0].dtype], int(max_rank), float(eps0), int(seed) & ((1 << 64) - 1),
+        _PREC[prec], L.ptr_array([c.data_ptr() for c in out]), got,
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+    return _narrowed(out, dims, [got[i] for i in range(N + 1)])
+
+
+def sum_round_eps(summands, coeffs, max_rank: int, eps0: float, seed: int = 0,
+                  prec: str = "f64", stream=None):
+    """Rounding of sum_j coeffs[j] * summands[j] to the tolerance eps0
+    (tt_sum_round_eps).  Returns the output cores at the chosen ranks."""
+    import ctypes
+    if prec not in _PREC:
+        raise ValueError(f"unknown prec {prec!r}")
+    s = len(summands)
+    dims, _ = _shape_of(summands[0])
+    N = len(dims)
+    flat_ranks, ptrs = [], []
+    for t in summands:
+        _check_cores(t)
+        d, r = _shape_of(t)
+        if d != dims:
+            raise ValueError("summands must share mode sizes")
+        flat_ranks += r
+        ptrs += [c.data_ptr() for c in t]
+    formal = [1] + [sum(_shape_of(t)[1][n] for t in summands) for n in range(1, N)] + [1]
+    sr, _ = plan(dims, formal, max_rank, 0)
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_sum_round_eps_workspace(s, N, L.i64_array(dims), L.i64_array(flat_ranks),
+                                               int(max_rank), _PREC[prec], ctypes.byref(b)))
+    dev = summands[0][0].device
+    ws = _workspace(b.value, dev)
+    out = [torch.empty((sr[n], dims[n], sr[n + 1]), dtype=summands[0][0].dtype, device=dev)
+           for n in range(N)]
+    cf = None
+    if coeffs is not None:
+        cf = (ctypes.c_double * s)(*[float(c) for c in coeffs])
+    got = L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_sum_round_eps(
+        s, N, L.i64_array(dims), L.i64_array(flat_ranks), L.ptr_array(ptrs), cf,
+        _DTYPE[summands[0][0].dtype], int(max_rank), float(eps0), int(seed) & ((1 << 64) - 1),
+        _PREC[prec], L.ptr_array([c.data_ptr() for c in out]), got,
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+    return _narrowed(out, dims, [got[i] for i in range(N + 1)])
+
+
 def round_rand_noalloc(cores, target_rank: int, oversample: int = 0, seed: int = 0,
                        prec: str = "f64", out=None, stream=None):
     """Randomize-then-Orthogonalize rounding through tt_round_rand_noalloc

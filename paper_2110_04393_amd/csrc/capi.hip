@@ -368,7 +368,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   // second pass for kept directions far below the largest (FP64 storage)
   const bool refine = P.truncate && sizeof(T) == 8;
   int *ctl = nullptr, *nmask = nullptr;
-  double *U1 = nullptr, *G2 = nullptr, *rscr = nullptr, *cscr = nullptr;
+  double *U1 = nullptr, *G2 = nullptr, *rscr = nullptr, *cscr = nullptr, *lamc = nullptr;
   T *Ff = nullptr, *Bb = nullptr;
   if (refine) {
     int64_t cmax = 1;
@@ -381,6 +381,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     Ff = c.arena.take<T>((size_t)(lm * lm));
     Bb = c.arena.take<T>((size_t)(lm * cmax));
     cscr = c.arena.take<double>(trunc_complete_scratch(lm, cmax));
+    lamc = c.arena.take<double>((size_t)lm);
   }
   if (P.truncate) {
     gbuf = c.arena.take<double>((size_t)(lm * lm));
@@ -485,13 +486,26 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     cur = dst;
   }
 
+  if (P.ranks_out)
+    for (int n = 0; n <= N; ++n) P.ranks_out[n] = P.truncate ? P.out[n] : L[n];
   if (!P.truncate) return TT_OK;
 
-  // ---- right-to-left truncation of the left-orthogonal result
+  // ---- right-to-left truncation of the left-orthogonal result (to the
+  // plan's ranks, or with eps_mode to the smallest ranks meeting the eps rule
+  // of Algorithm 2: eps = eps0 ||X|| / sqrt(N-1), ||X|| = ||X_N||_F since
+  // cores 1..N-1 are left-orthogonal; the rank of each bond is read back)
+  double *dnorm = nullptr;
+  int *dk = nullptr;
+  if (P.eps_mode) {
+    dnorm = c.arena.take<double>(1);
+    dk = c.arena.take<int>((size_t)N + 1);
+    if (!c.dry) TTR_TRY(frob_norm<T>(xs[N], L[N - 1] * dims[N - 1], dnorm, c.s));
+  }
   const T *hsrc = xs[N];
   int64_t rr = 1;  // right rank of the current core
   for (int n = N; n >= 2; --n) {
-    const int64_t lr = L[n - 1], k = P.out[n - 1], cols = dims[n - 1] * rr;
+    const int64_t lr = L[n - 1], kcap = P.out[n - 1], cols = dims[n - 1] * rr;
+    const int64_t keig = P.eps_mode ? lr : kcap;
     if (gram_supported(lr, cols))  // both forms size the split buffer
       c.partial_need = std::max(c.partial_need, gram_partial_elems(lr, cols) * sizeof(double));
     if (gram_enabled(lr, cols)) {
@@ -521,10 +535,10 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
     }
     if (!c.dry)
-      TTR_TRY(eig_trunc<T>(gbuf, lr, k, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s,
+      TTR_TRY(eig_trunc<T>(gbuf, lr, keig, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s,
                            refine ? ctl : nullptr, refine ? kTruncRefineTau : 0.0, U1));
-    if (refine) {
-      // second pass (runs only when ctl[0] = 1, decided on the device)
+    // second pass's contractions (only when ctl[0] = 1, decided on the device)
+    auto refine_contractions = [&]() -> int {
       GemmX b;  // B = U1^T H(X_n)
       b.A = U1;
       b.lda = lr;
@@ -547,26 +561,56 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
         if (!c.dry)
           TTR_TRY(gram_run(Bb, p.store, true, cols, lr, cols, G2, lr, c.partial, c.partial_cap,
                            c.s, ctl));
-      } else {
-        GemmX g;
-        g.A = Bb;
-        g.lda = cols;
-        g.a_kc = true;
-        g.ta = p.store;
-        g.B = Bb;
-        g.ldb = cols;
-        g.b_kc = true;
-        g.tb = p.store;
-        g.C = G2;
-        g.ldc = lr;
-        g.tc = DType::F64;
-        g.M = lr;
-        g.N = lr;
-        g.K = cols;
-        g.math = DType::F64;
-        g.gate = ctl;
-        TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
+        return TT_OK;
       }
+      GemmX g;
+      g.A = Bb;
+      g.lda = cols;
+      g.a_kc = true;
+      g.ta = p.store;
+      g.B = Bb;
+      g.ldb = cols;
+      g.b_kc = true;
+      g.tb = p.store;
+      g.C = G2;
+      g.ldc = lr;
+      g.tc = DType::F64;
+      g.M = lr;
+      g.N = lr;
+      g.K = cols;
+      g.math = DType::F64;
+      g.gate = ctl;
+      return gemm(c, g, TT_SITE_TRUNC);
+    };
+    int64_t k = kcap;
+    if (P.eps_mode) {
+      // the rank from the eps rule; with weak directions present their
+      // eigenvalues come from the second pass (the first resolves them only
+      // to about u lambda_1)
+      const double *lsel = lam;
+      if (refine) {
+        TTR_TRY(refine_contractions());
+        if (!c.dry) TTR_TRY(trunc_refine_eps<T>(G2, U1, lr, ctl, nmask, rscr, lam, lamc, c.s));
+        lsel = lamc;
+      }
+      if (!c.dry) {
+        TTR_TRY(select_rank(lsel, (int)lr, dnorm, P.eps0, N, (int)kcap, dk + n - 1,
+                            tails + n - 1, c.s));
+        int hk = 0;
+        TTR_HIP(hipMemcpyAsync(&hk, dk + n - 1, sizeof(int), hipMemcpyDeviceToHost, c.s));
+        TTR_HIP(hipStreamSynchronize(c.s));
+        if (hk < 1 || hk > kcap) return fail(TT_ENUMERIC, "tolerance rounding: invalid rank");
+        k = hk;
+        if (k < keig) {  // first-pass factors of the chosen rank (tail kept from the rule)
+          TTR_TRY(trunc_factors<T>(lam, U, lr, k, Pf, Sf, escr, c.s));
+          if (refine) TTR_TRY(trunc_refine_setk(ctl, k, c.s));
+        }
+        if (refine) TTR_TRY(trunc_refine_final<T>(G2, U1, lr, k, ctl, nmask, rscr, Ff, Pf, c.s));
+      }
+    }
+    if (P.ranks_out) P.ranks_out[n - 1] = k;
+    if (refine && !P.eps_mode) {
+      TTR_TRY(refine_contractions());
       if (!c.dry) TTR_TRY(trunc_refine_solve<T>(G2, U1, lr, k, ctl, nmask, rscr, Ff, Pf, c.s));
     }
     // new core: H(X_n) <- s^-1 U^T H(X_n) (first pass), or F B when the
@@ -1304,11 +1348,16 @@ int tt_round_rand_workspace(int32_t N, const int64_t *dims, const int64_t *ranks
   return tt_sum_round_workspace(1, N, dims, ranks, target_rank, oversample, prec, bytes);
 }
 
-int tt_sum_round_workspace(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
-                           int64_t target_rank, int64_t oversample, int32_t prec,
-                           size_t *bytes) {
+static int sum_round_workspace_mode(int32_t s, int32_t N, const int64_t *dims,
+                                    const int64_t *ranks, int64_t target_rank,
+                                    int64_t oversample, int32_t prec, bool eps_mode,
+                                    size_t *bytes) {
   Problem P;
   TTR_TRY(make_problem(P, s, N, dims, ranks, target_rank, oversample, nullptr));
+  if (eps_mode) {
+    P.eps_mode = true;
+    P.truncate = true;
+  }
   Prec pc;
   TTR_TRY(prec_cfg(prec, pc));
   if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
@@ -1331,6 +1380,19 @@ int tt_sum_round_workspace(int32_t s, int32_t N, const int64_t *dims, const int6
         return round_exec<float>(c, P, pc, Y.data(), (const void *const *)Sk.data(), out.data());
       },
       bytes);
+}
+int tt_sum_round_workspace(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                           int64_t target_rank, int64_t oversample, int32_t prec,
+                           size_t *bytes) {
+  return sum_round_workspace_mode(s, N, dims, ranks, target_rank, oversample, prec, false, bytes);
+}
+int tt_sum_round_eps_workspace(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                               int64_t max_rank, int32_t prec, size_t *bytes) {
+  return sum_round_workspace_mode(s, N, dims, ranks, max_rank, 0, prec, true, bytes);
+}
+int tt_round_rand_eps_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                int64_t max_rank, int32_t prec, size_t *bytes) {
+  return sum_round_workspace_mode(1, N, dims, ranks, max_rank, 0, prec, true, bytes);
 }
 
 int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims, const int64_t *sketch_ranks,
@@ -1387,15 +1449,32 @@ int round_typed(const Problem &P, const Prec &pc, const void *const *cores, bool
   });
 }
 
+// with eps0 >= 0: tolerance-driven rounding (target_rank = the largest rank
+// l, no oversampling; the ranks chosen go to ranks_out)
+void set_eps_mode(Problem &P, double eps0, int64_t *ranks_out) {
+  P.eps_mode = eps0 > 0.0;
+  P.eps0 = eps0;
+  P.truncate = P.eps_mode;
+  P.ranks_out = ranks_out;
+}
+
 int round_common(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
                         const void *const *cores, const double *coeffs, int32_t dtype,
                         int64_t target_rank, int64_t oversample, bool gen, uint64_t seed,
                         const int64_t *sketch_ranks, const void *const *sketch_cores,
                         int32_t prec, void *const *out_cores, void *workspace, size_t ws_bytes,
-                        void *stream) {
+                        void *stream, double eps0 = -1.0, int64_t *ranks_out = nullptr) {
   read_env();
   Problem P;
   TTR_TRY(make_problem(P, s, N, dims, ranks, target_rank, oversample, coeffs));
+  if (eps0 >= 0.0) {
+    if (!(eps0 < 1.0)) return fail(TT_EINVAL, "eps0 must lie in [0, 1)");
+    if (!ranks_out) return fail(TT_EINVAL, "null out_ranks");
+    set_eps_mode(P, eps0, ranks_out);
+    if (N == 1) {
+      ranks_out[0] = ranks_out[1] = 1;
+    }
+  }
   Prec pc;
   TTR_TRY(prec_cfg(prec, pc));
   TTR_TRY(check_dtype(dtype, pc));
@@ -1609,6 +1688,25 @@ int tt_sum_round(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks
   return round_common(s, N, dims, ranks, cores, coeffs, dtype, target_rank, oversample, true,
                       sketch_seed, nullptr, nullptr, prec, out_cores, workspace, ws_bytes,
                       stream);
+}
+
+int tt_round_rand_eps(int32_t N, const int64_t *dims, const int64_t *ranks,
+                      const void *const *cores, int32_t dtype, int64_t max_rank, double eps0,
+                      uint64_t sketch_seed, int32_t prec, void *const *out_cores,
+                      int64_t *out_ranks, void *workspace, size_t ws_bytes, void *stream) {
+  return round_common(1, N, dims, ranks, cores, nullptr, dtype, max_rank, 0, true, sketch_seed,
+                      nullptr, nullptr, prec, out_cores, workspace, ws_bytes, stream, eps0,
+                      out_ranks);
+}
+
+int tt_sum_round_eps(int32_t s, int32_t N, const int64_t *dims, const int64_t *ranks,
+                     const void *const *cores, const double *coeffs, int32_t dtype,
+                     int64_t max_rank, double eps0, uint64_t sketch_seed, int32_t prec,
+                     void *const *out_cores, int64_t *out_ranks, void *workspace,
+                     size_t ws_bytes, void *stream) {
+  return round_common(s, N, dims, ranks, cores, coeffs, dtype, max_rank, 0, true, sketch_seed,
+                      nullptr, nullptr, prec, out_cores, workspace, ws_bytes, stream, eps0,
+                      out_ranks);
 }
 
 int tt_round_svd_plan(int32_t N, const int64_t *dims, const int64_t *ranks, int64_t max_rank,

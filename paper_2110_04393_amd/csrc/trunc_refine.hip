@@ -50,25 +50,32 @@ constexpr int kRefMaxN = TT_MAX_SKETCH_RANK;
 // Cholesky factor and its inverse).
 constexpr double kNullRel = 1e-26;
 
-template <typename T>
-__global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *G2,
-                                                                  const double *U1, int n, int k,
-                                                                  int *ctl, int *nullmask,
-                                                                  double *scratch, T *F, T *P) {
-  if (ctl[0] == 0) return;
-  extern __shared__ double lds[];
-  const int w = ctl[1];
+// Eigenpairs of the weak block G2[w:, w:] (lam2 descending, U2 columns),
+// Jacobi in LDS.  scratch: gw (n*n), lam2 (n), U2 (n*n), M1 (n*k), Q2 (n*k).
+__device__ void weak_block_eig(const double *G2, int n, int w, double *scratch) {
   const int nw = n - w;
-  double *gw = scratch, *lam2 = gw + n * n, *U2 = lam2 + n, *M1 = U2 + n * n;
-  double *Q2 = M1 + n * k;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nw * nw; e += blockDim.x) {
+  double *gw = scratch, *lam2 = gw + n * n, *U2 = lam2 + n;
+  for (int e = threadIdx.x; e < nw * nw; e += blockDim.x) {
     const int i = e / nw, j = e - i * nw;
     gw[e] = G2[(w + i) * n + w + j];
   }
   __syncthreads();
   jacobi_eig_kernel_body(gw, lam2, U2, nw, nullptr, nullptr, false);
   __syncthreads();
+}
+
+// From the weak-block eigenvectors: T = blockdiag(I_w, U2[:, :k-w]), the
+// Cholesky factor L of T^T G2 T (null directions detected), F = L^-1 T^T
+// and P = U1 G2 F^T.
+template <typename T>
+__device__ void refine_factors(const double *G2, const double *U1, int n, int k, int *ctl,
+                               int *nullmask, double *scratch, T *F, T *P) {
+  extern __shared__ double lds[];
+  const int w = ctl[1];
+  const int nw = n - w;
+  double *U2 = scratch + n * n + n, *M1 = U2 + n * n;
+  double *Q2 = M1 + n * k;
+  const int tid = threadIdx.x;
   // T(i, j) = delta_ij (j < w); U2(i - w, j - w) (j >= w, i >= w); else 0
   auto Tij = [&](int i, int j) -> double {
     if (j < w) return i == j ? 1.0 : 0.0;
@@ -174,6 +181,40 @@ __global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *
     P[e] = nullmask[a] ? (T)0 : (T)acc;
   }
   if (tid == 0) ctl[2] = s_null;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *G2,
+                                                                  const double *U1, int n, int k,
+                                                                  int *ctl, int *nullmask,
+                                                                  double *scratch, T *F, T *P) {
+  if (ctl[0] == 0) return;
+  weak_block_eig(G2, n, ctl[1], scratch);
+  refine_factors<T>(G2, U1, n, k, ctl, nullmask, scratch, F, P);
+}
+
+// tolerance mode: the weak eigenpairs first, the factors once k is known
+__global__ __launch_bounds__(kEigThreads) void trunc_weak_kernel(const double *G2, int n,
+                                                                 const int *ctl, double *scratch,
+                                                                 const double *lam,
+                                                                 double *lamc) {
+  const int w = ctl[1];
+  const bool second = ctl[0] != 0;
+  if (second) weak_block_eig(G2, n, w, scratch);
+  // the spectrum the rank is chosen from: first-pass eigenvalues above the
+  // split, second-pass ones below it
+  const double *lam2 = scratch + n * n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    lamc[j] = (second && j >= w) ? lam2[j - w] : lam[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEigThreads) void trunc_final_kernel(const double *G2,
+                                                                  const double *U1, int n, int k,
+                                                                  int *ctl, int *nullmask,
+                                                                  double *scratch, T *F, T *P) {
+  if (ctl[0] == 0) return;
+  refine_factors<T>(G2, U1, n, k, ctl, nullmask, scratch, F, P);
 }
 
 // Null rows of the new core C (k x cols, row-major; nullmask[j] = 1 marks a
@@ -341,7 +382,17 @@ __global__ void trunc_ctl_kernel(const double *lam, const double *U, int n, int 
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) U1[e] = U[e];
 }
 
+__global__ void trunc_setk_kernel(int *ctl, int k) {
+  if (threadIdx.x == 0) ctl[0] = (ctl[0] != 0 && k > ctl[1]) ? 1 : 0;
+}
+
 }  // namespace
+
+int trunc_refine_setk(int *ctl, int64_t k, hipStream_t s) {
+  hipLaunchKernelGGL(trunc_setk_kernel, dim3(1), dim3(64), 0, s, ctl, (int)k);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
 
 int trunc_refine_ctl(const double *lam, const double *U, int64_t n, int64_t k, double tau,
                      int *ctl, double *U1, hipStream_t s) {
@@ -394,6 +445,49 @@ size_t trunc_complete_scratch(int64_t k, int64_t cols) {
   return (size_t)(cols + 2 * k * k + k * k + 2 * k);
 }
 
+template <typename T>
+int trunc_refine_eps(const double *G2, const double *U1, int64_t n, int *ctl, int *nullmask,
+                     double *scratch, const double *lam, double *lamc, hipStream_t s) {
+  (void)U1;
+  (void)nullmask;
+  const int np = (int)((n + 1) & ~1);
+  const size_t lds = 2 * sizeof(double) * (size_t)np * (size_t)(np + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)trunc_weak_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(trunc_weak_kernel, dim3(1), dim3(kEigThreads), lds, s, G2, (int)n, ctl,
+                     scratch, lam, lamc);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+template <typename T>
+int trunc_refine_final(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
+                       int *nullmask, double *scratch, T *F, T *P, hipStream_t s) {
+  if (n > kRefMaxN || k < 1 || k > n) return fail(TT_EINVAL, "internal: refinement shape");
+  const size_t lds = sizeof(double) * (size_t)k * (size_t)(2 * k + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)trunc_final_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((trunc_final_kernel<T>), dim3(1), dim3(kEigThreads), lds, s, G2, U1, (int)n,
+                     (int)k, ctl, nullmask, scratch, F, P);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int trunc_refine_eps<double>(const double *, const double *, int64_t, int *, int *,
+                                      double *, const double *, double *, hipStream_t);
+template int trunc_refine_eps<float>(const double *, const double *, int64_t, int *, int *,
+                                     double *, const double *, double *, hipStream_t);
+template int trunc_refine_final<double>(const double *, const double *, int64_t, int64_t, int *,
+                                        int *, double *, double *, double *, hipStream_t);
+template int trunc_refine_final<float>(const double *, const double *, int64_t, int64_t, int *,
+                                       int *, double *, float *, float *, hipStream_t);
 template int trunc_refine_solve<double>(const double *, const double *, int64_t, int64_t, int *,
                                         int *, double *, double *, double *, hipStream_t);
 template int trunc_refine_solve<float>(const double *, const double *, int64_t, int64_t, int *,

@@ -255,6 +255,12 @@ struct Problem {
   std::vector<double> coeffs;
   bool truncate = false;
   int64_t max_ell = 1;
+  // tolerance-driven truncation (section 3.2, remark after Algorithm 5):
+  // out holds the upper bounds l_n, the ranks chosen by the eps rule of
+  // Algorithm 2 are written to ranks_out (host, N+1 entries)
+  bool eps_mode = false;
+  double eps0 = 0.0;
+  int64_t *ranks_out = nullptr;
 };
 
 int check_shape(int32_t N, const int64_t *dims, const int64_t *ranks, const char *what);
@@ -399,8 +405,23 @@ int trunc_refine_complete(T *C, int64_t k, int64_t cols, const int *ctl, const i
                           double *scratch, hipStream_t s);
 size_t trunc_complete_scratch(int64_t k, int64_t cols);
 size_t trunc_refine_scratch(int64_t n, int64_t k);
+// the same in two steps for the tolerance mode: trunc_refine_eps forms the
+// weak-block eigenpairs (when ctl[0] = 1) and writes lamc (n): the spectrum
+// to choose the rank from (first-pass eigenvalues above the split, the
+// weak block's below it; lam itself when ctl[0] = 0); trunc_refine_final
+// then forms F and P for the chosen k
+template <typename T>
+int trunc_refine_eps(const double *G2, const double *U1, int64_t n, int *ctl, int *nullmask,
+                     double *scratch, const double *lam, double *lamc, hipStream_t s);
+template <typename T>
+int trunc_refine_final(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
+                       int *nullmask, double *scratch, T *F, T *P, hipStream_t s);
 int trunc_refine_ctl(const double *lam, const double *U, int64_t n, int64_t k, double tau,
                      int *ctl, double *U1, hipStream_t s);
+// after the kept rank k is chosen below the rank the solve was run for:
+// ctl[0] = (k > ctl[1]) (the second pass is needed only if a kept
+// eigenvalue is below the split)
+int trunc_refine_setk(int *ctl, int64_t k, hipStream_t s);
 
 struct EigGroupDesc {
   const double *G;
