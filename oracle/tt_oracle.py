@@ -10,6 +10,7 @@ rounding in the Tensor-Train format") step by step in its notation:
 
 * TT format, unfoldings H/V, sums of TTs ............ section 2.1 / 2.3
 * OrthogonalizeRL ................................... Algorithm 1
+* Orthogonalize-then-Randomize ...................... Algorithm 4
 * deterministic TT-Rounding ......................... Algorithm 2
 * PartialContractionsRL (the W_n chain) ............. Algorithm 3, eq. (RLContraction)
 * random Gaussian TT sketch ......................... Definition 3.1
@@ -433,15 +434,53 @@ def round_sum_rand(summands, coeffs, target, oversample=0, seed=None, sketch=Non
 
 def orthogonalize_rl(Y):
     """Algorithm 1: for n = N .. 2, QR of H(X_n)^T, H(X_n) <- Q^T,
-    X_{n-1} <- X_{n-1} x_3 R^T.  Returns a right-orthogonal TT."""
+    X_{n-1} <- X_{n-1} x_3 R^T.  Returns a right-orthogonal TT.  When
+    H(X_n)^T is wide (I_n r_n < r_{n-1} rows), Q is square and the bond rank
+    drops to I_n r_n; Q is then the QR factor of the leading square block of
+    H(X_n)^T (diag >= 0), R = Q^T H(X_n)^T."""
     X = [np.array(c, dtype=np.float64) for c in Y]
     for n in range(len(X) - 1, 0, -1):
-        Q, R = qr_pos(H(X[n]).T)
+        Ht = H(X[n]).T
+        m, cc = Ht.shape
+        if m >= cc:
+            Q, R = qr_pos(Ht)
+        else:
+            Q, _ = qr_pos(Ht[:, :m])
+            R = Q.T @ Ht
         k = Q.shape[1]
         X[n] = Q.T.reshape(k, X[n].shape[1], X[n].shape[2])
         prev = X[n - 1]
         X[n - 1] = (V(prev) @ R.T).reshape(prev.shape[0], prev.shape[1], k)
     return X
+
+
+def gaussian_matrix(seed, n, rows, cols):
+    """The Gaussian matrix Omega_n (rows x cols) of Algorithm 4: the
+    Definition 3.1 generator for a single core of rows*cols entries keyed by
+    seed + n, iid N(0, 1/(rows cols)), read row-major."""
+    return make_sketch(int(seed) + int(n), [rows * cols], [1, 1])[0].reshape(rows, cols)
+
+
+def round_orth_rand(Y, target, oversample=0, seed=None, omegas=None, truncate=True):
+    """Orthogonalize-then-Randomize (Algorithm 4): OrthogonalizeRL (Algorithm 1),
+    then for n = 1 .. N-1 with Z_n = V(X_n): Y_n = Z_n Omega_n, thin QR
+    (diag(R) >= 0), V(X_n) <- Q, M_n = Q^T Z_n, H(X_{n+1}) = M_n H(X_{n+1}).
+    Sketch ranks l_n from plan_ranks on the ranks after Algorithm 1; Omega_n
+    (R_n x l_n) given or drawn by gaussian_matrix(seed, n, ...).  With
+    truncate and some r_n < l_n the left-orthogonal result is truncated as
+    round_rand's."""
+    X = orthogonalize_rl(Y)
+    N = len(X)
+    if N == 1:
+        return X
+    dims, ranks = dims_of(X), ranks_of(X)
+    ell, out_ranks = plan_ranks(dims, ranks, target, oversample)
+    if omegas is None:
+        omegas = [None] + [gaussian_matrix(seed, n, ranks[n], ell[n]) for n in range(1, N)]
+    out = rto_sweep(X, omegas)
+    if truncate and any(out_ranks[n] < ell[n] for n in range(N + 1)):
+        out, _ = truncate_rl(out, out_ranks)
+    return out
 
 
 def _trunc_rank(S, eps_abs, max_rank):

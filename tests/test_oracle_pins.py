@@ -639,3 +639,73 @@ def test_round_sum_rand_eps_equals_assembled():
     Z, zr, _ = O.round_rand_eps(S, 8, 1e-10, seed=3)
     assert ranks == zr == [1, 4, 4, 4, 4, 1]
     assert O.rel_diff(X, S) < 1e-12
+
+
+# ---------------------------------------------------------------- Algorithm 4
+
+def test_orthogonalize_rl_wide_panel_gauge():
+    # I_N r_N < r_{N-1}: the last bond drops to I_N and the result is still
+    # right-orthogonal and equal to the input
+    Y = G.random_tt(5, [3, 4, 2], [1, 3, 5, 1])
+    X = O.orthogonalize_rl(Y)
+    assert O.ranks_of(X) == [1, 3, 2, 1]
+    assert O.rel_diff(X, Y) < 1e-13
+    for c in X[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-14
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_orth_rand_equals_rto_with_partial_contractions_as_omega(seed):
+    # Omega_n = W_n = H(X_{n+1:N}) H(Rk_{n+1:N})^T of the right-orthogonalised
+    # X turns Algorithm 4's sweep into Algorithm 5's on X, and Algorithm 5 is
+    # invariant under the gauge change of Algorithm 1: the outputs agree core
+    # by core
+    Y = tiny_tt(seed, N=5, I=3, R=4)
+    X = O.orthogonalize_rl(Y)
+    dims, ranks = O.dims_of(X), O.ranks_of(X)
+    ell, _ = O.plan_ranks(dims, ranks, 3, 0)
+    Rk = O.make_sketch(seed + 9, dims, ell)
+    W = O.partial_contractions_rl(X, Rk)
+    a = O.round_orth_rand(Y, 3, 0, omegas=W)
+    b = O.round_rand(Y, 3, 0, sketch=Rk)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", RNG_SEEDS)
+def test_orth_rand_equals_dense_range_finder(seed):
+    # on the right-orthogonal X, V(X_n) Omega_n = T_n H(X_{n+1:N})^T Omega_n
+    # with T_n the n-th sequential unfolding: the dense sequential range
+    # finder with the sketch H(X_{n+1:N})^T Omega_n gives the same cores
+    Y = tiny_tt(seed, N=4, I=3, R=3)
+    X = O.orthogonalize_rl(Y)
+    N = len(X)
+    dims, ranks = O.dims_of(X), O.ranks_of(X)
+    ell, _ = O.plan_ranks(dims, ranks, 2, 1)
+    om = [None] + [O.gaussian_matrix(seed, n, ranks[n], ell[n]) for n in range(1, N)]
+    out = O.round_orth_rand(Y, 2, 1, omegas=om, truncate=False)
+    T = O.full(Y).reshape(dims[0], -1)
+    for n in range(1, N):
+        right = O.full_with_left_rank(X[n:])  # (R_n, I_{n+1} ... I_N)
+        Q, _ = O.qr_pos(T @ right.T @ om[n])
+        np.testing.assert_allclose(Q, O.V(out[n - 1]), atol=1e-11)
+        T = (Q.T @ T).reshape(ell[n] * dims[n], -1)
+
+
+def test_orth_rand_exact_on_small_sum_workload():
+    w = G.workload_small_sum()
+    twoA = [2.0 * w["A"][0]] + [c.copy() for c in w["A"][1:]]
+    out = O.round_orth_rand(w["X"], w["target"], w["oversample"], seed=w["sketch_seed"])
+    assert O.rel_diff(out, twoA) <= 1e-12
+    for c in out[1:]:
+        Hn = O.H(c)
+        assert np.abs(Hn @ Hn.T - np.eye(Hn.shape[0])).max() < 1e-12
+
+
+def test_gaussian_matrix_distribution():
+    M = O.gaussian_matrix(7, 3, 300, 200)
+    assert M.shape == (300, 200)
+    assert abs(M.mean()) < 3e-4
+    assert abs(M.var() * 300 * 200 - 1.0) < 2e-2
+    np.testing.assert_array_equal(M, O.make_sketch(10, [60000], [1, 1])[0].reshape(300, 200))
