@@ -305,6 +305,37 @@ TT_API int tt_round_rand_backward(int32_t N, const int64_t *dims, const int64_t 
                                   void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Orthogonalize-then-Randomize (Algorithm 4, section 3.1).  Algorithm 1
+ * right-orthogonalises the input (thin QR of H(X_n)^T for n = N..2; when
+ * that panel is wide, I_n r_n < r_{n-1}, the bond drops to I_n r_n and Q is
+ * the QR factor of its leading square block), then for n = 1..N-1 with
+ * Z_n = V(X_n): Y_n = Z_n Omega_n, thin QR Y_n = Q R (diag(R) >= 0),
+ * V(X_n) <- Q, M_n = Q^T Z_n, H(X_{n+1}) = M_n H(X_{n+1}); then the same
+ * truncation as tt_round_rand when an out rank is below its sketch rank.
+ * Omega_n is R_n x l_n (R_n the rank after Algorithm 1) with iid
+ * N(0, 1/(R_n l_n)) entries, read row-major from the tt_make_sketch
+ * generator for one core of R_n l_n entries (ranks 1, 1) with seed + n.
+ *   tt_round_orth_rand_plan   host only: the sketch and out ranks
+ *                             (tt_round_rand_plan on the ranks after
+ *                             Algorithm 1)
+ *   prec                      TT_PREC_F64 (TT_F64) or TT_PREC_F32 (TT_F32)
+ *   out_cores[N]              caller buffers at the plan's out ranks
+ * Limits: every input bond rank <= TT_MAX_SKETCH_RANK (TT_EUNSUPPORTED).
+ * Asynchronous on `stream`.
+ */
+TT_API int tt_round_orth_rand_plan(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                   int64_t target_rank, int64_t oversample,
+                                   int64_t *sketch_ranks, int64_t *out_ranks);
+TT_API int tt_round_orth_rand_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                        int64_t target_rank, int64_t oversample, int32_t prec,
+                                        size_t *bytes);
+TT_API int tt_round_orth_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
+                              const void *const *cores, int32_t dtype, int64_t target_rank,
+                              int64_t oversample, uint64_t seed, int32_t prec,
+                              void *const *out_cores, void *workspace, size_t ws_bytes,
+                              void *stream);
+
+/*
  * Deterministic TT-rounding (Algorithms 1 and 2), the comparator of the
  * randomized methods.  Algorithm 1 right-orthogonalises the input by thin
  * QR factorisations from core N down to core 2; Algorithm 2 then sweeps left

@@ -55,6 +55,11 @@ _SIGS = {
                                                   P_size]),
     "tt_sum_round_eps": (ctypes.c_int, [c_i32, c_i32, P_i64, P_i64, P_vp, P_dbl, c_i32, c_i64,
                                         c_dbl, c_u64, c_i32, P_vp, P_i64, vp, c_size, vp]),
+    "tt_round_orth_rand_plan": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i64, P_i64, P_i64]),
+    "tt_round_orth_rand_workspace": (ctypes.c_int, [c_i32, P_i64, P_i64, c_i64, c_i64, c_i32,
+                                                    P_size]),
+    "tt_round_orth_rand": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64, c_u64,
+                                          c_i32, P_vp, vp, c_size, vp]),
     "tt_round_rand_noalloc": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64,
                                              c_u64, c_i32, P_vp, vp]),
     "tt_round_rand_with_sketch": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64,

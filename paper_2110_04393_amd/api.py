@@ -400,6 +400,43 @@ def sum_round_eps(summands, coeffs, max_rank: int, eps0: float, seed: int = 0,
     return _narrowed(out, dims, [got[i] for i in range(N + 1)])
 
 
+def orth_rand_plan(dims, ranks, target_rank: int, oversample: int = 0):
+    """Sketch and out ranks of Orthogonalize-then-Randomize (host only)."""
+    N = len(dims)
+    sr = L.i64_array([0] * (N + 1))
+    orr = L.i64_array([0] * (N + 1))
+    L.check(L.lib().tt_round_orth_rand_plan(N, L.i64_array(dims), L.i64_array(ranks),
+                                            int(target_rank), int(oversample), sr, orr))
+    return [sr[i] for i in range(N + 1)], [orr[i] for i in range(N + 1)]
+
+
+def round_orth_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0,
+                    prec: str = "f64", stream=None):
+    """Orthogonalize-then-Randomize rounding (Algorithm 4, tt_round_orth_rand);
+    returns new output cores."""
+    import ctypes
+    _check_cores(cores)
+    if prec not in ("f64", "f32"):
+        raise ValueError("tt_round_orth_rand takes prec 'f64' or 'f32'")
+    dims, ranks = _shape_of(cores)
+    N = len(dims)
+    _, out_ranks = orth_rand_plan(dims, ranks, target_rank, oversample)
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_round_orth_rand_workspace(N, L.i64_array(dims), L.i64_array(ranks),
+                                                 int(target_rank), int(oversample), _PREC[prec],
+                                                 ctypes.byref(b)))
+    dev = cores[0].device
+    ws = _workspace(b.value, dev)
+    out = [torch.empty((out_ranks[n], dims[n], out_ranks[n + 1]), dtype=cores[0].dtype,
+                       device=dev) for n in range(N)]
+    L.check(L.lib().tt_round_orth_rand(
+        N, L.i64_array(dims), L.i64_array(ranks), L.ptr_array([c.data_ptr() for c in cores]),
+        _DTYPE[cores[0].dtype], int(target_rank), int(oversample), int(seed) & ((1 << 64) - 1),
+        _PREC[prec], L.ptr_array([c.data_ptr() for c in out]), ctypes.c_void_p(ws.data_ptr()),
+        ws.numel(), _stream_handle(stream)))
+    return out
+
+
 def round_rand_noalloc(cores, target_rank: int, oversample: int = 0, seed: int = 0,
                        prec: str = "f64", out=None, stream=None):
     """Randomize-then-Orthogonalize rounding through tt_round_rand_noalloc

@@ -317,16 +317,19 @@ constexpr double kTruncRefineTau = 1e-4;
 // out: output cores.
 template <typename T>
 int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
-               const void *const *Sk, T *const *out) {
+               const void *const *Sk, T *const *out, T *const *W_given = nullptr) {
   const int N = P.N, s = P.s;
   const int64_t *dims = P.dims.data();
   const std::vector<int64_t> &L = P.ell;
   const std::vector<int64_t> &Rs = P.Rsum;
 
   // ---- W chains: stacked W_n = [W^(1)_n; ...; W^(s)_n], (sum_j R^(j)_n) x l_n
+  // (or the sketch matrices of Algorithm 4 when given: Y_n = Z_n W_n alike)
   std::vector<T *> W(N, nullptr);
-  for (int n = 1; n <= N - 1; ++n) W[n] = c.arena.take<T>((size_t)(Rs[n] * L[n]));
-  {
+  if (W_given) {
+    for (int n = 1; n <= N - 1; ++n) W[n] = W_given[n];
+  } else {
+    for (int n = 1; n <= N - 1; ++n) W[n] = c.arena.take<T>((size_t)(Rs[n] * L[n]));
     std::vector<const int64_t *> Rj(s);
     for (int j = 0; j < s; ++j) Rj[j] = P.R[j].data();
     TTR_TRY(wchain<T>(c, p, p.renorm, N, dims, s, Rj.data(), Y, L.data(), Sk, W.data()));
@@ -1008,15 +1011,72 @@ int backward_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   return TT_OK;
 }
 
+// ---------------------------------------------------------------- Algorithm 1
+// Right-to-left orthogonalisation of the working cores xs[1..N] (each buffer
+// large enough for any core of the train; ranks left[0..N], updated),
+// rr = the ranks after it.  Core n = N..2 with H = H(X_n) (c x m,
+// m = I_n r_n):
+//   m >= c: thin QR of H^T (transposed into a tall panel) gives Q; the new
+//           core is Q^T, and R^T = H Q is carried into X_{n-1};
+//   m <  c: the rank drops to m; Q is the QR factor of the leading m x m
+//           block of H^T (its first m rows of H, transposed), the new core
+//           Q^T, and R^T = H Q is carried into X_{n-1}.
+template <typename T>
+int orth_rl(Ctx &c, int N, const int64_t *dims, const std::vector<int64_t> &rr,
+            std::vector<T *> &xs, T *&spare, T *pan, T *qb, T *rt, QrScratch &qs,
+            std::vector<int64_t> &left) {
+  for (int n = N; n >= 2; --n) {
+    const int64_t cc = left[n - 1], I = dims[n - 1], m = I * rr[n];
+    const int64_t rows_prev = left[n - 2] * dims[n - 2];
+    const int64_t q = std::min(m, cc);  // columns of Q, the new bond rank
+    c.partial_need = std::max(c.partial_need, qr_partial_elems(m, q) * sizeof(double));
+    if (!c.dry) {
+      // tall panel H^T (m x cc), or the leading square block (m x m)
+      if (m >= cc)
+        TTR_TRY(transpose<T>(pan, xs[n], cc, m, c.s));
+      else
+        TTR_TRY(transpose<T>(pan, xs[n], m, m, c.s));
+      qs.partial = c.partial;
+      TTR_TRY(qr_thin<T>(pan, qb, m, q, qs, c.s));
+    }
+    Gemm<T> g;  // R^T = H Q  (cc x q)
+    g.A = xs[n];
+    g.lda = m;
+    g.a_kc = true;
+    g.B = qb;
+    g.ldb = q;
+    g.b_kc = false;
+    g.C = rt;
+    g.ldc = q;
+    g.M = cc;
+    g.N = q;
+    g.K = m;
+    TTR_TRY(gemm(c, g));
+    if (!c.dry) TTR_TRY(transpose<T>(xs[n], qb, m, q, c.s));  // new core: Q^T
+    Gemm<T> h;  // V(X_{n-1}) <- V(X_{n-1}) R^T
+    h.A = xs[n - 1];
+    h.lda = cc;
+    h.a_kc = true;
+    h.B = rt;
+    h.ldb = q;
+    h.b_kc = false;
+    h.C = spare;
+    h.ldc = q;
+    h.M = rows_prev;
+    h.N = q;
+    h.K = cc;
+    TTR_TRY(gemm(c, h));
+    std::swap(xs[n - 1], spare);
+    left[n - 1] = q;
+  }
+  return TT_OK;
+}
+
 // ---------------------------------------------------------------- TT-SVD
 // Deterministic rounding: Algorithm 1 (right-to-left orthogonalisation)
 // followed by Algorithm 2 (left-to-right truncation).
 //
-// Algorithm 1, core n = N..2: with H = H(X_n) (c x m, m = I_n r_n):
-//   m >= c: thin QR of H^T (transposed into a tall panel) gives Q; the new
-//           core is Q^T, and R^T = H Q is carried into X_{n-1};
-//   m <  c: the rank drops to m; the new core is the identity and H itself
-//           is carried into X_{n-1} (an exact gauge change).
+// Algorithm 1: orth_rl.
 // Algorithm 2, core n = 1..N-1: with A = V(X_n) (m x c), the SVD of the QR
 // factor R of A has the right singular vectors and singular values of the
 // Gram A^T A = R^T R; with its leading eigenpairs (V_k, s_k^2):
@@ -1099,64 +1159,7 @@ int svd_exec(Ctx &c, const SvdPlan &P, const T *const *Y, double eps0, T *const 
                         c.s));
   std::vector<int64_t> left(P.R.begin(), P.R.end());  // current bond ranks
   // ---- Algorithm 1
-  for (int n = N; n >= 2; --n) {
-    const int64_t cc = left[n - 1], I = dims[n - 1], m = I * P.rr[n];
-    const int64_t rows_prev = left[n - 2] * dims[n - 2];
-    if (m >= cc) {
-      c.partial_need = std::max(c.partial_need, qr_partial_elems(m, cc) * sizeof(double));
-      if (!c.dry) {
-        TTR_TRY(transpose<T>(pan, xs[n], cc, m, c.s));  // H^T: m x cc
-        qs.partial = c.partial;
-        TTR_TRY(qr_thin<T>(pan, qb, m, cc, qs, c.s));
-      }
-      Gemm<T> g;  // R^T = H Q  (cc x cc)
-      g.A = xs[n];
-      g.lda = m;
-      g.a_kc = true;
-      g.B = qb;
-      g.ldb = cc;
-      g.b_kc = false;
-      g.C = rt;
-      g.ldc = cc;
-      g.M = cc;
-      g.N = cc;
-      g.K = m;
-      TTR_TRY(gemm(c, g));
-      if (!c.dry) TTR_TRY(transpose<T>(xs[n], qb, m, cc, c.s));  // new core: Q^T
-      Gemm<T> h;  // V(X_{n-1}) <- V(X_{n-1}) R^T
-      h.A = xs[n - 1];
-      h.lda = cc;
-      h.a_kc = true;
-      h.B = rt;
-      h.ldb = cc;
-      h.b_kc = false;
-      h.C = spare;
-      h.ldc = cc;
-      h.M = rows_prev;
-      h.N = cc;
-      h.K = cc;
-      TTR_TRY(gemm(c, h));
-      std::swap(xs[n - 1], spare);
-      left[n - 1] = cc;
-    } else {
-      Gemm<T> h;  // V(X_{n-1}) <- V(X_{n-1}) H(X_n), core n <- I (m x m)
-      h.A = xs[n - 1];
-      h.lda = cc;
-      h.a_kc = true;
-      h.B = xs[n];
-      h.ldb = m;
-      h.b_kc = false;
-      h.C = spare;
-      h.ldc = m;
-      h.M = rows_prev;
-      h.N = m;
-      h.K = cc;
-      TTR_TRY(gemm(c, h));
-      std::swap(xs[n - 1], spare);
-      if (!c.dry) TTR_TRY(fill_identity<T>(xs[n], m, c.s));
-      left[n - 1] = m;
-    }
-  }
+  TTR_TRY(orth_rl<T>(c, N, dims, P.rr, xs, spare, pan, qb, rt, qs, left));
   // ||Y|| = ||X_1||_F once the other cores are orthonormal
   if (!c.dry && eps0 > 0.0) TTR_TRY(frob_norm<T>(xs[1], dims[0] * left[1], dnorm, c.s));
   // ---- Algorithm 2
@@ -1274,6 +1277,73 @@ int svd_exec(Ctx &c, const SvdPlan &P, const T *const *Y, double eps0, T *const 
 }
 
 // Sketch cores in the workspace, in the mode's sketch storage type.
+// ---------------------------------------------------------------- Algorithm 4
+// Orthogonalize-then-Randomize: Algorithm 1 on working copies of the input,
+// then the sweep of Algorithm 5 with the Gaussian matrices Omega_n (R_n x
+// l_n, drawn on the device like a sketch core keyed by seed + n) in place of
+// the partial contractions, then the same truncation.
+struct OrthPlan {
+  int N = 0;
+  std::vector<int64_t> dims, R, rr;
+  int64_t core_max = 1, max_c = 1;
+};
+
+int make_orth_plan(OrthPlan &P, int N, const int64_t *dims, const int64_t *ranks) {
+  TTR_TRY(check_shape(N, dims, ranks, "tt_round_orth_rand"));
+  P.N = N;
+  P.dims.assign(dims, dims + N);
+  P.R.assign(ranks, ranks + N + 1);
+  P.rr.assign(N + 1, 1);
+  for (int n = N; n >= 2; --n) P.rr[n - 1] = std::min(P.R[n - 1], dims[n - 1] * P.rr[n]);
+  for (int n = 0; n < N; ++n) {
+    P.core_max = std::max(P.core_max, P.R[n] * dims[n] * P.R[n + 1]);
+    P.max_c = std::max(P.max_c, P.R[n]);
+  }
+  if (N > 1 && P.max_c > TT_MAX_SKETCH_RANK)
+    return fail(TT_EUNSUPPORTED, "tt_round_orth_rand: a bond rank above TT_MAX_SKETCH_RANK");
+  return TT_OK;
+}
+
+template <typename T>
+int orth_rand_exec(Ctx &c, const OrthPlan &O, const Problem &P2, const Prec &p,
+                   const T *const *Y, uint64_t seed, T *const *out) {
+  const int N = O.N;
+  const int64_t *dims = O.dims.data();
+  std::vector<T *> xs(N + 1, nullptr);
+  for (int n = 1; n <= N; ++n) xs[n] = c.arena.take<T>((size_t)O.core_max);
+  T *spare = c.arena.take<T>((size_t)O.core_max);
+  T *pan = c.arena.take<T>((size_t)O.core_max);
+  T *qb = c.arena.take<T>((size_t)O.core_max);
+  const int64_t lc = O.max_c;
+  T *rt = c.arena.take<T>((size_t)(lc * lc));
+  QrScratch qs;
+  qs.gram = c.arena.take<double>((size_t)std::max(lc * lc, 2 * lc));
+  qs.rinv = c.arena.take<double>((size_t)std::max(lc * lc, 2 * lc));
+  if (sizeof(T) == 4) qs.rinv_f = c.arena.take<float>((size_t)(lc * lc));
+  qs.q1 = c.arena.take<T>((size_t)O.core_max);
+  qs.flag = c.arena.take<int>(4);
+  for (int n = 1; n <= N; ++n)
+    if (!c.dry)
+      TTR_TRY(copy2d<T>(xs[n], 1, Y[n - 1], 1, O.R[n - 1] * dims[n - 1] * O.R[n], 1, 1.0, 0.0,
+                        c.s));
+  std::vector<int64_t> left(O.R.begin(), O.R.end());
+  TTR_TRY(orth_rl<T>(c, N, dims, O.rr, xs, spare, pan, qb, rt, qs, left));
+  // Omega_n (R_n x l_n), n = 1..N-1
+  std::vector<T *> om(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) {
+    const int64_t cnt = O.rr[n] * P2.ell[n];
+    om[n] = c.arena.take<T>((size_t)cnt);
+    if (!c.dry) {
+      const int64_t d1[1] = {cnt}, r1[2] = {1, 1};
+      void *ptr = om[n];
+      TTR_TRY(sketch_generate(seed + (uint64_t)n, 1, d1, r1, (int)p.store, &ptr, c.s));
+    }
+  }
+  std::vector<const T *> cores(N);
+  for (int n = 0; n < N; ++n) cores[n] = xs[n + 1];
+  return round_exec<T>(c, P2, p, cores.data(), nullptr, out, om.data());
+}
+
 int sketch_exec(Ctx &c, const Problem &P, const Prec &p, std::vector<void *> &Sk) {
   Sk.assign(P.N, nullptr);
   for (int n = 0; n < P.N; ++n)
@@ -1996,6 +2066,82 @@ int tt_round_two_sided(int32_t N, const int64_t *dims, const int64_t *ranks,
     return two_sided_body(c, N, dims, ranks, ell, rho, (const double *const *)cores, seed_left,
                           seed_right, (double *const *)out_cores);
   });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int tt_round_orth_rand_plan(int32_t N, const int64_t *dims, const int64_t *ranks,
+                            int64_t target_rank, int64_t oversample, int64_t *sketch_ranks,
+                            int64_t *out_ranks) {
+  OrthPlan O;
+  TTR_TRY(make_orth_plan(O, N, dims, ranks));
+  return tt_round_rand_plan(N, dims, O.rr.data(), target_rank, oversample, sketch_ranks,
+                            out_ranks);
+}
+
+static int orth_common(int32_t N, const int64_t *dims, const int64_t *ranks,
+                       const void *const *cores, int32_t dtype, int64_t target_rank,
+                       int64_t oversample, uint64_t seed, int32_t prec, void *const *out_cores,
+                       void *workspace, size_t ws_bytes, void *stream, size_t *bytes) {
+  read_env();
+  OrthPlan O;
+  TTR_TRY(make_orth_plan(O, N, dims, ranks));
+  Problem P2;
+  TTR_TRY(make_problem(P2, 1, N, dims, O.rr.data(), target_rank, oversample, nullptr));
+  Prec pc;
+  TTR_TRY(prec_cfg(prec, pc));
+  if (prec == TT_PREC_MIXED_BF16)
+    return fail(TT_EUNSUPPORTED, "tt_round_orth_rand: TT_PREC_F64 or TT_PREC_F32");
+  // the workspace query runs the same sequence without buffers
+  std::vector<const void *> no_in(N, nullptr);
+  std::vector<void *> no_out(N, nullptr);
+  const void *const *in = cores ? cores : no_in.data();
+  void *const *outp = out_cores ? out_cores : no_out.data();
+  auto body = [&](Ctx &c) -> int {
+    if (pc.store == DType::F64)
+      return orth_rand_exec<double>(c, O, P2, pc, (const double *const *)in, seed,
+                                    (double *const *)outp);
+    return orth_rand_exec<float>(c, O, P2, pc, (const float *const *)in, seed,
+                                 (float *const *)outp);
+  };
+  if (bytes) {
+    if (N == 1) {
+      *bytes = 0;
+      return TT_OK;
+    }
+    return measure_workspace(body, bytes);
+  }
+  TTR_TRY(check_dtype(dtype, pc));
+  TTR_TRY(check_ptrs(N, cores, "input cores"));
+  TTR_TRY(check_ptrs(N, out_cores, "output cores"));
+  hipStream_t st = (hipStream_t)stream;
+  if (N == 1) {
+    const int64_t cnt = dims[0];
+    if (pc.store == DType::F64)
+      return copy2d<double>((double *)out_cores[0], 1, (const double *)cores[0], 1, cnt, 1, 1.0,
+                            0.0, st);
+    return copy2d<float>((float *)out_cores[0], 1, (const float *)cores[0], 1, cnt, 1, 1.0, 0.0,
+                         st);
+  }
+  return run_with_workspace(workspace, ws_bytes, st, body);
+}
+
+int tt_round_orth_rand_workspace(int32_t N, const int64_t *dims, const int64_t *ranks,
+                                 int64_t target_rank, int64_t oversample, int32_t prec,
+                                 size_t *bytes) {
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  return orth_common(N, dims, ranks, nullptr, prec == TT_PREC_F64 ? TT_F64 : TT_F32,
+                     target_rank, oversample, 0, prec, nullptr, nullptr, 0, nullptr, bytes);
+}
+
+int tt_round_orth_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
+                       const void *const *cores, int32_t dtype, int64_t target_rank,
+                       int64_t oversample, uint64_t seed, int32_t prec, void *const *out_cores,
+                       void *workspace, size_t ws_bytes, void *stream) {
+  return orth_common(N, dims, ranks, cores, dtype, target_rank, oversample, seed, prec,
+                     out_cores, workspace, ws_bytes, stream, nullptr);
 }
 
 }  // extern "C"

@@ -154,3 +154,35 @@ def test_two_sided_workspace_and_limits():
                                     L.ptr_array([1, 2, 3, 4]), 1, 60, 0, 1,
                                     L.ptr_array([5, 6, 7, 8]), None, 0, None)
     assert rc == -5  # FP32 cores are refused before any launch
+
+
+def test_orth_rand_plan_and_workspace():
+    # ranks after Algorithm 1 (the last bond drops to I_N = 7), then the
+    # plan of tt_round_rand on them; the queries run without a GPU
+    dims, ranks = [9, 8, 7], [1, 9, 12, 1]
+    rr = [1, 9, 7, 1]
+    assert tt.orth_rand_plan(dims, ranks, 4, 2) == tuple(O.plan_ranks(dims, rr, 4, 2))
+    for prec in (L.TT_PREC_F64, L.TT_PREC_F32):
+        b = ctypes.c_size_t(0)
+        L.check(L.lib().tt_round_orth_rand_workspace(3, L.i64_array(dims), L.i64_array(ranks), 4,
+                                                     2, prec, ctypes.byref(b)))
+        assert b.value > 0
+    b = ctypes.c_size_t(0)
+    st = L.lib().tt_round_orth_rand_workspace(3, L.i64_array(dims), L.i64_array(ranks), 4, 2,
+                                              L.TT_PREC_MIXED_BF16, ctypes.byref(b))
+    assert st == L.TT_EUNSUPPORTED
+
+
+def test_eps_workspace_queries():
+    for prec in (L.TT_PREC_F64, L.TT_PREC_F32):
+        b = ctypes.c_size_t(0)
+        L.check(L.lib().tt_round_rand_eps_workspace(30, L.i64_array([100] * 30),
+                                                    L.i64_array([1] + [200] * 29 + [1]), 60, prec,
+                                                    ctypes.byref(b)))
+        fixed = tt.round_rand_workspace([100] * 30, [1] + [200] * 29 + [1], 60, 0,
+                                        "f64" if prec == L.TT_PREC_F64 else "f32")
+        assert b.value >= fixed > 0
+        L.check(L.lib().tt_sum_round_eps_workspace(2, 4, L.i64_array([5] * 4),
+                                                   L.i64_array([1, 3, 3, 3, 1] * 2), 5, prec,
+                                                   ctypes.byref(b)))
+        assert b.value > 0
