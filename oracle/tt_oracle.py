@@ -690,3 +690,84 @@ def rto_flops(dims, ranks, ell):
         f += 2.0 * ell[n] * m * ranks[n]           # Q^T Z_n
         f += 2.0 * ell[n] * ranks[n] * dims[n] * ranks[n + 1]  # M_n H(Y_{n+1})
     return f
+
+
+# ----------------------------------------------------------------------------
+# Section 4.2: TT-GMRES with randomized rounding of the sums
+# ----------------------------------------------------------------------------
+
+
+def apply_mode_matrix(core, M):
+    """core x_2 M: out[a, i, b] = sum_j M[i, j] core[a, j, b]."""
+    return np.einsum("ij,ajb->aib", M, core)
+
+
+def operator_terms(mats, X):
+    """The N terms (A_{i,1} x ... x A_{i,N}) X of a Kronecker-sum operator
+    applied to the TT X, each a TT with X's ranks (mats[i][n] None = I)."""
+    return [[c if M is None else apply_mode_matrix(c, M) for M, c in zip(row, X)]
+            for row in mats]
+
+
+def tt_gmres(mats, f, precond, max_rank, round_eps, tol, max_iter, seed):
+    """Right-preconditioned TT-GMRES (section 4.2) with every sum rounded by
+    Algorithm 7 to the tolerance round_eps (round_sum_rand_eps, sketch rank
+    max_rank).  x_0 = 0, beta = ||f||, V_1 = f / beta; step k:
+      Y = (P x I x ... x I) V_k                     (P the preconditioner)
+      W = round(sum_i (A_{i,1} x ... x A_{i,N}) Y)  (seed + 2k - 1)
+      h_jk = <V_j, W>,  j = 1..k
+      Z = round(W - sum_j h_jk V_j)                 (seed + 2k)
+      h_{k+1,k} = ||Z||,  V_{k+1} = Z / h_{k+1,k}
+    and the least-squares problem min ||beta e_1 - H y|| by Givens rotations;
+    the residual estimate |g_{k+1}| / beta is recorded.  It stops when that
+    falls to tol or after max_iter steps; then x = (P x I ..) round(sum_j y_j
+    V_j) (seed + 2 m + 1).  Returns (x, residual history, iterations)."""
+    f = [np.array(c, dtype=np.float64) for c in f]
+    beta = math.sqrt(inner(f, f))
+    V = [[f[0] / beta] + [c.copy() for c in f[1:]]]
+    Hm = np.zeros((max_iter + 1, max_iter))
+    cs, sn = np.zeros(max_iter), np.zeros(max_iter)
+    g = np.zeros(max_iter + 1)
+    g[0] = beta
+    res = [1.0]
+    m = 0
+    for k in range(1, max_iter + 1):
+        Vk = V[k - 1]
+        Y = [apply_mode_matrix(Vk[0], precond)] + Vk[1:]
+        terms = operator_terms(mats, Y)
+        W, _, _ = round_sum_rand_eps(terms, None, max_rank, round_eps, seed=seed + 2 * k - 1)
+        h = [inner(V[j], W) for j in range(k)]
+        Z, _, _ = round_sum_rand_eps([W] + V, [1.0] + [-x for x in h], max_rank, round_eps,
+                                     seed=seed + 2 * k)
+        hz = float(np.linalg.norm(Z[0]))
+        V.append([Z[0] / hz] + Z[1:])
+        col = np.array(h + [hz])
+        for j in range(k - 1):  # previous rotations
+            a, b = col[j], col[j + 1]
+            col[j], col[j + 1] = cs[j] * a + sn[j] * b, -sn[j] * a + cs[j] * b
+        r = math.hypot(col[k - 1], col[k])
+        cs[k - 1], sn[k - 1] = col[k - 1] / r, col[k] / r
+        col[k - 1], col[k] = r, 0.0
+        Hm[:k + 1, k - 1] = col
+        g[k] = -sn[k - 1] * g[k - 1]
+        g[k - 1] = cs[k - 1] * g[k - 1]
+        res.append(abs(g[k]) / beta)
+        m = k
+        if res[-1] <= tol:
+            break
+    y = np.linalg.solve(np.triu(Hm[:m, :m]), g[:m])
+    U, _, _ = round_sum_rand_eps(V[:m], list(y), max_rank, round_eps, seed=seed + 2 * m + 1)
+    x = [apply_mode_matrix(U[0], precond)] + U[1:]
+    return x, res, m
+
+
+def kron_operator_dense(mats, dims):
+    """The dense matrix sum_i A_{i,1} x ... x A_{i,N} (C order of the modes),
+    for checks on tiny problems."""
+    tot = 0.0
+    for row in mats:
+        K = np.ones((1, 1))
+        for M, d in zip(row, dims):
+            K = np.kron(K, np.eye(d) if M is None else M)
+        tot = tot + K
+    return tot

@@ -709,3 +709,56 @@ def test_gaussian_matrix_distribution():
     assert abs(M.mean()) < 3e-4
     assert abs(M.var() * 300 * 200 - 1.0) < 2e-2
     np.testing.assert_array_equal(M, O.make_sketch(10, [60000], [1, 1])[0].reshape(300, 200))
+
+
+# ---------------------------------------------------------------- TT-GMRES (section 4.2)
+
+def _dense_gmres_residuals(A, P, f, m):
+    # right-preconditioned GMRES on the dense system, modified Gram-Schmidt
+    n = f.size
+    beta = np.linalg.norm(f)
+    Vd = np.zeros((n, m + 1))
+    Hd = np.zeros((m + 1, m))
+    Vd[:, 0] = f / beta
+    res = [1.0]
+    for k in range(m):
+        w = A @ (P @ Vd[:, k])
+        for j in range(k + 1):
+            Hd[j, k] = Vd[:, j] @ w
+            w = w - Hd[j, k] * Vd[:, j]
+        Hd[k + 1, k] = np.linalg.norm(w)
+        Vd[:, k + 1] = w / Hd[k + 1, k]
+        e1 = np.zeros(k + 2)
+        e1[0] = beta
+        y, *_ = np.linalg.lstsq(Hd[:k + 2, :k + 1], e1, rcond=None)
+        res.append(np.linalg.norm(e1 - Hd[:k + 2, :k + 1] @ y) / beta)
+    return res
+
+
+def test_tt_gmres_matches_dense_gmres_when_rounding_is_exact():
+    # tiny problem, rounding tolerance at the rounding level and sketch rank
+    # above every rank that appears: the TT iteration is GMRES itself
+    op = G.parametric_operator(N=3, I_space=6, I_param=4)
+    dims = op["dims"]
+    A = O.kron_operator_dense(op["mats"], dims)
+    P = np.kron(op["precond"], np.eye(int(np.prod(dims[1:]))))
+    f = O.full(op["f"]).ravel()
+    x, res, m = O.tt_gmres(op["mats"], op["f"], op["precond"], 24, 1e-14, 1e-10, 40, seed=5)
+    dres = _dense_gmres_residuals(A, P, f, m)
+    np.testing.assert_allclose(res, dres, rtol=1e-6, atol=1e-12)
+    assert res[-1] <= 1e-10
+    xd = O.full(x).ravel()
+    assert np.linalg.norm(A @ xd - f) / np.linalg.norm(f) <= 1e-9
+
+
+def test_tt_gmres_true_residual_meets_tolerance():
+    # rounding tolerance well below the solver tolerance: the true residual
+    # of the returned TT follows the estimate
+    op = G.parametric_operator(N=4, I_space=10, I_param=5)
+    dims = op["dims"]
+    A = O.kron_operator_dense(op["mats"], dims)
+    f = O.full(op["f"]).ravel()
+    x, res, m = O.tt_gmres(op["mats"], op["f"], op["precond"], 30, 1e-10, 1e-7, 30, seed=9)
+    assert res[-1] <= 1e-7
+    xd = O.full(x).ravel()
+    assert np.linalg.norm(A @ xd - f) / np.linalg.norm(f) <= 1e-6

@@ -188,3 +188,45 @@ def batched_specs(seed=0, B=64):
                           input_seed=BATCH_SEED_BASE + b,
                           sketch_seed=SKETCH_SEED_BASE + 10000 + b))
     return specs
+
+
+def parametric_operator(N=5, I_space=64, I_param=16, reaction=10.0):
+    """A synthetic stand-in for the parametric diffusion system of section 4.2
+    (its cookie-problem data are not available): the operator
+    sum_{i=1}^{N} A_{i,1} x ... x A_{i,N} on I_space x I_param^(N-1) with
+    A_{1,1} = K (the 1D finite-difference Laplacian on I_space interior
+    points of (0, 1)), chi_i the indicator of the i-th of N-1 equal
+    subintervals, A_{i,i} = diag(rho) with the
+    parameter values rho linearly spaced in [1, 10], and identities
+    elsewhere (None); A_{i,1} = reaction diag(chi_i) for i >= 2 (a reaction
+    term on the i-th subinterval, weighted by the i-th parameter).  The right-hand
+    side f is the rank-1 TT of all ones, and
+    the right preconditioner is (sum_i A_{i,1})^{-1} on the first mode (the
+    mean-based preconditioner of the section).  Returns dict(mats, f,
+    precond, dims) with mats[i][n] a float64 matrix or None."""
+    h = 1.0 / (I_space + 1)
+    K = (np.diag(np.full(I_space, 2.0)) - np.diag(np.ones(I_space - 1), 1)
+         - np.diag(np.ones(I_space - 1), -1)) / (h * h)
+    dims = [I_space] + [I_param] * (N - 1)
+    rho = np.linspace(1.0, 10.0, I_param)
+    mats = [[None] * N for _ in range(N)]
+    mats[0][0] = K
+    edges = np.linspace(0, I_space, N).astype(int)
+    for i in range(1, N):
+        chi = np.zeros(I_space)
+        chi[edges[i - 1]:edges[i]] = 1.0
+        mats[i][0] = reaction * np.diag(chi)
+        mats[i][i] = np.diag(rho)
+    S = sum(mats[i][0] for i in range(N))
+    precond = np.linalg.inv(S)
+    f = [np.ones((1, d, 1)) for d in dims]
+    return dict(mats=mats, f=f, precond=precond, dims=dims)
+
+
+def workload_gmres(k=3):
+    """The TT-GMRES workload: the parametric operator with N=5, 64 spatial
+    points, 16 samples per parameter; sketch rank 60, rounding tolerance
+    1e-9, solver tolerance 1e-8 (the section's), at most 40 iterations."""
+    op = parametric_operator(N=5, I_space=64, I_param=16)
+    return dict(op=op, max_rank=60, round_eps=1e-9, tol=1e-8, max_iter=40,
+                seed=SKETCH_SEED_BASE + k)
