@@ -336,6 +336,43 @@ TT_API int tt_round_orth_rand(int32_t N, const int64_t *dims, const int64_t *ran
                               void *stream);
 
 /*
+ * TT-GMRES (section 4.2): right-preconditioned GMRES for
+ * (sum_{t=1}^{T} A_{t,1} x ... x A_{t,N}) x = f on TTs, every sum of TTs
+ * rounded by Algorithm 7 to the relative tolerance round_eps (as
+ * tt_sum_round_eps, sketch rank max_rank).  With x_0 = 0, beta = ||f||,
+ * V_1 = f / beta, step k: Y = (P x I x ... x I) V_k; W = round(sum_t
+ * (A_{t,1} x ... x A_{t,N}) Y) (sketch seed + 2k - 1); h_jk = <V_j, W> for
+ * j <= k (Algorithm 3 with the second TT of rank r, section 3.5);
+ * Z = round(W - sum_j h_jk V_j) (seed + 2k); h_{k+1,k} = ||Z||,
+ * V_{k+1} = Z / h_{k+1,k}; Givens rotations of the Hessenberg column (k+1
+ * scalars, on the host); stop when |g_{k+1}| / beta <= tol or after max_iter
+ * steps; x = (P x I ..) round(sum_j y_j V_j) (seed + 2m + 1).  The call reads
+ * scalars back after every step (it waits for `stream`).
+ *   op_mats[T*N]   device I_n x I_n row-major matrices A_{t,n} (entry
+ *                  t*N + n), NULL = identity
+ *   precond        device I_1 x I_1 matrix P applied to the first mode, or
+ *                  NULL (no preconditioner)
+ *   f_ranks[N+1], f_cores[N]   the right-hand side (ranks <= max_rank)
+ *   dtype          TT_F64
+ *   max_rank       sketch rank of every rounding (<= TT_MAX_SKETCH_RANK)
+ *   x_cores[N]     caller buffers of the max_rank shapes (core n at least
+ *                  max_rank^2 I_n elements); written C-contiguous with the
+ *                  ranks returned in x_ranks[N+1] (host)
+ *   residuals      host, max_iter + 1 entries: the estimate |g_{k+1}|/beta
+ *                  after step k (residuals[0] = 1)
+ *   iterations     host: the number of steps taken
+ * Limits: N >= 2, 1 <= max_iter <= 63.
+ */
+TT_API int tt_gmres_workspace(int32_t N, const int64_t *dims, int32_t T, const int64_t *f_ranks,
+                              int64_t max_rank, int32_t max_iter, size_t *bytes);
+TT_API int tt_gmres(int32_t N, const int64_t *dims, int32_t T, const void *const *op_mats,
+                    const void *precond, const int64_t *f_ranks, const void *const *f_cores,
+                    int32_t dtype, int64_t max_rank, double round_eps, double tol,
+                    int32_t max_iter, uint64_t seed, void *const *x_cores, int64_t *x_ranks,
+                    double *residuals, int32_t *iterations, void *workspace, size_t ws_bytes,
+                    void *stream);
+
+/*
  * Deterministic TT-rounding (Algorithms 1 and 2), the comparator of the
  * randomized methods.  Algorithm 1 right-orthogonalises the input by thin
  * QR factorisations from core N down to core 2; Algorithm 2 then sweeps left

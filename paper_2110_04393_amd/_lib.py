@@ -60,6 +60,10 @@ _SIGS = {
                                                     P_size]),
     "tt_round_orth_rand": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64, c_u64,
                                           c_i32, P_vp, vp, c_size, vp]),
+    "tt_gmres_workspace": (ctypes.c_int, [c_i32, P_i64, c_i32, P_i64, c_i64, c_i32, P_size]),
+    "tt_gmres": (ctypes.c_int, [c_i32, P_i64, c_i32, P_vp, vp, P_i64, P_vp, c_i32, c_i64, c_dbl,
+                                c_dbl, c_i32, c_u64, P_vp, P_i64, P_dbl,
+                                ctypes.POINTER(c_i32), vp, c_size, vp]),
     "tt_round_rand_noalloc": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64,
                                              c_u64, c_i32, P_vp, vp]),
     "tt_round_rand_with_sketch": (ctypes.c_int, [c_i32, P_i64, P_i64, P_vp, c_i32, c_i64, c_i64,

@@ -437,6 +437,43 @@ def round_orth_rand(cores, target_rank: int, oversample: int = 0, seed: int = 0,
     return out
 
 
+def gmres(mats, f_cores, precond=None, max_rank: int = 60, round_eps: float = 1e-9,
+          tol: float = 1e-8, max_iter: int = 40, seed: int = 0, stream=None):
+    """TT-GMRES (tt_gmres; section 4.2) for sum_t A_{t,1} x ... x A_{t,N}
+    applied to x equal to f.  mats[t][n]: device FP64 I_n x I_n matrices or
+    None (identity); precond: device I_1 x I_1 or None.  Returns
+    (x cores at their ranks, residual estimates, iterations)."""
+    import ctypes
+    _check_cores(f_cores, "f")
+    dims, fr = _shape_of(f_cores)
+    N, T = len(dims), len(mats)
+    dev = f_cores[0].device
+    flat = []
+    for row in mats:
+        if len(row) != N:
+            raise ValueError("every operator term needs N matrices (None = identity)")
+        flat += [0 if M is None else M.data_ptr() for M in row]
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_gmres_workspace(N, L.i64_array(dims), T, L.i64_array(fr), int(max_rank),
+                                       int(max_iter), ctypes.byref(b)))
+    ws = _workspace(b.value, dev)
+    out = [torch.empty((int(max_rank) ** 2 * d,), dtype=torch.float64, device=dev) for d in dims]
+    xr = L.i64_array([0] * (N + 1))
+    res = (ctypes.c_double * (int(max_iter) + 1))()
+    it = ctypes.c_int32(0)
+    L.check(L.lib().tt_gmres(
+        N, L.i64_array(dims), T, L.ptr_array(flat),
+        ctypes.c_void_p(precond.data_ptr() if precond is not None else 0), L.i64_array(fr),
+        L.ptr_array([c.data_ptr() for c in f_cores]), _DTYPE[f_cores[0].dtype], int(max_rank),
+        float(round_eps), float(tol), int(max_iter), int(seed) & ((1 << 64) - 1),
+        L.ptr_array([c.data_ptr() for c in out]), xr, res, ctypes.byref(it),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+    ranks = [xr[i] for i in range(N + 1)]
+    x = [out[n][:ranks[n] * dims[n] * ranks[n + 1]].view(ranks[n], dims[n], ranks[n + 1])
+         for n in range(N)]
+    return x, [res[i] for i in range(it.value + 1)], it.value
+
+
 def round_rand_noalloc(cores, target_rank: int, oversample: int = 0, seed: int = 0,
                        prec: str = "f64", out=None, stream=None):
     """Randomize-then-Orthogonalize rounding through tt_round_rand_noalloc

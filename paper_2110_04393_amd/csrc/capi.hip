@@ -117,6 +117,7 @@ struct Ctx {
   size_t partial_need = 0;  // bytes of split-K partials
   void *partial = nullptr;
   size_t partial_cap = 0;   // bytes
+  size_t peak = 0;          // largest arena offset of nested, rolled-back regions
 };
 
 // Opt-in launch timer (tt_timing_start / tt_timing_stop).
@@ -1277,6 +1278,281 @@ int svd_exec(Ctx &c, const SvdPlan &P, const T *const *Y, double eps0, T *const 
 }
 
 // Sketch cores in the workspace, in the mode's sketch storage type.
+
+int sketch_exec(Ctx &c, const Problem &P, const Prec &p, std::vector<void *> &Sk);
+
+// ---------------------------------------------------------------- TT-GMRES
+// Section 4.2: right-preconditioned GMRES on TTs whose sums are rounded by
+// Algorithm 7 to a tolerance (the section 3.2 remark after Algorithm 5).
+// With x_0 = 0, beta = ||f||, V_1 = f / beta, step k:
+//   Y = (P x I ... x I) V_k
+//   W = round(sum_t (A_{t,1} x ... x A_{t,N}) Y)        sketch seed + 2k - 1
+//   h_jk = <V_j, W>, j = 1..k                           (Algorithm 3 + first cores)
+//   Z = round(W - sum_j h_jk V_j),  V_{k+1} = Z / ||Z||  sketch seed + 2k
+// (||Z|| is the norm of Z's first core: the truncation leaves cores 2..N
+// right-orthogonal), Givens rotations of the Hessenberg column on the host
+// (k+1 scalars), residual estimate |g_{k+1}| / beta; at the end
+// x = (P x I ..) round(sum_j y_j V_j) (seed + 2m + 1).
+struct GmresSpec {
+  int N = 0, T = 0;
+  std::vector<int64_t> dims;
+  const void *const *mats = nullptr;  // [T * N], null = identity
+  const void *precond = nullptr;      // I_1 x I_1 or null
+  std::vector<int64_t> fr;            // ranks of f
+  const void *const *f = nullptr;
+  int64_t lmax = 0;
+  double round_eps = 0.0, tol = 0.0;
+  int max_iter = 0;
+  uint64_t seed = 0;
+};
+
+// out (caller buffers of capacity l x I x l) = sum_j coeffs[j] X_j rounded to
+// eps0 (sketch rank lmax); ranks to out_ranks.  Scratch is rolled back.
+template <typename T>
+int round_eps_into(Ctx &c, int N, const int64_t *dims, const std::vector<const T *> &cores,
+                   const std::vector<std::vector<int64_t>> &ranks,
+                   const std::vector<double> &coeffs, int64_t lmax, double eps0, uint64_t seed,
+                   T *const *out, std::vector<int64_t> &out_ranks) {
+  const int s = (int)ranks.size();
+  std::vector<int64_t> flat;
+  for (const auto &r : ranks) flat.insert(flat.end(), r.begin(), r.end());
+  Problem P;
+  TTR_TRY(make_problem(P, s, N, dims, flat.data(), lmax, 0, coeffs.data()));
+  out_ranks.assign(N + 1, 1);
+  P.eps_mode = true;
+  P.eps0 = eps0;
+  P.truncate = true;
+  P.ranks_out = out_ranks.data();
+  Prec pc;
+  TTR_TRY(prec_cfg(TT_PREC_F64, pc));
+  const size_t mark = c.arena.off;
+  std::vector<void *> Skw;
+  TTR_TRY(sketch_exec(c, P, pc, Skw));
+  if (!c.dry)
+    TTR_TRY(sketch_generate(seed, N, P.dims.data(), P.ell.data(), (int)pc.sk,
+                            (void *const *)Skw.data(), c.s));
+  TTR_TRY(round_exec<T>(c, P, pc, cores.data(), (const void *const *)Skw.data(), out));
+  c.peak = std::max(c.peak, c.arena.off);
+  c.arena.off = mark;
+  return TT_OK;
+}
+
+// out[j] = <X_j, Y> (device) for s TTs X_j against one TT Y
+template <typename T>
+int tt_dots(Ctx &c, int N, const int64_t *dims, const std::vector<const T *> &X,
+            const std::vector<std::vector<int64_t>> &xr, const T *const *Y,
+            const std::vector<int64_t> &yr, double *out) {
+  const int s = (int)xr.size();
+  if (s > kFirstDotsMax) return fail(TT_EINVAL, "internal: too many inner products");
+  const size_t mark = c.arena.off;
+  std::vector<T *> W(N, nullptr);
+  for (int n = 1; n <= N - 1; ++n) {
+    int64_t rows = 0;
+    for (int j = 0; j < s; ++j) rows += xr[j][n];
+    W[n] = c.arena.take<T>((size_t)(rows * yr[n]));
+  }
+  Prec pc;
+  TTR_TRY(prec_cfg(TT_PREC_F64, pc));
+  std::vector<const int64_t *> Rj(s);
+  for (int j = 0; j < s; ++j) Rj[j] = xr[j].data();
+  TTR_TRY(wchain<T>(c, pc, false, N, dims, s, Rj.data(), X.data(), yr.data(),
+                    (const void *const *)Y, W.data()));
+  if (!c.dry) {
+    FirstDots<T> a;
+    int64_t off = 0;
+    for (int j = 0; j < s; ++j) {
+      a.X[j] = X[(size_t)j * N];
+      a.W[j] = W[1] + off * yr[1];
+      a.r[j] = (int)xr[j][1];
+      off += xr[j][1];
+    }
+    a.Y = Y[0];
+    a.I = (int)dims[0];
+    a.ry = (int)yr[1];
+    a.out = out;
+    TTR_TRY(first_dots<T>(a, s, c.s));
+  }
+  c.peak = std::max(c.peak, c.arena.off);
+  c.arena.off = mark;
+  return TT_OK;
+}
+
+// core n (r0 x I x r1) <- M core n along the mode index (batched over r0)
+template <typename T>
+int apply_mode(Ctx &c, const T *M, const T *core, T *dst, int64_t r0, int64_t I, int64_t r1) {
+  Gemm<T> g;
+  g.A = M;
+  g.lda = I;
+  g.a_kc = true;
+  g.B = core;
+  g.ldb = r1;
+  g.b_kc = false;
+  g.C = dst;
+  g.ldc = r1;
+  g.M = I;
+  g.N = r1;
+  g.K = I;
+  g.batch = r0;
+  g.sA = 0;
+  g.sB = I * r1;
+  g.sC = I * r1;
+  return gemm(c, g);
+}
+
+template <typename T>
+int gmres_exec(Ctx &c, const GmresSpec &S, T *const *x_out, int64_t *x_ranks, double *res,
+               int32_t *iters) {
+  const int N = S.N, m = S.max_iter, Tn = S.T;
+  const int64_t *dims = S.dims.data();
+  const int64_t l = S.lmax;
+  int64_t Imax = 1;
+  for (int n = 0; n < N; ++n) Imax = std::max(Imax, dims[n]);
+  int64_t fmax = 1;
+  for (int n = 0; n < N; ++n) fmax = std::max(fmax, S.fr[n] * dims[n] * S.fr[n + 1]);
+  const size_t cap = (size_t)std::max<int64_t>(l * l * Imax, fmax);
+  std::vector<std::vector<T *>> V(m + 2, std::vector<T *>(N, nullptr));
+  for (int k = 1; k <= m + 1; ++k)
+    for (int n = 0; n < N; ++n) V[k][n] = c.arena.take<T>(cap);
+  std::vector<T *> Wc(N), terms((size_t)Tn * N, nullptr);
+  for (int n = 0; n < N; ++n) Wc[n] = c.arena.take<T>(cap);
+  for (int t = 0; t < Tn; ++t)
+    for (int n = 0; n < N; ++n)
+      if (S.mats[(size_t)t * N + n]) terms[(size_t)t * N + n] = c.arena.take<T>(cap);
+  T *y1 = c.arena.take<T>(cap), *u1 = c.arena.take<T>(cap);
+  double *dots = c.arena.take<double>((size_t)m + 2);
+  std::vector<std::vector<int64_t>> vr(m + 2);
+  // beta = ||f|| and V_1 = f / beta
+  std::vector<const T *> fc(N);
+  for (int n = 0; n < N; ++n) fc[n] = static_cast<const T *>(S.f[n]);
+  double beta = 1.0;
+  {
+    TTR_TRY(tt_dots<T>(c, N, dims, fc, {S.fr}, fc.data(), S.fr, dots));
+    if (!c.dry) {
+      TTR_HIP(hipMemcpyAsync(&beta, dots, sizeof(double), hipMemcpyDeviceToHost, c.s));
+      TTR_HIP(hipStreamSynchronize(c.s));
+      if (!(beta > 0.0) || !std::isfinite(beta)) return fail(TT_EINVAL, "tt_gmres: f is zero");
+      beta = std::sqrt(beta);
+    }
+    for (int n = 0; n < N; ++n)
+      if (!c.dry)
+        TTR_TRY(copy2d<T>(V[1][n], 1, fc[n], 1, S.fr[n] * dims[n] * S.fr[n + 1], 1,
+                          n == 0 ? 1.0 / beta : 1.0, 0.0, c.s));
+    vr[1] = S.fr;
+  }
+  std::vector<double> Hc((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+  g[0] = beta;
+  if (res) res[0] = 1.0;
+  int done = 0;
+  for (int k = 1; k <= m; ++k) {
+    // Y = (P x I ..) V_k
+    const T *Ycore0 = V[k][0];
+    if (S.precond) {
+      TTR_TRY(apply_mode<T>(c, static_cast<const T *>(S.precond), V[k][0], y1, 1, dims[0],
+                            vr[k][1]));
+      Ycore0 = y1;
+    }
+    // operator terms and W
+    std::vector<const T *> tc((size_t)Tn * N);
+    std::vector<std::vector<int64_t>> tr(Tn, vr[k]);
+    for (int t = 0; t < Tn; ++t)
+      for (int n = 0; n < N; ++n) {
+        const T *src = n == 0 ? Ycore0 : V[k][n];
+        const T *M = static_cast<const T *>(S.mats[(size_t)t * N + n]);
+        if (M) {
+          TTR_TRY(apply_mode<T>(c, M, src, terms[(size_t)t * N + n], vr[k][n], dims[n],
+                                vr[k][n + 1]));
+          src = terms[(size_t)t * N + n];
+        }
+        tc[(size_t)t * N + n] = src;
+      }
+    std::vector<int64_t> wr;
+    TTR_TRY(round_eps_into<T>(c, N, dims, tc, tr, std::vector<double>(Tn, 1.0), l, S.round_eps,
+                              S.seed + 2 * (uint64_t)k - 1, Wc.data(), wr));
+    // h_jk = <V_j, W>
+    std::vector<const T *> vc;
+    std::vector<std::vector<int64_t>> vrs;
+    for (int j = 1; j <= k; ++j) {
+      for (int n = 0; n < N; ++n) vc.push_back(V[j][n]);
+      vrs.push_back(vr[j]);
+    }
+    TTR_TRY(tt_dots<T>(c, N, dims, vc, vrs, Wc.data(), wr, dots));
+    std::vector<double> h(k + 1, 0.0);
+    if (!c.dry) {
+      TTR_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * k, hipMemcpyDeviceToHost, c.s));
+      TTR_HIP(hipStreamSynchronize(c.s));
+    }
+    // Z = W - sum_j h_jk V_j, into V_{k+1}
+    std::vector<const T *> zc;
+    std::vector<std::vector<int64_t>> zr;
+    std::vector<double> zco;
+    for (int n = 0; n < N; ++n) zc.push_back(Wc[n]);
+    zr.push_back(wr);
+    zco.push_back(1.0);
+    for (int j = 1; j <= k; ++j) {
+      for (int n = 0; n < N; ++n) zc.push_back(V[j][n]);
+      zr.push_back(vr[j]);
+      zco.push_back(-h[j - 1]);
+    }
+    TTR_TRY(round_eps_into<T>(c, N, dims, zc, zr, zco, l, S.round_eps, S.seed + 2 * (uint64_t)k,
+                              V[k + 1].data(), vr[k + 1]));
+    double hz = 1.0;
+    if (!c.dry) {
+      TTR_TRY(frob_norm<T>(V[k + 1][0], dims[0] * vr[k + 1][1], dots, c.s));
+      TTR_HIP(hipMemcpyAsync(&hz, dots, sizeof(double), hipMemcpyDeviceToHost, c.s));
+      TTR_HIP(hipStreamSynchronize(c.s));
+      if (!(hz > 0.0) || !std::isfinite(hz)) hz = 0.0;
+      if (hz > 0.0)
+        TTR_TRY(copy2d<T>(V[k + 1][0], 1, V[k + 1][0], 1, dims[0] * vr[k + 1][1], 1, 1.0 / hz,
+                          0.0, c.s));
+    }
+    h[k] = hz;
+    // Givens rotations of the new Hessenberg column
+    for (int j = 0; j < k - 1; ++j) {
+      const double a = h[j], b = h[j + 1];
+      h[j] = cs[j] * a + sn[j] * b;
+      h[j + 1] = -sn[j] * a + cs[j] * b;
+    }
+    const double r = std::hypot(h[k - 1], h[k]);
+    cs[k - 1] = r > 0.0 ? h[k - 1] / r : 1.0;
+    sn[k - 1] = r > 0.0 ? h[k] / r : 0.0;
+    h[k - 1] = r;
+    h[k] = 0.0;
+    for (int j = 0; j <= k; ++j) Hc[(size_t)j * m + (k - 1)] = h[j];
+    g[k] = -sn[k - 1] * g[k - 1];
+    g[k - 1] = cs[k - 1] * g[k - 1];
+    const double est = std::fabs(g[k]) / beta;
+    if (res) res[k] = est;
+    done = k;
+    if (!c.dry && (est <= S.tol || hz == 0.0)) break;
+  }
+  // y from the triangular system, x = (P x I ..) round(sum_j y_j V_j)
+  std::vector<double> y(done, 0.0);
+  for (int i = done - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int j = i + 1; j < done; ++j) acc -= Hc[(size_t)i * m + j] * y[j];
+    const double d = Hc[(size_t)i * m + i];
+    y[i] = d != 0.0 ? acc / d : 0.0;
+  }
+  std::vector<const T *> uc;
+  std::vector<std::vector<int64_t>> ur;
+  for (int j = 1; j <= done; ++j) {
+    for (int n = 0; n < N; ++n) uc.push_back(V[j][n]);
+    ur.push_back(vr[j]);
+  }
+  std::vector<T *> uout(N);
+  uout[0] = S.precond ? u1 : x_out[0];
+  for (int n = 1; n < N; ++n) uout[n] = x_out[n];
+  std::vector<int64_t> xr;
+  TTR_TRY(round_eps_into<T>(c, N, dims, uc, ur, y, l, S.round_eps, S.seed + 2 * (uint64_t)done + 1,
+                            uout.data(), xr));
+  if (S.precond)
+    TTR_TRY(apply_mode<T>(c, static_cast<const T *>(S.precond), u1, x_out[0], 1, dims[0], xr[1]));
+  if (x_ranks)
+    for (int n = 0; n <= N; ++n) x_ranks[n] = xr[n];
+  if (iters) *iters = done;
+  return TT_OK;
+}
+
 // ---------------------------------------------------------------- Algorithm 4
 // Orthogonalize-then-Randomize: Algorithm 1 on working copies of the input,
 // then the sweep of Algorithm 5 with the Gaussian matrices Omega_n (R_n x
@@ -1360,7 +1636,7 @@ int run_with_workspace(void *workspace, size_t ws_bytes, hipStream_t s, F body) 
   dry.dry = true;
   TTR_TRY(body(dry));
   const size_t partial_bytes = (dry.partial_need + 255) & ~size_t(255);
-  const size_t need = partial_bytes + dry.arena.off;
+  const size_t need = partial_bytes + std::max(dry.arena.off, dry.peak);
   if (!workspace && need > 0) return fail(TT_EINVAL, "null workspace");
   if (ws_bytes < need)
     return fail(TT_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -1383,7 +1659,7 @@ int measure_workspace(F body, size_t *bytes) {
   Ctx dry;
   dry.dry = true;
   TTR_TRY(body(dry));
-  *bytes = ((dry.partial_need + 255) & ~size_t(255)) + dry.arena.off;
+  *bytes = ((dry.partial_need + 255) & ~size_t(255)) + std::max(dry.arena.off, dry.peak);
   return TT_OK;
 }
 
@@ -2142,6 +2418,91 @@ int tt_round_orth_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
                        void *workspace, size_t ws_bytes, void *stream) {
   return orth_common(N, dims, ranks, cores, dtype, target_rank, oversample, seed, prec,
                      out_cores, workspace, ws_bytes, stream, nullptr);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+static int gmres_common(int32_t N, const int64_t *dims, int32_t T, const void *const *op_mats,
+                        const void *precond, const int64_t *f_ranks, const void *const *f_cores,
+                        int32_t dtype, int64_t max_rank, double round_eps, double tol,
+                        int32_t max_iter, uint64_t seed, void *const *x_cores, int64_t *x_ranks,
+                        double *residuals, int32_t *iterations, void *workspace,
+                        size_t ws_bytes, void *stream, size_t *bytes) {
+  read_env();
+  TTR_TRY(check_shape(N, dims, f_ranks, "tt_gmres: f"));
+  if (N < 2) return fail(TT_EUNSUPPORTED, "tt_gmres: order N >= 2");
+  if (T < 1) return fail(TT_EINVAL, "tt_gmres: at least one operator term");
+  if (max_iter < 1 || max_iter + 1 > kFirstDotsMax)
+    return fail(TT_EUNSUPPORTED, "tt_gmres: max_iter in 1 .. 63");
+  if (!(round_eps > 0.0 && round_eps < 1.0)) return fail(TT_EINVAL, "tt_gmres: round_eps in (0, 1)");
+  if (!(tol > 0.0)) return fail(TT_EINVAL, "tt_gmres: tol > 0");
+  if (max_rank < 1 || max_rank > TT_MAX_SKETCH_RANK)
+    return fail(TT_EUNSUPPORTED, "tt_gmres: max_rank in 1 .. TT_MAX_SKETCH_RANK");
+  for (int n = 1; n < N; ++n)
+    if (f_ranks[n] > max_rank) return fail(TT_EINVAL, "tt_gmres: f ranks above max_rank");
+  if (dtype != TT_F64) return fail(TT_EUNSUPPORTED, "tt_gmres: TT_F64 storage only");
+  GmresSpec S;
+  S.N = N;
+  S.T = T;
+  S.dims.assign(dims, dims + N);
+  std::vector<const void *> no_mats;
+  if (!op_mats && bytes) {
+    no_mats.assign((size_t)T * N, nullptr);
+    S.mats = no_mats.data();
+  } else {
+    if (!op_mats) return fail(TT_EINVAL, "tt_gmres: null operator matrix array");
+    S.mats = op_mats;
+  }
+  S.precond = precond;
+  S.fr.assign(f_ranks, f_ranks + N + 1);
+  std::vector<const void *> no_f(N, nullptr);
+  S.f = f_cores ? f_cores : no_f.data();
+  S.lmax = max_rank;
+  S.round_eps = round_eps;
+  S.tol = tol;
+  S.max_iter = max_iter;
+  S.seed = seed;
+  std::vector<void *> no_x(N, nullptr);
+  void *const *xo = x_cores ? x_cores : no_x.data();
+  auto body = [&](Ctx &c) -> int {
+    return gmres_exec<double>(c, S, (double *const *)xo, c.dry ? nullptr : x_ranks,
+                              c.dry ? nullptr : residuals, c.dry ? nullptr : iterations);
+  };
+  if (bytes) {
+    // the sizes do not depend on the operator matrices being set
+    if (!op_mats) {
+      // treat every matrix as present for the sizing
+      static const char dummy = 0;
+      no_mats.assign((size_t)T * N, &dummy);
+      S.mats = no_mats.data();
+      if (!precond) S.precond = &dummy;
+    }
+    return measure_workspace(body, bytes);
+  }
+  TTR_TRY(check_ptrs(N, f_cores, "tt_gmres: f cores"));
+  TTR_TRY(check_ptrs(N, x_cores, "tt_gmres: x cores"));
+  if (!x_ranks || !residuals || !iterations) return fail(TT_EINVAL, "tt_gmres: null output");
+  return run_with_workspace(workspace, ws_bytes, (hipStream_t)stream, body);
+}
+
+int tt_gmres_workspace(int32_t N, const int64_t *dims, int32_t T, const int64_t *f_ranks,
+                       int64_t max_rank, int32_t max_iter, size_t *bytes) {
+  if (!bytes) return fail(TT_EINVAL, "null bytes pointer");
+  return gmres_common(N, dims, T, nullptr, nullptr, f_ranks, nullptr, TT_F64, max_rank, 0.5, 1.0,
+                      max_iter, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr,
+                      bytes);
+}
+
+int tt_gmres(int32_t N, const int64_t *dims, int32_t T, const void *const *op_mats,
+             const void *precond, const int64_t *f_ranks, const void *const *f_cores,
+             int32_t dtype, int64_t max_rank, double round_eps, double tol, int32_t max_iter,
+             uint64_t seed, void *const *x_cores, int64_t *x_ranks, double *residuals,
+             int32_t *iterations, void *workspace, size_t ws_bytes, void *stream) {
+  return gmres_common(N, dims, T, op_mats, precond, f_ranks, f_cores, dtype, max_rank, round_eps,
+                      tol, max_iter, seed, x_cores, x_ranks, residuals, iterations, workspace,
+                      ws_bytes, stream, nullptr);
 }
 
 }  // extern "C"

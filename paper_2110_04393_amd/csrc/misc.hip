@@ -215,6 +215,29 @@ __global__ __launch_bounds__(256) void tri_inv_upper_kernel(const double *R, int
   if (tid == 0) *flag = first ? s_bad : (*flag | s_bad);
 }
 
+// <X_j, Y> from the partial contraction W_1^(j) = H(X^(j)_{2:N}) H(Y_{2:N})^T:
+// out[j] = sum_i X^(j)_1(i, :) W_1^(j) Y_1(i, :)^T (first cores 1 x I x r),
+// one workgroup per j, fixed summation order.
+template <typename T>
+__global__ __launch_bounds__(256) void first_dots_kernel(FirstDots<T> a) {
+  __shared__ double s_part[4];
+  const int j = blockIdx.x;
+  const T *X = a.X[j];
+  const T *W = a.W[j];
+  const int r = a.r[j];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < a.I * a.ry; e += 256) {
+    const int i = e / a.ry, b = e - i * a.ry;
+    double t = 0.0;
+    for (int q = 0; q < r; ++q) t += (double)X[i * r + q] * (double)W[q * a.ry + b];
+    acc += t * (double)a.Y[i * a.ry + b];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) a.out[j] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+}
+
 }  // namespace
 
 template <typename T>
@@ -306,6 +329,17 @@ int tri_inv_upper(const double *R, int64_t n, double *X, float *Xf, int *flag, b
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
+
+template <typename T>
+int first_dots(const FirstDots<T> &a, int count, hipStream_t s) {
+  if (count <= 0) return TT_OK;
+  if (count > kFirstDotsMax) return fail(TT_EINVAL, "internal: too many first-core dots");
+  hipLaunchKernelGGL((first_dots_kernel<T>), dim3(count), dim3(256), 0, s, a);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int first_dots<double>(const FirstDots<double> &, int, hipStream_t);
+template int first_dots<float>(const FirstDots<float> &, int, hipStream_t);
 
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s) {
   if (count <= 0) return TT_OK;

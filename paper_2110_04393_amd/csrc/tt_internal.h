@@ -477,6 +477,22 @@ int nystrom_scale(const double *lam, const double *U, int64_t n, double rcond, d
 int tri_inv_upper(const double *R, int64_t n, double *X, float *Xf, int *flag, bool first,
                   hipStream_t s);
 
+// Inner products <X_j, Y> of TTs from their first cores (1 x I x r_j and
+// 1 x I x ry) and the partial contractions W_1^(j) (r_j x ry, leading
+// dimension ry): out[j] (device, FP64), up to kFirstDotsMax per launch.
+constexpr int kFirstDotsMax = 64;
+template <typename T>
+struct FirstDots {
+  const T *X[kFirstDotsMax];
+  const T *W[kFirstDotsMax];
+  int r[kFirstDotsMax];
+  const T *Y = nullptr;
+  int I = 0, ry = 0;
+  double *out = nullptr;
+};
+template <typename T>
+int first_dots(const FirstDots<T> &a, int count, hipStream_t s);
+
 // dst = RNE_bf16(src)
 int round_to_bf16(__bf16 *dst, const float *src, int64_t count, hipStream_t s);
 

@@ -186,3 +186,16 @@ def test_eps_workspace_queries():
                                                    L.i64_array([1, 3, 3, 3, 1] * 2), 5, prec,
                                                    ctypes.byref(b)))
         assert b.value > 0
+
+
+def test_gmres_workspace_and_argument_checks():
+    dims = [64, 16, 16, 16, 16]
+    b = ctypes.c_size_t(0)
+    L.check(L.lib().tt_gmres_workspace(5, L.i64_array(dims), 5, L.i64_array([1] * 6), 60, 40,
+                                       ctypes.byref(b)))
+    assert b.value > 0
+    # max_iter beyond the limit and max_rank beyond the sketch-rank limit
+    assert L.lib().tt_gmres_workspace(5, L.i64_array(dims), 5, L.i64_array([1] * 6), 60, 64,
+                                      ctypes.byref(b)) == L.TT_EUNSUPPORTED
+    assert L.lib().tt_gmres_workspace(5, L.i64_array(dims), 5, L.i64_array([1] * 6), 200, 10,
+                                      ctypes.byref(b)) == L.TT_EUNSUPPORTED
