@@ -46,7 +46,10 @@ METRIC = "ms per randomized TT-rounding + %MFMA peak; mixed-prec vs FP64 at tol"
 # copy (FETCH_SIZE counts half of the copy's reads: x 2.0; WRITE_SIZE x 1.0).
 # Source: profiles/wfuse_wchain_single_tt_N30_I100_R200_fp64_pmc_traffic.md.
 # Valid for the kernel as measured there; anything else reports null.
-MEASURED_TRAFFIC = {("single_tt", "f64", 6): {"read_bytes": 37.06e6, "write_bytes": 1.63e6}}
+# The BF16 entry is the mixed-precision form of the same level (wfuse_bf16_kernel),
+# profiles/wfuse_bf16_wchain_single_tt_N30_I100_R200_pmc_traffic.md.
+MEASURED_TRAFFIC = {("single_tt", "f64", 6): {"read_bytes": 37.06e6, "write_bytes": 1.63e6},
+                    ("single_tt", "bf16", 6): {"read_bytes": 17.67e6, "write_bytes": 0.816e6}}
 
 SITE_NAMES = {0: "wchain_z", 1: "wchain_w", 2: "sweep_y", 3: "sweep_m", 4: "sweep_next",
               5: "trunc", 6: "wchain_fused"}
@@ -109,10 +112,12 @@ def site_flops(site, dims, ell, summand_ranks, fused=False):
                for m, n, k in site_launches(site, dims, ell, summand_ranks, fused))
 
 
-def site_bytes(site, dims, ell, summand_ranks, elem, fused=False):
+def site_bytes(site, dims, ell, summand_ranks, elem, fused=False, sk_elem=None):
     """Algorithmic HBM bytes of one step's launches: each operand read once,
-    the result written once (elem bytes per value).  A fused level reads
-    Y_n, W_n and Sk_n and writes W_{n-1}; Z_n never reaches memory."""
+    the result written once (elem bytes per value; the sketch cores of a fused
+    level at sk_elem, 2 for the BF16 sketch).  A fused level reads Y_n, W_n and
+    Sk_n and writes W_{n-1}; Z_n never reaches memory."""
+    sk_elem = elem if sk_elem is None else sk_elem
     if site != 6:
         return sum(float(elem) * (m * k + k * n + m * n)
                    for m, n, k in site_launches(site, dims, ell, summand_ranks, fused))
@@ -120,7 +125,7 @@ def site_bytes(site, dims, ell, summand_ranks, elem, fused=False):
     tot = 0.0
     for (m1, n1, k1), (m2, n2, k2) in zip(pr[0::2], pr[1::2]):
         # (R0 I, L1, R1) then (R0, L0, I L1): Y + W + Sk + W_{n-1}
-        tot += float(elem) * (m1 * k1 + k1 * n1 + k2 * n2 + m2 * n2)
+        tot += float(elem) * (m1 * k1 + k1 * n1 + m2 * n2) + float(sk_elem) * k2 * n2
     return tot
 
 
@@ -329,7 +334,7 @@ def main():
     if math_dt == "bf16":
         # bandwidth-bound at these shapes: algorithmic bytes against HBM peak
         nbytes = site_bytes(site, dims, ell, summand_ranks, STORE_BYTES[args.prec],
-                            fused) * args.steps
+                            fused, sk_elem=2) * args.steps
         achieved = nbytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
@@ -344,10 +349,15 @@ def main():
     if mt:
         roofline["traffic"] = mt["read_bytes"] + mt["write_bytes"]
         roofline["traffic_detail"] = dict(mt, unit="bytes per launch",
-                                          algorithmic_bytes=site_bytes(site, dims, ell,
-                                                                       summand_ranks, 8, fused)
+                                          algorithmic_bytes=site_bytes(
+                                              site, dims, ell, summand_ranks,
+                                              STORE_BYTES[args.prec], fused,
+                                              sk_elem=2 if math_dt == "bf16" else None)
                                           / max(cnt // max(args.steps, 1), 1))
-    roofline.update(kernel=SITE_KERNEL[site], math=math_dt,
+    kname = SITE_KERNEL[site]
+    if site == 6 and math_dt == "bf16":
+        kname = kname.replace("wfuse_kernel", "wfuse_bf16_kernel")
+    roofline.update(kernel=kname, math=math_dt,
                     launches_per_step=cnt // max(args.steps, 1),
                     avg_launch_us=round(per_launch_us, 2),
                     site_ms_per_step={SITE_NAMES[k]: round(v[0] / args.steps, 4)
