@@ -10,17 +10,18 @@
 // rest of the method uses.
 //
 // Ill-conditioned panels: when a first-pass pivot falls below 1e-14 of its
-// original diagonal entry, chol_shift_kernel (always enqueued, a no-op
-// otherwise) factors G + s I instead, s = 11 (m n + n (n + 1)) u trace(G)
-// (shifted CholeskyQR, Fukaya et al. 2020), and sets flag bit 1; the second
-// pass runs as usual and a third CholeskyQR pass (the cholqr_fix_* kernels, no-ops
-// unless bit 1 is set) restores orthogonality to rounding.
+// original diagonal entry, the same Cholesky kernel factors G + s I instead,
+// s = 11 (m n + n (n + 1)) u trace(G) (shifted CholeskyQR, Fukaya et al.
+// 2020), and sets flag bit 1; the second pass runs as usual and a third
+// CholeskyQR pass (the cholqr_fix_* kernels, no-ops unless bit 1 is set)
+// restores orthogonality to rounding.
 //
 // Robust path: Householder QR in one workgroup, used for panels of at most 8
 // columns and, without a host round trip, whenever a pivot still breaks down
 // (flag bit 0: the sketch is rank deficient, e.g. rounding A+A with a sketch
-// wider than the rank).  The Householder kernel is always enqueued and returns
-// at once unless that bit is set.  Householder columns are sign-normalised
+// wider than the rank).  For the latter it runs inside the third pass's
+// one-workgroup kernel (always enqueued, returning at once unless bit 0 or
+// bit 1 is set).  Householder columns are sign-normalised
 // afterwards so that diag(R) >= 0 (zero counts as +).
 #include "fastmath.h"
 #include <algorithm>
@@ -65,10 +66,10 @@ constexpr int kCholThreads = 256;
 constexpr double kNearIdentity = 0x1p-30, kNearIdentityF32 = 0x1p-17;
 
 template <int NMAX>
-__device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Rinv,
-                                                     float *Rinv_f, int n, int *flag,
-                                                     int or_flag, double sh = 0.0,
-                                                     int mark = 0) {
+__device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rinv,
+                                                    float *Rinv_f, int n, int *flag,
+                                                    int or_flag, double sh = 0.0,
+                                                    int mark = 0) {
   constexpr int NB = NMAX / 2;      // augmented column slots per lane (2 NMAX columns)
   constexpr int NBL = NMAX / 4;     // slots of the left block
   constexpr int NA = NMAX / 16;     // row blocks
@@ -104,7 +105,7 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
         Rinv[e] = x;
         if (Rinv_f) Rinv_f[e] = (float)x;
       }
-      return;
+      return 0;
     }
   }
   // sh: shift added to the diagonal (shifted CholeskyQR), 0 otherwise
@@ -181,32 +182,29 @@ __device__ __forceinline__ void chol_inv_kernel_body(const double *G, double *Ri
     }
   }
   __syncthreads();
+  const int bad_all = s_bad;
   if (tid == 0) {
     if (or_flag) {
       // after a shifted first pass (bit 1) the third pass decides
-      if (s_bad && !(*flag & 2)) *flag = *flag | 1;
+      if (bad_all && !(*flag & 2)) *flag = *flag | 1;
     } else {
-      *flag = s_bad | mark;
+      *flag = bad_all | mark;
     }
   }
+  return bad_all;
 }
 
+// Without shift_c: one factorisation as above.  With shift_c > 0 (first
+// CholeskyQR pass): a breakdown is redone at once, in the same workgroup, on
+// G + s I with s = shift_c trace(G) (the trace bounds ||Y||_2^2); the flag
+// then reads 2 (bit 1: a third pass is due), or 3 if even the shifted matrix
+// breaks down.
 template <int NMAX>
 __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_inv_kernel(const double *G, double *Rinv,
                                                                 float *Rinv_f, int n, int *flag,
-                                                                int or_flag) {
-  chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, or_flag);
-}
-
-// The first CholeskyQR pass again, on G + s I with s = shift_c trace(G) (the
-// trace bounds ||Y||_2^2), run only when that pass broke down (flag bit 0);
-// the flag then reads 2 (bit 1: a third pass is due), or 3 if even the
-// shifted matrix breaks down.
-template <int NMAX>
-__global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_shift_kernel(const double *G, double *Rinv,
-                                                                float *Rinv_f, int n, int *flag,
-                                                                double shift_c) {
-  if ((*flag & 1) == 0) return;
+                                                                int or_flag, double shift_c) {
+  const int bad = chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, or_flag);
+  if (!bad || or_flag || !(shift_c > 0.0)) return;
   __shared__ double s_trace;
   if (threadIdx.x == 0) {
     double t = 0.0;
@@ -227,8 +225,9 @@ __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1,
 //              factors G = R^T R and writes R^{-1} to rinv; a pivot not above
 //              1e-4 of its diagonal entry (cond(Q)^2 too large for one pass
 //              to restore orthogonality to rounding) sets flag bit 0, and the
-//              Householder kernel that follows recomputes Q from Y;
-//   fix_apply: Q <- Q R^{-1}, the same rows per workgroup.
+//              same workgroup then recomputes Q from Y by Householder QR (as
+//              it does when bit 0 was already set by the second pass);
+//   fix_apply: Q <- Q R^{-1}, the same rows per workgroup, unless bit 0 is set.
 constexpr int kFixThreads = 256, kFixRows = 32, kFixMaxGroups = 32;
 constexpr int kFixPer = (96 * 97 / 2 + kFixThreads - 1) / kFixThreads;
 constexpr int kFixCholThreads = 1024;
@@ -286,11 +285,8 @@ __global__ __launch_bounds__(kFixThreads) void cholqr_fix_gram_kernel(const T *Q
     if (tid + t * kFixThreads < npair) P[pi[t] * n + pj[t]] = acc[t];
 }
 
-__global__ __launch_bounds__(kFixCholThreads) void cholqr_fix_chol_kernel(int n, int groups,
-                                                                          const double *part,
-                                                                          double *rinv,
-                                                                          int *flag) {
-  if ((*flag & 3) != 2) return;
+__device__ __forceinline__ int cholqr_fix_chol_body(int n, int groups, const double *part,
+                                                   double *rinv, int *flag) {
   extern __shared__ double fx_lds[];
   double *A = fx_lds;          // G, then R (upper)
   double *B = fx_lds + n * n;  // R^{-1}
@@ -342,7 +338,9 @@ __global__ __launch_bounds__(kFixCholThreads) void cholqr_fix_chol_kernel(int n,
   }
   __syncthreads();
   for (int e = tid; e < n * n; e += kFixCholThreads) rinv[e] = B[e];
-  if (tid == 0 && s_bad) *flag = *flag | 1;
+  const int bad = s_bad;
+  if (tid == 0 && bad) *flag = *flag | 1;
+  return bad;
 }
 
 template <typename T>
@@ -491,6 +489,28 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T *Y, T *
   householder_kernel_body<T>(Y, Q, work_g, rdiag, tau, m, n, flag, always, use_lds);
 }
 
+// The one-workgroup part of the rescue after the second CholeskyQR pass: the
+// third pass's Cholesky when the first pass was shifted (flag bits 1..0 = 10),
+// then Householder QR of Y into Q when bit 0 is set (by the second pass, by
+// the shifted first pass, or by that Cholesky).  The flag is read once at the
+// start; the Cholesky's verdict reaches the Householder step through LDS.
+static_assert(kFixCholThreads == kHhThreads, "one workgroup shape for both steps");
+template <typename T>
+__global__ __launch_bounds__(kHhThreads) void cholqr_rescue_kernel(int n, int groups,
+                                                                   const double *part,
+                                                                   double *rinv, int *flag,
+                                                                   const T *Y, T *Q, T *work_g,
+                                                                   int64_t m, int use_lds) {
+  const int fl = *flag;
+  int hh = fl & 1;
+  if ((fl & 3) == 2 && cholqr_fix_chol_body(n, groups, part, rinv, flag)) hh = 1;
+  if (!hh) return;
+  __syncthreads();
+  // rdiag = rinv[0..n), tau = rinv[n..2n): R^{-1} of the third pass is not
+  // applied once bit 0 is set
+  householder_kernel_body<T>(Y, Q, work_g, rinv, rinv + n, m, n, flag, 1, use_lds);
+}
+
 template <int NMAX>
 __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_group_kernel(const CholGroupDesc *tab) {
   const CholGroupDesc &e = tab[blockIdx.x];
@@ -524,11 +544,7 @@ template <int NMAX>
 static int chol_inv_launch(const double *G, double *Rinv, float *Rinv_f, int n, int *flag,
                            int or_flag, hipStream_t s, double shift_c) {
   hipLaunchKernelGGL((chol_inv_kernel<NMAX>), dim3(1), dim3(kCholThreads), 0, s, G, Rinv, Rinv_f,
-                     n, flag, or_flag);
-  TTR_HIP(hipGetLastError());
-  if (shift_c > 0.0)
-    hipLaunchKernelGGL((chol_shift_kernel<NMAX>), dim3(1), dim3(kCholThreads), 0, s, G, Rinv,
-                       Rinv_f, n, flag, shift_c);
+                     n, flag, or_flag, shift_c);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
@@ -566,9 +582,12 @@ static int householder(const T *Y, T *Q, T *work, double *rdiag, double *tau, in
   return TT_OK;
 }
 
+// Third pass and Householder rescue after the second CholeskyQR pass (all
+// three launches return at once on a panel that needed neither); q1 is the
+// Householder's global scratch when the panel does not fit in LDS.
 template <typename T>
-static int cholqr_fix(T *Q, int64_t m, int64_t n, int *flag, double *part, size_t part_bytes,
-                      double *rinv, hipStream_t s) {
+static int cholqr_fix(const T *Y, T *Q, T *q1, int64_t m, int64_t n, int *flag, double *part,
+                      size_t part_bytes, double *rinv, hipStream_t s) {
   if (n > 96) return fail(TT_EUNSUPPORTED, "QR panel wider than 96");
   const int64_t rows = fix_rows(m);
   const int64_t groups = (m + rows - 1) / rows;
@@ -576,7 +595,7 @@ static int cholqr_fix(T *Q, int64_t m, int64_t n, int *flag, double *part, size_
     return fail(TT_EINVAL, "internal: split buffer too small for the third QR pass");
   static bool attr_set = false;
   if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_chol_kernel,
+    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_rescue_kernel<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
     TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_apply_kernel<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
@@ -585,9 +604,11 @@ static int cholqr_fix(T *Q, int64_t m, int64_t n, int *flag, double *part, size_
   hipLaunchKernelGGL((cholqr_fix_gram_kernel<T>), dim3((unsigned)groups), dim3(kFixThreads), 0, s,
                      Q, m, (int)n, rows, flag, part);
   TTR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(cholqr_fix_chol_kernel, dim3(1), dim3(kFixCholThreads),
-                     2 * (size_t)(n * n) * sizeof(double), s, (int)n, (int)groups, part, rinv,
-                     flag);
+  const bool hh_lds = (m * n <= kHhLdsElems);
+  const size_t lds = std::max(2 * (size_t)(n * n) * sizeof(double),
+                              hh_lds ? 2 * sizeof(T) * (size_t)(m * n) : (size_t)0);
+  hipLaunchKernelGGL((cholqr_rescue_kernel<T>), dim3(1), dim3(kHhThreads), lds, s, (int)n,
+                     (int)groups, part, rinv, flag, Y, Q, q1, m, hh_lds ? 1 : 0);
   TTR_HIP(hipGetLastError());
   hipLaunchKernelGGL((cholqr_fix_apply_kernel<T>), dim3((unsigned)groups), dim3(kFixThreads),
                      (size_t)(n * n + kFixRows * n) * sizeof(double), s, Q, m, (int)n, rows,
@@ -656,12 +677,11 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     h.K = n;
     TTR_TRY(gemm_run<T>(h, s));
   }
-  // third pass when the first one was shifted (no-op otherwise), then the
-  // Householder fallback (no-op unless a pivot broke down); q1 and rinv are
-  // free again once the GEMMs above have run (same stream).
-  TTR_TRY(cholqr_fix<T>(Q, m, n, ws.flag, static_cast<double *>(ws.partial),
-                        qr_partial_elems(m, n) * sizeof(double), ws.rinv, s));
-  return householder<T>(Y, Q, q1, ws.rinv, ws.rinv + n, m, n, ws.flag, 0, s);
+  // third pass when the first one was shifted and the Householder fallback
+  // when a pivot broke down (no-ops otherwise); q1 and rinv are free again
+  // once the GEMMs above have run (same stream).
+  return cholqr_fix<T>(Y, Q, q1, m, n, ws.flag, static_cast<double *>(ws.partial),
+                       qr_partial_elems(m, n) * sizeof(double), ws.rinv, s);
 }
 
 template int qr_thin<double>(const double *, double *, int64_t, int64_t, QrScratch &,
