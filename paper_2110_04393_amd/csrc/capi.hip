@@ -19,6 +19,8 @@
 
 namespace ttr {
 
+thread_local bool g_spec_off = false;
+
 static thread_local std::string g_err = "no error";
 
 void set_error(const std::string &msg) { g_err = msg; }
@@ -118,6 +120,8 @@ struct Ctx {
   void *partial = nullptr;
   size_t partial_cap = 0;   // bytes
   size_t peak = 0;          // largest arena offset of nested, rolled-back regions
+  int *spec_flags = nullptr;  // speculative rounding: flags to read back (device)
+  int spec_count = 0;
 };
 
 // Opt-in launch timer (tt_timing_start / tt_timing_stop).
@@ -355,6 +359,16 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   if (sizeof(T) == 4) qs.rinv_f = c.arena.take<float>((size_t)(lm * lm));
   qs.q1 = c.arena.take<T>((size_t)ys_max);
   qs.flag = c.arena.take<int>(4);
+  // speculative form: QR flag of core n at sflags[4 n], truncation control of
+  // bond n at sflags[4 (N + 1) + 4 n], cleared first (the form is never
+  // captured into a graph)
+  int *sflags = c.arena.take<int>((size_t)8 * (N + 1));
+  qs.speculative = P.spec;
+  if (P.spec && !c.dry) {
+    TTR_HIP(hipMemsetAsync(sflags, 0, sizeof(int) * 8 * (size_t)(N + 1), c.s));
+    c.spec_flags = sflags;
+    c.spec_count = 8 * (N + 1);
+  }
   // the QR's own split-K Gram (FP64 accumulator) uses the shared partial buffer
   for (int n = 1; n <= N - 1; ++n) {
     const size_t need = qr_partial_elems(L[n - 1] * dims[n - 1], L[n]) * sizeof(double);
@@ -434,6 +448,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     g.K = Rs[n];
     TTR_TRY(gemm(c, g, TT_SITE_SWEEP_Y));
     qs.partial = c.partial;
+    if (P.spec) qs.flag = sflags + 4 * n;
     if (!c.dry) TTR_TRY(qr_thin<T>(ys, xs[n], m, L[n], qs, c.s));
     Gemm<T> h;  // M_n = Q^T Z_n
     h.A = xs[n];
@@ -538,9 +553,11 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     g.math = DType::F64;
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
     }
+    // (speculative: the bond's own control word, read back by the caller)
+    int *ctl_b = P.spec ? sflags + 4 * (N + 1) + 4 * n : ctl;
     if (!c.dry)
       TTR_TRY(eig_trunc<T>(gbuf, lr, keig, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s,
-                           refine ? ctl : nullptr, refine ? kTruncRefineTau : 0.0, U1));
+                           refine ? ctl_b : nullptr, refine ? kTruncRefineTau : 0.0, U1));
     // second pass's contractions (only when ctl[0] = 1, decided on the device)
     auto refine_contractions = [&]() -> int {
       GemmX b;  // B = U1^T H(X_n)
@@ -613,7 +630,8 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
       }
     }
     if (P.ranks_out) P.ranks_out[n - 1] = k;
-    if (refine && !P.eps_mode) {
+    const bool guarded = refine && !P.spec;  // the second pass's launches are enqueued
+    if (guarded && !P.eps_mode) {
       TTR_TRY(refine_contractions());
       if (!c.dry) TTR_TRY(trunc_refine_solve<T>(G2, U1, lr, k, ctl, nmask, rscr, Ff, Pf, c.s));
     }
@@ -632,14 +650,14 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     h.N = cols;
     h.K = lr;
     GemmX hx = h.x();
-    if (refine) {
+    if (guarded) {
       hx.sel = ctl;
       hx.A2 = Ff;
       hx.B2 = Bb;
     }
     TTR_TRY(gemm(c, hx, TT_SITE_TRUNC));
     // orthonormal rows in place of directions with no information left
-    if (refine && !c.dry)
+    if (guarded && !c.dry)
       TTR_TRY(trunc_refine_complete<T>(out[n - 1], k, cols, ctl, nmask, cscr, c.s));
     Gemm<T> p;  // X_{n-1} <- X_{n-1} x_3 (U s)
     const int64_t rows = L[n - 2] * dims[n - 2];
@@ -1755,6 +1773,19 @@ int tt_make_sketch(uint64_t seed, int32_t N, const int64_t *dims, const int64_t 
 namespace ttr {
 namespace {
 
+// The speculative form synchronises with its stream at the end: not under
+// stream capture, not in tolerance mode (which reads back ranks per bond and
+// keeps its second pass), not for callers that set g_spec_off, and not with
+// TT_SPECULATE=0 in the environment.
+bool speculation_allowed(const Problem &P, hipStream_t s) {
+  if (P.eps_mode || g_spec_off) return false;
+  const char *e = std::getenv("TT_SPECULATE");
+  if (e && !std::strcmp(e, "0")) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusNone;
+}
+
 template <typename T>
 int round_typed(const Problem &P, const Prec &pc, const void *const *cores, bool gen,
                        uint64_t seed, const void *const *sketch_cores, void *const *out_cores,
@@ -1791,7 +1822,33 @@ int round_typed(const Problem &P, const Prec &pc, const void *const *cores, bool
         Sk[n] = Skw[n];
       }
     }
-    return round_exec<T>(c, P, pc, Y, Sk.data(), out);
+    // Speculative form first when the call may wait for its stream: the
+    // rescue launches that a well-conditioned input never needs are left out,
+    // the flags are read back once, and a set flag (a QR pivot breakdown or a
+    // truncation that needs its second pass) redoes the rounding guarded on
+    // the same workspace layout.  Under stream capture, in tolerance mode and
+    // for callers that cannot wait, the guarded form runs directly.
+    Problem Q = P;
+    Q.spec = speculation_allowed(P, c.s);
+    const size_t off0 = c.arena.off;
+    TTR_TRY(round_exec<T>(c, Q, pc, Y, Sk.data(), out));
+    if (c.dry || !Q.spec) return TT_OK;
+    std::vector<int> hf((size_t)c.spec_count);
+    TTR_HIP(hipMemcpyAsync(hf.data(), c.spec_flags, sizeof(int) * hf.size(),
+                           hipMemcpyDeviceToHost, c.s));
+    TTR_HIP(hipStreamSynchronize(c.s));
+    bool redo = false;
+    for (int n = 0; n <= N; ++n)
+      redo = redo || hf[(size_t)4 * n] != 0 || hf[(size_t)4 * (N + 1) + 4 * n] != 0;
+    if (!redo) return TT_OK;
+    Q.spec = false;
+    c.arena.off = off0;
+    c.spec_flags = nullptr;
+    const int timed_site = g_timer.site;  // the per-site timer keeps the first run only
+    g_timer.site = -1;
+    const int rc = round_exec<T>(c, Q, pc, Y, Sk.data(), out);
+    g_timer.site = timed_site;
+    return rc;
   });
 }
 

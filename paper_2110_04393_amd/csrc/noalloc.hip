@@ -61,6 +61,12 @@ int tt_round_rand_noalloc(int32_t N, const int64_t *dims, const int64_t *ranks,
                                      std::to_string((size_t)TT_NOALLOC_SCRATCH_BYTES));
   void *ws = nullptr;
   TTR_TRY(scratch_address(&ws));
+  // the guarded form: no read-back, no synchronisation, no host buffer
+  struct SpecOff {
+    bool prev = g_spec_off;
+    SpecOff() { g_spec_off = true; }
+    ~SpecOff() { g_spec_off = prev; }
+  } guard;
   return tt_round_rand(N, dims, ranks, cores, dtype, target_rank, oversample, sketch_seed, prec,
                        out_cores, ws, (size_t)TT_NOALLOC_SCRATCH_BYTES, stream);
 }

@@ -679,7 +679,9 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   }
   // third pass when the first one was shifted and the Householder fallback
   // when a pivot broke down (no-ops otherwise); q1 and rinv are free again
-  // once the GEMMs above have run (same stream).
+  // once the GEMMs above have run (same stream).  The speculative form leaves
+  // them out: its caller reads the flag back and redoes the QR guarded.
+  if (ws.speculative) return TT_OK;
   return cholqr_fix<T>(Y, Q, q1, m, n, ws.flag, static_cast<double *>(ws.partial),
                        qr_partial_elems(m, n) * sizeof(double), ws.rinv, s);
 }

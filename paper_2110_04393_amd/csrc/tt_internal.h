@@ -261,7 +261,16 @@ struct Problem {
   bool eps_mode = false;
   double eps0 = 0.0;
   int64_t *ranks_out = nullptr;
+  // speculative form: the guarded rescue launches (third CholeskyQR pass,
+  // Householder fallback, second truncation pass) are left out and every
+  // core's QR flag and every bond's truncation control is kept for the
+  // caller to read back; a set one means the rounding must be redone guarded
+  bool spec = false;
 };
+
+// Set by callers that must not synchronise or read back (the no-allocation
+// entry point): roundings on this thread take the guarded form only.
+extern thread_local bool g_spec_off;
 
 int check_shape(int32_t N, const int64_t *dims, const int64_t *ranks, const char *what);
 int check_ptrs(int32_t N, const void *const *p, const char *what);
@@ -290,6 +299,7 @@ struct QrScratch {
   void *q1 = nullptr;          // m*n elements of the storage type
   int *flag = nullptr;         // 1 int
   void *partial = nullptr;     // split-K partials
+  bool speculative = false;    // leave out the third pass and the Householder rescue
 };
 size_t qr_partial_elems(int64_t m, int64_t n);
 // FP64 Gram of a tall panel: G = A^T A (n x n, ld ldg) for A(k, m) stored
