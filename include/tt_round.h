@@ -175,6 +175,19 @@ TT_API int tt_partial_contractions_rl(int32_t N, const int64_t *dims,
  *                           (out_ranks[n], dims[n], out_ranks[n+1])
  *   workspace, ws_bytes     >= tt_round_rand_workspace(...)
  * N = 1 copies the single core.
+ *
+ * Synchronisation.  Unless the stream is being captured, the call returns
+ * after the stream has finished the rounding: it runs a speculative form
+ * that leaves out the guarded rescue launches (the third CholeskyQR pass
+ * after a shifted first pass, the Householder fallback, the second pass of
+ * the truncation for kept directions far below the largest), reads the
+ * per-core breakdown flags and per-bond truncation controls back once, and
+ * when one is set redoes the rounding in the guarded form (all launches
+ * enqueued, each rescue returning at once unless its flag is set) on the
+ * same workspace.  Both forms give the same bits where no flag is set.
+ * Under stream capture, or with TT_SPECULATE=0 in the environment, only the
+ * guarded form is enqueued and the call returns without waiting.  The same
+ * holds for tt_round_rand_with_sketch and tt_sum_round.
  */
 TT_API int tt_round_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
                   const void *const *cores, int32_t dtype, int64_t target_rank,
@@ -193,7 +206,8 @@ TT_API int tt_round_rand(int32_t N, const int64_t *dims, const int64_t *ranks,
  * GPU uses that GPU's one array: calls that may overlap on one GPU (other
  * host threads, unordered streams) race and must be serialised by the
  * caller.  The array's device address is looked up on the first call on each
- * device (the current device).
+ * device (the current device).  The call always takes the guarded form of
+ * tt_round_rand: it neither reads back nor waits for the stream.
  */
 #define TT_NOALLOC_SCRATCH_BYTES (256u << 20) /* 256 MiB per GPU */
 TT_API int tt_round_rand_noalloc(int32_t N, const int64_t *dims, const int64_t *ranks,
