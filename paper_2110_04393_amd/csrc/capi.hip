@@ -120,8 +120,6 @@ struct Ctx {
   void *partial = nullptr;
   size_t partial_cap = 0;   // bytes
   size_t peak = 0;          // largest arena offset of nested, rolled-back regions
-  int *spec_flags = nullptr;  // speculative rounding: flags to read back (device)
-  int spec_count = 0;
 };
 
 // Opt-in launch timer (tt_timing_start / tt_timing_stop).
@@ -312,6 +310,21 @@ int wchain(Ctx &c, const Prec &p, bool renorm, int N, const int64_t *dims, int s
 }
 
 // ---------------------------------------------------------------- rounding
+// Speculative form: copies `count` device flag words back (waits for the
+// stream).
+int read_flags(Ctx &c, const int *d, int count, std::vector<int> &h) {
+  h.assign((size_t)count, 0);
+  TTR_HIP(hipMemcpyAsync(h.data(), d, sizeof(int) * (size_t)count, hipMemcpyDeviceToHost, c.s));
+  TTR_HIP(hipStreamSynchronize(c.s));
+  return TT_OK;
+}
+// The per-site timer records the first run of a phase only, not its redo.
+struct TimerPause {
+  int site = g_timer.site;
+  TimerPause() { g_timer.site = -1; }
+  ~TimerPause() { g_timer.site = site; }
+};
+
 // Kept eigenvalues of a truncation Gram below this fraction of the largest
 // (singular values below 1e-2 of the largest) take the second pass of
 // trunc_refine.hip; above it the first pass resolves the kept directions and
@@ -363,11 +376,13 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   // bond n at sflags[4 (N + 1) + 4 n], cleared first (the form is never
   // captured into a graph)
   int *sflags = c.arena.take<int>((size_t)8 * (N + 1));
-  qs.speculative = P.spec;
+  int *const qflag = qs.flag;
+  // sflags[0]: the speculative sweep's go word (1, cleared on a breakdown,
+  // after which its launches return at once)
+  int *const go = sflags;
   if (P.spec && !c.dry) {
     TTR_HIP(hipMemsetAsync(sflags, 0, sizeof(int) * 8 * (size_t)(N + 1), c.s));
-    c.spec_flags = sflags;
-    c.spec_count = 8 * (N + 1);
+    TTR_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(go), 1, 1, c.s));
   }
   // the QR's own split-K Gram (FP64 accumulator) uses the shared partial buffer
   for (int n = 1; n <= N - 1; ++n) {
@@ -431,7 +446,12 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     cur = x1;
   }
 
-  // ---- left-to-right sweep
+  // ---- left-to-right sweep; spec: the speculative form (Problem::spec)
+  const T *const first = cur;
+  auto sweep = [&](bool spec) -> int {
+  const T *cur = first;
+  qs.speculative = spec;
+  qs.go = spec ? go : nullptr;
   for (int n = 1; n <= N - 1; ++n) {
     const int64_t m = L[n - 1] * dims[n - 1];
     Gemm<T> g;  // Y_n = Z_n W_n
@@ -446,9 +466,11 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     g.M = m;
     g.N = L[n];
     g.K = Rs[n];
-    TTR_TRY(gemm(c, g, TT_SITE_SWEEP_Y));
+    GemmX gx = g.x();
+    gx.gate = qs.go;
+    TTR_TRY(gemm(c, gx, TT_SITE_SWEEP_Y));
     qs.partial = c.partial;
-    if (P.spec) qs.flag = sflags + 4 * n;
+    qs.flag = spec ? sflags + 4 * n : qflag;
     if (!c.dry) TTR_TRY(qr_thin<T>(ys, xs[n], m, L[n], qs, c.s));
     Gemm<T> h;  // M_n = Q^T Z_n
     h.A = xs[n];
@@ -462,7 +484,9 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     h.M = L[n];
     h.N = Rs[n];
     h.K = m;
-    TTR_TRY(gemm(c, h, TT_SITE_SWEEP_M));
+    GemmX hx = h.x();
+    hx.gate = qs.go;
+    TTR_TRY(gemm(c, hx, TT_SITE_SWEEP_M));
     // next core
     const int64_t I1 = dims[n];
     const bool last = (n + 1 == N);
@@ -498,11 +522,31 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
         k.sB = rj1;
         k.sC = Rs[n + 1];
       }
-      TTR_TRY(gemm(c, k, TT_SITE_SWEEP_NEXT));
+      GemmX kx = k.x();
+      kx.gate = qs.go;
+      TTR_TRY(gemm(c, kx, TT_SITE_SWEEP_NEXT));
       offm += rj;
       offn += rj1;
     }
     cur = dst;
+  }
+  return TT_OK;
+  };
+  // A speculative sweep whose flags show a breakdown is redone guarded (the W
+  // chain is kept), and the truncation then runs guarded too: an input that
+  // needed the thin QR's rescue usually needs the truncation's second pass.
+  bool trunc_spec = P.spec;
+  TTR_TRY(sweep(P.spec));
+  std::vector<int> hf;
+  if (P.spec && !c.dry) {
+    TTR_TRY(read_flags(c, sflags, 4 * (N + 1), hf));
+    bool bad = false;
+    for (int n = 1; n <= N - 1; ++n) bad = bad || hf[(size_t)4 * n] != 0;
+    if (bad) {
+      TimerPause tp;
+      TTR_TRY(sweep(false));
+      trunc_spec = false;
+    }
   }
 
   if (P.ranks_out)
@@ -520,6 +564,9 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     dk = c.arena.take<int>((size_t)N + 1);
     if (!c.dry) TTR_TRY(frob_norm<T>(xs[N], L[N - 1] * dims[N - 1], dnorm, c.s));
   }
+  // the sweep's output xs stays intact: a speculative truncation whose
+  // controls show that a bond needed the second pass is redone guarded
+  auto truncate = [&](bool spec) -> int {
   const T *hsrc = xs[N];
   int64_t rr = 1;  // right rank of the current core
   for (int n = N; n >= 2; --n) {
@@ -554,7 +601,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     TTR_TRY(gemm(c, g, TT_SITE_TRUNC));
     }
     // (speculative: the bond's own control word, read back by the caller)
-    int *ctl_b = P.spec ? sflags + 4 * (N + 1) + 4 * n : ctl;
+    int *ctl_b = spec ? sflags + 4 * (N + 1) + 4 * n : ctl;
     if (!c.dry)
       TTR_TRY(eig_trunc<T>(gbuf, lr, keig, lam, U, Pf, Sf, tails + n - 1, eflag, escr, c.s,
                            refine ? ctl_b : nullptr, refine ? kTruncRefineTau : 0.0, U1));
@@ -630,7 +677,7 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
       }
     }
     if (P.ranks_out) P.ranks_out[n - 1] = k;
-    const bool guarded = refine && !P.spec;  // the second pass's launches are enqueued
+    const bool guarded = refine && !spec;  // the second pass's launches are enqueued
     if (guarded && !P.eps_mode) {
       TTR_TRY(refine_contractions());
       if (!c.dry) TTR_TRY(trunc_refine_solve<T>(G2, U1, lr, k, ctl, nmask, rscr, Ff, Pf, c.s));
@@ -676,6 +723,18 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     TTR_TRY(gemm(c, p, TT_SITE_TRUNC));
     hsrc = dst;
     rr = k;
+  }
+  return TT_OK;
+  };
+  TTR_TRY(truncate(trunc_spec));
+  if (trunc_spec && !c.dry) {
+    TTR_TRY(read_flags(c, sflags + 4 * (N + 1), 4 * (N + 1), hf));
+    bool bad = false;
+    for (int n = 2; n <= N; ++n) bad = bad || hf[(size_t)4 * n] != 0;
+    if (bad) {
+      TimerPause tp;
+      TTR_TRY(truncate(false));
+    }
   }
   return TT_OK;
 }
@@ -1822,33 +1881,15 @@ int round_typed(const Problem &P, const Prec &pc, const void *const *cores, bool
         Sk[n] = Skw[n];
       }
     }
-    // Speculative form first when the call may wait for its stream: the
-    // rescue launches that a well-conditioned input never needs are left out,
-    // the flags are read back once, and a set flag (a QR pivot breakdown or a
-    // truncation that needs its second pass) redoes the rounding guarded on
-    // the same workspace layout.  Under stream capture, in tolerance mode and
-    // for callers that cannot wait, the guarded form runs directly.
+    // Speculative form when the call may wait for its stream: the rescue
+    // launches that a well-conditioned input never needs are left out, the
+    // flags are read back after the sweep and after the truncation, and a
+    // phase with a set flag is redone guarded (round_exec).  Under stream
+    // capture, in tolerance mode and for callers that cannot wait, the guarded
+    // form runs directly.
     Problem Q = P;
     Q.spec = speculation_allowed(P, c.s);
-    const size_t off0 = c.arena.off;
-    TTR_TRY(round_exec<T>(c, Q, pc, Y, Sk.data(), out));
-    if (c.dry || !Q.spec) return TT_OK;
-    std::vector<int> hf((size_t)c.spec_count);
-    TTR_HIP(hipMemcpyAsync(hf.data(), c.spec_flags, sizeof(int) * hf.size(),
-                           hipMemcpyDeviceToHost, c.s));
-    TTR_HIP(hipStreamSynchronize(c.s));
-    bool redo = false;
-    for (int n = 0; n <= N; ++n)
-      redo = redo || hf[(size_t)4 * n] != 0 || hf[(size_t)4 * (N + 1) + 4 * n] != 0;
-    if (!redo) return TT_OK;
-    Q.spec = false;
-    c.arena.off = off0;
-    c.spec_flags = nullptr;
-    const int timed_site = g_timer.site;  // the per-site timer keeps the first run only
-    g_timer.site = -1;
-    const int rc = round_exec<T>(c, Q, pc, Y, Sk.data(), out);
-    g_timer.site = timed_site;
-    return rc;
+    return round_exec<T>(c, Q, pc, Y, Sk.data(), out);
   });
 }
 

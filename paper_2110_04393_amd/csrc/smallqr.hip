@@ -198,13 +198,21 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
 // CholeskyQR pass): a breakdown is redone at once, in the same workgroup, on
 // G + s I with s = shift_c trace(G) (the trace bounds ||Y||_2^2); the flag
 // then reads 2 (bit 1: a third pass is due), or 3 if even the shifted matrix
-// breaks down.
+// breaks down.  With go (speculative sweep): nothing runs once *go is 0, and
+// a breakdown clears it instead of being repaired (the flag keeps it).
 template <int NMAX>
 __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_inv_kernel(const double *G, double *Rinv,
                                                                 float *Rinv_f, int n, int *flag,
-                                                                int or_flag, double shift_c) {
+                                                                int or_flag, double shift_c,
+                                                                int *go) {
+  if (go && *go == 0) return;
   const int bad = chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, or_flag);
-  if (!bad || or_flag || !(shift_c > 0.0)) return;
+  if (!bad) return;
+  if (go) {
+    if (threadIdx.x == 0) *go = 0;
+    return;
+  }
+  if (or_flag || !(shift_c > 0.0)) return;
   __shared__ double s_trace;
   if (threadIdx.x == 0) {
     double t = 0.0;
@@ -542,19 +550,19 @@ size_t qr_partial_elems(int64_t m, int64_t n) {
 
 template <int NMAX>
 static int chol_inv_launch(const double *G, double *Rinv, float *Rinv_f, int n, int *flag,
-                           int or_flag, hipStream_t s, double shift_c) {
+                           int or_flag, hipStream_t s, double shift_c, int *go) {
   hipLaunchKernelGGL((chol_inv_kernel<NMAX>), dim3(1), dim3(kCholThreads), 0, s, G, Rinv, Rinv_f,
-                     n, flag, or_flag, shift_c);
+                     n, flag, or_flag, shift_c, go);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
 
 // Cholesky + inverse of the n x n Gram (n <= TT_MAX_SKETCH_RANK)
 static int chol_inv(const double *G, double *Rinv, float *Rinv_f, int n, int *flag, int or_flag,
-                    hipStream_t s, double shift_c = 0.0) {
-  if (n <= 32) return chol_inv_launch<32>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c);
-  if (n <= 64) return chol_inv_launch<64>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c);
-  if (n <= 96) return chol_inv_launch<96>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c);
+                    hipStream_t s, double shift_c = 0.0, int *go = nullptr) {
+  if (n <= 32) return chol_inv_launch<32>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c, go);
+  if (n <= 64) return chol_inv_launch<64>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c, go);
+  if (n <= 96) return chol_inv_launch<96>(G, Rinv, Rinv_f, n, flag, or_flag, s, shift_c, go);
   return fail(TT_EUNSUPPORTED, "Cholesky of a Gram matrix wider than 96");
 }
 
@@ -635,7 +643,7 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     T *dst = pass == 0 ? q1 : Q;
     if (gram_enabled(n, m)) {
       TTR_TRY(gram_run(src, DTypeOf<T>::value, false, n, n, m, ws.gram, n, ws.partial,
-                       gram_partial_elems(n, m) * sizeof(double), s));
+                       gram_partial_elems(n, m) * sizeof(double), s, ws.go));
     } else {
     GemmX g;  // G = src^T src, accumulated in FP64
     g.A = src;
@@ -655,6 +663,7 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     g.K = m;
     g.splits = gemm_pick_splits(n, n, m, DType::F64);
     g.partial = ws.partial;
+    g.gate = ws.go;
     TTR_TRY(gemmx_run(g, s));
     }
     // first pass: shifted retry on breakdown, s = 11 (m n + n (n + 1)) u trace(G)
@@ -662,7 +671,7 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     const double shift_c =
         pass == 0 ? 11.0 * (double)(m * n + n * (n + 1)) * (f32 ? 0x1p-24 : 0x1p-53) : 0.0;
     TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s,
-                     shift_c));
+                     shift_c, ws.go));
     Gemm<T> h;  // dst = src Rinv, in the storage precision
     h.A = src;
     h.lda = n;
@@ -675,7 +684,9 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     h.M = m;
     h.N = n;
     h.K = n;
-    TTR_TRY(gemm_run<T>(h, s));
+    GemmX hx = h.x();
+    hx.gate = ws.go;
+    TTR_TRY(gemmx_run(hx, s));
   }
   // third pass when the first one was shifted and the Householder fallback
   // when a pivot broke down (no-ops otherwise); q1 and rinv are free again

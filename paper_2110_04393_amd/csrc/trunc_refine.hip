@@ -29,7 +29,7 @@
 //      Kept directions at the rounding level of B (no information left in
 //      them) get zero rows of F and columns of P, and the core receives
 //      orthonormal rows orthogonal to the others in their place
-//      ............................................ trunc_complete_kernel
+//      ............................. trunc_complete_prep/_rows_kernel
 // ctl[0] (1 = run this pass), ctl[1] = w and ctl[3] = the leading dimension
 // of the first pass's eigenvector array are written by the first pass; every
 // kernel here and the GEMMs of steps 2 and 4 return at once when ctl[0] = 0.
@@ -221,24 +221,25 @@ __global__ __launch_bounds__(kEigThreads) void trunc_final_kernel(const double *
 // zero row) receive orthonormal rows orthogonal to the others.  The good
 // rows are orthonormal, so for a unit vector e_i the residual
 // r = e_i - C^T C e_i = e_i - sum_j C(j, i) C_j is orthogonal to them with
-// no dot products to form, and |r|^2 = 1 - |C(:, i)|^2.  One workgroup
-// (always enqueued, returning at once unless the second pass found null
-// rows) takes the m columns i of smallest |C(:, i)| (their squares sum to
-// the number of good rows over cols >= k columns), forms the m x m Gram of
-// the residuals, delta_ab - C(:, i_a) . C(:, i_b), its Cholesky factor L and
-// the coefficients W = L^-1 A, A(a, j) = C(j, i_a), then writes row a of the
-// completion sum_b L^-1(a, b) e_{i_b} - sum_j W(a, j) C_j, one column per
-// thread.  sc: trunc_complete_scratch(k, cols) doubles.
+// no dot products to form, and |r|^2 = 1 - |C(:, i)|^2.  The first kernel
+// (one workgroup) takes the m columns i of smallest |C(:, i)| (their squares
+// sum to the number of good rows over cols >= k columns), forms the m x m
+// Gram of the residuals, delta_ab - C(:, i_a) .
+// C(:, i_b), its Cholesky factor L, and the coefficients W = L^-1 A,
+// A(a, j) = C(j, i_a); the second writes row a of the completion
+// sum_b L^-1(a, b) e_{i_b} - sum_j W(a, j) C_j, one column per thread.
+// sc: trunc_complete_scratch(k, cols) doubles.
 constexpr int kCompThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kCompThreads) void trunc_complete_kernel(
-    T *C, int k, int64_t cols, const int *ctl, const int *nullmask, double *sc) {
+__global__ __launch_bounds__(kCompThreads) void trunc_complete_prep_kernel(
+    const T *C, int k, int64_t cols, const int *ctl, const int *nullmask, double *sc) {
   if (ctl[0] == 0 || ctl[2] == 0) return;
   const int m = ctl[2];
   double *cn = sc;                        // cols: squared column norms of the good rows
   double *Li = cn + cols;                 // m x m
   double *W = Li + m * m;                 // m x k
+  int *sel = reinterpret_cast<int *>(W + m * k);
   double *s_g = W + m * k + m;            // m x m: the residuals' Gram, then its factor
   __shared__ int s_sel[kRefMaxN];
   const int tid = threadIdx.x;
@@ -327,25 +328,35 @@ __global__ __launch_bounds__(kCompThreads) void trunc_complete_kernel(
       for (int b = 0; b <= a; ++b) w += Li[a * m + b] * (double)C[(int64_t)j * cols + s_sel[b]];
     W[e] = w;
   }
-  // rows a of the completion (null rows s_rows[a] of C), one column per
-  // thread; Li and W were written by this workgroup above
+  for (int a = tid; a < m; a += kCompThreads) sel[a] = s_sel[a];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void trunc_complete_rows_kernel(T *C, int k, int64_t cols,
+                                                                  const int *ctl,
+                                                                  const int *nullmask,
+                                                                  const double *sc) {
+  if (ctl[0] == 0 || ctl[2] == 0) return;
+  const int m = ctl[2];
+  const double *Li = sc + cols, *W = Li + m * m;
+  const int *sel = reinterpret_cast<const int *>(W + m * k);
   __shared__ int s_rows[kRefMaxN];
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     int a = 0;
     for (int j = 0; j < k; ++j)
       if (nullmask[j]) s_rows[a++] = j;
   }
   __syncthreads();
-  for (int64_t c = tid; c < cols; c += kCompThreads) {
-    double col[kRefMaxN];
-    for (int j = 0; j < k; ++j) col[j] = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + c];
-    for (int a = 0; a < m; ++a) {
-      double v = 0.0;
-      for (int b = 0; b <= a; ++b)
-        if (s_sel[b] == c) v += Li[a * m + b];
-      for (int j = 0; j < k; ++j) v -= W[a * k + j] * col[j];
-      C[(int64_t)s_rows[a] * cols + c] = (T)v;
-    }
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double col[kRefMaxN];
+  for (int j = 0; j < k; ++j) col[j] = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + c];
+  for (int a = 0; a < m; ++a) {
+    double v = 0.0;
+    for (int b = 0; b <= a; ++b)
+      if (sel[b] == c) v += Li[a * m + b];
+    for (int j = 0; j < k; ++j) v -= W[a * k + j] * col[j];
+    C[(int64_t)s_rows[a] * cols + c] = (T)v;
   }
 }
 
@@ -418,8 +429,11 @@ template <typename T>
 int trunc_refine_complete(T *C, int64_t k, int64_t cols, const int *ctl, const int *nullmask,
                           double *scratch, hipStream_t s) {
   if (k > kRefMaxN || cols < k) return fail(TT_EINVAL, "internal: completion shape");
-  hipLaunchKernelGGL((trunc_complete_kernel<T>), dim3(1), dim3(kCompThreads), 0, s, C, (int)k,
-                     cols, ctl, nullmask, scratch);
+  hipLaunchKernelGGL((trunc_complete_prep_kernel<T>), dim3(1), dim3(kCompThreads), 0, s, C,
+                     (int)k, cols, ctl, nullmask, scratch);
+  TTR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((trunc_complete_rows_kernel<T>), dim3((unsigned)((cols + 255) / 256)),
+                     dim3(256), 0, s, C, (int)k, cols, ctl, nullmask, scratch);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }

@@ -300,6 +300,8 @@ struct QrScratch {
   int *flag = nullptr;         // 1 int
   void *partial = nullptr;     // split-K partials
   bool speculative = false;    // leave out the third pass and the Householder rescue
+  int *go = nullptr;           // speculative: launches run while *go != 0; a pivot
+                               // breakdown clears it (the caller redoes the sweep)
 };
 size_t qr_partial_elems(int64_t m, int64_t n);
 // FP64 Gram of a tall panel: G = A^T A (n x n, ld ldg) for A(k, m) stored
