@@ -180,11 +180,14 @@ TT_API int tt_partial_contractions_rl(int32_t N, const int64_t *dims,
  * after the stream has finished the rounding: it runs a speculative form
  * that leaves out the guarded rescue launches (the third CholeskyQR pass
  * after a shifted first pass, the Householder fallback, the second pass of
- * the truncation for kept directions far below the largest), reads the
- * per-core breakdown flags and per-bond truncation controls back once, and
- * when one is set redoes the rounding in the guarded form (all launches
- * enqueued, each rescue returning at once unless its flag is set) on the
- * same workspace.  Both forms give the same bits where no flag is set.
+ * the truncation for kept directions far below the largest).  It reads the
+ * per-core breakdown flags back after the sweep (a breakdown also stops the
+ * speculative sweep's remaining launches on the device) and redoes the sweep
+ * in the guarded form (all launches enqueued, each rescue returning at once
+ * unless its flag is set) when one is set, the truncation then running
+ * guarded as well; otherwise it reads the per-bond truncation controls back
+ * after the truncation and redoes the truncation guarded when one is set.
+ * Both forms give the same bits where no flag is set.
  * Under stream capture, or with TT_SPECULATE=0 in the environment, only the
  * guarded form is enqueued and the call returns without waiting.  The same
  * holds for tt_round_rand_with_sketch and tt_sum_round.
