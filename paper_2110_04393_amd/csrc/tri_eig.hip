@@ -403,20 +403,22 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
     s_dr[i] = (i < n) ? d_in[n - 1 - i] : 4.0;
     s_er[i] = (i < n - 1) ? e_in[n - 2 - i] : 0.0;
   }
-  {
-    // reflectors and taus, eight loads in flight per lane
-    const int total = (n - 2) * n;
-    for (int e0 = lane; e0 < total; e0 += 8 * 64) {
-      double t[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = (e0 + 64 * u < total) ? Vr[e0 + 64 * u] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (e0 + 64 * u < total) s_V[e0 + 64 * u] = t[u];
-    }
-    for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
-  }
+  for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
   __syncthreads();
+  // The reflectors go from global memory straight to LDS (16 bytes per lane
+  // and load, no registers) while the eigenvalue and the twisted
+  // factorisation run, which do not read them; the barrier after the
+  // factorisation waits for the loads.  Only the waves that form an
+  // eigenvector load them (and so never end with a load in flight).  A lane
+  // loads the pair e, e + 1 with e < total <= n^2 - 2, inside Vr's n^2 values.
+  if (w < k) {
+    const int total = (n - 2) * n;
+    for (int e0 = 0; e0 < total; e0 += 128)
+      if (e0 + 2 * lane < total)
+        __builtin_amdgcn_global_load_lds(
+            static_cast<const void *>(Vr + e0 + 2 * lane),
+            (__attribute__((address_space(3))) void *)(s_V + e0), 16, 0, 0);
+  }
 
   const int a = n - 1 - w;
   double lo = -1.0 - 1e-13, hi = 1.0 + 1e-13;
