@@ -480,11 +480,34 @@ def metric_second_half(args, tt, wl, timed, build, dev, out64, res):
     log(f"near-low-rank variant: f64 {low_ms['f64']:.3f}, bf16 {low_ms['bf16']:.3f}, "
         f"f32 {low_ms['f32']:.3f} ms/rounding")
     res["mixed_precision"] = mp
+    res["deterministic_comparator"] = deterministic_comparator(args, tt, timed, dev)
     # the batched form
     bres, b_outs, b_specs, b_inputs = run_batched(args, "f32", with_f64=True)
     res["batched"] = bres
     return dict(low_in=low_in, low_out=low_out, lw=lw, b_outs=b_outs, b_specs=b_specs,
                 b_inputs=b_inputs)
+
+
+def deterministic_comparator(args, tt, timed, dev):
+    """Deterministic rounding (Algorithms 1 and 2, tt_round_svd) next to RtO on
+    the largest bond rank the comparator takes: N=30, I=100, rank 96, cores
+    N(0,1)/sqrt(I*R), rounded to rank 50 (RtO: sketch rank 60)."""
+    import torch
+
+    import tt_inputs as G
+    N, I, R = 30, 100, 96
+    dims, ranks = G.uniform_tt_shape(N, I, R)
+    Y = G.random_tt(G.INPUT_SEED_BASE + 7, dims, ranks, scale="nominal")
+    cores = [torch.from_numpy(c).to(dev) for c in Y]
+    plan = tt.RoundPlan(dims, ranks, 50, 10, "f64", dev)
+    steps = max(3, args.steps // 4)
+    ms_rand, _ = timed(lambda: plan.run(cores, seed=2001), steps, 1)
+    ms_svd, _ = timed(lambda: tt.round_svd(cores, eps0=0.0, max_rank=50), steps, 1)
+    log(f"deterministic comparator at N={N} I={I} R={R} -> 50: tt_round_svd {ms_svd:.3f} ms, "
+        f"RtO {ms_rand:.3f} ms ({ms_svd / ms_rand:.2f}x)")
+    return {"config": f"N={N}, I={I}, rank {R} -> 50 (RtO sketch 60)",
+            "ms_round_svd": round(ms_svd, 4), "ms_round_rand": round(ms_rand, 4),
+            "ratio_svd_over_rand": round(ms_svd / ms_rand, 3)}
 
 
 def extra_accuracy(extra, res):

@@ -92,3 +92,18 @@ def test_round_svd_single_core(gpu_lib):
     Y = G.random_tt(5, [7], [1, 1])
     out = host(gpu_lib.round_svd(dev(Y), eps0=0.1))
     np.testing.assert_array_equal(out[0], Y[0])
+
+
+def test_round_svd_largest_bond(gpu_lib):
+    # bond rank 96, the largest the comparator takes (the Cholesky and Jacobi
+    # solvers of n = 96), kept rank 50: the configuration bench.py times it on
+    # (there N = 30, I = 100)
+    say("round_svd N=6 I=100 R=96 -> 50")
+    Y = G.random_tt(303, [100] * 6, [1] + [96] * 5 + [1], scale="nominal")
+    out = host(gpu_lib.round_svd(dev(Y), eps0=0.0, max_rank=50))
+    ref, rr, _ = O.round_svd(Y, 0.0, 50)
+    assert O.ranks_of(out) == rr
+    err = O.rel_diff(out, ref)
+    print(f"rel err vs oracle {err:.3e}")
+    assert err <= 1e-10
+    assert left_orth_dev(out) <= 1e-12
