@@ -75,12 +75,6 @@ __device__ __forceinline__ double min8(double v) {
   v = fmin(v, dppd<0x4E>(v));
   return fmin(v, dppd<0x141>(v));
 }
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 // full-wavefront sum, result uniform (all 64 lanes must be active)
 __device__ __forceinline__ double wave_sum(double v) {
   v = sum16(v);
@@ -174,22 +168,21 @@ __device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const dou
 // Householder tridiagonalisation of the n x n symmetric Gin (n <= NMAX, one
 // workgroup of four wavefronts, the matrix in registers).  Row i = 16 a + ty
 // belongs to wavefront a % 4 and is spread over the lane quad 4 ty .. 4 ty + 3:
-// lane tq holds the columns c = tq + 4 b.  The matrix is kept exactly
-// symmetric (the rank-2 update rounds both products before adding them), so
-// column j of step j is row j and the quad owning it builds the reflector
-// alone; p = tau A v is a quad reduction within the owners of each row.  Per
+// lane tq holds the columns c = tq + 4 b.  The rank-2 update is two FMAs
+// per entry, so the matrix stays symmetric to rounding only; the quad
+// owning row j builds the reflector of step j from that row (an O(u ||A||)
+// perturbation of the symmetric step, as the update's own rounding), and
+// p = tau A v is a quad reduction within the owners of each row.  Per
 // column the wavefronts exchange v, then p and the partial sums of p^T v,
 // through LDS: two barriers.  Writes the scaled d (n), e (n-1) with
 // ||T|| sc <= 1, the scale sc, and the reflectors (Vr row j = v_j over rows
 // j+1..n-1, v_j[0] = 1; taus[j]) to global scratch.
 constexpr int kTrThreads = 256;
 
-// a - (vi wc + wi vc) with both products rounded: the same bits for (i, c)
-// and (c, i)
+// a - vi wc - wi vc (two FMAs)
 __device__ __forceinline__ double sym_update(double a, double vi, double wc, double wi,
                                              double vc) {
-#pragma clang fp contract(off)
-  return a - (vi * wc + wi * vc);
+  return fma(-vi, wc, fma(-wi, vc, a));
 }
 
 template <int NMAX>

@@ -28,6 +28,14 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v + dppd<0x4E>(v);
 }
 
+// value of lane `lane` (wavefront-uniform) in every lane
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // f(integral_constant<int, I>) for I = B .. E-1, unrolled at compile time
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
