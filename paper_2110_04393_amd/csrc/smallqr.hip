@@ -13,8 +13,10 @@
 // original diagonal entry, the same Cholesky kernel factors G + s I instead,
 // s = 11 (m n + n (n + 1)) u trace(G) (shifted CholeskyQR, Fukaya et al.
 // 2020), and sets flag bit 1; the second pass runs as usual and a third
-// CholeskyQR pass (the cholqr_fix_* kernels, no-ops unless bit 1 is set)
-// restores orthogonality to rounding.
+// CholeskyQR pass restores orthogonality to rounding: the Gram kernel, the
+// one-workgroup rescue kernel (the blocked Cholesky below with a stricter
+// pivot test) and the GEMM Q R^-1 with a copy back, all gated on flag word 1,
+// which the second pass sets when the first was shifted.
 //
 // Robust path: Householder QR in one workgroup, used for panels of at most 8
 // columns and, without a host round trip, whenever a pivot still breaks down
@@ -61,10 +63,11 @@ int g_qr_mode = 0;  // 0 auto, 1 householder, 2 cholqr2
 // column; the LDS panel buffer alternates, so a panel is never overwritten
 // while it is read.
 //
-// A pivot d_j that is not finite or not above 1e-14 of the original diagonal
-// entry raises the flag (or_flag = 0: flag overwritten, else or-ed) and is
-// replaced by the original diagonal (1 if that is not positive) so that the
-// results stay finite.
+// A pivot d_j that is not finite or not above piv_rel (1e-14) of the
+// original diagonal entry raises the flag (or_flag = 0: flag overwritten,
+// else or-ed) and is replaced by the original diagonal (1 if that is not
+// positive) so that the results stay finite.  NW wavefronts (4, or 16 in the
+// third pass's one-workgroup kernel) share the block rows.
 //
 // The second pass of CholeskyQR2 (or_flag = 1) factors G = Q1^T Q1 = I + E
 // with E of the order of cond(Y)^2 u.  When max |E_ij| <= tol the factor is
@@ -78,14 +81,15 @@ constexpr int kCholThreads = 256;
 constexpr double kNearIdentity = 0x1p-30, kNearIdentityF32 = 0x1p-17;
 typedef double chol_d4 __attribute__((ext_vector_type(4)));
 
-template <int NMAX>
+template <int NMAX, int NW = 4>
 __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rinv,
                                                     float *Rinv_f, int n, int *flag,
                                                     int or_flag, double sh = 0.0,
-                                                    int mark = 0) {
-  constexpr int NRB = NMAX / 16;       // block rows
-  constexpr int NCB = 2 * NRB;         // block columns of [G | I]
-  constexpr int NSL = (NRB + 3) / 4;   // block rows per wavefront
+                                                    int mark = 0, double piv_rel = 1e-14) {
+  constexpr int NT = 64 * NW;               // threads
+  constexpr int NRB = NMAX / 16;            // block rows
+  constexpr int NCB = 2 * NRB;              // block columns of [G | I]
+  constexpr int NSL = (NRB + NW - 1) / NW;  // block rows per wavefront
   static_assert(NMAX % 16 == 0, "rows in blocks of 16");
   __shared__ double s_pan[2][4][2 * NMAX];  // the scaled rows of a panel
   __shared__ double s_d0[NMAX];
@@ -95,9 +99,9 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
 
   if (or_flag) {
     // second pass: first-order factor when G is within 2^-30 of I
-    __shared__ double s_emax[4];
+    __shared__ double s_emax[NW];
     double em = 0.0;
-    for (int e = tid; e < n * n; e += kCholThreads) {
+    for (int e = tid; e < n * n; e += NT) {
       const int i = e / n, c = e - i * n;
       em = fmax(em, fabs(G[e] - (i == c ? 1.0 : 0.0)));
     }
@@ -109,9 +113,11 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
     em = fmax(em, __shfl_xor(em, 1));
     if (lane == 0) s_emax[wave] = em;
     __syncthreads();
-    const double emax = fmax(fmax(s_emax[0], s_emax[1]), fmax(s_emax[2], s_emax[3]));
+    double emax = s_emax[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) emax = fmax(emax, s_emax[w]);
     if (emax <= (Rinv_f ? kNearIdentityF32 : kNearIdentity)) {  // also false for NaN
-      for (int e = tid; e < n * n; e += kCholThreads) {
+      for (int e = tid; e < n * n; e += NT) {
         const int i = e / n, c = e - i * n;
         const double x = (i == c) ? 1.0 - 0.5 * (G[e] - 1.0) : ((i < c) ? -G[e] : 0.0);
         Rinv[e] = x;
@@ -124,7 +130,7 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
   chol_d4 X[NSL][NCB];
 #pragma unroll
   for (int sl = 0; sl < NSL; ++sl) {
-    const int I = wave + 4 * sl;
+    const int I = wave + NW * sl;
 #pragma unroll
     for (int J = 0; J < NCB; ++J) {
 #pragma unroll
@@ -143,14 +149,14 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
       }
     }
   }
-  for (int i = tid; i < NMAX; i += kCholThreads) s_d0[i] = (i < n) ? G[i * n + i] + sh : 1.0;
+  for (int i = tid; i < NMAX; i += NT) s_d0[i] = (i < n) ? G[i * n + i] + sh : 1.0;
   if (tid == 0) s_bad = 0;
   __syncthreads();
   int bad = 0;
 
   static_for<0, NMAX / 4>([&](auto pc) __attribute__((always_inline)) {
     constexpr int p = decltype(pc)::value;
-    constexpr int j0 = 4 * p, I0 = j0 / 16, w0 = I0 % 4, sl0 = I0 / 4, jj0 = (j0 % 16) / 4;
+    constexpr int j0 = 4 * p, I0 = j0 / 16, w0 = I0 % NW, sl0 = I0 / NW, jj0 = (j0 % 16) / 4;
     constexpr int buf = p & 1;
     // live block columns: left part from I0 on, right part up to column j0 + 3
     constexpr int JR = NRB + (j0 + 3) / 16;
@@ -173,7 +179,7 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
 #pragma unroll
       for (int u = 0; u < t; ++u) d = fma(-R4[u][t], R4[u][t], d);
       const double d0 = s_d0[j0 + t];
-      if (!(d > 1e-14 * d0) || !(d0 > 0.0) || !isfinite(d)) {
+      if (!(d > piv_rel * d0) || !(d0 > 0.0) || !isfinite(d)) {
         d = (d0 > 0.0 && isfinite(d0)) ? d0 : 1.0;
         bad = 1;
       }
@@ -226,7 +232,7 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
     // gives A[r][q] = -P_q(row 16 I + r) and B[q][r] = P_q(16 J + r))
 #pragma unroll
     for (int sl = 0; sl < NSL; ++sl) {
-      const int I = wave + 4 * sl;
+      const int I = wave + NW * sl;
       if (I >= I0 && I < NRB) {
         const int row = 16 * I + r;
         const double a = (row > j0 + 3) ? -panel_at(row) : 0.0;
@@ -242,7 +248,7 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
   // Rinv[c][i] = B[i][c] (right block, lower triangular)
 #pragma unroll
   for (int sl = 0; sl < NSL; ++sl) {
-    const int I = wave + 4 * sl;
+    const int I = wave + NW * sl;
     if (I < NRB) {
 #pragma unroll
       for (int J = NRB; J < NCB; ++J) {
@@ -284,6 +290,9 @@ __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1,
                                                                 int *go) {
   if (go && *go == 0) return;
   const int bad = chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, or_flag);
+  // second pass: word 1 = the third pass is due (the first pass was shifted
+  // and nothing broke down since)
+  if (or_flag && threadIdx.x == 0) flag[1] = ((flag[0] & 3) == 2) ? 1 : 0;
   if (!bad) return;
   if (go) {
     if (threadIdx.x == 0) *go = 0;
@@ -298,160 +307,6 @@ __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1,
   }
   __syncthreads();
   chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, 0, shift_c * s_trace, 2);
-}
-
-// Third CholeskyQR pass on Q (m x n row-major, n <= 96), in place, run only
-// when the first pass needed its shift (flag == 2), in three kernels that
-// return at once otherwise:
-//   fix_gram:  workgroup w forms the FP64 Gram of its rows (fix_rows(m) of
-//              them, staged 32 at a time in LDS) into part + w n n (upper
-//              triangle);
-//   fix_chol:  one workgroup adds the partial Grams in workgroup order,
-//              factors G = R^T R and writes R^{-1} to rinv; a pivot not above
-//              1e-4 of its diagonal entry (cond(Q)^2 too large for one pass
-//              to restore orthogonality to rounding) sets flag bit 0, and the
-//              same workgroup then recomputes Q from Y by Householder QR (as
-//              it does when bit 0 was already set by the second pass);
-//   fix_apply: Q <- Q R^{-1}, the same rows per workgroup, unless bit 0 is set.
-constexpr int kFixThreads = 256, kFixRows = 32, kFixMaxGroups = 32;
-constexpr int kFixPer = (96 * 97 / 2 + kFixThreads - 1) / kFixThreads;
-constexpr int kFixCholThreads = 1024;
-
-int64_t fix_rows(int64_t m) {  // rows per workgroup: a multiple of 32, at most 32 groups
-  // (few workgroups: the launches are enqueued on every QR and are usually
-  // no-ops, whose cost grows with the grid)
-  const int64_t ch = (m + kFixRows - 1) / kFixRows;
-  return kFixRows * ((ch + kFixMaxGroups - 1) / kFixMaxGroups);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kFixThreads) void cholqr_fix_gram_kernel(const T *Q, int64_t m, int n,
-                                                                      int64_t rows,
-                                                                      const int *flag,
-                                                                      double *part) {
-  if ((*flag & 3) != 2) return;
-  __shared__ double B[kFixRows * 96];
-  const int tid = threadIdx.x;
-  const int npair = n * (n + 1) / 2;
-  double acc[kFixPer];
-  int pi[kFixPer], pj[kFixPer];
-#pragma unroll
-  for (int t = 0; t < kFixPer; ++t) {
-    const int e = tid + t * kFixThreads;
-    int i = 0, rem = e;
-    while (e < npair && rem >= n - i) {
-      rem -= n - i;
-      ++i;
-    }
-    pi[t] = i;
-    pj[t] = i + rem;
-    acc[t] = 0.0;
-  }
-  const int64_t rbeg = (int64_t)blockIdx.x * rows, rend = min<int64_t>(m, rbeg + rows);
-  for (int64_t r0 = rbeg; r0 < rend; r0 += kFixRows) {
-    const int nr = (int)min<int64_t>(kFixRows, rend - r0);
-    __syncthreads();
-    for (int e = tid; e < kFixRows * n; e += kFixThreads)
-      B[e] = e < nr * n ? (double)Q[r0 * n + e] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kFixPer; ++t) {
-      if (tid + t * kFixThreads < npair) {
-        double a = acc[t];
-#pragma unroll 4
-        for (int r = 0; r < kFixRows; ++r) a = fma(B[r * n + pi[t]], B[r * n + pj[t]], a);
-        acc[t] = a;
-      }
-    }
-  }
-  double *P = part + (int64_t)blockIdx.x * n * n;
-#pragma unroll
-  for (int t = 0; t < kFixPer; ++t)
-    if (tid + t * kFixThreads < npair) P[pi[t] * n + pj[t]] = acc[t];
-}
-
-__device__ __forceinline__ int cholqr_fix_chol_body(int n, int groups, const double *part,
-                                                   double *rinv, int *flag) {
-  extern __shared__ double fx_lds[];
-  double *A = fx_lds;          // G, then R (upper)
-  double *B = fx_lds + n * n;  // R^{-1}
-  __shared__ double s_r, s_d0[96];
-  __shared__ int s_bad;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += kFixCholThreads) {
-    const int i = e / n, j = e - i * n;
-    if (j < i) continue;
-    double a = 0.0;
-    for (int w = 0; w < groups; ++w) a += part[(int64_t)w * n * n + e];
-    A[e] = a;
-  }
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int j = tid; j < n; j += kFixCholThreads) s_d0[j] = A[j * n + j];
-  __syncthreads();
-  // right-looking Cholesky on the upper triangle: A = R^T R
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double d = A[j * n + j];
-      if (!(d > 1e-4 * s_d0[j]) || !isfinite(d)) {
-        s_bad = 1;
-        d = 1.0;
-      }
-      s_r = sqrt(d);
-      A[j * n + j] = s_r;
-    }
-    __syncthreads();
-    const double rj = s_r;
-    for (int c = j + 1 + tid; c < n; c += kFixCholThreads) A[j * n + c] /= rj;
-    __syncthreads();
-    const int w = n - j - 1;
-    for (int e = tid; e < w * w; e += kFixCholThreads) {
-      const int i = j + 1 + e / w, c = j + 1 + e % w;
-      if (c >= i) A[i * n + c] -= A[j * n + i] * A[j * n + c];
-    }
-    __syncthreads();
-  }
-  // R^{-1} (upper) by back substitution, one column per thread
-  for (int c = tid; c < n; c += kFixCholThreads) {
-    for (int j = n - 1; j > c; --j) B[j * n + c] = 0.0;
-    B[c * n + c] = 1.0 / A[c * n + c];
-    for (int j = c - 1; j >= 0; --j) {
-      double sum = 0.0;
-      for (int k = j + 1; k <= c; ++k) sum = fma(A[j * n + k], B[k * n + c], sum);
-      B[j * n + c] = -sum / A[j * n + j];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += kFixCholThreads) rinv[e] = B[e];
-  const int bad = s_bad;
-  if (tid == 0 && bad) *flag = *flag | 1;
-  return bad;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kFixThreads) void cholqr_fix_apply_kernel(T *Q, int64_t m, int n,
-                                                                       int64_t rows,
-                                                                       const double *rinv,
-                                                                       const int *flag) {
-  if ((*flag & 3) != 2) return;
-  extern __shared__ double fx_lds[];
-  double *X = fx_lds;          // R^{-1}, n x n
-  double *A = fx_lds + n * n;  // 32 rows of Q
-  const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += kFixThreads) X[e] = rinv[e];
-  const int64_t rbeg = (int64_t)blockIdx.x * rows, rend = min<int64_t>(m, rbeg + rows);
-  for (int64_t r0 = rbeg; r0 < rend; r0 += kFixRows) {
-    const int nr = (int)min<int64_t>(kFixRows, rend - r0);
-    __syncthreads();
-    for (int e = tid; e < nr * n; e += kFixThreads) A[e] = (double)Q[r0 * n + e];
-    __syncthreads();
-    for (int e = tid; e < nr * n; e += kFixThreads) {
-      const int r = e / n, c = e - r * n;
-      double sum = 0.0;
-      for (int k = 0; k <= c; ++k) sum = fma(A[r * n + k], X[k * n + c], sum);
-      Q[r0 * n + e] = (T)sum;
-    }
-  }
 }
 
 // One workgroup Householder QR of the m x n row-major Y into Q (m x n), with
@@ -574,26 +429,43 @@ __global__ __launch_bounds__(kHhThreads) void householder_kernel(const T *Y, T *
   householder_kernel_body<T>(Y, Q, work_g, rdiag, tau, m, n, flag, always, use_lds);
 }
 
-// The one-workgroup part of the rescue after the second CholeskyQR pass: the
-// third pass's Cholesky when the first pass was shifted (flag bits 1..0 = 10),
-// then Householder QR of Y into Q when bit 0 is set (by the second pass, by
-// the shifted first pass, or by that Cholesky).  The flag is read once at the
-// start; the Cholesky's verdict reaches the Householder step through LDS.
-static_assert(kFixCholThreads == kHhThreads, "one workgroup shape for both steps");
-template <typename T>
-__global__ __launch_bounds__(kHhThreads) void cholqr_rescue_kernel(int n, int groups,
-                                                                   const double *part,
-                                                                   double *rinv, int *flag,
-                                                                   const T *Y, T *Q, T *work_g,
-                                                                   int64_t m, int use_lds) {
-  const int fl = *flag;
+// The one-workgroup part of the rescue after the second CholeskyQR pass.
+// When the third pass is due (flag word 1, set by the second pass when the
+// first one was shifted) it factors the Gram of Q (G3) by the blocked
+// Cholesky with a pivot test of 1e-4 of the diagonal (cond(Q)^2 too large
+// for one more pass to restore orthogonality to rounding fails it) into
+// rinv; a failed pivot sets flag bit 0 and clears word 1.  Then, when bit 0
+// is set (by the second pass, by the shifted first pass or by that
+// Cholesky), Householder QR of Y into Q (word 1 cleared, so the gated GEMM
+// and copy of the third pass do nothing).  Words read once at the start.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(kHhThreads) void cholqr_rescue_kernel(const double *G3, double *rinv,
+                                                                   float *rinv_f, int n,
+                                                                   int *flag, const T *Y, T *Q,
+                                                                   T *work_g, int64_t m,
+                                                                   int use_lds) {
+  const int fl = flag[0], due = flag[1];
   int hh = fl & 1;
-  if ((fl & 3) == 2 && cholqr_fix_chol_body(n, groups, part, rinv, flag)) hh = 1;
+  if (due) {
+    // or_flag 0 with mark 2: flag word 0 reads 2 after it, 3 on a failed pivot
+    if (chol_inv_kernel_body<NMAX, kHhThreads / 64>(G3, rinv, rinv_f, n, flag, 0, 0.0, 2, 1e-4))
+      hh = 1;
+  }
   if (!hh) return;
   __syncthreads();
-  // rdiag = rinv[0..n), tau = rinv[n..2n): R^{-1} of the third pass is not
-  // applied once bit 0 is set
+  if (threadIdx.x == 0) flag[1] = 0;
+  // rdiag = rinv[0..n), tau = rinv[n..2n)
   householder_kernel_body<T>(Y, Q, work_g, rinv, rinv + n, m, n, flag, 1, use_lds);
+}
+
+// dst = src for count elements when *gate != 0
+template <typename T>
+__global__ __launch_bounds__(256) void gated_copy_kernel(T *dst, const T *src, int64_t count,
+                                                         const int *gate) {
+  if (*gate == 0) return;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * 256)
+    dst[e] = src[e];
 }
 
 template <int NMAX>
@@ -619,10 +491,7 @@ size_t qr_partial_elems(int64_t m, int64_t n) {
   // the Gram takes (both sizes, so that the choice can change between calls)
   const int sp = gemm_pick_splits(n, n, m, DType::F64);
   const size_t gemm_need = sp > 1 ? (size_t)sp * n * n : 0;
-  // and the partial Grams of the third pass (ill-conditioned panels)
-  const size_t fix_need = (size_t)(((m + fix_rows(m) - 1) / fix_rows(m)) * n * n);
-  return std::max(std::max(gemm_need, fix_need),
-                  gram_supported(n, m) ? gram_partial_elems(n, m) : (size_t)0);
+  return std::max(gemm_need, gram_supported(n, m) ? gram_partial_elems(n, m) : (size_t)0);
 }
 
 template <int NMAX>
@@ -667,37 +536,108 @@ static int householder(const T *Y, T *Q, T *work, double *rdiag, double *tau, in
   return TT_OK;
 }
 
-// Third pass and Householder rescue after the second CholeskyQR pass (all
-// three launches return at once on a panel that needed neither); q1 is the
-// Householder's global scratch when the panel does not fit in LDS.
+// G = src^T src (n x n, FP64) by the Gram kernel, or the split-K GEMM where
+// it does not apply; nothing runs while *gate is 0 (gate may be null)
 template <typename T>
-static int cholqr_fix(const T *Y, T *Q, T *q1, int64_t m, int64_t n, int *flag, double *part,
-                      size_t part_bytes, double *rinv, hipStream_t s) {
-  if (n > 96) return fail(TT_EUNSUPPORTED, "QR panel wider than 96");
-  const int64_t rows = fix_rows(m);
-  const int64_t groups = (m + rows - 1) / rows;
-  if ((size_t)(groups * n * n) * sizeof(double) > part_bytes || !part)
-    return fail(TT_EINVAL, "internal: split buffer too small for the third QR pass");
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_rescue_kernel<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
-    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_fix_apply_kernel<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048));
-    attr_set = true;
+static int qr_gram(const T *src, int64_t m, int64_t n, QrScratch &ws, const int *gate,
+                   hipStream_t s) {
+  if (gram_enabled(n, m))
+    return gram_run(src, DTypeOf<T>::value, false, n, n, m, ws.gram, n, ws.partial,
+                    gram_partial_elems(n, m) * sizeof(double), s, gate);
+  GemmX g;  // accumulated in FP64
+  g.A = src;
+  g.lda = n;
+  g.a_kc = false;
+  g.ta = DTypeOf<T>::value;
+  g.B = src;
+  g.ldb = n;
+  g.b_kc = false;
+  g.tb = DTypeOf<T>::value;
+  g.C = ws.gram;
+  g.ldc = n;
+  g.tc = DType::F64;
+  g.math = DType::F64;
+  g.M = n;
+  g.N = n;
+  g.K = m;
+  g.splits = gemm_pick_splits(n, n, m, DType::F64);
+  g.partial = ws.partial;
+  g.gate = gate;
+  return gemmx_run(g, s);
+}
+
+// dst = src Rinv (m x n times the n x n R^-1, in the storage precision)
+template <typename T>
+static int qr_apply(const T *src, T *dst, int64_t m, int64_t n, const T *rinv, const int *gate,
+                    hipStream_t s) {
+  Gemm<T> h;
+  h.A = src;
+  h.lda = n;
+  h.a_kc = true;
+  h.B = rinv;
+  h.ldb = n;
+  h.b_kc = false;
+  h.C = dst;
+  h.ldc = n;
+  h.M = m;
+  h.N = n;
+  h.K = n;
+  GemmX hx = h.x();
+  hx.gate = gate;
+  return gemmx_run(hx, s);
+}
+
+template <typename T, int NMAX>
+static int rescue_launch(const double *G3, double *rinv, float *rinv_f, int n, int *flag,
+                         const T *Y, T *Q, T *q1, int64_t m, hipStream_t s) {
+  // the Householder step keeps the panel in LDS when it fits beside the
+  // kernel's static LDS (the Cholesky's panel buffers), else in q1
+  static size_t max_dyn = 0;
+  if (!max_dyn) {
+    hipFuncAttributes fa;
+    TTR_HIP(hipFuncGetAttributes(&fa, (const void *)cholqr_rescue_kernel<T, NMAX>));
+    const size_t dyn = 160 * 1024 - fa.sharedSizeBytes;
+    TTR_HIP(hipFuncSetAttribute((const void *)cholqr_rescue_kernel<T, NMAX>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    max_dyn = dyn;
   }
-  hipLaunchKernelGGL((cholqr_fix_gram_kernel<T>), dim3((unsigned)groups), dim3(kFixThreads), 0, s,
-                     Q, m, (int)n, rows, flag, part);
+  const size_t need = 2 * sizeof(T) * (size_t)(m * n);
+  const bool hh_lds = (m * n <= kHhLdsElems) && need <= max_dyn;
+  const size_t lds = hh_lds ? need : 0;
+  hipLaunchKernelGGL((cholqr_rescue_kernel<T, NMAX>), dim3(1), dim3(kHhThreads), lds, s, G3,
+                     rinv, rinv_f, n, flag, Y, Q, q1, m, hh_lds ? 1 : 0);
   TTR_HIP(hipGetLastError());
-  const bool hh_lds = (m * n <= kHhLdsElems);
-  const size_t lds = std::max(2 * (size_t)(n * n) * sizeof(double),
-                              hh_lds ? 2 * sizeof(T) * (size_t)(m * n) : (size_t)0);
-  hipLaunchKernelGGL((cholqr_rescue_kernel<T>), dim3(1), dim3(kHhThreads), lds, s, (int)n,
-                     (int)groups, part, rinv, flag, Y, Q, q1, m, hh_lds ? 1 : 0);
-  TTR_HIP(hipGetLastError());
-  hipLaunchKernelGGL((cholqr_fix_apply_kernel<T>), dim3((unsigned)groups), dim3(kFixThreads),
-                     (size_t)(n * n + kFixRows * n) * sizeof(double), s, Q, m, (int)n, rows,
-                     rinv, flag);
+  return TT_OK;
+}
+
+// The guarded rescue after the second CholeskyQR pass, all gated on the
+// device (nothing runs on a panel that needs neither): the third pass, G3 =
+// Q^T Q, its Cholesky and R3^-1, q1 = Q R3^-1 and Q <- q1 (gated on flag word
+// 1), and the Householder fallback inside the rescue kernel (flag bit 0).
+// q1 and rinv are free again once the second pass's GEMMs have run (same
+// stream); q1 is also the Householder's global scratch when the panel does
+// not fit in LDS.
+template <typename T>
+static int cholqr_fix(const T *Y, T *Q, T *q1, int64_t m, int64_t n, QrScratch &ws,
+                      hipStream_t s) {
+  if (n > 96) return fail(TT_EUNSUPPORTED, "QR panel wider than 96");
+  const bool f32 = sizeof(T) == 4;
+  int *const due = ws.flag + 1;
+  TTR_TRY(qr_gram<T>(Q, m, n, ws, due, s));
+  float *rf = f32 ? ws.rinv_f : nullptr;
+  if (n <= 32) {
+    TTR_TRY((rescue_launch<T, 32>(ws.gram, ws.rinv, rf, (int)n, ws.flag, Y, Q, q1, m, s)));
+  } else if (n <= 64) {
+    TTR_TRY((rescue_launch<T, 64>(ws.gram, ws.rinv, rf, (int)n, ws.flag, Y, Q, q1, m, s)));
+  } else {
+    TTR_TRY((rescue_launch<T, 96>(ws.gram, ws.rinv, rf, (int)n, ws.flag, Y, Q, q1, m, s)));
+  }
+  const T *rinv_t = f32 ? reinterpret_cast<const T *>(ws.rinv_f)
+                        : reinterpret_cast<const T *>(ws.rinv);
+  TTR_TRY(qr_apply<T>(Q, q1, m, n, rinv_t, due, s));
+  const int64_t cnt = m * n;
+  const unsigned blocks = (unsigned)std::min<int64_t>((cnt + 255) / 256, 1024);
+  hipLaunchKernelGGL((gated_copy_kernel<T>), dim3(blocks), dim3(256), 0, s, Q, q1, cnt, due);
   TTR_HIP(hipGetLastError());
   return TT_OK;
 }
@@ -718,60 +658,20 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   for (int pass = 0; pass < 2; ++pass) {
     const T *src = pass == 0 ? Y : q1;
     T *dst = pass == 0 ? q1 : Q;
-    if (gram_enabled(n, m)) {
-      TTR_TRY(gram_run(src, DTypeOf<T>::value, false, n, n, m, ws.gram, n, ws.partial,
-                       gram_partial_elems(n, m) * sizeof(double), s, ws.go));
-    } else {
-    GemmX g;  // G = src^T src, accumulated in FP64
-    g.A = src;
-    g.lda = n;
-    g.a_kc = false;
-    g.ta = DTypeOf<T>::value;
-    g.B = src;
-    g.ldb = n;
-    g.b_kc = false;
-    g.tb = DTypeOf<T>::value;
-    g.C = ws.gram;
-    g.ldc = n;
-    g.tc = DType::F64;
-    g.math = DType::F64;
-    g.M = n;
-    g.N = n;
-    g.K = m;
-    g.splits = gemm_pick_splits(n, n, m, DType::F64);
-    g.partial = ws.partial;
-    g.gate = ws.go;
-    TTR_TRY(gemmx_run(g, s));
-    }
+    TTR_TRY(qr_gram<T>(src, m, n, ws, ws.go, s));
     // first pass: shifted retry on breakdown, s = 11 (m n + n (n + 1)) u trace(G)
     // with u the unit roundoff of the storage (shifted CholeskyQR3)
     const double shift_c =
         pass == 0 ? 11.0 * (double)(m * n + n * (n + 1)) * (f32 ? 0x1p-24 : 0x1p-53) : 0.0;
     TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s,
                      shift_c, ws.go));
-    Gemm<T> h;  // dst = src Rinv, in the storage precision
-    h.A = src;
-    h.lda = n;
-    h.a_kc = true;
-    h.B = rinv_t;
-    h.ldb = n;
-    h.b_kc = false;
-    h.C = dst;
-    h.ldc = n;
-    h.M = m;
-    h.N = n;
-    h.K = n;
-    GemmX hx = h.x();
-    hx.gate = ws.go;
-    TTR_TRY(gemmx_run(hx, s));
+    TTR_TRY(qr_apply<T>(src, dst, m, n, rinv_t, ws.go, s));  // dst = src Rinv
   }
   // third pass when the first one was shifted and the Householder fallback
-  // when a pivot broke down (no-ops otherwise); q1 and rinv are free again
-  // once the GEMMs above have run (same stream).  The speculative form leaves
+  // when a pivot broke down (no-ops otherwise).  The speculative form leaves
   // them out: its caller reads the flag back and redoes the QR guarded.
   if (ws.speculative) return TT_OK;
-  return cholqr_fix<T>(Y, Q, q1, m, n, ws.flag, static_cast<double *>(ws.partial),
-                       qr_partial_elems(m, n) * sizeof(double), ws.rinv, s);
+  return cholqr_fix<T>(Y, Q, q1, m, n, ws, s);
 }
 
 template int qr_thin<double>(const double *, double *, int64_t, int64_t, QrScratch &,
