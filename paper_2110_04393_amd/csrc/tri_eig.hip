@@ -31,6 +31,7 @@
 // always enqueued after this one and return at once unless the flag is set.
 #include "fastmath.h"
 #include "jacobi.h"
+#include "ldsmm.h"
 #include "tt_internal.h"
 #include "wave.h"
 
@@ -91,41 +92,6 @@ __device__ __forceinline__ double wave_min(double v) {
 
 // ---------------------------------------------------------------- LDS GEMM
 typedef double d4_t __attribute__((ext_vector_type(4)));
-
-// C(MxN) = alpha * op(A)(MxK) * B(KxN) + beta * Cin, all in LDS (row-major,
-// leading dimensions lda/ldb/ldc), op(A) = A or A^T; the output may go to
-// global memory (ldc row-major).  16x16 blocks are dealt round-robin to the
-// wavefronts; f64 MFMA layout: A lane (r, q) = A[m0+r][k+q], B lane =
-// B[k+q][n0+r], D register j = row q + 4j, column r.
-template <bool TA>
-__device__ void lds_gemm(const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                         int M, int N, int K, double alpha, const double *Cin, int ldci,
-                         double beta) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
-  const int bm = (M + 15) / 16, bn = (N + 15) / 16;
-  for (int blk = wave; blk < bm * bn; blk += nw) {
-    const int m0 = (blk / bn) * 16, n0 = (blk % bn) * 16;
-    d4_t acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + q;
-      const int m = m0 + r, n = n0 + r;
-      double a = 0.0, b = 0.0;
-      if (k < K && m < M) a = TA ? A[k * lda + m] : A[m * lda + k];
-      if (k < K && n < N) b = B[k * ldb + n];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = m0 + q + 4 * j, col = n0 + r;
-      if (row < M && col < N) {
-        double v = alpha * acc[j];
-        if (beta != 0.0) v += beta * Cin[row * ldci + col];
-        C[row * ldc + col] = v;
-      }
-    }
-  }
-}
 
 // Z (n x k, LDS, leading dimension ld) <- Z E (E: k x k, LDS, lde), in place:
 // every 16-row block of Z is owned by one wavefront, which finishes all its
@@ -640,7 +606,7 @@ __device__ __forceinline__ bool tri_finish_part(
     mingap = wave_min(mingap);
     if (lane == 0 && !(mingap >= 1e-9)) s_bad = 1;
   }
-  lds_gemm<true>(Z, ld, Z, ld, E, ld, kc, kc, n, 1.0, nullptr, 0, 0.0);
+  lds_gemm<true, false>(Z, ld, Z, ld, E, ld, kc, kc, n, 1.0, nullptr, 0, 0.0);
   __syncthreads();
   {
     double dev = 0.0;

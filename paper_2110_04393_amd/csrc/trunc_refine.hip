@@ -23,7 +23,7 @@
 //      accuracy at the scale of that block), T = blockdiag(I_w, U2_{k-w})
 //      (l x k), the Gram of the kept rows T^T B is T^T G2 T = L L^T
 //      (Cholesky, which also removes the small strong-weak couplings), and
-//      F = L^-1 T^T, P = U1 G2 F^T ................... trunc_solve_kernel
+//      F = L^-1 T^T, P = U1 G2 F^T ...... trunc_weak_kernel, trunc_final_kernel
 //   4. new core C = F B (orthonormal rows, GEMM) and X_{n-1} <- X_{n-1} P:
 //      P C = U1 B B^T F^T F B is H projected onto the kept row space.
 //      Kept directions at the rounding level of B (no information left in
@@ -35,8 +35,10 @@
 // kernel here and the GEMMs of steps 2 and 4 return at once when ctl[0] = 0.
 #include <algorithm>
 
+#include "cholblk.h"
 #include "fastmath.h"
 #include "jacobi.h"
+#include "ldsmm.h"
 #include "tt_internal.h"
 
 namespace ttr {
@@ -45,9 +47,8 @@ namespace {
 constexpr int kRefMaxN = TT_MAX_SKETCH_RANK;
 
 // Step 3 of the header.  scratch: gw (n*n), lam2 (n), U2 (n*n), M1 (n*k),
-// Q2 (n*k) doubles.  F (k x n) and P (n x k) are written in the storage type
-// T.  Dynamic LDS: the Jacobi solve's, at least k (2k + 1) doubles (the
-// Cholesky factor and its inverse).
+// Q2 (n*k), R^-1 (k*k) doubles (trunc_refine_scratch).  F (k x n) and P
+// (n x k) are written in the storage type T.
 constexpr double kNullRel = 1e-26;
 
 // Eigenpairs of the weak block G2[w:, w:] (lam2 descending, U2 columns),
@@ -66,141 +67,99 @@ __device__ void weak_block_eig(const double *G2, int n, int w, double *scratch) 
 
 // From the weak-block eigenvectors: T = blockdiag(I_w, U2[:, :k-w]), the
 // Cholesky factor L of T^T G2 T (null directions detected), F = L^-1 T^T
-// and P = U1 G2 F^T.
-template <typename T>
+// and P = U1 G2 F^T.  The products are f64 MFMA block products of the
+// workgroup (lds_gemm); L^T and L^-T come from the blocked factorisation of
+// the QR (cholblk.h) in its null mode, T^T G2 T staged in LDS.  scratch: gw
+// (n*n, free again after the weak-block solve: F before its rounding), lam2
+// (n), U2 (n*n), M1 (n*k, later P before its rounding), Q2 (n*k), R^-1
+// (k*k).  Dynamic LDS: at least k*k doubles.
+template <typename T, int NMAX>
 __device__ void refine_factors(const double *G2, const double *U1, int n, int k, int *ctl,
                                int *nullmask, double *scratch, T *F, T *P) {
   extern __shared__ double lds[];
   const int w = ctl[1];
-  const int nw = n - w;
+  const int nw = n - w, kw = k - w;
+  double *Ft = scratch;
   double *U2 = scratch + n * n + n, *M1 = U2 + n * n;
-  double *Q2 = M1 + n * k;
+  double *Q2 = M1 + n * k, *Ri = Q2 + n * k;
+  double *Gt = lds;  // k x k
   const int tid = threadIdx.x;
-  // T(i, j) = delta_ij (j < w); U2(i - w, j - w) (j >= w, i >= w); else 0
-  auto Tij = [&](int i, int j) -> double {
-    if (j < w) return i == j ? 1.0 : 0.0;
-    return i >= w ? U2[(i - w) * nw + (j - w)] : 0.0;
-  };
-  // M1 = G2 T (n x k)
-  for (int e = tid; e < n * k; e += blockDim.x) {
-    const int i = e / k, j = e - i * k;
-    double acc = 0.0;
-    if (j < w) {
-      acc = G2[i * n + j];
-    } else {
-      for (int m = w; m < n; ++m) acc += G2[i * n + m] * U2[(m - w) * nw + (j - w)];
-    }
-    M1[e] = acc;
+  // M1 = G2 T: the first w columns are those of G2, the others G2[:, w:] U2[:, :k-w]
+  for (int e = tid; e < n * w; e += blockDim.x) {
+    const int i = e / w, j = e - i * w;
+    M1[i * k + j] = G2[i * n + j];
   }
+  if (kw > 0) lds_gemm<false, false>(G2 + w, n, U2, nw, M1 + w, k, n, kw, nw);
   __syncthreads();
-  // Gt = T^T M1 (k x k) into LDS, ld k + 1
-  const int ldl = k + 1;
-  double *L = lds, *Li = lds + k * ldl;  // Li: k x k, leading dimension k
-  for (int e = tid; e < k * k; e += blockDim.x) {
-    const int a = e / k, b = e - a * k;
-    double acc = 0.0;
-    if (a < w) {
-      acc = M1[a * k + b];
-    } else {
-      for (int m = w; m < n; ++m) acc += U2[(m - w) * nw + (a - w)] * M1[m * k + b];
-    }
-    L[a * ldl + b] = acc;
-  }
+  // Gt = T^T M1: the first w rows are those of M1, the others U2[:, :k-w]^T M1[w:, :]
+  for (int e = tid; e < w * k; e += blockDim.x) Gt[e] = M1[e];
+  if (kw > 0) lds_gemm<true, false>(U2, nw, M1 + w * k, k, Gt + w * k, k, kw, k, nw);
   __syncthreads();
   // symmetrise (the two triangles of T^T G2 T differ by rounding)
   for (int e = tid; e < k * k; e += blockDim.x) {
     const int a = e / k, b = e - a * k;
     if (a > b) {
-      const double v = 0.5 * (L[a * ldl + b] + L[b * ldl + a]);
-      L[a * ldl + b] = v;
+      const double v = 0.5 * (Gt[a * k + b] + Gt[b * k + a]);
+      Gt[a * k + b] = v;
+      Gt[b * k + a] = v;
     }
   }
-  __syncthreads();
-  // Cholesky Gt = L L^T (lower triangle, column by column).  A kept weak
-  // direction whose part orthogonal to the previous ones is at the rounding
-  // level of B (pivot <= kNullRel max_i G2_ii, i.e. below about 1e-13 of the
-  // largest singular value) carries no information: its row of F and column
-  // of P are set to zero and trunc_complete_kernel gives the core an
-  // orthonormal row in its place.
-  __shared__ int s_null;
+  // A kept weak direction whose part orthogonal to the previous ones is at
+  // the rounding level of B (pivot <= kNullRel max_i G2_ii, i.e. below about
+  // 1e-13 of the largest singular value) carries no information: its row of
+  // F and column of P are set to zero and trunc_complete_prep/_rows_kernel
+  // give the core an orthonormal row in its place.
   __shared__ double s_gmax;
   if (tid == 0) {
     double gm = 0.0;
     for (int i = 0; i < n; ++i) gm = fmax(gm, G2[i * n + i]);
     s_gmax = gm;
-    s_null = 0;
   }
   __syncthreads();
-  const double dnull = kNullRel * s_gmax;
-  for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      const double d = L[j * ldl + j];
-      const bool null = !(d > dnull);
-      if (null) ++s_null;
-      nullmask[j] = null ? 1 : 0;
-      L[j * ldl + j] = null ? 1e300 : sqrt(d);
-    }
-    __syncthreads();
-    const double ljj = L[j * ldl + j];
-    for (int i = j + 1 + tid; i < k; i += blockDim.x) L[i * ldl + j] /= ljj;
-    __syncthreads();
-    for (int e = tid; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
-      const int i = j + 1 + e / (k - j - 1), c = j + 1 + e % (k - j - 1);
-      if (c <= i) L[i * ldl + c] -= L[i * ldl + j] * L[c * ldl + j];
-    }
-    __syncthreads();
+  // Gt = R^T R, Ri = R^-1 (upper); L = R^T, L^-1 = Ri^T
+  chol_inv_kernel_body<NMAX, kEigThreads / 64>(Gt, Ri, nullptr, k, nullptr, 0, 0.0, 0, 0.0,
+                                               nullmask, kNullRel * s_gmax);
+  // F = L^-1 T^T (k x n): columns < w are those of L^-1, the others
+  // L^-1[:, w:k] U2[:, :k-w]^T = Ri[w:k, :]^T U2[:, :k-w]^T
+  for (int e = tid; e < k * w; e += blockDim.x) {
+    const int a = e / w, b = e - a * w;
+    Ft[a * n + b] = Ri[b * k + a];
   }
-  // Li = L^-1 (lower), one column per thread by forward substitution
-  for (int c = tid; c < k; c += blockDim.x) {
-    for (int i = 0; i < k; ++i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int m = c; m < i; ++m) acc -= L[i * ldl + m] * Li[m * k + c];
-      Li[i * k + c] = (i < c) ? 0.0 : acc / L[i * ldl + i];
-    }
-  }
+  if (kw > 0) lds_gemm<true, true>(Ri + w * k, k, U2, nw, Ft + w, n, k, nw, kw);
+  // Q2 = M1 L^-T = M1 Ri (n x k) = G2 T L^-T = G2 F^T
+  lds_gemm<false, false>(M1, k, Ri, k, Q2, k, n, k, k);
   __syncthreads();
-  // F = Li T^T (k x n);  Q2 = M1 Li^T (n x k) = G2 F^T
   for (int e = tid; e < k * n; e += blockDim.x) {
-    const int a = e / n, i = e - a * n;
-    double acc = 0.0;
-    for (int b = 0; b <= a; ++b) acc += Li[a * k + b] * Tij(i, b);
-    F[e] = nullmask[a] ? (T)0 : (T)acc;
+    const int a = e / n;
+    F[e] = nullmask[a] ? (T)0 : (T)Ft[e];
   }
-  for (int e = tid; e < n * k; e += blockDim.x) {
-    const int i = e / k, a = e - i * k;
-    double acc = 0.0;
-    for (int b = 0; b <= a; ++b) acc += M1[i * k + b] * Li[a * k + b];
-    Q2[e] = acc;
-  }
+  // P = U1 Q2 (n x k), into M1
+  lds_gemm<false, false>(U1, n, Q2, k, M1, k, n, k, n);
   __syncthreads();
-  // P = U1 Q2 (n x k)
   for (int e = tid; e < n * k; e += blockDim.x) {
-    const int i = e / k, a = e - i * k;
-    double acc = 0.0;
-    for (int m = 0; m < n; ++m) acc += U1[i * n + m] * Q2[m * k + a];
-    P[e] = nullmask[a] ? (T)0 : (T)acc;
+    const int a = e % k;
+    P[e] = nullmask[a] ? (T)0 : (T)M1[e];
   }
-  if (tid == 0) ctl[2] = s_null;
+  if (tid == 0) {
+    int cnt = 0;
+    for (int a = 0; a < k; ++a) cnt += nullmask[a];
+    ctl[2] = cnt;
+  }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kEigThreads) void trunc_solve_kernel(const double *G2,
-                                                                  const double *U1, int n, int k,
-                                                                  int *ctl, int *nullmask,
-                                                                  double *scratch, T *F, T *P) {
-  if (ctl[0] == 0) return;
-  weak_block_eig(G2, n, ctl[1], scratch);
-  refine_factors<T>(G2, U1, n, k, ctl, nullmask, scratch, F, P);
-}
-
-// tolerance mode: the weak eigenpairs first, the factors once k is known
+// The weak eigenpairs (the factors follow in trunc_final_kernel, in
+// tolerance mode once k is known).  With lamc: the spectrum the rank is
+// chosen from, also when the second pass does not run; without: nothing
+// runs unless it does.
 __global__ __launch_bounds__(kEigThreads) void trunc_weak_kernel(const double *G2, int n,
                                                                  const int *ctl, double *scratch,
                                                                  const double *lam,
                                                                  double *lamc) {
   const int w = ctl[1];
   const bool second = ctl[0] != 0;
+  if (!second && !lamc) return;
   if (second) weak_block_eig(G2, n, w, scratch);
+  if (!lamc) return;
   // the spectrum the rank is chosen from: first-pass eigenvalues above the
   // split, second-pass ones below it
   const double *lam2 = scratch + n * n;
@@ -208,13 +167,13 @@ __global__ __launch_bounds__(kEigThreads) void trunc_weak_kernel(const double *G
     lamc[j] = (second && j >= w) ? lam2[j - w] : lam[j];
 }
 
-template <typename T>
+template <typename T, int NMAX>
 __global__ __launch_bounds__(kEigThreads) void trunc_final_kernel(const double *G2,
                                                                   const double *U1, int n, int k,
                                                                   int *ctl, int *nullmask,
                                                                   double *scratch, T *F, T *P) {
   if (ctl[0] == 0) return;
-  refine_factors<T>(G2, U1, n, k, ctl, nullmask, scratch, F, P);
+  refine_factors<T, NMAX>(G2, U1, n, k, ctl, nullmask, scratch, F, P);
 }
 
 // Null rows of the new core C (k x cols, row-major; nullmask[j] = 1 marks a
@@ -406,23 +365,47 @@ size_t trunc_refine_scratch(int64_t n, int64_t k) {
   return (size_t)(n * n + n + n * n + n * k + n * k + 2 * k * k);
 }
 
+template <typename T, int NMAX>
+static int final_launch(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
+                        int *nullmask, double *scratch, T *F, T *P, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)k * (size_t)k;
+  hipLaunchKernelGGL((trunc_final_kernel<T, NMAX>), dim3(1), dim3(kEigThreads), lds, s, G2, U1,
+                     (int)n, (int)k, ctl, nullmask, scratch, F, P);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
+template <typename T>
+static int final_run(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
+                     int *nullmask, double *scratch, T *F, T *P, hipStream_t s) {
+  if (n > kRefMaxN || k < 1 || k > n) return fail(TT_EINVAL, "internal: refinement shape");
+  if (k <= 32) return final_launch<T, 32>(G2, U1, n, k, ctl, nullmask, scratch, F, P, s);
+  if (k <= 64) return final_launch<T, 64>(G2, U1, n, k, ctl, nullmask, scratch, F, P, s);
+  return final_launch<T, 96>(G2, U1, n, k, ctl, nullmask, scratch, F, P, s);
+}
+
+static int weak_launch(const double *G2, int64_t n, int *ctl, double *scratch, const double *lam,
+                       double *lamc, hipStream_t s) {
+  const int np = (int)((n + 1) & ~1);
+  const size_t lds = 2 * sizeof(double) * (size_t)np * (size_t)(np + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    TTR_HIP(hipFuncSetAttribute((const void *)trunc_weak_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(trunc_weak_kernel, dim3(1), dim3(kEigThreads), lds, s, G2, (int)n, ctl,
+                     scratch, lam, lamc);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+
 template <typename T>
 int trunc_refine_solve(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
                        int *nullmask, double *scratch, T *F, T *P, hipStream_t s) {
   if (n > kRefMaxN || k < 1 || k > n) return fail(TT_EINVAL, "internal: refinement shape");
-  const int np = (int)((n + 1) & ~1);
-  const size_t lds = std::max<size_t>(2 * sizeof(double) * (size_t)np * (size_t)(np + 1),
-                                      sizeof(double) * (size_t)k * (size_t)(2 * k + 1));
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)trunc_solve_kernel<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((trunc_solve_kernel<T>), dim3(1), dim3(kEigThreads), lds, s, G2, U1, (int)n,
-                     (int)k, ctl, nullmask, scratch, F, P);
-  TTR_HIP(hipGetLastError());
-  return TT_OK;
+  TTR_TRY(weak_launch(G2, n, ctl, scratch, nullptr, nullptr, s));
+  return final_run<T>(G2, U1, n, k, ctl, nullmask, scratch, F, P, s);
 }
 
 template <typename T>
@@ -450,35 +433,13 @@ int trunc_refine_eps(const double *G2, const double *U1, int64_t n, int *ctl, in
                      double *scratch, const double *lam, double *lamc, hipStream_t s) {
   (void)U1;
   (void)nullmask;
-  const int np = (int)((n + 1) & ~1);
-  const size_t lds = 2 * sizeof(double) * (size_t)np * (size_t)(np + 1);
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)trunc_weak_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(trunc_weak_kernel, dim3(1), dim3(kEigThreads), lds, s, G2, (int)n, ctl,
-                     scratch, lam, lamc);
-  TTR_HIP(hipGetLastError());
-  return TT_OK;
+  return weak_launch(G2, n, ctl, scratch, lam, lamc, s);
 }
 
 template <typename T>
 int trunc_refine_final(const double *G2, const double *U1, int64_t n, int64_t k, int *ctl,
                        int *nullmask, double *scratch, T *F, T *P, hipStream_t s) {
-  if (n > kRefMaxN || k < 1 || k > n) return fail(TT_EINVAL, "internal: refinement shape");
-  const size_t lds = sizeof(double) * (size_t)k * (size_t)(2 * k + 1);
-  static bool attr_set = false;
-  if (!attr_set) {
-    TTR_HIP(hipFuncSetAttribute((const void *)trunc_final_kernel<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((trunc_final_kernel<T>), dim3(1), dim3(kEigThreads), lds, s, G2, U1, (int)n,
-                     (int)k, ctl, nullmask, scratch, F, P);
-  TTR_HIP(hipGetLastError());
-  return TT_OK;
+  return final_run<T>(G2, U1, n, k, ctl, nullmask, scratch, F, P, s);
 }
 template int trunc_refine_eps<double>(const double *, const double *, int64_t, int *, int *,
                                       double *, const double *, double *, hipStream_t);
