@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kEigThreads) void trunc_final_kernel(const double *
 // sc: trunc_complete_scratch(k, cols) doubles.
 constexpr int kCompThreads = 1024;
 
-template <typename T>
+template <typename T, int NMAX>
 __global__ __launch_bounds__(kCompThreads) void trunc_complete_prep_kernel(
     const T *C, int k, int64_t cols, const int *ctl, const int *nullmask, double *sc) {
   if (ctl[0] == 0 || ctl[2] == 0) return;
@@ -199,16 +199,33 @@ __global__ __launch_bounds__(kCompThreads) void trunc_complete_prep_kernel(
   double *Li = cn + cols;                 // m x m
   double *W = Li + m * m;                 // m x k
   int *sel = reinterpret_cast<int *>(W + m * k);
-  double *s_g = W + m * k + m;            // m x m: the residuals' Gram, then its factor
+  double *Ri = W + m * k + m;             // m x m: R^-1 of the residuals' Gram R^T R
+  double *Gr = Ri + m * m;                // m x m: the residuals' Gram
+  extern __shared__ double cp_lds[];
+  double *Cs = cp_lds;                    // k x m: the selected columns (good rows)
   __shared__ int s_sel[kRefMaxN];
   const int tid = threadIdx.x;
+  // squared column norms; a thread's columns c = tid + t kCompThreads stay
+  // in registers for the selection when there are at most kPer of them
+  constexpr int kPer = 8;
+  const bool cached = cols <= (int64_t)kPer * kCompThreads;
+  double mine[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) mine[t] = 1e300;
   for (int64_t c = tid; c < cols; c += kCompThreads) {
     double a = 0.0;
+#pragma unroll 8
     for (int j = 0; j < k; ++j) {
       const double v = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + c];
-      a += v * v;
+      a = fma(v, v, a);
     }
-    cn[c] = a;
+    if (cached) {
+#pragma unroll
+      for (int t = 0; t < kPer; ++t)
+        if (c == tid + (int64_t)t * kCompThreads) mine[t] = a;
+    } else {
+      cn[c] = a;
+    }
   }
   __syncthreads();
   // the m columns of smallest norm, one block-wide argmin per pick (ties to
@@ -219,11 +236,20 @@ __global__ __launch_bounds__(kCompThreads) void trunc_complete_prep_kernel(
   for (int a = 0; a < m; ++a) {
     double bv = 1e300;
     int64_t bi = cols;
-    for (int64_t c = tid; c < cols; c += kCompThreads)
-      if (cn[c] < bv) {
-        bv = cn[c];
-        bi = c;
-      }
+    if (cached) {
+#pragma unroll
+      for (int t = 0; t < kPer; ++t)
+        if (mine[t] < bv) {
+          bv = mine[t];
+          bi = tid + (int64_t)t * kCompThreads;
+        }
+    } else {
+      for (int64_t c = tid; c < cols; c += kCompThreads)
+        if (cn[c] < bv) {
+          bv = cn[c];
+          bi = c;
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) {
       const double ov = __shfl_xor(bv, off);
       const int64_t oi = __shfl_xor(bi, off);
@@ -244,51 +270,46 @@ __global__ __launch_bounds__(kCompThreads) void trunc_complete_prep_kernel(
           s_bi[0] = s_bi[w2];
         }
       s_sel[a] = (int)s_bi[0];
-      cn[s_bi[0]] = 1e300;
+      if (!cached) cn[s_bi[0]] = 1e300;
     }
     __syncthreads();
+    if (cached) {
+      const int64_t cw = s_sel[a];
+#pragma unroll
+      for (int t = 0; t < kPer; ++t)
+        if (cw == tid + (int64_t)t * kCompThreads) mine[t] = 1e300;
+    }
   }
-  // Gram of the residuals, then its Cholesky factor in place (lower)
+  // the selected columns over the good rows into LDS, then the residuals'
+  // Gram delta_ab - C(:, i_a) . C(:, i_b)
+  for (int e = tid; e < k * m; e += kCompThreads) {
+    const int j = e / m, a = e - j * m;
+    Cs[e] = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + s_sel[a]];
+  }
+  __syncthreads();
   for (int e = tid; e < m * m; e += kCompThreads) {
     const int a = e / m, b = e - a * m;
     double g = (a == b) ? 1.0 : 0.0;
-    for (int j = 0; j < k; ++j) {
-      if (nullmask[j]) continue;
-      g -= (double)C[(int64_t)j * cols + s_sel[a]] * (double)C[(int64_t)j * cols + s_sel[b]];
-    }
-    s_g[a * m + b] = g;
+    for (int j = 0; j < k; ++j) g = fma(-Cs[j * m + a], Cs[j * m + b], g);
+    Gr[e] = g;
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int j = 0; j < m; ++j) {
-      double d = s_g[j * m + j];
-      for (int p = 0; p < j; ++p) d -= s_g[j * m + p] * s_g[j * m + p];
-      const double ljj = sqrt(fmax(d, 1e-300));
-      s_g[j * m + j] = ljj;
-      for (int i = j + 1; i < m; ++i) {
-        double v = s_g[i * m + j];
-        for (int p = 0; p < j; ++p) v -= s_g[i * m + p] * s_g[j * m + p];
-        s_g[i * m + j] = v / ljj;
-      }
-    }
-    for (int c = 0; c < m; ++c)
-      for (int i = 0; i < m; ++i) {
-        double acc = (i == c) ? 1.0 : 0.0;
-        for (int p = c; p < i; ++p) acc -= s_g[i * m + p] * Li[p * m + c];
-        Li[i * m + c] = (i < c) ? 0.0 : acc / s_g[i * m + i];
-      }
+  // Gr = R^T R (blocked factorisation of the QR), L = R^T, L^-1 = Ri^T
+  chol_inv_kernel_body<NMAX, kCompThreads / 64>(Gr, Ri, nullptr, m, nullptr, 0);
+  for (int e = tid; e < m * m; e += kCompThreads) {
+    const int i = e / m, c = e - i * m;
+    Li[e] = Ri[c * m + i];
   }
-  __syncthreads();
-  // W = Li A, A(a, j) = C(j, sel_a) over the good rows
+  // W = L^-1 A, A(a, j) = C(j, sel_a) over the good rows
   for (int e = tid; e < m * k; e += kCompThreads) {
     const int a = e / k, j = e - a * k;
     double w = 0.0;
-    if (!nullmask[j])
-      for (int b = 0; b <= a; ++b) w += Li[a * m + b] * (double)C[(int64_t)j * cols + s_sel[b]];
+    for (int b = 0; b <= a; ++b) w = fma(Ri[b * m + a], Cs[j * m + b], w);
     W[e] = w;
   }
   for (int a = tid; a < m; a += kCompThreads) sel[a] = s_sel[a];
 }
+
 
 template <typename T>
 __global__ __launch_bounds__(256) void trunc_complete_rows_kernel(T *C, int k, int64_t cols,
@@ -308,13 +329,19 @@ __global__ __launch_bounds__(256) void trunc_complete_rows_kernel(T *C, int k, i
   __syncthreads();
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
+  // the column in registers (loops unrolled to the largest k)
   double col[kRefMaxN];
-  for (int j = 0; j < k; ++j) col[j] = nullmask[j] ? 0.0 : (double)C[(int64_t)j * cols + c];
+#pragma unroll
+  for (int j = 0; j < kRefMaxN; ++j)
+    col[j] = (j < k && !nullmask[j]) ? (double)C[(int64_t)j * cols + c] : 0.0;
   for (int a = 0; a < m; ++a) {
     double v = 0.0;
     for (int b = 0; b <= a; ++b)
       if (sel[b] == c) v += Li[a * m + b];
-    for (int j = 0; j < k; ++j) v -= W[a * k + j] * col[j];
+    const double *wa = W + a * k;
+#pragma unroll
+    for (int j = 0; j < kRefMaxN; ++j)
+      if (j < k) v = fma(-wa[j], col[j], v);
     C[(int64_t)s_rows[a] * cols + c] = (T)v;
   }
 }
@@ -412,8 +439,17 @@ template <typename T>
 int trunc_refine_complete(T *C, int64_t k, int64_t cols, const int *ctl, const int *nullmask,
                           double *scratch, hipStream_t s) {
   if (k > kRefMaxN || cols < k) return fail(TT_EINVAL, "internal: completion shape");
-  hipLaunchKernelGGL((trunc_complete_prep_kernel<T>), dim3(1), dim3(kCompThreads), 0, s, C,
-                     (int)k, cols, ctl, nullmask, scratch);
+  // dynamic LDS: the selected columns (k x m, m <= k)
+  const size_t lds = sizeof(double) * (size_t)(k * k);
+  if (k <= 32)
+    hipLaunchKernelGGL((trunc_complete_prep_kernel<T, 32>), dim3(1), dim3(kCompThreads), lds, s,
+                       C, (int)k, cols, ctl, nullmask, scratch);
+  else if (k <= 64)
+    hipLaunchKernelGGL((trunc_complete_prep_kernel<T, 64>), dim3(1), dim3(kCompThreads), lds, s,
+                       C, (int)k, cols, ctl, nullmask, scratch);
+  else
+    hipLaunchKernelGGL((trunc_complete_prep_kernel<T, 96>), dim3(1), dim3(kCompThreads), lds, s,
+                       C, (int)k, cols, ctl, nullmask, scratch);
   TTR_HIP(hipGetLastError());
   hipLaunchKernelGGL((trunc_complete_rows_kernel<T>), dim3((unsigned)((cols + 255) / 256)),
                      dim3(256), 0, s, C, (int)k, cols, ctl, nullmask, scratch);
@@ -425,7 +461,9 @@ template int trunc_refine_complete<double>(double *, int64_t, int64_t, const int
 template int trunc_refine_complete<float>(float *, int64_t, int64_t, const int *, const int *,
                                           double *, hipStream_t);
 size_t trunc_complete_scratch(int64_t k, int64_t cols) {
-  return (size_t)(cols + 2 * k * k + k * k + 2 * k);
+  // norms (cols), L^-1 (m*m), W (m*k), the picks (m ints), R^-1 and the
+  // residuals' Gram (m*m each), m <= k
+  return (size_t)(cols + 4 * k * k + 2 * k);
 }
 
 template <typename T>
