@@ -398,8 +398,9 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   int *eflag = nullptr;
   double *escr = nullptr;
   T *Pf = nullptr, *Sf = nullptr, *tb[2] = {nullptr, nullptr};
-  // second pass for kept directions far below the largest (FP64 storage)
-  const bool refine = P.truncate && sizeof(T) == 8;
+  // second pass for kept directions far below the largest (its contractions
+  // in FP64 arithmetic whatever the storage)
+  const bool refine = P.truncate;
   int *ctl = nullptr, *nmask = nullptr;
   double *U1 = nullptr, *G2 = nullptr, *rscr = nullptr, *cscr = nullptr, *lamc = nullptr;
   T *Ff = nullptr, *Bb = nullptr;

@@ -690,6 +690,9 @@ bool dispatch(int v, const GemmX &g, const TileMap &tm, int64_t grid, hipStream_
     case tkey(D::F64, D::F32, D::F32, D::F64):
       launch_types<MathF64, float, float, double>(v, g, tm, grid, s, tab, count);
       return true;
+    case tkey(D::F64, D::F64, D::F32, D::F32):  // FP64 factor times FP32 storage
+      launch_types<MathF64, double, float, float>(v, g, tm, grid, s, tab, count);
+      return true;
     case tkey(D::F32, D::F32, D::F32, D::F32):
       launch_types<MathF32, float, float, float>(v, g, tm, grid, s, tab, count);
       return true;
