@@ -510,56 +510,61 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
   tri_vec_body<NMAX>(d_in, e_in, n, k, Vr, taus, lam_out, Uz, flag, blockIdx.x);
 }
 
-// U1 (n x n, row-major, global) = Q of the full Householder QR of the first
-// w columns of Z (LDS, leading dimension ld; overwritten by the reflectors):
-// an orthonormal basis whose first w columns are +-Z[:, :w] and whose others
-// span their complement (the basis of the second truncation pass,
-// trunc_refine.hip).  All threads of the workgroup.
-__device__ void complement_basis(double *Z, int ld, int n, int w, double *U1) {
-  __shared__ double s_tau[kTeNMax + 1], s_dot[kTeNMax + 1];
+// U1 (n x n, row-major, global) = [Z[:, :w] | C]: the w orthonormal columns
+// of Z (LDS, leading dimension ld) and an orthonormal basis C of their
+// complement (the basis of the second truncation pass, trunc_refine.hip).
+// C comes from a pivoted Cholesky factorisation of the projector
+// P = I - Z_w Z_w^T (rank n - w): P = C C^T with C of full column rank, so
+// C = V Q for any orthonormal basis V of range(P) and an orthogonal Q, i.e.
+// C has orthonormal columns itself; the diagonal pivoting keeps every step
+// at a pivot of at least (n - w - j) / n of the remaining trace.  n - w steps
+// of a rank-1 update, three barriers each.  P is formed in Pw (LDS, n x ld).
+// All threads of the workgroup.
+__device__ void complement_basis(const double *Z, int ld, int n, int w, double *Pw, double *U1) {
+  __shared__ double s_col[kTeNMax + 1];
+  __shared__ int s_piv;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = 0; j < w; ++j) {
-    if (wave == 0) {
-      double a = 0.0;
-      for (int i = j + lane; i < n; i += 64) a += Z[i * ld + j] * Z[i * ld + j];
-      const double nrm2 = wave_sum(a);
-      if (lane == 0) {
-        const double x0 = Z[j * ld + j];
-        const double nrm = sqrt(nrm2);
-        const double alpha = x0 >= 0.0 ? -nrm : nrm;
-        const double v0 = x0 - alpha;
-        const double vv = nrm2 - x0 * x0 + v0 * v0;
-        s_tau[j] = vv > 0.0 ? 2.0 / vv : 0.0;
-        Z[j * ld + j] = v0;
-      }
-    }
-    __syncthreads();
-    for (int c = j + 1 + wave; c < w; c += blockDim.x >> 6) {
-      double a = 0.0;
-      for (int i = j + lane; i < n; i += 64) a += Z[i * ld + j] * Z[i * ld + c];
-      a = wave_sum(a);
-      if (lane == 0) s_dot[c] = a;
-    }
-    __syncthreads();
-    for (int e = tid; e < (n - j) * (w - j - 1); e += blockDim.x) {
-      const int i = j + e / (w - j - 1), c = j + 1 + e % (w - j - 1);
-      Z[i * ld + c] -= s_tau[j] * Z[i * ld + j] * s_dot[c];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < n * n; e += blockDim.x) U1[e] = (e / n == e % n) ? 1.0 : 0.0;
+  lds_gemm<false, true>(Z, ld, Z, ld, Pw, ld, n, n, w, -1.0, nullptr, 0, 0.0);
   __syncthreads();
-  for (int j = w - 1; j >= 0; --j) {
-    for (int c = wave; c < n; c += blockDim.x >> 6) {
-      double a = 0.0;
-      for (int i = j + lane; i < n; i += 64) a += Z[i * ld + j] * U1[i * n + c];
-      a = wave_sum(a);
-      if (lane == 0) s_dot[c] = a;
+  for (int i = tid; i < n; i += blockDim.x) Pw[i * ld + i] += 1.0;
+  for (int e = tid; e < n * w; e += blockDim.x) {
+    const int i = e / w, c = e - i * w;
+    U1[i * n + c] = Z[i * ld + c];
+  }
+  __syncthreads();
+  for (int j = 0; j < n - w; ++j) {
+    if (wave == 0) {
+      double best = -1e300;
+      int bi = 0;
+      for (int i = lane; i < n; i += 64) {
+        const double d = Pw[i * ld + i];
+        if (d > best) {
+          best = d;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) s_piv = bi;
     }
     __syncthreads();
-    for (int e = tid; e < (n - j) * n; e += blockDim.x) {
-      const int i = j + e / n, c = e % n;
-      U1[i * n + c] -= s_tau[j] * Z[i * ld + j] * s_dot[c];
+    const int pv = s_piv;
+    const double rp = rsq_f64(fmax(Pw[pv * ld + pv], 1e-300));
+    for (int i = tid; i < n; i += blockDim.x) {
+      const double c = Pw[i * ld + pv] * rp;
+      s_col[i] = c;
+      U1[i * n + w + j] = c;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = e / n, c = e - i * n;
+      Pw[i * ld + c] = fma(-s_col[i], s_col[c], Pw[i * ld + c]);
     }
     __syncthreads();
   }
@@ -656,7 +661,7 @@ __device__ __forceinline__ bool tri_finish_part(
   }
   if (second) {
     __syncthreads();
-    complement_basis(Z, ld, n, kc, U1);
+    complement_basis(Z, ld, n, kc, E, U1);
   }
   return true;
 }
