@@ -536,17 +536,20 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   // A speculative sweep whose flags show a breakdown is redone guarded (the W
   // chain is kept), and the truncation then runs guarded too: an input that
   // needed the thin QR's rescue usually needs the truncation's second pass.
-  bool trunc_spec = P.spec;
+  // With a truncation following, the flags are read back after its first
+  // bond, so that one synchronisation covers both.
   TTR_TRY(sweep(P.spec));
   std::vector<int> hf;
-  if (P.spec && !c.dry) {
-    TTR_TRY(read_flags(c, sflags, 4 * (N + 1), hf));
+  auto sweep_bad = [&]() {
     bool bad = false;
     for (int n = 1; n <= N - 1; ++n) bad = bad || hf[(size_t)4 * n] != 0;
-    if (bad) {
+    return bad;
+  };
+  if (P.spec && !c.dry && !P.truncate) {
+    TTR_TRY(read_flags(c, sflags, 4 * (N + 1), hf));
+    if (sweep_bad()) {
       TimerPause tp;
       TTR_TRY(sweep(false));
-      trunc_spec = false;
     }
   }
 
@@ -566,11 +569,17 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     if (!c.dry) TTR_TRY(frob_norm<T>(xs[N], L[N - 1] * dims[N - 1], dnorm, c.s));
   }
   // the sweep's output xs stays intact: a speculative truncation whose
-  // controls show that a bond needed the second pass is redone guarded
-  auto truncate = [&](bool spec) -> int {
+  // controls show that a bond needed the second pass is redone guarded.
+  // truncate(spec, hi, lo) runs bonds hi down to lo, from the start when
+  // hi = N.
   const T *hsrc = xs[N];
   int64_t rr = 1;  // right rank of the current core
-  for (int n = N; n >= 2; --n) {
+  auto truncate = [&](bool spec, int n_hi, int n_lo) -> int {
+  if (n_hi == N) {
+    hsrc = xs[N];
+    rr = 1;
+  }
+  for (int n = n_hi; n >= n_lo; --n) {
     const int64_t lr = L[n - 1], kcap = P.out[n - 1], cols = dims[n - 1] * rr;
     const int64_t keig = P.eps_mode ? lr : kcap;
     if (gram_supported(lr, cols))  // both forms size the split buffer
@@ -727,15 +736,28 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
   }
   return TT_OK;
   };
-  TTR_TRY(truncate(trunc_spec));
-  if (trunc_spec && !c.dry) {
-    TTR_TRY(read_flags(c, sflags + 4 * (N + 1), 4 * (N + 1), hf));
-    bool bad = false;
-    for (int n = 2; n <= N; ++n) bad = bad || hf[(size_t)4 * n] != 0;
-    if (bad) {
-      TimerPause tp;
-      TTR_TRY(truncate(false));
-    }
+  if (!P.spec || c.dry) return truncate(P.spec, N, 2);
+  // speculative: the first bond, then one read-back of the sweep's flags and
+  // that bond's control; a bond that needs the second pass makes the whole
+  // truncation run guarded
+  TTR_TRY(truncate(true, N, N));
+  TTR_TRY(read_flags(c, sflags, 8 * (N + 1), hf));
+  if (sweep_bad()) {
+    TimerPause tp;
+    TTR_TRY(sweep(false));
+    return truncate(false, N, 2);
+  }
+  if (hf[(size_t)4 * (N + 1) + 4 * N] != 0) {
+    TimerPause tp;
+    return truncate(false, N, 2);
+  }
+  TTR_TRY(truncate(true, N - 1, 2));
+  TTR_TRY(read_flags(c, sflags + 4 * (N + 1), 4 * (N + 1), hf));
+  bool bad = false;
+  for (int n = 2; n <= N; ++n) bad = bad || hf[(size_t)4 * n] != 0;
+  if (bad) {
+    TimerPause tp;
+    TTR_TRY(truncate(false, N, 2));
   }
   return TT_OK;
 }
