@@ -181,13 +181,15 @@ TT_API int tt_partial_contractions_rl(int32_t N, const int64_t *dims,
  * that leaves out the guarded rescue launches (the third CholeskyQR pass
  * after a shifted first pass, the Householder fallback, the second pass of
  * the truncation for kept directions far below the largest).  It reads the
- * per-core breakdown flags back after the sweep (a breakdown also stops the
- * speculative sweep's remaining launches on the device) and redoes the sweep
- * in the guarded form (all launches enqueued, each rescue returning at once
- * unless its flag is set) when one is set, the truncation then running
- * guarded as well; otherwise it reads the per-bond truncation controls back
- * after the truncation and redoes the truncation guarded when one is set.
- * Both forms give the same bits where no flag is set.
+ * per-core breakdown flags back once, after the sweep and the truncation's
+ * first bond (a breakdown also stops the speculative sweep's remaining
+ * launches on the device): a set flag redoes the sweep in the guarded form
+ * (all launches enqueued, each rescue returning at once unless its flag is
+ * set) and runs the whole truncation guarded; a first bond that needs the
+ * second pass runs the whole truncation guarded; otherwise the truncation
+ * continues speculatively, its per-bond controls are read back at the end,
+ * and a set one redoes the truncation guarded.  Both forms give the same
+ * bits where no flag is set.
  * Under stream capture, or with TT_SPECULATE=0 in the environment, only the
  * guarded form is enqueued and the call returns without waiting.  The same
  * holds for tt_round_rand_with_sketch and tt_sum_round.
