@@ -76,18 +76,46 @@ __device__ __forceinline__ double min8(double v) {
   v = fmin(v, dppd<0x4E>(v));
   return fmin(v, dppd<0x141>(v));
 }
-// full-wavefront sum, result uniform (all 64 lanes must be active)
+// Full-wavefront reductions, result uniform (all 64 lanes must be active).
+// After the row reduction every lane of row r holds row r's result; row 1
+// then combines row 0's (lane 15) and row 3 row 2's (lane 47), and rows 2
+// and 3 combine lane 31's, so that lane 63 holds the result, in the order
+// (r0 op r1) op (r2 op r3) for sums.  Rows 0 and 2 combine a 0 read from
+// outside the broadcast in between, which never reaches lane 63.
 __device__ __forceinline__ double wave_sum(double v) {
   v = sum16(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  v += dpp_row_bcast<0x142, 0xA>(v);
+  v += dpp_row_bcast<0x143, 0xC>(v);
+  return readlane_d(v, 63);
+}
+// two sums at once, their steps interleaved
+__device__ __forceinline__ void wave_sum2(double &a, double &b) {
+  a += dppd<0xB1>(a);
+  b += dppd<0xB1>(b);
+  a += dppd<0x4E>(a);
+  b += dppd<0x4E>(b);
+  a += dppd<0x141>(a);
+  b += dppd<0x141>(b);
+  a += dppd<0x140>(a);
+  b += dppd<0x140>(b);
+  a += dpp_row_bcast<0x142, 0xA>(a);
+  b += dpp_row_bcast<0x142, 0xA>(b);
+  a += dpp_row_bcast<0x143, 0xC>(a);
+  b += dpp_row_bcast<0x143, 0xC>(b);
+  a = readlane_d(a, 63);
+  b = readlane_d(b, 63);
 }
 __device__ __forceinline__ double wave_max(double v) {
   v = max16(v);
-  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+  v = fmax(v, dpp_row_bcast<0x142, 0xA>(v));
+  v = fmax(v, dpp_row_bcast<0x143, 0xC>(v));
+  return readlane_d(v, 63);
 }
 __device__ __forceinline__ double wave_min(double v) {
   v = min16(v);
-  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
+  v = fmin(v, dpp_row_bcast<0x142, 0xA>(v));
+  v = fmin(v, dpp_row_bcast<0x143, 0xC>(v));
+  return readlane_d(v, 63);
 }
 
 // ---------------------------------------------------------------- LDS GEMM
@@ -142,7 +170,9 @@ __device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const dou
 // column the wavefronts exchange v, then p and the partial sums of p^T v,
 // through LDS: two barriers.  Writes the scaled d (n), e (n-1) with
 // ||T|| sc <= 1, the scale sc, and the reflectors (Vr row j = v_j over rows
-// j+1..n-1, v_j[0] = 1; taus[j]) to global scratch.
+// j+1..n-1, v_j[0] = 1; taus[j]) to global scratch, followed in Vr by the
+// products v_j^T v_(j+1) (j < n-3) with which the eigenvector kernel applies
+// the reflectors two at a time.
 constexpr int kTrThreads = 256;
 
 // a - vi wc - wi vc (two FMAs)
@@ -293,6 +323,13 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
     if (c < n) Vr[e] = s_V[j][(c & 3) * NB + (c >> 2)];
   }
   for (int j = tid; j < n - 2; j += kTrThreads) taus[j] = s_tau[j];
+  // v_j^T v_(j+1): v_(j+1) starts at row j + 2
+  for (int j = tid; j < n - 3; j += kTrThreads) {
+    double acc = 0.0;
+    for (int c = j + 2; c < n; ++c)
+      acc = fma(s_V[j][(c & 3) * NB + (c >> 2)], s_V[j + 1][(c & 3) * NB + (c >> 2)], acc);
+    Vr[(n - 2) * n + j] = acc;
+  }
   if (wave == 0) {
     double mx = 0.0;
     for (int i = lane; i < n; i += 64) {
@@ -328,15 +365,24 @@ __global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gi
 // without branches.
 //  * eigenvalue: 64-point multisection of [-1, 1] (9 iterations of a 65-fold
 //    shrink); lane l counts the sign changes of the leading-minor
-//    determinants p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} at its point
-//    (a zero p_i takes the sign opposite to p_{i-1}), rescaled by a power of
-//    two every 8 steps;
+//    determinants p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} at its point,
+//    rescaled by a power of two every 8 steps, one FMA per step on the
+//    dependent chain.  An exact zero p_i counts by its sign bit (+0 as
+//    positive): then p_{i+1} = -e_i^2 p_{i-1} has the sign opposite to
+//    p_{i-1}, so the two changes p_{i-1} -> p_i -> p_{i+1} count one whatever
+//    sign p_i is given, as in the usual convention; only a zero as the last
+//    minor (x itself an eigenvalue) may count differently, which moves x to
+//    one side of the bracket without changing the limit;
 //  * for w < k the eigenvector: twisted factorisation (lanes 0-31 the
 //    top-down LDL^T, lanes 32-63 the same recurrence on the reversed matrix,
 //    i.e. the bottom-up UDU^T), twist r = argmin |gamma_r|, z from products
 //    of the factors (log-step scans), then the Householder reflectors of
 //    kernel 1 applied backwards give u = Q z, written to column w of U (n x k)
-//    unnormalised by sc.
+//    unnormalised by sc.  The reflectors go two at a time: for the pair
+//    H_a H_b (a = b - 1, b applied first) both products v_b^T z and v_a^T z
+//    are reduced together, and v_a^T (H_b z) = v_a^T z - tau_b (v_a^T v_b)
+//    (v_b^T z) with v_a^T v_b from kernel 1, so the chain holds one wavefront
+//    reduction per pair.
 constexpr double kTiny = 1e-300;
 
 template <int NMAX>
@@ -349,8 +395,8 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   __shared__ double s_dr[NMAX + 1], s_er[NMAX + 1];  // T reversed, same padding
   __shared__ double s_f[2][NMAX];  // L_i (top-down), U_{n-1-i} (bottom-up)
   __shared__ double s_z[NMAX];
-  __shared__ double s_V[NMAX * NMAX];  // reflectors: s_V[j n + i - j - 1]
-  __shared__ double s_tau[NMAX];
+  __shared__ double s_V[NMAX * NMAX + 1];  // reflectors: s_V[j n + i - j - 1]; last: 0
+  __shared__ double s_tau[NMAX], s_vv[NMAX];  // tau_j, v_j^T v_(j+1)
   __shared__ double s_sc[2][2][128];   // scan buffers (lower, upper factors)
   const int lane = threadIdx.x;
   for (int i = lane; i <= NMAX; i += 64) {
@@ -363,6 +409,8 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
     s_er[i] = (i < n - 1) ? e_in[n - 2 - i] : 0.0;
   }
   for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
+  for (int j = lane; j < n - 3; j += 64) s_vv[j] = Vr[(n - 2) * n + j];
+  if (lane == 0) s_V[NMAX * NMAX] = 0.0;
   __syncthreads();
   // The reflectors go from global memory straight to LDS (16 bytes per lane
   // and load, no registers) while the eigenvalue and the twisted
@@ -384,12 +432,10 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   for (int it = 0; it < 9; ++it) {
     const double x = lo + (double)(lane + 1) * (hi - lo) * (1.0 / 65.0);
     double pp = 1.0, p = s_d[0] - x;
-    if (p == 0.0) p = -kTiny;
-    int cnt = (p < 0.0) ? 1 : 0;
+    int cnt = (int)((unsigned)__double2hiint(p) >> 31);
     static_for<1, NMAX>([&](auto ic) __attribute__((always_inline)) {
       constexpr int i = decltype(ic)::value;
-      double pn = fma(s_d[i] - x, p, -s_e2[i - 1] * pp);
-      pn = (pn == 0.0) ? ((p > 0.0) ? -kTiny : kTiny) : pn;
+      const double pn = fma(s_d[i] - x, p, -s_e2[i - 1] * pp);
       cnt += (int)((unsigned)(__double2hiint(pn) ^ __double2hiint(p)) >> 31);
       pp = p;
       p = pn;
@@ -488,15 +534,29 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   const double inv = rsq_f64(wave_sum(z0 * z0 + z1 * z1));
   z0 *= inv;
   z1 *= inv;
-  for (int j = n - 3; j >= 0; --j) {
-    const double tau = s_tau[j];
-    // v_j over rows j+1..n-1; lane row i holds v = Vr[j][i - j - 1]
-    const int i0 = lane, i1 = lane + 64;
-    const double v0 = (i0 > j && i0 < n) ? s_V[j * n + i0 - j - 1] : 0.0;
-    const double v1 = (i1 > j && i1 < n) ? s_V[j * n + i1 - j - 1] : 0.0;
-    const double dot = wave_sum(v0 * z0 + v1 * z1);
-    z0 = fma(-tau * dot, v0, z0);
-    z1 = fma(-tau * dot, v1, z1);
+  const int i0 = lane, i1 = lane + 64;
+  // v_j at the rows of this lane: rows outside j+1..n-1 read the zero kept
+  // after the reflectors, so every lane reads without a branch
+  auto vrow = [&](int j, int i) -> double {
+    return s_V[(i > j && i < n) ? j * n + i - j - 1 : NMAX * NMAX];
+  };
+  int j = n - 3;
+  for (; j >= 1; j -= 2) {
+    const int b = j, a = j - 1;
+    const double vb0 = vrow(b, i0), va0 = vrow(a, i0);
+    const double vb1 = NMAX > 64 ? vrow(b, i1) : 0.0, va1 = NMAX > 64 ? vrow(a, i1) : 0.0;
+    double sb = fma(vb1, z1, vb0 * z0), sa = fma(va1, z1, va0 * z0);
+    wave_sum2(sb, sa);
+    const double cb = s_tau[b] * sb;
+    const double ca = s_tau[a] * fma(-s_vv[a], cb, sa);
+    z0 = fma(-ca, va0, fma(-cb, vb0, z0));
+    z1 = fma(-ca, va1, fma(-cb, vb1, z1));
+  }
+  if (j == 0) {
+    const double v0 = vrow(0, i0), v1 = NMAX > 64 ? vrow(0, i1) : 0.0;
+    const double c0 = s_tau[0] * wave_sum(fma(v1, z1, v0 * z0));
+    z0 = fma(-c0, v0, z0);
+    z1 = fma(-c0, v1, z1);
   }
   if (lane < n) Uz[lane * k + w] = z0;
   if (lane + 64 < n) Uz[(lane + 64) * k + w] = z1;

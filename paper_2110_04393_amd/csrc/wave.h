@@ -6,13 +6,27 @@
 
 namespace ttr {
 
-// DPP move of a double within a row of 16 lanes (CTRL: the DPP control word)
+// DPP move of a double within a row of 16 lanes (CTRL: the DPP control word;
+// every lane's source lies in its own row, so no lane reads out of range and
+// the move needs no prior value in its destination)
 template <int CTRL>
 __device__ __forceinline__ double dppd(double v) {
   const long long x = __double_as_longlong(v);
   int lo = (int)(x & 0xffffffffll), hi = (int)(x >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP row broadcast of a double to the rows of ROWMASK: row_bcast:15 (0x142)
+// sends lane 15 of each row to the next row, row_bcast:31 (0x143) sends lane
+// 31 to rows 2 and 3; lanes of rows outside ROWMASK read 0
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_row_bcast(double v) {
+  const long long x = __double_as_longlong(v);
+  int lo = (int)(x & 0xffffffffll), hi = (int)(x >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
