@@ -105,6 +105,30 @@ __device__ __forceinline__ void wave_sum2(double &a, double &b) {
   a = readlane_d(a, 63);
   b = readlane_d(b, 63);
 }
+// three sums at once, their steps interleaved
+__device__ __forceinline__ void wave_sum3(double &a, double &b, double &c) {
+  a += dppd<0xB1>(a);
+  b += dppd<0xB1>(b);
+  c += dppd<0xB1>(c);
+  a += dppd<0x4E>(a);
+  b += dppd<0x4E>(b);
+  c += dppd<0x4E>(c);
+  a += dppd<0x141>(a);
+  b += dppd<0x141>(b);
+  c += dppd<0x141>(c);
+  a += dppd<0x140>(a);
+  b += dppd<0x140>(b);
+  c += dppd<0x140>(c);
+  a += dpp_row_bcast<0x142, 0xA>(a);
+  b += dpp_row_bcast<0x142, 0xA>(b);
+  c += dpp_row_bcast<0x142, 0xA>(c);
+  a += dpp_row_bcast<0x143, 0xC>(a);
+  b += dpp_row_bcast<0x143, 0xC>(b);
+  c += dpp_row_bcast<0x143, 0xC>(c);
+  a = readlane_d(a, 63);
+  b = readlane_d(b, 63);
+  c = readlane_d(c, 63);
+}
 __device__ __forceinline__ double wave_max(double v) {
   v = max16(v);
   v = fmax(v, dpp_row_bcast<0x142, 0xA>(v));
@@ -171,8 +195,8 @@ __device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const dou
 // through LDS: two barriers.  Writes the scaled d (n), e (n-1) with
 // ||T|| sc <= 1, the scale sc, and the reflectors (Vr row j = v_j over rows
 // j+1..n-1, v_j[0] = 1; taus[j]) to global scratch, followed in Vr by the
-// products v_j^T v_(j+1) (j < n-3) with which the eigenvector kernel applies
-// the reflectors two at a time.
+// products v_j^T v_(j+1) (j < n-3) and v_j^T v_(j+2) (j < n-4) with which
+// the eigenvector kernel applies the reflectors three at a time.
 constexpr int kTrThreads = 256;
 
 // a - vi wc - wi vc (two FMAs)
@@ -323,12 +347,13 @@ __device__ __forceinline__ void tri_reduce_body(const double *Gin, int n, double
     if (c < n) Vr[e] = s_V[j][(c & 3) * NB + (c >> 2)];
   }
   for (int j = tid; j < n - 2; j += kTrThreads) taus[j] = s_tau[j];
-  // v_j^T v_(j+1): v_(j+1) starts at row j + 2
-  for (int j = tid; j < n - 3; j += kTrThreads) {
+  // v_j^T v_(j+1) (v_(j+1) starts at row j + 2) and v_j^T v_(j+2) (row j + 3)
+  for (int t = tid; t < 2 * n - 7; t += kTrThreads) {
+    const int dist = t < n - 3 ? 1 : 2, j = t < n - 3 ? t : t - (n - 3);
     double acc = 0.0;
-    for (int c = j + 2; c < n; ++c)
-      acc = fma(s_V[j][(c & 3) * NB + (c >> 2)], s_V[j + 1][(c & 3) * NB + (c >> 2)], acc);
-    Vr[(n - 2) * n + j] = acc;
+    for (int c = j + 1 + dist; c < n; ++c)
+      acc = fma(s_V[j][(c & 3) * NB + (c >> 2)], s_V[j + dist][(c & 3) * NB + (c >> 2)], acc);
+    Vr[(n - 2) * n + t] = acc;
   }
   if (wave == 0) {
     double mx = 0.0;
@@ -375,14 +400,16 @@ __global__ __launch_bounds__(kTrThreads) void tri_reduce_kernel(const double *Gi
 //    one side of the bracket without changing the limit;
 //  * for w < k the eigenvector: twisted factorisation (lanes 0-31 the
 //    top-down LDL^T, lanes 32-63 the same recurrence on the reversed matrix,
-//    i.e. the bottom-up UDU^T), twist r = argmin |gamma_r|, z from products
+//    i.e. the bottom-up UDU^T; pivots as ratios of consecutive minors, so the
+//    chain is one FMA per step), twist r = argmin |gamma_r|, z from products
 //    of the factors (log-step scans), then the Householder reflectors of
 //    kernel 1 applied backwards give u = Q z, written to column w of U (n x k)
-//    unnormalised by sc.  The reflectors go two at a time: for the pair
-//    H_a H_b (a = b - 1, b applied first) both products v_b^T z and v_a^T z
-//    are reduced together, and v_a^T (H_b z) = v_a^T z - tau_b (v_a^T v_b)
-//    (v_b^T z) with v_a^T v_b from kernel 1, so the chain holds one wavefront
-//    reduction per pair.
+//    unnormalised by sc.  The reflectors go three at a time: for H_a H_b H_c
+//    (a = b - 1 = c - 2, c applied first) the products v_c^T z, v_b^T z,
+//    v_a^T z are reduced together, and the updates they miss follow from the
+//    products of the reflectors themselves (from kernel 1): v_b^T (H_c z) =
+//    v_b^T z - tau_c (v_b^T v_c) (v_c^T z), and so on, so the chain holds
+//    one wavefront reduction per block.
 constexpr double kTiny = 1e-300;
 
 template <int NMAX>
@@ -392,11 +419,13 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
                                              int w) {
   if (*flag) return;
   __shared__ double s_d[NMAX + 1], s_e[NMAX + 1], s_e2[NMAX + 1];
-  __shared__ double s_dr[NMAX + 1], s_er[NMAX + 1];  // T reversed, same padding
+  __shared__ double s_dr[NMAX + 1], s_er[NMAX + 1], s_er2[NMAX + 1];  // T reversed
+  __shared__ double2 s_pq[2 * NMAX];  // (p_i, p_{i-1}) of both directions
+  __shared__ double2 s_pqj[8 * 64];    // the other lanes' copies
   __shared__ double s_f[2][NMAX];  // L_i (top-down), U_{n-1-i} (bottom-up)
   __shared__ double s_z[NMAX];
   __shared__ double s_V[NMAX * NMAX + 1];  // reflectors: s_V[j n + i - j - 1]; last: 0
-  __shared__ double s_tau[NMAX], s_vv[NMAX];  // tau_j, v_j^T v_(j+1)
+  __shared__ double s_tau[NMAX], s_vv[NMAX], s_vv2[NMAX];  // tau_j, v_j^T v_(j+1), v_j^T v_(j+2)
   __shared__ double s_sc[2][2][128];   // scan buffers (lower, upper factors)
   const int lane = threadIdx.x;
   for (int i = lane; i <= NMAX; i += 64) {
@@ -407,9 +436,11 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
     s_e2[i] = ev * ev;
     s_dr[i] = (i < n) ? d_in[n - 1 - i] : 4.0;
     s_er[i] = (i < n - 1) ? e_in[n - 2 - i] : 0.0;
+    s_er2[i] = s_er[i] * s_er[i];
   }
   for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
   for (int j = lane; j < n - 3; j += 64) s_vv[j] = Vr[(n - 2) * n + j];
+  for (int j = lane; j < n - 4; j += 64) s_vv2[j] = Vr[(n - 2) * n + (n - 3) + j];
   if (lane == 0) s_V[NMAX * NMAX] = 0.0;
   __syncthreads();
   // The reflectors go from global memory straight to LDS (16 bytes per lane
@@ -454,22 +485,67 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   if (lane == 0) lam_out[w] = lam;
   if (w >= k) return;
   // twisted factorisation: lanes 0-31 run the top-down recurrence on T, lanes
-  // 32-63 on T reversed; lane 0 gives L_i, lane 32 gives U_{n-1-i}
+  // 32-63 on T reversed; lane 0 gives L_i, lane 32 gives U_{n-1-i}.  The
+  // pivots D_i = (d_i - lam) - e_{i-1}^2 / D_{i-1} are the ratios p_i / p_{i-1}
+  // of the leading minors of T - lam I, p_i = (d_i - lam) p_{i-1} -
+  // e_{i-1}^2 p_{i-2}: the chain runs that recurrence (one FMA per step, with
+  // the same relative perturbations of d_i - lam, e^2 and the result per step
+  // as the pivot recurrence), the writer keeps each pair (p_i, p_{i-1}) in one
+  // scale, and L_i = e_i / D_i = e_i p_{i-1} / p_i is formed afterwards for all
+  // i at once (a zero pivot replaced by a tiny one, as in the pivot form).
   const bool rev = lane >= 32;
   {
     const double *D = rev ? s_dr : s_d;
-    const double *E = rev ? s_er : s_e;
-    double *F = s_f[rev ? 1 : 0];
+    const double *E2 = rev ? s_er2 : s_e2;
+    // lanes 0 and 32 write step i to slot i, the others to eight slots of
+    // their own (one per step of a block): one store per step at a fixed
+    // offset from a block base, and no branch in the chain
     const bool writer = (lane & 31) == 0;
-    double dp = D[0] - lam;
-    static_for<0, NMAX - 1>([&](auto ic) __attribute__((always_inline)) {
-      constexpr int i = decltype(ic)::value;
-      if (dp == 0.0) dp = kTiny;
-      const double ei = E[i];
-      const double f = ei * rcp_f64(dp);
-      if (writer) F[i] = f;
-      dp = (D[i + 1] - lam) - f * ei;
+    double2 *const PQ = writer ? s_pq + (rev ? NMAX : 0) : s_pqj + 8 * lane;
+    double2 *blk = PQ;
+    // d_{i+1} and e_i^2 in blocks of 8 steps, each block loaded one block ahead
+    double dc[8], ec[8], dn[8], en[8];
+    static_for<0, 8>([&](auto uc) __attribute__((always_inline)) {
+      constexpr int u = decltype(uc)::value;
+      dc[u] = D[u + 1];
+      ec[u] = E2[u];
     });
+    double pp = 1.0, p = D[0] - lam;
+    static_for<0, NMAX - 1>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int i = decltype(ic)::value, t = i % 8;
+      if constexpr (t == 0) {
+        blk = writer ? PQ + i : PQ;
+        static_for<0, 8>([&](auto uc) __attribute__((always_inline)) {
+          constexpr int u = decltype(uc)::value, ii = i + 8 + u;
+          if constexpr (ii < NMAX - 1) {
+            dn[u] = D[ii + 1];
+            en[u] = E2[ii];
+          }
+        });
+      }
+      blk[t] = make_double2(p, pp);
+      const double pn = fma(dc[t] - lam, p, -ec[t] * pp);
+      pp = p;
+      p = pn;
+      if constexpr (t == 7) {
+        const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p), fabs(pp)));
+        p = ldexp(p, -ex);
+        pp = ldexp(pp, -ex);
+        static_for<0, 8>([&](auto uc) __attribute__((always_inline)) {
+          constexpr int u = decltype(uc)::value;
+          dc[u] = dn[u];
+          ec[u] = en[u];
+        });
+      }
+    });
+  }
+  __syncthreads();
+  for (int i = lane; i < 2 * (NMAX - 1); i += 64) {
+    const int h = i >= NMAX - 1 ? 1 : 0, t = i - h * (NMAX - 1);
+    const double2 q = s_pq[h * NMAX + t];
+    double dp = q.x * rcp_f64(q.y);
+    if (dp == 0.0) dp = kTiny;
+    s_f[h][t] = (h ? s_er[t] : s_e[t]) * rcp_f64(dp);
   }
   __syncthreads();
   // L_i = s_f[0][i], U_i = s_f[1][n-1-i]
@@ -540,9 +616,23 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   auto vrow = [&](int j, int i) -> double {
     return s_V[(i > j && i < n) ? j * n + i - j - 1 : NMAX * NMAX];
   };
+  // blocks of three reflectors (c = j applied first, then b = j-1, a = j-2)
   int j = n - 3;
-  for (; j >= 1; j -= 2) {
-    const int b = j, a = j - 1;
+  for (; j >= 2; j -= 3) {
+    const int c = j, b = j - 1, a = j - 2;
+    const double vc0 = vrow(c, i0), vb0 = vrow(b, i0), va0 = vrow(a, i0);
+    const double vc1 = NMAX > 64 ? vrow(c, i1) : 0.0, vb1 = NMAX > 64 ? vrow(b, i1) : 0.0;
+    const double va1 = NMAX > 64 ? vrow(a, i1) : 0.0;
+    double sc = fma(vc1, z1, vc0 * z0), sb = fma(vb1, z1, vb0 * z0), sa = fma(va1, z1, va0 * z0);
+    wave_sum3(sc, sb, sa);
+    const double cc = s_tau[c] * sc;
+    const double cb = s_tau[b] * fma(-s_vv[b], cc, sb);
+    const double ca = s_tau[a] * fma(-s_vv[a], cb, fma(-s_vv2[a], cc, sa));
+    z0 = fma(-ca, va0, fma(-cb, vb0, fma(-cc, vc0, z0)));
+    z1 = fma(-ca, va1, fma(-cb, vb1, fma(-cc, vc1, z1)));
+  }
+  if (j == 1) {
+    const int b = 1, a = 0;
     const double vb0 = vrow(b, i0), va0 = vrow(a, i0);
     const double vb1 = NMAX > 64 ? vrow(b, i1) : 0.0, va1 = NMAX > 64 ? vrow(a, i1) : 0.0;
     double sb = fma(vb1, z1, vb0 * z0), sa = fma(va1, z1, va0 * z0);
@@ -551,8 +641,7 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
     const double ca = s_tau[a] * fma(-s_vv[a], cb, sa);
     z0 = fma(-ca, va0, fma(-cb, vb0, z0));
     z1 = fma(-ca, va1, fma(-cb, vb1, z1));
-  }
-  if (j == 0) {
+  } else if (j == 0) {
     const double v0 = vrow(0, i0), v1 = NMAX > 64 ? vrow(0, i1) : 0.0;
     const double c0 = s_tau[0] * wave_sum(fma(v1, z1, v0 * z0));
     z0 = fma(-c0, v0, z0);
