@@ -142,45 +142,6 @@ __device__ __forceinline__ double wave_min(double v) {
   return readlane_d(v, 63);
 }
 
-// ---------------------------------------------------------------- LDS GEMM
-typedef double d4_t __attribute__((ext_vector_type(4)));
-
-// Z (n x k, LDS, leading dimension ld) <- Z E (E: k x k, LDS, lde), in place:
-// every 16-row block of Z is owned by one wavefront, which finishes all its
-// products (k <= 80, at most 5 column blocks in registers) before writing.
-__device__ void lds_right_mul_inplace(double *Z, int ld, int n, int k, const double *E,
-                                      int lde) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
-  const int cbs = (k + 15) / 16;
-  for (int m0 = wave * 16; m0 < n; m0 += nw * 16) {
-    d4_t acc[5];
-#pragma unroll
-    for (int cb = 0; cb < 5; ++cb) acc[cb] = d4_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < k; k0 += 4) {
-      const int kk = k0 + q, m = m0 + r;
-      const double a = (kk < k && m < n) ? Z[m * ld + kk] : 0.0;
-#pragma unroll
-      for (int cb = 0; cb < 5; ++cb) {
-        if (cb < cbs) {
-          const int c = cb * 16 + r;
-          const double b = (kk < k && c < k) ? E[kk * lde + c] : 0.0;
-          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int cb = 0; cb < 5; ++cb) {
-      if (cb < cbs) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int row = m0 + q + 4 * j, col = cb * 16 + r;
-          if (row < n && col < k) Z[row * ld + col] = acc[cb][j];
-        }
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------- kernel 1
 // Householder tridiagonalisation of the n x n symmetric Gin (n <= NMAX, one
@@ -733,6 +694,7 @@ __device__ __forceinline__ bool tri_finish_part(
   const int ld = n | 1;
   double *Z = lds;             // n x ld (k columns)
   double *E = lds + n * ld;    // k x ld
+  double *W = E + n * ld;      // n x ld: Z after the Newton-Schulz step
   __shared__ double s_lam[kTeNMax + 1];
   __shared__ int s_bad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -778,8 +740,13 @@ __device__ __forceinline__ bool tri_finish_part(
     E[a * ld + b] = (a == b ? 1.5 : 0.0) - 0.5 * E[a * ld + b];
   }
   __syncthreads();
-  lds_right_mul_inplace(Z, ld, n, kc, E, ld);
+  lds_gemm<false, false>(Z, ld, E, ld, W, ld, n, kc, kc);
+  for (int e = tid; e < n * (k - kc); e += blockDim.x) {  // columns past kc as they are
+    const int i = e / (k - kc), c = kc + (e - i * (k - kc));
+    W[i * ld + c] = Z[i * ld + c];
+  }
   __syncthreads();
+  Z = W;
   if (ctl && tid == 0) {
     ctl[0] = kc < k ? 1 : 0;
     ctl[1] = kc;
@@ -888,11 +855,11 @@ static int g_eig_mode = 0;  // 0 tridiagonal solver (Jacobi on its failure), 1 J
 
 void eig_set_mode(int mode) { g_eig_mode = mode; }
 
-// dynamic LDS of the finish kernel: Z and E of kernel 3, or G and V of the
-// Jacobi fallback, whichever is larger
+// dynamic LDS of the finish kernel: Z, E and W of kernel 3, or G and V of
+// the Jacobi fallback, whichever is larger
 static size_t finish_lds(int n) {
   const int ld = n | 1, np = (n + 1) & ~1;
-  return sizeof(double) * std::max<size_t>(2 * (size_t)n * ld, 2 * (size_t)np * (np + 1));
+  return sizeof(double) * std::max<size_t>(3 * (size_t)n * ld, 2 * (size_t)np * (np + 1));
 }
 
 template <typename T>
