@@ -23,6 +23,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // (the split sum takes at most 256 splits)
 constexpr int kGramThreads = 1024;  // sixteen wavefronts
 constexpr int kMaxN = 128;
+constexpr int kApplyGramMaxN = 96;  // chunk and R staged together in LDS
 
 // A(k, m) of the panel: AKC = false: A is K x n row-major (leading dimension
 // lda); AKC = true: the panel is stored transposed, n x K row-major (H of a
@@ -108,6 +109,105 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const TA *A, int64_t
   }
 }
 
+// Q = Y R for one chunk of rows of Y (K x n, FP64, row-major) and the n x n
+// upper-triangular R (the R^-1 of the previous CholeskyQR pass), written to Q,
+// then the chunk's contribution to Q^T Q as in gram_kernel: the first
+// CholeskyQR pass's product and the second pass's Gram in one launch, Q not
+// read back.  The chunk and R are staged in LDS; the wavefronts form the
+// chunk's 16 x 16 blocks of Q (k-steps past the block's last column skipped:
+// R is zero below its diagonal; four accumulators over consecutive k-steps),
+// the chunk of Q replaces that of Y in LDS, and the Gram follows.  Rows past
+// K and columns past n are zero in both stagings, so they are zero in Q.
+template <int kChunk>
+__global__ __launch_bounds__(kGramThreads) void apply_gram_kernel(const double *Y, const double *R,
+                                                                  double *Q, int n, int64_t K,
+                                                                  double *out, int direct,
+                                                                  int64_t ldg, const int *gate) {
+  if (gate && *gate == 0) return;
+  extern __shared__ __attribute__((aligned(16))) double gs[];  // [kChunk][ld], then R [np][ld]
+  const int ld = ((n + 15) / 16) * 16 + 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t k0 = (int64_t)blockIdx.x * kChunk;
+  const int nk = (int)min<int64_t>(kChunk, K - k0);
+  const int np = ((n + 15) / 16) * 16;
+  double *Rs = gs + kChunk * ld;
+  for (int e = tid; e < kChunk * np; e += kGramThreads) {
+    const int k = e / np, m = e - k * np;
+    gs[k * ld + m] = (k < nk && m < n) ? Y[(k0 + k) * n + m] : 0.0;
+  }
+  for (int e = tid; e < np * np; e += kGramThreads) {
+    const int k = e / np, m = e - k * np;
+    Rs[k * ld + m] = (k < n && m < n) ? R[k * n + m] : 0.0;
+  }
+  __syncthreads();
+  // blocks of Q: at most (64 / 16) x (96 / 16) = 24, two per wavefront
+  const int bm = kChunk / 16, bn = np / 16;
+  d4_t acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int blk = wave + h * (kGramThreads / 64);
+    if (blk < bm * bn) {
+      const int I = blk / bn, J = blk - I * bn;
+      const double *pa = gs + (16 * I + r) * ld + q;
+      const double *pb = Rs + q * ld + 16 * J + r;
+      const int kend = 16 * (J + 1);  // R(k, c) = 0 for k > c
+      d4_t a4[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+      for (int kk = 0; kk < kend; kk += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          a4[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk + 4 * u], pb[(kk + 4 * u) * ld],
+                                                      a4[u], 0, 0, 0);
+      }
+      acc[h] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    }
+  }
+  __syncthreads();  // every read of the chunk of Y is done
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int blk = wave + h * (kGramThreads / 64);
+    if (blk < bm * bn) {
+      const int I = blk / bn, J = blk - I * bn;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 16 * I + q + 4 * j, col = 16 * J + r;
+        gs[row * ld + col] = acc[h][j];
+        if (row < nk && col < n) Q[(k0 + row) * n + col] = acc[h][j];
+      }
+    }
+  }
+  __syncthreads();
+  const int nb = np / 16, nblk = nb * (nb + 1) / 2;
+  for (int blk = wave; blk < nblk; blk += kGramThreads / 64) {
+    int Ib = 0, rem = blk;
+    while (rem >= nb - Ib) {
+      rem -= nb - Ib;
+      ++Ib;
+    }
+    const int Jb = Ib + rem;
+    d4_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const double *pa = gs + q * ld + 16 * Ib + r;
+    const double *pb = gs + q * ld + 16 * Jb + r;
+#pragma unroll 4
+    for (int kk = 0; kk < kChunk; kk += 8) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk * ld], pb[kk * ld], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[(kk + 4) * ld], pb[(kk + 4) * ld], acc1,
+                                                 0, 0, 0);
+    }
+    const d4_t g = acc0 + acc1;
+    double *o = direct ? out : out + (int64_t)blockIdx.x * n * n;
+    const int64_t ldo = direct ? ldg : n;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = 16 * Ib + q + 4 * j, col = 16 * Jb + r;
+      if (row < n && col < n) {
+        o[row * ldo + col] = g[j];
+        if (Ib != Jb) o[col * ldo + row] = g[j];
+      }
+    }
+  }
+}
+
 int chunk_rows(int64_t K) { return (K + 31) / 32 <= 256 ? 32 : 64; }
 int64_t chunks_of(int64_t K) { return (K + chunk_rows(K) - 1) / chunk_rows(K); }
 
@@ -145,6 +245,40 @@ int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t 
   return TT_OK;
 }
 
+template <int kChunk>
+int launch_apply(const double *Y, const double *R, double *Q, int64_t n, int64_t K, double *G,
+                 int64_t ldg, void *partial, hipStream_t s, const int *gate) {
+  const int64_t nc = (K + kChunk - 1) / kChunk;
+  const int ld = (int)(((n + 15) / 16) * 16 + 2), np = (int)(((n + 15) / 16) * 16);
+  const size_t lds = (size_t)(kChunk + np) * ld * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_gram_kernel<kChunk>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr = true;
+  }
+  const bool direct = nc == 1;
+  hipLaunchKernelGGL((apply_gram_kernel<kChunk>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
+                     Y, R, Q, (int)n, K, direct ? G : static_cast<double *>(partial),
+                     direct ? 1 : 0, ldg, gate);
+  TTR_HIP(hipGetLastError());
+  if (!direct) {
+    GemmX g;  // the chunk splits, summed in a fixed order
+    g.C = G;
+    g.ldc = ldg;
+    g.tc = DType::F64;
+    g.M = n;
+    g.N = n;
+    g.K = 1;
+    g.math = DType::F64;
+    g.splits = (int)nc;
+    g.partial = partial;
+    g.gate = gate;
+    TTR_TRY(gemm_reduce_splits(g, s));
+  }
+  return TT_OK;
+}
+
 }  // namespace
 
 static int g_gram_mode = 0;  // 0: this kernel where supported, 1: split-K GEMM
@@ -160,6 +294,20 @@ bool gram_enabled(int64_t n, int64_t K) { return g_gram_mode == 0 && gram_suppor
 size_t gram_partial_elems(int64_t n, int64_t K) {
   const int64_t nc = chunks_of(K);
   return nc > 1 ? (size_t)(nc * n * n) : 0;
+}
+
+bool apply_gram_supported(int64_t n, int64_t K) {
+  return gram_enabled(n, K) && n <= kApplyGramMaxN;
+}
+
+int apply_gram_run(const double *Y, const double *R, double *Q, int64_t n, int64_t K, double *G,
+                   int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s,
+                   const int *gate) {
+  if (!apply_gram_supported(n, K)) return fail(TT_EINVAL, "internal: fused product and Gram shape");
+  if (gram_partial_elems(n, K) * sizeof(double) > partial_bytes)
+    return fail(TT_EINVAL, "internal: split buffer too small for the Gram");
+  return chunk_rows(K) == 32 ? launch_apply<32>(Y, R, Q, n, K, G, ldg, partial, s, gate)
+                             : launch_apply<64>(Y, R, Q, n, K, G, ldg, partial, s, gate);
 }
 
 int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t K, double *G,

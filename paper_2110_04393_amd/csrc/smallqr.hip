@@ -415,17 +415,24 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   const bool f32 = sizeof(T) == 4;
   T *q1 = reinterpret_cast<T *>(ws.q1);
   const T *rinv_t = f32 ? reinterpret_cast<const T *>(ws.rinv_f) : reinterpret_cast<const T *>(ws.rinv);
+  // FP64: the first pass's product and the second pass's Gram in one launch
+  const bool fused = !f32 && apply_gram_supported(n, m);
   for (int pass = 0; pass < 2; ++pass) {
     const T *src = pass == 0 ? Y : q1;
     T *dst = pass == 0 ? q1 : Q;
-    TTR_TRY(qr_gram<T>(src, m, n, ws, ws.go, s));
+    if (pass == 0 || !fused) TTR_TRY(qr_gram<T>(src, m, n, ws, ws.go, s));
     // first pass: shifted retry on breakdown, s = 11 (m n + n (n + 1)) u trace(G)
     // with u the unit roundoff of the storage (shifted CholeskyQR3)
     const double shift_c =
         pass == 0 ? 11.0 * (double)(m * n + n * (n + 1)) * (f32 ? 0x1p-24 : 0x1p-53) : 0.0;
     TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s,
                      shift_c, ws.go));
-    TTR_TRY(qr_apply<T>(src, dst, m, n, rinv_t, ws.go, s));  // dst = src Rinv
+    if (pass == 0 && fused)
+      TTR_TRY(apply_gram_run(reinterpret_cast<const double *>(src), ws.rinv,
+                             reinterpret_cast<double *>(dst), n, m, ws.gram, n, ws.partial,
+                             gram_partial_elems(n, m) * sizeof(double), s, ws.go));
+    else
+      TTR_TRY(qr_apply<T>(src, dst, m, n, rinv_t, ws.go, s));  // dst = src Rinv
   }
   // third pass when the first one was shifted and the Householder fallback
   // when a pivot broke down (no-ops otherwise).  The speculative form leaves
