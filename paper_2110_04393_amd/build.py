@@ -33,13 +33,25 @@ COMMON = [
 ]
 
 
+# One-workgroup factorisation kernels that read and write MFMA accumulators
+# with ordinary vector instructions between the products (the blocked
+# Cholesky, the eigen finish, the second truncation pass): accumulators in
+# VGPRs instead of AGPRs, which saves the copies between the two files.  The
+# streaming GEMM and W-chain kernels keep the default (AGPRs as extra room).
+PER_FILE = {
+    "smallqr.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "tri_eig.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "trunc_refine.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *PER_FILE.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
