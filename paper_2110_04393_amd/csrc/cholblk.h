@@ -77,10 +77,8 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
     // second pass: first-order factor when G is within 2^-30 of I
     __shared__ double s_emax[NW];
     double em = 0.0;
-    for (int e = tid; e < n * n; e += NT) {
-      const int i = e / n, c = e - i * n;
-      em = fmax(em, fabs(G[e] - (i == c ? 1.0 : 0.0)));
-    }
+    for (int i = wave; i < n; i += NW)
+      for (int c = lane; c < n; c += 64) em = fmax(em, fabs(G[i * n + c] - (i == c ? 1.0 : 0.0)));
     em = fmax(em, __shfl_xor(em, 32));
     em = fmax(em, __shfl_xor(em, 16));
     em = fmax(em, __shfl_xor(em, 8));
@@ -93,12 +91,13 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
 #pragma unroll
     for (int w = 1; w < NW; ++w) emax = fmax(emax, s_emax[w]);
     if (emax <= (Rinv_f ? kNearIdentityF32 : kNearIdentity)) {  // also false for NaN
-      for (int e = tid; e < n * n; e += NT) {
-        const int i = e / n, c = e - i * n;
-        const double x = (i == c) ? 1.0 - 0.5 * (G[e] - 1.0) : ((i < c) ? -G[e] : 0.0);
-        Rinv[e] = x;
-        if (Rinv_f) Rinv_f[e] = (float)x;
-      }
+      for (int i = wave; i < n; i += NW)
+        for (int c = lane; c < n; c += 64) {
+          const int e = i * n + c;
+          const double x = (i == c) ? 1.0 - 0.5 * (G[e] - 1.0) : ((i < c) ? -G[e] : 0.0);
+          Rinv[e] = x;
+          if (Rinv_f) Rinv_f[e] = (float)x;
+        }
       return 0;
     }
   }
