@@ -7,28 +7,29 @@
 // leading eigenpairs.  On a GPU the cost of such a solve is the length of its
 // chain of dependent steps, so the method is chosen for that:
 //
-//   1. Householder tridiagonalisation G = Q T Q^T in LDS, two barriers per
-//      column: phase b forms p = tau A22 v and y = Q v (8 lanes per row, DPP
-//      sums); phase d updates A22 -= v w^T + w v^T and Q -= tau y v^T while the
-//      first wavefront already builds the next reflector from the updated
-//      column it computes itself.
-//   2. Eigenvalues k+1 (the (k+1)-th to check the gap) by multisection: 16 lanes
-//      per eigenvalue evaluate Sturm counts at 16 points of the bracket
-//      (17-fold shrink per iteration, 14 iterations), each count being the
-//      sign changes of the leading-minor determinants
-//      p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}   (one dependent FMA per step,
-//      rescaled by powers of two).
-//   3. Eigenvectors of T by twisted factorisation (one lane per eigenvalue):
-//      T - lambda I = L+ D+ L+^T = U- D- U-^T, twist r = argmin |gamma_r|,
-//      z_r = 1 and z propagated outwards with the factors.
-//   4. One Newton-Schulz step Z <- Z (3/2 I - 1/2 Z^T Z) (FP64 MFMA) restores
-//      orthogonality lost to close eigenvalues, then U = Q Z (FP64 MFMA).
+//   1. Householder tridiagonalisation G = Q T Q^T with the matrix in
+//      registers (tri_reduce_kernel, one workgroup, two barriers per column;
+//      the reflectors are kept for step 3, with the products v_j^T v_(j+1)
+//      and v_j^T v_(j+2)).
+//   2. The k+1 leading eigenvalues (the (k+1)-th to check the gap) by
+//      multisection, one wavefront per eigenvalue (tri_vec_kernel): the 64
+//      lanes evaluate Sturm counts at 64 points of the bracket (65-fold
+//      shrink, 9 iterations), each count the sign changes of the
+//      leading-minor determinants p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}
+//      (one dependent FMA per step, rescaled by powers of two).
+//   3. In the same wavefront, the eigenvector of T by twisted factorisation
+//      (T - lambda I = L+ D+ L+^T = U- D- U-^T, pivots as ratios of
+//      consecutive minors; twist r = argmin |gamma_r|; z_r = 1 and z
+//      propagated outwards with the factors), then u = Q z with the
+//      reflectors of step 1 applied three at a time.
+//   4. tri_finish_kernel: one Newton-Schulz step Z <- Z (3/2 I - 1/2 Z^T Z)
+//      (FP64 MFMA products in LDS) restores orthogonality lost to close
+//      eigenvalues, then the factors of the truncation.
 //
-// A device flag selects the Jacobi solver (eig.hip) instead when the wanted
-// eigenvalues are not separated by 1e-9 ||T|| (repeated or near-repeated
-// eigenvalues, an exactly split T) or the orthogonality defect before the
-// Newton-Schulz step exceeds 1e-6; that kernel and the factor kernel are
-// always enqueued after this one and return at once unless the flag is set.
+// The finish kernel runs the cyclic Jacobi solver (jacobi.h) itself instead
+// when the wanted eigenvalues are not separated by 1e-9 ||T|| (repeated or
+// near-repeated eigenvalues, an exactly split T) or the orthogonality defect
+// before the Newton-Schulz step exceeds 1e-6.
 #include "fastmath.h"
 #include "jacobi.h"
 #include "ldsmm.h"
