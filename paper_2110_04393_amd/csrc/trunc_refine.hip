@@ -15,8 +15,8 @@
 // recovers that accuracy with two more contractions of H:
 //   1. U1 = [U_s | U_w]: U_s the w eigenvectors of the first pass above
 //      tau lambda_1 (accurate, separated from the rest), U_w an orthonormal
-//      basis of their complement (Householder QR of U_s, Q formed explicitly;
-//      built by the first pass's finish kernel, tri_eig.hip)
+//      basis of their complement (pivoted Cholesky of I - U_s U_s^T; built
+//      by the first pass's finish kernel, tri_eig.hip)
 //   2. B = U1^T H (GEMM) and G2 = B B^T (FP64 Gram of B): the weak rows of B
 //      are formed and multiplied at their own scale
 //   3. eigenpairs of the weak block G2[w:, w:] (cyclic Jacobi, absolute
