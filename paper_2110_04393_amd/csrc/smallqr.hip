@@ -1,11 +1,12 @@
 // Thin QR of tall-skinny sketches (Algorithm 5 / Algorithm 7: QR of Y_n).
 //
 // Fast path: CholeskyQR2 in FP64.  G = Y^T Y (the panel-Gram kernel, MFMA over
-// 64-row chunks and a split sum; the split-K GEMM for panels it does not
-// take), G = R^T R by a
-// one-workgroup Cholesky that also forms R^{-1}, Q1 = Y R^{-1} (MFMA); the same
-// again on Q1 (whose Gram is within rounding of I, so that its factor is
-// usually taken to first order).  Both Cholesky factors have positive
+// 32- or 64-row chunks and a split sum; the split-K GEMM for panels it does
+// not take), G = R^T R by a one-workgroup Cholesky that also forms R^{-1},
+// Q1 = Y R^{-1} (MFMA); the same again on Q1 (whose Gram is within rounding
+// of I, so that its factor is usually taken to first order).  With FP64
+// storage the product Q1 = Y R^{-1} and the Gram of Q1 are one kernel
+// (apply_gram_run, gram.hip).  Both Cholesky factors have positive
 // diagonals, so the final R = R2 R1 has diag(R) > 0, the normalisation the
 // rest of the method uses.
 //
