@@ -136,6 +136,20 @@ __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_row_bcast<0x143, 0xC>(v));
   return readlane_d(v, 63);
 }
+// the same for an int
+template <int CTRL>
+__device__ __forceinline__ int dppi(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int wave_min_int(int v) {
+  v = min(v, dppi<0xB1>(v));
+  v = min(v, dppi<0x4E>(v));
+  v = min(v, dppi<0x141>(v));
+  v = min(v, dppi<0x140>(v));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xA, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
 __device__ __forceinline__ double wave_min(double v) {
   v = min16(v);
   v = fmin(v, dpp_row_bcast<0x142, 0xA>(v));
@@ -629,55 +643,51 @@ __global__ __launch_bounds__(64) void tri_vec_kernel(const double *d_in, const d
 // C = V Q for any orthonormal basis V of range(P) and an orthogonal Q, i.e.
 // C has orthonormal columns itself; the diagonal pivoting keeps every step
 // at a pivot of at least (n - w - j) / n of the remaining trace.  n - w steps
-// of a rank-1 update, three barriers each.  P is formed in Pw (LDS, n x ld).
-// All threads of the workgroup.
-__device__ void complement_basis(const double *Z, int ld, int n, int w, double *Pw, double *U1) {
-  __shared__ double s_col[kTeNMax + 1];
-  __shared__ int s_piv;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  lds_gemm<false, true>(Z, ld, Z, ld, Pw, ld, n, n, w, -1.0, nullptr, 0, 0.0);
+// of a rank-1 update, one barrier each: P alternates between Pa and Pb (LDS,
+// n x ld each), every wavefront finds the pivot itself (largest diagonal
+// entry, lowest index on ties) and every thread forms the entries of the
+// pivot column it needs, so nothing is handed between wavefronts within a
+// step.  All threads of the workgroup (at most kTeThreads).
+__device__ void complement_basis(const double *Z, int ld, int n, int w, double *Pa, double *Pb,
+                                 double *U1) {
+  constexpr int kPer = (kTeNMax * kTeNMax + kTeThreads - 1) / kTeThreads;
+  const int tid = threadIdx.x, lane = tid & 63;
+  lds_gemm<false, true>(Z, ld, Z, ld, Pa, ld, n, n, w, -1.0, nullptr, 0, 0.0);
   __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) Pw[i * ld + i] += 1.0;
+  for (int i = tid; i < n; i += blockDim.x) Pa[i * ld + i] += 1.0;
   for (int e = tid; e < n * w; e += blockDim.x) {
     const int i = e / w, c = e - i * w;
     U1[i * n + c] = Z[i * ld + c];
   }
+  // the entries (i, c) of P this thread updates, the same at every step
+  int ei[kPer], ec[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + u * kTeThreads;
+    ei[u] = e < n * n ? e / n : -1;
+    ec[u] = e < n * n ? e - (e / n) * n : 0;
+  }
   __syncthreads();
   for (int j = 0; j < n - w; ++j) {
-    if (wave == 0) {
-      double best = -1e300;
-      int bi = 0;
-      for (int i = lane; i < n; i += 64) {
-        const double d = Pw[i * ld + i];
-        if (d > best) {
-          best = d;
-          bi = i;
-        }
+    const double d0 = lane < n ? Pa[lane * ld + lane] : -1e300;
+    const double d1 = lane + 64 < n ? Pa[(lane + 64) * ld + lane + 64] : -1e300;
+    const double best = fmax(d0, d1);
+    const int bi = d1 > d0 ? lane + 64 : lane;
+    const double mx = wave_max(best);
+    const int pv = wave_min_int(best == mx ? bi : 1 << 30);
+    const double rp = rsq_f64(fmax(mx, 1e-300));
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      if (ei[u] >= 0) {
+        const int i = ei[u], c = ec[u];
+        Pb[i * ld + c] = fma(-(Pa[i * ld + pv] * rp), Pa[c * ld + pv] * rp, Pa[i * ld + c]);
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) s_piv = bi;
     }
+    for (int i = tid; i < n; i += blockDim.x) U1[i * n + w + j] = Pa[i * ld + pv] * rp;
     __syncthreads();
-    const int pv = s_piv;
-    const double rp = rsq_f64(fmax(Pw[pv * ld + pv], 1e-300));
-    for (int i = tid; i < n; i += blockDim.x) {
-      const double c = Pw[i * ld + pv] * rp;
-      s_col[i] = c;
-      U1[i * n + w + j] = c;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += blockDim.x) {
-      const int i = e / n, c = e - i * n;
-      Pw[i * ld + c] = fma(-s_col[i], s_col[c], Pw[i * ld + c]);
-    }
-    __syncthreads();
+    double *t = Pa;
+    Pa = Pb;
+    Pb = t;
   }
 }
 
@@ -778,7 +788,7 @@ __device__ __forceinline__ bool tri_finish_part(
   }
   if (second) {
     __syncthreads();
-    complement_basis(Z, ld, n, kc, E, U1);
+    complement_basis(Z, ld, n, kc, E, lds, U1);  // lds: the Z before the Newton-Schulz step
   }
   return true;
 }
