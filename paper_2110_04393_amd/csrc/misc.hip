@@ -186,11 +186,14 @@ __global__ __launch_bounds__(256) void tri_inv_upper_kernel(const double *R, int
   __shared__ double s_max;
   __shared__ int s_bad;
   const int tid = threadIdx.x;
-  if (tid == 0) {
+  if (tid < 64) {  // one wavefront, its loads all in flight together
     double mx = 0.0;
-    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(R[i * n + i]));
-    s_max = mx;
-    s_bad = 0;
+    for (int i = tid; i < n; i += 64) mx = fmax(mx, fabs(R[i * n + i]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (tid == 0) {
+      s_max = mx;
+      s_bad = 0;
+    }
   }
   __syncthreads();
   const double floor_d = 64.0 * 1.1102230246251565e-16 * s_max;

@@ -61,10 +61,11 @@ __global__ __launch_bounds__(kCholThreads) __attribute__((amdgpu_waves_per_eu(1,
   }
   if (or_flag || !(shift_c > 0.0)) return;
   __shared__ double s_trace;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {  // one wavefront, its loads all in flight together
     double t = 0.0;
-    for (int i = 0; i < n; ++i) t += G[i * n + i];
-    s_trace = t;
+    for (int i = threadIdx.x; i < n; i += 64) t += G[i * n + i];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (threadIdx.x == 0) s_trace = t;
   }
   __syncthreads();
   chol_inv_kernel_body<NMAX>(G, Rinv, Rinv_f, n, flag, 0, shift_c * s_trace, 2);

@@ -110,10 +110,11 @@ __device__ void refine_factors(const double *G2, const double *U1, int n, int k,
   // F and column of P are set to zero and trunc_complete_prep/_rows_kernel
   // give the core an orthonormal row in its place.
   __shared__ double s_gmax;
-  if (tid == 0) {
+  if (tid < 64) {  // one wavefront, its loads all in flight together
     double gm = 0.0;
-    for (int i = 0; i < n; ++i) gm = fmax(gm, G2[i * n + i]);
-    s_gmax = gm;
+    for (int i = tid; i < n; i += 64) gm = fmax(gm, G2[i * n + i]);
+    for (int off = 32; off > 0; off >>= 1) gm = fmax(gm, __shfl_xor(gm, off));
+    if (tid == 0) s_gmax = gm;
   }
   __syncthreads();
   // Gt = R^T R, Ri = R^-1 (upper); L = R^T, L^-1 = Ri^T
@@ -140,10 +141,11 @@ __device__ void refine_factors(const double *G2, const double *U1, int n, int k,
     const int a = e % k;
     P[e] = nullmask[a] ? (T)0 : (T)M1[e];
   }
-  if (tid == 0) {
+  if (tid < 64) {
     int cnt = 0;
-    for (int a = 0; a < k; ++a) cnt += nullmask[a];
-    ctl[2] = cnt;
+    for (int a = tid; a < k; a += 64) cnt += nullmask[a];
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (tid == 0) ctl[2] = cnt;
   }
 }
 
@@ -321,10 +323,16 @@ __global__ __launch_bounds__(256) void trunc_complete_rows_kernel(T *C, int k, i
   const double *Li = sc + cols, *W = Li + m * m;
   const int *sel = reinterpret_cast<const int *>(W + m * k);
   __shared__ int s_rows[kRefMaxN];
-  if (threadIdx.x == 0) {
-    int a = 0;
-    for (int j = 0; j < k; ++j)
-      if (nullmask[j]) s_rows[a++] = j;
+  if (threadIdx.x < 64) {  // the null rows in order, by ballots of 64 at a time
+    const int lane = threadIdx.x;
+    int base = 0;
+    for (int j0 = 0; j0 < k; j0 += 64) {
+      const int j = j0 + lane;
+      const bool isnull = j < k && nullmask[j] != 0;
+      const unsigned long long m = __ballot(isnull);
+      if (isnull) s_rows[base + __popcll(m & ((1ull << lane) - 1))] = j;
+      base += __popcll(m);
+    }
   }
   __syncthreads();
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
