@@ -109,18 +109,20 @@ __global__ __launch_bounds__(kGramThreads) void gram_kernel(const TA *A, int64_t
   }
 }
 
-// Q = Y R for one chunk of rows of Y (K x n, FP64, row-major) and the n x n
-// upper-triangular R (the R^-1 of the previous CholeskyQR pass), written to Q,
-// then the chunk's contribution to Q^T Q as in gram_kernel: the first
+// Q = Y R for one chunk of rows of Y (K x n, row-major, FP64 or FP32
+// storage) and the n x n upper-triangular FP64 R (the R^-1 of the previous
+// CholeskyQR pass), in FP64 arithmetic, written to Q in the storage type,
+// then the chunk's contribution to Q^T Q (of Q as stored) as in gram_kernel:
+// the first
 // CholeskyQR pass's product and the second pass's Gram in one launch, Q not
 // read back.  The chunk and R are staged in LDS; the wavefronts form the
 // chunk's 16 x 16 blocks of Q (k-steps past the block's last column skipped:
 // R is zero below its diagonal; four accumulators over consecutive k-steps),
 // the chunk of Q replaces that of Y in LDS, and the Gram follows.  Rows past
 // K and columns past n are zero in both stagings, so they are zero in Q.
-template <int kChunk>
-__global__ __launch_bounds__(kGramThreads) void apply_gram_kernel(const double *Y, const double *R,
-                                                                  double *Q, int n, int64_t K,
+template <typename TS, int kChunk>
+__global__ __launch_bounds__(kGramThreads) void apply_gram_kernel(const TS *Y, const double *R,
+                                                                  TS *Q, int n, int64_t K,
                                                                   double *out, int direct,
                                                                   int64_t ldg, const int *gate) {
   if (gate && *gate == 0) return;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kGramThreads) void apply_gram_kernel(const double *
   double *Rs = gs + kChunk * ld;
   for (int e = tid; e < kChunk * np; e += kGramThreads) {
     const int k = e / np, m = e - k * np;
-    gs[k * ld + m] = (k < nk && m < n) ? Y[(k0 + k) * n + m] : 0.0;
+    gs[k * ld + m] = (k < nk && m < n) ? (double)Y[(k0 + k) * n + m] : 0.0;
   }
   for (int e = tid; e < np * np; e += kGramThreads) {
     const int k = e / np, m = e - k * np;
@@ -171,8 +173,9 @@ __global__ __launch_bounds__(kGramThreads) void apply_gram_kernel(const double *
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = 16 * I + q + 4 * j, col = 16 * J + r;
-        gs[row * ld + col] = acc[h][j];
-        if (row < nk && col < n) Q[(k0 + row) * n + col] = acc[h][j];
+        const TS v = (TS)acc[h][j];
+        gs[row * ld + col] = (double)v;
+        if (row < nk && col < n) Q[(k0 + row) * n + col] = v;
       }
     }
   }
@@ -245,20 +248,20 @@ int launch(const void *A, int64_t lda, int64_t n, int64_t K, double *G, int64_t 
   return TT_OK;
 }
 
-template <int kChunk>
-int launch_apply(const double *Y, const double *R, double *Q, int64_t n, int64_t K, double *G,
+template <typename TS, int kChunk>
+int launch_apply(const TS *Y, const double *R, TS *Q, int64_t n, int64_t K, double *G,
                  int64_t ldg, void *partial, hipStream_t s, const int *gate) {
   const int64_t nc = (K + kChunk - 1) / kChunk;
   const int ld = (int)(((n + 15) / 16) * 16 + 2), np = (int)(((n + 15) / 16) * 16);
   const size_t lds = (size_t)(kChunk + np) * ld * sizeof(double);
   static bool attr = false;
   if (!attr) {
-    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_gram_kernel<kChunk>),
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_gram_kernel<TS, kChunk>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
   const bool direct = nc == 1;
-  hipLaunchKernelGGL((apply_gram_kernel<kChunk>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
+  hipLaunchKernelGGL((apply_gram_kernel<TS, kChunk>), dim3((unsigned)nc), dim3(kGramThreads), lds, s,
                      Y, R, Q, (int)n, K, direct ? G : static_cast<double *>(partial),
                      direct ? 1 : 0, ldg, gate);
   TTR_HIP(hipGetLastError());
@@ -300,14 +303,26 @@ bool apply_gram_supported(int64_t n, int64_t K) {
   return gram_enabled(n, K) && n <= kApplyGramMaxN;
 }
 
-int apply_gram_run(const double *Y, const double *R, double *Q, int64_t n, int64_t K, double *G,
-                   int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s,
+int apply_gram_run(const void *Y, DType ts, const double *R, void *Q, int64_t n, int64_t K,
+                   double *G, int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s,
                    const int *gate) {
   if (!apply_gram_supported(n, K)) return fail(TT_EINVAL, "internal: fused product and Gram shape");
   if (gram_partial_elems(n, K) * sizeof(double) > partial_bytes)
     return fail(TT_EINVAL, "internal: split buffer too small for the Gram");
-  return chunk_rows(K) == 32 ? launch_apply<32>(Y, R, Q, n, K, G, ldg, partial, s, gate)
-                             : launch_apply<64>(Y, R, Q, n, K, G, ldg, partial, s, gate);
+  const bool c32 = chunk_rows(K) == 32;
+  if (ts == DType::F64) {
+    const double *y = static_cast<const double *>(Y);
+    double *q = static_cast<double *>(Q);
+    return c32 ? launch_apply<double, 32>(y, R, q, n, K, G, ldg, partial, s, gate)
+               : launch_apply<double, 64>(y, R, q, n, K, G, ldg, partial, s, gate);
+  }
+  if (ts == DType::F32) {
+    const float *y = static_cast<const float *>(Y);
+    float *q = static_cast<float *>(Q);
+    return c32 ? launch_apply<float, 32>(y, R, q, n, K, G, ldg, partial, s, gate)
+               : launch_apply<float, 64>(y, R, q, n, K, G, ldg, partial, s, gate);
+  }
+  return fail(TT_EINVAL, "internal: storage type of the fused product");
 }
 
 int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t K, double *G,

@@ -4,9 +4,9 @@
 // 32- or 64-row chunks and a split sum; the split-K GEMM for panels it does
 // not take), G = R^T R by a one-workgroup Cholesky that also forms R^{-1},
 // Q1 = Y R^{-1} (MFMA); the same again on Q1 (whose Gram is within rounding
-// of I, so that its factor is usually taken to first order).  With FP64
-// storage the product Q1 = Y R^{-1} and the Gram of Q1 are one kernel
-// (apply_gram_run, gram.hip).  Both Cholesky factors have positive
+// of I, so that its factor is usually taken to first order).  The product
+// Q1 = Y R^{-1} (FP64 arithmetic, also with FP32 storage) and the Gram of Q1
+// are one kernel (apply_gram_run, gram.hip).  Both Cholesky factors have positive
 // diagonals, so the final R = R2 R1 has diag(R) > 0, the normalisation the
 // rest of the method uses.
 //
@@ -417,8 +417,9 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
   const bool f32 = sizeof(T) == 4;
   T *q1 = reinterpret_cast<T *>(ws.q1);
   const T *rinv_t = f32 ? reinterpret_cast<const T *>(ws.rinv_f) : reinterpret_cast<const T *>(ws.rinv);
-  // FP64: the first pass's product and the second pass's Gram in one launch
-  const bool fused = !f32 && apply_gram_supported(n, m);
+  // the first pass's product (FP64 arithmetic, Q1 rounded to the storage)
+  // and the second pass's Gram in one launch
+  const bool fused = apply_gram_supported(n, m);
   for (int pass = 0; pass < 2; ++pass) {
     const T *src = pass == 0 ? Y : q1;
     T *dst = pass == 0 ? q1 : Q;
@@ -430,8 +431,7 @@ int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s
     TTR_TRY(chol_inv(ws.gram, ws.rinv, f32 ? ws.rinv_f : nullptr, (int)n, ws.flag, pass, s,
                      shift_c, ws.go));
     if (pass == 0 && fused)
-      TTR_TRY(apply_gram_run(reinterpret_cast<const double *>(src), ws.rinv,
-                             reinterpret_cast<double *>(dst), n, m, ws.gram, n, ws.partial,
+      TTR_TRY(apply_gram_run(src, DTypeOf<T>::value, ws.rinv, dst, n, m, ws.gram, n, ws.partial,
                              gram_partial_elems(n, m) * sizeof(double), s, ws.go));
     else
       TTR_TRY(qr_apply<T>(src, dst, m, n, rinv_t, ws.go, s));  // dst = src Rinv

@@ -316,11 +316,12 @@ int gram_run(const void *A, DType ta, bool a_kc, int64_t lda, int64_t n, int64_t
              const int *gate = nullptr);
 void gram_set_mode(int mode);
 bool gram_enabled(int64_t n, int64_t K);
-// Q = Y R (Y: K x n FP64 row-major, R: n x n upper triangular, FP64) and
-// G = Q^T Q from the same launch (n <= 96; the split buffer as for gram_run)
+// Q = Y R (Y, Q: K x n row-major in the storage type ts, FP64 or FP32; R:
+// n x n upper triangular, FP64; FP64 arithmetic) and G = Q^T Q of Q as
+// stored, from the same launch (n <= 96; the split buffer as for gram_run)
 bool apply_gram_supported(int64_t n, int64_t K);
-int apply_gram_run(const double *Y, const double *R, double *Q, int64_t n, int64_t K, double *G,
-                   int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s,
+int apply_gram_run(const void *Y, DType ts, const double *R, void *Q, int64_t n, int64_t K,
+                   double *G, int64_t ldg, void *partial, size_t partial_bytes, hipStream_t s,
                    const int *gate = nullptr);
 template <typename T>
 int qr_thin(const T *Y, T *Q, int64_t m, int64_t n, QrScratch &ws, hipStream_t s);
