@@ -30,7 +30,8 @@
  *   TT_PREC_F32 and TT_PREC_MIXED_BF16 need TT_F32 storage; a mismatch is
  *   TT_EINVAL).  In the FP32 modes the Gram matrices of the thin QR and of
  *   the truncation are accumulated in FP64 from the FP32 operands and
- *   factorised in FP64, and every partial contraction W_n is rescaled by a
+ *   factorised in FP64 (the first CholeskyQR product Y R^-1 is also formed
+ *   in FP64 and rounded to FP32), and every partial contraction W_n is rescaled by a
  *   power of two as soon as it is formed (the QR of Y_n = Z_n W_n, hence the
  *   result, is invariant under positive scalings of W_n; the rescaling keeps
  *   long trains inside the FP32 exponent range).  TT_PREC_MIXED_BF16 draws
@@ -71,7 +72,8 @@ typedef enum {
 
 typedef enum {
   TT_PREC_F64 = 0,        /* all arithmetic in FP64 (MFMA f64)                    */
-  TT_PREC_F32 = 1,        /* all arithmetic in FP32 except Gram/Cholesky in FP64  */
+  TT_PREC_F32 = 1,        /* FP32 arithmetic except the Gram/Cholesky steps and
+                             the first CholeskyQR product, in FP64             */
   TT_PREC_MIXED_BF16 = 2  /* W chain in BF16 MFMA with FP32 accumulation, sweep
                              in FP32, Gram/Cholesky and tails in FP64            */
 } tt_prec;
