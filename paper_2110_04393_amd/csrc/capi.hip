@@ -492,6 +492,29 @@ int round_exec(Ctx &c, const Problem &P, const Prec &p, const T *const *Y,
     const int64_t I1 = dims[n];
     const bool last = (n + 1 == N);
     T *dst = last ? xs[N] : xb[n & 1];
+    if (s > 1 && !last) {
+      // all summands' slice-wise products in one launch when they fit
+      std::vector<SumNextEntry> se((size_t)s);
+      int64_t om = 0, on = 0;
+      for (int j = 0; j < s; ++j) {
+        se[j].Y = Y[(size_t)j * N + n];
+        se[j].offm = om;
+        se[j].offn = on;
+        se[j].rj = (int32_t)P.R[j][n];
+        se[j].rj1 = (int32_t)P.R[j][n + 1];
+        om += P.R[j][n];
+        on += P.R[j][n + 1];
+      }
+      if (sum_next_fits(sizeof(T), L[n], I1, se.data(), s)) {
+        if (!c.dry)
+          TTR_TRY(timed_launch(c, TT_SITE_SWEEP_NEXT, true, [&] {
+            return sum_next_run<T>(mbuf, Rs[n], dst, L[n], I1, Rs[n + 1], se.data(), s, qs.go,
+                                   c.s);
+          }));
+        cur = dst;
+        continue;
+      }
+    }
     int64_t offm = 0, offn = 0;
     for (int j = 0; j < s; ++j) {
       const T *Yj = Y[(size_t)j * N + n];

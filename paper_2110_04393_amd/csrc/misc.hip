@@ -2,6 +2,8 @@
 // (assembling the first core of a sum, N = 1 copies, gathering outputs), the
 // power-of-two renormalisation of a partial contraction, and FP32 -> BF16
 // rounding of a caller-given sketch.
+#include <algorithm>
+
 #include "tt_internal.h"
 
 namespace ttr {
@@ -241,6 +243,59 @@ __global__ __launch_bounds__(256) void first_dots_kernel(FirstDots<T> a) {
   if (threadIdx.x == 0) a.out[j] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
 }
 
+// Next core of a sum (sum_next_run): workgroup (summand j, a block of
+// kSumNextI mode indices) stages the summand's columns of M once and each
+// slice Y_j(:, i, :) in turn in LDS, and every thread forms outputs of the
+// slice as dot products of length r_j.
+constexpr int kSumNextThreads = 256, kSumNextI = 4;
+constexpr size_t kSumNextLds = 64 * 1024;
+
+struct SumNextArgs {
+  const void *M;
+  int64_t ldm;
+  void *X;
+  int64_t ldx, rs1, L, I1;
+  const int *gate;
+  int count;
+  SumNextEntry e[kSumNextMax];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kSumNextThreads) void sum_next_kernel(SumNextArgs a) {
+  if (a.gate && *a.gate == 0) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char sn_lds[];
+  T *As = reinterpret_cast<T *>(sn_lds);
+  const int tid = threadIdx.x;
+  const int64_t nib = (a.I1 + kSumNextI - 1) / kSumNextI;
+  const int j = (int)(blockIdx.x / nib);
+  const int64_t i0 = (int64_t)(blockIdx.x % nib) * kSumNextI;
+  const SumNextEntry &e = a.e[j];
+  const int L = (int)a.L, rj = e.rj, rj1 = e.rj1;
+  T *Bs = As + L * rj;
+  const T *M = static_cast<const T *>(a.M);
+  const T *Y = static_cast<const T *>(e.Y);
+  T *X = static_cast<T *>(a.X);
+  for (int t = tid; t < L * rj; t += kSumNextThreads) {
+    const int r = t / rj, c = t - r * rj;
+    As[t] = M[r * a.ldm + e.offm + c];
+  }
+  const int64_t iend = min(i0 + kSumNextI, a.I1);
+  for (int64_t i = i0; i < iend; ++i) {
+    __syncthreads();  // the previous slice is no longer read
+    for (int t = tid; t < rj * rj1; t += kSumNextThreads) {
+      const int r = t / rj1, c = t - r * rj1;
+      Bs[t] = Y[(r * a.I1 + i) * rj1 + c];
+    }
+    __syncthreads();
+    for (int t = tid; t < L * rj1; t += kSumNextThreads) {
+      const int r = t / rj1, c = t - r * rj1;
+      T acc = T(0);
+      for (int k = 0; k < rj; ++k) acc = fma(As[r * rj + k], Bs[k * rj1 + c], acc);
+      X[r * a.ldx + i * a.rs1 + e.offn + c] = acc;
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -274,6 +329,54 @@ int frob_norm(const T *x, int64_t count, double *out, hipStream_t s) {
 }
 template int frob_norm<double>(const double *, int64_t, double *, hipStream_t);
 template int frob_norm<float>(const float *, int64_t, double *, hipStream_t);
+
+static size_t sum_next_lds(size_t elem, int64_t L, const SumNextEntry *e, int count) {
+  size_t lds = 0;
+  for (int j = 0; j < count; ++j)
+    lds = std::max(lds, elem * (size_t)(L * e[j].rj + (int64_t)e[j].rj * e[j].rj1));
+  return lds;
+}
+
+bool sum_next_fits(size_t elem, int64_t L, int64_t I1, const SumNextEntry *e, int count) {
+  if (count < 1 || count > kSumNextMax || L < 1 || I1 < 1) return false;
+  for (int j = 0; j < count; ++j)
+    if (e[j].rj < 1 || e[j].rj1 < 1) return false;
+  return sum_next_lds(elem, L, e, count) <= kSumNextLds;
+}
+
+template <typename T>
+int sum_next_run(const T *M, int64_t ldm, T *X, int64_t L, int64_t I1, int64_t rs1,
+                 const SumNextEntry *e, int count, const int *gate, hipStream_t s) {
+  if (!sum_next_fits(sizeof(T), L, I1, e, count))
+    return fail(TT_EINVAL, "internal: sum next-core shape");
+  const size_t lds = sum_next_lds(sizeof(T), L, e, count);
+  static bool attr = false;
+  if (!attr && lds > 48 * 1024) {
+    TTR_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sum_next_kernel<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSumNextLds));
+    attr = true;
+  }
+  SumNextArgs a;
+  a.M = M;
+  a.ldm = ldm;
+  a.X = X;
+  a.ldx = I1 * rs1;
+  a.rs1 = rs1;
+  a.L = L;
+  a.I1 = I1;
+  a.gate = gate;
+  a.count = count;
+  for (int j = 0; j < count; ++j) a.e[j] = e[j];
+  const int64_t nib = (I1 + kSumNextI - 1) / kSumNextI;
+  hipLaunchKernelGGL(sum_next_kernel<T>, dim3((unsigned)(nib * count)), dim3(kSumNextThreads), lds,
+                     s, a);
+  TTR_HIP(hipGetLastError());
+  return TT_OK;
+}
+template int sum_next_run<double>(const double *, int64_t, double *, int64_t, int64_t, int64_t,
+                                  const SumNextEntry *, int, const int *, hipStream_t);
+template int sum_next_run<float>(const float *, int64_t, float *, int64_t, int64_t, int64_t,
+                                 const SumNextEntry *, int, const int *, hipStream_t);
 
 int select_rank(const double *lam, int n, const double *norm, double eps0, int N, int kmax,
                 int *k_out, double *tail_out, hipStream_t s) {

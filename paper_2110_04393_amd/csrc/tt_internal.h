@@ -526,6 +526,24 @@ template <typename T>
 int frob_norm(const T *x, int64_t count, double *out, hipStream_t s);
 // eps-truncation rank from descending eigenvalues lam of a Gram matrix:
 // smallest k >= 1 with sum_{j>=k} lam_j <= (eps0 norm)^2/(N-1), capped by kmax
+// Next core of a sum, slice-wise for every summand in one launch (Algorithm
+// 7): X(:, i, offn_j + c) = M(:, offm_j + k) Y_j(k, i, c) summed over k < r_j,
+// for all summands j and mode indices i < I1.  M: L x ldm row-major (the
+// summands' columns side by side), Y_j: r_j x I1 x r1_j, X: L x I1 x rs1.
+// Storage T (FP64 or FP32), arithmetic in T.  sum_next_fits (elem =
+// sizeof(T)) is false when the shapes do not fit (more than kSumNextMax
+// summands, or the operands of one summand beyond the LDS budget); the caller
+// then takes one GEMM per summand.
+constexpr int kSumNextMax = 24;
+struct SumNextEntry {
+  const void *Y;
+  int64_t offm, offn;
+  int32_t rj, rj1;
+};
+bool sum_next_fits(size_t elem, int64_t L, int64_t I1, const SumNextEntry *e, int count);
+template <typename T>
+int sum_next_run(const T *M, int64_t ldm, T *X, int64_t L, int64_t I1, int64_t rs1,
+                 const SumNextEntry *e, int count, const int *gate, hipStream_t s);
 int select_rank(const double *lam, int n, const double *norm, double eps0, int N, int kmax,
                 int *k_out, double *tail_out, hipStream_t s);
 
