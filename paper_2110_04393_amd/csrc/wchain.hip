@@ -269,6 +269,11 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
   for (int bb = 0; bb < NBB; ++bb) acc2[bb] = acc_t{0, 0, 0, 0};
   const T *wrow = Wt + (16 * cb + r) * ldk + 4 * q;
   const T *yfrag = Ys + r * YR + 4 * q;
+  // with eight c-blocks (L1 > 64), c-blocks past L1 and b-blocks past L0
+  // (padding of the tile shape) hold zeros: their wavefronts only load and
+  // stage, and no product runs on them (the four-block form keeps its
+  // branch-free products)
+  const bool cb_live = NCB == 4 || 16 * cb < (int)p.L1;
 
   // Batch g (buffer g % 2): issue the loads of batch g + 2 into the
   // registers of batch g (already staged), run the NCB positions of batch g
@@ -284,7 +289,7 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
       static_for<0, NCB>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         const int c = bi * NCB + s;
-        if (c < nch) {
+        if (c < nch && cb_live) {
           T w[4], y[4];
           F::load4(wrow + 16 * c, w);
           F::load4(yfrag + (b * NCB + s) * POS, y);
@@ -299,10 +304,18 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_kernel(const WFuseArgs p
     // beyond L0 multiply zeros
     const acc_t z = acc1[0] + acc1[1];
     acc1[0] = acc1[1] = acc_t{0, 0, 0, 0};
+    if constexpr (NCB == 4) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int bb = 0; bb < NBB; ++bb) acc2[bb] = F::mma(z[j], sk[bb][j], acc2[bb]);
+        for (int bb = 0; bb < NBB; ++bb) acc2[bb] = F::mma(z[j], sk[bb][j], acc2[bb]);
+    } else if (cb_live) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int bb = 0; bb < NBB; ++bb)
+          if (bb < p.nbb) acc2[bb] = F::mma(z[j], sk[bb][j], acc2[bb]);
+    }
     loadsk(u + 1, sk);
   }
 
@@ -492,6 +505,7 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_bf16_kernel(const WFuseA
   for (int bb = 0; bb < NBB; ++bb) acc2[bb] = f4_t{0, 0, 0, 0};
   const __bf16 *wrow = Wt + (16 * cb + r) * ldk + 8 * q;
   const __bf16 *yfrag = Ys + r * YR + 8 * q;
+  const bool cb_live = NCB == 4 || 16 * cb < (int)p.L1;  // as in wfuse_kernel
   const int nbw = (int)((p.ipg + ULN - 1) / ULN) * bpu;
   int g = 0;
   for (int u = 0; u * bpu < nbw; ++u) {
@@ -501,7 +515,7 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_bf16_kernel(const WFuseA
       static_for<0, NCB>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         const int c = bi * NCB + s;
-        if (c < nch) {
+        if (c < nch && cb_live) {
           const bf8_t w = *reinterpret_cast<const bf8_t *>(wrow + 32 * c);
           const bf8_t y = *reinterpret_cast<const bf8_t *>(yfrag + (b * NCB + s) * POS);
           acc1[s & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, y, acc1[s & 1], 0, 0, 0);
@@ -514,9 +528,16 @@ __global__ __launch_bounds__(64 * NCB * ULN) void wfuse_bf16_kernel(const WFuseA
     acc1[0] = acc1[1] = f4_t{0, 0, 0, 0};
     const float zv[4] = {zs[0], zs[1], zs[2], zs[3]};
     const bf8_t z = bf16_lo4(zv);
+    if constexpr (NCB == 4) {
 #pragma unroll
-    for (int bb = 0; bb < NBB; ++bb)
-      acc2[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(z, bf16_lo4(sk[bb]), acc2[bb], 0, 0, 0);
+      for (int bb = 0; bb < NBB; ++bb)
+        acc2[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(z, bf16_lo4(sk[bb]), acc2[bb], 0, 0, 0);
+    } else if (cb_live) {
+#pragma unroll
+      for (int bb = 0; bb < NBB; ++bb)
+        if (bb < p.nbb)
+          acc2[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(z, bf16_lo4(sk[bb]), acc2[bb], 0, 0, 0);
+    }
     loadsk(u + 1, sk);
   }
 
