@@ -203,10 +203,17 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
       return x;
     };
     const double rdiag = q == 0 ? R4[0][0] : q == 1 ? R4[1][1] : q == 2 ? R4[2][2] : R4[3][3];
+    // row q of the final panel at this lane's column of every live block,
+    // formed once for the owner's rows and the update's B operands
+    double pv[NCB];
+    static_for<I0, JR + 1>([&](auto Jc) __attribute__((always_inline)) {
+      constexpr int J = decltype(Jc)::value;
+      pv[J] = panel_at(16 * J + r);
+    });
     if (wave == w0) {
       static_for<I0, JR + 1>([&](auto Jc) __attribute__((always_inline)) {
         constexpr int J = decltype(Jc)::value;
-        double x = panel_at(16 * J + r);
+        double x = pv[J];
         if constexpr (J < NRB) {
           const int c = 16 * J + r;
           if (c == j0 + q) x = rdiag;
@@ -225,8 +232,7 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
         const double a = (row > j0 + 3) ? -panel_at(row) : 0.0;
         static_for<I0, JR + 1>([&](auto Jc) __attribute__((always_inline)) {
           constexpr int J = decltype(Jc)::value;
-          const double b = panel_at(16 * J + r);
-          X[sl][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, X[sl][J], 0, 0, 0);
+          X[sl][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, pv[J], X[sl][J], 0, 0, 0);
         });
       }
     }
