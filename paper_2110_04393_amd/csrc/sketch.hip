@@ -36,14 +36,16 @@ struct SketchTable {
   void *ptr[kMaxCoresPerLaunch];
 };
 
+// blockIdx.y picks the core, so the table reads are uniform over the
+// workgroup; blockIdx.x strides over that core's element pairs.
 __global__ __launch_bounds__(256) void sketch_kernel(SketchTable t) {
-  const int64_t total = t.pair_begin[t.ncores];
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int c = 0;
-    while (g >= t.pair_begin[c + 1]) ++c;
-    const int64_t p = g - t.pair_begin[c];
-    const uint64_t key = t.key[c];
+  const int c = blockIdx.y;
+  const int64_t pairs = t.pair_begin[c + 1] - t.pair_begin[c];
+  const int64_t cnt = t.count[c];
+  const uint64_t key = t.key[c];
+  const double scale = t.sqrt_count[c];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs;
+       p += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t a = mix64(key + (uint64_t)(2 * p + 1) * kGamma);
     const uint64_t b = mix64(key + (uint64_t)(2 * p + 2) * kGamma);
     const double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53;
@@ -52,21 +54,20 @@ __global__ __launch_bounds__(256) void sketch_kernel(SketchTable t) {
     const double th = 6.283185307179586 * u2;
     double sn, cs;
     sincos(th, &sn, &cs);
-    const double scale = t.sqrt_count[c];
     const double z0 = rad * cs / scale, z1 = rad * sn / scale;
     const int64_t e = 2 * p;
     if (t.dtype == TT_F64) {
       double *o = static_cast<double *>(t.ptr[c]);
       o[e] = z0;
-      if (e + 1 < t.count[c]) o[e + 1] = z1;
+      if (e + 1 < cnt) o[e + 1] = z1;
     } else if (t.dtype == TT_F32) {
       float *o = static_cast<float *>(t.ptr[c]);
       o[e] = (float)z0;
-      if (e + 1 < t.count[c]) o[e + 1] = (float)z1;
+      if (e + 1 < cnt) o[e + 1] = (float)z1;
     } else {  // BF16: rounded to FP32, then to BF16 (both to nearest even)
       __bf16 *o = static_cast<__bf16 *>(t.ptr[c]);
       o[e] = bf16_rne((float)z0);
-      if (e + 1 < t.count[c]) o[e + 1] = bf16_rne((float)z1);
+      if (e + 1 < cnt) o[e + 1] = bf16_rne((float)z1);
     }
   }
 }
@@ -89,10 +90,14 @@ int sketch_generate(uint64_t seed, int N, const int64_t *dims, const int64_t *sr
       t.ptr[c] = cores[n];
       t.pair_begin[c + 1] = t.pair_begin[c] + (cnt + 1) / 2;
     }
-    const int64_t total = t.pair_begin[t.ncores];
-    if (total == 0) continue;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(sketch_kernel, dim3((unsigned)blocks), dim3(256), 0, s, t);
+    int64_t most = 0;
+    for (int c = 0; c < t.ncores; ++c)
+      most = std::max(most, t.pair_begin[c + 1] - t.pair_begin[c]);
+    if (most == 0) continue;
+    // About 4096 workgroups over the whole launch, each thread a few pairs.
+    const int64_t cap = std::max<int64_t>(1, 4096 / t.ncores);
+    const int64_t bx = std::min<int64_t>((most + 255) / 256, cap);
+    hipLaunchKernelGGL(sketch_kernel, dim3((unsigned)bx, (unsigned)t.ncores), dim3(256), 0, s, t);
     TTR_HIP(hipGetLastError());
   }
   return TT_OK;
