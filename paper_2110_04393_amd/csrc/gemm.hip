@@ -529,8 +529,9 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_group_kernel(const GemmGrou
 }
 
 // Sum of the split-K partials into C: 32 output elements per workgroup, the
-// eight wavefront-quarters each summing whole groups of eight partials (all
-// loads of a group in flight), then the group sums added in index order.
+// eight wavefront-quarters each summing whole groups of eight partials (the
+// loads of all of a quarter's groups in flight together), then the group
+// sums added in index order.
 // Entry blockIdx.y of the table (or the single product g).
 constexpr int kRedElems = 32;
 constexpr int kRedMaxGroups = 32;  // 256 partials
@@ -545,16 +546,38 @@ __device__ __forceinline__ void splitk_reduce_body(const GemmX &g) {
   const int64_t idx = (int64_t)blockIdx.x * kRedElems + t;
   const bool ok = idx < total;
   const TP *part = static_cast<const TP *>(g.partial);
-  for (int grp = part_of; grp < G; grp += 256 / kRedElems) {
-    TP v[kSplitGroup];
+  // all of a thread's groups are loaded before any is summed, so their loads
+  // are in flight together
+  constexpr int kQuarters = 256 / kRedElems, kPerQuarter = kRedMaxGroups / kQuarters;
+  // (addresses clamped into the buffer and the extra values dropped after
+  // the load, so no load sits behind a branch)
+  TP v[kPerQuarter][kSplitGroup];
+  const int64_t idc = ok ? idx : 0;
+#pragma unroll
+  for (int h = 0; h < kPerQuarter; ++h) {
+    const int grp = part_of + kQuarters * h;
+    if (kQuarters * h >= G) break;  // uniform over the workgroup
 #pragma unroll
     for (int u = 0; u < kSplitGroup; ++u) {
       const int p = grp * kSplitGroup + u;
-      v[u] = (ok && p < P) ? part[(int64_t)p * total + idx] : TP(0);
+      v[h][u] = part[(int64_t)min(p, P - 1) * total + idc];
     }
+  }
+#pragma unroll
+  for (int h = 0; h < kPerQuarter; ++h) {
+    if (kQuarters * h >= G) break;
+    const int grp = part_of + kQuarters * h;
+#pragma unroll
+    for (int u = 0; u < kSplitGroup; ++u)
+      if (!ok || grp * kSplitGroup + u >= P) v[h][u] = TP(0);
+  }
+#pragma unroll
+  for (int h = 0; h < kPerQuarter; ++h) {
+    const int grp = part_of + kQuarters * h;
+    if (grp >= G) break;
     TP gs = TP(0);
 #pragma unroll
-    for (int u = 0; u < kSplitGroup; ++u) gs += v[u];
+    for (int u = 0; u < kSplitGroup; ++u) gs += v[h][u];
     s_gs[grp][t] = gs;
   }
   __syncthreads();
