@@ -75,10 +75,27 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
 
   if (or_flag) {
     // second pass: first-order factor when G is within 2^-30 of I
+    // a thread's entries (rows wave + NW t, columns lane + 64 u) are loaded
+    // together (addresses clamped into G, entries past n dropped after the
+    // load) and kept for the factor below
+    constexpr int NRW = (NMAX + NW - 1) / NW, NCU = (NMAX + 63) / 64;
     __shared__ double s_emax[NW];
+    double gv[NRW][NCU];
+#pragma unroll
+    for (int t = 0; t < NRW; ++t)
+#pragma unroll
+      for (int u = 0; u < NCU; ++u) {
+        const int i = min(wave + NW * t, n - 1), c = min(lane + 64 * u, n - 1);
+        gv[t][u] = G[i * n + c];
+      }
     double em = 0.0;
-    for (int i = wave; i < n; i += NW)
-      for (int c = lane; c < n; c += 64) em = fmax(em, fabs(G[i * n + c] - (i == c ? 1.0 : 0.0)));
+#pragma unroll
+    for (int t = 0; t < NRW; ++t)
+#pragma unroll
+      for (int u = 0; u < NCU; ++u) {
+        const int i = wave + NW * t, c = lane + 64 * u;
+        if (i < n && c < n) em = fmax(em, fabs(gv[t][u] - (i == c ? 1.0 : 0.0)));
+      }
     em = fmax(em, __shfl_xor(em, 32));
     em = fmax(em, __shfl_xor(em, 16));
     em = fmax(em, __shfl_xor(em, 8));
@@ -91,10 +108,15 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
 #pragma unroll
     for (int w = 1; w < NW; ++w) emax = fmax(emax, s_emax[w]);
     if (emax <= (Rinv_f ? kNearIdentityF32 : kNearIdentity)) {  // also false for NaN
-      for (int i = wave; i < n; i += NW)
-        for (int c = lane; c < n; c += 64) {
+#pragma unroll
+      for (int t = 0; t < NRW; ++t)
+#pragma unroll
+        for (int u = 0; u < NCU; ++u) {
+          const int i = wave + NW * t, c = lane + 64 * u;
+          if (i >= n || c >= n) continue;
           const int e = i * n + c;
-          const double x = (i == c) ? 1.0 - 0.5 * (G[e] - 1.0) : ((i < c) ? -G[e] : 0.0);
+          const double g = gv[t][u];
+          const double x = (i == c) ? 1.0 - 0.5 * (g - 1.0) : ((i < c) ? -g : 0.0);
           Rinv[e] = x;
           if (Rinv_f) Rinv_f[e] = (float)x;
         }
