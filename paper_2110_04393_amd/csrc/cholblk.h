@@ -123,7 +123,21 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
       return 0;
     }
   }
-  // sh: shift added to the diagonal (shifted CholeskyQR), 0 otherwise
+  // sh: shift added to the diagonal (shifted CholeskyQR), 0 otherwise.
+  // The lower-triangle entries G(max(i, c), min(i, c)) of a thread's part of
+  // the left block columns are loaded first, all together (indices clamped
+  // into G; entries outside the n x n matrix are not used).
+  double gl[NSL][NRB][4];
+#pragma unroll
+  for (int sl = 0; sl < NSL; ++sl)
+#pragma unroll
+    for (int J = 0; J < NRB; ++J)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = 16 * (wave + NW * sl) + q + 4 * jj, c = 16 * J + r;
+        const int hi = min(max(i, c), n - 1), lo = min(min(i, c), n - 1);
+        gl[sl][J][jj] = G[hi * n + lo];
+      }
   chol_d4 X[NSL][NCB];
 #pragma unroll
   for (int sl = 0; sl < NSL; ++sl) {
@@ -136,7 +150,7 @@ __device__ __forceinline__ int chol_inv_kernel_body(const double *G, double *Rin
         double v = 0.0;
         if (I < NRB) {
           if (J < NRB) {
-            if (i < n && c < n) v = ((i >= c) ? G[i * n + c] : G[c * n + i]) + (i == c ? sh : 0.0);
+            if (i < n && c < n) v = gl[sl][J][jj] + (i == c ? sh : 0.0);
             else if (i == c) v = 1.0;
           } else {
             v = (c - NMAX == i) ? 1.0 : 0.0;
