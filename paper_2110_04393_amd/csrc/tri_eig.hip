@@ -404,19 +404,63 @@ __device__ __forceinline__ void tri_vec_body(const double *d_in, const double *e
   __shared__ double s_tau[NMAX], s_vv[NMAX], s_vv2[NMAX];  // tau_j, v_j^T v_(j+1), v_j^T v_(j+2)
   __shared__ double s_sc[2][2][128];   // scan buffers (lower, upper factors)
   const int lane = threadIdx.x;
-  for (int i = lane; i <= NMAX; i += 64) {
-    const double dv = (i < n) ? d_in[i] : 4.0;
-    const double ev = (i < n - 1) ? e_in[i] : 0.0;
-    s_d[i] = dv;
-    s_e[i] = ev;
-    s_e2[i] = ev * ev;
-    s_dr[i] = (i < n) ? d_in[n - 1 - i] : 4.0;
-    s_er[i] = (i < n - 1) ? e_in[n - 2 - i] : 0.0;
-    s_er2[i] = s_er[i] * s_er[i];
+  if (n >= 5) {
+    // every load first, all in flight together (indices clamped into d_in
+    // (n), e_in (n - 1), taus (n - 2) and Vr (n^2); values outside the
+    // ranges below are dropped), then the LDS stores
+    constexpr int NI = (NMAX + 1 + 63) / 64, NJ = (NMAX + 63) / 64;
+    double dv[NI], ev[NI], drv[NI], erv[NI], tv[NJ], v1[NJ], v2[NJ];
+#pragma unroll
+    for (int u = 0; u < NI; ++u) {
+      const int i = lane + 64 * u;
+      dv[u] = d_in[min(i, n - 1)];
+      ev[u] = e_in[min(i, n - 2)];
+      drv[u] = d_in[max(n - 1 - i, 0)];
+      erv[u] = e_in[max(n - 2 - i, 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = lane + 64 * u;
+      tv[u] = taus[min(j, n - 3)];
+      v1[u] = Vr[(n - 2) * n + min(j, n - 4)];
+      v2[u] = Vr[(n - 2) * n + (n - 3) + min(j, n - 5)];
+    }
+#pragma unroll
+    for (int u = 0; u < NI; ++u) {
+      const int i = lane + 64 * u;
+      if (i <= NMAX) {
+        const double d = (i < n) ? dv[u] : 4.0, e = (i < n - 1) ? ev[u] : 0.0;
+        const double er = (i < n - 1) ? erv[u] : 0.0;
+        s_d[i] = d;
+        s_e[i] = e;
+        s_e2[i] = e * e;
+        s_dr[i] = (i < n) ? drv[u] : 4.0;
+        s_er[i] = er;
+        s_er2[i] = er * er;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = lane + 64 * u;
+      if (j < n - 2) s_tau[j] = tv[u];
+      if (j < n - 3) s_vv[j] = v1[u];
+      if (j < n - 4) s_vv2[j] = v2[u];
+    }
+  } else {
+    for (int i = lane; i <= NMAX; i += 64) {
+      const double dv = (i < n) ? d_in[i] : 4.0;
+      const double ev = (i < n - 1) ? e_in[i] : 0.0;
+      s_d[i] = dv;
+      s_e[i] = ev;
+      s_e2[i] = ev * ev;
+      s_dr[i] = (i < n) ? d_in[n - 1 - i] : 4.0;
+      s_er[i] = (i < n - 1) ? e_in[n - 2 - i] : 0.0;
+      s_er2[i] = s_er[i] * s_er[i];
+    }
+    for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
+    for (int j = lane; j < n - 3; j += 64) s_vv[j] = Vr[(n - 2) * n + j];
+    for (int j = lane; j < n - 4; j += 64) s_vv2[j] = Vr[(n - 2) * n + (n - 3) + j];
   }
-  for (int j = lane; j < n - 2; j += 64) s_tau[j] = taus[j];
-  for (int j = lane; j < n - 3; j += 64) s_vv[j] = Vr[(n - 2) * n + j];
-  for (int j = lane; j < n - 4; j += 64) s_vv2[j] = Vr[(n - 2) * n + (n - 3) + j];
   if (lane == 0) s_V[NMAX * NMAX] = 0.0;
   __syncthreads();
   // The reflectors go from global memory straight to LDS (16 bytes per lane
